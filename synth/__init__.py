@@ -1,0 +1,323 @@
+"""Seeded synthetic workloads for CAPS filtered search.
+
+This module only draws inputs: vectors, per-point attribute sets, query
+vectors and query constraints.  It holds none of the method's arithmetic
+(no partitioning, no distances, no ranking); both the CPU oracle and the
+GPU library read what it produces.
+
+Workload shapes follow the five configurations the build targets
+(small Gaussian-mixture parity case; a SIFT1M-shaped integer corpus; an
+angular corpus with label sets; the router's training set on the second
+corpus; a 10M-point serving corpus).  The paper's own evaluation attaches
+synthetic attributes to public corpora (Evaluation, "Datasets"); those
+corpora are not available here and these generators stand in for them.
+
+Random streams: numpy ``Generator(PCG64)`` seeded from
+``SeedSequence(seed).spawn(4)`` -> (vectors, attributes, queries,
+constraints).  Zipf(s) over a finite vocabulary V puts P(r) proportional
+to (r+1)^-s for r = 0..V-1 (value 0 most frequent), sampled by inverse CDF.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+BASE_SEED = 2308_15014
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    x: np.ndarray                      # (N, d) float32, row-major
+    dense: Optional[np.ndarray]        # (N, L) uint32 or None
+    dense_vocab: List[int]             # vocabulary size per dense attribute
+    label_off: Optional[np.ndarray]    # (N+1,) int64 CSR offsets or None
+    labels: Optional[np.ndarray]       # (nnz,) uint32 or None
+    label_vocab: int                   # 0 when there are no labels
+    q: np.ndarray                      # (Q, d) float32
+    con_off: np.ndarray                # (Q+1,) int32 CSR over constraint pairs
+    con_attr: np.ndarray               # (nc,) int32: dense attr index, or L for a label
+    con_val: np.ndarray                # (nc,) int32
+    metric: int                        # 0 squared L2, 1 inner product
+    n_partitions: int                  # B
+    aft_height: int                    # h
+    kmeans_iters: int
+    k: int
+    nprobe: int
+    seed: int
+    selectivity: Optional[np.ndarray] = None   # |D_C|/N per query when known
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.x.shape[1])
+
+    @property
+    def n_q(self) -> int:
+        return int(self.q.shape[0])
+
+    @property
+    def n_dense(self) -> int:
+        return 0 if self.dense is None else int(self.dense.shape[1])
+
+
+def zipf_cdf(vocab: int, s: float) -> np.ndarray:
+    w = (np.arange(1, vocab + 1, dtype=np.float64)) ** (-s)
+    c = np.cumsum(w)
+    return c / c[-1]
+
+
+def zipf_draw(rng: np.random.Generator, cdf: np.ndarray, size) -> np.ndarray:
+    u = rng.random(size)
+    v = np.searchsorted(cdf, u, side="right")
+    return np.minimum(v, len(cdf) - 1).astype(np.uint32)
+
+
+def draw_dense(rng, n, vocabs, s):
+    cols = [zipf_draw(rng, zipf_cdf(v, s), n) for v in vocabs]
+    return np.stack(cols, axis=1).astype(np.uint32)
+
+
+def draw_label_sets(rng, n, vocab, s, max_size=8):
+    """Per point: size ~ U{1..max_size}; labels Zipf(s) without replacement
+    (a duplicate draw is drawn again)."""
+    cdf = zipf_cdf(vocab, s)
+    size = rng.integers(1, max_size + 1, size=n)
+    lab = zipf_draw(rng, cdf, (n, max_size)).astype(np.int64)
+    for c in range(1, max_size):
+        active = size > c
+        while True:
+            dup = np.zeros(n, dtype=bool)
+            for e in range(c):
+                dup |= lab[:, c] == lab[:, e]
+            dup &= active
+            cnt = int(dup.sum())
+            if cnt == 0:
+                break
+            lab[dup, c] = zipf_draw(rng, cdf, cnt)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(size)
+    mask = np.arange(max_size)[None, :] < size[:, None]
+    labels = lab[mask].astype(np.uint32)
+    return off, labels
+
+
+class _DenseCounter:
+    """|{i : a_i[attr]=val for every constrained attr}| from a joint count
+    table (used only to keep queries inside a selectivity band)."""
+
+    def __init__(self, dense, vocabs):
+        self.vocabs = list(vocabs)
+        flat = np.zeros(dense.shape[0], dtype=np.int64)
+        for i, v in enumerate(vocabs):
+            flat = flat * v + dense[:, i].astype(np.int64)
+        total = int(np.prod(vocabs))
+        self.table = np.bincount(flat, minlength=total).reshape(vocabs)
+
+    def count(self, pairs):
+        idx = [slice(None)] * len(self.vocabs)
+        for a, v in pairs:
+            if idx[a] != slice(None) and idx[a] != v:
+                return 0
+            idx[a] = v
+        return int(self.table[tuple(idx)].sum())
+
+
+class _LabelCounter:
+    """Counts points holding every label of a set, from posting lists."""
+
+    def __init__(self, off, labels, n):
+        self.n = n
+        owner = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+        order = np.argsort(labels, kind="stable")
+        self.lab_sorted = labels[order]
+        self.own_sorted = owner[order]
+
+    def posting(self, lab):
+        lo = np.searchsorted(self.lab_sorted, lab, side="left")
+        hi = np.searchsorted(self.lab_sorted, lab, side="right")
+        return self.own_sorted[lo:hi]
+
+    def ids(self, labs):
+        if not labs:
+            return None
+        lists = sorted((self.posting(l) for l in labs), key=len)
+        cur = lists[0]
+        for p in lists[1:]:
+            if cur.size == 0:
+                break
+            cur = np.intersect1d(cur, p, assume_unique=True)
+        return cur
+
+
+def draw_constraints(rng, n_q, n, dense, label_off, labels, cmin, cmax,
+                     band=None, counter=None):
+    """Each query copies c ~ U{cmin..cmax} attributes (dense values and/or
+    labels) of a uniformly drawn database point, chosen without replacement.
+    When ``band`` = (lo, hi) is given, a draw whose |D_C|/N falls outside the
+    band is discarded and drawn again."""
+    n_dense = 0 if dense is None else dense.shape[1]
+    off = [0]
+    attrs: List[int] = []
+    vals: List[int] = []
+    sel = np.zeros(n_q, dtype=np.float64)
+    for qi in range(n_q):
+        for _attempt in range(100000):
+            pt = int(rng.integers(n))
+            pool = [(a, int(dense[pt, a])) for a in range(n_dense)]
+            if labels is not None:
+                pool += [(n_dense, int(l)) for l in labels[label_off[pt]:label_off[pt + 1]]]
+            c = int(rng.integers(cmin, cmax + 1))
+            c = min(c, len(pool))
+            pick = rng.choice(len(pool), size=c, replace=False)
+            pairs = [pool[j] for j in sorted(pick)]
+            if counter is None:
+                break
+            cnt = counter(pairs)
+            frac = cnt / n
+            sel[qi] = frac
+            if band is None or (band[0] <= frac <= band[1]):
+                break
+        else:
+            raise RuntimeError("selectivity band unreachable")
+        for a, v in pairs:
+            attrs.append(a)
+            vals.append(v)
+        off.append(len(attrs))
+    return (np.asarray(off, dtype=np.int32), np.asarray(attrs, dtype=np.int32),
+            np.asarray(vals, dtype=np.int32), sel)
+
+
+def _streams(seed):
+    ss = np.random.SeedSequence(seed)
+    return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(4)]
+
+
+def make_c1(n=10_000, n_q=100, seed=None) -> Workload:
+    """Gaussian mixture: 16 means ~ N(0, 4I), points = mean + N(0, I), d=32.
+    Three dense attributes (10/10/20) Zipf(1.0).  Queries are database points
+    plus N(0, 0.1 I); each carries 1-2 constraints copied from an independently
+    drawn database point.  B=32, h=2, 10 Lloyd iterations, k=10, nprobe=4, L2."""
+    seed = BASE_SEED + 1 if seed is None else seed
+    rv, ra, rq, rc = _streams(seed)
+    d = 32
+    means = rv.normal(0.0, 2.0, size=(16, d))
+    comp = rv.integers(16, size=n)
+    x = (means[comp] + rv.normal(0.0, 1.0, size=(n, d))).astype(np.float32)
+    vocab = [10, 10, 20]
+    dense = draw_dense(ra, n, vocab, 1.0)
+    src = rq.integers(n, size=n_q)
+    q = (x[src].astype(np.float64) + rq.normal(0.0, np.sqrt(0.1), size=(n_q, d))).astype(np.float32)
+    cnt = _DenseCounter(dense, vocab)
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, None, None, 1, 2, None, cnt.count)
+    return Workload("c1", x, dense, vocab, None, None, 0, q, co, ca, cv, 0,
+                    32, 2, 10, 10, 4, seed, sel)
+
+
+def make_c2(n=1_000_000, n_q=10_000, seed=None, band=(0.001, 0.30), n_partitions=1024) -> Workload:
+    """SIFT1M-shaped: uniform integers 0..255 stored as float32, d=128.
+    Three dense attributes (10/50/200) Zipf(1.0).  Queries: uniform integers,
+    1-3 constraints, selectivity |D_C|/N within ``band``.  B=1024, h=2."""
+    seed = BASE_SEED + 2 if seed is None else seed
+    rv, ra, rq, rc = _streams(seed)
+    d = 128
+    x = rv.integers(0, 256, size=(n, d), dtype=np.int32).astype(np.float32)
+    vocab = [10, 50, 200]
+    dense = draw_dense(ra, n, vocab, 1.0)
+    q = rq.integers(0, 256, size=(n_q, d), dtype=np.int32).astype(np.float32)
+    cnt = _DenseCounter(dense, vocab)
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, None, None, 1, 3, band, cnt.count)
+    return Workload("c2", x, dense, vocab, None, None, 0, q, co, ca, cv, 0,
+                    n_partitions, 2, 10, 10, 32, seed, sel)
+
+
+def make_c2_queries(n_q, seed, n=1_000_000, band=(0.001, 0.30)):
+    """Extra query sets drawn from the c2 query generator with another seed
+    (router training and held-out sets).  The corpus itself is unchanged."""
+    base = make_c2(n=n, n_q=1, band=band)
+    _rv, _ra, rq, rc = _streams(seed)
+    q = rq.integers(0, 256, size=(n_q, base.d), dtype=np.int32).astype(np.float32)
+    cnt = _DenseCounter(base.dense, base.dense_vocab)
+    co, ca, cv, sel = draw_constraints(rc, n_q, base.n, base.dense, None, None, 1, 3, band, cnt.count)
+    return q, co, ca, cv, sel
+
+
+def make_c3(n=5_000_000, n_q=10_000, seed=None, n_partitions=4096) -> Workload:
+    """Angular corpus: g/|g| with g ~ N(0, I), d=96, inner product.  Each
+    point holds 1-8 labels from a vocabulary of 1000, Zipf(1.1).  Queries:
+    fresh unit Gaussians with 1-4 label constraints.  B=4096, h=4."""
+    seed = BASE_SEED + 3 if seed is None else seed
+    rv, ra, rq, rc = _streams(seed)
+    d = 96
+    g = rv.standard_normal(size=(n, d))
+    x = (g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
+    del g
+    off, labels = draw_label_sets(ra, n, 1000, 1.1)
+    gq = rq.standard_normal(size=(n_q, d))
+    q = (gq / np.linalg.norm(gq, axis=1, keepdims=True)).astype(np.float32)
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, None, off, labels, 1, 4, None, None)
+    return Workload("c3", x, None, [], off, labels, 1000, q, co, ca, cv, 1,
+                    n_partitions, 4, 10, 10, 64, seed, None)
+
+
+def make_c5(n=10_000_000, n_q=10_000, seed=None, n_partitions=8192,
+            band=(0.0001, 0.50)) -> Workload:
+    """Serving corpus: c2-style integer vectors (exact in FP16), d=128, three
+    dense attributes (10/50/200, Zipf 1.0) plus label sets of 1-8 labels from
+    5000, Zipf(1.1).  Queries: 1-4 constraints mixing both kinds, selectivity
+    within ``band``.  B=8192, h=4."""
+    seed = BASE_SEED + 5 if seed is None else seed
+    rv, ra, rq, rc = _streams(seed)
+    d = 128
+    x = rv.integers(0, 256, size=(n, d), dtype=np.int32).astype(np.float32)
+    vocab = [10, 50, 200]
+    dense = draw_dense(ra, n, vocab, 1.0)
+    off, labels = draw_label_sets(ra, n, 5000, 1.1)
+    q = rq.integers(0, 256, size=(n_q, d), dtype=np.int32).astype(np.float32)
+    dc = _DenseCounter(dense, vocab)
+    lc = _LabelCounter(off, labels, n)
+
+    def count(pairs):
+        dp = [(a, v) for a, v in pairs if a < 3]
+        lp = [v for a, v in pairs if a == 3]
+        if not lp:
+            return dc.count(dp)
+        ids = lc.ids(lp)
+        if ids.size == 0:
+            return 0
+        m = np.ones(ids.size, dtype=bool)
+        for a, v in dp:
+            m &= dense[ids, a] == v
+        return int(m.sum())
+
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, off, labels, 1, 4, band, count)
+    return Workload("c5", x, dense, vocab, off, labels, 5000, q, co, ca, cv, 0,
+                    n_partitions, 4, 10, 10, 64, seed, sel)
+
+
+def make_tiny(rng_seed, n, d, n_q, vocabs=(3, 4), label_vocab=0, metric=0,
+              b=4, h=2, cmin=0, cmax=2, integer=False, max_labels=4):
+    """Small random workloads for exhaustive and property tests."""
+    rv, ra, rq, rc = _streams(rng_seed)
+    if integer:
+        x = rv.integers(0, 8, size=(n, d)).astype(np.float32)
+        q = rq.integers(0, 8, size=(n_q, d)).astype(np.float32)
+    else:
+        x = rv.normal(size=(n, d)).astype(np.float32)
+        q = rq.normal(size=(n_q, d)).astype(np.float32)
+    dense = draw_dense(ra, n, list(vocabs), 1.0) if vocabs else None
+    if label_vocab:
+        off, labels = draw_label_sets(ra, n, label_vocab, 1.1, max_size=max_labels)
+    else:
+        off, labels = None, None
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, off, labels, cmin, cmax, None, None)
+    return Workload("tiny", x, dense, list(vocabs) if vocabs else [], off, labels,
+                    label_vocab, q, co, ca, cv, metric, b, h, 5, 5, 2, rng_seed, None)
+
+
+MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c5": make_c5}
