@@ -1,0 +1,177 @@
+/*
+ * caps.h -- C ABI of libcaps, an MI355X (gfx950) implementation of CAPS
+ * filtered partitioned search (Gupta et al., "CAPS: A Practical Partition
+ * Index for Filtered Similarity Search", arXiv 2308.15014).
+ *
+ * Problem (Definitions 1 and 2): given points (x_i, a_i) with x_i in R^d and
+ * categorical attributes a_i, and a query (q, b), return the k nearest
+ * points among D_C = { i : a_i satisfies every constraint of b }.
+ * Attributes come in two kinds (Section 2 "Attribute Model", Table 1):
+ *   dense:  L_dense attributes with one value each, value < vocab[attr];
+ *   labels: a set of up to 8 distinct labels per point, label < label_vocab.
+ * A query constraint is a pair (attr, val): attr in [0, L_dense) names a
+ * dense attribute, attr == L_dense names a label.  Constraints are ANDed;
+ * unconstrained attributes match anything.
+ *
+ * Index (Algorithm 1): first-level partitions f from seeded Lloyd k-means
+ * (Section 5.2 "Index creation"), then in every partition a truncated
+ * Attribute Frequency Tree of height h giving h+1 disjoint sub-partitions,
+ * stored as a CSR (Appendix "Index size").
+ * Query (Algorithm 2): score the B centroids, probe the best nprobe
+ * partitions, choose the sub-partitions that can hold valid points, filter
+ * exactly, scan distances, keep the top k.
+ *
+ * Conventions
+ *   - Status codes only; nothing is thrown across the ABI.  On a non-OK
+ *     status outputs are left unspecified and caps_last_error() returns a
+ *     thread-local message.
+ *   - Buffers are owned by the caller; the index owns its device copies.
+ *   - Ranking is a total order: squared L2 ascending, or inner product
+ *     descending, then point id ascending.  Fewer than k valid points pad
+ *     with id -1 and +inf (L2) / -inf (IP).
+ *   - FP32 mode arithmetic: each distance is a sequential fused
+ *     multiply-add chain over dimensions in ascending order (L2:
+ *     t = x_j - q_j, acc = fma(t, t, acc); IP: acc = fma(x_j, q_j, acc)),
+ *     -0 reported as +0.  Results are therefore deterministic and identical
+ *     for a query alone or inside any batch.
+ */
+#ifndef CAPS_H
+#define CAPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct caps_index caps_index;
+
+typedef enum {
+    CAPS_OK = 0,
+    CAPS_EINVAL = -1,        /* an argument is out of range or malformed */
+    CAPS_ENOMEM = -2,        /* device or host allocation failed */
+    CAPS_EDEVICE = -3,       /* a HIP runtime call failed */
+    CAPS_EUNSUPPORTED = -4,  /* valid input outside what this build supports */
+    CAPS_EBUSY = -5,         /* server queue full */
+    CAPS_EIO = -6            /* file could not be read or written */
+} caps_status;
+
+enum { CAPS_METRIC_L2 = 0, CAPS_METRIC_IP = 1 };
+
+typedef struct {
+    int32_t metric;          /* CAPS_METRIC_L2 (squared) or CAPS_METRIC_IP */
+    int32_t n_partitions;    /* B, 1 <= B <= min(n, 8192) */
+    int32_t kmeans_iters;    /* Lloyd iterations before the final assignment */
+    int32_t aft_height;      /* h, 0 <= h <= 15: h tagged levels + remainder */
+    uint64_t seed;           /* drives the init sampler (splitmix64 +
+                                partial Fisher-Yates over 0..n-1) */
+    const int32_t *init_ids; /* optional host array of B initial point ids;
+                                overrides seed when not NULL */
+} caps_build_params;
+
+/*
+ * caps_build -- Algorithm 1.  All pointers are HOST pointers; data is
+ * copied to the current device and the index stays resident there.
+ *   x          n x d float32, row-major, finite
+ *   dense_vals n x n_dense uint32 row-major, dense_vals[i*n_dense+a] <
+ *              dense_vocab[a]; NULL when n_dense == 0
+ *   dense_vocab n_dense vocabulary sizes (>= 1); packed widths must total
+ *              <= 32 bits (ceil(log2(vocab)) bits per attribute)
+ *   label_off  n+1 int64 CSR offsets into labels, or NULL (no labels)
+ *   labels     label ids < label_vocab <= 65535, at most 8 distinct per
+ *              point (a repeated label is an error)
+ *   stream     hipStream_t to run on (NULL = default stream); the call
+ *              synchronises it before returning
+ * k-means: init centroids at the sampled points; each iteration assigns
+ * every point to argmin_c (|c|^2 - 2 x.c) [IP: argmin -x.c] with ties to
+ * the smaller c, then sets every non-empty centroid to the FP64 mean of its
+ * points summed in ascending id, rounded to FP32 (IP: then divided by its
+ * FP64 norm); a final assignment defines the partitions.
+ * AFT: per partition, h times: tag = the attribute value (dense value or
+ * label) held by most remaining points, ties to the smaller token
+ * (token = dense offset + value, labels after all dense values); the points
+ * holding it form the next sub-partition.
+ * Errors: EINVAL (shapes, vocabularies, non-finite x, B > n), EUNSUPPORTED
+ * (limits above), ENOMEM, EDEVICE.
+ */
+caps_status caps_build(const float *x, int64_t n, int32_t d,
+                       const uint32_t *dense_vals, int32_t n_dense, const int32_t *dense_vocab,
+                       const int64_t *label_off, const uint32_t *labels, int32_t label_vocab,
+                       const caps_build_params *params, void *stream, caps_index **out);
+
+typedef struct {
+    int32_t k;        /* 1 <= k <= 64 */
+    int32_t nprobe;   /* m, 1 <= m <= B */
+    int32_t rule;     /* 0: exact sub-partition choice (skip only
+                         sub-partitions whose tags prove them empty of valid
+                         points); 1: Algorithm 2 read literally (one
+                         sub-partition per partition; lossy, for ablation) */
+    int32_t reserved;
+} caps_search_params;
+
+/*
+ * caps_search -- Algorithm 2 over a batch.  All pointers are DEVICE
+ * pointers on the index's device; work is enqueued on `stream` and the call
+ * returns without synchronising.
+ *   q           n_q x d float32 row-major
+ *   con_off     n_q+1 int32 CSR offsets over constraint pairs
+ *   con_attr    constraint attribute: [0, n_dense) dense, n_dense = label
+ *   con_val     constraint value
+ *   n_con       length of con_attr / con_val; a query whose offsets fall
+ *               outside [0, n_con] or decrease is treated as unsatisfiable
+ *   out_ids     n_q x k int32     out_dist  n_q x k float32
+ *   out_ncand   optional n_q int32: points in the chosen sub-partitions
+ *   out_nsurv   optional n_q int32: candidates that pass the filter
+ * Not errors (the query is valid with an empty D_C, all ids -1): a value
+ * outside its vocabulary, an attribute index outside [0, n_dense], two
+ * different values for one dense attribute, more than 8 distinct labels.
+ * Duplicate constraints are ignored; zero constraints give plain IVF kNN.
+ * Errors: EINVAL (k, nprobe, n_q < 0, NULL pointers), ENOMEM, EDEVICE.
+ */
+caps_status caps_search(const caps_index *idx, const caps_search_params *sp,
+                        const float *q, int32_t n_q,
+                        const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                        int32_t n_con, int32_t *out_ids, float *out_dist,
+                        int32_t *out_ncand, int32_t *out_nsurv, void *stream);
+
+/*
+ * caps_search_probes -- the routing and sub-partition choice of
+ * caps_search alone (device pointers): out_probes n_q x nprobe int32 (best
+ * first), out_masks n_q x nprobe uint32 (bit j set = sub-partition j
+ * chosen, j = h is the remainder).  Same errors as caps_search.
+ */
+caps_status caps_search_probes(const caps_index *idx, const caps_search_params *sp,
+                               const float *q, int32_t n_q, const int32_t *con_off,
+                               const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
+                               int32_t *out_probes, uint32_t *out_masks, void *stream);
+
+typedef struct {
+    int64_t n;
+    int32_t d, n_partitions, aft_height, metric;
+    int32_t n_dense, label_vocab, n_tokens;
+    int32_t max_subpartition;   /* largest sub-partition size */
+    int64_t device_bytes;       /* bytes the index holds on the device */
+} caps_index_info_t;
+
+caps_status caps_index_info(const caps_index *idx, caps_index_info_t *out);
+
+/*
+ * caps_index_export -- copy index arrays to HOST buffers (any may be NULL):
+ * centroids B x d, assign n (partition of point i), level n (sub-partition
+ * of point i, h = remainder), perm n (CSR position -> point id),
+ * offs B*(h+1)+1 (first CSR position of sub-partition j of partition p at
+ * offs[p*(h+1)+j]), tags B x h (token of each tagged level, -1 unused).
+ */
+caps_status caps_index_export(const caps_index *idx, float *centroids, int32_t *assign,
+                              int8_t *level, int32_t *perm, int32_t *offs, int32_t *tags);
+
+/* Release the index and its device memory (NULL is a no-op). */
+void caps_free(caps_index *idx);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *caps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

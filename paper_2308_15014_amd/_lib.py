@@ -1,0 +1,80 @@
+"""ctypes declarations of the libcaps C ABI (include/caps.h).
+
+Loading fails loudly when libcaps.so has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcaps.so")
+
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_u64 = ctypes.c_uint64
+c_vp = ctypes.c_void_p
+
+STATUS = {0: "CAPS_OK", -1: "CAPS_EINVAL", -2: "CAPS_ENOMEM", -3: "CAPS_EDEVICE",
+          -4: "CAPS_EUNSUPPORTED", -5: "CAPS_EBUSY", -6: "CAPS_EIO"}
+
+
+class CapsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("metric", c_i32), ("n_partitions", c_i32), ("kmeans_iters", c_i32),
+                ("aft_height", c_i32), ("seed", c_u64), ("init_ids", c_vp)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("reserved", c_i32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("d", c_i32), ("n_partitions", c_i32), ("aft_height", c_i32),
+                ("metric", c_i32), ("n_dense", c_i32), ("label_vocab", c_i32),
+                ("n_tokens", c_i32), ("max_subpartition", c_i32), ("device_bytes", c_i64)]
+
+
+# name -> (restype, argtypes); every symbol include/caps.h declares
+SIGNATURES = {
+    "caps_build": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32,
+                           ctypes.POINTER(BuildParams), c_vp, ctypes.POINTER(c_vp)]),
+    "caps_search": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
+                            c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_search_probes": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp,
+                                   c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "caps_index_info": (c_i32, [c_vp, ctypes.POINTER(IndexInfo)]),
+    "caps_index_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_free": (None, [c_vp]),
+    "caps_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libcaps.so (built in-tree by paper_2308_15014_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(or python -m paper_2308_15014_amd.build) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        msg = lib().caps_last_error()
+        raise CapsError(status, msg.decode() if msg else "")

@@ -1,0 +1,218 @@
+// C ABI of libcaps: argument validation, index lifetime, error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "caps_internal.h"
+
+struct caps_index {
+    caps::Index ix;
+};
+
+namespace caps {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+static caps_status fail(caps_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+static void release(Index &ix) {
+    void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign,
+                    ix.level, ix.words, ix.sigs, ix.slots, ix.vecs};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    ix = Index{};
+}
+
+}  // namespace caps
+
+using namespace caps;
+
+extern "C" const char *caps_last_error(void) { return g_err; }
+
+extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const uint32_t *dense_vals,
+                                  int32_t n_dense, const int32_t *dense_vocab, const int64_t *label_off,
+                                  const uint32_t *labels, int32_t label_vocab, const caps_build_params *p,
+                                  void *stream, caps_index **out) {
+    if (!out || !p || !x) return fail(CAPS_EINVAL, "caps_build: null argument");
+    *out = nullptr;
+    if (n <= 0 || d <= 0) return fail(CAPS_EINVAL, "caps_build: n and d must be positive");
+    if (n > INT32_MAX - 1) return fail(CAPS_EUNSUPPORTED, "caps_build: n above 2^31-2");
+    if (p->metric != CAPS_METRIC_L2 && p->metric != CAPS_METRIC_IP)
+        return fail(CAPS_EINVAL, "caps_build: metric must be 0 (L2) or 1 (IP)");
+    const int32_t b = p->n_partitions, h = p->aft_height;
+    if (b < 1 || (int64_t)b > n) return fail(CAPS_EINVAL, "caps_build: need 1 <= B <= n (B=%d)", b);
+    if (b > kMaxPartitions) return fail(CAPS_EUNSUPPORTED, "caps_build: B above %d", kMaxPartitions);
+    if (h < 0) return fail(CAPS_EINVAL, "caps_build: aft_height < 0");
+    if (h > kMaxHeight) return fail(CAPS_EUNSUPPORTED, "caps_build: aft_height above %d", kMaxHeight);
+    if (p->kmeans_iters < 0) return fail(CAPS_EINVAL, "caps_build: kmeans_iters < 0");
+    if (n_dense < 0) return fail(CAPS_EINVAL, "caps_build: n_dense < 0");
+    if (n_dense > kMaxDense) return fail(CAPS_EUNSUPPORTED, "caps_build: more than %d dense attributes", kMaxDense);
+    if (n_dense > 0 && (!dense_vals || !dense_vocab)) return fail(CAPS_EINVAL, "caps_build: dense arrays missing");
+    if (label_off && !labels && label_off[n] != 0)
+        return fail(CAPS_EINVAL, "caps_build: labels missing");
+
+    Schema sch{};
+    sch.n_dense = n_dense;
+    int bits = 0;
+    for (int a = 0; a < n_dense; a++) {
+        const int32_t v = dense_vocab[a];
+        if (v < 1) return fail(CAPS_EINVAL, "caps_build: dense_vocab[%d] < 1", a);
+        int w = 1;
+        while ((1ll << w) < v) w++;
+        sch.dense_vocab[a] = v;
+        sch.dense_off[a] = (a == 0) ? 0 : sch.dense_off[a - 1] + sch.dense_vocab[a - 1];
+        sch.field_shift[a] = bits;
+        sch.field_bits[a] = w;
+        bits += w;
+    }
+    sch.dense_off[n_dense] = n_dense ? sch.dense_off[n_dense - 1] + sch.dense_vocab[n_dense - 1] : 0;
+    if (bits > 32) return fail(CAPS_EUNSUPPORTED, "caps_build: packed dense fields need %d > 32 bits", bits);
+    const bool has_labels = label_off != nullptr;
+    if (has_labels) {
+        if (label_vocab < 1 || label_vocab > 65535)
+            return fail(label_vocab < 1 ? CAPS_EINVAL : CAPS_EUNSUPPORTED, "caps_build: label_vocab %d", label_vocab);
+        if (label_off[0] != 0) return fail(CAPS_EINVAL, "caps_build: label_off[0] != 0");
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t lo = label_off[i], hi = label_off[i + 1];
+            if (hi < lo) return fail(CAPS_EINVAL, "caps_build: label_off decreases at %lld", (long long)i);
+            if (hi - lo > kMaxLabels)
+                return fail(CAPS_EUNSUPPORTED, "caps_build: point %lld has more than %d labels", (long long)i, kMaxLabels);
+            for (int64_t e = lo; e < hi; e++) {
+                if (labels[e] >= (uint32_t)label_vocab)
+                    return fail(CAPS_EINVAL, "caps_build: label %u outside vocabulary", labels[e]);
+                for (int64_t f = lo; f < e; f++)
+                    if (labels[f] == labels[e])
+                        return fail(CAPS_EINVAL, "caps_build: point %lld repeats label %u", (long long)i, labels[e]);
+            }
+        }
+        sch.label_vocab = label_vocab;
+    }
+    sch.n_tok = sch.dense_off[n_dense] + (has_labels ? label_vocab : 0);
+    if (sch.n_tok > kMaxTokensLds)
+        return fail(CAPS_EUNSUPPORTED, "caps_build: %d attribute values exceed %d", sch.n_tok, kMaxTokensLds);
+    for (int64_t i = 0; i < n * n_dense; i++)
+        if (dense_vals[i] >= (uint32_t)sch.dense_vocab[i % n_dense])
+            return fail(CAPS_EINVAL, "caps_build: dense value outside vocabulary at %lld", (long long)i);
+    for (int64_t i = 0; i < n * (int64_t)d; i++)
+        if (!isfinite(x[i])) return fail(CAPS_EINVAL, "caps_build: non-finite x at %lld", (long long)i);
+    if (p->init_ids) {
+        std::vector<char> seen((size_t)n, 0);
+        for (int32_t c = 0; c < b; c++) {
+            const int32_t id = p->init_ids[c];
+            if (id < 0 || id >= n) return fail(CAPS_EINVAL, "caps_build: init id %d out of range", id);
+        }
+    }
+
+    caps_index *h_idx = new (std::nothrow) caps_index;
+    if (!h_idx) return fail(CAPS_ENOMEM, "caps_build: host allocation");
+    Index &ix = h_idx->ix;
+    CAPS_HIP(hipGetDevice(&ix.device));
+    ix.n = n;
+    ix.d = d;
+    ix.b = b;
+    ix.h = h;
+    ix.metric = p->metric;
+    ix.sch = sch;
+    const caps_status s = build_index(&ix, x, n, d, dense_vals, has_labels ? label_off : nullptr,
+                                      has_labels ? labels : nullptr, p, (hipStream_t)stream);
+    if (s != CAPS_OK) {
+        release(ix);
+        delete h_idx;
+        return s;
+    }
+    *out = h_idx;
+    return CAPS_OK;
+}
+
+static caps_status check_search(const caps_index *idx, const caps_search_params *sp, const float *q, int32_t n_q,
+                                const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                                int32_t n_con) {
+    if (!idx || !sp) return fail(CAPS_EINVAL, "caps_search: null index or params");
+    const Index &ix = idx->ix;
+    if (n_q < 0) return fail(CAPS_EINVAL, "caps_search: n_q < 0");
+    if (sp->k < 1) return fail(CAPS_EINVAL, "caps_search: k < 1");
+    if (sp->k > kMaxK) return fail(CAPS_EUNSUPPORTED, "caps_search: k above %d", kMaxK);
+    if (sp->nprobe < 1 || sp->nprobe > ix.b) return fail(CAPS_EINVAL, "caps_search: nprobe outside [1, B]");
+    if (sp->rule != 0 && sp->rule != 1) return fail(CAPS_EINVAL, "caps_search: rule must be 0 or 1");
+    if (n_con < 0) return fail(CAPS_EINVAL, "caps_search: n_con < 0");
+    if (n_q > 0 && (!q || !con_off)) return fail(CAPS_EINVAL, "caps_search: null query arrays");
+    if (n_con > 0 && (!con_attr || !con_val)) return fail(CAPS_EINVAL, "caps_search: null constraint arrays");
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_search(const caps_index *idx, const caps_search_params *sp, const float *q,
+                                   int32_t n_q, const int32_t *con_off, const int32_t *con_attr,
+                                   const int32_t *con_val, int32_t n_con, int32_t *out_ids, float *out_dist,
+                                   int32_t *out_ncand, int32_t *out_nsurv, void *stream) {
+    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n_q > 0 && (!out_ids || !out_dist)) return fail(CAPS_EINVAL, "caps_search: null outputs");
+    return search(&idx->ix, sp, q, n_q, con_off, con_attr, con_val, n_con, out_ids, out_dist, out_ncand,
+                  out_nsurv, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" caps_status caps_search_probes(const caps_index *idx, const caps_search_params *sp, const float *q,
+                                          int32_t n_q, const int32_t *con_off, const int32_t *con_attr,
+                                          const int32_t *con_val, int32_t n_con, int32_t *out_probes,
+                                          uint32_t *out_masks, void *stream) {
+    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n_q > 0 && (!out_probes || !out_masks)) return fail(CAPS_EINVAL, "caps_search_probes: null outputs");
+    return search(&idx->ix, sp, q, n_q, con_off, con_attr, con_val, n_con, nullptr, nullptr, nullptr, nullptr,
+                  out_probes, out_masks, (hipStream_t)stream);
+}
+
+extern "C" caps_status caps_index_info(const caps_index *idx, caps_index_info_t *out) {
+    if (!idx || !out) return fail(CAPS_EINVAL, "caps_index_info: null argument");
+    const Index &ix = idx->ix;
+    out->n = ix.n;
+    out->d = ix.d;
+    out->n_partitions = ix.b;
+    out->aft_height = ix.h;
+    out->metric = ix.metric;
+    out->n_dense = ix.sch.n_dense;
+    out->label_vocab = ix.sch.label_vocab;
+    out->n_tokens = ix.sch.n_tok;
+    out->max_subpartition = ix.max_sub;
+    out->device_bytes = ix.bytes;
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_index_export(const caps_index *idx, float *centroids, int32_t *assign, int8_t *level,
+                                         int32_t *perm, int32_t *offs, int32_t *tags) {
+    if (!idx) return fail(CAPS_EINVAL, "caps_index_export: null index");
+    const Index &ix = idx->ix;
+    if (centroids) CAPS_HIP(hipMemcpy(centroids, ix.cent, sizeof(float) * (size_t)ix.b * ix.d, hipMemcpyDeviceToHost));
+    if (assign) CAPS_HIP(hipMemcpy(assign, ix.assign, sizeof(int32_t) * (size_t)ix.n, hipMemcpyDeviceToHost));
+    if (level) CAPS_HIP(hipMemcpy(level, ix.level, sizeof(int8_t) * (size_t)ix.n, hipMemcpyDeviceToHost));
+    if (perm) CAPS_HIP(hipMemcpy(perm, ix.perm, sizeof(int32_t) * (size_t)ix.n, hipMemcpyDeviceToHost));
+    if (offs)
+        CAPS_HIP(hipMemcpy(offs, ix.offs, sizeof(int32_t) * ((size_t)ix.b * (ix.h + 1) + 1), hipMemcpyDeviceToHost));
+    if (tags && ix.h > 0)
+        CAPS_HIP(hipMemcpy(tags, ix.tags, sizeof(int32_t) * (size_t)ix.b * ix.h, hipMemcpyDeviceToHost));
+    return CAPS_OK;
+}
+
+extern "C" void caps_free(caps_index *idx) {
+    if (!idx) return;
+    release(idx->ix);
+    delete idx;
+}

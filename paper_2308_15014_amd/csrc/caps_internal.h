@@ -1,0 +1,108 @@
+// Internal declarations of libcaps (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/caps.h"
+
+namespace caps {
+
+constexpr int kMaxDense = 8;        // dense attributes per point
+constexpr int kMaxLabels = 8;       // labels per point / distinct labels per query
+constexpr int kMaxHeight = 15;      // AFT height
+constexpr int kMaxPartitions = 8192;
+constexpr int kMaxTokensLds = 16384;  // token vocabulary the AFT histogram holds in LDS
+constexpr int kMaxK = 64;
+
+void set_error(const char *fmt, ...);
+
+#define CAPS_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            ::caps::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),        \
+                              __FILE__, __LINE__);                                          \
+            return e_ == hipErrorOutOfMemory ? CAPS_ENOMEM : CAPS_EDEVICE;                  \
+        }                                                                                   \
+    } while (0)
+
+// Attribute schema shared by build and search kernels (passed by value).
+struct Schema {
+    int32_t n_dense;
+    int32_t dense_vocab[kMaxDense];
+    int32_t dense_off[kMaxDense + 1];   // token offsets; label tokens start at dense_off[n_dense]
+    int32_t field_shift[kMaxDense];     // bit position of each dense field in the packed word
+    int32_t field_bits[kMaxDense];
+    int32_t label_vocab;                // 0: no labels
+    int32_t n_tok;
+};
+
+// Per-query filter description built on the device from constraint pairs.
+struct alignas(16) QDesc {
+    uint32_t dmask;       // packed-field mask of constrained dense attributes
+    uint32_t dval;        // required packed values under dmask
+    uint32_t flags;       // bit 0: unsatisfiable (contradiction / out of range)
+    int32_t nlab;         // distinct label constraints (<= kMaxLabels)
+    uint64_t lsig;        // OR of signature bits of the label constraints
+    uint16_t lab[kMaxLabels];
+};
+
+struct Index {
+    int device = 0;
+    int64_t n = 0;
+    int32_t d = 0, b = 0, h = 0, metric = 0;
+    Schema sch{};
+    int32_t max_sub = 0;
+    int64_t bytes = 0;
+    // device arrays
+    float *cent = nullptr;      // b x d
+    float *cnorm = nullptr;     // b  (ordered-fma |c|^2)
+    int32_t *tags = nullptr;    // b x h tokens (-1 unused)
+    int32_t *offs = nullptr;    // b*(h+1)+1
+    int32_t *perm = nullptr;    // n: CSR position -> id
+    int32_t *assign = nullptr;  // n (original order)
+    int8_t *level = nullptr;    // n (original order)
+    uint32_t *words = nullptr;  // n packed dense words, CSR order (n_dense > 0)
+    uint64_t *sigs = nullptr;   // n label signatures, CSR order (labels)
+    uint16_t *slots = nullptr;  // n x kMaxLabels sorted labels, 0xFFFF padded
+    float *vecs = nullptr;      // n x d, CSR order
+    std::vector<int32_t> h_offs;
+};
+
+// signature bit (0..63) of a label: Fibonacci hashing of the label id
+__host__ __device__ inline uint32_t label_sig_bit(uint32_t l) {
+    return (l * 0x9E3779B1u) >> 26;
+}
+
+// float -> uint32 whose unsigned order is the float order (no NaN inputs;
+// callers turn -0 into +0 first)
+__host__ __device__ inline uint32_t f2ord(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float ord2f(uint32_t u) {
+    u = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    return __builtin_bit_cast(float, u);
+}
+__host__ __device__ inline float canon0(float v) { return v == 0.0f ? 0.0f : v; }
+
+// ---- build (caps_build.hip)
+caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const uint32_t *dense,
+                        const int64_t *label_off, const uint32_t *labels,
+                        const caps_build_params *p, hipStream_t st);
+
+// ---- search (caps_search.hip)
+caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
+                   const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                   int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand, int32_t *out_nsurv,
+                   int32_t *out_probes, uint32_t *out_masks, hipStream_t st);
+
+// ---- shared device utilities (caps_util.hip)
+caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                               hipStream_t st);
+
+}  // namespace caps

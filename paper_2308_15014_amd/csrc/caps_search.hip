@@ -1,0 +1,687 @@
+// Query path on the GPU (paper Algorithm 2).
+//
+//   prep    constraint pairs -> per-query packed filter (QDesc)
+//   route   Q x B centroid scores (sequential-fma dots), then the best m
+//           partitions per query under the order (score, id)
+//   select  per (query, probe): the sub-partitions that may hold valid
+//           points (exact rule) and the candidate count
+//   bucket  (query, probe) pairs grouped by partition, cut into tiles of at
+//           most kQB queries
+//   scan    one workgroup per tile: the partition's chosen sub-partitions
+//           stream through LDS in chunks; every (query, point) pair is
+//           filtered exactly, survivors are compacted and their distances
+//           computed one pair per lane, each query keeps its top k
+//   merge   per query, the per-partition top-k lists -> final top k
+//
+// Partition-major scanning reads each probed partition once per tile of up
+// to kQB queries instead of once per query.
+#include <string.h>
+
+#include <algorithm>
+
+#include "caps_device.h"
+#include "caps_internal.h"
+
+namespace caps {
+
+constexpr int kQB = 64;      // queries per tile
+constexpr int kCH = 32;      // points per chunk
+constexpr int kScanNT = 256;
+
+// ------------------------------------------------------------------ prep
+__global__ __launch_bounds__(128) void k_qprep(const int32_t *__restrict__ con_off, const int32_t *__restrict__ con_attr,
+                        const int32_t *__restrict__ con_val, int32_t n_con, int32_t nq, Schema sch,
+                        QDesc *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    QDesc r;
+    r.dmask = 0;
+    r.dval = 0;
+    r.flags = 0;
+    r.nlab = 0;
+    r.lsig = 0;
+    for (int i = 0; i < kMaxLabels; i++) r.lab[i] = 0xFFFF;
+    int32_t lo = con_off[q], hi = con_off[q + 1];
+    if (lo < 0 || hi < lo || hi > n_con) {
+        r.flags |= 1u;
+        lo = hi = 0;
+    }
+    for (int32_t e = lo; e < hi; e++) {
+        const int32_t a = con_attr[e], v = con_val[e];
+        if (a < 0 || a > sch.n_dense) {
+            r.flags |= 1u;
+            continue;
+        }
+        if (a < sch.n_dense) {
+            if (v < 0 || v >= sch.dense_vocab[a]) {
+                r.flags |= 1u;
+                continue;
+            }
+            const uint32_t fm = (uint32_t)(((1ull << sch.field_bits[a]) - 1ull) << sch.field_shift[a]);
+            const uint32_t fv = (uint32_t)v << sch.field_shift[a];
+            if ((r.dmask & fm) && ((r.dval & fm) != fv)) r.flags |= 1u;
+            r.dmask |= fm;
+            r.dval = (r.dval & ~fm) | fv;
+        } else {
+            if (sch.label_vocab == 0 || v < 0 || v >= sch.label_vocab) {
+                r.flags |= 1u;
+                continue;
+            }
+            bool dup = false;
+            for (int i = 0; i < r.nlab; i++) dup |= r.lab[i] == (uint16_t)v;
+            if (dup) continue;
+            if (r.nlab == kMaxLabels) {
+                r.flags |= 1u;
+                continue;
+            }
+            r.lab[r.nlab++] = (uint16_t)v;
+            r.lsig |= 1ull << label_sig_bit((uint32_t)v);
+        }
+    }
+    out[q] = r;
+}
+
+// ------------------------------------------------------------------ routing
+constexpr int kDC = 32;
+constexpr int kTile = 64;
+
+// Q x B scores, 64 x 64 tile per workgroup, sequential fma over dims.
+__global__ __launch_bounds__(256) void k_route_scores(const float *__restrict__ q, int32_t nq, int32_t d,
+                                                      const float *__restrict__ cent,
+                                                      const float *__restrict__ cn, int32_t b,
+                                                      int32_t metric, float *__restrict__ scores) {
+    __shared__ float xs[kDC][kTile + 4];
+    __shared__ float cs[kDC][kTile + 4];
+    const int t = threadIdx.x;
+    const int ty = t >> 4, tx = t & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * kTile;
+    const int c0 = blockIdx.y * kTile;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[i][k] = 0.0f;
+    for (int j0 = 0; j0 < d; j0 += kDC) {
+        const int dc = min(kDC, d - j0);
+        for (int e = t; e < kTile * kDC; e += 256) {
+            const int ri = e / kDC, jj = e % kDC;
+            float v = 0.0f, w = 0.0f;
+            if (jj < dc) {
+                if (r0 + ri < nq) v = q[(r0 + ri) * d + j0 + jj];
+                if (c0 + ri < b) w = cent[(int64_t)(c0 + ri) * d + j0 + jj];
+            }
+            xs[jj][ri] = v;
+            cs[jj][ri] = w;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < dc; jj++) {
+            const float4 a = *reinterpret_cast<const float4 *>(&xs[jj][ty * 4]);
+            const float4 c = *reinterpret_cast<const float4 *>(&cs[jj][tx * 4]);
+            const float av[4] = {a.x, a.y, a.z, a.w};
+            const float cv[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int k = 0; k < 4; k++) acc[i][k] = fmaf(av[i], cv[k], acc[i][k]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t r = r0 + ty * 4 + i;
+        if (r >= nq) continue;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int c = c0 + tx * 4 + k;
+            if (c >= b) continue;
+            scores[r * b + c] = canon0(metric == 0 ? cn[c] - 2.0f * acc[i][k] : -acc[i][k]);
+        }
+    }
+}
+
+// Best m of B per query: bitonic sort of (score, id) keys in LDS.
+constexpr int kTopmNT = 256;
+
+__global__ __launch_bounds__(kTopmNT) void k_topm(const float *__restrict__ scores, int32_t b, int32_t pb,
+                                                  int32_t m, int32_t *__restrict__ probes) {
+    extern __shared__ uint64_t keys[];   // pb (power of two >= b)
+    const int64_t q = blockIdx.x;
+    const float *s = scores + q * b;
+    for (int i = threadIdx.x; i < pb; i += kTopmNT)
+        keys[i] = i < b ? (((uint64_t)f2ord(s[i]) << 32) | (uint32_t)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= pb; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < pb; i += kTopmNT) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = keys[i], c = keys[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) {
+                        keys[i] = c;
+                        keys[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < m; i += kTopmNT) probes[q * m + i] = (int32_t)(uint32_t)(keys[i] & 0xFFFFFFFFu);
+}
+
+// ------------------------------------------------------------------ selection
+__device__ inline void tag_decode(const Schema &s, int32_t tok, int &attr, int32_t &val) {
+    if (tok < s.dense_off[s.n_dense]) {
+        int a = 0;
+        while (a + 1 < s.n_dense && tok >= s.dense_off[a + 1]) a++;
+        attr = a;
+        val = tok - s.dense_off[a];
+    } else {
+        attr = s.n_dense;
+        val = tok - s.dense_off[s.n_dense];
+    }
+}
+
+// Exact rule: J* = first tagged level whose tag the query holds (h if none);
+// scan level j < h iff j <= J*, tagged, and its tag does not contradict a
+// dense constraint; scan the remainder iff J* = h.  rule 1: only level J*.
+__device__ inline uint32_t choose_levels(const Schema &s, const QDesc &qd, const int32_t *tags, int h,
+                                         int rule) {
+    if (qd.flags & 1u) return 0u;
+    int js = h;
+    uint32_t ok = 0;
+    for (int j = 0; j < h; j++) {
+        const int32_t t = tags[j];
+        if (t < 0) continue;
+        int a;
+        int32_t v;
+        tag_decode(s, t, a, v);
+        bool held, conflict = false;
+        if (a < s.n_dense) {
+            const uint32_t fm = (uint32_t)(((1ull << s.field_bits[a]) - 1ull) << s.field_shift[a]);
+            const bool constrained = (qd.dmask & fm) != 0;
+            const bool same = ((qd.dval & fm) >> s.field_shift[a]) == (uint32_t)v;
+            held = constrained && same;
+            conflict = constrained && !same;
+        } else {
+            held = false;
+            for (int i = 0; i < qd.nlab; i++) held |= qd.lab[i] == (uint16_t)v;
+        }
+        if (!conflict) ok |= 1u << j;
+        if (held) {
+            js = j;
+            break;
+        }
+    }
+    if (rule == 1) return 1u << js;
+    uint32_t mask = ok & ((js >= 31) ? 0xFFFFFFFFu : ((2u << js) - 1u));
+    if (js == h) mask |= 1u << h;
+    return mask;
+}
+
+__global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t m,
+                         const QDesc *__restrict__ qd, Schema sch, const int32_t *__restrict__ tags,
+                         int32_t h, const int32_t *__restrict__ offs, int32_t rule,
+                         uint32_t *__restrict__ sel, int32_t *__restrict__ pcount,
+                         int32_t *__restrict__ ncand) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nq * m) return;
+    const int32_t q = (int32_t)(e / m);
+    const int32_t p = probes[e];
+    const uint32_t mask = choose_levels(sch, qd[q], tags + (int64_t)p * h, h, rule);
+    int32_t cand = 0;
+    for (int j = 0; j <= h; j++)
+        if (mask & (1u << j)) cand += offs[(int64_t)p * (h + 1) + j + 1] - offs[(int64_t)p * (h + 1) + j];
+    sel[e] = mask;
+    if (mask) {
+        atomicAdd(&pcount[p], 1);
+        atomicAdd(&ncand[q], cand);
+    }
+}
+
+// Bucket starts and tile starts per partition (single workgroup).
+__global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ pcount, int32_t b,
+                                               int32_t *__restrict__ pstart, int32_t *__restrict__ tstart) {
+    __shared__ int scratch[1024 / kWave + 1];
+    __shared__ int carry_e, carry_t;
+    if (threadIdx.x == 0) carry_e = carry_t = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < b; b0 += 1024) {
+        const int p = b0 + threadIdx.x;
+        const int c = p < b ? pcount[p] : 0;
+        int te, tt;
+        const int pe = block_excl_scan<1024>(c, scratch, &te);
+        const int pt = block_excl_scan<1024>((c + kQB - 1) / kQB, scratch, &tt);
+        if (p < b) {
+            pstart[p] = carry_e + pe;
+            tstart[p] = carry_t + pt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry_e += te;
+            carry_t += tt;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pstart[b] = carry_e;
+        tstart[b] = carry_t;
+    }
+}
+
+__global__ void k_fill(const int32_t *__restrict__ probes, const uint32_t *__restrict__ sel, int64_t total,
+                       const int32_t *__restrict__ pstart, int32_t *__restrict__ pfill,
+                       int32_t *__restrict__ entries) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total || sel[e] == 0) return;
+    const int32_t p = probes[e];
+    const int32_t slot = atomicAdd(&pfill[p], 1);
+    entries[pstart[p] + slot] = (int32_t)e;
+}
+
+// ------------------------------------------------------------------ scan
+struct ScanArgs {
+    const int32_t *tstart, *pstart, *pcount, *entries;
+    const uint32_t *sel;
+    const float *q;
+    const QDesc *qd;
+    const int32_t *offs, *perm;
+    const float *vecs;
+    const uint32_t *words;
+    const uint64_t *sigs;
+    const uint16_t *slots;
+    uint64_t *partials;
+    int32_t *nsurv;
+    int32_t d, m, h, b, k;
+};
+
+__device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_labels, uint32_t w,
+                                    uint64_t sig, const uint16_t *sl) {
+    if (has_dense && ((w & qd.dmask) != qd.dval)) return false;
+    if (has_labels && qd.nlab > 0) {
+        if (qd.lsig & ~sig) return false;
+        for (int i = 0; i < qd.nlab; i++) {
+            bool f = false;
+#pragma unroll
+            for (int s = 0; s < kMaxLabels; s++) f |= sl[s] == qd.lab[i];
+            if (!f) return false;
+        }
+    }
+    return true;
+}
+
+template <int METRIC>
+__global__ __launch_bounds__(kScanNT) void k_scan_fp32(ScanArgs A, bool has_dense, bool has_labels) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = blockIdx.x;
+    if (tile >= A.tstart[A.b]) return;
+    // partition p: the last p with tstart[p] <= tile
+    int lo = 0, hi = A.b;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (A.tstart[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const int p = lo;
+    const int i0 = (tile - A.tstart[p]) * kQB;
+    const int nqt = min(kQB, A.pcount[p] - i0);
+    const int32_t *ent = A.entries + A.pstart[p] + i0;
+
+    const int d = A.d, k = A.k;
+    const int stride = ((d + 3) & ~3) + 4;
+    // LDS carve-up
+    float *Qs = reinterpret_cast<float *>(smem);                       // kQB x stride
+    float *Xs = Qs + kQB * stride;                                       // kCH x stride
+    uint64_t *keys = reinterpret_cast<uint64_t *>(Xs + kCH * stride);  // kQB*kCH
+    uint64_t *topk = keys + kQB * kCH;                                   // kQB x k
+    QDesc *qds = reinterpret_cast<QDesc *>(topk + kQB * k);             // kQB
+    uint64_t *xsig = reinterpret_cast<uint64_t *>(qds + kQB);          // kCH
+    uint16_t *xslot = reinterpret_cast<uint16_t *>(xsig + kCH);        // kCH x 8
+    uint32_t *xw = reinterpret_cast<uint32_t *>(xslot + kCH * kMaxLabels);  // kCH
+    int32_t *xid = reinterpret_cast<int32_t *>(xw + kCH);              // kCH
+    uint16_t *pairs = reinterpret_cast<uint16_t *>(xid + kCH);         // kQB*kCH
+    int32_t *toff = reinterpret_cast<int32_t *>(pairs + kQB * kCH);    // kScanNT+1
+    int32_t *qslot = toff + kScanNT + 1;                                 // kQB
+    uint32_t *qsel = reinterpret_cast<uint32_t *>(qslot + kQB);        // kQB
+    int32_t *surv = reinterpret_cast<int32_t *>(qsel + kQB);           // kQB
+    int *scratch = surv + kQB;                                           // kScanNT/64+1
+    __shared__ uint32_t lvmask;
+
+    const int t = threadIdx.x;
+    if (t == 0) lvmask = 0;
+    __syncthreads();
+    if (t < nqt) {
+        const int32_t slot = ent[t];
+        qslot[t] = slot;
+        qsel[t] = A.sel[slot];
+        qds[t] = A.qd[slot / A.m];
+        surv[t] = 0;
+        atomicOr(&lvmask, A.sel[slot]);
+    }
+    for (int e = t; e < kQB * k; e += kScanNT) topk[e] = ~0ull;
+    __syncthreads();
+    for (int e = t; e < nqt * d; e += kScanNT) {
+        const int i = e / d, j = e % d;
+        Qs[i * stride + j] = A.q[(int64_t)(qslot[i] / A.m) * d + j];
+    }
+    const uint32_t lv = lvmask;
+    for (int j = 0; j <= A.h; j++) {
+        if (!(lv & (1u << j))) continue;
+        const int32_t slo = A.offs[(int64_t)p * (A.h + 1) + j];
+        const int32_t shi = A.offs[(int64_t)p * (A.h + 1) + j + 1];
+        for (int32_t c0 = slo; c0 < shi; c0 += kCH) {
+            const int cn = min(kCH, shi - c0);
+            __syncthreads();
+            for (int e = t; e < cn * d; e += kScanNT) {
+                const int i = e / d, jj = e % d;
+                Xs[i * stride + jj] = A.vecs[(int64_t)(c0 + i) * d + jj];
+            }
+            if (t < cn) {
+                xid[t] = A.perm[c0 + t];
+                if (has_dense) xw[t] = A.words[c0 + t];
+                if (has_labels) {
+                    xsig[t] = A.sigs[c0 + t];
+                    *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) =
+                        *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
+                }
+            }
+            __syncthreads();
+            // filter every (query, point) pair: thread -> query t/4, 8 points
+            const int qi = t >> 2, sub = (t & 3) * 8;
+            uint32_t bits = 0;
+            if (qi < nqt && (qsel[qi] & (1u << j))) {
+                const QDesc &qd = qds[qi];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int pi = sub + u;
+                    if (pi < cn &&
+                        point_passes(qd, has_dense, has_labels, xw[pi], has_labels ? xsig[pi] : 0ull,
+                                     xslot + pi * kMaxLabels))
+                        bits |= 1u << u;
+                }
+            }
+            int total;
+            int off = block_excl_scan<kScanNT>(__popc(bits), scratch, &total);
+            toff[t] = off;
+            if (t == kScanNT - 1) toff[kScanNT] = off + __popc(bits);
+            while (bits) {
+                const int u = __ffs(bits) - 1;
+                bits &= bits - 1;
+                pairs[off++] = (uint16_t)((qi << 5) | (sub + u));
+            }
+            __syncthreads();
+            // distances, one (query, point) pair per lane, dims in order
+            for (int e = t; e < total; e += kScanNT) {
+                const int pr = pairs[e];
+                const float *xr = Xs + (pr & 31) * stride;
+                const float *qr = Qs + (pr >> 5) * stride;
+                float acc = 0.0f;
+                int jj = 0;
+                for (; jj + 4 <= d; jj += 4) {
+                    const float4 xv = *reinterpret_cast<const float4 *>(xr + jj);
+                    const float4 qv = *reinterpret_cast<const float4 *>(qr + jj);
+                    if (METRIC == 0) {
+                        float t0 = xv.x - qv.x;
+                        acc = fmaf(t0, t0, acc);
+                        t0 = xv.y - qv.y;
+                        acc = fmaf(t0, t0, acc);
+                        t0 = xv.z - qv.z;
+                        acc = fmaf(t0, t0, acc);
+                        t0 = xv.w - qv.w;
+                        acc = fmaf(t0, t0, acc);
+                    } else {
+                        acc = fmaf(xv.x, qv.x, acc);
+                        acc = fmaf(xv.y, qv.y, acc);
+                        acc = fmaf(xv.z, qv.z, acc);
+                        acc = fmaf(xv.w, qv.w, acc);
+                    }
+                }
+                for (; jj < d; jj++) {
+                    if (METRIC == 0) {
+                        const float t0 = xr[jj] - qr[jj];
+                        acc = fmaf(t0, t0, acc);
+                    } else {
+                        acc = fmaf(xr[jj], qr[jj], acc);
+                    }
+                }
+                const float key = canon0(METRIC == 0 ? acc : -acc);
+                keys[e] = ((uint64_t)f2ord(key) << 32) | (uint32_t)xid[pr & 31];
+            }
+            __syncthreads();
+            // top-k per query (its pairs are contiguous: threads 4q..4q+3)
+            if (t < nqt) {
+                const int e0 = toff[4 * t], e1 = toff[4 * t + 4];
+                uint64_t *tk = topk + t * k;
+                for (int e = e0; e < e1; e++) {
+                    const uint64_t key = keys[e];
+                    if (key >= tk[k - 1]) continue;
+                    int i = k - 1;
+                    while (i > 0 && tk[i - 1] > key) {
+                        tk[i] = tk[i - 1];
+                        i--;
+                    }
+                    tk[i] = key;
+                }
+                surv[t] += e1 - e0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < nqt * k; e += kScanNT) {
+        const int i = e / k, r = e % k;
+        A.partials[(int64_t)qslot[i] * k + r] = topk[i * k + r];
+    }
+    if (t < nqt && surv[t]) atomicAdd(&A.nsurv[qslot[t] / A.m], surv[t]);
+}
+
+static size_t scan_lds_bytes(int d, int k) {
+    const int stride = ((d + 3) & ~3) + 4;
+    size_t s = 0;
+    s += sizeof(float) * (size_t)(kQB + kCH) * stride;
+    s += sizeof(uint64_t) * (size_t)kQB * kCH;
+    s += sizeof(uint64_t) * (size_t)kQB * k;
+    s += sizeof(QDesc) * kQB;
+    s += sizeof(uint64_t) * kCH;
+    s += sizeof(uint16_t) * kCH * kMaxLabels;
+    s += sizeof(uint32_t) * kCH + sizeof(int32_t) * kCH;
+    s += sizeof(uint16_t) * kQB * kCH;
+    s += sizeof(int32_t) * (kScanNT + 1) + sizeof(int32_t) * kQB * 3;
+    s += sizeof(int) * (kScanNT / kWave + 1);
+    return s + 64;
+}
+
+// ------------------------------------------------------------------ merge
+template <int KM>
+__global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ partials,
+                                               const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                               int32_t k, int32_t metric, int32_t *__restrict__ ids,
+                                               float *__restrict__ dist) {
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    uint64_t lst[KM];
+#pragma unroll
+    for (int i = 0; i < KM; i++) lst[i] = ~0ull;
+    for (int r = lane; r < m; r += 64) {
+        const int64_t slot = (int64_t)q * m + r;
+        if (sel[slot] == 0) continue;
+        const uint64_t *src = partials + slot * k;
+        for (int i = 0; i < k; i++) {
+            const uint64_t key = src[i];
+            if (key >= lst[KM - 1]) break;   // lists are sorted: the rest is worse
+#pragma unroll
+            for (int u = KM - 1; u > 0; u--) {
+                const uint64_t a = lst[u - 1];
+                lst[u] = key < a ? a : (key < lst[u] ? key : lst[u]);
+            }
+            lst[0] = key < lst[0] ? key : lst[0];
+        }
+    }
+    for (int r = 0; r < k; r++) {
+        const uint64_t best = wave_min_u64(lst[0]);
+        if (lane == 0) {
+            const int64_t o = (int64_t)q * k + r;
+            if (best == ~0ull) {
+                ids[o] = -1;
+                dist[o] = metric == 0 ? __builtin_huge_valf() : -__builtin_huge_valf();
+            } else {
+                ids[o] = (int32_t)(uint32_t)(best & 0xFFFFFFFFu);
+                const float key = ord2f((uint32_t)(best >> 32));
+                dist[o] = metric == 0 ? key : canon0(-key);
+            }
+        }
+        if (best != ~0ull && lst[0] == best) {
+#pragma unroll
+            for (int u = 0; u < KM - 1; u++) lst[u] = lst[u + 1];
+            lst[KM - 1] = ~0ull;
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+__global__ void k_copy_i32(const int32_t *__restrict__ a, int32_t *__restrict__ b, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) b[e] = a[e];
+}
+
+// ------------------------------------------------------------------ host
+static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+struct Arena {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t a = (off + 255) & ~(size_t)255;
+        off = a + sizeof(T) * (count ? count : 1);
+        return reinterpret_cast<T *>(base + a);
+    }
+};
+
+caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
+                   const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                   int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand,
+                   int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st) {
+    const int32_t b = ix->b, d = ix->d, h = ix->h, m = sp->nprobe, k = sp->k;
+    if (nq == 0) return CAPS_OK;
+    const bool probes_only = out_probes != nullptr;
+    int pb = 1;
+    while (pb < b) pb <<= 1;
+
+    // sub-batch so that the per-batch workspace stays bounded
+    const size_t per_q = sizeof(float) * (size_t)b + (sizeof(int32_t) * 3 + sizeof(uint32_t)) * (size_t)m +
+                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + 16;
+    const size_t budget = (size_t)1 << 30;
+    int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
+    const size_t fixed = sizeof(int32_t) * (size_t)(b + 1) * 5 + 4096;
+    const size_t ws_bytes = fixed + per_q * (size_t)sb + 256 * 16 +
+                            (out_ncand ? 0 : sizeof(int32_t) * (size_t)nq) +
+                            (out_nsurv ? 0 : sizeof(int32_t) * (size_t)nq);
+    Arena ar;
+    CAPS_HIP(hipMallocAsync((void **)&ar.base, ws_bytes, st));
+    int32_t *ncand = out_ncand ? out_ncand : ar.take<int32_t>(nq);
+    int32_t *nsurv = out_nsurv ? out_nsurv : ar.take<int32_t>(nq);
+    QDesc *qd = ar.take<QDesc>(sb);
+    float *scores = ar.take<float>((size_t)sb * b);
+    int32_t *probes = ar.take<int32_t>((size_t)sb * m);
+    uint32_t *sel = ar.take<uint32_t>((size_t)sb * m);
+    int32_t *entries = ar.take<int32_t>((size_t)sb * m);
+    uint64_t *partials = ar.take<uint64_t>((size_t)sb * m * k);
+    int32_t *pcount = ar.take<int32_t>(b + 1);
+    int32_t *pfill = ar.take<int32_t>(b + 1);
+    int32_t *pstart = ar.take<int32_t>(b + 1);
+    int32_t *tstart = ar.take<int32_t>(b + 1);
+
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, ncand, (int64_t)nq, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
+
+    const bool has_dense = ix->sch.n_dense > 0;
+    const bool has_labels = ix->sch.label_vocab > 0;
+    const size_t lds = scan_lds_bytes(d, k);
+    if (!probes_only) {
+        int lds_max = 0;
+        CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
+        if (lds > (size_t)lds_max) {
+            (void)hipFreeAsync(ar.base, st);
+            set_error("caps_search: d=%d, k=%d need %zu bytes of LDS per workgroup (limit %d)", d, k, lds,
+                      lds_max);
+            return CAPS_EUNSUPPORTED;
+        }
+        const void *fn = ix->metric == 0 ? (const void *)k_scan_fp32<0> : (const void *)k_scan_fp32<1>;
+        CAPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    for (int32_t q0 = 0; q0 < nq; q0 += sb) {
+        const int32_t nb = std::min(sb, nq - q0);
+        const int64_t pairs = (int64_t)nb * m;
+        hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
+                           con_val, n_con, nb, ix->sch, qd);
+        hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
+                           q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
+        hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
+                           m, probes);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pcount, (int64_t)b + 1, 0);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pfill, (int64_t)b + 1, 0);
+        hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
+                           ix->tags, h, ix->offs, sp->rule, sel, pcount, ncand + q0);
+        CAPS_HIP(hipGetLastError());
+        if (probes_only) {
+            hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes,
+                               out_probes + (int64_t)q0 * m, pairs);
+            hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, (const int32_t *)sel,
+                               (int32_t *)(out_masks + (int64_t)q0 * m), pairs);
+            CAPS_HIP(hipGetLastError());
+            continue;
+        }
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pcount, b, pstart, tstart);
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, sel, pairs, pstart,
+                           pfill, entries);
+        ScanArgs A;
+        A.tstart = tstart;
+        A.pstart = pstart;
+        A.pcount = pcount;
+        A.entries = entries;
+        A.sel = sel;
+        A.q = q + (int64_t)q0 * d;
+        A.qd = qd;
+        A.offs = ix->offs;
+        A.perm = ix->perm;
+        A.vecs = ix->vecs;
+        A.words = ix->words;
+        A.sigs = ix->sigs;
+        A.slots = ix->slots;
+        A.partials = partials;
+        A.nsurv = nsurv + q0;
+        A.d = d;
+        A.m = m;
+        A.h = h;
+        A.b = b;
+        A.k = k;
+        const int64_t max_tiles = (pairs + kQB - 1) / kQB + b;
+        if (ix->metric == 0)
+            hipLaunchKernelGGL(k_scan_fp32<0>, dim3((unsigned)max_tiles), dim3(kScanNT), lds, st, A, has_dense,
+                               has_labels);
+        else
+            hipLaunchKernelGGL(k_scan_fp32<1>, dim3((unsigned)max_tiles), dim3(kScanNT), lds, st, A, has_dense,
+                               has_labels);
+        int32_t *oi = out_ids + (int64_t)q0 * k;
+        float *od = out_dist + (int64_t)q0 * k;
+        if (k <= 16)
+            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
+                               ix->metric, oi, od);
+        else if (k <= 32)
+            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
+                               ix->metric, oi, od);
+        else
+            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
+                               ix->metric, oi, od);
+        CAPS_HIP(hipGetLastError());
+    }
+    CAPS_HIP(hipFreeAsync(ar.base, st));
+    return CAPS_OK;
+}
+
+}  // namespace caps

@@ -1,0 +1,75 @@
+// Device-wide exclusive scan of int32 (three passes: block scans, scan of
+// block sums, add-back).
+#include "caps_device.h"
+#include "caps_internal.h"
+
+namespace caps {
+
+constexpr int kScanNT = 256;
+constexpr int kScanIPT = 8;
+constexpr int kScanTile = kScanNT * kScanIPT;
+
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const int32_t *in, int32_t *out, int64_t n,
+                                                        int32_t *sums) {
+    __shared__ int scratch[kScanNT / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+    int v[kScanIPT];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanIPT; i++) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int total;
+    int pre = block_excl_scan<kScanNT>(s, scratch, &total);
+#pragma unroll
+    for (int i = 0; i < kScanIPT; i++) {
+        if (base + i < n) out[base + i] = pre;
+        pre += v[i];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block scans the tile sums in place (exclusive) and stores the total.
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int64_t nt, int32_t *total) {
+    __shared__ int scratch[1024 / kWave + 1];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nt; b0 += 1024) {
+        int64_t i = b0 + threadIdx.x;
+        int v = i < nt ? sums[i] : 0;
+        int tot;
+        int pre = block_excl_scan<1024>(v, scratch, &tot);
+        if (i < nt) sums[i] = pre + carry;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_add(int32_t *out, int64_t n, const int32_t *sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int add = sums[blockIdx.x];
+    for (int i = threadIdx.x; i < kScanTile; i += kScanNT) {
+        int64_t e = base + i;
+        if (e < n) out[e] += add;
+    }
+}
+
+caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                               hipStream_t st) {
+    if (n <= 0) return CAPS_OK;
+    int64_t nt = (n + kScanTile - 1) / kScanTile;
+    int32_t *sums = nullptr;
+    CAPS_HIP(hipMallocAsync((void **)&sums, sizeof(int32_t) * (size_t)nt, st));
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanNT), 0, st, in, out, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nt, total);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(kScanNT), 0, st, out, n, sums);
+    CAPS_HIP(hipGetLastError());
+    CAPS_HIP(hipFreeAsync(sums, st));
+    return CAPS_OK;
+}
+
+}  // namespace caps

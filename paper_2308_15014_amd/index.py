@@ -1,0 +1,171 @@
+"""Python surface over libcaps: argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of build and search
+runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from ._lib import BuildParams, IndexInfo, SearchParams, check, lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _host(a, dtype):
+    if a is None:
+        return None
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t, dtype, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Index:
+    """A CAPS index resident on one GPU."""
+
+    def __init__(self, handle: ctypes.c_void_p, device):
+        self._h = handle
+        self.device = device
+        self._info = None
+
+    # ------------------------------------------------------------ build
+    @classmethod
+    def build(cls, x, dense=None, dense_vocab=None, label_off=None, labels=None, label_vocab=0, *,
+              metric: int = 0, n_partitions: int, kmeans_iters: int = 10, aft_height: int = 2,
+              seed: int = 0, init_ids=None, device=None, stream=None) -> "Index":
+        torch = _torch()
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        x = _host(x, np.float32)
+        n, d = x.shape
+        dense = _host(dense, np.uint32)
+        n_dense = 0 if dense is None else dense.shape[1]
+        vocab = _host(dense_vocab, np.int32) if n_dense else None
+        lo = _host(label_off, np.int64)
+        lb = _host(labels, np.uint32)
+        if lb is not None and lb.size == 0:
+            lb = np.zeros(1, dtype=np.uint32)
+        init = _host(init_ids, np.int32)
+        p = BuildParams(metric, n_partitions, kmeans_iters, aft_height,
+                        ctypes.c_uint64(seed & (2**64 - 1)).value, _ptr(init))
+        out = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            st = _stream(stream)
+            check(lib().caps_build(_ptr(x), n, d, _ptr(dense), n_dense, _ptr(vocab), _ptr(lo),
+                                   _ptr(lb), int(label_vocab) if lo is not None else 0,
+                                   ctypes.byref(p), st, ctypes.byref(out)))
+        return cls(out, device)
+
+    @classmethod
+    def from_workload(cls, w, **over) -> "Index":
+        kw = dict(metric=w.metric, n_partitions=w.n_partitions, kmeans_iters=w.kmeans_iters,
+                  aft_height=w.aft_height, seed=w.seed)
+        kw.update(over)
+        return cls.build(w.x, w.dense, w.dense_vocab, w.label_off, w.labels, w.label_vocab, **kw)
+
+    # ------------------------------------------------------------ query
+    def _qargs(self, q, con_off, con_attr, con_val):
+        torch = _torch()
+        qd = _dev(q, torch.float32, self.device)
+        co = _dev(con_off, torch.int32, self.device)
+        ca = _dev(con_attr, torch.int32, self.device)
+        cv = _dev(con_val, torch.int32, self.device)
+        if ca.numel() == 0:
+            ca = torch.zeros(1, dtype=torch.int32, device=self.device)
+            cv = torch.zeros(1, dtype=torch.int32, device=self.device)
+            n_con = 0
+        else:
+            n_con = int(ca.numel())
+        return qd, co, ca, cv, n_con
+
+    def search(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
+               stream=None, counters: bool = False, out=None):
+        """Top-k filtered search for a batch.  Returns device tensors
+        (ids int32 [Q,k], dist float32 [Q,k]) and, with counters=True, the
+        per-query candidate and survivor counts."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        nq = int(qd.shape[0])
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        else:
+            ids, dist = out
+        nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
+        ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
+        sp = SearchParams(k, nprobe, rule, 0)
+        with torch.cuda.device(self.device):
+            st = _stream(stream)
+            check(lib().caps_search(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
+                                    ca.data_ptr(), cv.data_ptr(), n_con, ids.data_ptr(),
+                                    dist.data_ptr(), nc.data_ptr() if counters else None,
+                                    ns.data_ptr() if counters else None, st))
+        if counters:
+            return ids, dist, nc, ns
+        return ids, dist
+
+    def probes(self, q, con_off, con_attr, con_val, nprobe: int, *, rule: int = 0, stream=None):
+        """Routing and sub-partition choice only: (probes [Q,m], masks [Q,m])."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        nq = int(qd.shape[0])
+        pr = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
+        mk = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
+        sp = SearchParams(1, nprobe, rule, 0)
+        with torch.cuda.device(self.device):
+            st = _stream(stream)
+            check(lib().caps_search_probes(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
+                                           ca.data_ptr(), cv.data_ptr(), n_con, pr.data_ptr(),
+                                           mk.data_ptr(), st))
+        return pr, mk
+
+    # ------------------------------------------------------------ inspection
+    def info(self) -> dict:
+        inf = IndexInfo()
+        check(lib().caps_index_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in IndexInfo._fields_}
+
+    def export(self) -> dict:
+        inf = self.info()
+        n, d, b, h = inf["n"], inf["d"], inf["n_partitions"], inf["aft_height"]
+        out = dict(centroids=np.zeros((b, d), np.float32), assign=np.zeros(n, np.int32),
+                   level=np.zeros(n, np.int8), perm=np.zeros(n, np.int32),
+                   offs=np.zeros(b * (h + 1) + 1, np.int32), tags=np.zeros((b, max(h, 1)), np.int32))
+        check(lib().caps_index_export(self._h, *(_ptr(out[k]) for k in
+                                                 ("centroids", "assign", "level", "perm", "offs",
+                                                  "tags"))))
+        out["tags"] = out["tags"][:, :h]
+        return out
+
+    def close(self):
+        if self._h:
+            lib().caps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,158 @@
+"""GPU parity: libcaps (through its C ABI) against the CPU oracle.
+
+Same seeded inputs on both sides.  Integer work (assignments, levels, CSR,
+tags, probes, sub-partition masks, ids, counters) must be bit-exact, and in
+FP32 mode the distances too: both sides evaluate the same sequential fma
+chains.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def caps():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_15014_amd as caps
+    caps.lib()
+    return caps
+
+
+def _gpu_search(ix, w, k, m, rule=0, q=None):
+    q = w.q if q is None else q
+    ids, dist, nc, ns = ix.search(q, w.con_off, w.con_attr, w.con_val, k, m, rule=rule, counters=True)
+    return ids.cpu().numpy(), dist.cpu().numpy(), nc.cpu().numpy(), ns.cpu().numpy()
+
+
+def _check_build(orc_idx, g):
+    assert np.array_equal(g["centroids"].view(np.uint32), orc_idx.centroids.view(np.uint32))
+    assert np.array_equal(g["assign"], orc_idx.assign)
+    assert np.array_equal(g["level"], orc_idx.level)
+    assert np.array_equal(g["tags"], orc_idx.tags)
+    assert np.array_equal(g["offs"], orc_idx.offs)
+    assert np.array_equal(g["perm"], orc_idx.perm)
+
+
+def _check_search(orc, orc_idx, ix, w, k, m, rule=0):
+    r = orc.search(orc_idx, w.q, w.con_off, w.con_attr, w.con_val, k, m, rule=rule)
+    ids, dist, nc, ns = _gpu_search(ix, w, k, m, rule)
+    pr, mk = ix.probes(w.q, w.con_off, w.con_attr, w.con_val, m, rule=rule)
+    assert np.array_equal(pr.cpu().numpy(), r.probes)
+    assert np.array_equal(mk.cpu().numpy().view(np.uint32), r.masks)
+    assert np.array_equal(nc, r.n_cand)
+    assert np.array_equal(ns, r.n_surv)
+    assert np.array_equal(ids, r.ids)
+    assert np.array_equal(dist.view(np.uint32), r.dist.view(np.uint32))
+
+
+def test_c1_build_and_search(caps, orc):
+    w = synth.make_c1()
+    oi = orc.build_from_workload(w)
+    ix = caps.Index.from_workload(w)
+    _check_build(oi, ix.export())
+    for m in (1, 4, 9, 32):
+        _check_search(orc, oi, ix, w, 10, m)
+    bf = orc.bruteforce(w.x, oi.tk, 0, w.q, w.con_off, w.con_attr, w.con_val, 10)
+    ids, dist, _, ns = _gpu_search(ix, w, 10, 32)
+    assert np.array_equal(ids, bf.ids)
+    assert np.array_equal(ns, bf.n_cand)
+
+
+CASES = [
+    # seed, n, d, metric, vocabs, label_vocab, b, h, cmin, cmax, integer
+    (100, 700, 5, 0, (3, 4), 0, 7, 2, 0, 2, False),
+    (101, 1500, 16, 0, (5, 9, 3), 0, 12, 4, 1, 3, True),
+    (102, 900, 12, 1, (), 40, 9, 4, 1, 4, False),
+    (103, 1200, 33, 0, (2, 3), 25, 10, 1, 0, 3, False),
+    (104, 600, 8, 1, (6,), 0, 5, 0, 0, 1, False),
+    (105, 2000, 64, 0, (4, 4, 4, 4), 60, 16, 3, 0, 5, False),
+    (106, 300, 3, 0, (3,), 0, 1, 2, 0, 1, True),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_tiny_parity(caps, orc, case):
+    seed, n, d, metric, voc, lv, b, h, cmin, cmax, integer = case
+    w = synth.make_tiny(seed, n=n, d=d, n_q=150, vocabs=voc, label_vocab=lv, metric=metric, b=b, h=h,
+                        cmin=cmin, cmax=cmax, integer=integer, max_labels=8)
+    oi = orc.build_from_workload(w, iters=4)
+    ix = caps.Index.from_workload(w, kmeans_iters=4)
+    _check_build(oi, ix.export())
+    for m in sorted({1, max(1, b // 3), b}):
+        for k in (1, 7):
+            _check_search(orc, oi, ix, w, k, m)
+    _check_search(orc, oi, ix, w, 5, max(1, b // 2), rule=1)
+
+
+def test_edge_cases(caps, orc):
+    import torch
+    w = synth.make_tiny(7, n=500, d=6, n_q=5, vocabs=(3, 4), label_vocab=10, b=5, h=2)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2)
+    q = np.random.default_rng(0).normal(size=(8, 6)).astype(np.float32)
+    pairs = [[], [(0, 1), (0, 2)], [(1, 99)], [(9, 0)], [(0, 1), (0, 1)], [(2, 3), (2, 3), (0, 0)],
+             [(2, 0), (2, 1), (2, 2), (2, 3), (2, 4), (2, 5), (2, 6), (2, 7), (2, 8)], [(0, -1)]]
+    co = np.cumsum([0] + [len(p) for p in pairs]).astype(np.int32)
+    ca = np.array([a for p in pairs for a, _ in p], dtype=np.int32)
+    cv = np.array([v for p in pairs for _, v in p], dtype=np.int32)
+    r = orc.search(oi, q, co, ca, cv, 64, 5)
+    ids, dist, nc, ns = ix.search(q, co, ca, cv, 64, 5, counters=True)
+    assert np.array_equal(ids.cpu().numpy(), r.ids)
+    assert np.array_equal(dist.cpu().numpy().view(np.uint32), r.dist.view(np.uint32))
+    assert np.array_equal(nc.cpu().numpy(), r.n_cand)
+    # empty batch
+    e = ix.search(np.zeros((0, 6), np.float32), np.zeros(1, np.int32), np.zeros(0, np.int32),
+                  np.zeros(0, np.int32), 3, 2)
+    assert e[0].shape == (0, 3)
+    # malformed offsets: the query is unsatisfiable, the others unaffected
+    bad = co.copy()
+    bad[2] = 10_000
+    ids2, _ = ix.search(q, bad, ca, cv, 64, 5)
+    ids2 = ids2.cpu().numpy()
+    assert np.all(ids2[1] == -1) and np.all(ids2[2] == -1)
+    assert np.array_equal(ids2[0], r.ids[0])
+    # argument errors
+    with pytest.raises(caps.CapsError):
+        ix.search(q, co, ca, cv, 0, 2)
+    with pytest.raises(caps.CapsError):
+        ix.search(q, co, ca, cv, 3, 6)
+    torch.cuda.synchronize()
+
+
+def test_determinism_and_batch_invariance(caps, orc):
+    w = synth.make_tiny(8, n=3000, d=24, n_q=200, vocabs=(4, 6), label_vocab=30, b=20, h=3, cmin=0,
+                        cmax=3)
+    ix = caps.Index.from_workload(w, kmeans_iters=3)
+    a = _gpu_search(ix, w, 10, 6)
+    b = _gpu_search(ix, w, 10, 6)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        sub = np.sort(rng.choice(w.n_q, size=rng.integers(1, 40), replace=False))
+        co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sub])]).astype(np.int32)
+        ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sub]).astype(np.int32)
+        cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sub]).astype(np.int32)
+        ids, dist = ix.search(w.q[sub], co, ca, cv, 10, 6)
+        assert np.array_equal(ids.cpu().numpy(), a[0][sub])
+        assert np.array_equal(dist.cpu().numpy().view(np.uint32), a[1][sub].view(np.uint32))
+
+
+def test_build_errors(caps):
+    x = np.zeros((10, 4), np.float32)
+    with pytest.raises(caps.CapsError):
+        caps.Index.build(x, n_partitions=11)
+    x[3, 1] = np.nan
+    with pytest.raises(caps.CapsError):
+        caps.Index.build(x, n_partitions=2)
+    x = np.zeros((10, 4), np.float32)
+    with pytest.raises(caps.CapsError):
+        caps.Index.build(x, np.full((10, 1), 5, np.uint32), [3], n_partitions=2)
+    lo = np.array([0, 2] + [2] * 9, np.int64)
+    with pytest.raises(caps.CapsError):
+        caps.Index.build(x, None, None, lo, np.array([1, 1], np.uint32), 4, n_partitions=2)
