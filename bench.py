@@ -1,0 +1,254 @@
+"""Benchmark: filtered queries/s at recall@10 >= 0.9 on one MI355X.
+
+Workload (SIFT1M-shaped synthetic corpus): N = 1,000,000 points, d = 128,
+uniform integers 0..255 stored as float32; three dense attributes with
+vocabularies 10/50/200, Zipf(1.0); B = 1024 k-means partitions (10 Lloyd
+iterations, seeded), AFT height h = 2; 10,000 queries (uniform integers),
+each with 1-3 AND constraints of selectivity 0.1%-30%; k = 10, squared L2.
+
+Procedure
+  1. draw the workload (seeded), build the index on the GPU;
+  2. ground truth: the same search with every partition probed, which
+     returns exactly the filtered brute-force top-10 (integer data: the FP32
+     distances are exact);
+  3. sweep nprobe and take the smallest with mean recall@10 >= 0.9;
+  4. W warmup steps, then K timed steps at that nprobe, each step one search
+     of the whole 10,000-query batch with inputs resident in HBM;
+  5. stage timing with HIP events on the search stream; the dominant kernel
+     (the filtered scan) is reported against the vector-ALU roofline;
+  6. CPU baseline: the oracle's query path on a bounded sample of the same
+     queries at the same nprobe, on the host's cores.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "filtered queries/s at recall@10>=0.9 (plain FP32 centroid-routed CAPS)"
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 FP32 VALU lane
+# operations per second (non-packed).  One survivor-dimension of the exact
+# squared-L2 scan is a subtract and a fused multiply-add: two VALU
+# operations carrying three floating-point operations.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+SCAN_PEAK_TFLOPS = VALU_LANE_OPS / 2 * 3 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def recall10(found, truth, nvalid):
+    r = np.zeros(found.shape[0])
+    for i in range(found.shape[0]):
+        denom = min(10, int(nvalid[i]))
+        if denom == 0:
+            r[i] = 1.0
+            continue
+        t = set(truth[i][truth[i] >= 0].tolist())
+        f = set(found[i][found[i] >= 0].tolist())
+        r[i] = len(t & f) / denom
+    return r
+
+
+def cpu_baseline(ix, w, m, budget_s=20.0):
+    """Oracle query path (C, OpenMP over queries) on a bounded query sample,
+    with the GPU-built index's partitions and CSR as its index."""
+    import oracle
+    g = ix.export()
+    oi = oracle.Index(w.x, oracle.workload_tokens(w), w.metric, w.n_partitions, w.aft_height,
+                      g["centroids"], g["assign"], g["tags"], g["level"], g["perm"], g["offs"],
+                      np.zeros(0, np.int32))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = 64
+    total_q, total_t = 0, 0.0
+    start = 0
+    while total_t < budget_s and start < w.n_q:
+        sel = np.arange(start, min(w.n_q, start + n))
+        co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
+        ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+        cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.search(oi, w.q[sel], co, ca, cv, 10, m)
+        total_t += time.perf_counter() - t0
+        total_q += len(sel)
+        start += len(sel)
+        n = min(4 * n, 4096)
+    return {"value": total_q / total_t, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {total_q} of the {w.n_q} queries at nprobe={m} "
+                      f"({total_t:.1f} s of CPU work, OpenMP over queries)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
+    ap.add_argument("--target", type=float, default=0.9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md, 'Sharding').", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    w = synth.make_c2(n=args.n, n_q=args.nq)
+    log(f"workload: N={w.n} d={w.d} Q={w.n_q} generated in {time.perf_counter() - t0:.1f}s")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = caps.Index.from_workload(w)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = ix.info()
+    log(f"build: {build_s:.2f}s, index {info['device_bytes'] / 2**20:.0f} MiB on device, "
+        f"largest sub-partition {info['max_subpartition']}")
+
+    q = torch.from_numpy(w.q).to(dev)
+    co = torch.from_numpy(w.con_off).to(dev)
+    ca = torch.from_numpy(w.con_attr).to(dev)
+    cv = torch.from_numpy(w.con_val).to(dev)
+    k = 10
+    B = w.n_partitions
+
+    t0 = time.perf_counter()
+    tid, _, _, tsurv = ix.search(q, co, ca, cv, k, B, counters=True)
+    truth = tid.cpu().numpy()
+    nvalid = tsurv.cpu().numpy()
+    log(f"truth (all {B} partitions probed): {time.perf_counter() - t0:.2f}s, "
+        f"mean |D_C| = {nvalid.mean():.0f}")
+
+    sweep = []
+    if args.nprobe:
+        cand = [args.nprobe]
+    else:
+        cand = [8, 16, 32, 64, 128, 256, 384, 512, 640, 768, 832, 896, 960, 1024]
+    chosen = None
+    for m in cand:
+        if m > B:
+            continue
+        ids, _, nc, ns = ix.search(q, co, ca, cv, k, m, counters=True)
+        rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
+        sweep.append({"nprobe": m, "recall@10": round(rec, 4),
+                      "cand_per_q": float(nc.float().mean()), "surv_per_q": float(ns.float().mean())})
+        log(f"  nprobe={m:5d} recall@10={rec:.4f} cand/q={sweep[-1]['cand_per_q']:.0f} "
+            f"surv/q={sweep[-1]['surv_per_q']:.0f}")
+        if rec >= args.target:
+            chosen = m
+            break
+    if chosen is None:
+        chosen = cand[-1]
+    m = chosen
+    rec = sweep[-1]["recall@10"]
+
+    ids = torch.empty((w.n_q, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((w.n_q, k), dtype=torch.float32, device=dev)
+    nc = torch.empty(w.n_q, dtype=torch.int32, device=dev)
+    ns = torch.empty(w.n_q, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        ix.search(q, co, ca, cv, k, m, out=(ids, dist))
+    torch.cuda.synchronize()
+
+    # counters of the timed workload (for the roofline's algorithmic work)
+    _, _, nc, ns = ix.search(q, co, ca, cv, k, m, counters=True)
+    surv_total = int(ns.to(torch.int64).sum())
+    cand_total = int(nc.to(torch.int64).sum())
+    torch.cuda.synchronize()
+
+    caps.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ix.search(q, co, ca, cv, k, m, out=(ids, dist))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = caps.profile_read()
+    caps.profile_enable(False)
+
+    if args.calib_copy:
+        a = torch.empty(128 * 2**20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ms_step = el * 1e3 / args.steps
+    qps = w.n_q * args.steps / el
+    scan_ms, scan_n = prof["scan"]
+    scan_avg_s = scan_ms / 1e3 / max(scan_n, 1)
+    launches_per_step = scan_n / args.steps
+    flops_per_launch = 3.0 * w.d * surv_total / launches_per_step
+    achieved = flops_per_launch / scan_avg_s / 1e12
+    stage_ms = {s: round(v[0] / args.steps, 4) for s, v in prof.items()}
+    log(f"timed: {args.steps} steps, {ms_step:.3f} ms/step, {qps:,.0f} queries/s at nprobe={m} "
+        f"recall@10={rec:.4f}")
+    log(f"stages (ms/step): {stage_ms}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "c2: N=1M d=128 uniform-int0-255 fp32, 3 dense attrs (10/50/200, Zipf 1.0), "
+                        "B=1024 Lloyd-10 h=2, 10k queries with 1-3 AND constraints, selectivity "
+                        "0.1-30%, k=10, squared L2",
+            "n": w.n, "d": w.d, "n_queries": w.n_q, "k": k, "nprobe": m, "recall@10": rec,
+            "recall_target": args.target, "build_s": round(build_s, 3),
+            "cand_per_query": cand_total / w.n_q, "surv_per_query": surv_total / w.n_q,
+            "stage_ms_per_step": stage_ms, "sweep": sweep,
+        },
+        "roofline": {
+            "kernel": "k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(SCAN_PEAK_TFLOPS, 2),
+            "unit": "TFLOP/s",
+            "frac": round(achieved / SCAN_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "avg_launch_ms": round(scan_avg_s * 1e3, 4),
+            "algorithmic_flops_per_launch": flops_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle query path on a query sample ...")
+        out["cpu_baseline"] = cpu_baseline(ix, w, m)
+        log(f"  {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

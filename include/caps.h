@@ -165,6 +165,30 @@ caps_status caps_index_info(const caps_index *idx, caps_index_info_t *out);
 caps_status caps_index_export(const caps_index *idx, float *centroids, int32_t *assign,
                               int8_t *level, int32_t *perm, int32_t *offs, int32_t *tags);
 
+/*
+ * Stage timing for benchmarks.  While enabled, caps_search records a pair of
+ * HIP events around each stage on the stream it runs on; caps_profile_read
+ * waits for the recorded events and returns the summed milliseconds and the
+ * number of timed launches per stage since caps_profile_enable(1).  Process
+ * wide; intended for single-threaded benchmark drivers.
+ */
+enum {
+    CAPS_STAGE_PREP = 0,    /* constraint pairs -> packed filters */
+    CAPS_STAGE_ROUTE = 1,   /* query x centroid scores */
+    CAPS_STAGE_TOPM = 2,    /* best nprobe partitions */
+    CAPS_STAGE_SELECT = 3,  /* sub-partition choice and bucketing */
+    CAPS_STAGE_SCAN = 4,    /* filtered distance scan (per-partition top-k) */
+    CAPS_STAGE_MERGE = 5,   /* per-query top-k merge */
+    CAPS_N_STAGES = 8
+};
+typedef struct {
+    double ms[CAPS_N_STAGES];
+    int64_t launches[CAPS_N_STAGES];
+} caps_profile_t;
+
+caps_status caps_profile_enable(int32_t on);        /* on != 0 clears and starts */
+caps_status caps_profile_read(caps_profile_t *out); /* synchronises the events */
+
 /* Release the index and its device memory (NULL is a no-op). */
 void caps_free(caps_index *idx);
 

@@ -3,7 +3,7 @@
 The compute lives in libcaps.so (hand-written HIP for gfx950, C ABI in
 include/caps.h); this package marshals arguments to it.
 """
-from ._lib import CapsError, lib  # noqa: F401
+from ._lib import CapsError, lib, profile_enable, profile_read  # noqa: F401
 from .index import Index  # noqa: F401
 
 __all__ = ["Index", "CapsError", "lib"]

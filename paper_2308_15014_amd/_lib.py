@@ -41,6 +41,12 @@ class IndexInfo(ctypes.Structure):
                 ("n_tokens", c_i32), ("max_subpartition", c_i32), ("device_bytes", c_i64)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", c_i64 * 8)]
+
+
+STAGES = ["prep", "route", "topm", "select", "scan", "merge"]
+
 # name -> (restype, argtypes); every symbol include/caps.h declares
 SIGNATURES = {
     "caps_build": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32,
@@ -52,6 +58,8 @@ SIGNATURES = {
     "caps_index_info": (c_i32, [c_vp, ctypes.POINTER(IndexInfo)]),
     "caps_index_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_free": (None, [c_vp]),
+    "caps_profile_enable": (c_i32, [c_i32]),
+    "caps_profile_read": (c_i32, [ctypes.POINTER(Profile)]),
     "caps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -72,6 +80,17 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def profile_enable(on: bool = True):
+    check(lib().caps_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{stage: (total ms, launches)} since profile_enable(True)."""
+    p = Profile()
+    check(lib().caps_profile_read(ctypes.byref(p)))
+    return {s: (p.ms[i], int(p.launches[i])) for i, s in enumerate(STAGES)}
 
 
 def check(status: int):

@@ -101,6 +101,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand, int32_t *out_nsurv,
                    int32_t *out_probes, uint32_t *out_masks, hipStream_t st);
 
+// ---- stage timer (caps_util.hip): no-ops unless enabled
+void prof_begin(int stage, hipStream_t st);
+void prof_end(int stage, hipStream_t st);
+
 // ---- shared device utilities (caps_util.hip)
 caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
                                hipStream_t st);

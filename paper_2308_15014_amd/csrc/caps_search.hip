@@ -6,7 +6,7 @@
 //   select  per (query, probe): the sub-partitions that may hold valid
 //           points (exact rule) and the candidate count
 //   bucket  (query, probe) pairs grouped by partition, cut into tiles of at
-//           most kQB queries
+//           most 128 queries
 //   scan    one workgroup per tile: the partition's chosen sub-partitions
 //           stream through LDS in chunks; every (query, point) pair is
 //           filtered exactly, survivors are compacted and their distances
@@ -14,7 +14,7 @@
 //   merge   per query, the per-partition top-k lists -> final top k
 //
 // Partition-major scanning reads each probed partition once per tile of up
-// to kQB queries instead of once per query.
+// to 128 queries instead of once per query.
 #include <string.h>
 
 #include <algorithm>
@@ -24,9 +24,6 @@
 
 namespace caps {
 
-constexpr int kQB = 64;      // queries per tile
-constexpr int kCH = 32;      // points per chunk
-constexpr int kScanNT = 256;
 
 // ------------------------------------------------------------------ prep
 __global__ __launch_bounds__(128) void k_qprep(const int32_t *__restrict__ con_off, const int32_t *__restrict__ con_attr,
@@ -240,7 +237,7 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
 }
 
 // Bucket starts and tile starts per partition (single workgroup).
-__global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ pcount, int32_t b,
+__global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ pcount, int32_t b, int32_t qb,
                                                int32_t *__restrict__ pstart, int32_t *__restrict__ tstart) {
     __shared__ int scratch[1024 / kWave + 1];
     __shared__ int carry_e, carry_t;
@@ -251,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ pcoun
         const int c = p < b ? pcount[p] : 0;
         int te, tt;
         const int pe = block_excl_scan<1024>(c, scratch, &te);
-        const int pt = block_excl_scan<1024>((c + kQB - 1) / kQB, scratch, &tt);
+        const int pt = block_excl_scan<1024>((c + qb - 1) / qb, scratch, &tt);
         if (p < b) {
             pstart[p] = carry_e + pe;
             tstart[p] = carry_t + pt;
@@ -291,10 +288,12 @@ struct ScanArgs {
     const uint64_t *sigs;
     const uint16_t *slots;
     uint64_t *partials;
+    uint64_t *tau;        // per query: shared upper bound on its final k-th key
     int32_t *nsurv;
     int32_t d, m, h, b, k;
 };
 
+// Exact filter of one point against one query (Definition 1 with wildcards).
 __device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_labels, uint32_t w,
                                     uint64_t sig, const uint16_t *sl) {
     if (has_dense && ((w & qd.dmask) != qd.dval)) return false;
@@ -310,12 +309,73 @@ __device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_la
     return true;
 }
 
-template <int METRIC>
-__global__ __launch_bounds__(kScanNT) void k_scan_fp32(ScanArgs A, bool has_dense, bool has_labels) {
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kCH = 32 * 2;    // points per chunk (one per lane)
+constexpr int kQPW = 16;       // queries owned by each wave
+constexpr int kRing = 128;     // per-wave pending-pair ring
+
+// Per-tile LDS layout (QB = NW * 16 queries, one chunk of kCH points).
+struct ScanLds {
+    size_t qs, xs, xid, xw, xsig, xslot, ring, lst, tau, lcnt, qsel, qslot, qd, surv, total;
+    int stride;
+    __host__ __device__ ScanLds(int d, int nw, int kmax) {
+        const int qb = nw * kQPW;
+        stride = ((d + 3) & ~3) + 4;
+        size_t o = 0;
+        auto take = [&](size_t bytes) __host__ __device__ {
+            o = (o + 15) & ~(size_t)15;
+            size_t r = o;
+            o += bytes;
+            return r;
+        };
+        qs = take(sizeof(float) * (size_t)qb * stride);
+        xs = take(sizeof(float) * (size_t)kCH * stride);
+        xid = take(sizeof(int32_t) * kCH);
+        xw = take(sizeof(uint32_t) * kCH);
+        xsig = take(sizeof(uint64_t) * kCH);
+        xslot = take(sizeof(uint16_t) * kCH * kMaxLabels);
+        ring = take(sizeof(uint16_t) * (size_t)nw * kRing);
+        lst = take(sizeof(uint64_t) * (size_t)qb * kmax);
+        tau = take(sizeof(uint64_t) * qb);
+        lcnt = take(sizeof(int32_t) * qb);
+        qsel = take(sizeof(uint32_t) * qb);
+        qslot = take(sizeof(int32_t) * qb);
+        qd = take(sizeof(QDesc) * qb);
+        surv = take(sizeof(int32_t) * qb);
+        total = take(16);
+    }
+};
+
+// Partition-major filtered scan.  One workgroup = one tile (a partition and
+// up to QB of the queries probing it); wave w owns queries 16w..16w+15 and
+// does their filtering, survivor compaction, distances and top-k without
+// further workgroup barriers.  Each chunk of 64 points of a chosen
+// sub-partition sits in LDS, one point per lane for the filter; survivors go
+// to a per-wave ring of (query, point) pairs and are scanned one pair per
+// lane, dimensions in ascending order.  Each query keeps its best k of the
+// tile in LDS; a survivor is kept only if it beats the query's threshold,
+// the smaller of the tile's own k-th key and the shared bound published by
+// finished tiles (any k valid points bound the final k-th key from above,
+// so no result of the exact top-k is ever dropped).
+template <int METRIC, bool HAS_LABELS, bool VEC4, int KMAX, int NW>
+__global__ __launch_bounds__(NW * 64) void k_scan_fp32(ScanArgs A) {
+    constexpr int QB = NW * kQPW;
+    constexpr int NT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t lvmask;
     const int tile = blockIdx.x;
     if (tile >= A.tstart[A.b]) return;
-    // partition p: the last p with tstart[p] <= tile
     int lo = 0, hi = A.b;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -323,171 +383,223 @@ __global__ __launch_bounds__(kScanNT) void k_scan_fp32(ScanArgs A, bool has_dens
         else hi = mid;
     }
     const int p = lo;
-    const int i0 = (tile - A.tstart[p]) * kQB;
-    const int nqt = min(kQB, A.pcount[p] - i0);
+    const int i0 = (tile - A.tstart[p]) * QB;
+    const int nqt = min(QB, A.pcount[p] - i0);
     const int32_t *ent = A.entries + A.pstart[p] + i0;
 
     const int d = A.d, k = A.k;
-    const int stride = ((d + 3) & ~3) + 4;
-    // LDS carve-up
-    float *Qs = reinterpret_cast<float *>(smem);                       // kQB x stride
-    float *Xs = Qs + kQB * stride;                                       // kCH x stride
-    uint64_t *keys = reinterpret_cast<uint64_t *>(Xs + kCH * stride);  // kQB*kCH
-    uint64_t *topk = keys + kQB * kCH;                                   // kQB x k
-    QDesc *qds = reinterpret_cast<QDesc *>(topk + kQB * k);             // kQB
-    uint64_t *xsig = reinterpret_cast<uint64_t *>(qds + kQB);          // kCH
-    uint16_t *xslot = reinterpret_cast<uint16_t *>(xsig + kCH);        // kCH x 8
-    uint32_t *xw = reinterpret_cast<uint32_t *>(xslot + kCH * kMaxLabels);  // kCH
-    int32_t *xid = reinterpret_cast<int32_t *>(xw + kCH);              // kCH
-    uint16_t *pairs = reinterpret_cast<uint16_t *>(xid + kCH);         // kQB*kCH
-    int32_t *toff = reinterpret_cast<int32_t *>(pairs + kQB * kCH);    // kScanNT+1
-    int32_t *qslot = toff + kScanNT + 1;                                 // kQB
-    uint32_t *qsel = reinterpret_cast<uint32_t *>(qslot + kQB);        // kQB
-    int32_t *surv = reinterpret_cast<int32_t *>(qsel + kQB);           // kQB
-    int *scratch = surv + kQB;                                           // kScanNT/64+1
-    __shared__ uint32_t lvmask;
+    const ScanLds L(d, NW, KMAX);
+    const int stride = L.stride;
+    float *Qs = reinterpret_cast<float *>(smem + L.qs);
+    float *Xs = reinterpret_cast<float *>(smem + L.xs);
+    int32_t *xid = reinterpret_cast<int32_t *>(smem + L.xid);
+    uint32_t *xw = reinterpret_cast<uint32_t *>(smem + L.xw);
+    uint64_t *xsig = reinterpret_cast<uint64_t *>(smem + L.xsig);
+    uint16_t *xslot = reinterpret_cast<uint16_t *>(smem + L.xslot);
+    uint16_t *ring_all = reinterpret_cast<uint16_t *>(smem + L.ring);
+    uint64_t *lst = reinterpret_cast<uint64_t *>(smem + L.lst);
+    uint64_t *tau = reinterpret_cast<uint64_t *>(smem + L.tau);
+    int32_t *lcnt = reinterpret_cast<int32_t *>(smem + L.lcnt);
+    uint32_t *qsel = reinterpret_cast<uint32_t *>(smem + L.qsel);
+    int32_t *qslot = reinterpret_cast<int32_t *>(smem + L.qslot);
+    QDesc *qds = reinterpret_cast<QDesc *>(smem + L.qd);
+    int32_t *surv = reinterpret_cast<int32_t *>(smem + L.surv);
 
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const bool has_dense = A.words != nullptr;
     if (t == 0) lvmask = 0;
     __syncthreads();
-    if (t < nqt) {
-        const int32_t slot = ent[t];
-        qslot[t] = slot;
-        qsel[t] = A.sel[slot];
-        qds[t] = A.qd[slot / A.m];
-        surv[t] = 0;
-        atomicOr(&lvmask, A.sel[slot]);
+    for (int i = t; i < QB; i += NT) {
+        if (i < nqt) {
+            const int32_t slot = ent[i];
+            const int32_t qq = slot / A.m;
+            qslot[i] = slot;
+            qsel[i] = A.sel[slot];
+            qds[i] = A.qd[qq];
+            tau[i] = __hip_atomic_load(A.tau + qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(&lvmask, A.sel[slot]);
+        } else {
+            qsel[i] = 0;
+            qslot[i] = -1;
+        }
+        lcnt[i] = 0;
+        surv[i] = 0;
     }
-    for (int e = t; e < kQB * k; e += kScanNT) topk[e] = ~0ull;
+    // query rows: wave-per-row, lanes over 4-float groups
+    const int d4 = VEC4 ? (d >> 2) : d;
+    for (int r = w; r < nqt; r += NW) {
+        const int64_t qrow = (int64_t)(ent[r] / A.m) * d;
+        for (int c = lane; c < d4; c += 64) {
+            if (VEC4)
+                *reinterpret_cast<float4 *>(Qs + r * stride + 4 * c) =
+                    *reinterpret_cast<const float4 *>(A.q + qrow + 4 * c);
+            else
+                Qs[r * stride + c] = A.q[qrow + c];
+        }
+    }
     __syncthreads();
-    for (int e = t; e < nqt * d; e += kScanNT) {
-        const int i = e / d, j = e % d;
-        Qs[i * stride + j] = A.q[(int64_t)(qslot[i] / A.m) * d + j];
-    }
     const uint32_t lv = lvmask;
+    uint16_t *ring = ring_all + w * kRing;
+    const int qbase = w * kQPW;
+
     for (int j = 0; j <= A.h; j++) {
         if (!(lv & (1u << j))) continue;
         const int32_t slo = A.offs[(int64_t)p * (A.h + 1) + j];
         const int32_t shi = A.offs[(int64_t)p * (A.h + 1) + j + 1];
         for (int32_t c0 = slo; c0 < shi; c0 += kCH) {
             const int cn = min(kCH, shi - c0);
-            __syncthreads();
-            for (int e = t; e < cn * d; e += kScanNT) {
-                const int i = e / d, jj = e % d;
-                Xs[i * stride + jj] = A.vecs[(int64_t)(c0 + i) * d + jj];
+            __syncthreads();   // the previous chunk is no longer read
+            for (int r = w; r < cn; r += NW) {
+                const int64_t src = (int64_t)(c0 + r) * d;
+                for (int c = lane; c < d4; c += 64) {
+                    if (VEC4)
+                        *reinterpret_cast<float4 *>(Xs + r * stride + 4 * c) =
+                            *reinterpret_cast<const float4 *>(A.vecs + src + 4 * c);
+                    else
+                        Xs[r * stride + c] = A.vecs[src + c];
+                }
             }
             if (t < cn) {
                 xid[t] = A.perm[c0 + t];
                 if (has_dense) xw[t] = A.words[c0 + t];
-                if (has_labels) {
+                if (HAS_LABELS) {
                     xsig[t] = A.sigs[c0 + t];
                     *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) =
                         *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
                 }
             }
             __syncthreads();
-            // filter every (query, point) pair: thread -> query t/4, 8 points
-            const int qi = t >> 2, sub = (t & 3) * 8;
-            uint32_t bits = 0;
-            if (qi < nqt && (qsel[qi] & (1u << j))) {
+
+            // ---- wave-local: filter my queries against the chunk
+            const bool lane_ok = lane < cn;
+            const uint32_t myw = (has_dense && lane_ok) ? xw[lane] : 0u;
+            const uint64_t mysig = (HAS_LABELS && lane_ok) ? xsig[lane] : 0ull;
+            int pend = 0, head = 0;   // wave-uniform
+            auto process = [&](int n) {
+                // distances for ring entries head..head+n-1, one pair per lane
+                const bool v = lane < n;
+                const uint16_t en = v ? ring[(head + lane) & (kRing - 1)] : (uint16_t)0;
+                const int qi = qbase + (en >> 6);
+                const int pi = en & 63;
+                uint64_t key = ~0ull;
+                if (v) {
+                    const float *xr = Xs + pi * stride;
+                    const float *qr = Qs + qi * stride;
+                    float acc = 0.0f;
+                    int jj = 0;
+                    if (VEC4) {
+                        for (; jj < d; jj += 4) {
+                            const float4 xv = *reinterpret_cast<const float4 *>(xr + jj);
+                            const float4 qv = *reinterpret_cast<const float4 *>(qr + jj);
+                            if (METRIC == 0) {
+                                float t0 = xv.x - qv.x;
+                                acc = fmaf(t0, t0, acc);
+                                t0 = xv.y - qv.y;
+                                acc = fmaf(t0, t0, acc);
+                                t0 = xv.z - qv.z;
+                                acc = fmaf(t0, t0, acc);
+                                t0 = xv.w - qv.w;
+                                acc = fmaf(t0, t0, acc);
+                            } else {
+                                acc = fmaf(xv.x, qv.x, acc);
+                                acc = fmaf(xv.y, qv.y, acc);
+                                acc = fmaf(xv.z, qv.z, acc);
+                                acc = fmaf(xv.w, qv.w, acc);
+                            }
+                        }
+                    } else {
+                        for (; jj < d; jj++) {
+                            if (METRIC == 0) {
+                                const float t0 = xr[jj] - qr[jj];
+                                acc = fmaf(t0, t0, acc);
+                            } else {
+                                acc = fmaf(xr[jj], qr[jj], acc);
+                            }
+                        }
+                    }
+                    const float kf = canon0(METRIC == 0 ? acc : -acc);
+                    key = ((uint64_t)f2ord(kf) << 32) | (uint32_t)xid[pi];
+                }
+                uint64_t qual = __ballot(v && key < tau[qi]);
+                while (qual) {
+                    const int src = __builtin_ctzll(qual);
+                    qual &= qual - 1;
+                    const uint64_t K = readlane_u64(key, src);
+                    const int q = __builtin_amdgcn_readlane(qi, src);
+                    wave_sync();
+                    if (K >= tau[q]) continue;
+                    const int c = lcnt[q];
+                    uint64_t *ql = lst + q * KMAX;
+                    if (c < k) {
+                        if (lane == 0) {
+                            ql[c] = K;
+                            lcnt[q] = c + 1;
+                        }
+                        wave_sync();
+                        if (c + 1 == k) {
+                            const uint64_t mx = wave_max_u64(lane < k ? ql[lane] : 0ull);
+                            if (lane == 0 && mx < tau[q]) tau[q] = mx;
+                        }
+                    } else {
+                        const uint64_t cur = lane < k ? ql[lane] : 0ull;
+                        const uint64_t mx = wave_max_u64(cur);
+                        const uint64_t nv = (lane < k && cur == mx) ? K : cur;
+                        if (lane < k && cur == mx) ql[lane] = K;
+                        const uint64_t mx2 = wave_max_u64(lane < k ? nv : 0ull);
+                        if (lane == 0) tau[q] = mx2 < tau[q] ? mx2 : tau[q];
+                    }
+                    wave_sync();
+                }
+                head += n;
+            };
+            for (int i = 0; i < kQPW; i++) {
+                const int qi = qbase + i;
+                if (!(qsel[qi] & (1u << j))) continue;
                 const QDesc &qd = qds[qi];
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const int pi = sub + u;
-                    if (pi < cn &&
-                        point_passes(qd, has_dense, has_labels, xw[pi], has_labels ? xsig[pi] : 0ull,
-                                     xslot + pi * kMaxLabels))
-                        bits |= 1u << u;
+                const bool pass = lane_ok && point_passes(qd, has_dense, HAS_LABELS, myw, mysig,
+                                                          xslot + lane * kMaxLabels);
+                const uint64_t mask = __ballot(pass);
+                if (!mask) continue;
+                const int cnt = __popcll(mask);
+                if (pass) ring[(head + pend + __popcll(mask & lanemask_lt())) & (kRing - 1)] =
+                              (uint16_t)((i << 6) | lane);
+                if (lane == 0) surv[qi] += cnt;
+                pend += cnt;
+                wave_sync();
+                if (pend >= 64) {
+                    process(64);
+                    pend -= 64;
                 }
             }
-            int total;
-            int off = block_excl_scan<kScanNT>(__popc(bits), scratch, &total);
-            toff[t] = off;
-            if (t == kScanNT - 1) toff[kScanNT] = off + __popc(bits);
-            while (bits) {
-                const int u = __ffs(bits) - 1;
-                bits &= bits - 1;
-                pairs[off++] = (uint16_t)((qi << 5) | (sub + u));
-            }
-            __syncthreads();
-            // distances, one (query, point) pair per lane, dims in order
-            for (int e = t; e < total; e += kScanNT) {
-                const int pr = pairs[e];
-                const float *xr = Xs + (pr & 31) * stride;
-                const float *qr = Qs + (pr >> 5) * stride;
-                float acc = 0.0f;
-                int jj = 0;
-                for (; jj + 4 <= d; jj += 4) {
-                    const float4 xv = *reinterpret_cast<const float4 *>(xr + jj);
-                    const float4 qv = *reinterpret_cast<const float4 *>(qr + jj);
-                    if (METRIC == 0) {
-                        float t0 = xv.x - qv.x;
-                        acc = fmaf(t0, t0, acc);
-                        t0 = xv.y - qv.y;
-                        acc = fmaf(t0, t0, acc);
-                        t0 = xv.z - qv.z;
-                        acc = fmaf(t0, t0, acc);
-                        t0 = xv.w - qv.w;
-                        acc = fmaf(t0, t0, acc);
-                    } else {
-                        acc = fmaf(xv.x, qv.x, acc);
-                        acc = fmaf(xv.y, qv.y, acc);
-                        acc = fmaf(xv.z, qv.z, acc);
-                        acc = fmaf(xv.w, qv.w, acc);
-                    }
-                }
-                for (; jj < d; jj++) {
-                    if (METRIC == 0) {
-                        const float t0 = xr[jj] - qr[jj];
-                        acc = fmaf(t0, t0, acc);
-                    } else {
-                        acc = fmaf(xr[jj], qr[jj], acc);
-                    }
-                }
-                const float key = canon0(METRIC == 0 ? acc : -acc);
-                keys[e] = ((uint64_t)f2ord(key) << 32) | (uint32_t)xid[pr & 31];
-            }
-            __syncthreads();
-            // top-k per query (its pairs are contiguous: threads 4q..4q+3)
-            if (t < nqt) {
-                const int e0 = toff[4 * t], e1 = toff[4 * t + 4];
-                uint64_t *tk = topk + t * k;
-                for (int e = e0; e < e1; e++) {
-                    const uint64_t key = keys[e];
-                    if (key >= tk[k - 1]) continue;
-                    int i = k - 1;
-                    while (i > 0 && tk[i - 1] > key) {
-                        tk[i] = tk[i - 1];
-                        i--;
-                    }
-                    tk[i] = key;
-                }
-                surv[t] += e1 - e0;
-            }
+            if (pend > 0) process(pend);
         }
     }
     __syncthreads();
-    for (int e = t; e < nqt * k; e += kScanNT) {
-        const int i = e / k, r = e % k;
-        A.partials[(int64_t)qslot[i] * k + r] = topk[i * k + r];
+    // ---- finalize my queries: sort the kept keys, write the partial list,
+    // publish the k-th key, add the survivor count
+    for (int i = 0; i < kQPW; i++) {
+        const int qi = qbase + i;
+        if (qi >= nqt) break;
+        const int c = lcnt[qi];
+        const uint64_t v = lane < c ? lst[qi * KMAX + lane] : ~0ull;
+        int rank = 0;
+        for (int r = 0; r < c; r++) rank += readlane_u64(v, r) < v ? 1 : 0;
+        uint64_t *out = A.partials + (int64_t)qslot[qi] * k;
+        if (lane < c) out[rank] = v;
+        else if (lane < k) out[lane] = ~0ull;
+        const int32_t qq = qslot[qi] / A.m;
+        if (c == k) {
+            const uint64_t mx = wave_max_u64(v == ~0ull ? 0ull : v);
+            if (lane == 0) atomicMin((unsigned long long *)(A.tau + qq), (unsigned long long)mx);
+        }
+        if (lane == 0 && surv[qi]) atomicAdd(&A.nsurv[qq], surv[qi]);
     }
-    if (t < nqt && surv[t]) atomicAdd(&A.nsurv[qslot[t] / A.m], surv[t]);
 }
 
+static int scan_waves(int k) { return k <= 16 ? 8 : 4; }
+
 static size_t scan_lds_bytes(int d, int k) {
-    const int stride = ((d + 3) & ~3) + 4;
-    size_t s = 0;
-    s += sizeof(float) * (size_t)(kQB + kCH) * stride;
-    s += sizeof(uint64_t) * (size_t)kQB * kCH;
-    s += sizeof(uint64_t) * (size_t)kQB * k;
-    s += sizeof(QDesc) * kQB;
-    s += sizeof(uint64_t) * kCH;
-    s += sizeof(uint16_t) * kCH * kMaxLabels;
-    s += sizeof(uint32_t) * kCH + sizeof(int32_t) * kCH;
-    s += sizeof(uint16_t) * kQB * kCH;
-    s += sizeof(int32_t) * (kScanNT + 1) + sizeof(int32_t) * kQB * 3;
-    s += sizeof(int) * (kScanNT / kWave + 1);
-    return s + 64;
+    return ScanLds(d, scan_waves(k), k <= 16 ? 16 : 64).total + 64;
 }
 
 // ------------------------------------------------------------------ merge
@@ -543,12 +655,35 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (e < n) p[e] = v;
 }
 
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
 __global__ void k_copy_i32(const int32_t *__restrict__ a, int32_t *__restrict__ b, int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) b[e] = a[e];
 }
 
 // ------------------------------------------------------------------ host
+typedef void (*ScanFn)(ScanArgs);
+
+template <int METRIC, bool LAB, bool V4>
+static ScanFn pick_k(int k) {
+    if (k <= 16) return k_scan_fp32<METRIC, LAB, V4, 16, 8>;
+    return k_scan_fp32<METRIC, LAB, V4, 64, 4>;
+}
+
+template <int METRIC, bool LAB>
+static ScanFn pick_v(bool v4, int k) {
+    return v4 ? pick_k<METRIC, LAB, true>(k) : pick_k<METRIC, LAB, false>(k);
+}
+
+static ScanFn pick_scan(int metric, bool labels, bool v4, int k) {
+    if (metric == 0) return labels ? pick_v<0, true>(v4, k) : pick_v<0, false>(v4, k);
+    return labels ? pick_v<1, true>(v4, k) : pick_v<1, false>(v4, k);
+}
+
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 struct Arena {
@@ -574,7 +709,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
 
     // sub-batch so that the per-batch workspace stays bounded
     const size_t per_q = sizeof(float) * (size_t)b + (sizeof(int32_t) * 3 + sizeof(uint32_t)) * (size_t)m +
-                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + 16;
+                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + sizeof(uint64_t) + 16;
     const size_t budget = (size_t)1 << 30;
     int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
     const size_t fixed = sizeof(int32_t) * (size_t)(b + 1) * 5 + 4096;
@@ -591,6 +726,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     uint32_t *sel = ar.take<uint32_t>((size_t)sb * m);
     int32_t *entries = ar.take<int32_t>((size_t)sb * m);
     uint64_t *partials = ar.take<uint64_t>((size_t)sb * m * k);
+    uint64_t *tau = ar.take<uint64_t>((size_t)sb);
     int32_t *pcount = ar.take<int32_t>(b + 1);
     int32_t *pfill = ar.take<int32_t>(b + 1);
     int32_t *pstart = ar.take<int32_t>(b + 1);
@@ -599,9 +735,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, ncand, (int64_t)nq, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
 
-    const bool has_dense = ix->sch.n_dense > 0;
     const bool has_labels = ix->sch.label_vocab > 0;
     const size_t lds = scan_lds_bytes(d, k);
+    const int qb = scan_waves(k) * kQPW;
+    const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0, k);
     if (!probes_only) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
@@ -611,24 +748,31 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                       lds_max);
             return CAPS_EUNSUPPORTED;
         }
-        const void *fn = ix->metric == 0 ? (const void *)k_scan_fp32<0> : (const void *)k_scan_fp32<1>;
-        CAPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        CAPS_HIP(hipFuncSetAttribute((const void *)scan_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     for (int32_t q0 = 0; q0 < nq; q0 += sb) {
         const int32_t nb = std::min(sb, nq - q0);
         const int64_t pairs = (int64_t)nb * m;
+        prof_begin(CAPS_STAGE_PREP, st);
         hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
                            con_val, n_con, nb, ix->sch, qd);
+        prof_end(CAPS_STAGE_PREP, st);
+        prof_begin(CAPS_STAGE_ROUTE, st);
         hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
                            q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
+        prof_end(CAPS_STAGE_ROUTE, st);
+        prof_begin(CAPS_STAGE_TOPM, st);
         hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
                            m, probes);
+        prof_end(CAPS_STAGE_TOPM, st);
+        prof_begin(CAPS_STAGE_SELECT, st);
         hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pcount, (int64_t)b + 1, 0);
         hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pfill, (int64_t)b + 1, 0);
         hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
                            ix->tags, h, ix->offs, sp->rule, sel, pcount, ncand + q0);
         CAPS_HIP(hipGetLastError());
         if (probes_only) {
+            prof_end(CAPS_STAGE_SELECT, st);
             hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes,
                                out_probes + (int64_t)q0 * m, pairs);
             hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, (const int32_t *)sel,
@@ -636,9 +780,11 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             CAPS_HIP(hipGetLastError());
             continue;
         }
-        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pcount, b, pstart, tstart);
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pcount, b, qb, pstart, tstart);
+        hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
         hipLaunchKernelGGL(k_fill, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, sel, pairs, pstart,
                            pfill, entries);
+        prof_end(CAPS_STAGE_SELECT, st);
         ScanArgs A;
         A.tstart = tstart;
         A.pstart = pstart;
@@ -654,19 +800,18 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         A.sigs = ix->sigs;
         A.slots = ix->slots;
         A.partials = partials;
+        A.tau = tau;
         A.nsurv = nsurv + q0;
         A.d = d;
         A.m = m;
         A.h = h;
         A.b = b;
         A.k = k;
-        const int64_t max_tiles = (pairs + kQB - 1) / kQB + b;
-        if (ix->metric == 0)
-            hipLaunchKernelGGL(k_scan_fp32<0>, dim3((unsigned)max_tiles), dim3(kScanNT), lds, st, A, has_dense,
-                               has_labels);
-        else
-            hipLaunchKernelGGL(k_scan_fp32<1>, dim3((unsigned)max_tiles), dim3(kScanNT), lds, st, A, has_dense,
-                               has_labels);
+        const int64_t max_tiles = (pairs + qb - 1) / qb + b;
+        prof_begin(CAPS_STAGE_SCAN, st);
+        hipLaunchKernelGGL(scan_fn, dim3((unsigned)max_tiles), dim3(scan_waves(k) * 64), lds, st, A);
+        prof_end(CAPS_STAGE_SCAN, st);
+        prof_begin(CAPS_STAGE_MERGE, st);
         int32_t *oi = out_ids + (int64_t)q0 * k;
         float *od = out_dist + (int64_t)q0 * k;
         if (k <= 16)
@@ -678,6 +823,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         else
             hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
                                ix->metric, oi, od);
+        prof_end(CAPS_STAGE_MERGE, st);
         CAPS_HIP(hipGetLastError());
     }
     CAPS_HIP(hipFreeAsync(ar.base, st));

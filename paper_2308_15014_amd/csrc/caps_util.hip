@@ -1,5 +1,8 @@
 // Device-wide exclusive scan of int32 (three passes: block scans, scan of
 // block sums, add-back).
+#include <mutex>
+#include <vector>
+
 #include "caps_device.h"
 #include "caps_internal.h"
 
@@ -72,4 +75,69 @@ caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32
     return CAPS_OK;
 }
 
+// ------------------------------------------------------------------ stage timer
+namespace {
+struct Rec {
+    int stage;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Rec> g_recs;
+hipEvent_t g_open[CAPS_N_STAGES];
+caps_profile_t g_acc;
+}  // namespace
+
+void prof_begin(int stage, hipStream_t st) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    g_open[stage] = e;
+}
+
+void prof_end(int stage, hipStream_t st) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on || !g_open[stage]) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    g_recs.push_back({stage, g_open[stage], e});
+    g_open[stage] = nullptr;
+}
+
 }  // namespace caps
+
+extern "C" caps_status caps_profile_enable(int32_t on) {
+    using namespace caps;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_recs) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_recs.clear();
+    for (auto &e : g_open) e = nullptr;
+    g_acc = caps_profile_t{};
+    g_prof_on = on != 0;
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_profile_read(caps_profile_t *out) {
+    using namespace caps;
+    if (!out) return CAPS_EINVAL;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_recs) {
+        float ms = 0.0f;
+        CAPS_HIP(hipEventSynchronize(r.b));
+        CAPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        g_acc.ms[r.stage] += ms;
+        g_acc.launches[r.stage] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_recs.clear();
+    *out = g_acc;
+    return CAPS_OK;
+}
