@@ -219,8 +219,7 @@ __device__ inline uint32_t choose_levels(const Schema &s, const QDesc &qd, const
 __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t m,
                          const QDesc *__restrict__ qd, Schema sch, const int32_t *__restrict__ tags,
                          int32_t h, const int32_t *__restrict__ offs, int32_t rule,
-                         uint32_t *__restrict__ sel, int32_t *__restrict__ pcount,
-                         int32_t *__restrict__ ncand) {
+                         uint32_t *__restrict__ sel, int32_t *__restrict__ cand_out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)nq * m) return;
     const int32_t q = (int32_t)(e / m);
@@ -230,50 +229,68 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
     for (int j = 0; j <= h; j++)
         if (mask & (1u << j)) cand += offs[(int64_t)p * (h + 1) + j + 1] - offs[(int64_t)p * (h + 1) + j];
     sel[e] = mask;
-    if (mask) {
-        atomicAdd(&pcount[p], 1);
-        atomicAdd(&ncand[q], cand);
-    }
+    cand_out[e] = cand;
 }
 
-// Bucket starts and tile starts per partition (single workgroup).
-__global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ pcount, int32_t b, int32_t qb,
-                                               int32_t *__restrict__ pstart, int32_t *__restrict__ tstart) {
+// Bucketing of the chosen (query, probe) pairs by partition without global
+// atomics: block g counts its queries' pairs per partition (hist, stored
+// partition-major), an exclusive scan turns the counts into positions, and
+// the fill pass places each pair.
+constexpr int kBucketQ = 16;   // queries per bucketing block
+
+__global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
+                                                     const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                     int32_t b, int32_t ngrp, int32_t *__restrict__ hist) {
+    extern __shared__ int32_t cnt[];
+    for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
+    const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256)
+        if (sel[e]) atomicAdd(&cnt[probes[e]], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+}
+
+__global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
+                                                     const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                     int32_t b, int32_t ngrp, const int32_t *__restrict__ hscan,
+                                                     int32_t *__restrict__ entries) {
+    extern __shared__ int32_t run[];
+    for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
+    const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256)
+        if (sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
+}
+
+// Bucket starts, sizes and tile starts per partition (single workgroup).
+__global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan, const int32_t *__restrict__ total,
+                                               int32_t b, int32_t ngrp, int32_t qb, int32_t *__restrict__ pstart,
+                                               int32_t *__restrict__ pcount, int32_t *__restrict__ tstart) {
     __shared__ int scratch[1024 / kWave + 1];
-    __shared__ int carry_e, carry_t;
-    if (threadIdx.x == 0) carry_e = carry_t = 0;
+    __shared__ int carry_t;
+    if (threadIdx.x == 0) carry_t = 0;
     __syncthreads();
     for (int b0 = 0; b0 < b; b0 += 1024) {
         const int p = b0 + threadIdx.x;
-        const int c = p < b ? pcount[p] : 0;
-        int te, tt;
-        const int pe = block_excl_scan<1024>(c, scratch, &te);
-        const int pt = block_excl_scan<1024>((c + qb - 1) / qb, scratch, &tt);
+        int c = 0;
         if (p < b) {
-            pstart[p] = carry_e + pe;
-            tstart[p] = carry_t + pt;
+            const int32_t s0 = hscan[(int64_t)p * ngrp];
+            const int32_t s1 = p + 1 < b ? hscan[(int64_t)(p + 1) * ngrp] : *total;
+            pstart[p] = s0;
+            pcount[p] = s1 - s0;
+            c = s1 - s0;
         }
+        int tt;
+        const int pt = block_excl_scan<1024>((c + qb - 1) / qb, scratch, &tt);
+        if (p < b) tstart[p] = carry_t + pt;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            carry_e += te;
-            carry_t += tt;
-        }
+        if (threadIdx.x == 0) carry_t += tt;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        pstart[b] = carry_e;
-        tstart[b] = carry_t;
-    }
-}
-
-__global__ void k_fill(const int32_t *__restrict__ probes, const uint32_t *__restrict__ sel, int64_t total,
-                       const int32_t *__restrict__ pstart, int32_t *__restrict__ pfill,
-                       int32_t *__restrict__ entries) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total || sel[e] == 0) return;
-    const int32_t p = probes[e];
-    const int32_t slot = atomicAdd(&pfill[p], 1);
-    entries[pstart[p] + slot] = (int32_t)e;
+    if (threadIdx.x == 0) tstart[b] = carry_t;
 }
 
 // ------------------------------------------------------------------ scan
@@ -321,13 +338,14 @@ __device__ inline uint64_t readlane_u64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-constexpr int kCH = 32 * 2;    // points per chunk (one per lane)
+constexpr int kCH = 64;        // points per chunk (one per lane in the filter)
 constexpr int kQPW = 16;       // queries owned by each wave
 constexpr int kRing = 128;     // per-wave pending-pair ring
 
-// Per-tile LDS layout (QB = NW * 16 queries, one chunk of kCH points).
+// Per-tile LDS layout: QB = NW * 16 queries, one chunk of kCH points, and a
+// candidate buffer of 2*KMAX keys per query.
 struct ScanLds {
-    size_t qs, xs, xid, xw, xsig, xslot, ring, lst, tau, lcnt, qsel, qslot, qd, surv, total;
+    size_t qs, xs, xid, xw, xsig, xslot, ring, buf, bcnt, tau, qslot, qd, total;
     int stride;
     __host__ __device__ ScanLds(int d, int nw, int kmax) {
         const int qb = nw * kQPW;
@@ -339,41 +357,100 @@ struct ScanLds {
             o += bytes;
             return r;
         };
-        qs = take(sizeof(float) * (size_t)qb * stride);
-        xs = take(sizeof(float) * (size_t)kCH * stride);
+        bcnt = take(sizeof(int32_t) * qb);
+        tau = take(sizeof(uint64_t) * qb);
+        qslot = take(sizeof(int32_t) * qb);
+        qd = take(sizeof(QDesc) * qb);
         xid = take(sizeof(int32_t) * kCH);
         xw = take(sizeof(uint32_t) * kCH);
         xsig = take(sizeof(uint64_t) * kCH);
         xslot = take(sizeof(uint16_t) * kCH * kMaxLabels);
         ring = take(sizeof(uint16_t) * (size_t)nw * kRing);
-        lst = take(sizeof(uint64_t) * (size_t)qb * kmax);
-        tau = take(sizeof(uint64_t) * qb);
-        lcnt = take(sizeof(int32_t) * qb);
-        qsel = take(sizeof(uint32_t) * qb);
-        qslot = take(sizeof(int32_t) * qb);
-        qd = take(sizeof(QDesc) * qb);
-        surv = take(sizeof(int32_t) * qb);
+        buf = take(sizeof(uint64_t) * (size_t)qb * 2 * kmax);
+        xs = take(sizeof(float) * (size_t)kCH * stride);
+        qs = take(sizeof(float) * (size_t)qb * stride);
         total = take(16);
     }
 };
 
+// Keeps the best k of query q's candidate buffer, sorted ascending at the
+// front, and tightens its threshold.  Whole wave; ranks are unique because
+// keys carry the point id.
+template <int C>
+__device__ inline void buf_reduce(uint64_t *buf, int32_t *bcnt, uint64_t *tau, int q, int k) {
+    uint64_t *b = buf + q * C;
+    const int c = min(bcnt[q], C);
+    const int lane = threadIdx.x & 63;
+    const uint64_t v0 = lane < c ? b[lane] : ~0ull;
+    const uint64_t v1 = (C > 64 && lane + 64 < c) ? b[lane + 64] : ~0ull;
+    int r0 = 0, r1 = 0;
+    for (int j = 0; j < c; j++) {
+        const uint64_t u = b[j];
+        r0 += u < v0 ? 1 : 0;
+        if (C > 64) r1 += u < v1 ? 1 : 0;
+    }
+    wave_sync();
+    if (v0 != ~0ull && r0 < k) b[r0] = v0;
+    if (C > 64 && v1 != ~0ull && r1 < k) b[r1] = v1;
+    wave_sync();
+    const int nk = min(c, k);
+    if (lane == 0) {
+        bcnt[q] = nk;
+        if (nk == k && b[k - 1] < tau[q]) tau[q] = b[k - 1];
+    }
+    wave_sync();
+}
+
+// Issues the global loads of one chunk (rows c0.. of sub-partition j) into
+// registers; they land in LDS after the next workgroup barrier.
+template <bool VEC4, bool HAS_LABELS, int XPT, int NT>
+__device__ __attribute__((always_inline)) inline void fetch_chunk(
+    const ScanArgs &A, const int32_t *po, int j, int32_t c0, int d, int t, bool has_dense,
+    const int (&prow)[VEC4 ? XPT : 1], float __attribute__((ext_vector_type(4 * XPT))) & px, int32_t &pid,
+    uint32_t &pw, uint64_t &psig, uint4 &pslot) {
+    const int cn = min(kCH, po[j + 1] - c0);
+    if (VEC4) {
+        const float4 *src = reinterpret_cast<const float4 *>(A.vecs + (int64_t)c0 * d);
+#pragma unroll
+        for (int u = 0; u < XPT; u++) {
+            if (prow[u] < cn) {
+                const float4 v = src[t + u * NT];
+                px[4 * u + 0] = v.x;
+                px[4 * u + 1] = v.y;
+                px[4 * u + 2] = v.z;
+                px[4 * u + 3] = v.w;
+            }
+        }
+    }
+    if (t < cn) {
+        pid = A.perm[c0 + t];
+        if (has_dense) pw = A.words[c0 + t];
+        if (HAS_LABELS) {
+            psig = A.sigs[c0 + t];
+            pslot = *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
+        }
+    }
+}
+
 // Partition-major filtered scan.  One workgroup = one tile (a partition and
 // up to QB of the queries probing it); wave w owns queries 16w..16w+15 and
-// does their filtering, survivor compaction, distances and top-k without
-// further workgroup barriers.  Each chunk of 64 points of a chosen
-// sub-partition sits in LDS, one point per lane for the filter; survivors go
-// to a per-wave ring of (query, point) pairs and are scanned one pair per
-// lane, dimensions in ascending order.  Each query keeps its best k of the
-// tile in LDS; a survivor is kept only if it beats the query's threshold,
-// the smaller of the tile's own k-th key and the shared bound published by
-// finished tiles (any k valid points bound the final k-th key from above,
-// so no result of the exact top-k is ever dropped).
+// does their filtering, survivor compaction, distances and candidate
+// selection with no workgroup barrier beyond the two per chunk.  Chunks of
+// 64 points of the chosen sub-partitions go through LDS (the next chunk is
+// prefetched into registers); survivors go to a per-wave ring of (query,
+// point) pairs and are scanned one pair per lane, dimensions in ascending
+// order.  A survivor enters its query's buffer only if it beats the query's
+// threshold: the smaller of the tile's own k-th key and the shared bound
+// published by finished tiles (any k valid points bound the final k-th key
+// from above, so no member of the exact top-k is ever dropped).
 template <int METRIC, bool HAS_LABELS, bool VEC4, int KMAX, int NW>
-__global__ __launch_bounds__(NW * 64) void k_scan_fp32(ScanArgs A) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scan_fp32(ScanArgs A) {
     constexpr int QB = NW * kQPW;
     constexpr int NT = NW * 64;
+    constexpr int C = 2 * KMAX;
+    constexpr int XPT = (kCH * 64 + NT - 1) / NT;   // float4 of a chunk per thread (d <= 256)
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t lvmask;
+    __shared__ uint32_t lvmask_w[NW];
     const int tile = blockIdx.x;
     if (tile >= A.tstart[A.b]) return;
     int lo = 0, hi = A.b;
@@ -387,7 +464,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan_fp32(ScanArgs A) {
     const int nqt = min(QB, A.pcount[p] - i0);
     const int32_t *ent = A.entries + A.pstart[p] + i0;
 
-    const int d = A.d, k = A.k;
+    const int d = A.d, k = A.k, h = A.h;
     const ScanLds L(d, NW, KMAX);
     const int stride = L.stride;
     float *Qs = reinterpret_cast<float *>(smem + L.qs);
@@ -397,35 +474,38 @@ __global__ __launch_bounds__(NW * 64) void k_scan_fp32(ScanArgs A) {
     uint64_t *xsig = reinterpret_cast<uint64_t *>(smem + L.xsig);
     uint16_t *xslot = reinterpret_cast<uint16_t *>(smem + L.xslot);
     uint16_t *ring_all = reinterpret_cast<uint16_t *>(smem + L.ring);
-    uint64_t *lst = reinterpret_cast<uint64_t *>(smem + L.lst);
+    uint64_t *buf = reinterpret_cast<uint64_t *>(smem + L.buf);
+    int32_t *bcnt = reinterpret_cast<int32_t *>(smem + L.bcnt);
     uint64_t *tau = reinterpret_cast<uint64_t *>(smem + L.tau);
-    int32_t *lcnt = reinterpret_cast<int32_t *>(smem + L.lcnt);
-    uint32_t *qsel = reinterpret_cast<uint32_t *>(smem + L.qsel);
     int32_t *qslot = reinterpret_cast<int32_t *>(smem + L.qslot);
     QDesc *qds = reinterpret_cast<QDesc *>(smem + L.qd);
-    int32_t *surv = reinterpret_cast<int32_t *>(smem + L.surv);
 
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const bool has_dense = A.words != nullptr;
-    if (t == 0) lvmask = 0;
-    __syncthreads();
-    for (int i = t; i < QB; i += NT) {
-        if (i < nqt) {
-            const int32_t slot = ent[i];
-            const int32_t qq = slot / A.m;
-            qslot[i] = slot;
-            qsel[i] = A.sel[slot];
-            qds[i] = A.qd[qq];
-            tau[i] = __hip_atomic_load(A.tau + qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicOr(&lvmask, A.sel[slot]);
-        } else {
-            qsel[i] = 0;
-            qslot[i] = -1;
-        }
-        lcnt[i] = 0;
-        surv[i] = 0;
+    const int qbase = w * kQPW;
+    // per-query state; lane i < 16 of wave w keeps query qbase+i in registers
+    uint32_t my_sel = 0, my_dmask = 0, my_dval = 0;
+    int my_surv = 0;
+    int32_t my_qq = -1;
+    if (lane < kQPW && qbase + lane < nqt) {
+        const int qi = qbase + lane;
+        const int32_t slot = ent[qi];
+        my_qq = slot / A.m;
+        my_sel = A.sel[slot];
+        const QDesc qd = A.qd[my_qq];
+        my_dmask = qd.dmask;
+        my_dval = qd.dval;
+        qslot[qi] = slot;
+        qds[qi] = qd;
+        tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bcnt[qi] = 0;
     }
-    // query rows: wave-per-row, lanes over 4-float groups
+    {
+        uint32_t wor = my_sel;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wor |= __shfl_xor(wor, o, 64);
+        if (lane == 0) lvmask_w[w] = wor;
+    }
     const int d4 = VEC4 ? (d >> 2) : d;
     for (int r = w; r < nqt; r += NW) {
         const int64_t qrow = (int64_t)(ent[r] / A.m) * d;
@@ -438,162 +518,201 @@ __global__ __launch_bounds__(NW * 64) void k_scan_fp32(ScanArgs A) {
         }
     }
     __syncthreads();
-    const uint32_t lv = lvmask;
+    uint32_t lv = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) lv |= lvmask_w[i];
     uint16_t *ring = ring_all + w * kRing;
-    const int qbase = w * kQPW;
 
-    for (int j = 0; j <= A.h; j++) {
-        if (!(lv & (1u << j))) continue;
-        const int32_t slo = A.offs[(int64_t)p * (A.h + 1) + j];
-        const int32_t shi = A.offs[(int64_t)p * (A.h + 1) + j + 1];
-        for (int32_t c0 = slo; c0 < shi; c0 += kCH) {
-            const int cn = min(kCH, shi - c0);
-            __syncthreads();   // the previous chunk is no longer read
-            for (int r = w; r < cn; r += NW) {
-                const int64_t src = (int64_t)(c0 + r) * d;
-                for (int c = lane; c < d4; c += 64) {
-                    if (VEC4)
-                        *reinterpret_cast<float4 *>(Xs + r * stride + 4 * c) =
-                            *reinterpret_cast<const float4 *>(A.vecs + src + 4 * c);
-                    else
-                        Xs[r * stride + c] = A.vecs[src + c];
-                }
-            }
-            if (t < cn) {
-                xid[t] = A.perm[c0 + t];
-                if (has_dense) xw[t] = A.words[c0 + t];
-                if (HAS_LABELS) {
-                    xsig[t] = A.sigs[c0 + t];
-                    *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) =
-                        *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
-                }
-            }
-            __syncthreads();
-
-            // ---- wave-local: filter my queries against the chunk
-            const bool lane_ok = lane < cn;
-            const uint32_t myw = (has_dense && lane_ok) ? xw[lane] : 0u;
-            const uint64_t mysig = (HAS_LABELS && lane_ok) ? xsig[lane] : 0ull;
-            int pend = 0, head = 0;   // wave-uniform
-            auto process = [&](int n) {
-                // distances for ring entries head..head+n-1, one pair per lane
-                const bool v = lane < n;
-                const uint16_t en = v ? ring[(head + lane) & (kRing - 1)] : (uint16_t)0;
-                const int qi = qbase + (en >> 6);
-                const int pi = en & 63;
-                uint64_t key = ~0ull;
-                if (v) {
-                    const float *xr = Xs + pi * stride;
-                    const float *qr = Qs + qi * stride;
-                    float acc = 0.0f;
-                    int jj = 0;
-                    if (VEC4) {
-                        for (; jj < d; jj += 4) {
-                            const float4 xv = *reinterpret_cast<const float4 *>(xr + jj);
-                            const float4 qv = *reinterpret_cast<const float4 *>(qr + jj);
-                            if (METRIC == 0) {
-                                float t0 = xv.x - qv.x;
-                                acc = fmaf(t0, t0, acc);
-                                t0 = xv.y - qv.y;
-                                acc = fmaf(t0, t0, acc);
-                                t0 = xv.z - qv.z;
-                                acc = fmaf(t0, t0, acc);
-                                t0 = xv.w - qv.w;
-                                acc = fmaf(t0, t0, acc);
-                            } else {
-                                acc = fmaf(xv.x, qv.x, acc);
-                                acc = fmaf(xv.y, qv.y, acc);
-                                acc = fmaf(xv.z, qv.z, acc);
-                                acc = fmaf(xv.w, qv.w, acc);
-                            }
-                        }
-                    } else {
-                        for (; jj < d; jj++) {
-                            if (METRIC == 0) {
-                                const float t0 = xr[jj] - qr[jj];
-                                acc = fmaf(t0, t0, acc);
-                            } else {
-                                acc = fmaf(xr[jj], qr[jj], acc);
-                            }
-                        }
-                    }
-                    const float kf = canon0(METRIC == 0 ? acc : -acc);
-                    key = ((uint64_t)f2ord(kf) << 32) | (uint32_t)xid[pi];
-                }
-                uint64_t qual = __ballot(v && key < tau[qi]);
-                while (qual) {
-                    const int src = __builtin_ctzll(qual);
-                    qual &= qual - 1;
-                    const uint64_t K = readlane_u64(key, src);
-                    const int q = __builtin_amdgcn_readlane(qi, src);
-                    wave_sync();
-                    if (K >= tau[q]) continue;
-                    const int c = lcnt[q];
-                    uint64_t *ql = lst + q * KMAX;
-                    if (c < k) {
-                        if (lane == 0) {
-                            ql[c] = K;
-                            lcnt[q] = c + 1;
-                        }
-                        wave_sync();
-                        if (c + 1 == k) {
-                            const uint64_t mx = wave_max_u64(lane < k ? ql[lane] : 0ull);
-                            if (lane == 0 && mx < tau[q]) tau[q] = mx;
-                        }
-                    } else {
-                        const uint64_t cur = lane < k ? ql[lane] : 0ull;
-                        const uint64_t mx = wave_max_u64(cur);
-                        const uint64_t nv = (lane < k && cur == mx) ? K : cur;
-                        if (lane < k && cur == mx) ql[lane] = K;
-                        const uint64_t mx2 = wave_max_u64(lane < k ? nv : 0ull);
-                        if (lane == 0) tau[q] = mx2 < tau[q] ? mx2 : tau[q];
-                    }
-                    wave_sync();
-                }
-                head += n;
-            };
-            for (int i = 0; i < kQPW; i++) {
-                const int qi = qbase + i;
-                if (!(qsel[qi] & (1u << j))) continue;
-                const QDesc &qd = qds[qi];
-                const bool pass = lane_ok && point_passes(qd, has_dense, HAS_LABELS, myw, mysig,
-                                                          xslot + lane * kMaxLabels);
-                const uint64_t mask = __ballot(pass);
-                if (!mask) continue;
-                const int cnt = __popcll(mask);
-                if (pass) ring[(head + pend + __popcll(mask & lanemask_lt())) & (kRing - 1)] =
-                              (uint16_t)((i << 6) | lane);
-                if (lane == 0) surv[qi] += cnt;
-                pend += cnt;
-                wave_sync();
-                if (pend >= 64) {
-                    process(64);
-                    pend -= 64;
-                }
-            }
-            if (pend > 0) process(pend);
+    // chunk cursor over the chosen sub-partitions of partition p
+    const int32_t *po = A.offs + (int64_t)p * (h + 1);
+    auto advance = [&](int &j, int32_t &c0) {
+        c0 += kCH;
+        while (j <= h && (!(lv & (1u << j)) || c0 >= po[j + 1])) {
+            j++;
+            if (j <= h) c0 = po[j];
+        }
+    };
+    int cj = -1;
+    int32_t cc0 = 0;
+    {
+        cj = 0;
+        cc0 = po[0] - kCH;
+        advance(cj, cc0);
+    }
+    // register prefetch of one chunk: float4 number e of a chunk is row
+    // e / d4 (rows are contiguous in the CSR vectors)
+    float __attribute__((ext_vector_type(4 * XPT))) px = {};
+    int prow[VEC4 ? XPT : 1], plds[VEC4 ? XPT : 1];
+    if (VEC4) {
+#pragma unroll
+        for (int u = 0; u < XPT; u++) {
+            const int e = t + u * NT;
+            prow[u] = e / d4;
+            plds[u] = prow[u] * stride + 4 * (e - prow[u] * d4);
         }
     }
-    __syncthreads();
-    // ---- finalize my queries: sort the kept keys, write the partial list,
-    // publish the k-th key, add the survivor count
+    int32_t pid = 0;
+    uint32_t pw = 0;
+    uint64_t psig = 0;
+    uint4 pslot = make_uint4(0, 0, 0, 0);
+    if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
+
+    while (cj <= h) {
+        const int j = cj;
+        const int32_t c0 = cc0;
+        const int cn = min(kCH, po[j + 1] - c0);
+        __syncthreads();   // the previous chunk is no longer read
+        if (VEC4) {
+#pragma unroll
+            for (int u = 0; u < XPT; u++)
+                if (prow[u] < cn)
+                    *reinterpret_cast<float4 *>(Xs + plds[u]) =
+                        make_float4(px[4 * u], px[4 * u + 1], px[4 * u + 2], px[4 * u + 3]);
+        } else {
+            for (int e = t; e < cn * d; e += NT) {
+                const int r = e / d, c = e - r * d;
+                Xs[r * stride + c] = A.vecs[(int64_t)(c0 + r) * d + c];
+            }
+        }
+        if (t < cn) {
+            xid[t] = pid;
+            xw[t] = pw;
+            if (HAS_LABELS) {
+                xsig[t] = psig;
+                *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) = pslot;
+            }
+        }
+        advance(cj, cc0);
+        if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
+        // refresh the shared bounds of my queries
+        if (my_qq >= 0) {
+            const uint64_t g = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g < tau[qbase + lane]) tau[qbase + lane] = g;
+        }
+        __syncthreads();
+
+        // ---- wave-local: filter my queries against the chunk
+        const bool lane_ok = lane < cn;
+        const uint32_t myw = (has_dense && lane_ok) ? xw[lane] : 0u;
+        const uint64_t mysig = (HAS_LABELS && lane_ok) ? xsig[lane] : 0ull;
+        int pend = 0, head = 0;   // wave-uniform
+        auto process = [&](int n) {
+            const bool v = lane < n;
+            const uint16_t en = v ? ring[(head + lane) & (kRing - 1)] : (uint16_t)0;
+            const int qi = qbase + (en >> 6);
+            const int pi = en & 63;
+            uint64_t key = ~0ull;
+            if (v) {
+                const float *xr = Xs + pi * stride;
+                const float *qr = Qs + qi * stride;
+                float acc = 0.0f;
+                if (VEC4) {
+#pragma unroll 8
+                    for (int jj = 0; jj < d; jj += 4) {
+                        const float4 xv = *reinterpret_cast<const float4 *>(xr + jj);
+                        const float4 qv = *reinterpret_cast<const float4 *>(qr + jj);
+                        if (METRIC == 0) {
+                            float t0 = xv.x - qv.x;
+                            acc = fmaf(t0, t0, acc);
+                            t0 = xv.y - qv.y;
+                            acc = fmaf(t0, t0, acc);
+                            t0 = xv.z - qv.z;
+                            acc = fmaf(t0, t0, acc);
+                            t0 = xv.w - qv.w;
+                            acc = fmaf(t0, t0, acc);
+                        } else {
+                            acc = fmaf(xv.x, qv.x, acc);
+                            acc = fmaf(xv.y, qv.y, acc);
+                            acc = fmaf(xv.z, qv.z, acc);
+                            acc = fmaf(xv.w, qv.w, acc);
+                        }
+                    }
+                } else {
+                    for (int jj = 0; jj < d; jj++) {
+                        if (METRIC == 0) {
+                            const float t0 = xr[jj] - qr[jj];
+                            acc = fmaf(t0, t0, acc);
+                        } else {
+                            acc = fmaf(xr[jj], qr[jj], acc);
+                        }
+                    }
+                }
+                const float kf = canon0(METRIC == 0 ? acc : -acc);
+                key = ((uint64_t)f2ord(kf) << 32) | (uint32_t)xid[pi];
+            }
+            // append the qualifying keys to their queries' buffers; the wave
+            // owns these queries, so slots come from ballots, not atomics.
+            // Each step appends at least one key or empties a full buffer
+            // down to k entries, so 2 * 64 + 2 steps always suffice.
+            bool qual = v && key < tau[qi];
+            for (int guard = 0; guard < 2 * 64 + 2; guard++) {
+                const uint64_t todo = __ballot(qual);
+                if (!todo) break;
+                const int q = __builtin_amdgcn_readlane(qi, __builtin_ctzll(todo));
+                const uint64_t grp = __ballot(qual && qi == q);
+                const int c = bcnt[q];
+                const int room = C - c;
+                if (room <= 0) {
+                    wave_sync();
+                    buf_reduce<C>(buf, bcnt, tau, q, k);
+                    if (qual && qi == q) qual = key < tau[q];
+                    continue;
+                }
+                uint64_t take = grp;
+                while (__popcll(take) > room) take &= ~(1ull << (63 - __builtin_clzll(take)));
+                const bool mine = (take >> lane) & 1ull;
+                if (mine) {
+                    buf[q * C + c + __popcll(take & lanemask_lt())] = key;
+                    qual = false;
+                }
+                wave_sync();
+                if (lane == 0) bcnt[q] = c + __popcll(take);
+                wave_sync();
+            }
+            wave_sync();
+            head += n;
+        };
+        for (int i = 0; i < kQPW; i++) {
+            const uint32_t sl = __builtin_amdgcn_readlane(my_sel, i);
+            if (!(sl & (1u << j))) continue;
+            bool pass;
+            if (HAS_LABELS) {
+                pass = lane_ok && point_passes(qds[qbase + i], has_dense, true, myw, mysig,
+                                               xslot + lane * kMaxLabels);
+            } else {
+                const uint32_t dm = __builtin_amdgcn_readlane(my_dmask, i);
+                const uint32_t dv = __builtin_amdgcn_readlane(my_dval, i);
+                pass = lane_ok && ((myw & dm) == dv);
+            }
+            const uint64_t mask = __ballot(pass);
+            if (!mask) continue;
+            const int cnt = __popcll(mask);
+            if (pass) ring[(head + pend + __popcll(mask & lanemask_lt())) & (kRing - 1)] =
+                          (uint16_t)((i << 6) | lane);
+            if (lane == i) my_surv += cnt;
+            pend += cnt;
+            wave_sync();
+            if (pend >= 64) {
+                process(64);
+                pend -= 64;
+            }
+        }
+        if (pend > 0) process(pend);
+    }
+    // ---- finalize my queries: best k sorted, partial list, shared bound,
+    // survivor count
     for (int i = 0; i < kQPW; i++) {
         const int qi = qbase + i;
         if (qi >= nqt) break;
-        const int c = lcnt[qi];
-        const uint64_t v = lane < c ? lst[qi * KMAX + lane] : ~0ull;
-        int rank = 0;
-        for (int r = 0; r < c; r++) rank += readlane_u64(v, r) < v ? 1 : 0;
+        buf_reduce<C>(buf, bcnt, tau, qi, k);
+        const int c = bcnt[qi];
         uint64_t *out = A.partials + (int64_t)qslot[qi] * k;
-        if (lane < c) out[rank] = v;
-        else if (lane < k) out[lane] = ~0ull;
+        if (lane < k) out[lane] = lane < c ? buf[qi * C + lane] : ~0ull;
         const int32_t qq = qslot[qi] / A.m;
-        if (c == k) {
-            const uint64_t mx = wave_max_u64(v == ~0ull ? 0ull : v);
-            if (lane == 0) atomicMin((unsigned long long *)(A.tau + qq), (unsigned long long)mx);
-        }
-        if (lane == 0 && surv[qi]) atomicAdd(&A.nsurv[qq], surv[qi]);
+        if (lane == 0 && c == k)
+            atomicMin((unsigned long long *)(A.tau + qq), (unsigned long long)buf[qi * C + k - 1]);
     }
+    if (my_qq >= 0 && my_surv) atomicAdd(&A.nsurv[my_qq], my_surv);
 }
 
 static int scan_waves(int k) { return k <= 16 ? 8 : 4; }
@@ -605,18 +724,21 @@ static size_t scan_lds_bytes(int d, int k) {
 // ------------------------------------------------------------------ merge
 template <int KM>
 __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ partials,
-                                               const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                               int32_t k, int32_t metric, int32_t *__restrict__ ids,
-                                               float *__restrict__ dist) {
+                                               const uint32_t *__restrict__ sel, const int32_t *__restrict__ cand,
+                                               int32_t nq, int32_t m, int32_t k, int32_t metric,
+                                               int32_t *__restrict__ ids, float *__restrict__ dist,
+                                               int32_t *__restrict__ ncand) {
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= nq) return;
     uint64_t lst[KM];
 #pragma unroll
     for (int i = 0; i < KM; i++) lst[i] = ~0ull;
+    int nc = 0;
     for (int r = lane; r < m; r += 64) {
         const int64_t slot = (int64_t)q * m + r;
         if (sel[slot] == 0) continue;
+        nc += cand[slot];
         const uint64_t *src = partials + slot * k;
         for (int i = 0; i < k; i++) {
             const uint64_t key = src[i];
@@ -629,6 +751,9 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
             lst[0] = key < lst[0] ? key : lst[0];
         }
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nc += __shfl_xor(nc, o, 64);
+    if (lane == 0) ncand[q] = nc;
     for (int r = 0; r < k; r++) {
         const uint64_t best = wave_min_u64(lst[0]);
         if (lane == 0) {
@@ -686,16 +811,57 @@ static ScanFn pick_scan(int metric, bool labels, bool v4, int k) {
 
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Bump allocator over one workspace allocation.  With base == nullptr it
+// only measures, so the same sequence of takes sizes the allocation; with a
+// base it refuses to hand out bytes beyond `cap`.
 struct Arena {
     char *base = nullptr;
-    size_t off = 0;
+    size_t off = 0, cap = 0;
+    bool overflow = false;
     template <class T>
     T *take(size_t count) {
-        size_t a = (off + 255) & ~(size_t)255;
-        off = a + sizeof(T) * (count ? count : 1);
-        return reinterpret_cast<T *>(base + a);
+        const size_t a = (off + 255) & ~(size_t)255;
+        const size_t bytes = sizeof(T) * (count ? count : 1);
+        if (base && a + bytes > cap) {
+            overflow = true;
+            return nullptr;
+        }
+        off = a + bytes;
+        return base ? reinterpret_cast<T *>(base + a) : nullptr;
     }
 };
+
+struct SearchWs {
+    int32_t *ncand, *nsurv;
+    QDesc *qd;
+    float *scores;
+    int32_t *probes;
+    uint32_t *sel;
+    int32_t *cand, *entries;
+    uint64_t *partials, *tau;
+    int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
+};
+
+static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
+                  bool own_ncand, bool own_nsurv) {
+    const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
+    w.ncand = own_ncand ? ar.take<int32_t>(nq) : nullptr;
+    w.nsurv = own_nsurv ? ar.take<int32_t>(nq) : nullptr;
+    w.qd = ar.take<QDesc>(sb);
+    w.scores = ar.take<float>((size_t)sb * b);
+    w.probes = ar.take<int32_t>((size_t)sb * m);
+    w.sel = ar.take<uint32_t>((size_t)sb * m);
+    w.cand = ar.take<int32_t>((size_t)sb * m);
+    w.entries = ar.take<int32_t>((size_t)sb * m);
+    w.partials = ar.take<uint64_t>((size_t)sb * m * k);
+    w.tau = ar.take<uint64_t>((size_t)sb);
+    w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.htotal = ar.take<int32_t>(1);
+    w.pcount = ar.take<int32_t>(b + 1);
+    w.pstart = ar.take<int32_t>(b + 1);
+    w.tstart = ar.take<int32_t>(b + 1);
+}
 
 caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
                    const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
@@ -707,38 +873,43 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     int pb = 1;
     while (pb < b) pb <<= 1;
 
-    // sub-batch so that the per-batch workspace stays bounded
-    const size_t per_q = sizeof(float) * (size_t)b + (sizeof(int32_t) * 3 + sizeof(uint32_t)) * (size_t)m +
-                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + sizeof(uint64_t) + 16;
+    // sub-batch so that the per-batch workspace stays bounded (~1 GiB)
+    const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 4 * (size_t)m +
+                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + sizeof(uint64_t) +
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + 64;
     const size_t budget = (size_t)1 << 30;
-    int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
-    const size_t fixed = sizeof(int32_t) * (size_t)(b + 1) * 5 + 4096;
-    const size_t ws_bytes = fixed + per_q * (size_t)sb + 256 * 16 +
-                            (out_ncand ? 0 : sizeof(int32_t) * (size_t)nq) +
-                            (out_nsurv ? 0 : sizeof(int32_t) * (size_t)nq);
+    const int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
+    SearchWs W;
+    Arena measure;
+    carve(measure, W, nq, sb, b, m, k, !out_ncand, !out_nsurv);
     Arena ar;
-    CAPS_HIP(hipMallocAsync((void **)&ar.base, ws_bytes, st));
-    int32_t *ncand = out_ncand ? out_ncand : ar.take<int32_t>(nq);
-    int32_t *nsurv = out_nsurv ? out_nsurv : ar.take<int32_t>(nq);
-    QDesc *qd = ar.take<QDesc>(sb);
-    float *scores = ar.take<float>((size_t)sb * b);
-    int32_t *probes = ar.take<int32_t>((size_t)sb * m);
-    uint32_t *sel = ar.take<uint32_t>((size_t)sb * m);
-    int32_t *entries = ar.take<int32_t>((size_t)sb * m);
-    uint64_t *partials = ar.take<uint64_t>((size_t)sb * m * k);
-    uint64_t *tau = ar.take<uint64_t>((size_t)sb);
-    int32_t *pcount = ar.take<int32_t>(b + 1);
-    int32_t *pfill = ar.take<int32_t>(b + 1);
-    int32_t *pstart = ar.take<int32_t>(b + 1);
-    int32_t *tstart = ar.take<int32_t>(b + 1);
+    ar.cap = measure.off;
+    CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
+    carve(ar, W, nq, sb, b, m, k, !out_ncand, !out_nsurv);
+    if (ar.overflow) {
+        (void)hipFreeAsync(ar.base, st);
+        set_error("caps_search: internal workspace layout error");
+        return CAPS_EDEVICE;
+    }
+    int32_t *ncand = out_ncand ? out_ncand : W.ncand;
+    int32_t *nsurv = out_nsurv ? out_nsurv : W.nsurv;
+    QDesc *qd = W.qd;
+    float *scores = W.scores;
+    int32_t *probes = W.probes;
+    uint32_t *sel = W.sel;
+    int32_t *cand = W.cand;
+    int32_t *entries = W.entries;
+    uint64_t *partials = W.partials;
+    uint64_t *tau = W.tau;
+    int32_t *hist = W.hist, *hscan = W.hscan, *htotal = W.htotal;
+    int32_t *pcount = W.pcount, *pstart = W.pstart, *tstart = W.tstart;
 
-    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, ncand, (int64_t)nq, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
 
     const bool has_labels = ix->sch.label_vocab > 0;
     const size_t lds = scan_lds_bytes(d, k);
     const int qb = scan_waves(k) * kQPW;
-    const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0, k);
+    const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0 && d <= 256, k);
     if (!probes_only) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
@@ -753,6 +924,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     for (int32_t q0 = 0; q0 < nq; q0 += sb) {
         const int32_t nb = std::min(sb, nq - q0);
         const int64_t pairs = (int64_t)nb * m;
+        const int32_t ngrp = (nb + kBucketQ - 1) / kBucketQ;
         prof_begin(CAPS_STAGE_PREP, st);
         hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
                            con_val, n_con, nb, ix->sch, qd);
@@ -766,10 +938,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                            m, probes);
         prof_end(CAPS_STAGE_TOPM, st);
         prof_begin(CAPS_STAGE_SELECT, st);
-        hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pcount, (int64_t)b + 1, 0);
-        hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(b + 1, 256)), dim3(256), 0, st, pfill, (int64_t)b + 1, 0);
         hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
-                           ix->tags, h, ix->offs, sp->rule, sel, pcount, ncand + q0);
+                           ix->tags, h, ix->offs, sp->rule, sel, cand);
         CAPS_HIP(hipGetLastError());
         if (probes_only) {
             prof_end(CAPS_STAGE_SELECT, st);
@@ -780,10 +950,17 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             CAPS_HIP(hipGetLastError());
             continue;
         }
-        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pcount, b, qb, pstart, tstart);
+        hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel, nb,
+                           m, b, ngrp, hist);
+        {
+            const caps_status s = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
+            if (s != CAPS_OK) return s;
+        }
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount, tstart);
+        hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel, nb,
+                           m, b, ngrp, hscan, entries);
         hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, sel, pairs, pstart,
-                           pfill, entries);
+        CAPS_HIP(hipGetLastError());
         prof_end(CAPS_STAGE_SELECT, st);
         ScanArgs A;
         A.tstart = tstart;
@@ -815,14 +992,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         int32_t *oi = out_ids + (int64_t)q0 * k;
         float *od = out_dist + (int64_t)q0 * k;
         if (k <= 16)
-            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
-                               ix->metric, oi, od);
+            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
+                               ix->metric, oi, od, ncand + q0);
         else if (k <= 32)
-            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
-                               ix->metric, oi, od);
+            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
+                               ix->metric, oi, od, ncand + q0);
         else
-            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, nb, m, k,
-                               ix->metric, oi, od);
+            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
+                               ix->metric, oi, od, ncand + q0);
         prof_end(CAPS_STAGE_MERGE, st);
         CAPS_HIP(hipGetLastError());
     }
