@@ -191,9 +191,11 @@ def main():
     caps.profile_enable(False)
 
     if args.calib_copy:
-        a = torch.empty(128 * 2**20, dtype=torch.float32, device=dev)
+        # a plain streaming kernel of known traffic (reads 512 MiB, writes
+        # 512 MiB) for scaling the TCC byte counters
+        a = torch.ones(128 * 2**20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
 

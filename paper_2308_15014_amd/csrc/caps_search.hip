@@ -384,6 +384,7 @@ __device__ inline void buf_reduce(uint64_t *buf, int32_t *bcnt, uint64_t *tau, i
     const uint64_t v0 = lane < c ? b[lane] : ~0ull;
     const uint64_t v1 = (C > 64 && lane + 64 < c) ? b[lane + 64] : ~0ull;
     int r0 = 0, r1 = 0;
+#pragma unroll 8
     for (int j = 0; j < c; j++) {
         const uint64_t u = b[j];
         r0 += u < v0 ? 1 : 0;
@@ -451,6 +452,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     constexpr int XPT = (kCH * 64 + NT - 1) / NT;   // float4 of a chunk per thread (d <= 256)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t lvmask_w[NW];
+    __shared__ int32_t spo[kMaxHeight + 2];
     const int tile = blockIdx.x;
     if (tile >= A.tstart[A.b]) return;
     int lo = 0, hi = A.b;
@@ -483,6 +485,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const bool has_dense = A.words != nullptr;
     const int qbase = w * kQPW;
+    if (t <= h + 1) spo[t] = A.offs[(int64_t)p * (h + 1) + t];
     // per-query state; lane i < 16 of wave w keeps query qbase+i in registers
     uint32_t my_sel = 0, my_dmask = 0, my_dval = 0;
     int my_surv = 0;
@@ -524,7 +527,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     uint16_t *ring = ring_all + w * kRing;
 
     // chunk cursor over the chosen sub-partitions of partition p
-    const int32_t *po = A.offs + (int64_t)p * (h + 1);
+    const int32_t *po = spo;
     auto advance = [&](int &j, int32_t &c0) {
         c0 += kCH;
         while (j <= h && (!(lv & (1u << j)) || c0 >= po[j + 1])) {
@@ -557,6 +560,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     uint4 pslot = make_uint4(0, 0, 0, 0);
     if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
 
+    uint64_t g_next = ~0ull;
     while (cj <= h) {
         const int j = cj;
         const int32_t c0 = cc0;
@@ -584,10 +588,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
         }
         advance(cj, cc0);
         if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
-        // refresh the shared bounds of my queries
+        // refresh the shared bounds of my queries with the value loaded one
+        // chunk ago, and start the next load (its latency overlaps a chunk)
         if (my_qq >= 0) {
-            const uint64_t g = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (g < tau[qbase + lane]) tau[qbase + lane] = g;
+            if (g_next < tau[qbase + lane]) tau[qbase + lane] = g_next;
+            g_next = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
 
@@ -597,6 +602,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
         const uint64_t mysig = (HAS_LABELS && lane_ok) ? xsig[lane] : 0ull;
         int pend = 0, head = 0;   // wave-uniform
         auto process = [&](int n) {
+            wave_sync();   // ring entries written by this wave are visible
             const bool v = lane < n;
             const uint16_t en = v ? ring[(head + lane) & (kRing - 1)] : (uint16_t)0;
             const int qi = qbase + (en >> 6);
@@ -691,7 +697,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
                           (uint16_t)((i << 6) | lane);
             if (lane == i) my_surv += cnt;
             pend += cnt;
-            wave_sync();
             if (pend >= 64) {
                 process(64);
                 pend -= 64;
