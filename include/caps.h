@@ -58,6 +58,13 @@ typedef enum {
 
 enum { CAPS_METRIC_L2 = 0, CAPS_METRIC_IP = 1 };
 
+/* Low-precision copy of the vectors kept beside the FP32 ones for the
+ * MFMA scan of search mode 1.  BF16 and FP16: round-to-nearest-even of each
+ * FP32 coordinate.  FP8: OCP E4M3 (finite, max 448) with one FP32 scale per
+ * vector, s = max_j |x_j| / 448 (1 for the zero vector), code_j =
+ * round-to-nearest-even of x_j / s saturated to +-448; the value is s*code. */
+enum { CAPS_PREC_NONE = 0, CAPS_PREC_BF16 = 1, CAPS_PREC_FP8 = 2, CAPS_PREC_FP16 = 3 };
+
 typedef struct {
     int32_t metric;          /* CAPS_METRIC_L2 (squared) or CAPS_METRIC_IP */
     int32_t n_partitions;    /* B, 1 <= B <= min(n, 8192) */
@@ -67,6 +74,9 @@ typedef struct {
                                 partial Fisher-Yates over 0..n-1) */
     const int32_t *init_ids; /* optional host array of B initial point ids;
                                 overrides seed when not NULL */
+    int32_t precision;       /* CAPS_PREC_*: also store a low-precision copy
+                                (needed by search mode 1) */
+    int32_t reserved;
 } caps_build_params;
 
 /*
@@ -106,6 +116,16 @@ typedef struct {
                          sub-partitions whose tags prove them empty of valid
                          points); 1: Algorithm 2 read literally (one
                          sub-partition per partition; lossy, for ablation) */
+    int32_t mode;     /* 0: exact FP32 scan.  1: the index's low-precision
+                         copy is scanned with matrix cores (FP32 accumulation),
+                         each query keeps its best `rerank` candidates under the
+                         approximate score (L2: |x|^2 - 2 x.q with the exact FP32
+                         |x|^2; IP: -x.q), and those are rescored with the exact
+                         FP32 arithmetic to give the final top k.  The filter is
+                         exact in both modes; distances returned in mode 1 are
+                         the exact FP32 distances of the returned ids. */
+    int32_t rerank;   /* mode 1: candidates rescored per query, k <= rerank
+                         <= 64; 0 means min(4k, 64) */
     int32_t reserved;
 } caps_search_params;
 
@@ -126,7 +146,8 @@ typedef struct {
  * outside its vocabulary, an attribute index outside [0, n_dense], two
  * different values for one dense attribute, more than 8 distinct labels.
  * Duplicate constraints are ignored; zero constraints give plain IVF kNN.
- * Errors: EINVAL (k, nprobe, n_q < 0, NULL pointers), ENOMEM, EDEVICE.
+ * Errors: EINVAL (k, nprobe, n_q < 0, NULL pointers, mode 1 on an index
+ * without a low-precision copy, rerank outside [k, 64]), ENOMEM, EDEVICE.
  */
 caps_status caps_search(const caps_index *idx, const caps_search_params *sp,
                         const float *q, int32_t n_q,
@@ -150,6 +171,7 @@ typedef struct {
     int32_t d, n_partitions, aft_height, metric;
     int32_t n_dense, label_vocab, n_tokens;
     int32_t max_subpartition;   /* largest sub-partition size */
+    int32_t precision;          /* CAPS_PREC_* of the low-precision copy */
     int64_t device_bytes;       /* bytes the index holds on the device */
 } caps_index_info_t;
 
@@ -188,6 +210,15 @@ typedef struct {
 
 caps_status caps_profile_enable(int32_t on);        /* on != 0 clears and starts */
 caps_status caps_profile_read(caps_profile_t *out); /* synchronises the events */
+
+/*
+ * caps_index_export_lowp -- copy the low-precision copy to HOST buffers (any
+ * may be NULL): codes n x dpad (2-byte BF16/FP16 bit patterns or 1-byte FP8
+ * codes, CSR order, dpad = d rounded up to a multiple of 32, zero padded),
+ * scale n (FP8 per-vector scales, CSR order), xnorm n (exact FP32 |x|^2 of
+ * each CSR row, sequential fma).  EINVAL if the index has no such copy.
+ */
+caps_status caps_index_export_lowp(const caps_index *idx, void *codes, float *scale, float *xnorm);
 
 /* Release the index and its device memory (NULL is a no-op). */
 void caps_free(caps_index *idx);

@@ -28,17 +28,23 @@ class CapsError(RuntimeError):
 
 class BuildParams(ctypes.Structure):
     _fields_ = [("metric", c_i32), ("n_partitions", c_i32), ("kmeans_iters", c_i32),
-                ("aft_height", c_i32), ("seed", c_u64), ("init_ids", c_vp)]
+                ("aft_height", c_i32), ("seed", c_u64), ("init_ids", c_vp),
+                ("precision", c_i32), ("reserved", c_i32)]
 
 
 class SearchParams(ctypes.Structure):
-    _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("reserved", c_i32)]
+    _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("mode", c_i32),
+                ("rerank", c_i32), ("reserved", c_i32)]
+
+
+PREC = {"none": 0, "fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 
 
 class IndexInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("d", c_i32), ("n_partitions", c_i32), ("aft_height", c_i32),
                 ("metric", c_i32), ("n_dense", c_i32), ("label_vocab", c_i32),
-                ("n_tokens", c_i32), ("max_subpartition", c_i32), ("device_bytes", c_i64)]
+                ("n_tokens", c_i32), ("max_subpartition", c_i32), ("precision", c_i32),
+                ("device_bytes", c_i64)]
 
 
 class Profile(ctypes.Structure):
@@ -57,6 +63,7 @@ SIGNATURES = {
                                    c_vp, c_i32, c_vp, c_vp, c_vp]),
     "caps_index_info": (c_i32, [c_vp, ctypes.POINTER(IndexInfo)]),
     "caps_index_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_index_export_lowp": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "caps_free": (None, [c_vp]),
     "caps_profile_enable": (c_i32, [c_i32]),
     "caps_profile_read": (c_i32, [ctypes.POINTER(Profile)]),

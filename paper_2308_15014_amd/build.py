@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcaps.so")
 
-SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_util.hip"]
+SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_mfma.hip", "caps_util.hip"]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written out
 # explicitly (fmaf); the compiler must not fuse anything else, so that the

@@ -34,8 +34,8 @@ static caps_status fail(caps_status s, const char *fmt, ...) {
 }
 
 static void release(Index &ix) {
-    void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign,
-                    ix.level, ix.words, ix.sigs, ix.slots, ix.vecs};
+    void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign, ix.level,
+                    ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     ix = Index{};
@@ -63,6 +63,10 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
     if (h < 0) return fail(CAPS_EINVAL, "caps_build: aft_height < 0");
     if (h > kMaxHeight) return fail(CAPS_EUNSUPPORTED, "caps_build: aft_height above %d", kMaxHeight);
     if (p->kmeans_iters < 0) return fail(CAPS_EINVAL, "caps_build: kmeans_iters < 0");
+    if (p->precision < CAPS_PREC_NONE || p->precision > CAPS_PREC_FP16)
+        return fail(CAPS_EINVAL, "caps_build: precision must be one of CAPS_PREC_*");
+    if (p->precision != CAPS_PREC_NONE && d > 256)
+        return fail(CAPS_EUNSUPPORTED, "caps_build: the low-precision copy needs d <= 256");
     if (n_dense < 0) return fail(CAPS_EINVAL, "caps_build: n_dense < 0");
     if (n_dense > kMaxDense) return fail(CAPS_EUNSUPPORTED, "caps_build: more than %d dense attributes", kMaxDense);
     if (n_dense > 0 && (!dense_vals || !dense_vocab)) return fail(CAPS_EINVAL, "caps_build: dense arrays missing");
@@ -131,8 +135,11 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
     ix.h = h;
     ix.metric = p->metric;
     ix.sch = sch;
-    const caps_status s = build_index(&ix, x, n, d, dense_vals, has_labels ? label_off : nullptr,
-                                      has_labels ? labels : nullptr, p, (hipStream_t)stream);
+    ix.prec = p->precision;
+    caps_status s = build_index(&ix, x, n, d, dense_vals, has_labels ? label_off : nullptr,
+                                has_labels ? labels : nullptr, p, (hipStream_t)stream);
+    if (s == CAPS_OK) s = build_lowp(&ix, (hipStream_t)stream);
+    if (s == CAPS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) s = CAPS_EDEVICE;
     if (s != CAPS_OK) {
         release(ix);
         delete h_idx;
@@ -152,6 +159,13 @@ static caps_status check_search(const caps_index *idx, const caps_search_params 
     if (sp->k > kMaxK) return fail(CAPS_EUNSUPPORTED, "caps_search: k above %d", kMaxK);
     if (sp->nprobe < 1 || sp->nprobe > ix.b) return fail(CAPS_EINVAL, "caps_search: nprobe outside [1, B]");
     if (sp->rule != 0 && sp->rule != 1) return fail(CAPS_EINVAL, "caps_search: rule must be 0 or 1");
+    if (sp->mode != 0 && sp->mode != 1) return fail(CAPS_EINVAL, "caps_search: mode must be 0 or 1");
+    if (sp->mode == 1) {
+        if (ix.prec == CAPS_PREC_NONE)
+            return fail(CAPS_EINVAL, "caps_search: mode 1 needs an index built with a precision");
+        if (sp->rerank != 0 && (sp->rerank < sp->k || sp->rerank > kMaxK))
+            return fail(CAPS_EINVAL, "caps_search: rerank must be in [k, %d]", kMaxK);
+    }
     if (n_con < 0) return fail(CAPS_EINVAL, "caps_search: n_con < 0");
     if (n_q > 0 && (!q || !con_off)) return fail(CAPS_EINVAL, "caps_search: null query arrays");
     if (n_con > 0 && (!con_attr || !con_val)) return fail(CAPS_EINVAL, "caps_search: null constraint arrays");
@@ -192,6 +206,7 @@ extern "C" caps_status caps_index_info(const caps_index *idx, caps_index_info_t 
     out->label_vocab = ix.sch.label_vocab;
     out->n_tokens = ix.sch.n_tok;
     out->max_subpartition = ix.max_sub;
+    out->precision = ix.prec;
     out->device_bytes = ix.bytes;
     return CAPS_OK;
 }
@@ -208,6 +223,17 @@ extern "C" caps_status caps_index_export(const caps_index *idx, float *centroids
         CAPS_HIP(hipMemcpy(offs, ix.offs, sizeof(int32_t) * ((size_t)ix.b * (ix.h + 1) + 1), hipMemcpyDeviceToHost));
     if (tags && ix.h > 0)
         CAPS_HIP(hipMemcpy(tags, ix.tags, sizeof(int32_t) * (size_t)ix.b * ix.h, hipMemcpyDeviceToHost));
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_index_export_lowp(const caps_index *idx, void *codes, float *scale, float *xnorm) {
+    if (!idx) return fail(CAPS_EINVAL, "caps_index_export_lowp: null index");
+    const Index &ix = idx->ix;
+    if (ix.prec == CAPS_PREC_NONE) return fail(CAPS_EINVAL, "caps_index_export_lowp: no low-precision copy");
+    const size_t es = ix.prec == CAPS_PREC_FP8 ? 1 : 2;
+    if (codes) CAPS_HIP(hipMemcpy(codes, ix.lvecs, (size_t)ix.n * ix.dpad * es, hipMemcpyDeviceToHost));
+    if (scale && ix.lscale) CAPS_HIP(hipMemcpy(scale, ix.lscale, sizeof(float) * (size_t)ix.n, hipMemcpyDeviceToHost));
+    if (xnorm) CAPS_HIP(hipMemcpy(xnorm, ix.xnorm, sizeof(float) * (size_t)ix.n, hipMemcpyDeviceToHost));
     return CAPS_OK;
 }
 

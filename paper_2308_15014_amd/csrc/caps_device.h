@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "caps_internal.h"
+
 namespace caps {
 
 constexpr int kWave = 64;
@@ -77,6 +79,70 @@ __device__ inline uint64_t wave_match(uint32_t key, int nbits) {
         peers &= ((key >> b) & 1u) ? bal : ~bal;
     }
     return peers;
+}
+
+// Exact filter of one point against one query (Definition 1 with wildcards).
+__device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_labels, uint32_t w,
+                                    uint64_t sig, const uint16_t *sl) {
+    if (has_dense && ((w & qd.dmask) != qd.dval)) return false;
+    if (has_labels && qd.nlab > 0) {
+        if (qd.lsig & ~sig) return false;
+        for (int i = 0; i < qd.nlab; i++) {
+            bool f = false;
+#pragma unroll
+            for (int s = 0; s < kMaxLabels; s++) f |= sl[s] == qd.lab[i];
+            if (!f) return false;
+        }
+    }
+    return true;
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Keeps the best k (k <= 64) of query q's candidate buffer of capacity C,
+// sorted ascending at the front, and tightens its threshold.  Whole wave;
+// each lane ranks C/64 entries against all of them; ranks are unique because
+// keys carry a point id or position.
+template <int C>
+__device__ inline void buf_reduce(uint64_t *buf, int32_t *bcnt, uint64_t *tau, int q, int k) {
+    constexpr int EPL = (C + 63) / 64;
+    uint64_t *b = buf + q * C;
+    const int c = min(bcnt[q], C);
+    const int lane = threadIdx.x & 63;
+    uint64_t v[EPL];
+    int rk[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+        v[e] = lane + 64 * e < c ? b[lane + 64 * e] : ~0ull;
+        rk[e] = 0;
+    }
+#pragma unroll 4
+    for (int j = 0; j < c; j++) {
+        const uint64_t u = b[j];
+#pragma unroll
+        for (int e = 0; e < EPL; e++) rk[e] += u < v[e] ? 1 : 0;
+    }
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < EPL; e++)
+        if (v[e] != ~0ull && rk[e] < k) b[rk[e]] = v[e];
+    wave_sync();
+    const int nk = min(c, k);
+    if (lane == 0) {
+        bcnt[q] = nk;
+        if (nk == k && b[k - 1] < tau[q]) tau[q] = b[k - 1];
+    }
+    wave_sync();
 }
 
 }  // namespace caps

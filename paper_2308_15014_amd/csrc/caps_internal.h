@@ -70,6 +70,12 @@ struct Index {
     uint64_t *sigs = nullptr;   // n label signatures, CSR order (labels)
     uint16_t *slots = nullptr;  // n x kMaxLabels sorted labels, 0xFFFF padded
     float *vecs = nullptr;      // n x d, CSR order
+    // low-precision copy for the matrix-core scan (search mode 1)
+    int32_t prec = 0;           // CAPS_PREC_*
+    int32_t dpad = 0;           // d rounded up to a multiple of 32 (zero padded)
+    void *lvecs = nullptr;      // n x dpad elements (2 bytes BF16/FP16, 1 byte FP8), CSR order
+    float *lscale = nullptr;    // n per-vector FP8 scales (FP8 only)
+    float *xnorm = nullptr;     // n exact FP32 |x|^2 (sequential fma), CSR order
     std::vector<int32_t> h_offs;
 };
 
@@ -104,6 +110,17 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
 // ---- stage timer (caps_util.hip): no-ops unless enabled
 void prof_begin(int stage, hipStream_t st);
 void prof_end(int stage, hipStream_t st);
+
+// ---- low-precision path (caps_mfma.hip)
+caps_status build_lowp(Index *ix, hipStream_t st);
+size_t lowp_scan_lds(const Index *ix, int r);
+struct LowpArgs;
+caps_status lowp_scan_and_merge(const Index *ix, const float *q, int32_t nb, const int32_t *tstart,
+                                const int32_t *pstart, const int32_t *pcount, const int32_t *entries,
+                                const uint32_t *sel, const QDesc *qd, int32_t m, int32_t k, int32_t r,
+                                void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt, uint64_t *tau,
+                                const int32_t *cand, int32_t *nsurv, int32_t *ncand, int32_t *out_ids,
+                                float *out_dist, int32_t max_tiles, hipStream_t st);
 
 // ---- shared device utilities (caps_util.hip)
 caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,

@@ -310,34 +310,6 @@ struct ScanArgs {
     int32_t d, m, h, b, k;
 };
 
-// Exact filter of one point against one query (Definition 1 with wildcards).
-__device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_labels, uint32_t w,
-                                    uint64_t sig, const uint16_t *sl) {
-    if (has_dense && ((w & qd.dmask) != qd.dval)) return false;
-    if (has_labels && qd.nlab > 0) {
-        if (qd.lsig & ~sig) return false;
-        for (int i = 0; i < qd.nlab; i++) {
-            bool f = false;
-#pragma unroll
-            for (int s = 0; s < kMaxLabels; s++) f |= sl[s] == qd.lab[i];
-            if (!f) return false;
-        }
-    }
-    return true;
-}
-
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 constexpr int kCH = 64;        // points per chunk (one per lane in the filter)
 constexpr int kQPW = 16;       // queries owned by each wave
 constexpr int kRing = 128;     // per-wave pending-pair ring
@@ -372,35 +344,6 @@ struct ScanLds {
         total = take(16);
     }
 };
-
-// Keeps the best k of query q's candidate buffer, sorted ascending at the
-// front, and tightens its threshold.  Whole wave; ranks are unique because
-// keys carry the point id.
-template <int C>
-__device__ inline void buf_reduce(uint64_t *buf, int32_t *bcnt, uint64_t *tau, int q, int k) {
-    uint64_t *b = buf + q * C;
-    const int c = min(bcnt[q], C);
-    const int lane = threadIdx.x & 63;
-    const uint64_t v0 = lane < c ? b[lane] : ~0ull;
-    const uint64_t v1 = (C > 64 && lane + 64 < c) ? b[lane + 64] : ~0ull;
-    int r0 = 0, r1 = 0;
-#pragma unroll 8
-    for (int j = 0; j < c; j++) {
-        const uint64_t u = b[j];
-        r0 += u < v0 ? 1 : 0;
-        if (C > 64) r1 += u < v1 ? 1 : 0;
-    }
-    wave_sync();
-    if (v0 != ~0ull && r0 < k) b[r0] = v0;
-    if (C > 64 && v1 != ~0ull && r1 < k) b[r1] = v1;
-    wave_sync();
-    const int nk = min(c, k);
-    if (lane == 0) {
-        bcnt[q] = nk;
-        if (nk == k && b[k - 1] < tau[q]) tau[q] = b[k - 1];
-    }
-    wave_sync();
-}
 
 // Issues the global loads of one chunk (rows c0.. of sub-partition j) into
 // registers; they land in LDS after the next workgroup barrier.
@@ -836,7 +779,12 @@ struct Arena {
     }
 };
 
+int lowp_qb();
+
 struct SearchWs {
+    uint8_t *qlow;
+    float *qscale;
+    int32_t *pcnt;
     int32_t *ncand, *nsurv;
     QDesc *qd;
     float *scores;
@@ -848,8 +796,11 @@ struct SearchWs {
 };
 
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
-                  bool own_ncand, bool own_nsurv) {
+                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes) {
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
+    w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
+    w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
+    w.pcnt = qlow_row_bytes ? ar.take<int32_t>((size_t)sb * m) : nullptr;
     w.ncand = own_ncand ? ar.take<int32_t>(nq) : nullptr;
     w.nsurv = own_nsurv ? ar.take<int32_t>(nq) : nullptr;
     w.qd = ar.take<QDesc>(sb);
@@ -873,24 +824,27 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand,
                    int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st) {
     const int32_t b = ix->b, d = ix->d, h = ix->h, m = sp->nprobe, k = sp->k;
+    const bool lowp = sp->mode == 1;
+    const int32_t r = lowp ? (sp->rerank > 0 ? sp->rerank : std::min(4 * k, kMaxK)) : k;
     if (nq == 0) return CAPS_OK;
     const bool probes_only = out_probes != nullptr;
     int pb = 1;
     while (pb < b) pb <<= 1;
 
     // sub-batch so that the per-batch workspace stays bounded (~1 GiB)
-    const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 4 * (size_t)m +
-                         sizeof(uint64_t) * (size_t)m * k + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + 64;
+    const size_t qlow_row = lowp ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
+    const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
+                         sizeof(uint64_t) * (size_t)m * r + sizeof(QDesc) + sizeof(uint64_t) +
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 64;
     const size_t budget = (size_t)1 << 30;
     const int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, sb, b, m, k, !out_ncand, !out_nsurv);
+    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row);
     Arena ar;
     ar.cap = measure.off;
     CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
-    carve(ar, W, nq, sb, b, m, k, !out_ncand, !out_nsurv);
+    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row);
     if (ar.overflow) {
         (void)hipFreeAsync(ar.base, st);
         set_error("caps_search: internal workspace layout error");
@@ -912,10 +866,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
 
     const bool has_labels = ix->sch.label_vocab > 0;
-    const size_t lds = scan_lds_bytes(d, k);
-    const int qb = scan_waves(k) * kQPW;
+    const size_t lds = lowp ? lowp_scan_lds(ix, r) : scan_lds_bytes(d, k);
+    const int qb = lowp ? lowp_qb() : scan_waves(k) * kQPW;
     const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0 && d <= 256, k);
-    if (!probes_only) {
+    if (!probes_only && !lowp) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
         if (lds > (size_t)lds_max) {
@@ -990,6 +944,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         A.b = b;
         A.k = k;
         const int64_t max_tiles = (pairs + qb - 1) / qb + b;
+        if (lowp) {
+            const caps_status ls = lowp_scan_and_merge(
+                ix, q + (int64_t)q0 * d, nb, tstart, pstart, pcount, entries, sel, qd, m, k, r, W.qlow, W.qscale,
+                partials, W.pcnt, tau, cand, nsurv + q0, ncand + q0, out_ids + (int64_t)q0 * k,
+                out_dist + (int64_t)q0 * k, (int32_t)max_tiles, st);
+            if (ls != CAPS_OK) return ls;
+            continue;
+        }
         prof_begin(CAPS_STAGE_SCAN, st);
         hipLaunchKernelGGL(scan_fn, dim3((unsigned)max_tiles), dim3(scan_waves(k) * 64), lds, st, A);
         prof_end(CAPS_STAGE_SCAN, st);

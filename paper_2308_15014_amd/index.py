@@ -10,7 +10,7 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import BuildParams, IndexInfo, SearchParams, check, lib
+from ._lib import PREC, BuildParams, IndexInfo, SearchParams, check, lib
 
 
 def _torch():
@@ -55,7 +55,7 @@ class Index:
     @classmethod
     def build(cls, x, dense=None, dense_vocab=None, label_off=None, labels=None, label_vocab=0, *,
               metric: int = 0, n_partitions: int, kmeans_iters: int = 10, aft_height: int = 2,
-              seed: int = 0, init_ids=None, device=None, stream=None) -> "Index":
+              seed: int = 0, init_ids=None, precision="none", device=None, stream=None) -> "Index":
         torch = _torch()
         device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         x = _host(x, np.float32)
@@ -68,8 +68,9 @@ class Index:
         if lb is not None and lb.size == 0:
             lb = np.zeros(1, dtype=np.uint32)
         init = _host(init_ids, np.int32)
+        prec = PREC[precision] if isinstance(precision, str) else int(precision)
         p = BuildParams(metric, n_partitions, kmeans_iters, aft_height,
-                        ctypes.c_uint64(seed & (2**64 - 1)).value, _ptr(init))
+                        ctypes.c_uint64(seed & (2**64 - 1)).value, _ptr(init), prec, 0)
         out = ctypes.c_void_p()
         with torch.cuda.device(device):
             st = _stream(stream)
@@ -101,10 +102,12 @@ class Index:
         return qd, co, ca, cv, n_con
 
     def search(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
-               stream=None, counters: bool = False, out=None):
+               mode: int = 0, rerank: int = 0, stream=None, counters: bool = False, out=None):
         """Top-k filtered search for a batch.  Returns device tensors
         (ids int32 [Q,k], dist float32 [Q,k]) and, with counters=True, the
-        per-query candidate and survivor counts."""
+        per-query candidate and survivor counts.  mode 1 scans the
+        low-precision copy with matrix cores and rescores `rerank`
+        candidates per query exactly."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
@@ -115,7 +118,7 @@ class Index:
             ids, dist = out
         nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
         ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
-        sp = SearchParams(k, nprobe, rule, 0)
+        sp = SearchParams(k, nprobe, rule, mode, rerank, 0)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
@@ -133,7 +136,7 @@ class Index:
         nq = int(qd.shape[0])
         pr = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
         mk = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
-        sp = SearchParams(1, nprobe, rule, 0)
+        sp = SearchParams(1, nprobe, rule, 0, 0, 0)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search_probes(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
@@ -158,6 +161,18 @@ class Index:
                                                   "tags"))))
         out["tags"] = out["tags"][:, :h]
         return out
+
+    def export_lowp(self) -> dict:
+        """Low-precision copy: codes [n, dpad] (uint16 bit patterns or uint8
+        FP8 codes), per-vector scales (FP8) and exact |x|^2, CSR order."""
+        inf = self.info()
+        n, d, prec = inf["n"], inf["d"], inf["precision"]
+        dpad = (d + 31) // 32 * 32
+        codes = np.zeros((n, dpad), np.uint8 if prec == PREC["fp8"] else np.uint16)
+        scale = np.zeros(n, np.float32)
+        xnorm = np.zeros(n, np.float32)
+        check(lib().caps_index_export_lowp(self._h, _ptr(codes), _ptr(scale), _ptr(xnorm)))
+        return dict(codes=codes, scale=scale, xnorm=xnorm, precision=prec)
 
     def close(self):
         if self._h:
