@@ -42,6 +42,8 @@ METRIC = "filtered queries/s at recall@10>=0.9 (plain FP32 centroid-routed CAPS)
 # operations carrying three floating-point operations.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 SCAN_PEAK_TFLOPS = VALU_LANE_OPS / 2 * 3 / 1e12
+# published dense BF16 matrix-core peak of MI355X
+MFMA_BF16_PEAK = 2500.0
 
 
 def log(*a):
@@ -122,7 +124,7 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ix = caps.Index.from_workload(w)
+    ix = caps.Index.from_workload(w, precision="bf16")
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = ix.info()
@@ -143,52 +145,70 @@ def main():
     log(f"truth (all {B} partitions probed): {time.perf_counter() - t0:.2f}s, "
         f"mean |D_C| = {nvalid.mean():.0f}")
 
-    sweep = []
-    if args.nprobe:
-        cand = [args.nprobe]
-    else:
-        cand = [8, 16, 32, 64, 128, 256, 384, 512, 640, 768, 832, 896, 960, 1024]
-    chosen = None
-    for m in cand:
-        if m > B:
-            continue
-        ids, _, nc, ns = ix.search(q, co, ca, cv, k, m, counters=True)
-        rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
-        sweep.append({"nprobe": m, "recall@10": round(rec, 4),
-                      "cand_per_q": float(nc.float().mean()), "surv_per_q": float(ns.float().mean())})
-        log(f"  nprobe={m:5d} recall@10={rec:.4f} cand/q={sweep[-1]['cand_per_q']:.0f} "
-            f"surv/q={sweep[-1]['surv_per_q']:.0f}")
-        if rec >= args.target:
-            chosen = m
-            break
-    if chosen is None:
-        chosen = cand[-1]
-    m = chosen
-    rec = sweep[-1]["recall@10"]
+    def measure(mode, label):
+        sweep = []
+        cand = [args.nprobe] if args.nprobe else [8, 16, 32, 64, 128, 256, 384, 512, 640, 768, 832, 896,
+                                                  960, 1024]
+        chosen = None
+        for m in cand:
+            if m > B:
+                continue
+            ids, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, counters=True)
+            rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
+            sweep.append({"nprobe": m, "recall@10": round(rec, 4),
+                          "cand_per_q": float(nc.float().mean()), "surv_per_q": float(ns.float().mean())})
+            log(f"  [{label}] nprobe={m:5d} recall@10={rec:.4f} cand/q={sweep[-1]['cand_per_q']:.0f} "
+                f"surv/q={sweep[-1]['surv_per_q']:.0f}")
+            if rec >= args.target:
+                chosen = m
+                break
+        m = chosen if chosen is not None else cand[-1]
+        rec = sweep[-1]["recall@10"]
+        ids = torch.empty((w.n_q, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((w.n_q, k), dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            ix.search(q, co, ca, cv, k, m, mode=mode, out=(ids, dist))
+        _, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, counters=True)
+        surv_total = int(ns.to(torch.int64).sum())
+        cand_total = int(nc.to(torch.int64).sum())
+        torch.cuda.synchronize()
+        caps.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ix.search(q, co, ca, cv, k, m, mode=mode, out=(ids, dist))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = caps.profile_read()
+        caps.profile_enable(False)
+        ms_step = el * 1e3 / args.steps
+        qps = w.n_q * args.steps / el
+        scan_ms, scan_n = prof["scan"]
+        scan_avg_s = scan_ms / 1e3 / max(scan_n, 1)
+        launches_per_step = max(scan_n, 1) / args.steps
+        stage_ms = {s_: round(v[0] / args.steps, 4) for s_, v in prof.items()}
+        log(f"[{label}] timed: {args.steps} steps, {ms_step:.3f} ms/step, {qps:,.0f} queries/s at nprobe={m} "
+            f"recall@10={rec:.4f}; stages ms/step {stage_ms}")
+        if mode == 0:
+            work = 3.0 * w.d * surv_total / launches_per_step
+            roof = {"kernel": "k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)",
+                    "bound": "alu", "achieved": round(work / scan_avg_s / 1e12, 3),
+                    "peak": round(SCAN_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+                    "frac": round(work / scan_avg_s / 1e12 / SCAN_PEAK_TFLOPS, 4), "traffic": None,
+                    "avg_launch_ms": round(scan_avg_s * 1e3, 4), "algorithmic_flops_per_launch": work}
+        else:
+            work = 2.0 * w.d * cand_total / launches_per_step
+            roof = {"kernel": "k_scan_mfma<bf16> (query x candidate dot products on MFMA, exact filter "
+                              "epilogue, per-query top-4k)",
+                    "bound": "mfma", "achieved": round(work / scan_avg_s / 1e12, 3), "peak": MFMA_BF16_PEAK,
+                    "unit": "TFLOP/s", "frac": round(work / scan_avg_s / 1e12 / MFMA_BF16_PEAK, 4),
+                    "traffic": None, "avg_launch_ms": round(scan_avg_s * 1e3, 4),
+                    "algorithmic_flops_per_launch": work}
+        return dict(nprobe=m, recall=rec, qps=qps, ms_step=ms_step, stage_ms=stage_ms, sweep=sweep,
+                    cand_per_query=cand_total / w.n_q, surv_per_query=surv_total / w.n_q, roofline=roof)
 
-    ids = torch.empty((w.n_q, k), dtype=torch.int32, device=dev)
-    dist = torch.empty((w.n_q, k), dtype=torch.float32, device=dev)
-    nc = torch.empty(w.n_q, dtype=torch.int32, device=dev)
-    ns = torch.empty(w.n_q, dtype=torch.int32, device=dev)
-    for _ in range(args.warmup):
-        ix.search(q, co, ca, cv, k, m, out=(ids, dist))
-    torch.cuda.synchronize()
-
-    # counters of the timed workload (for the roofline's algorithmic work)
-    _, _, nc, ns = ix.search(q, co, ca, cv, k, m, counters=True)
-    surv_total = int(ns.to(torch.int64).sum())
-    cand_total = int(nc.to(torch.int64).sum())
-    torch.cuda.synchronize()
-
-    caps.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ix.search(q, co, ca, cv, k, m, out=(ids, dist))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = caps.profile_read()
-    caps.profile_enable(False)
+    plain = measure(0, "fp32")
+    lowp = measure(1, "bf16")
 
     if args.calib_copy:
         # a plain streaming kernel of known traffic (reads 512 MiB, writes
@@ -199,26 +219,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    ms_step = el * 1e3 / args.steps
-    qps = w.n_q * args.steps / el
-    scan_ms, scan_n = prof["scan"]
-    scan_avg_s = scan_ms / 1e3 / max(scan_n, 1)
-    launches_per_step = scan_n / args.steps
-    flops_per_launch = 3.0 * w.d * surv_total / launches_per_step
-    achieved = flops_per_launch / scan_avg_s / 1e12
-    stage_ms = {s: round(v[0] / args.steps, 4) for s, v in prof.items()}
-    log(f"timed: {args.steps} steps, {ms_step:.3f} ms/step, {qps:,.0f} queries/s at nprobe={m} "
-        f"recall@10={rec:.4f}")
-    log(f"stages (ms/step): {stage_ms}")
-
     out = {
         "metric": METRIC,
-        "value": round(qps, 1),
+        "value": round(plain["qps"], 1),
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(plain["ms_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -228,26 +236,24 @@ def main():
             "workload": "c2: N=1M d=128 uniform-int0-255 fp32, 3 dense attrs (10/50/200, Zipf 1.0), "
                         "B=1024 Lloyd-10 h=2, 10k queries with 1-3 AND constraints, selectivity "
                         "0.1-30%, k=10, squared L2",
-            "n": w.n, "d": w.d, "n_queries": w.n_q, "k": k, "nprobe": m, "recall@10": rec,
-            "recall_target": args.target, "build_s": round(build_s, 3),
-            "cand_per_query": cand_total / w.n_q, "surv_per_query": surv_total / w.n_q,
-            "stage_ms_per_step": stage_ms, "sweep": sweep,
+            "n": w.n, "d": w.d, "n_queries": w.n_q, "k": k, "nprobe": plain["nprobe"],
+            "recall@10": plain["recall"], "recall_target": args.target, "build_s": round(build_s, 3),
+            "cand_per_query": plain["cand_per_query"], "surv_per_query": plain["surv_per_query"],
+            "stage_ms_per_step": plain["stage_ms"], "sweep": plain["sweep"],
         },
-        "roofline": {
-            "kernel": "k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)",
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(SCAN_PEAK_TFLOPS, 2),
-            "unit": "TFLOP/s",
-            "frac": round(achieved / SCAN_PEAK_TFLOPS, 4),
-            "traffic": None,
-            "avg_launch_ms": round(scan_avg_s * 1e3, 4),
-            "algorithmic_flops_per_launch": flops_per_launch,
+        "roofline": plain["roofline"],
+        "modes": {
+            "fp32_centroid": {"queries_per_s": round(plain["qps"], 1), "nprobe": plain["nprobe"],
+                              "recall@10": plain["recall"], "ms_per_step": round(plain["ms_step"], 4)},
+            "bf16_centroid": {"queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"],
+                              "recall@10": lowp["recall"], "ms_per_step": round(lowp["ms_step"], 4),
+                              "rerank": 4 * k, "stage_ms_per_step": lowp["stage_ms"],
+                              "roofline": lowp["roofline"]},
         },
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle query path on a query sample ...")
-        out["cpu_baseline"] = cpu_baseline(ix, w, m)
+        out["cpu_baseline"] = cpu_baseline(ix, w, plain["nprobe"])
         log(f"  {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

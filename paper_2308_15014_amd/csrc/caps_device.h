@@ -145,4 +145,45 @@ __device__ inline void buf_reduce(uint64_t *buf, int32_t *bcnt, uint64_t *tau, i
     wave_sync();
 }
 
+// One wave: collects the keys of query slots slot0 + [r0, r1) of a partial
+// list array (slot_len keys per slot; `pcnt` gives the count per slot, or
+// lists are padded with ~0) into an LDS pool of capacity CAP, keeping the
+// best `keep` (<= 64) sorted at the front; returns the sum of cand[] over the
+// live slots (0 when cand is null).  Slots with sel == 0 hold nothing.
+template <int CAP>
+__device__ inline int gather_best(uint64_t *pool, int32_t *npool, const uint64_t *partials, const int32_t *pcnt,
+                                  const uint32_t *sel, const int32_t *cand, int64_t slot0, int r0, int r1,
+                                  int slot_len, int keep) {
+    const int lane = threadIdx.x & 63;
+    uint64_t unused_bound = ~0ull;
+    if (lane == 0) *npool = 0;
+    wave_sync();
+    int nc = 0;
+    for (int rb = r0; rb < r1; rb += 64) {
+        const int rr = rb + lane;
+        const int64_t slot = slot0 + rr;
+        const bool live = rr < r1 && sel[slot] != 0;
+        const int c = live ? (pcnt ? pcnt[slot] : slot_len) : 0;
+        if (live && cand) nc += cand[slot];
+        int cmax = c;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, 64));
+        for (int i = 0; i < cmax; i++) {
+            const uint64_t key = i < c ? partials[slot * slot_len + i] : ~0ull;
+            const bool has = key != ~0ull;
+            const uint64_t bal = __ballot(has);
+            if (*npool + 64 > CAP) buf_reduce<CAP>(pool, npool, &unused_bound, 0, keep);
+            const int n2 = *npool;
+            if (has) pool[n2 + __popcll(bal & lanemask_lt())] = key;
+            wave_sync();
+            if (lane == 0) *npool = n2 + __popcll(bal);
+            wave_sync();
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nc += __shfl_xor(nc, o, 64);
+    buf_reduce<CAP>(pool, npool, &unused_bound, 0, keep);
+    return nc;
+}
+
 }  // namespace caps

@@ -114,13 +114,14 @@ void prof_end(int stage, hipStream_t st);
 // ---- low-precision path (caps_mfma.hip)
 caps_status build_lowp(Index *ix, hipStream_t st);
 size_t lowp_scan_lds(const Index *ix, int r);
-struct LowpArgs;
-caps_status lowp_scan_and_merge(const Index *ix, const float *q, int32_t nb, const int32_t *tstart,
-                                const int32_t *pstart, const int32_t *pcount, const int32_t *entries,
-                                const uint32_t *sel, const QDesc *qd, int32_t m, int32_t k, int32_t r,
-                                void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt, uint64_t *tau,
-                                const int32_t *cand, int32_t *nsurv, int32_t *ncand, int32_t *out_ids,
-                                float *out_dist, int32_t max_tiles, hipStream_t st);
+caps_status lowp_scan(const Index *ix, int32_t nb, const int32_t *tstart, const int32_t *pstart,
+                      const int32_t *pcount, const int32_t *entries, const uint32_t *sel, const QDesc *qd,
+                      int32_t m, int32_t r, void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt,
+                      uint64_t *tau, int32_t *nsurv, int32_t max_tiles, bool first_round, const float *q,
+                      hipStream_t st);
+caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
+                       int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,
+                       int32_t *out_ids, float *out_dist, hipStream_t st);
 
 // ---- shared device utilities (caps_util.hip)
 caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,

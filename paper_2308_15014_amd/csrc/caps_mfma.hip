@@ -385,7 +385,10 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
             for (int s = 0; s < MAXS; s++)
                 if (s < nsteps) acc[bb] = Op::mma(a[s], Op::load(xrow + s * KSTEP_BYTES), acc[bb]);
         }
-        // ---- epilogue: exact filter, approximate key, threshold, append
+        // ---- epilogue: exact filter, approximate key, threshold; keys that
+        // beat their query's threshold are appended (rare once bounds are tight)
+        float esc[16];
+        uint32_t qmask = 0;
 #pragma unroll
         for (int bb = 0; bb < 4; bb++) {
             const int pi = bb * 16 + (lane & 15);
@@ -406,9 +409,23 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
                 float dot = acc[bb][rr];
                 if (PREC == CAPS_PREC_FP8) dot = dot * ps * e_qsc[rr];
                 const float sc = canon0(METRIC == 0 ? pn - 2.0f * dot : -dot);
-                const uint64_t key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)(c0 + pi);
+                esc[bb * 4 + rr] = sc;
                 e_surv[rr] += pass ? 1 : 0;
-                const bool qual = pass && key < tau[qi];
+                const uint64_t key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)(c0 + pi);
+                if (pass && key < tau[qi]) qmask |= 1u << (bb * 4 + rr);
+            }
+        }
+        uint32_t anyq = qmask;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) anyq |= __shfl_xor(anyq, o, 64);
+        if (anyq) {
+#pragma unroll
+            for (int e = 0; e < 16; e++) {   // wave-uniform test per element
+                if (!((anyq >> e) & 1u)) continue;
+                const int bb = e >> 2, rr = e & 3;
+                const int qi = qbase + g * 4 + rr;
+                const uint64_t key = ((uint64_t)f2ord(esc[e]) << 32) | (uint32_t)(c0 + bb * 16 + (lane & 15));
+                const bool qual = ((qmask >> e) & 1u) && key < tau[qi];
                 append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
             }
         }
@@ -459,38 +476,8 @@ __global__ __launch_bounds__(256) void k_merge_rerank(const uint64_t *__restrict
     if (qq >= nq) return;
     uint64_t *pool = pool_all[wq];
     int32_t *npool = &npool_all[wq];
-    if (lane == 0) *npool = 0;
-    uint64_t dummy_tau = ~0ull;
-    int nc = 0;
-    wave_sync();
-    for (int r0 = 0; r0 < m; r0 += 64) {
-        const int rr = r0 + lane;
-        const int64_t slot = (int64_t)qq * m + rr;
-        const bool live = rr < m && sel[slot] != 0;
-        const int c = live ? pcnt[slot] : 0;
-        if (live) nc += cand[slot];
-        int cmax = c;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, 64));
-        for (int i = 0; i < cmax; i++) {
-            const bool has = i < c;
-            const uint64_t key = has ? partials[slot * r + i] : ~0ull;
-            const uint64_t bal = __ballot(has);
-            const int n = *npool;
-            if (n + 64 > kMCap) {
-                buf_reduce<kMCap>(pool, npool, &dummy_tau, 0, r);
-            }
-            const int n2 = *npool;
-            if (has) pool[n2 + __popcll(bal & lanemask_lt())] = key;
-            wave_sync();
-            if (lane == 0) *npool = n2 + __popcll(bal);
-            wave_sync();
-        }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nc += __shfl_xor(nc, o, 64);
+    const int nc = gather_best<kMCap>(pool, npool, partials, pcnt, sel, cand, (int64_t)qq * m, 0, m, r, r);
     if (lane == 0) ncand[qq] = nc;
-    buf_reduce<kMCap>(pool, npool, &dummy_tau, 0, r);
     const int nr = *npool;   // <= r <= 64, sorted by approximate key
     // exact FP32 rescoring, one candidate per lane
     uint64_t key2 = ~0ull;
@@ -550,14 +537,14 @@ size_t lowp_scan_lds(const Index *ix, int r) {
     return LowpLds(ix->dpad, esize_of(ix->prec), r <= 48 ? 64 : 128).total + 64;
 }
 
-caps_status lowp_scan_and_merge(const Index *ix, const float *q, int32_t nb, const int32_t *tstart,
-                                const int32_t *pstart, const int32_t *pcount, const int32_t *entries,
-                                const uint32_t *sel, const QDesc *qd, int32_t m, int32_t k, int32_t r,
-                                void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt, uint64_t *tau,
-                                const int32_t *cand, int32_t *nsurv, int32_t *ncand, int32_t *out_ids,
-                                float *out_dist, int32_t max_tiles, hipStream_t st) {
-    hipLaunchKernelGGL(k_qquant, dim3((nb + 127) / 128), dim3(128), 0, st, q, nb, ix->d, ix->dpad, ix->prec, qlow,
-                       qscale);
+caps_status lowp_scan(const Index *ix, int32_t nb, const int32_t *tstart, const int32_t *pstart,
+                      const int32_t *pcount, const int32_t *entries, const uint32_t *sel, const QDesc *qd,
+                      int32_t m, int32_t r, void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt,
+                      uint64_t *tau, int32_t *nsurv, int32_t max_tiles, bool first_round, const float *q,
+                      hipStream_t st) {
+    if (first_round)
+        hipLaunchKernelGGL(k_qquant, dim3((nb + 127) / 128), dim3(128), 0, st, q, nb, ix->d, ix->dpad, ix->prec,
+                           qlow, qscale);
     LowpArgs A;
     A.tstart = tstart;
     A.pstart = pstart;
@@ -590,6 +577,12 @@ caps_status lowp_scan_and_merge(const Index *ix, const float *q, int32_t nb, con
     hipLaunchKernelGGL(fn, dim3((unsigned)max_tiles), dim3(kLNT), lds, st, A);
     prof_end(CAPS_STAGE_SCAN, st);
     CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
+                       int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,
+                       int32_t *out_ids, float *out_dist, hipStream_t st) {
     prof_begin(CAPS_STAGE_MERGE, st);
     if (ix->metric == 0)
         hipLaunchKernelGGL(k_merge_rerank<0>, dim3((nb + 3) / 4), dim3(256), 0, st, partials, pcnt, sel, cand, nb, m,

@@ -240,29 +240,56 @@ constexpr int kBucketQ = 16;   // queries per bucketing block
 
 __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t b, int32_t ngrp, int32_t *__restrict__ hist) {
+                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                     int32_t *__restrict__ hist) {
     extern __shared__ int32_t cnt[];
     for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256)
-        if (sel[e]) atomicAdd(&cnt[probes[e]], 1);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const int32_t rr = (int32_t)(e % m);
+        if (rr >= r0 && rr < r1 && sel[e]) atomicAdd(&cnt[probes[e]], 1);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
 }
 
 __global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t b, int32_t ngrp, const int32_t *__restrict__ hscan,
+                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                     const int32_t *__restrict__ hscan,
                                                      int32_t *__restrict__ entries) {
     extern __shared__ int32_t run[];
     for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256)
-        if (sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const int32_t rr = (int32_t)(e % m);
+        if (rr >= r0 && rr < r1 && sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
+    }
+}
+
+// Seed bound: the keep-th best key over a query's first s probes (any keep
+// valid candidates bound the final keep-th key from above).  One wave per
+// query; ~0 when fewer than keep candidates were found.
+constexpr int kSeedCap = 256;
+
+__global__ __launch_bounds__(256) void k_seed_tau(const uint64_t *__restrict__ partials,
+                                                  const int32_t *__restrict__ pcnt,
+                                                  const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                  int32_t s, int32_t slot_len, int32_t keep,
+                                                  uint64_t *__restrict__ tau) {
+    __shared__ uint64_t pool_all[4][kSeedCap];
+    __shared__ int32_t npool_all[4];
+    const int wq = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qq = blockIdx.x * 4 + wq;
+    if (qq >= nq) return;
+    uint64_t *pool = pool_all[wq];
+    int32_t *npool = &npool_all[wq];
+    (void)gather_best<kSeedCap>(pool, npool, partials, pcnt, sel, nullptr, (int64_t)qq * m, 0, s, slot_len, keep);
+    if (lane == 0 && *npool == keep && pool[keep - 1] < tau[qq]) tau[qq] = pool[keep - 1];
 }
 
 // Bucket starts, sizes and tile starts per partition (single workgroup).
@@ -909,52 +936,77 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             CAPS_HIP(hipGetLastError());
             continue;
         }
-        hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel, nb,
-                           m, b, ngrp, hist);
-        {
-            const caps_status s = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
-            if (s != CAPS_OK) return s;
-        }
-        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount, tstart);
-        hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel, nb,
-                           m, b, ngrp, hscan, entries);
         hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
-        CAPS_HIP(hipGetLastError());
         prof_end(CAPS_STAGE_SELECT, st);
-        ScanArgs A;
-        A.tstart = tstart;
-        A.pstart = pstart;
-        A.pcount = pcount;
-        A.entries = entries;
-        A.sel = sel;
-        A.q = q + (int64_t)q0 * d;
-        A.qd = qd;
-        A.offs = ix->offs;
-        A.perm = ix->perm;
-        A.vecs = ix->vecs;
-        A.words = ix->words;
-        A.sigs = ix->sigs;
-        A.slots = ix->slots;
-        A.partials = partials;
-        A.tau = tau;
-        A.nsurv = nsurv + q0;
-        A.d = d;
-        A.m = m;
-        A.h = h;
-        A.b = b;
-        A.k = k;
-        const int64_t max_tiles = (pairs + qb - 1) / qb + b;
+        // Two rounds: the first probes of every query (best first) give each
+        // query a tight seed bound on its final r-th key; the remaining probes
+        // are scanned against it.
+        const int32_t s_seed = m >= 32 ? std::max(8, m / 16) : m;
+        for (int round = 0; round < 2; round++) {
+            const int32_t r0 = round == 0 ? 0 : s_seed;
+            const int32_t r1 = round == 0 ? s_seed : m;
+            if (r0 >= r1) continue;
+            prof_begin(CAPS_STAGE_SELECT, st);
+            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                               nb, m, r0, r1, b, ngrp, hist);
+            {
+                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
+                if (es != CAPS_OK) return es;
+            }
+            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
+                               tstart);
+            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                               nb, m, r0, r1, b, ngrp, hscan, entries);
+            CAPS_HIP(hipGetLastError());
+            prof_end(CAPS_STAGE_SELECT, st);
+            const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
+            if (lowp) {
+                const caps_status ls =
+                    lowp_scan(ix, nb, tstart, pstart, pcount, entries, sel, qd, m, r, W.qlow, W.qscale, partials,
+                              W.pcnt, tau, nsurv + q0, (int32_t)max_tiles, round == 0, q + (int64_t)q0 * d, st);
+                if (ls != CAPS_OK) return ls;
+            } else {
+                ScanArgs A;
+                A.tstart = tstart;
+                A.pstart = pstart;
+                A.pcount = pcount;
+                A.entries = entries;
+                A.sel = sel;
+                A.q = q + (int64_t)q0 * d;
+                A.qd = qd;
+                A.offs = ix->offs;
+                A.perm = ix->perm;
+                A.vecs = ix->vecs;
+                A.words = ix->words;
+                A.sigs = ix->sigs;
+                A.slots = ix->slots;
+                A.partials = partials;
+                A.tau = tau;
+                A.nsurv = nsurv + q0;
+                A.d = d;
+                A.m = m;
+                A.h = h;
+                A.b = b;
+                A.k = k;
+                prof_begin(CAPS_STAGE_SCAN, st);
+                hipLaunchKernelGGL(scan_fn, dim3((unsigned)max_tiles), dim3(scan_waves(k) * 64), lds, st, A);
+                prof_end(CAPS_STAGE_SCAN, st);
+                CAPS_HIP(hipGetLastError());
+            }
+            if (round == 0 && s_seed < m) {
+                prof_begin(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_seed_tau, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials,
+                                   lowp ? W.pcnt : nullptr, sel, nb, m, s_seed, r, r, tau);
+                prof_end(CAPS_STAGE_SELECT, st);
+                CAPS_HIP(hipGetLastError());
+            }
+        }
         if (lowp) {
-            const caps_status ls = lowp_scan_and_merge(
-                ix, q + (int64_t)q0 * d, nb, tstart, pstart, pcount, entries, sel, qd, m, k, r, W.qlow, W.qscale,
-                partials, W.pcnt, tau, cand, nsurv + q0, ncand + q0, out_ids + (int64_t)q0 * k,
-                out_dist + (int64_t)q0 * k, (int32_t)max_tiles, st);
+            const caps_status ls = lowp_merge(ix, q + (int64_t)q0 * d, nb, sel, m, k, r, partials, W.pcnt, cand,
+                                              ncand + q0, out_ids + (int64_t)q0 * k, out_dist + (int64_t)q0 * k, st);
             if (ls != CAPS_OK) return ls;
             continue;
         }
-        prof_begin(CAPS_STAGE_SCAN, st);
-        hipLaunchKernelGGL(scan_fn, dim3((unsigned)max_tiles), dim3(scan_waves(k) * 64), lds, st, A);
-        prof_end(CAPS_STAGE_SCAN, st);
         prof_begin(CAPS_STAGE_MERGE, st);
         int32_t *oi = out_ids + (int64_t)q0 * k;
         float *od = out_dist + (int64_t)q0 * k;
