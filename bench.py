@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
     ap.add_argument("--target", type=float, default=0.9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="fp32,bf16",
+                    help="comma list of search modes to time (the JSON needs fp32)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -207,8 +209,12 @@ def main():
         return dict(nprobe=m, recall=rec, qps=qps, ms_step=ms_step, stage_ms=stage_ms, sweep=sweep,
                     cand_per_query=cand_total / w.n_q, surv_per_query=surv_total / w.n_q, roofline=roof)
 
-    plain = measure(0, "fp32")
-    lowp = measure(1, "bf16")
+    modes = args.modes.split(",")
+    plain = measure(0, "fp32") if "fp32" in modes else None
+    lowp = measure(1, "bf16") if "bf16" in modes else None
+    if plain is None:
+        log("fp32 mode not timed: no JSON line")
+        return
 
     if args.calib_copy:
         # a plain streaming kernel of known traffic (reads 512 MiB, writes
@@ -245,12 +251,13 @@ def main():
         "modes": {
             "fp32_centroid": {"queries_per_s": round(plain["qps"], 1), "nprobe": plain["nprobe"],
                               "recall@10": plain["recall"], "ms_per_step": round(plain["ms_step"], 4)},
-            "bf16_centroid": {"queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"],
-                              "recall@10": lowp["recall"], "ms_per_step": round(lowp["ms_step"], 4),
-                              "rerank": 4 * k, "stage_ms_per_step": lowp["stage_ms"],
-                              "roofline": lowp["roofline"]},
         },
     }
+    if lowp is not None:
+        out["modes"]["bf16_centroid"] = {
+            "queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"], "recall@10": lowp["recall"],
+            "ms_per_step": round(lowp["ms_step"], 4), "rerank": 4 * k, "stage_ms_per_step": lowp["stage_ms"],
+            "roofline": lowp["roofline"]}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle query path on a query sample ...")
         out["cpu_baseline"] = cpu_baseline(ix, w, plain["nprobe"])

@@ -172,6 +172,7 @@ typedef struct {
     int32_t n_dense, label_vocab, n_tokens;
     int32_t max_subpartition;   /* largest sub-partition size */
     int32_t precision;          /* CAPS_PREC_* of the low-precision copy */
+    int32_t lowp_dpad;          /* row width of that copy (0 without one) */
     int64_t device_bytes;       /* bytes the index holds on the device */
 } caps_index_info_t;
 
@@ -214,7 +215,8 @@ caps_status caps_profile_read(caps_profile_t *out); /* synchronises the events *
 /*
  * caps_index_export_lowp -- copy the low-precision copy to HOST buffers (any
  * may be NULL): codes n x dpad (2-byte BF16/FP16 bit patterns or 1-byte FP8
- * codes, CSR order, dpad = d rounded up to a multiple of 32, zero padded),
+ * codes, CSR order, dpad = lowp_dpad of caps_index_info: the smallest of
+ * 32, 64, 128, 256 that is >= d, zero padded),
  * scale n (FP8 per-vector scales, CSR order), xnorm n (exact FP32 |x|^2 of
  * each CSR row, sequential fma).  EINVAL if the index has no such copy.
  */

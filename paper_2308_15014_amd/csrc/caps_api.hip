@@ -207,6 +207,7 @@ extern "C" caps_status caps_index_info(const caps_index *idx, caps_index_info_t 
     out->n_tokens = ix.sch.n_tok;
     out->max_subpartition = ix.max_sub;
     out->precision = ix.prec;
+    out->lowp_dpad = ix.prec == CAPS_PREC_NONE ? 0 : ix.dpad;
     out->device_bytes = ix.bytes;
     return CAPS_OK;
 }

@@ -10,6 +10,20 @@ namespace caps {
 
 constexpr int kWave = 64;
 
+// Workgroups of a launch are dealt to the 8 XCDs of the chip round-robin
+// (workgroup i runs on XCD i % 8), each XCD with its own L2.  Maps a launch
+// index to a tile so that every XCD receives one contiguous range of the
+// `ntiles` live tiles, in order: consecutive tiles (the same partition) then
+// share one L2.  Needs a grid of at least 8 * ceil(ntiles / 8) workgroups;
+// returns -1 for a workgroup without a tile.
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int bid, int ntiles) {
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    const int x = bid % kXcds, s = bid / kXcds;
+    const int vt = x * per + s;
+    return (s < per && vt < ntiles) ? vt : -1;
+}
+
 __device__ inline uint64_t lanemask_lt() {
     const int lane = threadIdx.x & (kWave - 1);
     return lane == 0 ? 0ull : (~0ull >> (kWave - lane));

@@ -72,7 +72,7 @@ struct Index {
     float *vecs = nullptr;      // n x d, CSR order
     // low-precision copy for the matrix-core scan (search mode 1)
     int32_t prec = 0;           // CAPS_PREC_*
-    int32_t dpad = 0;           // d rounded up to a multiple of 32 (zero padded)
+    int32_t dpad = 0;           // 32, 64, 128 or 256: smallest >= d (zero padded)
     void *lvecs = nullptr;      // n x dpad elements (2 bytes BF16/FP16, 1 byte FP8), CSR order
     float *lscale = nullptr;    // n per-vector FP8 scales (FP8 only)
     float *xnorm = nullptr;     // n exact FP32 |x|^2 (sequential fma), CSR order

@@ -84,7 +84,11 @@ static int esize_of(int prec) { return prec == CAPS_PREC_FP8 ? 1 : 2; }
 
 caps_status build_lowp(Index *ix, hipStream_t st) {
     if (ix->prec == CAPS_PREC_NONE) return CAPS_OK;
-    ix->dpad = (ix->d + 31) & ~31;
+    // rows padded to 32 x {1, 2, 4, 8} coordinates: the scan kernels are
+    // specialised on the number of 32-wide MFMA K-steps
+    int ns = 1;
+    while (32 * ns < ix->d) ns <<= 1;
+    ix->dpad = 32 * ns;
     const size_t eb = (size_t)esize_of(ix->prec);
     const size_t lbytes = (size_t)ix->n * ix->dpad * eb;
     CAPS_HIP(hipMalloc(&ix->lvecs, lbytes));
@@ -138,8 +142,8 @@ struct LowpArgs {
     uint64_t *partials;         // per (query, probe): up to r keys (score << 32 | CSR position)
     int32_t *pcnt;              // per (query, probe): number of keys written
     uint64_t *tau;              // per query: shared bound on its r-th approximate key
-    int32_t *nsurv;
-    int32_t dpad, m, h, b, r;
+    int32_t *nsurv;             // per query survivor counts, or null (not counted)
+    int32_t m, h, b, r, metric;
 };
 
 constexpr int kLNW = 4;          // waves per tile
@@ -147,16 +151,16 @@ constexpr int kLQPW = 16;        // queries per wave (MFMA rows)
 constexpr int kLQB = kLNW * kLQPW;
 constexpr int kLCH = 64;         // points per chunk: four 16-column MFMA blocks
 constexpr int kLNT = kLNW * 64;
+constexpr int kTauRefresh = 8;   // chunks between reads of the shared per-query bounds
 
 struct LowpLds {
-    size_t xl, xw, xn, xsc, xsig, xslot, buf, bcnt, tau, qslot, qd, total;
-    int xstride;   // bytes per staged row
-    __host__ __device__ LowpLds(int dpad, int esize, int cb) {
-        xstride = dpad * esize + 16;
+    size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, total;
+    __host__ __device__ constexpr LowpLds(int row_bytes, int cb)
+        : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), total(0) {
         size_t o = 0;
-        auto take = [&](size_t bytes) __host__ __device__ {
+        const auto take = [&o](size_t bytes) {
             o = (o + 15) & ~(size_t)15;
-            size_t r = o;
+            const size_t r = o;
             o += bytes;
             return r;
         };
@@ -167,10 +171,8 @@ struct LowpLds {
         xw = take(sizeof(uint32_t) * kLCH);
         xn = take(sizeof(float) * kLCH);
         xsc = take(sizeof(float) * kLCH);
-        xsig = take(sizeof(uint64_t) * kLCH);
-        xslot = take(sizeof(uint16_t) * kLCH * kMaxLabels);
         buf = take(sizeof(uint64_t) * (size_t)kLQB * cb);
-        xl = take((size_t)kLCH * xstride);
+        xl = take((size_t)kLCH * (row_bytes + 16));
         total = take(16);
     }
 };
@@ -234,20 +236,40 @@ __device__ inline void append_keys(bool qual, int qi, uint64_t key, uint64_t *bu
     }
 }
 
-template <int PREC, int METRIC, bool HAS_LABELS, int CB>
+// Float image of a bound key: every key below the bound has a score <= it.
+__device__ inline float bound_score(uint64_t t) {
+    return t == ~0ull ? __builtin_huge_valf() : ord2f((uint32_t)(t >> 32));
+}
+
+// One tile = one partition x up to 64 of the (query, probe) entries that
+// route to it.  Wave w owns queries 16w..16w+15: their A operands sit in
+// registers, their candidate buffers and bounds in LDS.  Chunks of 64 CSR
+// rows of the levels any of the tile's queries selected are staged in LDS
+// (the next chunk's loads are in flight while the current one is scored).
+// Per element the epilogue is branch free: one fused score, a compare against
+// the row's cached float bound (NaN for a row whose query skips the chunk's
+// level or has no query, NaN score for a padding column, so neither ever
+// compares true) and the packed dense-attribute test, reduced by ballots.
+// Exact keys, label tests and appends run only for elements that pass.
+template <int PREC, bool HAS_LABELS, int CB, int NS>
 __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
     constexpr int ES = Op::ES;
     constexpr int KSTEP_BYTES = 32 * ES;                 // one MFMA K-step of a row
     constexpr int LANE_BYTES = 8 * ES;                   // one lane's slice of a K-step
-    constexpr int MAXS = 8;                              // dpad <= 256
+    constexpr int ROWB = NS * KSTEP_BYTES;               // bytes per CSR row of the copy
+    constexpr int XSTRIDE = ROWB + 16;                   // padded LDS row (bank spread)
+    constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row
+    constexpr int PIECES = kLCH * V16;
+    constexpr int UPT = (PIECES + kLNT - 1) / kLNT;      // pieces per thread per chunk
+    constexpr LowpLds L(ROWB, CB);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t spo[kMaxHeight + 2];
     __shared__ uint32_t lvw[kLNW];
 
-    const int tile = blockIdx.x;
-    if (tile >= A.tstart[A.b]) return;
+    const int tile = xcd_tile(blockIdx.x, A.tstart[A.b]);
+    if (tile < 0) return;
     int lo = 0, hi = A.b;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -258,15 +280,11 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
     const int i0 = (tile - A.tstart[p]) * kLQB;
     const int nqt = min(kLQB, A.pcount[p] - i0);
     const int32_t *ent = A.entries + A.pstart[p] + i0;
-    const int h = A.h, r = A.r, dpad = A.dpad;
-    const int nsteps = dpad / 32;
-    const LowpLds L(dpad, ES, CB);
+    const int h = A.h, r = A.r;
     uint8_t *xl = smem + L.xl;
     uint32_t *xw = reinterpret_cast<uint32_t *>(smem + L.xw);
     float *xn = reinterpret_cast<float *>(smem + L.xn);
     float *xsc = reinterpret_cast<float *>(smem + L.xsc);
-    uint64_t *xsig = reinterpret_cast<uint64_t *>(smem + L.xsig);
-    uint16_t *xslot = reinterpret_cast<uint16_t *>(smem + L.xslot);
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem + L.buf);
     int32_t *bcnt = reinterpret_cast<int32_t *>(smem + L.bcnt);
     uint64_t *tau = reinterpret_cast<uint64_t *>(smem + L.tau);
@@ -276,6 +294,10 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int qbase = w * kLQPW;
     const bool has_dense = A.words != nullptr;
+    const bool l2 = A.metric == 0;
+    const bool count = A.nsurv != nullptr;
+    const float qnan = __builtin_nanf("");
+    const float cm = l2 ? -2.0f : -1.0f;   // score = cm * dot + |x|^2 (L2) or + 0 (IP)
     if (t <= h + 1) spo[t] = A.offs[(int64_t)p * (h + 1) + t];
     // per-query state (lane i < 16 of wave w: query qbase + i)
     uint32_t my_sel = 0;
@@ -286,10 +308,10 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
         my_qq = slot / A.m;
         my_sel = A.sel[slot];
         qslot[qi] = slot;
-        qds[qi] = A.qd[my_qq];
+        if (HAS_LABELS) qds[qi] = A.qd[my_qq];
         tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bcnt[qi] = 0;
     }
+    if (lane < kLQPW) bcnt[qbase + lane] = 0;   // rows without a query too
     {
         uint32_t wor = my_sel;
 #pragma unroll
@@ -297,147 +319,219 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
         if (lane == 0) lvw[w] = wor;
     }
     // MFMA A operands: query row qbase + lane%16, K slice (lane/16)*8 of each step
-    VT a[MAXS];
+    VT a[NS];
     {
         const int arow = qbase + (lane & 15);
         const bool aok = arow < nqt;
         const int64_t qq = aok ? (int64_t)(ent[arow] / A.m) : 0;
-        const uint8_t *src = A.qlow + qq * dpad * ES + (lane >> 4) * LANE_BYTES;
+        const uint8_t *src = A.qlow + qq * ROWB + (lane >> 4) * LANE_BYTES;
 #pragma unroll
-        for (int s = 0; s < MAXS; s++) {
-            if (s < nsteps && aok) a[s] = Op::load(src + s * KSTEP_BYTES);
-            else a[s] = VT{};
-        }
+        for (int s = 0; s < NS; s++) a[s] = aok ? Op::load(src + s * KSTEP_BYTES) : VT{};
     }
-    // per-lane epilogue state: rows (lane/16)*4 + rr are my four queries
+    // per-lane epilogue rows: (lane/16)*4 + rr of the wave's 16 queries
     const int g = lane >> 4;
-    uint32_t e_sel[4], e_mask[4], e_val[4];
-    float e_qsc[4];
-    int e_surv[4] = {0, 0, 0, 0};
+    uint32_t rsel[4], rmask[4], rval[4];
+    float rqs[4], rtf[4];
+    int rsurv[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int qi = qbase + g * 4 + rr;
-        e_sel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
+        rsel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
         if (qi < nqt) {
-            const int32_t slot = ent[qi];
-            const QDesc qd = A.qd[slot / A.m];
-            e_mask[rr] = qd.dmask;
-            e_val[rr] = qd.dval;
-            e_qsc[rr] = A.qscale[slot / A.m];
+            const int32_t qq = ent[qi] / A.m;
+            const QDesc qd = A.qd[qq];
+            rmask[rr] = qd.dmask;
+            rval[rr] = qd.dval;
+            rqs[rr] = PREC == CAPS_PREC_FP8 ? A.qscale[qq] : 1.0f;
         } else {
-            e_mask[rr] = 0;
-            e_val[rr] = 1;   // never matches
-            e_qsc[rr] = 0.0f;
+            rmask[rr] = 0;
+            rval[rr] = 1;   // never matches
+            rqs[rr] = 0.0f;
         }
     }
     __syncthreads();
+    auto refresh_bounds = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const int qi = qbase + g * 4 + rr;
+            rtf[rr] = qi < nqt ? bound_score(tau[qi]) : qnan;
+        }
+    };
+    refresh_bounds();
     uint32_t lv = 0;
 #pragma unroll
     for (int i = 0; i < kLNW; i++) lv |= lvw[i];
-    const int32_t *po = spo;
-    auto advance = [&](int &j, int32_t &c0) {
-        c0 += kLCH;
-        while (j <= h && (!(lv & (1u << j)) || c0 >= po[j + 1])) {
-            j++;
-            if (j <= h) c0 = po[j];
+    lv = __builtin_amdgcn_readfirstlane(lv);
+    // chunk cursor (wave-uniform, kept in scalar registers): level j, first
+    // row c0 of the chunk, end of the level
+    auto po = [&](int i) { return __builtin_amdgcn_readfirstlane(spo[i]); };
+    auto next_level = [&](int &j, int32_t &c0, int32_t &end) {
+        for (j++; j <= h; j++) {
+            if (!((lv >> j) & 1u)) continue;
+            c0 = po(j);
+            end = po(j + 1);
+            if (c0 < end) return;
         }
     };
-    int cj = 0;
-    int32_t cc0 = po[0] - kLCH;
-    advance(cj, cc0);
-    const int row_bytes = dpad * ES;
-    const int xstride = L.xstride;
+    auto advance = [&](int &j, int32_t &c0, int32_t &end) {
+        c0 += kLCH;
+        if (c0 >= end) next_level(j, c0, end);
+    };
+
+    // register staging of one chunk: UPT 16-byte pieces per thread, plus the
+    // per-point word / norm / scale held by the first 64 threads.  Rows past
+    // the level's end load the level's last row (in bounds); their columns are
+    // masked by a NaN norm.
+    typedef uint32_t PreT __attribute__((ext_vector_type(4 * UPT)));   // stays in VGPRs
+    PreT pre = {};
+    uint32_t pre_w = 0;
+    float pre_n = qnan, pre_s = 1.0f;
+    auto fetch = [&](int32_t c0, int cn) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.lvecs + (int64_t)c0 * ROWB);
+#pragma unroll
+        for (int u = 0; u < UPT; u++) {
+            const int e = t + u * kLNT;
+            if (PIECES % kLNT == 0 || e < PIECES) {
+                const int row = min(e / V16, cn - 1);
+                const uint4 v = src[row * V16 + e % V16];
+                pre[4 * u + 0] = v.x;
+                pre[4 * u + 1] = v.y;
+                pre[4 * u + 2] = v.z;
+                pre[4 * u + 3] = v.w;
+            }
+        }
+        if (t < kLCH) {
+            const int row = c0 + min(t, cn - 1);
+            const float xn2 = l2 ? A.xnorm[row] : 0.0f;
+            pre_w = has_dense ? A.words[row] : 0u;
+            pre_n = t < cn ? xn2 : qnan;
+            if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
+        }
+    };
+
+    int cj = -1;
+    int32_t cc0 = 0, cend = 0;
+    next_level(cj, cc0, cend);
+    if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
+    int nchunk = 0;
 
     while (cj <= h) {
         const int j = cj;
         const int32_t c0 = cc0;
-        const int cn = min(kLCH, po[j + 1] - c0);
+        const int cn = min(kLCH, cend - c0);
         __syncthreads();   // previous chunk fully consumed
-        {
-            const uint8_t *src = A.lvecs + (int64_t)c0 * row_bytes;
-            const int n16 = cn * row_bytes / 16;
-            const int per_row = row_bytes / 16;
-            for (int e = t; e < n16; e += kLNT) {
-                const int rrow = e / per_row, c = e - rrow * per_row;
-                *reinterpret_cast<uint4 *>(xl + rrow * xstride + 16 * c) = reinterpret_cast<const uint4 *>(src)[e];
-            }
-            if (t < cn) {
-                xw[t] = has_dense ? A.words[c0 + t] : 0u;
-                xn[t] = METRIC == 0 ? A.xnorm[c0 + t] : 0.0f;
-                xsc[t] = PREC == CAPS_PREC_FP8 ? A.lscale[c0 + t] : 1.0f;
-                if (HAS_LABELS) {
-                    xsig[t] = A.sigs[c0 + t];
-                    *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) =
-                        *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
-                }
-            }
+#pragma unroll
+        for (int u = 0; u < UPT; u++) {
+            const int e = t + u * kLNT;
+            if (PIECES % kLNT == 0 || e < PIECES)
+                *reinterpret_cast<uint4 *>(xl + (e / V16) * XSTRIDE + (e % V16) * 16) =
+                    make_uint4(pre[4 * u], pre[4 * u + 1], pre[4 * u + 2], pre[4 * u + 3]);
         }
-        advance(cj, cc0);
+        if (t < kLCH) {
+            xw[t] = pre_w;
+            xn[t] = pre_n;
+            xsc[t] = pre_s;
+        }
+        const bool refresh = (++nchunk % kTauRefresh) == 0;
+        if (refresh && lane < kLQPW && my_qq >= 0) {
+            const uint64_t gt = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (gt < tau[qbase + lane]) tau[qbase + lane] = gt;
+        }
+        advance(cj, cc0, cend);
+        if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
         __syncthreads();
+        if (refresh) refresh_bounds();
 
         // ---- MFMA: my 16 queries x the chunk's 64 points
         f32x4 acc[4];
 #pragma unroll
-        for (int bb = 0; bb < 4; bb++) {
-            acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            const uint8_t *xrow = xl + (bb * 16 + (lane & 15)) * xstride + (lane >> 4) * LANE_BYTES;
+        for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const uint8_t *xb = xl + (lane & 15) * XSTRIDE + (lane >> 4) * LANE_BYTES;
 #pragma unroll
-            for (int s = 0; s < MAXS; s++)
-                if (s < nsteps) acc[bb] = Op::mma(a[s], Op::load(xrow + s * KSTEP_BYTES), acc[bb]);
-        }
-        // ---- epilogue: exact filter, approximate key, threshold; keys that
-        // beat their query's threshold are appended (rare once bounds are tight)
-        float esc[16];
-        uint32_t qmask = 0;
+        for (int s = 0; s < NS; s++)
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++)
+                acc[bb] = Op::mma(a[s], Op::load(xb + bb * 16 * XSTRIDE + s * KSTEP_BYTES), acc[bb]);
+
+        // ---- epilogue, one 16-point block at a time
+        float tfj[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
 #pragma unroll
         for (int bb = 0; bb < 4; bb++) {
             const int pi = bb * 16 + (lane & 15);
-            const bool pok = pi < cn;
-            const uint32_t pw = pok ? xw[pi] : 0u;
-            const float pn = pok ? xn[pi] : 0.0f;
-            const float ps = pok ? xsc[pi] : 0.0f;
-            const uint64_t psig = (HAS_LABELS && pok) ? xsig[pi] : 0ull;
+            const uint32_t pw = xw[pi];
+            const float pn = xn[pi];
+            const float ps = xsc[pi];
+            float esc[4];
+            uint64_t hit[4];
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
-                const int qi = qbase + g * 4 + rr;
-                bool pass = pok && ((e_sel[rr] >> j) & 1u);
-                if (HAS_LABELS) {
-                    if (pass) pass = point_passes(qds[qi], has_dense, true, pw, psig, xslot + pi * kMaxLabels);
-                } else {
-                    pass = pass && ((pw & e_mask[rr]) == e_val[rr]);
-                }
-                float dot = acc[bb][rr];
-                if (PREC == CAPS_PREC_FP8) dot = dot * ps * e_qsc[rr];
-                const float sc = canon0(METRIC == 0 ? pn - 2.0f * dot : -dot);
-                esc[bb * 4 + rr] = sc;
-                e_surv[rr] += pass ? 1 : 0;
-                const uint64_t key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)(c0 + pi);
-                if (pass && key < tau[qi]) qmask |= 1u << (bb * 4 + rr);
+                float dd = acc[bb][rr];
+                if (PREC == CAPS_PREC_FP8) dd = dd * ps * rqs[rr];
+                esc[rr] = fmaf(cm, dd, pn);
+                // two single-compare ballots: each is one v_cmp into an SGPR pair
+                hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]) &
+                          __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
             }
-        }
-        uint32_t anyq = qmask;
+            if (count) {   // survivors of the exact filter (statistics only)
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) anyq |= __shfl_xor(anyq, o, 64);
-        if (anyq) {
+                for (int rr = 0; rr < 4; rr++) {
+                    bool ok = pi < cn && ((rsel[rr] >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
+                    if (HAS_LABELS && ok) {
+                        const int qi = qbase + g * 4 + rr;
+                        ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                          A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                    }
+                    rsurv[rr] += ok ? 1 : 0;
+                }
+            }
+            if (hit[0] | hit[1] | hit[2] | hit[3]) {
+                bool reduced = false;
 #pragma unroll
-            for (int e = 0; e < 16; e++) {   // wave-uniform test per element
-                if (!((anyq >> e) & 1u)) continue;
-                const int bb = e >> 2, rr = e & 3;
-                const int qi = qbase + g * 4 + rr;
-                const uint64_t key = ((uint64_t)f2ord(esc[e]) << 32) | (uint32_t)(c0 + bb * 16 + (lane & 15));
-                const bool qual = ((qmask >> e) & 1u) && key < tau[qi];
-                append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+                for (int rr = 0; rr < 4; rr++) {   // wave-uniform test per row group
+                    if (!hit[rr]) continue;
+                    // lanes 16g..16g+15 hold row 4g+rr: one query per 16-lane group
+                    const int qi = qbase + g * 4 + rr;
+                    bool qual = (hit[rr] >> lane) & 1ull;
+                    if (HAS_LABELS && qual)
+                        qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                            A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                    // the score bound admits ties with the current bound key;
+                    // such keys are no better than it and never reach the final r
+                    const uint64_t key = ((uint64_t)f2ord(canon0(esc[rr])) << 32) | (uint32_t)(c0 + pi);
+                    const uint64_t gm = __builtin_amdgcn_ballot_w64(qual) & (0xFFFFull << (16 * g));
+                    const int cnt = __popcll(gm);
+                    const int c = bcnt[qi];
+                    if (__builtin_amdgcn_ballot_w64(c + cnt > CB) == 0) {
+                        // every group's keys fit: direct slots, one count update per group
+                        if (qual) buf[qi * CB + c + __popcll(gm & lanemask_lt())] = key;
+                        if ((lane & 15) == 0 && cnt) bcnt[qi] = c + cnt;
+                        wave_sync();
+                    } else {
+                        wave_sync();
+                        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+                        reduced = true;
+                    }
+                }
+                if (reduced) {   // a full buffer was cut back to r keys: bounds moved
+                    refresh_bounds();
+#pragma unroll
+                    for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                }
             }
         }
     }
     // ---- survivors per query: sum over the 16 lanes that share a row group
+    if (count) {
 #pragma unroll
-    for (int rr = 0; rr < 4; rr++) {
-        int v = e_surv[rr];
+        for (int rr = 0; rr < 4; rr++) {
+            int v = rsurv[rr];
 #pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        const int qi = qbase + g * 4 + rr;
-        if ((lane & 15) == 0 && qi < nqt && v) atomicAdd(&A.nsurv[qslot[qi] / A.m], v);
+            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            const int qi = qbase + g * 4 + rr;
+            if ((lane & 15) == 0 && qi < nqt && v) atomicAdd(&A.nsurv[qslot[qi] / A.m], v);
+        }
     }
     // ---- finalize my queries: best r sorted, partial list, shared bound
     for (int i = 0; i < kLQPW; i++) {
@@ -454,7 +548,6 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
         }
     }
 }
-
 // ------------------------------------------------------------------ merge + rerank
 // One wave per query: collect the approximate candidates of all probes
 // (keeping the best r), rescore them with the exact FP32 arithmetic, keep k.
@@ -515,26 +608,35 @@ __global__ __launch_bounds__(256) void k_merge_rerank(const uint64_t *__restrict
 // ------------------------------------------------------------------ host
 typedef void (*LowpFn)(LowpArgs);
 
-template <int PREC, int METRIC, bool LAB>
+template <int PREC, bool LAB, int NS>
 static LowpFn pick_cb(int r) {
-    if (r <= 48) return k_scan_mfma<PREC, METRIC, LAB, 64>;
-    return k_scan_mfma<PREC, METRIC, LAB, 128>;
+    if (r <= 48) return k_scan_mfma<PREC, LAB, 64, NS>;
+    return k_scan_mfma<PREC, LAB, 128, NS>;
+}
+
+template <int PREC, int NS>
+static LowpFn pick_lab(bool lab, int r) {
+    return lab ? pick_cb<PREC, true, NS>(r) : pick_cb<PREC, false, NS>(r);
 }
 
 template <int PREC>
-static LowpFn pick_ml(int metric, bool lab, int r) {
-    if (metric == 0) return lab ? pick_cb<PREC, 0, true>(r) : pick_cb<PREC, 0, false>(r);
-    return lab ? pick_cb<PREC, 1, true>(r) : pick_cb<PREC, 1, false>(r);
+static LowpFn pick_ns(int ns, bool lab, int r) {
+    switch (ns) {
+        case 1: return pick_lab<PREC, 1>(lab, r);
+        case 2: return pick_lab<PREC, 2>(lab, r);
+        case 4: return pick_lab<PREC, 4>(lab, r);
+        default: return pick_lab<PREC, 8>(lab, r);
+    }
 }
 
-static LowpFn pick_lowp(int prec, int metric, bool lab, int r) {
-    if (prec == CAPS_PREC_BF16) return pick_ml<CAPS_PREC_BF16>(metric, lab, r);
-    if (prec == CAPS_PREC_FP16) return pick_ml<CAPS_PREC_FP16>(metric, lab, r);
-    return pick_ml<CAPS_PREC_FP8>(metric, lab, r);
+static LowpFn pick_lowp(int prec, int ns, bool lab, int r) {
+    if (prec == CAPS_PREC_BF16) return pick_ns<CAPS_PREC_BF16>(ns, lab, r);
+    if (prec == CAPS_PREC_FP16) return pick_ns<CAPS_PREC_FP16>(ns, lab, r);
+    return pick_ns<CAPS_PREC_FP8>(ns, lab, r);
 }
 
 size_t lowp_scan_lds(const Index *ix, int r) {
-    return LowpLds(ix->dpad, esize_of(ix->prec), r <= 48 ? 64 : 128).total + 64;
+    return LowpLds(ix->dpad * esize_of(ix->prec), r <= 48 ? 64 : 128).total + 64;
 }
 
 caps_status lowp_scan(const Index *ix, int32_t nb, const int32_t *tstart, const int32_t *pstart,
@@ -565,16 +667,17 @@ caps_status lowp_scan(const Index *ix, int32_t nb, const int32_t *tstart, const 
     A.pcnt = pcnt;
     A.tau = tau;
     A.nsurv = nsurv;
-    A.dpad = ix->dpad;
     A.m = m;
     A.h = ix->h;
     A.b = ix->b;
     A.r = r;
-    const LowpFn fn = pick_lowp(ix->prec, ix->metric, ix->sch.label_vocab > 0, r);
+    A.metric = ix->metric;
+    const LowpFn fn = pick_lowp(ix->prec, ix->dpad / 32, ix->sch.label_vocab > 0, r);
     const size_t lds = lowp_scan_lds(ix, r);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(CAPS_STAGE_SCAN, st);
-    hipLaunchKernelGGL(fn, dim3((unsigned)max_tiles), dim3(kLNT), lds, st, A);
+    const int32_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kLNT), lds, st, A);
     prof_end(CAPS_STAGE_SCAN, st);
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;

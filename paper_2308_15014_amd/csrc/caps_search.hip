@@ -423,8 +423,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t lvmask_w[NW];
     __shared__ int32_t spo[kMaxHeight + 2];
-    const int tile = blockIdx.x;
-    if (tile >= A.tstart[A.b]) return;
+    const int tile = xcd_tile(blockIdx.x, A.tstart[A.b]);
+    if (tile < 0) return;
     int lo = 0, hi = A.b;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -989,7 +989,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 A.b = b;
                 A.k = k;
                 prof_begin(CAPS_STAGE_SCAN, st);
-                hipLaunchKernelGGL(scan_fn, dim3((unsigned)max_tiles), dim3(scan_waves(k) * 64), lds, st, A);
+                const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
+                hipLaunchKernelGGL(scan_fn, dim3((unsigned)grid), dim3(scan_waves(k) * 64), lds, st, A);
                 prof_end(CAPS_STAGE_SCAN, st);
                 CAPS_HIP(hipGetLastError());
             }

@@ -166,8 +166,7 @@ class Index:
         """Low-precision copy: codes [n, dpad] (uint16 bit patterns or uint8
         FP8 codes), per-vector scales (FP8) and exact |x|^2, CSR order."""
         inf = self.info()
-        n, d, prec = inf["n"], inf["d"], inf["precision"]
-        dpad = (d + 31) // 32 * 32
+        n, prec, dpad = inf["n"], inf["precision"], inf["lowp_dpad"]
         codes = np.zeros((n, dpad), np.uint8 if prec == PREC["fp8"] else np.uint16)
         scale = np.zeros(n, np.float32)
         xnorm = np.zeros(n, np.float32)
