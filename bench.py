@@ -101,8 +101,10 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
     ap.add_argument("--target", type=float, default=0.9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="fp32,bf16",
-                    help="comma list of search modes to time (the JSON needs fp32)")
+    ap.add_argument("--modes", default="fp32,bf16,valu",
+                    help="comma list of search modes to time: fp32 (exact, mode 0), bf16 "
+                         "(approximate + rerank, mode 1), valu (exact, plain FP32 scan only, "
+                         "mode 2); the JSON line needs fp32")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -191,7 +193,7 @@ def main():
         stage_ms = {s_: round(v[0] / args.steps, 4) for s_, v in prof.items()}
         log(f"[{label}] timed: {args.steps} steps, {ms_step:.3f} ms/step, {qps:,.0f} queries/s at nprobe={m} "
             f"recall@10={rec:.4f}; stages ms/step {stage_ms}")
-        if mode == 0:
+        if mode == 2:
             work = 3.0 * w.d * surv_total / launches_per_step
             roof = {"kernel": "k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)",
                     "bound": "alu", "achieved": round(work / scan_avg_s / 1e12, 3),
@@ -199,9 +201,13 @@ def main():
                     "frac": round(work / scan_avg_s / 1e12 / SCAN_PEAK_TFLOPS, 4), "traffic": None,
                     "avg_launch_ms": round(scan_avg_s * 1e3, 4), "algorithmic_flops_per_launch": work}
         else:
+            # both matrix-core modes bound or score every candidate pair with
+            # one BF16 dot product of length d
+            what = ("exact keys: BF16 lower bounds on MFMA, exact FP32 rescoring of the pairs that "
+                    "can enter the top k" if mode == 0 else "approximate keys, per-query top-4k")
             work = 2.0 * w.d * cand_total / launches_per_step
-            roof = {"kernel": "k_scan_mfma<bf16> (query x candidate dot products on MFMA, exact filter "
-                              "epilogue, per-query top-4k)",
+            roof = {"kernel": f"k_scan_mfma<bf16> (query x candidate dot products on MFMA, exact filter "
+                              f"epilogue; {what})",
                     "bound": "mfma", "achieved": round(work / scan_avg_s / 1e12, 3), "peak": MFMA_BF16_PEAK,
                     "unit": "TFLOP/s", "frac": round(work / scan_avg_s / 1e12 / MFMA_BF16_PEAK, 4),
                     "traffic": None, "avg_launch_ms": round(scan_avg_s * 1e3, 4),
@@ -212,6 +218,7 @@ def main():
     modes = args.modes.split(",")
     plain = measure(0, "fp32") if "fp32" in modes else None
     lowp = measure(1, "bf16") if "bf16" in modes else None
+    valu = measure(2, "valu") if "valu" in modes else None
     if plain is None:
         log("fp32 mode not timed: no JSON line")
         return
@@ -253,6 +260,11 @@ def main():
                               "recall@10": plain["recall"], "ms_per_step": round(plain["ms_step"], 4)},
         },
     }
+    if valu is not None:
+        out["modes"]["fp32_plain_scan"] = {
+            "queries_per_s": round(valu["qps"], 1), "nprobe": valu["nprobe"], "recall@10": valu["recall"],
+            "ms_per_step": round(valu["ms_step"], 4), "stage_ms_per_step": valu["stage_ms"],
+            "roofline": valu["roofline"]}
     if lowp is not None:
         out["modes"]["bf16_centroid"] = {
             "queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"], "recall@10": lowp["recall"],

@@ -116,14 +116,23 @@ typedef struct {
                          sub-partitions whose tags prove them empty of valid
                          points); 1: Algorithm 2 read literally (one
                          sub-partition per partition; lossy, for ablation) */
-    int32_t mode;     /* 0: exact FP32 scan.  1: the index's low-precision
-                         copy is scanned with matrix cores (FP32 accumulation),
-                         each query keeps its best `rerank` candidates under the
-                         approximate score (L2: |x|^2 - 2 x.q with the exact FP32
-                         |x|^2; IP: -x.q), and those are rescored with the exact
-                         FP32 arithmetic to give the final top k.  The filter is
-                         exact in both modes; distances returned in mode 1 are
-                         the exact FP32 distances of the returned ids. */
+    int32_t mode;     /* 0: exact: the top k under the FP32 distance of the
+                         plain scan (sequential fma over ascending coordinates).
+                         On an index with a low-precision copy the copy is
+                         scanned with matrix cores to bound each pair's FP32
+                         distance from below (with its stored error norms and
+                         a rounding margin); pairs whose bound cannot beat the
+                         query's current k-th key are skipped and the others
+                         are rescored exactly, so the results equal the plain
+                         scan's.  1: approximate: the copy is scanned with
+                         matrix cores (FP32 accumulation), each query keeps its
+                         best `rerank` candidates under the approximate score
+                         (L2: |x|^2 - 2 x~.q~ with the FP32 |x|^2; IP: -x~.q~),
+                         and those are rescored with the exact FP32 arithmetic
+                         to give the final top k.  2: exact with the plain FP32
+                         scan only.  The filter is exact in every mode; the
+                         distances returned are the exact FP32 distances of the
+                         returned ids. */
     int32_t rerank;   /* mode 1: candidates rescored per query, k <= rerank
                          <= 64; 0 means min(4k, 64) */
     int32_t reserved;

@@ -10,6 +10,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcaps.so")
 
 SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_mfma.hip", "caps_util.hip"]
+# caps_scan_inst.hip once per (precision, key kind): the matrix-core scan
+# instantiations, compiled in parallel (CAPS_PREC_BF16 = 1, FP8 = 2, FP16 = 3)
+INSTANCES = [(f"caps_scan_{name}_{kind}", ["-DCAPS_INST_PREC=%d" % prec, "-DCAPS_INST_EXACT=%d" % ex])
+             for name, prec in (("bf16", 1), ("fp8", 2), ("fp16", 3))
+             for kind, ex in (("approx", 0), ("exact", 1))]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written out
 # explicitly (fmaf); the compiler must not fuse anything else, so that the
@@ -31,15 +36,35 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compiles every source to an object in parallel, then links."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    jobs = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
+    jobs += [("caps_scan_inst.hip", name + ".o", defs) for name, defs in INSTANCES]
+    for src, oname, defs in jobs:
+        obj = os.path.join(objdir, oname)
+        cmd = [hipcc()] + [f for f in FLAGS if f != "-shared"] + defs + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs, failed = [], []
+    for src, obj, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out + err)
+            failed.append(src)
+        objs.append(obj)
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libcaps.so")
+        raise RuntimeError("hipcc failed linking libcaps.so")
     os.replace(tmp, LIB)
     return LIB
 

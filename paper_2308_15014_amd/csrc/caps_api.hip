@@ -35,7 +35,7 @@ static caps_status fail(caps_status s, const char *fmt, ...) {
 
 static void release(Index &ix) {
     void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign, ix.level,
-                    ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm};
+                    ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm, ix.lerr, ix.lnrm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     ix = Index{};
@@ -159,7 +159,7 @@ static caps_status check_search(const caps_index *idx, const caps_search_params 
     if (sp->k > kMaxK) return fail(CAPS_EUNSUPPORTED, "caps_search: k above %d", kMaxK);
     if (sp->nprobe < 1 || sp->nprobe > ix.b) return fail(CAPS_EINVAL, "caps_search: nprobe outside [1, B]");
     if (sp->rule != 0 && sp->rule != 1) return fail(CAPS_EINVAL, "caps_search: rule must be 0 or 1");
-    if (sp->mode != 0 && sp->mode != 1) return fail(CAPS_EINVAL, "caps_search: mode must be 0 or 1");
+    if (sp->mode < 0 || sp->mode > 2) return fail(CAPS_EINVAL, "caps_search: mode must be 0, 1 or 2");
     if (sp->mode == 1) {
         if (ix.prec == CAPS_PREC_NONE)
             return fail(CAPS_EINVAL, "caps_search: mode 1 needs an index built with a precision");

@@ -76,6 +76,8 @@ struct Index {
     void *lvecs = nullptr;      // n x dpad elements (2 bytes BF16/FP16, 1 byte FP8), CSR order
     float *lscale = nullptr;    // n per-vector FP8 scales (FP8 only)
     float *xnorm = nullptr;     // n exact FP32 |x|^2 (sequential fma), CSR order
+    float *lerr = nullptr;      // n upper bounds on |x - x~| (x~: the copy's value), CSR order
+    float *lnrm = nullptr;      // n upper bounds on |x~|, CSR order
     std::vector<int32_t> h_offs;
 };
 
@@ -113,12 +115,23 @@ void prof_end(int stage, hipStream_t st);
 
 // ---- low-precision path (caps_mfma.hip)
 caps_status build_lowp(Index *ix, hipStream_t st);
-size_t lowp_scan_lds(const Index *ix, int r);
-caps_status lowp_scan(const Index *ix, int32_t nb, const int32_t *tstart, const int32_t *pstart,
-                      const int32_t *pcount, const int32_t *entries, const uint32_t *sel, const QDesc *qd,
-                      int32_t m, int32_t r, void *qlow, float *qscale, uint64_t *partials, int32_t *pcnt,
-                      uint64_t *tau, int32_t *nsurv, int32_t max_tiles, bool first_round, const float *q,
-                      hipStream_t st);
+// one launch of the matrix-core scan over a sub-batch of nb queries
+struct LowpScan {
+    int32_t nb, m, r;             // r: keys kept per (query, probe)
+    bool exact;                   // exact keys (mode 0) or approximate ones (mode 1)
+    bool first_round;             // also round the queries (first launch of a sub-batch)
+    int64_t max_tiles;
+    const int32_t *tstart, *pstart, *pcount, *entries;
+    const uint32_t *sel;
+    const QDesc *qd;
+    const float *q;               // nb x d FP32 queries of the sub-batch
+    void *qlow;
+    float *qscale, *qaux;
+    uint64_t *partials, *tau;
+    int32_t *pcnt, *nsurv;
+};
+size_t lowp_scan_lds(const Index *ix, int r, bool exact);
+caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);
 caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
                        int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,
                        int32_t *out_ids, float *out_dist, hipStream_t st);

@@ -1,0 +1,604 @@
+// Matrix-core scan kernel (internal): the tile kernel template shared by
+// the host dispatch in caps_mfma.hip and the per-precision instantiation
+// units (caps_scan_inst.hip, compiled once per precision and key kind).
+#pragma once
+
+#include <math.h>
+
+#include "caps_device.h"
+#include "caps_internal.h"
+
+namespace caps {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ scan
+struct LowpArgs {
+    const int32_t *tstart, *pstart, *pcount, *entries;
+    const uint32_t *sel;
+    const QDesc *qd;
+    const int32_t *offs;
+    const uint8_t *lvecs;       // CSR rows of dpad elements
+    const float *lscale, *xnorm, *lerr, *lnrm;
+    const uint32_t *words;
+    const uint64_t *sigs;
+    const uint16_t *slots;
+    const uint8_t *qlow;        // query rows of dpad elements
+    const float *qscale, *qaux;
+    const float *vecs, *q;      // FP32 CSR rows and queries (exact rescoring)
+    const int32_t *perm;
+    uint64_t *partials;         // per (query, probe): up to r keys
+    int32_t *pcnt;              // approximate: keys written per (query, probe)
+    uint64_t *tau;              // per query: shared bound on its r-th key
+    int32_t *nsurv;             // per query survivor counts, or null (not counted)
+    int32_t m, h, b, r, metric, d;
+    float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
+};
+
+constexpr int kLNW = 4;          // waves per tile
+constexpr int kLQPW = 16;        // queries per wave (MFMA rows)
+constexpr int kLQB = kLNW * kLQPW;
+constexpr int kLCH = 64;         // points per chunk: four 16-column MFMA blocks
+constexpr int kLNT = kLNW * 64;
+constexpr int kTauRefresh = 8;   // chunks between reads of the shared per-query bounds
+constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting rescoring
+
+struct LowpLds {
+    size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, total;
+    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, bool exact)
+        : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), total(0) {
+        size_t o = 0;
+        const auto take = [&o](size_t bytes) {
+            o = (o + 15) & ~(size_t)15;
+            const size_t r = o;
+            o += bytes;
+            return r;
+        };
+        bcnt = take(sizeof(int32_t) * kLQB);
+        tau = take(sizeof(uint64_t) * kLQB);
+        qslot = take(sizeof(int32_t) * kLQB);
+        qd = take(sizeof(QDesc) * kLQB);
+        xw = take(sizeof(uint32_t) * kLCH);
+        xn = take(sizeof(float) * kLCH);
+        xsc = take(sizeof(float) * kLCH);
+        ring = take(exact ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
+        buf = take(sizeof(uint64_t) * (size_t)kLQB * cb);
+        xl = take((size_t)kLCH * (row_bytes + 16));
+        total = take(16);
+    }
+};
+
+template <int PREC>
+struct MfmaOp;
+
+template <>
+struct MfmaOp<CAPS_PREC_BF16> {
+    typedef bf16x8 T;
+    static constexpr int ES = 2;
+    __device__ static T load(const uint8_t *p) { return __builtin_bit_cast(T, *reinterpret_cast<const uint4 *>(p)); }
+    __device__ static f32x4 mma(T a, T b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <>
+struct MfmaOp<CAPS_PREC_FP16> {
+    typedef f16x8 T;
+    static constexpr int ES = 2;
+    __device__ static T load(const uint8_t *p) { return __builtin_bit_cast(T, *reinterpret_cast<const uint4 *>(p)); }
+    __device__ static f32x4 mma(T a, T b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+template <>
+struct MfmaOp<CAPS_PREC_FP8> {
+    typedef long T;
+    static constexpr int ES = 1;
+    __device__ static T load(const uint8_t *p) { return *reinterpret_cast<const long *>(p); }
+    __device__ static f32x4 mma(T a, T b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+};
+
+// Appends the keys of lanes with `qual` set to their queries' buffers (the
+// wave owns those queries; slots come from ballots).  Bounded: every step
+// appends at least one key or shrinks a full buffer to r entries.
+template <int CB>
+__device__ inline void append_keys(bool qual, int qi, uint64_t key, uint64_t *buf, int32_t *bcnt, uint64_t *tau,
+                                   int r) {
+    const int lane = threadIdx.x & 63;
+    for (int guard = 0; guard < 2 * 64 + 2; guard++) {
+        const uint64_t todo = __ballot(qual);
+        if (!todo) break;
+        const int q = __builtin_amdgcn_readlane(qi, __builtin_ctzll(todo));
+        const uint64_t grp = __ballot(qual && qi == q);
+        const int c = bcnt[q];
+        const int room = CB - c;
+        if (room <= 0) {
+            wave_sync();
+            buf_reduce<CB>(buf, bcnt, tau, q, r);
+            if (qual && qi == q) qual = key < tau[q];
+            continue;
+        }
+        uint64_t take = grp;
+        while (__popcll(take) > room) take &= ~(1ull << (63 - __builtin_clzll(take)));
+        if ((take >> lane) & 1ull) {
+            buf[q * CB + c + __popcll(take & lanemask_lt())] = key;
+            qual = false;
+        }
+        wave_sync();
+        if (lane == 0) bcnt[q] = c + __popcll(take);
+        wave_sync();
+    }
+}
+
+// Float image of a bound key: every key below the bound has a score <= it.
+__device__ inline float bound_score(uint64_t t) {
+    return t == ~0ull ? __builtin_huge_valf() : ord2f((uint32_t)(t >> 32));
+}
+
+// Exact FP32 score of one pair: the sequential fma over ascending
+// coordinates of the plain scan (L2: sum (x_j - q_j)^2; IP: -sum x_j q_j).
+__device__ inline float exact_score(const float *__restrict__ xr, const float *__restrict__ qr, int d, bool l2) {
+    float acc = 0.0f;
+    if ((d & 3) == 0) {
+        for (int j = 0; j < d; j += 4) {
+            const float4 xv = *reinterpret_cast<const float4 *>(xr + j);
+            const float4 qv = *reinterpret_cast<const float4 *>(qr + j);
+            if (l2) {
+                float t0 = xv.x - qv.x;
+                acc = fmaf(t0, t0, acc);
+                t0 = xv.y - qv.y;
+                acc = fmaf(t0, t0, acc);
+                t0 = xv.z - qv.z;
+                acc = fmaf(t0, t0, acc);
+                t0 = xv.w - qv.w;
+                acc = fmaf(t0, t0, acc);
+            } else {
+                acc = fmaf(xv.x, qv.x, acc);
+                acc = fmaf(xv.y, qv.y, acc);
+                acc = fmaf(xv.z, qv.z, acc);
+                acc = fmaf(xv.w, qv.w, acc);
+            }
+        }
+    } else {
+        for (int j = 0; j < d; j++) {
+            if (l2) {
+                const float t0 = xr[j] - qr[j];
+                acc = fmaf(t0, t0, acc);
+            } else {
+                acc = fmaf(xr[j], qr[j], acc);
+            }
+        }
+    }
+    return canon0(l2 ? acc : -acc);
+}
+
+// One tile = one partition x up to 64 of the (query, probe) entries that
+// route to it.  Wave w owns queries 16w..16w+15: their A operands sit in
+// registers, their candidate buffers and bounds in LDS.  Chunks of 64 CSR
+// rows of the levels any of the tile's queries selected are staged in LDS
+// (the next chunk's loads are in flight while the current one is scored).
+// Per element the epilogue is branch free: one fused score, a compare against
+// the row's cached float bound (NaN for a row whose query skips the chunk's
+// level or has no query, NaN score for a padding column, so neither ever
+// compares true) and the packed dense-attribute test, reduced by ballots.
+// Label tests and buffer updates run only for elements that pass.
+//
+// EXACT: the per-point term of the score is |x|^2 (IP: 0) lowered by the
+// error norms against the tile's largest query norms and a relative margin,
+// the per-row bound is the query's k-th exact key raised by the margin, so
+// that an element fails only if its exact FP32 key is above the bound.
+// Passing elements queue in a per-wave ring and are rescored exactly, 64 at
+// a time, and enter the buffers with their exact keys (distance, point id).
+template <int PREC, bool HAS_LABELS, int CB, int NS, bool EXACT>
+__global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
+    typedef MfmaOp<PREC> Op;
+    typedef typename Op::T VT;
+    constexpr int ES = Op::ES;
+    constexpr int KSTEP_BYTES = 32 * ES;                 // one MFMA K-step of a row
+    constexpr int LANE_BYTES = 8 * ES;                   // one lane's slice of a K-step
+    constexpr int ROWB = NS * KSTEP_BYTES;               // bytes per CSR row of the copy
+    constexpr int XSTRIDE = ROWB + 16;                   // padded LDS row (bank spread)
+    constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row
+    constexpr int PIECES = kLCH * V16;
+    constexpr int UPT = (PIECES + kLNT - 1) / kLNT;      // pieces per thread per chunk
+    constexpr LowpLds L(ROWB, CB, EXACT);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t spo[kMaxHeight + 2];
+    __shared__ uint32_t lvw[kLNW];
+    __shared__ float qmx[2][kLNW];
+
+    const int tile = xcd_tile(blockIdx.x, A.tstart[A.b]);
+    if (tile < 0) return;
+    int lo = 0, hi = A.b;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (A.tstart[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const int p = lo;
+    const int i0 = (tile - A.tstart[p]) * kLQB;
+    const int nqt = min(kLQB, A.pcount[p] - i0);
+    const int32_t *ent = A.entries + A.pstart[p] + i0;
+    const int h = A.h, r = A.r;
+    uint8_t *xl = smem + L.xl;
+    uint32_t *xw = reinterpret_cast<uint32_t *>(smem + L.xw);
+    float *xn = reinterpret_cast<float *>(smem + L.xn);
+    float *xsc = reinterpret_cast<float *>(smem + L.xsc);
+    uint64_t *buf = reinterpret_cast<uint64_t *>(smem + L.buf);
+    int32_t *bcnt = reinterpret_cast<int32_t *>(smem + L.bcnt);
+    uint64_t *tau = reinterpret_cast<uint64_t *>(smem + L.tau);
+    int32_t *qslot = reinterpret_cast<int32_t *>(smem + L.qslot);
+    QDesc *qds = reinterpret_cast<QDesc *>(smem + L.qd);
+
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int qbase = w * kLQPW;
+    uint32_t *ring_pos = reinterpret_cast<uint32_t *>(smem + L.ring) + w * 2 * kVRing;
+    uint32_t *ring_row = ring_pos + kVRing;
+    const bool has_dense = A.words != nullptr;
+    const bool l2 = A.metric == 0;
+    const bool count = A.nsurv != nullptr;
+    const float qnan = __builtin_nanf("");
+    const float inf = __builtin_huge_valf();
+    const float cm = l2 ? -2.0f : -1.0f;   // score = cm * dot + per-point term
+    if (t <= h + 1) spo[t] = A.offs[(int64_t)p * (h + 1) + t];
+    // per-query state (lane i < 16 of wave w: query qbase + i)
+    uint32_t my_sel = 0;
+    int32_t my_qq = -1;
+    if (lane < kLQPW && qbase + lane < nqt) {
+        const int qi = qbase + lane;
+        const int32_t slot = ent[qi];
+        my_qq = slot / A.m;
+        my_sel = A.sel[slot];
+        qslot[qi] = slot;
+        if (HAS_LABELS) qds[qi] = A.qd[my_qq];
+        tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane < kLQPW) bcnt[qbase + lane] = 0;   // rows without a query too
+    {
+        uint32_t wor = my_sel;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wor |= __shfl_xor(wor, o, 64);
+        if (lane == 0) lvw[w] = wor;
+    }
+    // MFMA A operands: query row qbase + lane%16, K slice (lane/16)*8 of each step
+    VT a[NS];
+    {
+        const int arow = qbase + (lane & 15);
+        const bool aok = arow < nqt;
+        const int64_t qq = aok ? (int64_t)(ent[arow] / A.m) : 0;
+        const uint8_t *src = A.qlow + qq * ROWB + (lane >> 4) * LANE_BYTES;
+#pragma unroll
+        for (int s = 0; s < NS; s++) a[s] = aok ? Op::load(src + s * KSTEP_BYTES) : VT{};
+    }
+    // per-lane epilogue rows: (lane/16)*4 + rr of the wave's 16 queries
+    const int g = lane >> 4;
+    uint32_t rsel[4], rmask[4], rval[4];
+    float rqs[4], rtf[4], rnq[4];
+    int rsurv[4] = {0, 0, 0, 0};
+    float qa = 0.0f, qb = 0.0f;   // exact: largest |q| and |q - q~| + gam |q~| of my rows
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++) {
+        const int qi = qbase + g * 4 + rr;
+        rsel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
+        rnq[rr] = 0.0f;
+        if (qi < nqt) {
+            const int32_t qq = ent[qi] / A.m;
+            const QDesc qd = A.qd[qq];
+            rmask[rr] = qd.dmask;
+            rval[rr] = qd.dval;
+            rqs[rr] = PREC == CAPS_PREC_FP8 ? A.qscale[qq] : 1.0f;
+            if (EXACT) {
+                const float4 ax = *reinterpret_cast<const float4 *>(A.qaux + 4 * (int64_t)qq);
+                rnq[rr] = ax.y;
+                qa = fmaxf(qa, ax.x);
+                qb = fmaxf(qb, fmaf(A.gam, ax.w, ax.z));
+            }
+        } else {
+            rmask[rr] = 0;
+            rval[rr] = 1;   // never matches
+            rqs[rr] = 0.0f;
+        }
+    }
+    if (EXACT) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            qa = fmaxf(qa, __shfl_xor(qa, o, 64));
+            qb = fmaxf(qb, __shfl_xor(qb, o, 64));
+        }
+        if (lane == 0) {
+            qmx[0][w] = qa;
+            qmx[1][w] = qb;
+        }
+    }
+    __syncthreads();
+    if (EXACT) {
+#pragma unroll
+        for (int i = 0; i < kLNW; i++) {
+            qa = fmaxf(qa, qmx[0][i]);
+            qb = fmaxf(qb, qmx[1][i]);
+        }
+    }
+    // Row bound for the element test.  EXACT, L2: an element passes when
+    // pl - 2 x~.q~ <= tauD - |q|^2 + eta (|q|^2 + tauD); IP: pl - x~.q~ <=
+    // tauD + eta (|q|^2 + |tauD|) (pl: the point term of the staging step,
+    // tauD: the score of the query's bound key).
+    auto row_bound = [&](uint64_t tk, float nq) {
+        const float td = bound_score(tk);
+        if (!EXACT) return td;
+        if (!(td < inf)) return inf;
+        return l2 ? fmaf(A.eta, nq + td, td - nq) + 1e-37f : fmaf(A.eta, nq + fabsf(td), td) + 1e-37f;
+    };
+    auto refresh_bounds = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const int qi = qbase + g * 4 + rr;
+            rtf[rr] = qi < nqt ? row_bound(tau[qi], rnq[rr]) : qnan;
+        }
+    };
+    refresh_bounds();
+    uint32_t lv = 0;
+#pragma unroll
+    for (int i = 0; i < kLNW; i++) lv |= lvw[i];
+    lv = __builtin_amdgcn_readfirstlane(lv);
+    // chunk cursor (wave-uniform, kept in scalar registers): level j, first
+    // row c0 of the chunk, end of the level
+    auto po = [&](int i) { return __builtin_amdgcn_readfirstlane(spo[i]); };
+    auto next_level = [&](int &j, int32_t &c0, int32_t &end) {
+        for (j++; j <= h; j++) {
+            if (!((lv >> j) & 1u)) continue;
+            c0 = po(j);
+            end = po(j + 1);
+            if (c0 < end) return;
+        }
+    };
+    auto advance = [&](int &j, int32_t &c0, int32_t &end) {
+        c0 += kLCH;
+        if (c0 >= end) next_level(j, c0, end);
+    };
+
+    // register staging of one chunk: UPT 16-byte pieces per thread, plus the
+    // per-point word / score term / scale held by the first 64 threads.  Rows
+    // past the level's end load the level's last row (in bounds); their
+    // columns are masked by a NaN score term.
+    typedef uint32_t PreT __attribute__((ext_vector_type(4 * UPT)));   // stays in VGPRs
+    PreT pre = {};
+    uint32_t pre_w = 0;
+    float pre_n = qnan, pre_s = 1.0f;
+    auto fetch = [&](int32_t c0, int cn) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.lvecs + (int64_t)c0 * ROWB);
+#pragma unroll
+        for (int u = 0; u < UPT; u++) {
+            const int e = t + u * kLNT;
+            if (PIECES % kLNT == 0 || e < PIECES) {
+                const int row = min(e / V16, cn - 1);
+                const uint4 v = src[row * V16 + e % V16];
+                pre[4 * u + 0] = v.x;
+                pre[4 * u + 1] = v.y;
+                pre[4 * u + 2] = v.z;
+                pre[4 * u + 3] = v.w;
+            }
+        }
+        if (t < kLCH) {
+            const int row = c0 + min(t, cn - 1);
+            float pt;
+            if (EXACT) {
+                // lower-bound term: |x|^2 less twice the error-norm products
+                // and the margin (L2); minus the products and margin (IP)
+                const float nx = A.xnorm[row];
+                // (the product sum rounded in FP32, raised past its rounding)
+                const float slack = fmaf(A.lerr[row], qa, A.lnrm[row] * qb) * (1.0f + 0x1p-20f);
+                pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
+                if (!(fabsf(pt) < inf)) pt = -inf;   // no usable bound: always rescored
+            } else {
+                pt = l2 ? A.xnorm[row] : 0.0f;
+            }
+            pre_w = has_dense ? A.words[row] : 0u;
+            pre_n = t < cn ? pt : qnan;
+            if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
+        }
+    };
+
+    // exact: rescoring of queued pairs, one per lane
+    int vhead = 0, vtail = 0;   // wave-uniform ring cursors
+    auto verify = [&](int n) {
+        wave_sync();   // ring entries written by this wave are visible
+        const bool v = lane < n;
+        const int slot = (vtail + lane) & (kVRing - 1);
+        const uint32_t pos = v ? ring_pos[slot] : 0u;
+        const int qi = v ? (int)ring_row[slot] : qbase;
+        uint64_t key = ~0ull;
+        if (v) {
+            const int32_t qq = qslot[qi] / A.m;
+            const float sc = exact_score(A.vecs + (int64_t)pos * A.d, A.q + (int64_t)qq * A.d, A.d, l2);
+            key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)A.perm[pos];
+        }
+        const bool qual = v && key < tau[qi];
+        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+        vtail += n;
+    };
+
+    int cj = -1;
+    int32_t cc0 = 0, cend = 0;
+    next_level(cj, cc0, cend);
+    if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
+    int nchunk = 0;
+
+    while (cj <= h) {
+        const int j = cj;
+        const int32_t c0 = cc0;
+        const int cn = min(kLCH, cend - c0);
+        __syncthreads();   // previous chunk fully consumed
+#pragma unroll
+        for (int u = 0; u < UPT; u++) {
+            const int e = t + u * kLNT;
+            if (PIECES % kLNT == 0 || e < PIECES)
+                *reinterpret_cast<uint4 *>(xl + (e / V16) * XSTRIDE + (e % V16) * 16) =
+                    make_uint4(pre[4 * u], pre[4 * u + 1], pre[4 * u + 2], pre[4 * u + 3]);
+        }
+        if (t < kLCH) {
+            xw[t] = pre_w;
+            xn[t] = pre_n;
+            xsc[t] = pre_s;
+        }
+        const bool refresh = (++nchunk % kTauRefresh) == 0;
+        if (refresh && lane < kLQPW && my_qq >= 0) {
+            const uint64_t gt = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (gt < tau[qbase + lane]) tau[qbase + lane] = gt;
+        }
+        advance(cj, cc0, cend);
+        if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
+        __syncthreads();
+        if (refresh) refresh_bounds();
+
+        // ---- MFMA: my 16 queries x the chunk's 64 points
+        f32x4 acc[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const uint8_t *xb = xl + (lane & 15) * XSTRIDE + (lane >> 4) * LANE_BYTES;
+#pragma unroll
+        for (int s = 0; s < NS; s++)
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++)
+                acc[bb] = Op::mma(a[s], Op::load(xb + bb * 16 * XSTRIDE + s * KSTEP_BYTES), acc[bb]);
+
+        // ---- epilogue, one 16-point block at a time
+        float tfj[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) {
+            const int pi = bb * 16 + (lane & 15);
+            const uint32_t pw = xw[pi];
+            const float pn = xn[pi];
+            const float ps = xsc[pi];
+            float esc[4];
+            uint64_t hit[4];
+#pragma unroll
+            for (int rr = 0; rr < 4; rr++) {
+                float dd = acc[bb][rr];
+                if (PREC == CAPS_PREC_FP8) dd = dd * ps * rqs[rr];
+                esc[rr] = fmaf(cm, dd, pn);
+                // two single-compare ballots: each is one v_cmp into an SGPR pair
+                hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]) &
+                          __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
+            }
+            if (count) {   // survivors of the exact filter (statistics only)
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) {
+                    bool ok = pi < cn && ((rsel[rr] >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
+                    if (HAS_LABELS && ok) {
+                        const int qi = qbase + g * 4 + rr;
+                        ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                          A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                    }
+                    rsurv[rr] += ok ? 1 : 0;
+                }
+            }
+            if (hit[0] | hit[1] | hit[2] | hit[3]) {
+                bool moved = false;
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) {   // wave-uniform test per row group
+                    if (!hit[rr]) continue;
+                    // lanes 16g..16g+15 hold row 4g+rr: one query per 16-lane group
+                    const int qi = qbase + g * 4 + rr;
+                    bool qual = (hit[rr] >> lane) & 1ull;
+                    if (HAS_LABELS && qual)
+                        qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                            A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                    if (EXACT) {
+                        // queue the pair; rescore once 64 are pending
+                        const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
+                        if (qual) {
+                            const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
+                            ring_pos[sl] = (uint32_t)(c0 + pi);
+                            ring_row[sl] = (uint32_t)qi;
+                        }
+                        vhead += __popcll(qm);
+                        if (vhead - vtail >= 64) {
+                            verify(64);
+                            moved = true;
+                        }
+                        continue;
+                    }
+                    // the score bound admits ties with the current bound key;
+                    // such keys are no better than it and never reach the final r
+                    const uint64_t key = ((uint64_t)f2ord(canon0(esc[rr])) << 32) | (uint32_t)(c0 + pi);
+                    const uint64_t gm = __builtin_amdgcn_ballot_w64(qual) & (0xFFFFull << (16 * g));
+                    const int cnt = __popcll(gm);
+                    const int c = bcnt[qi];
+                    if (__builtin_amdgcn_ballot_w64(c + cnt > CB) == 0) {
+                        // every group's keys fit: direct slots, one count update per group
+                        if (qual) buf[qi * CB + c + __popcll(gm & lanemask_lt())] = key;
+                        if ((lane & 15) == 0 && cnt) bcnt[qi] = c + cnt;
+                        wave_sync();
+                    } else {
+                        wave_sync();
+                        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+                        moved = true;
+                    }
+                }
+                if (moved) {   // bounds may have tightened
+                    refresh_bounds();
+#pragma unroll
+                    for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                }
+            }
+        }
+    }
+    if (EXACT && vhead > vtail) verify(vhead - vtail);
+    // ---- survivors per query: sum over the 16 lanes that share a row group
+    if (count) {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            int v = rsurv[rr];
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            const int qi = qbase + g * 4 + rr;
+            if ((lane & 15) == 0 && qi < nqt && v) atomicAdd(&A.nsurv[qslot[qi] / A.m], v);
+        }
+    }
+    // ---- finalize my queries: best r sorted, partial list, shared bound
+    for (int i = 0; i < kLQPW; i++) {
+        const int qi = qbase + i;
+        if (qi >= nqt) break;
+        buf_reduce<CB>(buf, bcnt, tau, qi, r);
+        const int c = bcnt[qi];
+        const int32_t slot = qslot[qi];
+        uint64_t *out = A.partials + (int64_t)slot * r;
+        if (EXACT) {   // r = k keys per slot, padded (the plain scan's layout)
+            if (lane < r) out[lane] = lane < c ? buf[qi * CB + lane] : ~0ull;
+        } else if (lane < c) {
+            out[lane] = buf[qi * CB + lane];
+        }
+        if (lane == 0) {
+            if (!EXACT) A.pcnt[slot] = c;
+            if (c == r) atomicMin((unsigned long long *)(A.tau + slot / A.m), (unsigned long long)buf[qi * CB + r - 1]);
+        }
+    }
+}
+
+typedef void (*LowpFn)(LowpArgs);
+
+inline int lowp_cb(int r) { return r <= 48 ? 64 : 128; }
+
+template <int PREC, bool LAB, int NS, bool EX>
+LowpFn pick_cb(int r) {
+    if (lowp_cb(r) == 64) return k_scan_mfma<PREC, LAB, 64, NS, EX>;
+    return k_scan_mfma<PREC, LAB, 128, NS, EX>;
+}
+
+template <int PREC, int NS, bool EX>
+LowpFn pick_lab(bool lab, int r) {
+    return lab ? pick_cb<PREC, true, NS, EX>(r) : pick_cb<PREC, false, NS, EX>(r);
+}
+
+// the kernel for one precision and key kind (defined by caps_scan_inst.hip)
+template <int PREC, bool EX>
+LowpFn pick_ns(int ns, bool lab, int r);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, false>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, true>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, false>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, true>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, false>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, true>(int, bool, int);
+
+}  // namespace caps

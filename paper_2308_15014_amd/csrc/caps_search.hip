@@ -810,7 +810,7 @@ int lowp_qb();
 
 struct SearchWs {
     uint8_t *qlow;
-    float *qscale;
+    float *qscale, *qaux;
     int32_t *pcnt;
     int32_t *ncand, *nsurv;
     QDesc *qd;
@@ -827,6 +827,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
     w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
     w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
+    w.qaux = qlow_row_bytes ? ar.take<float>((size_t)sb * 4) : nullptr;
     w.pcnt = qlow_row_bytes ? ar.take<int32_t>((size_t)sb * m) : nullptr;
     w.ncand = own_ncand ? ar.take<int32_t>(nq) : nullptr;
     w.nsurv = own_nsurv ? ar.take<int32_t>(nq) : nullptr;
@@ -851,7 +852,12 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand,
                    int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st) {
     const int32_t b = ix->b, d = ix->d, h = ix->h, m = sp->nprobe, k = sp->k;
+    // mode 1: approximate keys on the matrix cores, rescored at the merge;
+    // mode 0 on an index with a low-precision copy: the matrix-core scan
+    // with exact keys (bounds prune, survivors are rescored exactly);
+    // otherwise (or mode 2) the plain FP32 scan
     const bool lowp = sp->mode == 1;
+    const bool mfma = lowp || (sp->mode == 0 && ix->prec != CAPS_PREC_NONE);
     const int32_t r = lowp ? (sp->rerank > 0 ? sp->rerank : std::min(4 * k, kMaxK)) : k;
     if (nq == 0) return CAPS_OK;
     const bool probes_only = out_probes != nullptr;
@@ -859,10 +865,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     while (pb < b) pb <<= 1;
 
     // sub-batch so that the per-batch workspace stays bounded (~1 GiB)
-    const size_t qlow_row = lowp ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
+    const size_t qlow_row = mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
     const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
                          sizeof(uint64_t) * (size_t)m * r + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 64;
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 5 * sizeof(float) + 64;
     const size_t budget = (size_t)1 << 30;
     const int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
     SearchWs W;
@@ -893,10 +899,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
 
     const bool has_labels = ix->sch.label_vocab > 0;
-    const size_t lds = lowp ? lowp_scan_lds(ix, r) : scan_lds_bytes(d, k);
-    const int qb = lowp ? lowp_qb() : scan_waves(k) * kQPW;
+    const size_t lds = mfma ? lowp_scan_lds(ix, r, !lowp) : scan_lds_bytes(d, k);
+    const int qb = mfma ? lowp_qb() : scan_waves(k) * kQPW;
     const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0 && d <= 256, k);
-    if (!probes_only && !lowp) {
+    if (!probes_only && !mfma) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
         if (lds > (size_t)lds_max) {
@@ -960,10 +966,29 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             CAPS_HIP(hipGetLastError());
             prof_end(CAPS_STAGE_SELECT, st);
             const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
-            if (lowp) {
-                const caps_status ls =
-                    lowp_scan(ix, nb, tstart, pstart, pcount, entries, sel, qd, m, r, W.qlow, W.qscale, partials,
-                              W.pcnt, tau, nsurv + q0, (int32_t)max_tiles, round == 0, q + (int64_t)q0 * d, st);
+            if (mfma) {
+                LowpScan S{};
+                S.nb = nb;
+                S.m = m;
+                S.r = r;
+                S.exact = !lowp;
+                S.first_round = round == 0;
+                S.max_tiles = max_tiles;
+                S.tstart = tstart;
+                S.pstart = pstart;
+                S.pcount = pcount;
+                S.entries = entries;
+                S.sel = sel;
+                S.qd = qd;
+                S.q = q + (int64_t)q0 * d;
+                S.qlow = W.qlow;
+                S.qscale = W.qscale;
+                S.qaux = W.qaux;
+                S.partials = partials;
+                S.tau = tau;
+                S.pcnt = W.pcnt;
+                S.nsurv = out_nsurv ? nsurv + q0 : nullptr;   // counted only when asked for
+                const caps_status ls = lowp_scan(ix, S, st);
                 if (ls != CAPS_OK) return ls;
             } else {
                 ScanArgs A;
