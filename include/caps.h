@@ -135,7 +135,13 @@ typedef struct {
                          returned ids. */
     int32_t rerank;   /* mode 1: candidates rescored per query, k <= rerank
                          <= 64; 0 means min(4k, 64) */
-    int32_t reserved;
+    int32_t routing;  /* 0: centroid routing (Algorithm 2).  1: the index's
+                         learned router (caps_router_train): probes = the m
+                         largest logits, ties to the smaller partition, with a
+                         per-query fallback to centroid routing when the
+                         router's softmax top-1 probability is below its
+                         fallback level or its probes hold fewer than k
+                         candidates.  EINVAL without a router. */
 } caps_search_params;
 
 /*
@@ -230,6 +236,86 @@ caps_status caps_profile_read(caps_profile_t *out); /* synchronises the events *
  * each CSR row, sequential fma).  EINVAL if the index has no such copy.
  */
 caps_status caps_index_export_lowp(const caps_index *idx, void *codes, float *scale, float *xnorm);
+
+/*
+ * Learned router (a two-layer perceptron on the query and its constraints;
+ * the filtered-label training of the paper's CAPS-BLISS variant, Section
+ * 5.2, with the k-means partitions kept fixed):
+ *   x = [q * in_scale + in_shift || e(C) || 0]  (BF16; width dpad = d + 64
+ *       rounded up to 32; e(C) = 64-wide multi-hot: each valid constraint
+ *       pair's token -- dense attribute i, value v: off_i + v; label l:
+ *       off_L + l -- sets position mix64(token) mod 64, mix64 being
+ *       splitmix64's output function)
+ *   h = relu(W1 x + b1)  (W1: hidden x dpad, rounded to BF16 after the product)
+ *   z = W2 h + b2        (W2: B x hidden; FP32 logits, one per partition)
+ * Products use BF16 operands with FP32 accumulation; masters are FP32.
+ * Training: Adam on the mean over rows of -(1/|S|) sum_{s in S} log softmax(z)_s,
+ * S = a row's distinct labels (partition ids; entries < 0 are padding, a
+ * row without labels contributes nothing).  The router lives in the index
+ * and is released with it.
+ */
+typedef struct {
+    int32_t hidden;        /* hidden width, a multiple of 16 in [16, 8192] */
+    int32_t epochs;        /* passes over the training rows */
+    int32_t batch;         /* rows per Adam step, 1..65536 */
+    int32_t reset;         /* 1: fresh weights from `seed`; 0: continue the index's router */
+    float lr, beta1, beta2, eps;   /* Adam (bias-corrected) */
+    float in_scale, in_shift;      /* input map of the query vector */
+    float fallback_prob;   /* search falls back to centroid routing below this
+                              softmax top-1 probability (0: never; > 1: always) */
+    int32_t reserved;
+    uint64_t seed;         /* weight init (W ~ U(+-1/sqrt(fan_in)), b = 0) and row shuffling */
+} caps_router_params;
+
+typedef struct {
+    int32_t present;       /* 0 if the index has no router */
+    int32_t din, dpad, hidden, n_out;
+    float in_scale, in_shift, fallback_prob;
+    int64_t steps;         /* Adam steps taken */
+} caps_router_info_t;
+
+/* Labels for training: per query the distinct partitions of its k ids (in
+ * order of first appearance, ids < 0 skipped), -1 padded.  ids and
+ * out_parts are DEVICE n x k int32 on the index's device; enqueued on
+ * `stream`. */
+caps_status caps_router_labels(const caps_index *idx, const int32_t *ids, int32_t n, int32_t k,
+                               int32_t *out_parts, void *stream);
+
+/* Trains the index's router on n DEVICE rows (q n x d float32, constraint
+ * CSR as in caps_search, labels n x n_labels int32).  out_loss: optional
+ * HOST array of `epochs` floats, the mean loss of each epoch.  Synchronises
+ * `stream` before returning.  Errors: EINVAL (arguments), ENOMEM, EDEVICE. */
+caps_status caps_router_train(caps_index *idx, const caps_router_params *p, const float *q, int32_t n,
+                              const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                              int32_t n_con, const int32_t *labels, int32_t n_labels, float *out_loss,
+                              void *stream);
+
+/* Sets the router from HOST FP32 weights (w1 hidden x dpad, b1 hidden, w2
+ * B x hidden, b2 B), or, with all four NULL, from fresh weights drawn from
+ * p->seed; Adam state is cleared.  Only hidden, in_scale, in_shift,
+ * fallback_prob and seed of p are used.  Synchronous. */
+caps_status caps_router_set(caps_index *idx, const caps_router_params *p, const float *w1, const float *b1,
+                            const float *w2, const float *b2);
+
+/* Copies the FP32 master weights to HOST arrays (any may be NULL).
+ * EINVAL without a router.  Synchronous. */
+caps_status caps_router_get(const caps_index *idx, float *w1, float *b1, float *w2, float *b2);
+
+caps_status caps_router_info(const caps_index *idx, caps_router_info_t *out);
+
+/* Router logits (DEVICE n x B float32) of n DEVICE query rows, enqueued on
+ * `stream`.  EINVAL without a router. */
+caps_status caps_router_logits(const caps_index *idx, const float *q, int32_t n, const int32_t *con_off,
+                               const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
+                               float *out_logits, void *stream);
+
+/* Mean loss and parameter gradients of one batch of n DEVICE rows (no
+ * update); gradients to HOST arrays laid out like the weights (any may be
+ * NULL).  Synchronises `stream`. */
+caps_status caps_router_grads(caps_index *idx, const float *q, int32_t n, const int32_t *con_off,
+                              const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
+                              const int32_t *labels, int32_t n_labels, float *out_loss, float *g_w1,
+                              float *g_b1, float *g_w2, float *g_b2, void *stream);
 
 /* Release the index and its device memory (NULL is a no-op). */
 void caps_free(caps_index *idx);

@@ -34,7 +34,20 @@ class BuildParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("mode", c_i32),
-                ("rerank", c_i32), ("reserved", c_i32)]
+                ("rerank", c_i32), ("routing", c_i32)]
+
+
+class RouterParams(ctypes.Structure):
+    _fields_ = [("hidden", c_i32), ("epochs", c_i32), ("batch", c_i32), ("reset", c_i32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("in_scale", ctypes.c_float), ("in_shift", ctypes.c_float),
+                ("fallback_prob", ctypes.c_float), ("reserved", c_i32), ("seed", c_u64)]
+
+
+class RouterInfo(ctypes.Structure):
+    _fields_ = [("present", c_i32), ("din", c_i32), ("dpad", c_i32), ("hidden", c_i32),
+                ("n_out", c_i32), ("in_scale", ctypes.c_float), ("in_shift", ctypes.c_float),
+                ("fallback_prob", ctypes.c_float), ("steps", c_i64)]
 
 
 PREC = {"none": 0, "fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
@@ -64,6 +77,15 @@ SIGNATURES = {
     "caps_index_info": (c_i32, [c_vp, ctypes.POINTER(IndexInfo)]),
     "caps_index_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_index_export_lowp": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "caps_router_labels": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp]),
+    "caps_router_train": (c_i32, [c_vp, ctypes.POINTER(RouterParams), c_vp, c_i32, c_vp, c_vp, c_vp,
+                                  c_i32, c_vp, c_i32, c_vp, c_vp]),
+    "caps_router_set": (c_i32, [c_vp, ctypes.POINTER(RouterParams), c_vp, c_vp, c_vp, c_vp]),
+    "caps_router_get": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_router_info": (c_i32, [c_vp, ctypes.POINTER(RouterInfo)]),
+    "caps_router_logits": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "caps_router_grads": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp,
+                                  c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_free": (None, [c_vp]),
     "caps_profile_enable": (c_i32, [c_i32]),
     "caps_profile_read": (c_i32, [ctypes.POINTER(Profile)]),

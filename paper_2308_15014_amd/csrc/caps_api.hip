@@ -10,10 +10,6 @@
 
 #include "caps_internal.h"
 
-struct caps_index {
-    caps::Index ix;
-};
-
 namespace caps {
 
 static thread_local char g_err[512];
@@ -38,6 +34,7 @@ static void release(Index &ix) {
                     ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm, ix.lerr, ix.lnrm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    router_free(ix.router);
     ix = Index{};
 }
 
@@ -166,6 +163,8 @@ static caps_status check_search(const caps_index *idx, const caps_search_params 
         if (sp->rerank != 0 && (sp->rerank < sp->k || sp->rerank > kMaxK))
             return fail(CAPS_EINVAL, "caps_search: rerank must be in [k, %d]", kMaxK);
     }
+    if (sp->routing != 0 && sp->routing != 1) return fail(CAPS_EINVAL, "caps_search: routing must be 0 or 1");
+    if (sp->routing == 1 && !ix.router) return fail(CAPS_EINVAL, "caps_search: routing 1 needs a trained router");
     if (n_con < 0) return fail(CAPS_EINVAL, "caps_search: n_con < 0");
     if (n_q > 0 && (!q || !con_off)) return fail(CAPS_EINVAL, "caps_search: null query arrays");
     if (n_con > 0 && (!con_attr || !con_val)) return fail(CAPS_EINVAL, "caps_search: null constraint arrays");

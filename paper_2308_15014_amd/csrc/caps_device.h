@@ -10,6 +10,16 @@ namespace caps {
 
 constexpr int kWave = 64;
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ inline uint16_t bf16_rne(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // Workgroups of a launch are dealt to the 8 XCDs of the chip round-robin
 // (workgroup i runs on XCD i % 8), each XCD with its own L2.  Maps a launch
 // index to a tile so that every XCD receives one contiguous range of the

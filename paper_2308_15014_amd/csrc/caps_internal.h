@@ -79,7 +79,21 @@ struct Index {
     float *lerr = nullptr;      // n upper bounds on |x - x~| (x~: the copy's value), CSR order
     float *lnrm = nullptr;      // n upper bounds on |x~|, CSR order
     std::vector<int32_t> h_offs;
+    struct Router *router = nullptr;   // learned router (owned), if trained or set
 };
+
+// Learned router state (caps_router.hip): a two-layer perceptron on
+// [q * in_scale + in_shift || 64-wide hashed constraint tokens].
+struct Router {
+    int32_t din = 0, dpad = 0, hid = 0, nout = 0;   // d + 64, padded to 32, hidden width, B
+    float in_scale = 1.0f, in_shift = 0.0f, fb_prob = 0.0f;
+    int64_t step = 0;                               // Adam steps taken
+    int64_t nparam = 0;                             // w1 (hid x dpad), b1, w2 (nout x hid), b2
+    int64_t o_b1 = 0, o_w2 = 0, o_b2 = 0;           // offsets into the parameter arrays
+    float *param = nullptr, *mom = nullptr, *vel = nullptr;   // FP32 masters and Adam moments
+    uint16_t *w1h = nullptr, *w2h = nullptr;                   // BF16 copies for the products
+};
+void router_free(Router *r);
 
 // signature bit (0..63) of a label: Fibonacci hashing of the label id
 __host__ __device__ inline uint32_t label_sig_bit(uint32_t l) {
@@ -140,4 +154,21 @@ caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32
 caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
                                hipStream_t st);
 
+// ---- learned routing inside a search (caps_router.hip): fills `scores`
+// (nb x B, smaller is better) from the router's logits and `conf` with the
+// softmax top-1 probability of each query; X and H are workspace of
+// nb x dpad and nb x hid BF16 elements.
+caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int32_t *con_off,
+                          const int32_t *con_attr, const int32_t *con_val, int32_t n_con, uint16_t *X,
+                          uint16_t *H, float *scores, float *conf, hipStream_t st);
+// per query: keep the router's probes unless its top-1 probability is below
+// the fallback level or its probes hold fewer than k candidates, else copy
+// the centroid probes
+caps_status router_fallback(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
+                            const int32_t *cand, const int32_t *probes_c, int32_t *probes, hipStream_t st);
+
 }  // namespace caps
+
+struct caps_index {
+    caps::Index ix;
+};

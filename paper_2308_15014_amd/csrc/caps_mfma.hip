@@ -30,12 +30,6 @@
 namespace caps {
 
 // ------------------------------------------------------------------ rounding
-__device__ inline uint16_t bf16_rne(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 __device__ inline uint16_t f16_rne_sat(float f) {
     f = fminf(fmaxf(f, -65504.0f), 65504.0f);
     return __builtin_bit_cast(uint16_t, (_Float16)f);

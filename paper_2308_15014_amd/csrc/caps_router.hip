@@ -1,0 +1,784 @@
+// Learned router: a two-layer perceptron that maps a query vector and its
+// constraints to one logit per partition, trained on the GPU on the
+// partitions that hold each query's exact filtered top-k (the filtered-label
+// idea of the paper's CAPS-BLISS variant, Section 5.2, with the k-means
+// partitions kept fixed).
+//
+//   x = [q * in_scale + in_shift || e(C) || 0]   (BF16, dpad = (d + 64) rounded up to 32)
+//   h = relu(W1 x + b1)                           (BF16 after the product)
+//   z = W2 h + b2                                 (FP32 logits, one per partition)
+//
+// e(C) is 64-wide multi-hot: every valid constraint pair's token (dense
+// attribute i, value v: off_i + v; label l: off_L + l) sets position
+// mix64(token) mod 64, mix64 being splitmix64's output function.
+//
+// Products run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) in one strided GEMM kernel; the softmax cross-entropy, bias
+// gradients and Adam (FP32 masters, BF16 copies) are plain kernels.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "caps_device.h"
+#include "caps_internal.h"
+
+namespace caps {
+
+constexpr int kEmbed = 64;
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------------ input rows (K14)
+// One workgroup per query: the affine map of the vector (product, then sum,
+// in FP32), BF16-rounded, then the hashed constraint tokens.
+__global__ __launch_bounds__(64) void k_router_input(const float *__restrict__ q, int32_t nq, int32_t d,
+                                                     const int32_t *__restrict__ con_off,
+                                                     const int32_t *__restrict__ con_attr,
+                                                     const int32_t *__restrict__ con_val, int32_t n_con, Schema sch,
+                                                     float scale, float shift, int32_t dpad,
+                                                     uint16_t *__restrict__ X) {
+    const int64_t i = blockIdx.x;
+    if (i >= nq) return;
+    uint16_t *row = X + i * dpad;
+    for (int j = threadIdx.x; j < dpad; j += 64) {
+        uint16_t v = 0;
+        if (j < d) {
+            const float a = q[i * d + j] * scale;
+            v = bf16_rne(a + shift);
+        }
+        row[j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t lo = con_off[i], hi = con_off[i + 1];
+        if (lo >= 0 && hi >= lo && hi <= n_con) {
+            for (int32_t e = lo; e < hi; e++) {
+                const int32_t a = con_attr[e], v = con_val[e];
+                int64_t tok = -1;
+                if (a >= 0 && a < sch.n_dense && v >= 0 && v < sch.dense_vocab[a])
+                    tok = sch.dense_off[a] + v;
+                else if (a == sch.n_dense && sch.label_vocab > 0 && v >= 0 && v < sch.label_vocab)
+                    tok = sch.dense_off[sch.n_dense] + v;
+                if (tok >= 0) row[d + (int)(mix64((uint64_t)tok) % kEmbed)] = 0x3F80;   // BF16 1.0
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ GEMM (K11, K12)
+// C[m][n] = sum_k A(m, k) B(n, k), A(m, k) = A[m*sam + k*sak], B(n, k) =
+// B[n*sbn + k*sbk] (BF16), FP32 accumulation.  64 x 64 tile per workgroup,
+// four waves of 32 x 32 (2 x 2 MFMA blocks), K in steps of 32 through LDS.
+// Epilogue: + bias[n], ReLU, zero where mask(m, n) <= 0 (a BF16 array with
+// leading dimension ldm), negation (scores, smaller is better); written as
+// FP32 and/or BF16 with leading dimension ldc.
+enum { kGemmRelu = 1, kGemmMask = 2, kGemmNeg = 4 };
+constexpr int kGT = 64, kGK = 32, kGKP = kGK + 8;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t sam, int64_t sak,
+                                                   const uint16_t *__restrict__ B, int64_t sbn, int64_t sbk,
+                                                   int32_t M, int32_t N, int32_t K, const float *__restrict__ bias,
+                                                   int32_t flags, const uint16_t *__restrict__ mask, int64_t ldm,
+                                                   float *__restrict__ C32, uint16_t *__restrict__ C16,
+                                                   int64_t ldc) {
+    __shared__ __align__(16) uint16_t As[kGT][kGKP];
+    __shared__ __align__(16) uint16_t Bs[kGT][kGKP];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // one operand tile: rows r0.., k0..; the fast thread index walks the
+    // unit-stride dimension so that the loads coalesce
+    auto load_tile = [&](uint16_t (*S)[kGKP], const uint16_t *P, int64_t srow, int64_t sk, int64_t r0, int32_t R,
+                         int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < kGT * kGK / 256; u++) {
+            const int e = t + u * 256;
+            int r, kk;
+            if (sk == 1) {
+                r = e / kGK;
+                kk = e % kGK;
+            } else {
+                r = e % kGT;
+                kk = e / kGT;
+            }
+            uint16_t v = 0;
+            if (r0 + r < R && k0 + kk < K) v = P[(r0 + r) * srow + (k0 + kk) * sk];
+            S[r][kk] = v;
+        }
+    };
+    for (int64_t k0 = 0; k0 < K; k0 += kGK) {
+        load_tile(As, A, sam, sak, m0, M, k0);
+        load_tile(Bs, B, sbn, sbk, n0, N, k0);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const bf16x8 a = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]));
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const bf16x8 b = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]));
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D row (lane/16)*4 + r, column lane%16 of each 16 x 16 block
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t mm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int64_t nn = n0 + wn + j * 16 + (lane & 15);
+                if (mm >= M || nn >= N) continue;
+                float v = acc[i][j][r];
+                if (bias) v = v + bias[nn];
+                if (flags & kGemmRelu) v = fmaxf(v, 0.0f);
+                if ((flags & kGemmMask) && !(__builtin_bit_cast(float, (uint32_t)mask[mm * ldm + nn] << 16) > 0.0f))
+                    v = 0.0f;
+                if (flags & kGemmNeg) v = canon0(-v);
+                if (C32) C32[mm * ldc + nn] = v;
+                if (C16) C16[mm * ldc + nn] = bf16_rne(v);
+            }
+}
+
+static caps_status gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbn, int64_t sbk,
+                        int32_t M, int32_t N, int32_t K, const float *bias, int32_t flags, const uint16_t *mask,
+                        int64_t ldm, float *C32, uint16_t *C16, int64_t ldc, hipStream_t st) {
+    if (M <= 0 || N <= 0) return CAPS_OK;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT)),
+                       dim3(256), 0, st, A, sam, sak, B, sbn, sbk, M, N, K, bias, flags, mask, ldm, C32, C16, ldc);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+// ------------------------------------------------------------------ loss (K12)
+// One workgroup per row: softmax of the logits, loss -(1/|S|) sum_{s in S}
+// log p_s over the row's distinct labels S (entries < 0 are padding), and
+// the logit gradient (p - y) / M with y uniform on S (both 0 when S is
+// empty), as FP32 and BF16.
+__global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, int32_t M, int32_t nout,
+                                                    const int32_t *__restrict__ labels, int32_t L,
+                                                    float *__restrict__ loss_rows, float *__restrict__ dZ32,
+                                                    uint16_t *__restrict__ dZ16) {
+    __shared__ float red[256];
+    __shared__ int32_t lab[64];
+    __shared__ int32_t nlab;
+    const int64_t i = blockIdx.x;
+    const float *z = Z + i * nout;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int n = 0;
+        for (int e = 0; e < L && n < 64; e++) {
+            const int32_t v = labels[i * L + e];
+            if (v < 0 || v >= nout) continue;
+            bool dup = false;
+            for (int f = 0; f < n; f++) dup |= lab[f] == v;
+            if (!dup) lab[n++] = v;
+        }
+        nlab = n;
+    }
+    float mx = -__builtin_huge_valf();
+    for (int j = t; j < nout; j += 256) mx = fmaxf(mx, z[j]);
+    red[t] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] = fmaxf(red[t], red[t + o]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    float s = 0.0f;
+    for (int j = t; j < nout; j += 256) s += expf(z[j] - mx);
+    red[t] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const float sum = red[0];
+    const int n = nlab;
+    const float inv = n ? 1.0f / (float)n : 0.0f;
+    for (int j = t; j < nout; j += 256) {
+        float y = 0.0f;
+        for (int f = 0; f < n; f++) y += lab[f] == j ? inv : 0.0f;
+        const float g = n ? (expf(z[j] - mx) / sum - y) / (float)M : 0.0f;
+        dZ32[i * nout + j] = g;
+        dZ16[i * nout + j] = bf16_rne(g);
+    }
+    if (t == 0) {
+        float l = 0.0f;
+        if (n) {
+            const float lse = logf(sum) + mx;
+            for (int f = 0; f < n; f++) l += lse - z[lab[f]];
+            l *= inv;
+        }
+        loss_rows[i] = l;
+    }
+}
+
+// Column sums of an M x N FP32 matrix, rows in ascending order.
+__global__ void k_colsum(const float *__restrict__ X, int32_t M, int32_t N, float *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.0f;
+    for (int64_t i = 0; i < M; i++) s += X[i * N + j];
+    out[j] = s;
+}
+
+// Adds the mean of M values to *acc (single workgroup).
+__global__ __launch_bounds__(256) void k_accum_mean(const float *__restrict__ v, int32_t M, float *__restrict__ acc) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < M; i += 256) s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *acc += red[0];
+}
+
+// ------------------------------------------------------------------ Adam (K13)
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = bf16_rne(x[i]);
+}
+
+// Rows perm[0..nb) of X (dpad BF16) and of the labels (L int32).
+__global__ void k_gather_batch(const uint16_t *__restrict__ X, const int32_t *__restrict__ labels,
+                               const int32_t *__restrict__ perm, int32_t nb, int32_t dpad, int32_t L,
+                               uint16_t *__restrict__ Xb, int32_t *__restrict__ Lb) {
+    const int64_t i = blockIdx.x;
+    if (i >= nb) return;
+    const int64_t src = perm[i];
+    for (int j = threadIdx.x; j < dpad; j += blockDim.x) Xb[i * dpad + j] = X[src * dpad + j];
+    for (int j = threadIdx.x; j < L; j += blockDim.x) Lb[i * L + j] = labels[src * L + j];
+}
+
+// ------------------------------------------------------------------ labels
+// Distinct partitions of each query's ids (in order of first appearance),
+// -1 padded; ids < 0 are skipped.
+__global__ void k_router_labels(const int32_t *__restrict__ ids, int32_t n, int32_t k,
+                                const int32_t *__restrict__ assign, int64_t npts, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int j = 0; j < k; j++) {
+        const int32_t id = ids[i * k + j];
+        if (id < 0 || id >= npts) continue;
+        const int32_t p = assign[id];
+        bool dup = false;
+        for (int f = 0; f < c; f++) dup |= out[i * k + f] == p;
+        if (!dup) out[i * k + c++] = p;
+    }
+    for (int j = c; j < k; j++) out[i * k + j] = -1;
+}
+
+// ------------------------------------------------------------------ inference
+// Softmax top-1 probability per row of negated logits (smaller is better).
+__global__ __launch_bounds__(64) void k_router_conf(const float *__restrict__ S, int32_t nb, int32_t nout,
+                                                    float *__restrict__ conf) {
+    const int64_t i = blockIdx.x;
+    if (i >= nb) return;
+    const float *s = S + i * nout;
+    float mn = __builtin_huge_valf();
+    for (int j = threadIdx.x; j < nout; j += 64) mn = fminf(mn, s[j]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
+    float sum = 0.0f;
+    for (int j = threadIdx.x; j < nout; j += 64) sum += expf(mn - s[j]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (threadIdx.x == 0) conf[i] = 1.0f / sum;
+}
+
+__global__ void k_router_fallback(int32_t nb, int32_t m, int32_t k, float fb_prob, const float *__restrict__ conf,
+                                  const int32_t *__restrict__ cand, const int32_t *__restrict__ probes_c,
+                                  int32_t *__restrict__ probes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int64_t c = 0;
+    for (int j = 0; j < m; j++) c += cand[i * m + j];
+    if (conf[i] < fb_prob || c < k)
+        for (int j = 0; j < m; j++) probes[i * m + j] = probes_c[i * m + j];
+}
+
+static int64_t nblk(int64_t n, int t) { return (n + t - 1) / t; }
+
+caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int32_t *con_off,
+                          const int32_t *con_attr, const int32_t *con_val, int32_t n_con, uint16_t *X,
+                          uint16_t *H, float *scores, float *conf, hipStream_t st) {
+    const Router &R = *ix->router;
+    hipLaunchKernelGGL(k_router_input, dim3((unsigned)nb), dim3(64), 0, st, q, nb, ix->d, con_off, con_attr,
+                       con_val, n_con, ix->sch, R.in_scale, R.in_shift, R.dpad, X);
+    CAPS_HIP(hipGetLastError());
+    caps_status s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, nb, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr,
+                         0, nullptr, H, R.hid, st);
+    if (s != CAPS_OK) return s;
+    s = gemm(H, R.hid, 1, R.w2h, R.hid, 1, nb, R.nout, R.hid, R.param + R.o_b2, kGemmNeg, nullptr, 0, scores,
+             nullptr, R.nout, st);
+    if (s != CAPS_OK) return s;
+    hipLaunchKernelGGL(k_router_conf, dim3((unsigned)nb), dim3(64), 0, st, scores, nb, R.nout, conf);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+caps_status router_fallback(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
+                            const int32_t *cand, const int32_t *probes_c, int32_t *probes, hipStream_t st) {
+    hipLaunchKernelGGL(k_router_fallback, dim3((unsigned)nblk(nb, 256)), dim3(256), 0, st, nb, m, k,
+                       ix->router->fb_prob, conf, cand, probes_c, probes);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+void router_free(Router *r) {
+    if (!r) return;
+    void *ptrs[] = {r->param, r->mom, r->vel, r->w1h, r->w2h};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete r;
+}
+
+// ------------------------------------------------------------------ host helpers
+static uint64_t sm64_next(uint64_t &s) {
+    s += 0x9E3779B97F4A7C15ull;
+    return mix64(s);
+}
+
+// Allocates a router for the index with zeroed moments; w1/b1/w2/b2 from
+// host arrays, or (when null) W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) drawn
+// from splitmix64(seed) and zero biases.
+static caps_status router_alloc(Index *ix, int32_t hid, float in_scale, float in_shift, float fb_prob, uint64_t seed,
+                                const float *w1, const float *b1, const float *w2, const float *b2) {
+    Router *R = new Router;
+    R->din = ix->d + kEmbed;
+    R->dpad = (R->din + 31) / 32 * 32;
+    R->hid = hid;
+    R->nout = ix->b;
+    R->in_scale = in_scale;
+    R->in_shift = in_shift;
+    R->fb_prob = fb_prob;
+    R->o_b1 = (int64_t)hid * R->dpad;
+    R->o_w2 = R->o_b1 + hid;
+    R->o_b2 = R->o_w2 + (int64_t)R->nout * hid;
+    R->nparam = R->o_b2 + R->nout;
+    std::vector<float> h((size_t)R->nparam, 0.0f);
+    if (w1) {
+        memcpy(h.data(), w1, sizeof(float) * (size_t)R->o_b1);
+        memcpy(h.data() + R->o_b1, b1, sizeof(float) * (size_t)hid);
+        memcpy(h.data() + R->o_w2, w2, sizeof(float) * (size_t)R->nout * hid);
+        memcpy(h.data() + R->o_b2, b2, sizeof(float) * (size_t)R->nout);
+    } else {
+        uint64_t s = seed;
+        const double a1 = 1.0 / sqrt((double)R->din), a2 = 1.0 / sqrt((double)hid);
+        for (int64_t r = 0; r < hid; r++)
+            for (int64_t c = 0; c < R->dpad; c++) {
+                const double u = (double)(sm64_next(s) >> 11) * 0x1p-53;
+                h[(size_t)(r * R->dpad + c)] = c < R->din ? (float)((2.0 * u - 1.0) * a1) : 0.0f;
+            }
+        for (int64_t e = 0; e < (int64_t)R->nout * hid; e++) {
+            const double u = (double)(sm64_next(s) >> 11) * 0x1p-53;
+            h[(size_t)(R->o_w2 + e)] = (float)((2.0 * u - 1.0) * a2);
+        }
+    }
+    const size_t pb = sizeof(float) * (size_t)R->nparam;
+    auto fail_free = [&](hipError_t e) {
+        router_free(R);
+        set_error("router allocation failed: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? CAPS_ENOMEM : CAPS_EDEVICE;
+    };
+    hipError_t e;
+    if ((e = hipMalloc((void **)&R->param, pb)) != hipSuccess) return fail_free(e);
+    if ((e = hipMalloc((void **)&R->mom, pb)) != hipSuccess) return fail_free(e);
+    if ((e = hipMalloc((void **)&R->vel, pb)) != hipSuccess) return fail_free(e);
+    if ((e = hipMalloc((void **)&R->w1h, sizeof(uint16_t) * (size_t)R->o_b1)) != hipSuccess) return fail_free(e);
+    if ((e = hipMalloc((void **)&R->w2h, sizeof(uint16_t) * (size_t)R->nout * hid)) != hipSuccess)
+        return fail_free(e);
+    if ((e = hipMemcpy(R->param, h.data(), pb, hipMemcpyHostToDevice)) != hipSuccess) return fail_free(e);
+    if ((e = hipMemset(R->mom, 0, pb)) != hipSuccess) return fail_free(e);
+    if ((e = hipMemset(R->vel, 0, pb)) != hipSuccess) return fail_free(e);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk(R->o_b1, 256)), dim3(256), 0, 0, R->param, R->o_b1, R->w1h);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk((int64_t)R->nout * hid, 256)), dim3(256), 0, 0,
+                       R->param + R->o_w2, (int64_t)R->nout * hid, R->w2h);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail_free(e);
+    router_free(ix->router);
+    ix->router = R;
+    return CAPS_OK;
+}
+
+// Workspace of one training / gradient batch of up to bs rows.
+struct BatchWs {
+    uint16_t *Xb, *Hb, *dZ16, *dH16;
+    int32_t *Lb;
+    float *Z, *dZ32, *dH32, *grad, *loss_rows;
+};
+
+static size_t batch_ws(const Router &R, int32_t bs, int32_t L, uint8_t *base, BatchWs *w) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        o = (o + 255) & ~(size_t)255;
+        uint8_t *p = base ? base + o : nullptr;
+        o += bytes;
+        return p;
+    };
+    BatchWs t;
+    t.Xb = (uint16_t *)take(sizeof(uint16_t) * (size_t)bs * R.dpad);
+    t.Hb = (uint16_t *)take(sizeof(uint16_t) * (size_t)bs * R.hid);
+    t.dZ16 = (uint16_t *)take(sizeof(uint16_t) * (size_t)bs * R.nout);
+    t.dH16 = (uint16_t *)take(sizeof(uint16_t) * (size_t)bs * R.hid);
+    t.Lb = (int32_t *)take(sizeof(int32_t) * (size_t)bs * std::max(L, 1));
+    t.Z = (float *)take(sizeof(float) * (size_t)bs * R.nout);
+    t.dZ32 = (float *)take(sizeof(float) * (size_t)bs * R.nout);
+    t.dH32 = (float *)take(sizeof(float) * (size_t)bs * R.hid);
+    t.grad = (float *)take(sizeof(float) * (size_t)R.nparam);
+    t.loss_rows = (float *)take(sizeof(float) * (size_t)bs);
+    if (w) *w = t;
+    return o + 256;
+}
+
+// Forward, loss and gradients of one batch already gathered into w.Xb / w.Lb.
+static caps_status batch_grads(const Router &R, const BatchWs &w, int32_t nb, int32_t L, hipStream_t st) {
+    caps_status s;
+    // h = relu(W1 x + b1), z = W2 h + b2
+    s = gemm(w.Xb, R.dpad, 1, R.w1h, R.dpad, 1, nb, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr, 0,
+             nullptr, w.Hb, R.hid, st);
+    if (s != CAPS_OK) return s;
+    s = gemm(w.Hb, R.hid, 1, R.w2h, R.hid, 1, nb, R.nout, R.hid, R.param + R.o_b2, 0, nullptr, 0, w.Z, nullptr,
+             R.nout, st);
+    if (s != CAPS_OK) return s;
+    hipLaunchKernelGGL(k_softmax_ce, dim3((unsigned)nb), dim3(256), 0, st, w.Z, nb, R.nout, w.Lb, L, w.loss_rows,
+                       w.dZ32, w.dZ16);
+    CAPS_HIP(hipGetLastError());
+    float *gw1 = w.grad, *gb1 = w.grad + R.o_b1, *gw2 = w.grad + R.o_w2, *gb2 = w.grad + R.o_b2;
+    // dW2 = dZ^T h;  db2 = column sums of dZ
+    s = gemm(w.dZ16, 1, R.nout, w.Hb, 1, R.hid, R.nout, R.hid, nb, nullptr, 0, nullptr, 0, gw2, nullptr, R.hid, st);
+    if (s != CAPS_OK) return s;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(R.nout, 256)), dim3(256), 0, st, w.dZ32, nb, R.nout, gb2);
+    // dH = (dZ W2) masked by h > 0;  db1 = column sums of dH
+    s = gemm(w.dZ16, R.nout, 1, R.w2h, 1, R.hid, nb, R.hid, R.nout, nullptr, kGemmMask, w.Hb, R.hid, w.dH32, w.dH16,
+             R.hid, st);
+    if (s != CAPS_OK) return s;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(R.hid, 256)), dim3(256), 0, st, w.dH32, nb, R.hid, gb1);
+    // dW1 = dH^T x
+    s = gemm(w.dH16, 1, R.hid, w.Xb, 1, R.dpad, R.hid, R.dpad, nb, nullptr, 0, nullptr, 0, gw1, nullptr, R.dpad, st);
+    if (s != CAPS_OK) return s;
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+static caps_status check_queries(const Index &ix, const float *q, int32_t n, const int32_t *con_off,
+                                 const int32_t *con_attr, const int32_t *con_val, int32_t n_con) {
+    if (n < 0 || n_con < 0) {
+        set_error("router: negative count");
+        return CAPS_EINVAL;
+    }
+    if (n > 0 && (!q || !con_off)) {
+        set_error("router: null query arrays");
+        return CAPS_EINVAL;
+    }
+    if (n_con > 0 && (!con_attr || !con_val)) {
+        set_error("router: null constraint arrays");
+        return CAPS_EINVAL;
+    }
+    (void)ix;
+    return CAPS_OK;
+}
+
+static caps_status check_params(const caps_router_params *p) {
+    if (!p) {
+        set_error("router: null params");
+        return CAPS_EINVAL;
+    }
+    if (p->hidden < 16 || p->hidden > 8192 || p->hidden % 16) {
+        set_error("router: hidden must be a multiple of 16 in [16, 8192]");
+        return CAPS_EINVAL;
+    }
+    if (!(p->in_scale == p->in_scale) || !(p->in_shift == p->in_shift) || !(p->fallback_prob == p->fallback_prob)) {
+        set_error("router: NaN parameter");
+        return CAPS_EINVAL;
+    }
+    return CAPS_OK;
+}
+
+}  // namespace caps
+
+using namespace caps;
+
+extern "C" caps_status caps_router_labels(const caps_index *idx, const int32_t *ids, int32_t n, int32_t k,
+                                          int32_t *out_parts, void *stream) {
+    if (!idx || n < 0 || k < 1 || (n > 0 && (!ids || !out_parts))) {
+        set_error("caps_router_labels: bad arguments");
+        return CAPS_EINVAL;
+    }
+    if (n == 0) return CAPS_OK;
+    hipLaunchKernelGGL(k_router_labels, dim3((unsigned)nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, ids, n, k,
+                       idx->ix.assign, idx->ix.n, out_parts);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_router_set(caps_index *idx, const caps_router_params *p, const float *w1,
+                                       const float *b1, const float *w2, const float *b2) {
+    if (!idx) {
+        set_error("caps_router_set: null index");
+        return CAPS_EINVAL;
+    }
+    caps_status s = check_params(p);
+    if (s != CAPS_OK) return s;
+    if (!w1 != !b1 || !w1 != !w2 || !w1 != !b2) {
+        set_error("caps_router_set: give all four weight arrays or none");
+        return CAPS_EINVAL;
+    }
+    return router_alloc(&idx->ix, p->hidden, p->in_scale, p->in_shift, p->fallback_prob, p->seed, w1, b1, w2, b2);
+}
+
+extern "C" caps_status caps_router_info(const caps_index *idx, caps_router_info_t *out) {
+    if (!idx || !out) {
+        set_error("caps_router_info: null argument");
+        return CAPS_EINVAL;
+    }
+    memset(out, 0, sizeof(*out));
+    const Router *R = idx->ix.router;
+    if (!R) return CAPS_OK;
+    out->present = 1;
+    out->din = R->din;
+    out->dpad = R->dpad;
+    out->hidden = R->hid;
+    out->n_out = R->nout;
+    out->in_scale = R->in_scale;
+    out->in_shift = R->in_shift;
+    out->fallback_prob = R->fb_prob;
+    out->steps = R->step;
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_router_get(const caps_index *idx, float *w1, float *b1, float *w2, float *b2) {
+    if (!idx || !idx->ix.router) {
+        set_error("caps_router_get: index has no router");
+        return CAPS_EINVAL;
+    }
+    const Router &R = *idx->ix.router;
+    CAPS_HIP(hipDeviceSynchronize());
+    if (w1) CAPS_HIP(hipMemcpy(w1, R.param, sizeof(float) * (size_t)R.o_b1, hipMemcpyDeviceToHost));
+    if (b1) CAPS_HIP(hipMemcpy(b1, R.param + R.o_b1, sizeof(float) * (size_t)R.hid, hipMemcpyDeviceToHost));
+    if (w2) CAPS_HIP(hipMemcpy(w2, R.param + R.o_w2, sizeof(float) * (size_t)R.nout * R.hid, hipMemcpyDeviceToHost));
+    if (b2) CAPS_HIP(hipMemcpy(b2, R.param + R.o_b2, sizeof(float) * (size_t)R.nout, hipMemcpyDeviceToHost));
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_router_logits(const caps_index *idx, const float *q, int32_t n, const int32_t *con_off,
+                                          const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
+                                          float *out_logits, void *stream) {
+    if (!idx || !idx->ix.router) {
+        set_error("caps_router_logits: index has no router");
+        return CAPS_EINVAL;
+    }
+    caps_status s = check_queries(idx->ix, q, n, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n == 0) return CAPS_OK;
+    if (!out_logits) {
+        set_error("caps_router_logits: null output");
+        return CAPS_EINVAL;
+    }
+    const Index &ix = idx->ix;
+    const Router &R = *ix.router;
+    hipStream_t st = (hipStream_t)stream;
+    uint16_t *ws = nullptr;
+    const size_t xb = sizeof(uint16_t) * (size_t)n * R.dpad, hb = sizeof(uint16_t) * (size_t)n * R.hid;
+    CAPS_HIP(hipMallocAsync((void **)&ws, xb + hb + 256, st));
+    uint16_t *X = ws, *H = reinterpret_cast<uint16_t *>(reinterpret_cast<uint8_t *>(ws) + ((xb + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(k_router_input, dim3((unsigned)n), dim3(64), 0, st, q, n, ix.d, con_off, con_attr, con_val,
+                       n_con, ix.sch, R.in_scale, R.in_shift, R.dpad, X);
+    s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, n, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr, 0, nullptr, H,
+             R.hid, st);
+    if (s == CAPS_OK)
+        s = gemm(H, R.hid, 1, R.w2h, R.hid, 1, n, R.nout, R.hid, R.param + R.o_b2, 0, nullptr, 0, out_logits,
+                 nullptr, R.nout, st);
+    (void)hipFreeAsync(ws, st);
+    return s;
+}
+
+// Loss and gradients of one batch (all n rows) without updating the router;
+// gradients go to host arrays laid out like the weights.
+extern "C" caps_status caps_router_grads(caps_index *idx, const float *q, int32_t n, const int32_t *con_off,
+                                         const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
+                                         const int32_t *labels, int32_t n_labels, float *out_loss, float *g_w1,
+                                         float *g_b1, float *g_w2, float *g_b2, void *stream) {
+    if (!idx || !idx->ix.router) {
+        set_error("caps_router_grads: index has no router");
+        return CAPS_EINVAL;
+    }
+    caps_status s = check_queries(idx->ix, q, n, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n < 1 || n_labels < 1 || !labels) {
+        set_error("caps_router_grads: need n >= 1 rows and labels");
+        return CAPS_EINVAL;
+    }
+    const Index &ix = idx->ix;
+    const Router &R = *ix.router;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = batch_ws(R, n, n_labels, nullptr, nullptr);
+    uint8_t *base = nullptr;
+    CAPS_HIP(hipMallocAsync((void **)&base, bytes, st));
+    BatchWs w;
+    batch_ws(R, n, n_labels, base, &w);
+    hipLaunchKernelGGL(k_router_input, dim3((unsigned)n), dim3(64), 0, st, q, n, ix.d, con_off, con_attr, con_val,
+                       n_con, ix.sch, R.in_scale, R.in_shift, R.dpad, w.Xb);
+    (void)hipMemcpyAsync(w.Lb, labels, sizeof(int32_t) * (size_t)n * n_labels, hipMemcpyDeviceToDevice, st);
+    s = batch_grads(R, w, n, n_labels, st);
+    float *acc = w.Z;   // the logits are consumed by now: first slot holds the loss sum
+    if (s == CAPS_OK) {
+        (void)hipMemsetAsync(acc, 0, sizeof(float), st);
+        hipLaunchKernelGGL(k_accum_mean, dim3(1), dim3(256), 0, st, w.loss_rows, n, acc);
+    }
+    std::vector<float> host(s == CAPS_OK ? (size_t)R.nparam : 0);
+    float lsum = 0.0f;
+    if (s == CAPS_OK) {
+        hipError_t e = hipMemcpyAsync(host.data(), w.grad, sizeof(float) * (size_t)R.nparam, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&lsum, acc, sizeof(float), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            set_error("caps_router_grads: %s", hipGetErrorString(e));
+            s = CAPS_EDEVICE;
+        }
+    }
+    (void)hipFreeAsync(base, st);
+    if (s != CAPS_OK) return s;
+    if (out_loss) *out_loss = lsum / (float)n;
+    if (g_w1) memcpy(g_w1, host.data(), sizeof(float) * (size_t)R.o_b1);
+    if (g_b1) memcpy(g_b1, host.data() + R.o_b1, sizeof(float) * (size_t)R.hid);
+    if (g_w2) memcpy(g_w2, host.data() + R.o_w2, sizeof(float) * (size_t)R.nout * R.hid);
+    if (g_b2) memcpy(g_b2, host.data() + R.o_b2, sizeof(float) * (size_t)R.nout);
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_router_train(caps_index *idx, const caps_router_params *p, const float *q, int32_t n,
+                                         const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                                         int32_t n_con, const int32_t *labels, int32_t n_labels, float *out_loss,
+                                         void *stream) {
+    if (!idx) {
+        set_error("caps_router_train: null index");
+        return CAPS_EINVAL;
+    }
+    caps_status s = check_params(p);
+    if (s != CAPS_OK) return s;
+    s = check_queries(idx->ix, q, n, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n < 1 || n_labels < 1 || !labels || p->epochs < 0 || p->batch < 1 || p->batch > (1 << 16) ||
+        !(p->lr > 0.0f) || !(p->beta1 >= 0.0f && p->beta1 < 1.0f) || !(p->beta2 >= 0.0f && p->beta2 < 1.0f) ||
+        !(p->eps > 0.0f)) {
+        set_error("caps_router_train: bad rows, labels, epochs, batch or optimiser parameters");
+        return CAPS_EINVAL;
+    }
+    Index &ix = idx->ix;
+    if (p->reset || !ix.router || ix.router->hid != p->hidden) {
+        s = router_alloc(&ix, p->hidden, p->in_scale, p->in_shift, p->fallback_prob, p->seed, nullptr, nullptr,
+                         nullptr, nullptr);
+        if (s != CAPS_OK) return s;
+    } else {
+        ix.router->in_scale = p->in_scale;
+        ix.router->in_shift = p->in_shift;
+        ix.router->fb_prob = p->fallback_prob;
+    }
+    Router &R = *ix.router;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t bs = std::min(p->batch, n);
+    // workspace: every input row once, the shuffle, one batch (256-byte aligned pieces)
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t off_perm = al(sizeof(uint16_t) * (size_t)n * R.dpad);
+    const size_t off_batch = al(off_perm + sizeof(int32_t) * (size_t)n);
+    const size_t total = off_batch + batch_ws(R, bs, n_labels, nullptr, nullptr);
+    uint8_t *base = nullptr;
+    CAPS_HIP(hipMallocAsync((void **)&base, total, st));
+    uint16_t *X = reinterpret_cast<uint16_t *>(base);
+    int32_t *perm = reinterpret_cast<int32_t *>(base + off_perm);
+    BatchWs w;
+    batch_ws(R, bs, n_labels, base + off_batch, &w);
+    hipLaunchKernelGGL(k_router_input, dim3((unsigned)n), dim3(64), 0, st, q, n, ix.d, con_off, con_attr, con_val,
+                       n_con, ix.sch, R.in_scale, R.in_shift, R.dpad, X);
+    CAPS_HIP(hipGetLastError());
+    std::vector<int32_t> order((size_t)n);
+    uint64_t rng = p->seed ^ 0xD1B54A32D192ED03ull;
+    float *loss_dev = nullptr;
+    CAPS_HIP(hipMallocAsync((void **)&loss_dev, sizeof(float), st));
+    for (int32_t ep = 0; ep < p->epochs && s == CAPS_OK; ep++) {
+        // Fisher-Yates shuffle of the rows from splitmix64
+        for (int32_t i = 0; i < n; i++) order[(size_t)i] = i;
+        for (int32_t i = n - 1; i > 0; i--) {
+            const int32_t j = (int32_t)(sm64_next(rng) % (uint64_t)(i + 1));
+            std::swap(order[(size_t)i], order[(size_t)j]);
+        }
+        hipError_t e = hipMemcpyAsync(perm, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);   // `order` is reused next epoch
+        if (e == hipSuccess) e = hipMemsetAsync(loss_dev, 0, sizeof(float), st);
+        if (e != hipSuccess) {
+            set_error("caps_router_train: %s", hipGetErrorString(e));
+            s = CAPS_EDEVICE;
+            break;
+        }
+        for (int32_t b0 = 0; b0 < n && s == CAPS_OK; b0 += bs) {
+            const int32_t nb = std::min(bs, n - b0);
+            hipLaunchKernelGGL(k_gather_batch, dim3((unsigned)nb), dim3(64), 0, st, X, labels, perm + b0, nb, R.dpad,
+                               n_labels, w.Xb, w.Lb);
+            s = batch_grads(R, w, nb, n_labels, st);
+            if (s != CAPS_OK) break;
+            hipLaunchKernelGGL(k_accum_mean, dim3(1), dim3(256), 0, st, w.loss_rows, nb, loss_dev);
+            R.step++;
+            const double bc1 = 1.0 - pow((double)p->beta1, (double)R.step);
+            const double bc2 = 1.0 - pow((double)p->beta2, (double)R.step);
+            hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(R.nparam, 256)), dim3(256), 0, st, R.param, w.grad, R.mom,
+                               R.vel, R.nparam, p->lr, p->beta1, p->beta2, p->eps, (float)bc1, (float)bc2);
+            hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk(R.o_b1, 256)), dim3(256), 0, st, R.param, R.o_b1,
+                               R.w1h);
+            hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk((int64_t)R.nout * R.hid, 256)), dim3(256), 0, st,
+                               R.param + R.o_w2, (int64_t)R.nout * R.hid, R.w2h);
+            e = hipGetLastError();
+            if (e != hipSuccess) {
+                set_error("caps_router_train: %s", hipGetErrorString(e));
+                s = CAPS_EDEVICE;
+            }
+        }
+        if (s == CAPS_OK && out_loss) {
+            float lsum = 0.0f;
+            e = hipMemcpyAsync(&lsum, loss_dev, sizeof(float), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                set_error("caps_router_train: %s", hipGetErrorString(e));
+                s = CAPS_EDEVICE;
+            }
+            out_loss[ep] = lsum / (float)n;   // mean over the epoch's rows
+        }
+    }
+    (void)hipFreeAsync(loss_dev, st);
+    (void)hipFreeAsync(base, st);
+    if (s == CAPS_OK) CAPS_HIP(hipStreamSynchronize(st));
+    return s;
+}

@@ -820,10 +820,13 @@ struct SearchWs {
     int32_t *cand, *entries;
     uint64_t *partials, *tau;
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
+    uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
+    float *conf;                // learned routing: softmax top-1 probability
+    int32_t *probes_c;          // learned routing: centroid probes for the fallback
 };
 
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
-                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes) {
+                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router) {
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
     w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
     w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
@@ -845,6 +848,10 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.pcount = ar.take<int32_t>(b + 1);
     w.pstart = ar.take<int32_t>(b + 1);
     w.tstart = ar.take<int32_t>(b + 1);
+    w.rx = router ? ar.take<uint16_t>((size_t)sb * router->dpad) : nullptr;
+    w.rh = router ? ar.take<uint16_t>((size_t)sb * router->hid) : nullptr;
+    w.conf = router ? ar.take<float>((size_t)sb) : nullptr;
+    w.probes_c = router ? ar.take<int32_t>((size_t)sb * m) : nullptr;
 }
 
 caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
@@ -868,16 +875,21 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     const size_t qlow_row = mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
     const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
                          sizeof(uint64_t) * (size_t)m * r + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 5 * sizeof(float) + 64;
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 5 * sizeof(float) + 64 +
+                         (sp->routing == 1 && ix->router
+                              ? sizeof(uint16_t) * (size_t)(ix->router->dpad + ix->router->hid) +
+                                    sizeof(float) + sizeof(int32_t) * (size_t)m
+                              : 0);
     const size_t budget = (size_t)1 << 30;
     const int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
+    const Router *router = sp->routing == 1 ? ix->router : nullptr;
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row);
+    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router);
     Arena ar;
     ar.cap = measure.off;
     CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
-    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row);
+    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router);
     if (ar.overflow) {
         (void)hipFreeAsync(ar.base, st);
         set_error("caps_search: internal workspace layout error");
@@ -921,14 +933,35 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
                            con_val, n_con, nb, ix->sch, qd);
         prof_end(CAPS_STAGE_PREP, st);
+        if (router) {
+            // learned routing: router probes, their candidate counts, then a
+            // per-query fallback to the centroid probes
+            prof_begin(CAPS_STAGE_ROUTE, st);
+            const caps_status rs = router_scores(ix, q + (int64_t)q0 * d, nb, con_off + q0, con_attr, con_val, n_con,
+                                                 W.rx, W.rh, scores, W.conf, st);
+            if (rs != CAPS_OK) return rs;
+            prof_end(CAPS_STAGE_ROUTE, st);
+            prof_begin(CAPS_STAGE_TOPM, st);
+            hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
+                               m, probes);
+            prof_end(CAPS_STAGE_TOPM, st);
+            prof_begin(CAPS_STAGE_SELECT, st);
+            hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
+                               ix->tags, h, ix->offs, sp->rule, sel, cand);
+            prof_end(CAPS_STAGE_SELECT, st);
+        }
         prof_begin(CAPS_STAGE_ROUTE, st);
         hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
                            q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
         prof_end(CAPS_STAGE_ROUTE, st);
         prof_begin(CAPS_STAGE_TOPM, st);
         hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
-                           m, probes);
+                           m, router ? W.probes_c : probes);
         prof_end(CAPS_STAGE_TOPM, st);
+        if (router) {
+            const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
+            if (fs != CAPS_OK) return fs;
+        }
         prof_begin(CAPS_STAGE_SELECT, st);
         hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
                            ix->tags, h, ix->offs, sp->rule, sel, cand);

@@ -10,7 +10,7 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import PREC, BuildParams, IndexInfo, SearchParams, check, lib
+from ._lib import PREC, BuildParams, IndexInfo, RouterInfo, RouterParams, SearchParams, check, lib
 
 
 def _torch():
@@ -102,12 +102,14 @@ class Index:
         return qd, co, ca, cv, n_con
 
     def search(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
-               mode: int = 0, rerank: int = 0, stream=None, counters: bool = False, out=None):
+               mode: int = 0, rerank: int = 0, routing: int = 0, stream=None, counters: bool = False,
+               out=None):
         """Top-k filtered search for a batch.  Returns device tensors
         (ids int32 [Q,k], dist float32 [Q,k]) and, with counters=True, the
         per-query candidate and survivor counts.  mode 1 scans the
         low-precision copy with matrix cores and rescores `rerank`
-        candidates per query exactly."""
+        candidates per query exactly; mode 2 forces the plain FP32 scan.
+        routing 1 uses the learned router (with its centroid fallback)."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
@@ -118,7 +120,7 @@ class Index:
             ids, dist = out
         nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
         ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
-        sp = SearchParams(k, nprobe, rule, mode, rerank, 0)
+        sp = SearchParams(k, nprobe, rule, mode, rerank, routing)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
@@ -129,20 +131,93 @@ class Index:
             return ids, dist, nc, ns
         return ids, dist
 
-    def probes(self, q, con_off, con_attr, con_val, nprobe: int, *, rule: int = 0, stream=None):
+    def probes(self, q, con_off, con_attr, con_val, nprobe: int, *, rule: int = 0, routing: int = 0,
+               k: int = 1, stream=None):
         """Routing and sub-partition choice only: (probes [Q,m], masks [Q,m])."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
         pr = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
         mk = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
-        sp = SearchParams(1, nprobe, rule, 0, 0, 0)
+        sp = SearchParams(k, nprobe, rule, 0, 0, routing)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search_probes(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
                                            ca.data_ptr(), cv.data_ptr(), n_con, pr.data_ptr(),
                                            mk.data_ptr(), st))
         return pr, mk
+
+    # ------------------------------------------------------------ learned router
+    @staticmethod
+    def _rparams(hidden=1024, epochs=1, batch=4096, reset=1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 in_scale=1.0, in_shift=0.0, fallback_prob=0.0, seed=0):
+        return RouterParams(hidden, epochs, batch, reset, lr, beta1, beta2, eps, in_scale, in_shift,
+                            fallback_prob, 0, ctypes.c_uint64(seed & (2**64 - 1)).value)
+
+    def router_labels(self, ids):
+        """Distinct partitions of each row of `ids` (device int32 n x k), -1 padded."""
+        torch = _torch()
+        ids = _dev(ids, torch.int32, self.device)
+        n, k = ids.shape
+        out = torch.empty((n, k), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().caps_router_labels(self._h, ids.data_ptr(), n, k, out.data_ptr(), _stream(None)))
+        return out
+
+    def router_train(self, q, con_off, con_attr, con_val, labels, **params):
+        """Trains the learned router on the GPU; returns the mean loss per epoch."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        lb = _dev(labels, torch.int32, self.device)
+        p = self._rparams(**params)
+        loss = np.zeros(max(p.epochs, 1), np.float32)
+        with torch.cuda.device(self.device):
+            check(lib().caps_router_train(self._h, ctypes.byref(p), qd.data_ptr(), int(qd.shape[0]),
+                                          co.data_ptr(), ca.data_ptr(), cv.data_ptr(), n_con, lb.data_ptr(),
+                                          int(lb.shape[1]), _ptr(loss), _stream(None)))
+        return loss[:p.epochs]
+
+    def router_set(self, w1=None, b1=None, w2=None, b2=None, **params):
+        p = self._rparams(**params)
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (w1, b1, w2, b2)]
+        check(lib().caps_router_set(self._h, ctypes.byref(p), *(_ptr(a) for a in arrs)))
+
+    def router_info(self) -> dict:
+        inf = RouterInfo()
+        check(lib().caps_router_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in RouterInfo._fields_}
+
+    def router_get(self) -> dict:
+        inf = self.router_info()
+        h, dp, b = inf["hidden"], inf["dpad"], inf["n_out"]
+        out = dict(w1=np.zeros((h, dp), np.float32), b1=np.zeros(h, np.float32),
+                   w2=np.zeros((b, h), np.float32), b2=np.zeros(b, np.float32))
+        check(lib().caps_router_get(self._h, *(_ptr(out[k]) for k in ("w1", "b1", "w2", "b2"))))
+        return out
+
+    def router_logits(self, q, con_off, con_attr, con_val):
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        n = int(qd.shape[0])
+        out = torch.empty((n, self.info()["n_partitions"]), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().caps_router_logits(self._h, qd.data_ptr(), n, co.data_ptr(), ca.data_ptr(),
+                                           cv.data_ptr(), n_con, out.data_ptr(), _stream(None)))
+        return out
+
+    def router_grads(self, q, con_off, con_attr, con_val, labels):
+        """(loss, {w1, b1, w2, b2} gradients) of one batch, no update."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        lb = _dev(labels, torch.int32, self.device)
+        g = {k: np.zeros_like(v) for k, v in self.router_get().items()}
+        loss = np.zeros(1, np.float32)
+        with torch.cuda.device(self.device):
+            check(lib().caps_router_grads(self._h, qd.data_ptr(), int(qd.shape[0]), co.data_ptr(),
+                                          ca.data_ptr(), cv.data_ptr(), n_con, lb.data_ptr(), int(lb.shape[1]),
+                                          _ptr(loss), *(_ptr(g[k]) for k in ("w1", "b1", "w2", "b2")),
+                                          _stream(None)))
+        return float(loss[0]), g
 
     # ------------------------------------------------------------ inspection
     def info(self) -> dict:

@@ -320,4 +320,28 @@ def make_tiny(rng_seed, n, d, n_q, vocabs=(3, 4), label_vocab=0, metric=0,
                     label_vocab, q, co, ca, cv, metric, b, h, 5, 5, 2, rng_seed, None)
 
 
-MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c5": make_c5}
+def make_routed(n=40_000, n_q=4000, seed=None, n_clusters=64, d=32, n_vals=8, purity=0.9):
+    """A workload where the filter, not the query vector alone, decides which
+    partitions hold the answers: a Gaussian mixture (means ~ N(0, 9I), unit
+    noise) whose single dense attribute equals cluster % n_vals with
+    probability `purity` (uniform otherwise).  Each query is a point near a
+    random cluster mean with one constraint whose value is drawn
+    independently of that cluster, so its filtered neighbours sit mostly in
+    other clusters.  B = n_clusters, h = 1."""
+    seed = BASE_SEED + 6 if seed is None else seed
+    rv, ra, rq, rc = _streams(seed)
+    means = rv.normal(0.0, 3.0, size=(n_clusters, d))
+    comp = rv.integers(n_clusters, size=n)
+    x = (means[comp] + rv.normal(0.0, 1.0, size=(n, d))).astype(np.float32)
+    keep = ra.random(n) < purity
+    attr = np.where(keep, comp % n_vals, ra.integers(n_vals, size=n)).astype(np.uint32)
+    qc = rq.integers(n_clusters, size=n_q)
+    q = (means[qc] + rq.normal(0.0, 1.0, size=(n_q, d))).astype(np.float32)
+    co = np.arange(n_q + 1, dtype=np.int32)
+    ca = np.zeros(n_q, dtype=np.int32)
+    cv = rc.integers(n_vals, size=n_q).astype(np.int32)
+    return Workload("routed", x, attr[:, None], [n_vals], None, None, 0, q, co, ca, cv, 0,
+                    n_clusters, 1, 10, 10, 4, seed, None)
+
+
+MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c5": make_c5, "routed": make_routed}

@@ -1,0 +1,136 @@
+"""GPU learned router against the FP64 oracle (oracle/router.py) and its
+behavioural contract: forward logits and batch gradients within 1e-4 of each
+tensor's norm (same BF16 operand roundings on both sides); a router that
+always falls back routes exactly like the centroids; training lowers the
+loss; and on a workload whose filters point away from the query's nearest
+clusters, learned routing finds more of the exact answers at a small nprobe."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import router as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def caps():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_15014_amd as caps
+    caps.lib()
+    return caps
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _weights(rng, hid, dp, b):
+    w = dict(w1=(rng.normal(size=(hid, dp)) * 0.15).astype(np.float32),
+             b1=(rng.normal(size=hid) * 0.1).astype(np.float32),
+             w2=(rng.normal(size=(b, hid)) * 0.15).astype(np.float32),
+             b2=(rng.normal(size=b) * 0.1).astype(np.float32))
+    return w
+
+
+def _subset(w, idx):
+    co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[idx])]).astype(np.int32)
+    ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in idx]).astype(np.int32)
+    cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in idx]).astype(np.int32)
+    return w.q[idx], co, ca, cv
+
+
+@pytest.fixture(scope="module")
+def tiny(caps):
+    w = synth.make_tiny(300, n=1500, d=32, n_q=90, vocabs=(3, 5), label_vocab=20, b=16, h=2, cmin=0, cmax=3)
+    ix = caps.Index.from_workload(w, kmeans_iters=3)
+    return w, ix
+
+
+def test_logits_match_oracle(caps, tiny):
+    w, ix = tiny
+    rng = np.random.default_rng(1)
+    dp = R.pad_width(w.d)
+    wt = _weights(rng, 64, dp, 16)
+    ix.router_set(**wt, hidden=64, in_scale=0.5, in_shift=0.1)
+    inf = ix.router_info()
+    assert inf["present"] == 1 and inf["dpad"] == dp and inf["n_out"] == 16
+    got = ix.router_logits(w.q, w.con_off, w.con_attr, w.con_val).cpu().numpy()
+    x = R.input_rows(w.q, w.con_off, w.con_attr, w.con_val, w.dense_vocab, w.label_vocab, 0.5, 0.1)
+    want, _ = R.forward(x, **wt)
+    assert _rel(got, want) < 1e-4
+    back = ix.router_get()
+    for k in wt:
+        assert np.array_equal(back[k], wt[k])
+
+
+def test_gradients_match_oracle(caps, tiny):
+    w, ix = tiny
+    rng = np.random.default_rng(2)
+    dp = R.pad_width(w.d)
+    wt = _weights(rng, 48, dp, 16)
+    ix.router_set(**wt, hidden=48, in_scale=0.7, in_shift=-0.2)
+    labels = rng.integers(-1, 16, size=(w.n_q, 3)).astype(np.int32)
+    loss, g = ix.router_grads(w.q, w.con_off, w.con_attr, w.con_val, labels)
+    x = R.input_rows(w.q, w.con_off, w.con_attr, w.con_val, w.dense_vocab, w.label_vocab, 0.7, -0.2)
+    want_loss, want = R.loss_and_grads(x, labels, **wt)
+    assert abs(loss - want_loss) <= 1e-4 * abs(want_loss)
+    for k in ("w1", "b1", "w2", "b2"):
+        assert _rel(g[k], want[k]) < 1e-4, k
+
+
+def test_always_fallback_is_centroid_routing(caps, tiny):
+    w, ix = tiny
+    rng = np.random.default_rng(3)
+    ix.router_set(**_weights(rng, 32, R.pad_width(w.d), 16), hidden=32, fallback_prob=1.5)
+    for m in (1, 5, 16):
+        for mode in (0, 2):
+            a = ix.search(w.q, w.con_off, w.con_attr, w.con_val, 7, m, mode=mode, routing=0, counters=True)
+            b = ix.search(w.q, w.con_off, w.con_attr, w.con_val, 7, m, mode=mode, routing=1, counters=True)
+            for x, y in zip(a, b):
+                assert np.array_equal(x.cpu().numpy().view(np.uint32), y.cpu().numpy().view(np.uint32))
+        pa, ma = ix.probes(w.q, w.con_off, w.con_attr, w.con_val, m, routing=0)
+        pb, mb = ix.probes(w.q, w.con_off, w.con_attr, w.con_val, m, routing=1, k=7)
+        assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+
+
+def test_labels_are_partitions_of_the_ids(caps, tiny):
+    w, ix = tiny
+    ids, _ = ix.search(w.q, w.con_off, w.con_attr, w.con_val, 10, 16)
+    lab = ix.router_labels(ids).cpu().numpy()
+    assign = ix.export()["assign"]
+    for i, row in enumerate(ids.cpu().numpy()):
+        want = []
+        for v in row:
+            if v >= 0 and assign[v] not in want:
+                want.append(int(assign[v]))
+        assert lab[i].tolist() == want + [-1] * (10 - len(want))
+
+
+def test_learned_routing_gain(caps):
+    w = synth.make_routed(n=40_000, n_q=6000, purity=1.0)
+    ix = caps.Index.from_workload(w)
+    b = w.n_partitions
+    tr, te = np.arange(0, 5000), np.arange(5000, 6000)
+    q, co, ca, cv = _subset(w, tr)
+    truth, _ = ix.search(q, co, ca, cv, 10, b)
+    labels = ix.router_labels(truth)
+    loss = ix.router_train(q, co, ca, cv, labels, hidden=256, epochs=30, batch=256, lr=2e-3,
+                           in_scale=1.0 / 3.0, seed=7)
+    assert loss[-1] < 0.6 * loss[0]
+    qt, cot, cat, cvt = _subset(w, te)
+    tt, _ = ix.search(qt, cot, cat, cvt, 10, b)
+    tt = tt.cpu().numpy()
+
+    def recall(ids):
+        ids = ids.cpu().numpy()
+        return np.mean([len(set(a[a >= 0]) & set(t[t >= 0])) / max(1, (t >= 0).sum()) for a, t in zip(ids, tt)])
+
+    m = 4
+    r0 = recall(ix.search(qt, cot, cat, cvt, 10, m, routing=0)[0])
+    r1 = recall(ix.search(qt, cot, cat, cvt, 10, m, routing=1)[0])
+    assert r1 > r0 + 0.15, (r0, r1)
