@@ -18,6 +18,10 @@ Procedure
      (the filtered scan) is reported against the vector-ALU roofline;
   6. CPU baseline: the oracle's query path on a bounded sample of the same
      queries at the same nprobe, on the host's cores.
+Modes: `value` is exact search (mode 0: BF16 lower bounds on the matrix
+cores, exact FP32 rescoring); `modes` also holds BF16 + rerank (mode 1),
+the plain FP32 scan (mode 2) and BF16 + learned router (a 192-1024-1024
+MLP trained on the GPU on 2M C2-shaped queries labelled by exact search).
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -101,10 +105,14 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
     ap.add_argument("--target", type=float, default=0.9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="fp32,bf16,valu",
+    ap.add_argument("--router-train", type=int, default=2_000_000,
+                    help="training queries for the learned router (mode 'router')")
+    ap.add_argument("--router-epochs", type=int, default=2)
+    ap.add_argument("--modes", default="fp32,bf16,valu,router",
                     help="comma list of search modes to time: fp32 (exact, mode 0), bf16 "
                          "(approximate + rerank, mode 1), valu (exact, plain FP32 scan only, "
-                         "mode 2); the JSON line needs fp32")
+                         "mode 2), router (BF16 + learned router: mode 1, routing 1); the JSON line "
+                         "needs fp32")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -149,7 +157,7 @@ def main():
     log(f"truth (all {B} partitions probed): {time.perf_counter() - t0:.2f}s, "
         f"mean |D_C| = {nvalid.mean():.0f}")
 
-    def measure(mode, label):
+    def measure(mode, label, routing=0):
         sweep = []
         cand = [args.nprobe] if args.nprobe else [8, 16, 32, 64, 128, 256, 384, 512, 640, 768, 832, 896,
                                                   960, 1024]
@@ -157,7 +165,7 @@ def main():
         for m in cand:
             if m > B:
                 continue
-            ids, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, counters=True)
+            ids, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, routing=routing, counters=True)
             rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
             sweep.append({"nprobe": m, "recall@10": round(rec, 4),
                           "cand_per_q": float(nc.float().mean()), "surv_per_q": float(ns.float().mean())})
@@ -171,8 +179,8 @@ def main():
         ids = torch.empty((w.n_q, k), dtype=torch.int32, device=dev)
         dist = torch.empty((w.n_q, k), dtype=torch.float32, device=dev)
         for _ in range(args.warmup):
-            ix.search(q, co, ca, cv, k, m, mode=mode, out=(ids, dist))
-        _, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, counters=True)
+            ix.search(q, co, ca, cv, k, m, mode=mode, routing=routing, out=(ids, dist))
+        _, _, nc, ns = ix.search(q, co, ca, cv, k, m, mode=mode, routing=routing, counters=True)
         surv_total = int(ns.to(torch.int64).sum())
         cand_total = int(nc.to(torch.int64).sum())
         torch.cuda.synchronize()
@@ -180,7 +188,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ix.search(q, co, ca, cv, k, m, mode=mode, out=(ids, dist))
+            ix.search(q, co, ca, cv, k, m, mode=mode, routing=routing, out=(ids, dist))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = caps.profile_read()
@@ -219,6 +227,32 @@ def main():
     plain = measure(0, "fp32") if "fp32" in modes else None
     lowp = measure(1, "bf16") if "bf16" in modes else None
     valu = measure(2, "valu") if "valu" in modes else None
+    routed = None
+    if "router" in modes:
+        # learned router on the same index: 2-layer MLP on [q/255 - 0.5 || hashed constraints],
+        # labels = partitions of the exact filtered top-10 (search at nprobe = B), trained on the GPU
+        t0 = time.perf_counter()
+        rq, rco, rca, rcv = synth.make_c2_train_queries(args.router_train, 2308_15014 + 40, w)
+        gen_s = time.perf_counter() - t0
+        rq_d = torch.from_numpy(rq).to(dev)
+        rco_d, rca_d, rcv_d = (torch.from_numpy(a).to(dev) for a in (rco, rca, rcv))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rids, _ = ix.search(rq_d, rco_d, rca_d, rcv_d, k, B)
+        labels = ix.router_labels(rids)
+        torch.cuda.synchronize()
+        label_s = time.perf_counter() - t0
+        del rids
+        t0 = time.perf_counter()
+        losses = ix.router_train(rq_d, rco_d, rca_d, rcv_d, labels, hidden=1024, epochs=args.router_epochs,
+                                 batch=4096, lr=1e-3, in_scale=1.0 / 255.0, in_shift=-0.5, seed=11)
+        train_s = time.perf_counter() - t0
+        del rq_d, rco_d, rca_d, rcv_d, labels
+        log(f"router: {args.router_train} training queries (generated {gen_s:.1f}s, labels {label_s:.1f}s), "
+            f"{args.router_epochs} epochs in {train_s:.1f}s, loss per epoch {[round(float(x), 4) for x in losses]}")
+        routed = measure(1, "bf16+router", routing=1)
+        routed.update(train_queries=args.router_train, epochs=args.router_epochs, train_s=round(train_s, 2),
+                      label_s=round(label_s, 2), loss=[round(float(x), 4) for x in losses])
     if plain is None:
         log("fp32 mode not timed: no JSON line")
         return
@@ -265,6 +299,14 @@ def main():
             "queries_per_s": round(valu["qps"], 1), "nprobe": valu["nprobe"], "recall@10": valu["recall"],
             "ms_per_step": round(valu["ms_step"], 4), "stage_ms_per_step": valu["stage_ms"],
             "roofline": valu["roofline"]}
+    if routed is not None:
+        out["modes"]["bf16_learned_router"] = {
+            "queries_per_s": round(routed["qps"], 1), "nprobe": routed["nprobe"], "recall@10": routed["recall"],
+            "ms_per_step": round(routed["ms_step"], 4), "stage_ms_per_step": routed["stage_ms"],
+            "router": {"layers": "192-1024-1024", "train_queries": routed["train_queries"],
+                       "epochs": routed["epochs"], "train_s": routed["train_s"], "label_s": routed["label_s"],
+                       "loss_per_epoch": routed["loss"]},
+            "sweep": routed["sweep"]}
     if lowp is not None:
         out["modes"]["bf16_centroid"] = {
             "queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"], "recall@10": lowp["recall"],

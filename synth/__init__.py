@@ -247,6 +247,55 @@ def make_c2_queries(n_q, seed, n=1_000_000, band=(0.001, 0.30)):
     return q, co, ca, cv, sel
 
 
+def make_c2_train_queries(n_q, seed, base: Workload, band=(0.001, 0.30)):
+    """Large query sets in the shape of c2's (uniform integer vectors, 1-3
+    constraints copied from a random point's dense attributes, |D_C|/N in
+    ``band``), drawn in vectorised rounds: every round draws a candidate for
+    each missing query and keeps those inside the band.  For router training
+    sets of millions of queries; the per-query generator above is the
+    reference for the benchmark's own query set."""
+    _rv, _ra, rq, rc = _streams(seed)
+    n, nd = base.n, base.dense.shape[1]
+    q = rq.integers(0, 256, size=(n_q, base.d), dtype=np.int32).astype(np.float32)
+    vocabs = list(base.dense_vocab)
+    cnt = _DenseCounter(base.dense, vocabs)
+    # count tables of every attribute subset (bit a set: attribute a constrained)
+    marg = {}
+    for sub in range(1 << nd):
+        keep = tuple(a for a in range(nd) if not (sub >> a) & 1)
+        marg[sub] = cnt.table.sum(axis=keep) if keep else cnt.table
+    nc = np.zeros(n_q, dtype=np.int64)
+    attr = np.zeros((n_q, nd), dtype=bool)
+    val = np.zeros((n_q, nd), dtype=np.int64)
+    todo = np.arange(n_q)
+    while len(todo):
+        k = len(todo)
+        pt = rc.integers(n, size=k)
+        c = np.minimum(rc.integers(1, 4, size=k), nd)
+        order = np.argsort(rc.random((k, nd)), axis=1)
+        chosen = np.zeros((k, nd), dtype=bool)
+        np.put_along_axis(chosen, order, np.arange(nd)[None, :] < c[:, None], axis=1)
+        v = base.dense[pt].astype(np.int64)
+        sub = (chosen * (1 << np.arange(nd))[None, :]).sum(axis=1)
+        counts = np.zeros(k, dtype=np.int64)
+        for sv in np.unique(sub):
+            rows = np.nonzero(sub == sv)[0]
+            sel_attrs = [a for a in range(nd) if (sv >> a) & 1]
+            counts[rows] = marg[int(sv)][tuple(v[rows, a] for a in sel_attrs)]
+        frac = counts / n
+        ok = (frac >= band[0]) & (frac <= band[1])
+        acc = todo[ok]
+        attr[acc] = chosen[ok]
+        val[acc] = v[ok]
+        nc[acc] = c[ok]
+        todo = todo[~ok]
+    co = np.concatenate([[0], np.cumsum(nc)]).astype(np.int32)
+    rows, cols = np.nonzero(attr)            # row-major: attributes ascending per query
+    ca = cols.astype(np.int32)
+    cv = val[rows, cols].astype(np.int32)
+    return q, co, ca, cv
+
+
 def make_c3(n=5_000_000, n_q=10_000, seed=None, n_partitions=4096) -> Workload:
     """Angular corpus: g/|g| with g ~ N(0, I), d=96, inner product.  Each
     point holds 1-8 labels from a vocabulary of 1000, Zipf(1.1).  Queries:
