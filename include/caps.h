@@ -317,6 +317,79 @@ caps_status caps_router_grads(caps_index *idx, const float *q, int32_t n, const 
                               const int32_t *labels, int32_t n_labels, float *out_loss, float *g_w1,
                               float *g_b1, float *g_w2, float *g_b2, void *stream);
 
+/*
+ * Serving loop: continuous batching of filtered queries against one index.
+ * Requests (one query vector + its constraint pairs, HOST memory, copied at
+ * submit) wait in a bounded queue; a scheduler thread owns `streams` batch
+ * slots and, whenever a slot is free, launches the oldest waiting requests
+ * (up to the batch cap) as one search on that slot's stream; results carry
+ * the latency from submit to completion.  All requests share the search
+ * parameters below.  A query's ids and distances do not depend on the batch
+ * it lands in.  The index must outlive the server.
+ */
+typedef struct {
+    int32_t k, nprobe, mode, routing, rerank;   /* as caps_search_params */
+    int32_t max_batch;        /* queries per launch, 1..65536 */
+    int32_t streams;          /* batches in flight, 1..8 */
+    int32_t queue_slots;      /* waiting requests admitted; submit returns EBUSY beyond */
+    int32_t max_constraints;  /* constraint pairs per request, 0..64 */
+    int32_t reserved;
+    int64_t workspace_bytes;  /* device budget of one batch's search workspace
+                                 (caps the batch size; 0: no cap) */
+    double batch_window_us;   /* wait up to this long for a batch to fill once a
+                                 slot is free (0: launch what is waiting) */
+} caps_server_params;
+
+typedef struct {
+    int64_t submitted;        /* accepted requests */
+    int64_t completed;        /* results produced (failed ones included) */
+    int64_t rejected;         /* submits refused with EBUSY */
+    int64_t failed;           /* results of batches whose search failed (ids -1) */
+    int64_t batches;
+    double mean_batch;        /* queries per launched batch */
+    double p50_ms, p99_ms, max_ms, mean_ms;   /* submit-to-completion latency */
+    double qps;               /* completed / (last completion - first submit) */
+    int32_t max_batch;        /* batch cap after the workspace budget */
+    int32_t reserved;
+} caps_server_stats_t;
+
+typedef struct caps_server caps_server;
+
+/* Starts the scheduler thread.  Errors: EINVAL (parameters; mode 1 without a
+ * low-precision copy; routing 1 without a router; a workspace budget below
+ * one query), ENOMEM, EDEVICE. */
+caps_status caps_server_create(const caps_index *idx, const caps_server_params *p, caps_server **out);
+
+/* Queues one request (q: d floats; n_con pairs).  *ticket identifies its
+ * result.  EBUSY when queue_slots requests wait; EINVAL for bad arguments or
+ * more than max_constraints pairs. */
+caps_status caps_server_submit(caps_server *srv, const float *q, int32_t n_con, const int32_t *con_attr,
+                               const int32_t *con_val, uint64_t *ticket);
+
+/* Submits n requests (q n x d, constraint CSR con_off n+1) at arrival_s[i]
+ * seconds after the call (non-decreasing), from the calling thread, and
+ * returns after the last one; tickets[i] = 0 marks a request refused with a
+ * full queue.  HOST arrays. */
+caps_status caps_server_replay(caps_server *srv, const float *q, const int32_t *con_off, const int32_t *con_attr,
+                               const int32_t *con_val, int32_t n, const double *arrival_s, uint64_t *tickets);
+
+/* Moves up to `max` finished results to HOST arrays: tickets, ids (max x k),
+ * dist (max x k), optional latency_ms and status (CAPS_OK or the batch's
+ * error).  *n_done = number written; never blocks. */
+caps_status caps_server_poll(caps_server *srv, int32_t max, uint64_t *tickets, int32_t *ids, float *dist,
+                             float *latency_ms, int32_t *status, int32_t *n_done);
+
+/* Waits until every accepted request has a result; EBUSY after timeout_s. */
+caps_status caps_server_drain(caps_server *srv, double timeout_s);
+
+/* Counters and latency percentiles since creation or the last reset;
+ * reset = 1 starts a new measurement window. */
+caps_status caps_server_stats(caps_server *srv, caps_server_stats_t *out, int32_t reset);
+
+/* Stops accepting, finishes what was accepted, joins the scheduler and
+ * frees the server (NULL is a no-op).  Unpolled results are dropped. */
+void caps_server_destroy(caps_server *srv);
+
 /* Release the index and its device memory (NULL is a no-op). */
 void caps_free(caps_index *idx);
 

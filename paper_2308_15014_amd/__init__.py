@@ -5,5 +5,6 @@ include/caps.h); this package marshals arguments to it.
 """
 from ._lib import CapsError, lib, profile_enable, profile_read  # noqa: F401
 from .index import Index  # noqa: F401
+from .server import Server  # noqa: F401
 
-__all__ = ["Index", "CapsError", "lib"]
+__all__ = ["Index", "Server", "CapsError", "lib"]

@@ -50,6 +50,20 @@ class RouterInfo(ctypes.Structure):
                 ("fallback_prob", ctypes.c_float), ("steps", c_i64)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("k", c_i32), ("nprobe", c_i32), ("mode", c_i32), ("routing", c_i32), ("rerank", c_i32),
+                ("max_batch", c_i32), ("streams", c_i32), ("queue_slots", c_i32),
+                ("max_constraints", c_i32), ("reserved", c_i32), ("workspace_bytes", c_i64),
+                ("batch_window_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("rejected", c_i64), ("failed", c_i64),
+                ("batches", c_i64), ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("qps", ctypes.c_double), ("max_batch", c_i32), ("reserved", c_i32)]
+
+
 PREC = {"none": 0, "fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 
 
@@ -86,6 +100,13 @@ SIGNATURES = {
     "caps_router_logits": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
     "caps_router_grads": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp,
                                   c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_server_create": (c_i32, [c_vp, ctypes.POINTER(ServerParams), ctypes.POINTER(c_vp)]),
+    "caps_server_submit": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, ctypes.POINTER(c_u64)]),
+    "caps_server_replay": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "caps_server_poll": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i32)]),
+    "caps_server_drain": (c_i32, [c_vp, ctypes.c_double]),
+    "caps_server_stats": (c_i32, [c_vp, ctypes.POINTER(ServerStats), c_i32]),
+    "caps_server_destroy": (None, [c_vp]),
     "caps_free": (None, [c_vp]),
     "caps_profile_enable": (c_i32, [c_i32]),
     "caps_profile_read": (c_i32, [ctypes.POINTER(Profile)]),

@@ -123,6 +123,9 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand, int32_t *out_nsurv,
                    int32_t *out_probes, uint32_t *out_masks, hipStream_t st);
 
+// device bytes the workspace of one search call of nq queries takes
+size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq);
+
 // ---- stage timer (caps_util.hip): no-ops unless enabled
 void prof_begin(int stage, hipStream_t st);
 void prof_end(int stage, hipStream_t st);

@@ -854,35 +854,61 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.probes_c = router ? ar.take<int32_t>((size_t)sb * m) : nullptr;
 }
 
+// Shape of one search call: which scan, keys per (query, probe), the
+// sub-batch that keeps the workspace near 1 GiB.
+struct SearchPlan {
+    bool lowp, mfma;
+    int32_t r, sb;
+    size_t qlow_row;
+    const Router *router;
+};
+
+static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int32_t nq) {
+    const int32_t b = ix->b, m = sp->nprobe, k = sp->k;
+    SearchPlan P;
+    // mode 1: approximate keys on the matrix cores, rescored at the merge;
+    // mode 0 on an index with a low-precision copy: the matrix-core scan
+    // with exact keys (bounds prune, survivors are rescored exactly);
+    // otherwise (or mode 2) the plain FP32 scan
+    P.lowp = sp->mode == 1;
+    P.mfma = P.lowp || (sp->mode == 0 && ix->prec != CAPS_PREC_NONE);
+    P.r = P.lowp ? (sp->rerank > 0 ? sp->rerank : std::min(4 * k, kMaxK)) : k;
+    P.router = sp->routing == 1 ? ix->router : nullptr;
+    P.qlow_row = P.mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
+    const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
+                         sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
+                         (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
+                                         sizeof(int32_t) * (size_t)m
+                                   : 0);
+    const size_t budget = (size_t)1 << 30;
+    P.sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nq, 1), budget / per_q));
+    return P;
+}
+
+size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq) {
+    const SearchPlan P = plan_search(ix, sp, nq);
+    SearchWs W;
+    Arena measure;
+    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router);
+    return measure.off;
+}
+
 caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
                    const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand,
                    int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st) {
     const int32_t b = ix->b, d = ix->d, h = ix->h, m = sp->nprobe, k = sp->k;
-    // mode 1: approximate keys on the matrix cores, rescored at the merge;
-    // mode 0 on an index with a low-precision copy: the matrix-core scan
-    // with exact keys (bounds prune, survivors are rescored exactly);
-    // otherwise (or mode 2) the plain FP32 scan
-    const bool lowp = sp->mode == 1;
-    const bool mfma = lowp || (sp->mode == 0 && ix->prec != CAPS_PREC_NONE);
-    const int32_t r = lowp ? (sp->rerank > 0 ? sp->rerank : std::min(4 * k, kMaxK)) : k;
     if (nq == 0) return CAPS_OK;
+    const SearchPlan P = plan_search(ix, sp, nq);
+    const bool lowp = P.lowp, mfma = P.mfma;
+    const int32_t r = P.r, sb = P.sb;
+    const size_t qlow_row = P.qlow_row;
+    const Router *router = P.router;
     const bool probes_only = out_probes != nullptr;
     int pb = 1;
     while (pb < b) pb <<= 1;
 
-    // sub-batch so that the per-batch workspace stays bounded (~1 GiB)
-    const size_t qlow_row = mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
-    const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
-                         sizeof(uint64_t) * (size_t)m * r + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + qlow_row + 5 * sizeof(float) + 64 +
-                         (sp->routing == 1 && ix->router
-                              ? sizeof(uint16_t) * (size_t)(ix->router->dpad + ix->router->hid) +
-                                    sizeof(float) + sizeof(int32_t) * (size_t)m
-                              : 0);
-    const size_t budget = (size_t)1 << 30;
-    const int32_t sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nq, budget / per_q));
-    const Router *router = sp->routing == 1 ? ix->router : nullptr;
     SearchWs W;
     Arena measure;
     carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router);

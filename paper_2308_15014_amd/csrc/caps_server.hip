@@ -1,0 +1,496 @@
+// Serving loop: continuous batching of filtered queries against one
+// HBM-resident index.
+//
+// Requests (one query vector and its constraint pairs, copied at submit)
+// wait in a bounded queue.  A scheduler thread owns `streams` batch slots;
+// whenever a slot is free and requests wait, it takes the oldest ones (up
+// to the batch cap, optionally waiting up to `batch_window_us` for a batch
+// to fill), packs them into pinned host buffers, and enqueues on the slot's
+// stream: host-to-device copies, one search call, device-to-host copies and
+// an event.  Slots run concurrently, so copies and kernels of different
+// batches overlap.  Finished slots are retired in completion order: each
+// request's ids and distances go to a result queue with its latency (submit
+// to the moment the scheduler sees the event complete).
+//
+// Admission: submit refuses (EBUSY) beyond `queue_slots` waiting requests;
+// the batch cap is the largest size whose search workspace (exact bytes of
+// the search's own layout) fits `workspace_bytes`.  A query's result does
+// not depend on the batch it lands in: every search kernel is batch
+// invariant.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "caps_internal.h"
+
+namespace caps {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvReq {
+    uint64_t ticket;
+    Clock::time_point t0;
+    std::vector<float> q;
+    std::vector<int32_t> attr, val;
+};
+
+struct SrvDone {
+    uint64_t ticket;
+    double lat_ms;
+    int32_t status;
+    std::vector<int32_t> ids;
+    std::vector<float> dist;
+};
+
+struct SrvSlot {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    caps_status status = CAPS_OK;
+    std::vector<SrvReq> reqs;
+    float *hq = nullptr, *hdist = nullptr, *dq = nullptr, *ddist = nullptr;
+    int32_t *hoff = nullptr, *hattr = nullptr, *hval = nullptr, *hids = nullptr;
+    int32_t *doff = nullptr, *dattr = nullptr, *dval = nullptr, *dids = nullptr;
+};
+
+struct Server {
+    const Index *ix = nullptr;
+    caps_server_params p{};
+    caps_search_params sp{};
+    int32_t d = 0, k = 0, cap = 0;
+    std::mutex mu;
+    std::condition_variable cv;        // new request / stop (scheduler side)
+    std::condition_variable cv_done;   // a batch retired (drain side)
+    std::deque<SrvReq> pending;
+    std::deque<SrvDone> done;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0, rejected = 0, failed = 0, batches = 0, batched = 0;
+    std::vector<double> lat;
+    Clock::time_point t_first{}, t_last{};
+    bool have_first = false;
+    std::string err;
+    std::vector<SrvSlot> slots;
+    std::thread worker;
+};
+
+static void retire(Server *S, SrvSlot &sl) {
+    const Clock::time_point t = Clock::now();
+    std::vector<SrvDone> out;
+    out.reserve(sl.reqs.size());
+    for (size_t i = 0; i < sl.reqs.size(); i++) {
+        SrvDone r;
+        r.ticket = sl.reqs[i].ticket;
+        r.lat_ms = std::chrono::duration<double, std::milli>(t - sl.reqs[i].t0).count();
+        r.status = sl.status;
+        r.ids.assign((size_t)S->k, -1);
+        r.dist.assign((size_t)S->k, 0.0f);
+        if (sl.status == CAPS_OK) {
+            memcpy(r.ids.data(), sl.hids + i * S->k, sizeof(int32_t) * (size_t)S->k);
+            memcpy(r.dist.data(), sl.hdist + i * S->k, sizeof(float) * (size_t)S->k);
+        }
+        out.push_back(std::move(r));
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto &r : out) {
+            S->lat.push_back(r.lat_ms);
+            if (r.status != CAPS_OK) S->failed++;
+            S->completed++;
+            S->done.push_back(std::move(r));
+        }
+        S->t_last = t;
+    }
+    S->cv_done.notify_all();
+    sl.busy = false;
+    sl.reqs.clear();
+}
+
+static void launch(Server *S, SrvSlot &sl, std::vector<SrvReq> &&batch) {
+    const int32_t nb = (int32_t)batch.size(), d = S->d, k = S->k;
+    int32_t ncon = 0;
+    sl.hoff[0] = 0;
+    for (int32_t i = 0; i < nb; i++) {
+        const SrvReq &r = batch[(size_t)i];
+        memcpy(sl.hq + (size_t)i * d, r.q.data(), sizeof(float) * (size_t)d);
+        for (size_t e = 0; e < r.attr.size(); e++) {
+            sl.hattr[ncon] = r.attr[e];
+            sl.hval[ncon] = r.val[e];
+            ncon++;
+        }
+        sl.hoff[i + 1] = ncon;
+    }
+    caps_status s = CAPS_OK;
+    hipError_t e = hipMemcpyAsync(sl.dq, sl.hq, sizeof(float) * (size_t)nb * d, hipMemcpyHostToDevice, sl.st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.doff, sl.hoff, sizeof(int32_t) * (size_t)(nb + 1), hipMemcpyHostToDevice, sl.st);
+    if (e == hipSuccess && ncon > 0)
+        e = hipMemcpyAsync(sl.dattr, sl.hattr, sizeof(int32_t) * (size_t)ncon, hipMemcpyHostToDevice, sl.st);
+    if (e == hipSuccess && ncon > 0)
+        e = hipMemcpyAsync(sl.dval, sl.hval, sizeof(int32_t) * (size_t)ncon, hipMemcpyHostToDevice, sl.st);
+    if (e != hipSuccess) s = CAPS_EDEVICE;
+    if (s == CAPS_OK)
+        s = search(S->ix, &S->sp, sl.dq, nb, sl.doff, sl.dattr, sl.dval, ncon, sl.dids, sl.ddist, nullptr, nullptr,
+                   nullptr, nullptr, sl.st);
+    if (s == CAPS_OK) {
+        e = hipMemcpyAsync(sl.hids, sl.dids, sizeof(int32_t) * (size_t)nb * k, hipMemcpyDeviceToHost, sl.st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl.hdist, sl.ddist, sizeof(float) * (size_t)nb * k, hipMemcpyDeviceToHost, sl.st);
+        if (e != hipSuccess) s = CAPS_EDEVICE;
+    }
+    if (s != CAPS_OK) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->err.empty()) S->err = caps_last_error();
+    }
+    sl.status = s;
+    sl.reqs = std::move(batch);
+    sl.busy = true;
+    if (hipEventRecord(sl.ev, sl.st) != hipSuccess) {
+        // no event to wait for: the stream is in error, finish the batch now
+        (void)hipStreamSynchronize(sl.st);
+        sl.status = CAPS_EDEVICE;
+        retire(S, sl);
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->batches++;
+        S->batched += nb;
+    }
+}
+
+static void run(Server *S) {
+    (void)hipSetDevice(S->ix->device);
+    const auto window = std::chrono::duration<double, std::micro>(S->p.batch_window_us);
+    for (;;) {
+        bool progressed = false, any_busy = false;
+        for (auto &sl : S->slots) {
+            if (!sl.busy) continue;
+            if (hipEventQuery(sl.ev) == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
+            retire(S, sl);
+            progressed = true;
+        }
+        SrvSlot *free_slot = nullptr;
+        for (auto &sl : S->slots)
+            if (!sl.busy) {
+                free_slot = &sl;
+                break;
+            }
+        std::vector<SrvReq> batch;
+        bool quit = false;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (free_slot && !S->pending.empty()) {
+                const bool fill = S->p.batch_window_us > 0 && !S->stop &&
+                                  (int32_t)S->pending.size() < S->cap &&
+                                  Clock::now() - S->pending.front().t0 < window;
+                if (!fill) {
+                    const size_t nb = std::min((size_t)S->cap, S->pending.size());
+                    batch.reserve(nb);
+                    for (size_t i = 0; i < nb; i++) {
+                        batch.push_back(std::move(S->pending.front()));
+                        S->pending.pop_front();
+                    }
+                }
+            }
+            if (batch.empty() && !progressed) {
+                bool busy_now = false;
+                for (auto &sl : S->slots) busy_now |= sl.busy;
+                if (S->stop && S->pending.empty() && !busy_now) {
+                    quit = true;
+                } else {
+                    // poll in-flight batches and the batch window at a fine grain,
+                    // otherwise sleep until a request arrives
+                    const bool fine = any_busy || !S->pending.empty();
+                    S->cv.wait_for(lk, fine ? std::chrono::microseconds(10) : std::chrono::microseconds(2000));
+                }
+            }
+        }
+        if (quit) break;
+        if (!batch.empty()) launch(S, *free_slot, std::move(batch));
+    }
+}
+
+static void free_slot(SrvSlot &sl) {
+    if (sl.st) (void)hipStreamSynchronize(sl.st);
+    void *host[] = {sl.hq, sl.hdist, sl.hoff, sl.hattr, sl.hval, sl.hids};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    void *dev[] = {sl.dq, sl.ddist, sl.doff, sl.dattr, sl.dval, sl.dids};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+}
+
+static void destroy(Server *S) {
+    if (S->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv.notify_all();
+        S->worker.join();
+    }
+    for (auto &sl : S->slots) free_slot(sl);
+    delete S;
+}
+
+static caps_status enqueue(Server *S, const float *q, int32_t n_con, const int32_t *attr, const int32_t *val,
+                           Clock::time_point t0, uint64_t *ticket) {
+    SrvReq r;
+    r.t0 = t0;
+    r.q.assign(q, q + S->d);
+    if (n_con > 0) {
+        r.attr.assign(attr, attr + n_con);
+        r.val.assign(val, val + n_con);
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            set_error("caps_server_submit: server is stopping");
+            return CAPS_EINVAL;
+        }
+        if ((int32_t)S->pending.size() >= S->p.queue_slots) {
+            S->rejected++;
+            set_error("caps_server_submit: queue full (%d waiting)", S->p.queue_slots);
+            return CAPS_EBUSY;
+        }
+        r.ticket = S->next_ticket++;
+        if (ticket) *ticket = r.ticket;
+        if (!S->have_first) {
+            S->t_first = t0;
+            S->have_first = true;
+        }
+        S->submitted++;
+        S->pending.push_back(std::move(r));
+    }
+    S->cv.notify_one();
+    return CAPS_OK;
+}
+
+}  // namespace caps
+
+using namespace caps;
+
+struct caps_server {
+    Server *s;
+};
+
+extern "C" caps_status caps_server_create(const caps_index *idx, const caps_server_params *p, caps_server **out) {
+    if (!idx || !p || !out) {
+        set_error("caps_server_create: null argument");
+        return CAPS_EINVAL;
+    }
+    *out = nullptr;
+    const Index &ix = idx->ix;
+    if (p->k < 1 || p->k > kMaxK || p->nprobe < 1 || p->nprobe > ix.b || p->mode < 0 || p->mode > 2 ||
+        p->routing < 0 || p->routing > 1 || p->max_batch < 1 || p->max_batch > 65536 || p->streams < 1 ||
+        p->streams > 8 || p->queue_slots < 1 || p->max_constraints < 0 || p->max_constraints > 64 ||
+        !(p->batch_window_us >= 0.0) || p->workspace_bytes < 0) {
+        set_error("caps_server_create: parameter out of range");
+        return CAPS_EINVAL;
+    }
+    if (p->mode == 1 && ix.prec == CAPS_PREC_NONE) {
+        set_error("caps_server_create: mode 1 needs an index with a low-precision copy");
+        return CAPS_EINVAL;
+    }
+    if (p->routing == 1 && !ix.router) {
+        set_error("caps_server_create: routing 1 needs a trained router");
+        return CAPS_EINVAL;
+    }
+    Server *S = new Server;
+    S->ix = &ix;
+    S->p = *p;
+    S->sp.k = p->k;
+    S->sp.nprobe = p->nprobe;
+    S->sp.rule = 0;
+    S->sp.mode = p->mode;
+    S->sp.rerank = p->rerank;
+    S->sp.routing = p->routing;
+    S->d = ix.d;
+    S->k = p->k;
+    // batch cap: largest size whose search workspace fits the budget
+    int32_t cap = p->max_batch;
+    if (p->workspace_bytes > 0) {
+        int32_t lo = 1, hi = p->max_batch;
+        if (search_workspace_bytes(&ix, &S->sp, 1) > (size_t)p->workspace_bytes) {
+            delete S;
+            set_error("caps_server_create: workspace_bytes below one query's search workspace");
+            return CAPS_EINVAL;
+        }
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo + 1) / 2;
+            if (search_workspace_bytes(&ix, &S->sp, mid) <= (size_t)p->workspace_bytes) lo = mid;
+            else hi = mid - 1;
+        }
+        cap = lo;
+    }
+    S->cap = cap;
+    const size_t mc = (size_t)std::max(1, cap * p->max_constraints);
+    S->slots.resize((size_t)p->streams);
+    hipError_t e = hipSetDevice(ix.device);
+    for (auto &sl : S->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hq, sizeof(float) * (size_t)cap * S->d, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hdist, sizeof(float) * (size_t)cap * S->k, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hoff, sizeof(int32_t) * (size_t)(cap + 1), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hattr, sizeof(int32_t) * mc, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hval, sizeof(int32_t) * mc, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hids, sizeof(int32_t) * (size_t)cap * S->k, 0);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.dq, sizeof(float) * (size_t)cap * S->d);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.ddist, sizeof(float) * (size_t)cap * S->k);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.doff, sizeof(int32_t) * (size_t)(cap + 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.dattr, sizeof(int32_t) * mc);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.dval, sizeof(int32_t) * mc);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.dids, sizeof(int32_t) * (size_t)cap * S->k);
+    }
+    if (e != hipSuccess) {
+        set_error("caps_server_create: %s", hipGetErrorString(e));
+        destroy(S);
+        return e == hipErrorOutOfMemory ? CAPS_ENOMEM : CAPS_EDEVICE;
+    }
+    S->worker = std::thread(run, S);
+    *out = new caps_server{S};
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_server_submit(caps_server *srv, const float *q, int32_t n_con, const int32_t *con_attr,
+                                          const int32_t *con_val, uint64_t *ticket) {
+    if (!srv || !q || n_con < 0 || (n_con > 0 && (!con_attr || !con_val))) {
+        set_error("caps_server_submit: bad arguments");
+        return CAPS_EINVAL;
+    }
+    if (n_con > srv->s->p.max_constraints) {
+        set_error("caps_server_submit: %d constraints, the server takes at most %d", n_con,
+                  srv->s->p.max_constraints);
+        return CAPS_EINVAL;
+    }
+    return enqueue(srv->s, q, n_con, con_attr, con_val, Clock::now(), ticket);
+}
+
+extern "C" caps_status caps_server_replay(caps_server *srv, const float *q, const int32_t *con_off,
+                                          const int32_t *con_attr, const int32_t *con_val, int32_t n,
+                                          const double *arrival_s, uint64_t *tickets) {
+    if (!srv || n < 0 || (n > 0 && (!q || !con_off || !arrival_s))) {
+        set_error("caps_server_replay: bad arguments");
+        return CAPS_EINVAL;
+    }
+    Server *S = srv->s;
+    const Clock::time_point start = Clock::now();
+    for (int32_t i = 0; i < n; i++) {
+        const int32_t lo = con_off[i], nc = con_off[i + 1] - con_off[i];
+        if (lo < 0 || nc < 0 || nc > S->p.max_constraints) {
+            set_error("caps_server_replay: request %d has bad constraint offsets or too many constraints", i);
+            return CAPS_EINVAL;
+        }
+        const Clock::time_point at =
+            start + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+        Clock::time_point now = Clock::now();
+        if (at - now > std::chrono::microseconds(200)) std::this_thread::sleep_until(at - std::chrono::microseconds(100));
+        while ((now = Clock::now()) < at) {
+        }
+        uint64_t tk = 0;
+        const caps_status s = enqueue(S, q + (size_t)i * S->d, nc, con_attr + lo, con_val + lo, at, &tk);
+        if (tickets) tickets[i] = s == CAPS_OK ? tk : 0;   // 0: refused (queue full)
+        if (s != CAPS_OK && s != CAPS_EBUSY) return s;
+    }
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_server_poll(caps_server *srv, int32_t max, uint64_t *tickets, int32_t *ids, float *dist,
+                                        float *latency_ms, int32_t *status, int32_t *n_done) {
+    if (!srv || max < 0 || !n_done || (max > 0 && (!tickets || !ids || !dist))) {
+        set_error("caps_server_poll: bad arguments");
+        return CAPS_EINVAL;
+    }
+    Server *S = srv->s;
+    std::lock_guard<std::mutex> lk(S->mu);
+    int32_t c = 0;
+    while (c < max && !S->done.empty()) {
+        SrvDone &r = S->done.front();
+        tickets[c] = r.ticket;
+        memcpy(ids + (size_t)c * S->k, r.ids.data(), sizeof(int32_t) * (size_t)S->k);
+        memcpy(dist + (size_t)c * S->k, r.dist.data(), sizeof(float) * (size_t)S->k);
+        if (latency_ms) latency_ms[c] = (float)r.lat_ms;
+        if (status) status[c] = r.status;
+        S->done.pop_front();
+        c++;
+    }
+    *n_done = c;
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_server_drain(caps_server *srv, double timeout_s) {
+    if (!srv) {
+        set_error("caps_server_drain: null server");
+        return CAPS_EINVAL;
+    }
+    Server *S = srv->s;
+    std::unique_lock<std::mutex> lk(S->mu);
+    const bool ok = S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                        [S] { return S->completed == S->submitted; });
+    if (!ok) {
+        set_error("caps_server_drain: %lld of %lld requests still open after %.1f s",
+                  (long long)(S->submitted - S->completed), (long long)S->submitted, timeout_s);
+        return CAPS_EBUSY;
+    }
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_server_stats(caps_server *srv, caps_server_stats_t *out, int32_t reset) {
+    if (!srv || !out) {
+        set_error("caps_server_stats: null argument");
+        return CAPS_EINVAL;
+    }
+    Server *S = srv->s;
+    std::lock_guard<std::mutex> lk(S->mu);
+    memset(out, 0, sizeof(*out));
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->rejected = S->rejected;
+    out->failed = S->failed;
+    out->batches = S->batches;
+    out->mean_batch = S->batches ? (double)S->batched / (double)S->batches : 0.0;
+    out->max_batch = S->cap;
+    if (!S->lat.empty()) {
+        std::vector<double> v = S->lat;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double f) {
+            const size_t i = (size_t)std::min<double>((double)v.size() - 1, floor(f * (double)(v.size() - 1) + 0.5));
+            return v[i];
+        };
+        double sum = 0.0;
+        for (double x : v) sum += x;
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        out->max_ms = v.back();
+        out->mean_ms = sum / (double)v.size();
+        const double span = std::chrono::duration<double>(S->t_last - S->t_first).count();
+        out->qps = span > 0 ? (double)S->completed / span : 0.0;
+    }
+    if (reset) {
+        S->submitted -= S->completed;
+        S->completed = S->rejected = S->failed = S->batches = S->batched = 0;
+        S->lat.clear();
+        S->have_first = false;
+    }
+    return CAPS_OK;
+}
+
+extern "C" void caps_server_destroy(caps_server *srv) {
+    if (!srv) return;
+    destroy(srv->s);
+    delete srv;
+}
