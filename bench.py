@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
     ap.add_argument("--target", type=float, default=0.9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rates", default="100000,250000,500000,750000",
+                    help="Poisson arrival rates (queries/s) for the serving sweep; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=0.4)
     ap.add_argument("--router-train", type=int, default=2_000_000,
                     help="training queries for the learned router (mode 'router')")
     ap.add_argument("--router-epochs", type=int, default=2)
@@ -257,6 +260,45 @@ def main():
         log("fp32 mode not timed: no JSON line")
         return
 
+    serving = []
+    if args.serve_rates and plain is not None:
+        # continuous batching under Poisson arrivals: exact mode at the same nprobe
+        qh, coh, cah, cvh = w.q, w.con_off, w.con_attr, w.con_val
+        srv = caps.Server(ix, k=k, nprobe=plain["nprobe"], mode=0, max_batch=4096, streams=2,
+                          max_constraints=8)
+        rng = np.random.default_rng(5)
+        for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+            n = int(rate * args.serve_seconds)
+            sel = np.arange(n) % w.n_q
+            co = np.concatenate([[0], np.cumsum(np.diff(coh)[sel])]).astype(np.int32)
+            ca = np.concatenate([cah[coh[i]:coh[i + 1]] for i in sel[:w.n_q]]).astype(np.int32)
+            cv = np.concatenate([cvh[coh[i]:coh[i + 1]] for i in sel[:w.n_q]]).astype(np.int32)
+            reps = (n + w.n_q - 1) // w.n_q
+            ca = np.tile(ca, reps)[:co[-1]]
+            cv = np.tile(cv, reps)[:co[-1]]
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+            srv.stats(reset=True)
+            tks = srv.replay(qh[sel], co, ca, cv, arrivals)
+            srv.drain(120.0)
+            st = srv.stats(reset=True)
+            found = {}
+            while True:
+                r = srv.poll()
+                if not len(r["tickets"]):
+                    break
+                for t, ids_ in zip(r["tickets"], r["ids"]):
+                    found[int(t)] = ids_
+            pos = {int(t): i for i, t in enumerate(tks) if t != 0}
+            got = np.stack([found[t] for t in pos])
+            qi = sel[np.array(list(pos.values()))]
+            rec = float(recall10(got, truth[qi], nvalid[qi]).mean())
+            row = {"offered_qps": rate, "achieved_qps": round(st["qps"], 1), "p50_ms": round(st["p50_ms"], 3),
+                   "p99_ms": round(st["p99_ms"], 3), "mean_batch": round(st["mean_batch"], 1),
+                   "requests": n, "rejected": st["rejected"], "recall@10": round(rec, 4)}
+            serving.append(row)
+            log(f"[serve] {row}")
+        srv.close()
+
     if args.calib_copy:
         # a plain streaming kernel of known traffic (reads 512 MiB, writes
         # 512 MiB) for scaling the TCC byte counters
@@ -299,6 +341,9 @@ def main():
             "queries_per_s": round(valu["qps"], 1), "nprobe": valu["nprobe"], "recall@10": valu["recall"],
             "ms_per_step": round(valu["ms_step"], 4), "stage_ms_per_step": valu["stage_ms"],
             "roofline": valu["roofline"]}
+    if serving:
+        out["serving"] = {"mode": "exact (mode 0)", "nprobe": plain["nprobe"], "max_batch": 4096, "streams": 2,
+                          "arrivals": "Poisson", "rates": serving}
     if routed is not None:
         out["modes"]["bf16_learned_router"] = {
             "queries_per_s": round(routed["qps"], 1), "nprobe": routed["nprobe"], "recall@10": routed["recall"],
