@@ -390,6 +390,18 @@ caps_status caps_server_stats(caps_server *srv, caps_server_stats_t *out, int32_
  * frees the server (NULL is a no-op).  Unpolled results are dropped. */
 void caps_server_destroy(caps_server *srv);
 
+/*
+ * Index files.  caps_save writes the index (arrays as they live in HBM, its
+ * low-precision copy and its router with the Adam state) to `path` as one
+ * versioned little-endian file; caps_load reads it into a new index on the
+ * current device (synchronous; `stream` is unused).  A loaded index answers
+ * every query exactly as the saved one.  Errors: EINVAL (null arguments),
+ * EIO (open/read/write failure, wrong magic or version, inconsistent
+ * contents), ENOMEM, EDEVICE.
+ */
+caps_status caps_save(const caps_index *idx, const char *path);
+caps_status caps_load(const char *path, void *stream, caps_index **out);
+
 /* Release the index and its device memory (NULL is a no-op). */
 void caps_free(caps_index *idx);
 

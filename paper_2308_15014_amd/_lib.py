@@ -107,6 +107,8 @@ SIGNATURES = {
     "caps_server_drain": (c_i32, [c_vp, ctypes.c_double]),
     "caps_server_stats": (c_i32, [c_vp, ctypes.POINTER(ServerStats), c_i32]),
     "caps_server_destroy": (None, [c_vp]),
+    "caps_save": (c_i32, [c_vp, ctypes.c_char_p]),
+    "caps_load": (c_i32, [ctypes.c_char_p, c_vp, ctypes.POINTER(c_vp)]),
     "caps_free": (None, [c_vp]),
     "caps_profile_enable": (c_i32, [c_i32]),
     "caps_profile_read": (c_i32, [ctypes.POINTER(Profile)]),

@@ -29,7 +29,7 @@ static caps_status fail(caps_status s, const char *fmt, ...) {
     return s;
 }
 
-static void release(Index &ix) {
+void release_index(Index &ix) {
     void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign, ix.level,
                     ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm, ix.lerr, ix.lnrm};
     for (void *p : ptrs)
@@ -138,7 +138,7 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
     if (s == CAPS_OK) s = build_lowp(&ix, (hipStream_t)stream);
     if (s == CAPS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) s = CAPS_EDEVICE;
     if (s != CAPS_OK) {
-        release(ix);
+        release_index(ix);
         delete h_idx;
         return s;
     }
@@ -239,6 +239,6 @@ extern "C" caps_status caps_index_export_lowp(const caps_index *idx, void *codes
 
 extern "C" void caps_free(caps_index *idx) {
     if (!idx) return;
-    release(idx->ix);
+    release_index(idx->ix);
     delete idx;
 }

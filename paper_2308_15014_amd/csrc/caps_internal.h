@@ -94,6 +94,8 @@ struct Router {
     uint16_t *w1h = nullptr, *w2h = nullptr;                   // BF16 copies for the products
 };
 void router_free(Router *r);
+// frees every device array of an index and resets it (caps_api.hip)
+void release_index(Index &ix);
 
 // signature bit (0..63) of a label: Fibonacci hashing of the label id
 __host__ __device__ inline uint32_t label_sig_bit(uint32_t l) {

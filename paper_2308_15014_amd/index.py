@@ -86,6 +86,18 @@ class Index:
         kw.update(over)
         return cls.build(w.x, w.dense, w.dense_vocab, w.label_off, w.labels, w.label_vocab, **kw)
 
+    def save(self, path: str):
+        check(lib().caps_save(self._h, str(path).encode()))
+
+    @classmethod
+    def load(cls, path: str, device=None) -> "Index":
+        torch = _torch()
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        out = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            check(lib().caps_load(str(path).encode(), None, ctypes.byref(out)))
+        return cls(out, device)
+
     # ------------------------------------------------------------ query
     def _qargs(self, q, con_off, con_attr, con_val):
         torch = _torch()

@@ -39,3 +39,16 @@ def test_binding_loads():
         pytest.skip("libcaps.so not built")
     L = _lib.lib()
     assert L.caps_last_error() is not None or True
+
+
+def test_load_refuses_missing_and_foreign_files(tmp_path):
+    """caps_load checks the file before touching the device."""
+    import ctypes
+    from paper_2308_15014_amd import _lib
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+    assert L.caps_load(str(tmp_path / "missing.caps").encode(), None, ctypes.byref(out)) == -6
+    p = tmp_path / "foreign.caps"
+    p.write_bytes(b"NOTCAPS!" + bytes(64))
+    assert L.caps_load(str(p).encode(), None, ctypes.byref(out)) == -6
+    assert not out.value
