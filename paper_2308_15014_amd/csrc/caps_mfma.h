@@ -45,7 +45,7 @@ constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting resco
 
 struct LowpLds {
     size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, total;
-    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, bool exact)
+    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, bool exact, bool labels)
         : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), total(0) {
         size_t o = 0;
         const auto take = [&o](size_t bytes) {
@@ -57,7 +57,7 @@ struct LowpLds {
         bcnt = take(sizeof(int32_t) * kLQB);
         tau = take(sizeof(uint64_t) * kLQB);
         qslot = take(sizeof(int32_t) * kLQB);
-        qd = take(sizeof(QDesc) * kLQB);
+        qd = take(labels ? sizeof(QDesc) * kLQB : 0);
         xw = take(sizeof(uint32_t) * kLCH);
         xn = take(sizeof(float) * kLCH);
         xsc = take(sizeof(float) * kLCH);
@@ -187,7 +187,7 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // Passing elements queue in a per-wave ring and are rescored exactly, 64 at
 // a time, and enter the buffers with their exact keys (distance, point id).
 template <int PREC, bool HAS_LABELS, int CB, int NS, bool EXACT>
-__global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void k_scan_mfma(LowpArgs A) {
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
     constexpr int ES = Op::ES;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
     constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row
     constexpr int PIECES = kLCH * V16;
     constexpr int UPT = (PIECES + kLNT - 1) / kLNT;      // pieces per thread per chunk
-    constexpr LowpLds L(ROWB, CB, EXACT);
+    constexpr LowpLds L(ROWB, CB, EXACT, HAS_LABELS);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t spo[kMaxHeight + 2];
     __shared__ uint32_t lvw[kLNW];
@@ -354,13 +354,19 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
     };
 
     // register staging of one chunk: UPT 16-byte pieces per thread, plus the
-    // per-point word / score term / scale held by the first 64 threads.  Rows
-    // past the level's end load the level's last row (in bounds); their
-    // columns are masked by a NaN score term.
+    // per-point word / score-term inputs / scale stored by the first 64
+    // threads.  Rows past the level's end load the level's last row (in
+    // bounds); their columns are masked by a NaN score term.  Only loads
+    // happen here: whatever consumes a loaded value runs after the next
+    // barrier (`point_term` and the LDS stores), so the loads stay in flight
+    // while the current chunk is scored.  `wsrc`: the packed words, or any
+    // array of n words when there are none (then unused).
+    const uint32_t *wsrc = has_dense ? A.words : reinterpret_cast<const uint32_t *>(A.xnorm);
     typedef uint32_t PreT __attribute__((ext_vector_type(4 * UPT)));   // stays in VGPRs
     PreT pre = {};
     uint32_t pre_w = 0;
-    float pre_n = qnan, pre_s = 1.0f;
+    float pre_x = 0.0f, pre_e = 0.0f, pre_l = 0.0f, pre_s = 1.0f;
+    bool pre_ok = false;
     auto fetch = [&](int32_t c0, int cn) {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.lvecs + (int64_t)c0 * ROWB);
 #pragma unroll
@@ -375,24 +381,34 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
                 pre[4 * u + 3] = v.w;
             }
         }
-        if (t < kLCH) {
-            const int row = c0 + min(t, cn - 1);
-            float pt;
-            if (EXACT) {
-                // lower-bound term: |x|^2 less twice the error-norm products
-                // and the margin (L2); minus the products and margin (IP)
-                const float nx = A.xnorm[row];
-                // (the product sum rounded in FP32, raised past its rounding)
-                const float slack = fmaf(A.lerr[row], qa, A.lnrm[row] * qb) * (1.0f + 0x1p-20f);
-                pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
-                if (!(fabsf(pt) < inf)) pt = -inf;   // no usable bound: always rescored
-            } else {
-                pt = l2 ? A.xnorm[row] : 0.0f;
-            }
-            pre_w = has_dense ? A.words[row] : 0u;
-            pre_n = t < cn ? pt : qnan;
-            if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
+        // every thread loads (only the first 64 store): no load is skipped on
+        // any path, so the compiler can count the loads in flight exactly
+        const int pt_row = min(t & (kLCH - 1), cn - 1);
+        const int row = c0 + pt_row;
+        pre_x = A.xnorm[row];
+        if (EXACT) {
+            pre_e = A.lerr[row];
+            pre_l = A.lnrm[row];
         }
+        pre_w = wsrc[row];
+        if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
+        pre_ok = t < cn;
+    };
+    // per-point term of the staged row (NaN for a padding row)
+    auto point_term = [&]() {
+        float pt;
+        if (EXACT) {
+            // lower-bound term: |x|^2 less twice the error-norm products and
+            // the margin (L2); minus the products and margin (IP)
+            const float nx = pre_x;
+            // (the product sum rounded in FP32, raised past its rounding)
+            const float slack = fmaf(pre_e, qa, pre_l * qb) * (1.0f + 0x1p-20f);
+            pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
+            if (!(fabsf(pt) < inf)) pt = -inf;   // no usable bound: always rescored
+        } else {
+            pt = l2 ? pre_x : 0.0f;
+        }
+        return pre_ok ? pt : qnan;
     };
 
     // exact: rescoring of queued pairs, one per lane
@@ -433,19 +449,25 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
                     make_uint4(pre[4 * u], pre[4 * u + 1], pre[4 * u + 2], pre[4 * u + 3]);
         }
         if (t < kLCH) {
-            xw[t] = pre_w;
-            xn[t] = pre_n;
+            xw[t] = has_dense ? pre_w : 0u;
+            xn[t] = point_term();
             xsc[t] = pre_s;
         }
+        // the shared bounds are read before the next chunk's loads are issued
+        // and used after them, so that their latency overlaps too
+        // (every lane loads every chunk and the last chunk fetches itself
+        // again, for the same reason as in `fetch`)
         const bool refresh = (++nchunk % kTauRefresh) == 0;
-        if (refresh && lane < kLQPW && my_qq >= 0) {
-            const uint64_t gt = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (gt < tau[qbase + lane]) tau[qbase + lane] = gt;
-        }
+        const uint64_t gt = __hip_atomic_load(A.tau + max(my_qq, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         advance(cj, cc0, cend);
-        if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
+        const bool more = cj <= h;
+        fetch(more ? cc0 : c0, more ? min(kLCH, cend - cc0) : cn);
         __syncthreads();
-        if (refresh) refresh_bounds();
+        if (refresh) {
+            if (lane < kLQPW && my_qq >= 0 && gt < tau[qbase + lane]) tau[qbase + lane] = gt;
+            wave_sync();   // the wave's own bound slots, read below
+            refresh_bounds();
+        }
 
         // ---- MFMA: my 16 queries x the chunk's 64 points
         f32x4 acc[4];
@@ -576,11 +598,15 @@ __global__ __launch_bounds__(kLNT) void k_scan_mfma(LowpArgs A) {
 
 typedef void (*LowpFn)(LowpArgs);
 
-inline int lowp_cb(int r) { return r <= 48 ? 64 : 128; }
+// Buffer capacity per query: r plus room to append before a reduction.  The
+// smaller buffers of small r let three workgroups share a compute unit's LDS.
+inline int lowp_cb(int r) { return r <= 16 ? 32 : r <= 48 ? 64 : 128; }
 
 template <int PREC, bool LAB, int NS, bool EX>
 LowpFn pick_cb(int r) {
-    if (lowp_cb(r) == 64) return k_scan_mfma<PREC, LAB, 64, NS, EX>;
+    const int cb = lowp_cb(r);
+    if (cb == 32) return k_scan_mfma<PREC, LAB, 32, NS, EX>;
+    if (cb == 64) return k_scan_mfma<PREC, LAB, 64, NS, EX>;
     return k_scan_mfma<PREC, LAB, 128, NS, EX>;
 }
 
