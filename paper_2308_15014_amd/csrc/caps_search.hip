@@ -373,33 +373,36 @@ struct ScanLds {
 };
 
 // Issues the global loads of one chunk (rows c0.. of sub-partition j) into
-// registers; they land in LDS after the next workgroup barrier.
-template <bool VEC4, bool HAS_LABELS, int XPT, int NT>
+// registers; they land in LDS after the next workgroup barrier.  Every load
+// is issued on every path (rows past the chunk's end load its last row, every
+// thread loads its point's id and word, `wsrc` stands in for absent words),
+// so the compiler counts the loads in flight exactly and nothing waits for
+// them before their consumers at the top of the next chunk.
+template <int XU, bool HAS_LABELS, int NT>
 __device__ __attribute__((always_inline)) inline void fetch_chunk(
-    const ScanArgs &A, const int32_t *po, int j, int32_t c0, int d, int t, bool has_dense,
-    const int (&prow)[VEC4 ? XPT : 1], float __attribute__((ext_vector_type(4 * XPT))) & px, int32_t &pid,
-    uint32_t &pw, uint64_t &psig, uint4 &pslot) {
+    const ScanArgs &A, const int32_t *po, int j, int32_t c0, int d, int t, const uint32_t *wsrc,
+    const int (&prow)[XU ? XU : 1], const int (&pcol)[XU ? XU : 1],
+    float __attribute__((ext_vector_type(4 * (XU ? XU : 1)))) & px, int32_t &pid, uint32_t &pw, uint64_t &psig,
+    uint4 &pslot) {
     const int cn = min(kCH, po[j + 1] - c0);
-    if (VEC4) {
+    if (XU) {
+        const int d4 = d >> 2;
         const float4 *src = reinterpret_cast<const float4 *>(A.vecs + (int64_t)c0 * d);
 #pragma unroll
-        for (int u = 0; u < XPT; u++) {
-            if (prow[u] < cn) {
-                const float4 v = src[t + u * NT];
-                px[4 * u + 0] = v.x;
-                px[4 * u + 1] = v.y;
-                px[4 * u + 2] = v.z;
-                px[4 * u + 3] = v.w;
-            }
+        for (int u = 0; u < XU; u++) {
+            const float4 v = src[min(prow[u], cn - 1) * d4 + pcol[u]];
+            px[4 * u + 0] = v.x;
+            px[4 * u + 1] = v.y;
+            px[4 * u + 2] = v.z;
+            px[4 * u + 3] = v.w;
         }
     }
-    if (t < cn) {
-        pid = A.perm[c0 + t];
-        if (has_dense) pw = A.words[c0 + t];
-        if (HAS_LABELS) {
-            psig = A.sigs[c0 + t];
-            pslot = *reinterpret_cast<const uint4 *>(A.slots + (int64_t)(c0 + t) * kMaxLabels);
-        }
+    const int32_t r = c0 + min(t & (kCH - 1), cn - 1);
+    pid = A.perm[r];
+    pw = wsrc[r];
+    if (HAS_LABELS) {
+        psig = A.sigs[r];
+        pslot = *reinterpret_cast<const uint4 *>(A.slots + (int64_t)r * kMaxLabels);
     }
 }
 
@@ -414,12 +417,15 @@ __device__ __attribute__((always_inline)) inline void fetch_chunk(
 // threshold: the smaller of the tile's own k-th key and the shared bound
 // published by finished tiles (any k valid points bound the final k-th key
 // from above, so no member of the exact top-k is ever dropped).
-template <int METRIC, bool HAS_LABELS, bool VEC4, int KMAX, int NW>
+//
+// XU: float4 loads per thread and chunk (XU * NT >= 64 * d / 4), or 0 for
+// rows whose length is not a multiple of 4 (scalar staging).
+template <int METRIC, bool HAS_LABELS, int XU, int KMAX, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scan_fp32(ScanArgs A) {
+    constexpr bool VEC4 = XU > 0;
     constexpr int QB = NW * kQPW;
     constexpr int NT = NW * 64;
     constexpr int C = 2 * KMAX;
-    constexpr int XPT = (kCH * 64 + NT - 1) / NT;   // float4 of a chunk per thread (d <= 256)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t lvmask_w[NW];
     __shared__ int32_t spo[kMaxHeight + 2];
@@ -514,21 +520,23 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     }
     // register prefetch of one chunk: float4 number e of a chunk is row
     // e / d4 (rows are contiguous in the CSR vectors)
-    float __attribute__((ext_vector_type(4 * XPT))) px = {};
-    int prow[VEC4 ? XPT : 1], plds[VEC4 ? XPT : 1];
+    float __attribute__((ext_vector_type(4 * (XU ? XU : 1)))) px = {};
+    int prow[XU ? XU : 1], pcol[XU ? XU : 1], plds[XU ? XU : 1];
     if (VEC4) {
 #pragma unroll
-        for (int u = 0; u < XPT; u++) {
+        for (int u = 0; u < XU; u++) {
             const int e = t + u * NT;
             prow[u] = e / d4;
-            plds[u] = prow[u] * stride + 4 * (e - prow[u] * d4);
+            pcol[u] = e - prow[u] * d4;
+            plds[u] = prow[u] * stride + 4 * pcol[u];
         }
     }
+    const uint32_t *wsrc = has_dense ? A.words : reinterpret_cast<const uint32_t *>(A.perm);
     int32_t pid = 0;
     uint32_t pw = 0;
     uint64_t psig = 0;
     uint4 pslot = make_uint4(0, 0, 0, 0);
-    if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
+    if (cj <= h) fetch_chunk<XU, HAS_LABELS, NT>(A, po, cj, cc0, d, t, wsrc, prow, pcol, px, pid, pw, psig, pslot);
 
     uint64_t g_next = ~0ull;
     while (cj <= h) {
@@ -538,7 +546,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
         __syncthreads();   // the previous chunk is no longer read
         if (VEC4) {
 #pragma unroll
-            for (int u = 0; u < XPT; u++)
+            for (int u = 0; u < XU; u++)
                 if (prow[u] < cn)
                     *reinterpret_cast<float4 *>(Xs + plds[u]) =
                         make_float4(px[4 * u], px[4 * u + 1], px[4 * u + 2], px[4 * u + 3]);
@@ -550,20 +558,21 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
         }
         if (t < cn) {
             xid[t] = pid;
-            xw[t] = pw;
+            xw[t] = has_dense ? pw : 0u;
             if (HAS_LABELS) {
                 xsig[t] = psig;
                 *reinterpret_cast<uint4 *>(xslot + t * kMaxLabels) = pslot;
             }
         }
         advance(cj, cc0);
-        if (cj <= h) fetch_chunk<VEC4, HAS_LABELS, XPT, NT>(A, po, cj, cc0, d, t, has_dense, prow, px, pid, pw, psig, pslot);
+        // (the last chunk fetches itself again: the loads are unconditional)
+        const bool more = cj <= h;
+        fetch_chunk<XU, HAS_LABELS, NT>(A, po, more ? cj : j, more ? cc0 : c0, d, t, wsrc, prow, pcol, px, pid, pw,
+                                        psig, pslot);
         // refresh the shared bounds of my queries with the value loaded one
         // chunk ago, and start the next load (its latency overlaps a chunk)
-        if (my_qq >= 0) {
-            if (g_next < tau[qbase + lane]) tau[qbase + lane] = g_next;
-            g_next = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (my_qq >= 0 && g_next < tau[qbase + lane]) tau[qbase + lane] = g_next;
+        g_next = __hip_atomic_load(A.tau + max(my_qq, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
 
         // ---- wave-local: filter my queries against the chunk
@@ -768,20 +777,30 @@ __global__ void k_copy_i32(const int32_t *__restrict__ a, int32_t *__restrict__ 
 // ------------------------------------------------------------------ host
 typedef void (*ScanFn)(ScanArgs);
 
-template <int METRIC, bool LAB, bool V4>
-static ScanFn pick_k(int k) {
-    if (k <= 16) return k_scan_fp32<METRIC, LAB, V4, 16, 8>;
-    return k_scan_fp32<METRIC, LAB, V4, 64, 4>;
+// Float4 loads per thread for a chunk of 64 rows of d coordinates: half the
+// d = 256 count when d <= 128, else the full count; 0 = scalar staging.
+static int scan_xu(int d, int k) {
+    if (d % 4 != 0 || d > 256) return 0;
+    const int full = 64 * 64 / (scan_waves(k) * 64);
+    return d <= 128 ? full / 2 : full;
 }
 
 template <int METRIC, bool LAB>
-static ScanFn pick_v(bool v4, int k) {
-    return v4 ? pick_k<METRIC, LAB, true>(k) : pick_k<METRIC, LAB, false>(k);
+static ScanFn pick_xu(int xu, int k) {
+    if (k <= 16) {   // 8 waves: 8 float4 per thread at d = 256
+        if (xu == 4) return k_scan_fp32<METRIC, LAB, 4, 16, 8>;
+        if (xu == 8) return k_scan_fp32<METRIC, LAB, 8, 16, 8>;
+        return k_scan_fp32<METRIC, LAB, 0, 16, 8>;
+    }
+    if (xu == 8) return k_scan_fp32<METRIC, LAB, 8, 64, 4>;   // 4 waves: 16 at d = 256
+    if (xu == 16) return k_scan_fp32<METRIC, LAB, 16, 64, 4>;
+    return k_scan_fp32<METRIC, LAB, 0, 64, 4>;
 }
 
-static ScanFn pick_scan(int metric, bool labels, bool v4, int k) {
-    if (metric == 0) return labels ? pick_v<0, true>(v4, k) : pick_v<0, false>(v4, k);
-    return labels ? pick_v<1, true>(v4, k) : pick_v<1, false>(v4, k);
+static ScanFn pick_scan(int metric, bool labels, int d, int k) {
+    const int xu = scan_xu(d, k);
+    if (metric == 0) return labels ? pick_xu<0, true>(xu, k) : pick_xu<0, false>(xu, k);
+    return labels ? pick_xu<1, true>(xu, k) : pick_xu<1, false>(xu, k);
 }
 
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -939,7 +958,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     const bool has_labels = ix->sch.label_vocab > 0;
     const size_t lds = mfma ? lowp_scan_lds(ix, r, !lowp) : scan_lds_bytes(d, k);
     const int qb = mfma ? lowp_qb() : scan_waves(k) * kQPW;
-    const ScanFn scan_fn = pick_scan(ix->metric, has_labels, (d % 4) == 0 && d <= 256, k);
+    const ScanFn scan_fn = pick_scan(ix->metric, has_labels, d, k);
     if (!probes_only && !mfma) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
