@@ -148,6 +148,8 @@ struct LowpScan {
     float *qscale, *qaux;
     uint64_t *partials, *tau;
     int32_t *pcnt, *nsurv;
+    int32_t *dpos, *dcnt;         // exact keys: deferred pairs per query (null: rescored in the scan)
+    int32_t dcap;                 // capacity of each query's deferred list
 };
 size_t lowp_scan_lds(const Index *ix, int r, bool exact);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);

@@ -31,7 +31,8 @@ struct LowpArgs {
     int32_t *pcnt;              // approximate: keys written per (query, probe)
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
-    int32_t m, h, b, r, metric, d;
+    int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count, or null
+    int32_t m, h, b, r, metric, d, dcap;
     float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
 };
 
@@ -44,9 +45,10 @@ constexpr int kTauRefresh = 8;   // chunks between reads of the shared per-query
 constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting rescoring
 
 struct LowpLds {
-    size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, total;
+    size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, dhist, qnq, scnt, total;
     __host__ __device__ constexpr LowpLds(int row_bytes, int cb, bool exact, bool labels)
-        : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), total(0) {
+        : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), dhist(0), qnq(0), scnt(0),
+          total(0) {
         size_t o = 0;
         const auto take = [&o](size_t bytes) {
             o = (o + 15) & ~(size_t)15;
@@ -62,6 +64,9 @@ struct LowpLds {
         xn = take(sizeof(float) * kLCH);
         xsc = take(sizeof(float) * kLCH);
         ring = take(exact ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
+        dhist = take(exact ? sizeof(int32_t) * kLNW * kLQPW : 0);
+        qnq = take(exact ? sizeof(float) * kLQB : 0);
+        scnt = take(sizeof(int32_t) * kLQB);
         buf = take(sizeof(uint64_t) * (size_t)kLQB * cb);
         xl = take((size_t)kLCH * (row_bytes + 16));
         total = take(16);
@@ -134,28 +139,45 @@ __device__ inline float bound_score(uint64_t t) {
 
 // Exact FP32 score of one pair: the sequential fma over ascending
 // coordinates of the plain scan (L2: sum (x_j - q_j)^2; IP: -sum x_j q_j).
+// Rows of a multiple of 4 go in batches of XB float4 loads per row, all
+// issued before the batch is summed, so one pair costs d / (4 XB) memory
+// round trips instead of d / 4; the summation order is unchanged.
+template <int XB>
 __device__ inline float exact_score(const float *__restrict__ xr, const float *__restrict__ qr, int d, bool l2) {
     float acc = 0.0f;
-    if ((d & 3) == 0) {
-        for (int j = 0; j < d; j += 4) {
-            const float4 xv = *reinterpret_cast<const float4 *>(xr + j);
-            const float4 qv = *reinterpret_cast<const float4 *>(qr + j);
-            if (l2) {
-                float t0 = xv.x - qv.x;
-                acc = fmaf(t0, t0, acc);
-                t0 = xv.y - qv.y;
-                acc = fmaf(t0, t0, acc);
-                t0 = xv.z - qv.z;
-                acc = fmaf(t0, t0, acc);
-                t0 = xv.w - qv.w;
-                acc = fmaf(t0, t0, acc);
-            } else {
-                acc = fmaf(xv.x, qv.x, acc);
-                acc = fmaf(xv.y, qv.y, acc);
-                acc = fmaf(xv.z, qv.z, acc);
-                acc = fmaf(xv.w, qv.w, acc);
-            }
+    auto add4 = [&](const float4 xv, const float4 qv) {
+        if (l2) {
+            float t0 = xv.x - qv.x;
+            acc = fmaf(t0, t0, acc);
+            t0 = xv.y - qv.y;
+            acc = fmaf(t0, t0, acc);
+            t0 = xv.z - qv.z;
+            acc = fmaf(t0, t0, acc);
+            t0 = xv.w - qv.w;
+            acc = fmaf(t0, t0, acc);
+        } else {
+            acc = fmaf(xv.x, qv.x, acc);
+            acc = fmaf(xv.y, qv.y, acc);
+            acc = fmaf(xv.z, qv.z, acc);
+            acc = fmaf(xv.w, qv.w, acc);
         }
+    };
+    if ((d & 3) == 0) {
+        const float4 *x4 = reinterpret_cast<const float4 *>(xr);
+        const float4 *q4 = reinterpret_cast<const float4 *>(qr);
+        const int d4 = d >> 2;
+        int j = 0;
+        for (; j + XB <= d4; j += XB) {
+            float4 xv[XB], qv[XB];
+#pragma unroll
+            for (int u = 0; u < XB; u++) {
+                xv[u] = x4[j + u];
+                qv[u] = q4[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < XB; u++) add4(xv[u], qv[u]);
+        }
+        for (; j < d4; j++) add4(x4[j], q4[j]);
     } else {
         for (int j = 0; j < d; j++) {
             if (l2) {
@@ -184,10 +206,17 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // error norms against the tile's largest query norms and a relative margin,
 // the per-row bound is the query's k-th exact key raised by the margin, so
 // that an element fails only if its exact FP32 key is above the bound.
-// Passing elements queue in a per-wave ring and are rescored exactly, 64 at
-// a time, and enter the buffers with their exact keys (distance, point id).
+// Passing elements queue in a per-wave ring.  Taken 64 at a time, they are
+// rescored exactly and enter the buffers with their exact keys (distance,
+// point id); or, when the launch has deferred lists (later probes, whose
+// bounds rarely tighten within a tile), they are appended to their queries'
+// lists in global memory and rescored by the merge, which overlaps many
+// more of the row reads than one tile can.
+// Three workgroups per compute unit (at most 168 VGPRs) up to 128-element
+// rows without label tests, two otherwise (their state does not fit).
 template <int PREC, bool HAS_LABELS, int CB, int NS, bool EXACT>
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void k_scan_mfma(LowpArgs A) {
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS ? 2 : 3))) void k_scan_mfma(
+    LowpArgs A) {
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
     constexpr int ES = Op::ES;
@@ -231,6 +260,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
     const int qbase = w * kLQPW;
     uint32_t *ring_pos = reinterpret_cast<uint32_t *>(smem + L.ring) + w * 2 * kVRing;
     uint32_t *ring_row = ring_pos + kVRing;
+    int32_t *dhist = reinterpret_cast<int32_t *>(smem + L.dhist) + w * kLQPW;
+    float *qnq = reinterpret_cast<float *>(smem + L.qnq);          // exact: |q|^2 per query
+    int32_t *scnt = reinterpret_cast<int32_t *>(smem + L.scnt);    // survivors per query (counted runs)
     const bool has_dense = A.words != nullptr;
     const bool l2 = A.metric == 0;
     const bool count = A.nsurv != nullptr;
@@ -250,7 +282,11 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
         if (HAS_LABELS) qds[qi] = A.qd[my_qq];
         tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (lane < kLQPW) bcnt[qbase + lane] = 0;   // rows without a query too
+    if (lane < kLQPW) {   // rows without a query too
+        bcnt[qbase + lane] = 0;
+        scnt[qbase + lane] = 0;
+        if (EXACT) qnq[qbase + lane] = my_qq >= 0 ? A.qaux[4 * (int64_t)my_qq + 1] : 0.0f;
+    }
     {
         uint32_t wor = my_sel;
 #pragma unroll
@@ -270,14 +306,12 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
     // per-lane epilogue rows: (lane/16)*4 + rr of the wave's 16 queries
     const int g = lane >> 4;
     uint32_t rsel[4], rmask[4], rval[4];
-    float rqs[4], rtf[4], rnq[4];
-    int rsurv[4] = {0, 0, 0, 0};
+    float rqs[4], rtf[4];
     float qa = 0.0f, qb = 0.0f;   // exact: largest |q| and |q - q~| + gam |q~| of my rows
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int qi = qbase + g * 4 + rr;
         rsel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
-        rnq[rr] = 0.0f;
         if (qi < nqt) {
             const int32_t qq = ent[qi] / A.m;
             const QDesc qd = A.qd[qq];
@@ -286,7 +320,6 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
             rqs[rr] = PREC == CAPS_PREC_FP8 ? A.qscale[qq] : 1.0f;
             if (EXACT) {
                 const float4 ax = *reinterpret_cast<const float4 *>(A.qaux + 4 * (int64_t)qq);
-                rnq[rr] = ax.y;
                 qa = fmaxf(qa, ax.x);
                 qb = fmaxf(qb, fmaf(A.gam, ax.w, ax.z));
             }
@@ -329,7 +362,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
             const int qi = qbase + g * 4 + rr;
-            rtf[rr] = qi < nqt ? row_bound(tau[qi], rnq[rr]) : qnan;
+            rtf[rr] = qi < nqt ? row_bound(tau[qi], EXACT ? qnq[qi] : 0.0f) : qnan;
         }
     };
     refresh_bounds();
@@ -411,23 +444,48 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
         return pre_ok ? pt : qnan;
     };
 
-    // exact: rescoring of queued pairs, one per lane
+    // exact: rescoring of queued pairs, one per lane (lanes with v set)
     int vhead = 0, vtail = 0;   // wave-uniform ring cursors
-    auto verify = [&](int n) {
+    auto rescore = [&](bool v, uint32_t pos, int qi) {
+        if (!__builtin_amdgcn_ballot_w64(v)) return;
+        uint64_t key = ~0ull;
+        if (v) {
+            const int32_t qq = qslot[qi] / A.m;
+            const float sc = exact_score<(HAS_LABELS && NS < 8) ? 2 : 4>(A.vecs + (int64_t)pos * A.d,
+                                                                         A.q + (int64_t)qq * A.d, A.d, l2);
+            key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)A.perm[pos];
+        }
+        const bool qual = v && key < tau[qi];
+        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+    };
+    // takes the next n queued pairs: with deferred lists, appends them to
+    // their queries' lists (one atomic per query) and rescores here only
+    // what no longer fits; otherwise rescores them all here
+    auto drain = [&](int n) {
         wave_sync();   // ring entries written by this wave are visible
         const bool v = lane < n;
         const int slot = (vtail + lane) & (kVRing - 1);
         const uint32_t pos = v ? ring_pos[slot] : 0u;
         const int qi = v ? (int)ring_row[slot] : qbase;
-        uint64_t key = ~0ull;
-        if (v) {
-            const int32_t qq = qslot[qi] / A.m;
-            const float sc = exact_score(A.vecs + (int64_t)pos * A.d, A.q + (int64_t)qq * A.d, A.d, l2);
-            key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)A.perm[pos];
-        }
-        const bool qual = v && key < tau[qi];
-        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
         vtail += n;
+        bool here = v;
+        if (A.dpos) {
+            // per-row counts in LDS: each pair's slot among its row's pairs,
+            // then one global atomic per row for the list offset
+            const int ri = qi - qbase;   // row of the wave, 0..15
+            if (lane < kLQPW) dhist[lane] = 0;
+            wave_sync();
+            const int rank = v ? atomicAdd(dhist + ri, 1) : 0;
+            wave_sync();
+            const int cnt = lane < kLQPW ? dhist[lane] : 0;
+            int base = 0;
+            if (cnt > 0) base = atomicAdd(A.dcnt + my_qq, cnt);
+            const int at = __shfl(base, ri, 64) + rank;
+            const bool fits = v && at < A.dcap;
+            if (fits) A.dpos[(int64_t)(qslot[qi] / A.m) * A.dcap + at] = (int32_t)pos;
+            here = v && !fits;
+        }
+        rescore(here, pos, qi);
     };
 
     int cj = -1;
@@ -510,7 +568,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
                         ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
                                           A.slots + (int64_t)(c0 + pi) * kMaxLabels);
                     }
-                    rsurv[rr] += ok ? 1 : 0;
+                    if (ok) atomicAdd(scnt + qbase + g * 4 + rr, 1);
                 }
             }
             if (hit[0] | hit[1] | hit[2] | hit[3]) {
@@ -534,7 +592,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
                         }
                         vhead += __popcll(qm);
                         if (vhead - vtail >= 64) {
-                            verify(64);
+                            drain(64);
                             moved = true;
                         }
                         continue;
@@ -564,17 +622,11 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(3))) void 
             }
         }
     }
-    if (EXACT && vhead > vtail) verify(vhead - vtail);
-    // ---- survivors per query: sum over the 16 lanes that share a row group
+    if (EXACT && vhead > vtail) drain(vhead - vtail);
+    // ---- survivors per query
     if (count) {
-#pragma unroll
-        for (int rr = 0; rr < 4; rr++) {
-            int v = rsurv[rr];
-#pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-            const int qi = qbase + g * 4 + rr;
-            if ((lane & 15) == 0 && qi < nqt && v) atomicAdd(&A.nsurv[qslot[qi] / A.m], v);
-        }
+        wave_sync();
+        if (lane < kLQPW && my_qq >= 0 && scnt[qbase + lane]) atomicAdd(&A.nsurv[my_qq], scnt[qbase + lane]);
     }
     // ---- finalize my queries: best r sorted, partial list, shared bound
     for (int i = 0; i < kLQPW; i++) {

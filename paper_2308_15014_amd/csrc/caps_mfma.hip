@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_merge_rerank(const uint64_t *__restrict
     uint64_t key2 = ~0ull;
     if (lane < nr) {
         const int32_t pos = (int32_t)(uint32_t)(pool[lane] & 0xFFFFFFFFu);
-        const float kf = exact_score(vecs + (int64_t)pos * d, q + (int64_t)qq * d, d, METRIC == 0);
+        const float kf = exact_score<8>(vecs + (int64_t)pos * d, q + (int64_t)qq * d, d, METRIC == 0);
         key2 = ((uint64_t)f2ord(kf) << 32) | (uint32_t)perm[pos];
     }
     int rank = 0;
@@ -269,6 +269,9 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.pcnt = S.pcnt;
     A.tau = S.tau;
     A.nsurv = S.nsurv;
+    A.dpos = S.dpos;
+    A.dcnt = S.dcnt;
+    A.dcap = S.dcap;
     A.m = S.m;
     A.h = ix->h;
     A.b = ix->b;

@@ -21,6 +21,7 @@
 
 #include "caps_device.h"
 #include "caps_internal.h"
+#include "caps_mfma.h"
 
 namespace caps {
 
@@ -706,18 +707,44 @@ static size_t scan_lds_bytes(int d, int k) {
 }
 
 // ------------------------------------------------------------------ merge
+// Deferred pairs of the exact matrix-core scan: CSR positions per query,
+// rescored here with the plain scan's arithmetic.
+struct Deferred {
+    const int32_t *pos, *cnt;   // null: none
+    int32_t cap, d;
+    const float *vecs, *q;      // FP32 CSR rows, the sub-batch's queries
+    const int32_t *perm;
+};
+
 template <int KM>
 __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ partials,
                                                const uint32_t *__restrict__ sel, const int32_t *__restrict__ cand,
                                                int32_t nq, int32_t m, int32_t k, int32_t metric,
                                                int32_t *__restrict__ ids, float *__restrict__ dist,
-                                               int32_t *__restrict__ ncand) {
+                                               int32_t *__restrict__ ncand, Deferred D) {
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= nq) return;
     uint64_t lst[KM];
 #pragma unroll
     for (int i = 0; i < KM; i++) lst[i] = ~0ull;
+    auto insert = [&](uint64_t key) {
+#pragma unroll
+        for (int u = KM - 1; u > 0; u--) {
+            const uint64_t a = lst[u - 1];
+            lst[u] = key < a ? a : (key < lst[u] ? key : lst[u]);
+        }
+        lst[0] = key < lst[0] ? key : lst[0];
+    };
+    if (D.pos) {
+        const int n = min(D.cnt[q], D.cap);
+        const float *qr = D.q + (int64_t)q * D.d;
+        for (int i = lane; i < n; i += 64) {
+            const int32_t pos = D.pos[(int64_t)q * D.cap + i];
+            const float sc = exact_score<8>(D.vecs + (int64_t)pos * D.d, qr, D.d, metric == 0);
+            insert(((uint64_t)f2ord(sc) << 32) | (uint32_t)D.perm[pos]);
+        }
+    }
     int nc = 0;
     for (int r = lane; r < m; r += 64) {
         const int64_t slot = (int64_t)q * m + r;
@@ -727,12 +754,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
         for (int i = 0; i < k; i++) {
             const uint64_t key = src[i];
             if (key >= lst[KM - 1]) break;   // lists are sorted: the rest is worse
-#pragma unroll
-            for (int u = KM - 1; u > 0; u--) {
-                const uint64_t a = lst[u - 1];
-                lst[u] = key < a ? a : (key < lst[u] ? key : lst[u]);
-            }
-            lst[0] = key < lst[0] ? key : lst[0];
+            insert(key);
         }
     }
 #pragma unroll
@@ -838,14 +860,19 @@ struct SearchWs {
     uint32_t *sel;
     int32_t *cand, *entries;
     uint64_t *partials, *tau;
+    int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
     float *conf;                // learned routing: softmax top-1 probability
     int32_t *probes_c;          // learned routing: centroid probes for the fallback
 };
 
+// Deferred pairs kept per query by the exact matrix-core scan (more are
+// rescored inside the scan).
+constexpr int32_t kDeferCap = 512;
+
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
-                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router) {
+                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router, bool defer) {
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
     w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
     w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
@@ -861,6 +888,8 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.entries = ar.take<int32_t>((size_t)sb * m);
     w.partials = ar.take<uint64_t>((size_t)sb * m * k);
     w.tau = ar.take<uint64_t>((size_t)sb);
+    w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
+    w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.htotal = ar.take<int32_t>(1);
@@ -876,7 +905,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
 // Shape of one search call: which scan, keys per (query, probe), the
 // sub-batch that keeps the workspace near 1 GiB.
 struct SearchPlan {
-    bool lowp, mfma;
+    bool lowp, mfma, defer;
     int32_t r, sb;
     size_t qlow_row;
     const Router *router;
@@ -891,12 +920,14 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
     // otherwise (or mode 2) the plain FP32 scan
     P.lowp = sp->mode == 1;
     P.mfma = P.lowp || (sp->mode == 0 && ix->prec != CAPS_PREC_NONE);
+    P.defer = P.mfma && !P.lowp;
     P.r = P.lowp ? (sp->rerank > 0 ? sp->rerank : std::min(4 * k, kMaxK)) : k;
     P.router = sp->routing == 1 ? ix->router : nullptr;
     P.qlow_row = P.mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
     const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
                          sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
                          2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
+                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 1) : 0) +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
@@ -909,7 +940,7 @@ size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int
     const SearchPlan P = plan_search(ix, sp, nq);
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router);
+    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router, P.defer);
     return measure.off;
 }
 
@@ -930,11 +961,11 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
 
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router);
+    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer);
     Arena ar;
     ar.cap = measure.off;
     CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
-    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router);
+    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer);
     if (ar.overflow) {
         (void)hipFreeAsync(ar.base, st);
         set_error("caps_search: internal workspace layout error");
@@ -1021,6 +1052,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             continue;
         }
         hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
+        if (P.defer) hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
         prof_end(CAPS_STAGE_SELECT, st);
         // Two rounds: the first probes of every query (best first) give each
         // query a tight seed bound on its final r-th key; the remaining probes
@@ -1066,6 +1098,12 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.tau = tau;
                 S.pcnt = W.pcnt;
                 S.nsurv = out_nsurv ? nsurv + q0 : nullptr;   // counted only when asked for
+                // the seed round rescores in the scan (its bounds tighten
+                // as it goes); the later probes defer their pairs
+                const bool defer_now = P.defer && round == 1;
+                S.dpos = defer_now ? W.dpos : nullptr;
+                S.dcnt = defer_now ? W.dcnt : nullptr;
+                S.dcap = kDeferCap;
                 const caps_status ls = lowp_scan(ix, S, st);
                 if (ls != CAPS_OK) return ls;
             } else {
@@ -1114,15 +1152,25 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         prof_begin(CAPS_STAGE_MERGE, st);
         int32_t *oi = out_ids + (int64_t)q0 * k;
         float *od = out_dist + (int64_t)q0 * k;
+        Deferred D{};
+        if (P.defer) {
+            D.pos = W.dpos;
+            D.cnt = W.dcnt;
+            D.cap = kDeferCap;
+            D.d = d;
+            D.vecs = ix->vecs;
+            D.q = q + (int64_t)q0 * d;
+            D.perm = ix->perm;
+        }
         if (k <= 16)
             hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0);
+                               ix->metric, oi, od, ncand + q0, D);
         else if (k <= 32)
             hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0);
+                               ix->metric, oi, od, ncand + q0, D);
         else
             hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0);
+                               ix->metric, oi, od, ncand + q0, D);
         prof_end(CAPS_STAGE_MERGE, st);
         CAPS_HIP(hipGetLastError());
     }

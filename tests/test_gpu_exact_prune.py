@@ -109,6 +109,50 @@ def test_exact_prune_integer_corpus(caps, orc):
         _check(orc, oi, ix, w.q, w.con_off, w.con_attr, w.con_val, 10, m)
 
 
+def _shell(c):
+    """Integer points at squared distance exactly 25 from c: c +- 5 e_i and
+    c + (+-3 e_i +- 4 e_j), c + (+-4 e_i +- 3 e_j) for i < j."""
+    d = len(c)
+    out = []
+    for i in range(d):
+        for s in (-5, 5):
+            v = c.copy()
+            v[i] += s
+            out.append(v)
+    for i in range(d):
+        for j in range(i + 1, d):
+            for a, b in ((3, 4), (4, 3)):
+                for sa in (-1, 1):
+                    for sb in (-1, 1):
+                        v = c.copy()
+                        v[i] += sa * a
+                        v[j] += sb * b
+                        out.append(v)
+    return np.array(out, np.float32)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_exact_prune_equidistant_shell(caps, orc, prec):
+    """Four thousand points at exactly the same distance from most queries,
+    spread over many partitions: the later probes find far more pairs that
+    tie with the seed bound than a query's deferred list holds, so part of
+    them is rescored inside the scan.  Ties go to the smaller id."""
+    d = 32
+    w = synth.make_tiny(220, n=8000, d=d, n_q=40, vocabs=(3,), label_vocab=0, b=64, h=1, cmin=0, cmax=1,
+                        integer=True)
+    c = np.full(d, 50.0, np.float32)
+    sh = _shell(c)
+    assert len(sh) == 2 * d + 8 * d * (d - 1) // 2
+    rng = np.random.default_rng(220)
+    w.x[rng.permutation(w.n)[:len(sh)]] = sh
+    w.q[:30] = c
+    oi = orc.build_from_workload(w, iters=3)
+    ix = caps.Index.from_workload(w, kmeans_iters=3, precision=prec)
+    for m in (48, 64):
+        for k in (10, 64):
+            _check(orc, oi, ix, w.q, w.con_off, w.con_attr, w.con_val, k, m)
+
+
 def test_exact_prune_edge_cases(caps, orc):
     w = synth.make_tiny(17, n=500, d=6, n_q=5, vocabs=(3, 4), label_vocab=10, b=5, h=2)
     oi = orc.build_from_workload(w, iters=2)
