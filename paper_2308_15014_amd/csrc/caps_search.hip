@@ -293,6 +293,38 @@ __global__ __launch_bounds__(256) void k_seed_tau(const uint64_t *__restrict__ p
     if (lane == 0 && *npool == keep && pool[keep - 1] < tau[qq]) tau[qq] = pool[keep - 1];
 }
 
+// Seed bound for exact keys from an approximate scan of a query's first s
+// probes: the keep (<= 64) best approximate candidates are rescored exactly;
+// being valid candidates, their k-th best exact key bounds the final k-th key
+// from above (~0 when fewer than k).  One wave per query.
+__global__ __launch_bounds__(256) void k_seed_exact(const uint64_t *__restrict__ partials,
+                                                    const int32_t *__restrict__ pcnt,
+                                                    const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                    int32_t s, int32_t slot_len, int32_t keep, int32_t k,
+                                                    const float *__restrict__ vecs, const float *__restrict__ q,
+                                                    const int32_t *__restrict__ perm, int32_t d, int32_t metric,
+                                                    uint64_t *__restrict__ tau) {
+    __shared__ uint64_t pool_all[4][kSeedCap];
+    __shared__ int32_t npool_all[4];
+    const int wq = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qq = blockIdx.x * 4 + wq;
+    if (qq >= nq) return;
+    uint64_t *pool = pool_all[wq];
+    int32_t *npool = &npool_all[wq];
+    (void)gather_best<kSeedCap>(pool, npool, partials, pcnt, sel, nullptr, (int64_t)qq * m, 0, s, slot_len, keep);
+    const int n = *npool;
+    uint64_t key = ~0ull;
+    if (lane < n) {   // approximate keys carry CSR positions
+        const uint32_t pos = (uint32_t)pool[lane];
+        const float sc = exact_score<8>(vecs + (int64_t)pos * d, q + (int64_t)qq * d, d, metric == 0);
+        key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)perm[pos];
+    }
+    int rank = 0;   // among the wave's exact keys (distinct ids)
+    for (int i = 0; i < n; i++) rank += readlane_u64(key, i) < key ? 1 : 0;
+    const uint64_t at = __ballot(lane < n && rank == k - 1);
+    if (lane == 0) tau[qq] = at ? readlane_u64(key, __builtin_ctzll(at)) : ~0ull;
+}
+
 // Bucket starts, sizes and tile starts per partition (single workgroup).
 __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan, const int32_t *__restrict__ total,
                                                int32_t b, int32_t ngrp, int32_t qb, int32_t *__restrict__ pstart,
@@ -1056,10 +1088,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         prof_end(CAPS_STAGE_SELECT, st);
         // Two rounds: the first probes of every query (best first) give each
         // query a tight seed bound on its final r-th key; the remaining probes
-        // are scanned against it.
+        // are scanned against it.  Exact keys on the matrix cores: the first
+        // round is an approximate scan of the seed probes whose best
+        // candidates are rescored exactly for the bound (k_seed_exact), and
+        // the second scans every probe, deferring its pairs to the merge.
         const int32_t s_seed = m >= 32 ? std::max(8, m / 16) : m;
+        const bool seeded_exact = P.defer && s_seed < m;
         for (int round = 0; round < 2; round++) {
-            const int32_t r0 = round == 0 ? 0 : s_seed;
+            const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
             const int32_t r1 = round == 0 ? s_seed : m;
             if (r0 >= r1) continue;
             prof_begin(CAPS_STAGE_SELECT, st);
@@ -1077,11 +1113,12 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             prof_end(CAPS_STAGE_SELECT, st);
             const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
             if (mfma) {
+                const bool seed_pass = seeded_exact && round == 0;
                 LowpScan S{};
                 S.nb = nb;
                 S.m = m;
                 S.r = r;
-                S.exact = !lowp;
+                S.exact = !lowp && !seed_pass;
                 S.first_round = round == 0;
                 S.max_tiles = max_tiles;
                 S.tstart = tstart;
@@ -1097,10 +1134,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.partials = partials;
                 S.tau = tau;
                 S.pcnt = W.pcnt;
-                S.nsurv = out_nsurv ? nsurv + q0 : nullptr;   // counted only when asked for
-                // the seed round rescores in the scan (its bounds tighten
-                // as it goes); the later probes defer their pairs
-                const bool defer_now = P.defer && round == 1;
+                S.nsurv = out_nsurv && !seed_pass ? nsurv + q0 : nullptr;   // counted only when asked for
+                const bool defer_now = seeded_exact && round == 1;
                 S.dpos = defer_now ? W.dpos : nullptr;
                 S.dcnt = defer_now ? W.dcnt : nullptr;
                 S.dcap = kDeferCap;
@@ -1135,7 +1170,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 prof_end(CAPS_STAGE_SCAN, st);
                 CAPS_HIP(hipGetLastError());
             }
-            if (round == 0 && s_seed < m) {
+            if (round == 0 && seeded_exact) {
+                prof_begin(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_seed_exact, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, W.pcnt, sel, nb,
+                                   m, s_seed, r, std::min(2 * k, 64), k, ix->vecs, q + (int64_t)q0 * d, ix->perm, d,
+                                   ix->metric, tau);
+                prof_end(CAPS_STAGE_SELECT, st);
+                CAPS_HIP(hipGetLastError());
+            } else if (round == 0 && s_seed < m) {
                 prof_begin(CAPS_STAGE_SELECT, st);
                 hipLaunchKernelGGL(k_seed_tau, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials,
                                    lowp ? W.pcnt : nullptr, sel, nb, m, s_seed, r, r, tau);
