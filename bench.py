@@ -20,8 +20,10 @@ Procedure
      queries at the same nprobe, on the host's cores.
 Modes: `value` is exact search (mode 0: BF16 lower bounds on the matrix
 cores, exact FP32 rescoring); `modes` also holds BF16 + rerank (mode 1),
-the plain FP32 scan (mode 2) and BF16 + learned router (a 192-1024-1024
-MLP trained on the GPU on 2M C2-shaped queries labelled by exact search).
+the plain FP32 scan (mode 2) and the learned router (a 192-1024-1024 MLP
+trained on the GPU on 2M C2-shaped queries labelled by exact search) in
+front of the BF16 matrix-core scan, with exact rescoring (mode 0) and with
+the top-4k rerank (mode 1).
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -114,7 +116,7 @@ def main():
     ap.add_argument("--modes", default="fp32,bf16,valu,router",
                     help="comma list of search modes to time: fp32 (exact, mode 0), bf16 "
                          "(approximate + rerank, mode 1), valu (exact, plain FP32 scan only, "
-                         "mode 2), router (BF16 + learned router: mode 1, routing 1); the JSON line "
+                         "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
@@ -230,7 +232,7 @@ def main():
     plain = measure(0, "fp32") if "fp32" in modes else None
     lowp = measure(1, "bf16") if "bf16" in modes else None
     valu = measure(2, "valu") if "valu" in modes else None
-    routed = None
+    routed = routed_rr = None
     if "router" in modes:
         # learned router on the same index: 2-layer MLP on [q/255 - 0.5 || hashed constraints],
         # labels = partitions of the exact filtered top-10 (search at nprobe = B), trained on the GPU
@@ -253,7 +255,8 @@ def main():
         del rq_d, rco_d, rca_d, rcv_d, labels
         log(f"router: {args.router_train} training queries (generated {gen_s:.1f}s, labels {label_s:.1f}s), "
             f"{args.router_epochs} epochs in {train_s:.1f}s, loss per epoch {[round(float(x), 4) for x in losses]}")
-        routed = measure(1, "bf16+router", routing=1)
+        routed = measure(0, "bf16+router", routing=1)
+        routed_rr = measure(1, "bf16-rerank+router", routing=1)
         routed.update(train_queries=args.router_train, epochs=args.router_epochs, train_s=round(train_s, 2),
                       label_s=round(label_s, 2), loss=[round(float(x), 4) for x in losses])
     if plain is None:
@@ -351,7 +354,13 @@ def main():
             "router": {"layers": "192-1024-1024", "train_queries": routed["train_queries"],
                        "epochs": routed["epochs"], "train_s": routed["train_s"], "label_s": routed["label_s"],
                        "loss_per_epoch": routed["loss"]},
+            "scan": "BF16 matrix-core bounds, exact FP32 rescoring (mode 0)",
             "sweep": routed["sweep"]}
+        out["modes"]["bf16_rerank_learned_router"] = {
+            "queries_per_s": round(routed_rr["qps"], 1), "nprobe": routed_rr["nprobe"],
+            "recall@10": routed_rr["recall"], "ms_per_step": round(routed_rr["ms_step"], 4),
+            "stage_ms_per_step": routed_rr["stage_ms"], "rerank": 4 * k,
+            "scan": "BF16 matrix-core scores, FP32 rerank of the top 4k (mode 1)", "sweep": routed_rr["sweep"]}
     if lowp is not None:
         out["modes"]["bf16_centroid"] = {
             "queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"], "recall@10": lowp["recall"],

@@ -217,6 +217,8 @@ enum {
     CAPS_STAGE_SELECT = 3,  /* sub-partition choice and bucketing */
     CAPS_STAGE_SCAN = 4,    /* filtered distance scan (per-partition top-k) */
     CAPS_STAGE_MERGE = 5,   /* per-query top-k merge */
+    CAPS_STAGE_SEED = 6,    /* exact search on the matrix cores: approximate scan of the
+                               first probes and the exact seed bound */
     CAPS_N_STAGES = 8
 };
 typedef struct {

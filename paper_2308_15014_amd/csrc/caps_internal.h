@@ -139,8 +139,10 @@ struct LowpScan {
     int32_t nb, m, r;             // r: keys kept per (query, probe)
     bool exact;                   // exact keys (mode 0) or approximate ones (mode 1)
     bool first_round;             // also round the queries (first launch of a sub-batch)
+    int stage;                    // profiling stage of the launch (CAPS_STAGE_SCAN or _SEED)
     int64_t max_tiles;
-    const int32_t *tstart, *pstart, *pcount, *entries;
+    const int4 *tiles;            // per tile: partition, first entry, entries (0: none)
+    const int32_t *entries;
     const uint32_t *sel;
     const QDesc *qd;
     const float *q;               // nb x d FP32 queries of the sub-batch

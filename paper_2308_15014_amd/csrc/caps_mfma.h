@@ -14,7 +14,8 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ scan
 struct LowpArgs {
-    const int32_t *tstart, *pstart, *pcount, *entries;
+    const int4 *tiles;          // per tile: partition, first entry, entries (0: no tile)
+    const int32_t *entries;
     const uint32_t *sel;
     const QDesc *qd;
     const int32_t *offs;
@@ -32,7 +33,7 @@ struct LowpArgs {
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
     int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count, or null
-    int32_t m, h, b, r, metric, d, dcap;
+    int32_t m, h, b, r, metric, d, dcap, ntiles;   // ntiles: length of `tiles` (the grid's tile range)
     float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
 };
 
@@ -233,18 +234,13 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     __shared__ uint32_t lvw[kLNW];
     __shared__ float qmx[2][kLNW];
 
-    const int tile = xcd_tile(blockIdx.x, A.tstart[A.b]);
+    const int tile = xcd_tile(blockIdx.x, A.ntiles);
     if (tile < 0) return;
-    int lo = 0, hi = A.b;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (A.tstart[mid] <= tile) lo = mid;
-        else hi = mid;
-    }
-    const int p = lo;
-    const int i0 = (tile - A.tstart[p]) * kLQB;
-    const int nqt = min(kLQB, A.pcount[p] - i0);
-    const int32_t *ent = A.entries + A.pstart[p] + i0;
+    const int4 dsc = A.tiles[tile];
+    if (dsc.z <= 0) return;
+    const int p = dsc.x;
+    const int nqt = dsc.z;
+    const int32_t *ent = A.entries + dsc.y;
     const int h = A.h, r = A.r;
     uint8_t *xl = smem + L.xl;
     uint32_t *xw = reinterpret_cast<uint32_t *>(smem + L.xw);

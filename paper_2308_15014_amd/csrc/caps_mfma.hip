@@ -244,9 +244,8 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
         hipLaunchKernelGGL(k_qquant, dim3((S.nb + 127) / 128), dim3(128), 0, st, S.q, S.nb, ix->d, ix->dpad, ix->prec,
                            S.qlow, S.qscale, S.qaux);
     LowpArgs A;
-    A.tstart = S.tstart;
-    A.pstart = S.pstart;
-    A.pcount = S.pcount;
+    A.tiles = S.tiles;
+    A.ntiles = (int32_t)S.max_tiles;
     A.entries = S.entries;
     A.sel = S.sel;
     A.qd = S.qd;
@@ -292,10 +291,10 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
                               : pick_prec<false>(ix->prec, ix->dpad / 32, lab, S.r);
     const size_t lds = lowp_scan_lds(ix, S.r, S.exact);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    prof_begin(CAPS_STAGE_SCAN, st);
+    prof_begin(S.stage, st);
     const int64_t grid = (S.max_tiles + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kLNT), lds, st, A);
-    prof_end(CAPS_STAGE_SCAN, st);
+    prof_end(S.stage, st);
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;
 }

@@ -79,7 +79,8 @@ __global__ __launch_bounds__(64) void k_router_input(const float *__restrict__ q
 // leading dimension ldm), negation (scores, smaller is better); written as
 // FP32 and/or BF16 with leading dimension ldc.
 enum { kGemmRelu = 1, kGemmMask = 2, kGemmNeg = 4 };
-constexpr int kGT = 64, kGK = 32, kGKP = kGK + 8;
+constexpr int kGT = 64, kGK = 64, kGKP = kGK + 8;
+enum { kGemmVecA = 8, kGemmVecB = 16 };   // operand rows are 16-byte aligned runs of K (vector loads)
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t sam, int64_t sak,
                                                    const uint16_t *__restrict__ B, int64_t sbn, int64_t sbk,
@@ -100,7 +101,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
     // one operand tile: rows r0.., k0..; the fast thread index walks the
     // unit-stride dimension so that the loads coalesce
     auto load_tile = [&](uint16_t (*S)[kGKP], const uint16_t *P, int64_t srow, int64_t sk, int64_t r0, int32_t R,
-                         int64_t k0) {
+                         int64_t k0, bool vec) {
+        if (vec) {   // 8 consecutive k per thread (K is a multiple of 8)
+#pragma unroll
+            for (int u = 0; u < kGT * kGK / (8 * 256); u++) {
+                const int e = t + u * 256;
+                const int r = e / (kGK / 8), kk = (e % (kGK / 8)) * 8;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (r0 + r < R && k0 + kk < K) v = *reinterpret_cast<const uint4 *>(P + (r0 + r) * srow + k0 + kk);
+                *reinterpret_cast<uint4 *>(&S[r][kk]) = v;
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < kGT * kGK / 256; u++) {
             const int e = t + u * 256;
@@ -118,20 +130,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
         }
     };
     for (int64_t k0 = 0; k0 < K; k0 += kGK) {
-        load_tile(As, A, sam, sak, m0, M, k0);
-        load_tile(Bs, B, sbn, sbk, n0, N, k0);
+        load_tile(As, A, sam, sak, m0, M, k0, (flags & kGemmVecA) != 0);
+        load_tile(Bs, B, sbn, sbk, n0, N, k0, (flags & kGemmVecB) != 0);
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            const bf16x8 a = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const uint4 *>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]));
+        for (int ks = 0; ks < kGK; ks += 32)
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const bf16x8 b = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const uint4 *>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]));
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; i++) {
+                const bf16x8 a = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(&As[wm + i * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const bf16x8 b = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const uint4 *>(&Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+                }
             }
-        }
         __syncthreads();
     }
     // D row (lane/16)*4 + r, column lane%16 of each 16 x 16 block
@@ -159,6 +173,11 @@ static caps_status gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint1
                         int32_t M, int32_t N, int32_t K, const float *bias, int32_t flags, const uint16_t *mask,
                         int64_t ldm, float *C32, uint16_t *C16, int64_t ldc, hipStream_t st) {
     if (M <= 0 || N <= 0) return CAPS_OK;
+    const auto vec_ok = [K](const uint16_t *P, int64_t srow, int64_t sk) {
+        return sk == 1 && K % 8 == 0 && srow % 8 == 0 && ((uintptr_t)P & 15) == 0;
+    };
+    if (vec_ok(A, sam, sak)) flags |= kGemmVecA;
+    if (vec_ok(B, sbn, sbk)) flags |= kGemmVecB;
     hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT)),
                        dim3(256), 0, st, A, sam, sak, B, sbn, sbk, M, N, K, bias, flags, mask, ldm, C32, C16, ldc);
     CAPS_HIP(hipGetLastError());

@@ -167,6 +167,87 @@ __global__ __launch_bounds__(kTopmNT) void k_topm(const float *__restrict__ scor
     for (int i = threadIdx.x; i < m; i += kTopmNT) probes[q * m + i] = (int32_t)(uint32_t)(keys[i] & 0xFFFFFFFFu);
 }
 
+// Same result for 256 <= pb <= 8192: thread t holds keys 4t..; the
+// compare-exchange stages of the bitonic network run in registers (partner in
+// the same thread), through lane shuffles (partner in the same wave) and
+// through LDS only when the partner is in another wave (3 stages at
+// pb = 1024 instead of 55 barrier stages).
+template <int KPT>
+__global__ __launch_bounds__(kTopmNT) void k_topm_reg(const float *__restrict__ scores, int32_t b, int32_t m,
+                                                      int32_t *__restrict__ probes) {
+    constexpr int PB = KPT * kTopmNT;
+    __shared__ uint64_t ex[PB];
+    const int64_t q = blockIdx.x;
+    const float *s = scores + q * b;
+    const int t = threadIdx.x;
+    uint64_t v[KPT];
+#pragma unroll
+    for (int r = 0; r < KPT; r++) {
+        const int i = t * KPT + r;
+        v[r] = i < b ? (((uint64_t)f2ord(s[i]) << 32) | (uint32_t)i) : ~0ull;
+    }
+    // element i keeps the smaller of (i, i ^ j) when it is the lower index of
+    // an ascending pair or the upper index of a descending one
+    auto keep = [](uint64_t a, uint64_t o, int i, int j, int k) {
+        const bool take_min = ((i & j) == 0) == ((i & k) == 0);
+        return take_min ? (o < a ? o : a) : (o > a ? o : a);
+    };
+    for (int k = 2; k <= PB; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < KPT) {
+#pragma unroll
+                for (int r = 0; r < KPT; r++) {
+                    const int rp = r ^ j;
+                    if (rp > r) {
+                        const int i = t * KPT + r;
+                        const uint64_t a = v[r], o = v[rp];
+                        v[r] = keep(a, o, i, j, k);
+                        v[rp] = keep(o, a, i ^ j, j, k);
+                    }
+                }
+            } else if (j < 64 * KPT) {
+                const int lm = j / KPT;
+#pragma unroll
+                for (int r = 0; r < KPT; r++) {
+                    const uint64_t o = __shfl_xor(v[r], lm, 64);
+                    v[r] = keep(v[r], o, t * KPT + r, j, k);
+                }
+            } else {
+                __syncthreads();   // the previous exchange is read
+#pragma unroll
+                for (int r = 0; r < KPT; r++) ex[t * KPT + r] = v[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < KPT; r++) {
+                    const int i = t * KPT + r;
+                    v[r] = keep(v[r], ex[i ^ j], i, j, k);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KPT; r++) {
+        const int i = t * KPT + r;
+        if (i < m) probes[q * m + i] = (int32_t)(uint32_t)(v[r] & 0xFFFFFFFFu);
+    }
+}
+
+// Launches the register bitonic top-m when pb allows, else the LDS one.
+static void launch_topm(const float *scores, int32_t nb, int32_t b, int32_t pb, int32_t m, int32_t *probes,
+                        hipStream_t st) {
+    switch (pb) {
+    case 256: hipLaunchKernelGGL(k_topm_reg<1>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 512: hipLaunchKernelGGL(k_topm_reg<2>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 1024: hipLaunchKernelGGL(k_topm_reg<4>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 2048: hipLaunchKernelGGL(k_topm_reg<8>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 4096: hipLaunchKernelGGL(k_topm_reg<16>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 8192: hipLaunchKernelGGL(k_topm_reg<32>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    default:
+        hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb, m,
+                           probes);
+    }
+}
+
 // ------------------------------------------------------------------ selection
 __device__ inline void tag_decode(const Schema &s, int32_t tok, int &attr, int32_t &val) {
     if (tok < s.dense_off[s.n_dense]) {
@@ -234,41 +315,53 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
 }
 
 // Bucketing of the chosen (query, probe) pairs by partition without global
-// atomics: block g counts its queries' pairs per partition (hist, stored
-// partition-major), an exclusive scan turns the counts into positions, and
-// the fill pass places each pair.
+// atomics: block g counts its queries' pairs per bucket (hist, stored
+// bucket-major), an exclusive scan turns the counts into positions, and the
+// fill pass places each pair.  A partition's pairs are further grouped by
+// their level mask (nc classes, nc = 2^(h+1) for h <= 3, else 1): a tile then
+// mostly holds queries that scan the same levels, and the scans skip the
+// levels none of a tile's queries selected.
 constexpr int kBucketQ = 16;   // queries per bucketing block
+
+// (the block histogram of b * nc counters must fit 64 KiB of LDS)
+inline int32_t bucket_classes(int32_t b, int32_t h) {
+    const int32_t nc = h <= 3 ? 1 << (h + 1) : 1;
+    return (int64_t)b * nc <= 16384 ? nc : 1;
+}
 
 __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
-                                                     int32_t *__restrict__ hist) {
+                                                     int32_t r0, int32_t r1, int32_t nbk, int32_t nc,
+                                                     int32_t ngrp, int32_t *__restrict__ hist) {
     extern __shared__ int32_t cnt[];
-    for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
+    for (int i = threadIdx.x; i < nbk; i += 256) cnt[i] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
         const int32_t rr = (int32_t)(e % m);
-        if (rr >= r0 && rr < r1 && sel[e]) atomicAdd(&cnt[probes[e]], 1);
+        const uint32_t sm = sel[e];
+        if (rr >= r0 && rr < r1 && sm) atomicAdd(&cnt[probes[e] * nc + (int32_t)(sm & (uint32_t)(nc - 1))], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+    for (int i = threadIdx.x; i < nbk; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
 }
 
 __global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
-                                                     const int32_t *__restrict__ hscan,
+                                                     int32_t r0, int32_t r1, int32_t nbk, int32_t nc,
+                                                     int32_t ngrp, const int32_t *__restrict__ hscan,
                                                      int32_t *__restrict__ entries) {
     extern __shared__ int32_t run[];
-    for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+    for (int i = threadIdx.x; i < nbk; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
         const int32_t rr = (int32_t)(e % m);
-        if (rr >= r0 && rr < r1 && sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
+        const uint32_t sm = sel[e];
+        if (rr >= r0 && rr < r1 && sm)
+            entries[atomicAdd(&run[probes[e] * nc + (int32_t)(sm & (uint32_t)(nc - 1))], 1)] = (int32_t)e;
     }
 }
 
@@ -327,8 +420,9 @@ __global__ __launch_bounds__(256) void k_seed_exact(const uint64_t *__restrict__
 
 // Bucket starts, sizes and tile starts per partition (single workgroup).
 __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan, const int32_t *__restrict__ total,
-                                               int32_t b, int32_t ngrp, int32_t qb, int32_t *__restrict__ pstart,
-                                               int32_t *__restrict__ pcount, int32_t *__restrict__ tstart) {
+                                               int32_t b, int32_t nc, int32_t ngrp, int32_t qb,
+                                               int32_t *__restrict__ pstart, int32_t *__restrict__ pcount,
+                                               int32_t *__restrict__ tstart) {
     __shared__ int scratch[1024 / kWave + 1];
     __shared__ int carry_t;
     if (threadIdx.x == 0) carry_t = 0;
@@ -337,8 +431,8 @@ __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan
         const int p = b0 + threadIdx.x;
         int c = 0;
         if (p < b) {
-            const int32_t s0 = hscan[(int64_t)p * ngrp];
-            const int32_t s1 = p + 1 < b ? hscan[(int64_t)(p + 1) * ngrp] : *total;
+            const int32_t s0 = hscan[(int64_t)p * nc * ngrp];
+            const int32_t s1 = p + 1 < b ? hscan[(int64_t)(p + 1) * nc * ngrp] : *total;
             pstart[p] = s0;
             pcount[p] = s1 - s0;
             c = s1 - s0;
@@ -353,9 +447,35 @@ __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan
     if (threadIdx.x == 0) tstart[b] = carry_t;
 }
 
+// Tile table for the scans: tile t < tstart[b] holds partition p with
+// tstart[p] <= t < tstart[p + 1] and its entries i0.., i0 = (t - tstart[p])
+// qb, up to qb of them; tiles past tstart[b] (up to the grid's range) hold
+// none.  One thread per tile.
+__global__ __launch_bounds__(256) void k_tile_desc(const int32_t *__restrict__ tstart,
+                                                   const int32_t *__restrict__ pstart,
+                                                   const int32_t *__restrict__ pcount, int32_t b, int32_t qb,
+                                                   int32_t ntiles, int4 *__restrict__ tiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int4 dsc = make_int4(0, 0, 0, 0);
+    if (t < tstart[b]) {
+        int lo = 0, hi = b;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tstart[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const int i0 = (t - tstart[lo]) * qb;
+        dsc = make_int4(lo, pstart[lo] + i0, min(qb, pcount[lo] - i0), 0);
+    }
+    tiles[t] = dsc;
+}
+
 // ------------------------------------------------------------------ scan
 struct ScanArgs {
-    const int32_t *tstart, *pstart, *pcount, *entries;
+    const int4 *tiles;     // per tile: partition, first entry, entries (0: no tile)
+    int32_t ntiles;        // length of `tiles` (the grid's tile range)
+    const int32_t *entries;
     const uint32_t *sel;
     const float *q;
     const QDesc *qd;
@@ -462,18 +582,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t lvmask_w[NW];
     __shared__ int32_t spo[kMaxHeight + 2];
-    const int tile = xcd_tile(blockIdx.x, A.tstart[A.b]);
+    const int tile = xcd_tile(blockIdx.x, A.ntiles);
     if (tile < 0) return;
-    int lo = 0, hi = A.b;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (A.tstart[mid] <= tile) lo = mid;
-        else hi = mid;
-    }
-    const int p = lo;
-    const int i0 = (tile - A.tstart[p]) * QB;
-    const int nqt = min(QB, A.pcount[p] - i0);
-    const int32_t *ent = A.entries + A.pstart[p] + i0;
+    const int4 dsc = A.tiles[tile];
+    if (dsc.z <= 0) return;
+    const int p = dsc.x;
+    const int nqt = dsc.z;
+    const int32_t *ent = A.entries + dsc.y;
 
     const int d = A.d, k = A.k, h = A.h;
     const ScanLds L(d, NW, KMAX);
@@ -894,17 +1009,24 @@ struct SearchWs {
     uint64_t *partials, *tau;
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
+    int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
     float *conf;                // learned routing: softmax top-1 probability
     int32_t *probes_c;          // learned routing: centroid probes for the fallback
 };
+
+// Tiles of one round at most: every (query, probe) entry in tiles of at
+// least 64 entries, plus one partial tile per partition, rounded up to the
+// XCD multiple of the grid.
+static int64_t tile_cap(int64_t sb, int64_t m, int64_t b) { return (sb * m + 63) / 64 + b + kXcds; }
 
 // Deferred pairs kept per query by the exact matrix-core scan (more are
 // rescored inside the scan).
 constexpr int32_t kDeferCap = 512;
 
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
-                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router, bool defer) {
+                  bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router, bool defer,
+                  int32_t nc) {
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
     w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
     w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
@@ -922,12 +1044,13 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.tau = ar.take<uint64_t>((size_t)sb);
     w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
-    w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
-    w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.hist = ar.take<int32_t>((size_t)b * nc * ngrp_max + 1);
+    w.hscan = ar.take<int32_t>((size_t)b * nc * ngrp_max + 1);
     w.htotal = ar.take<int32_t>(1);
     w.pcount = ar.take<int32_t>(b + 1);
     w.pstart = ar.take<int32_t>(b + 1);
     w.tstart = ar.take<int32_t>(b + 1);
+    w.tiles = ar.take<int4>(tile_cap(sb, m, b));
     w.rx = router ? ar.take<uint16_t>((size_t)sb * router->dpad) : nullptr;
     w.rh = router ? ar.take<uint16_t>((size_t)sb * router->hid) : nullptr;
     w.conf = router ? ar.take<float>((size_t)sb) : nullptr;
@@ -958,8 +1081,9 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
     P.qlow_row = P.mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
     const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
                          sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
-                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 1) : 0) +
+                         2 * sizeof(int32_t) * (size_t)b * bucket_classes(b, ix->h) / kBucketQ + P.qlow_row +
+                         5 * sizeof(float) + 64 +
+                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 1) : 0) + sizeof(int4) * (size_t)m / 64 +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
@@ -972,7 +1096,8 @@ size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int
     const SearchPlan P = plan_search(ix, sp, nq);
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router, P.defer);
+    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router, P.defer,
+          bucket_classes(ix->b, ix->h));
     return measure.off;
 }
 
@@ -985,6 +1110,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     const SearchPlan P = plan_search(ix, sp, nq);
     const bool lowp = P.lowp, mfma = P.mfma;
     const int32_t r = P.r, sb = P.sb;
+    const int32_t nc = bucket_classes(b, h);
     const size_t qlow_row = P.qlow_row;
     const Router *router = P.router;
     const bool probes_only = out_probes != nullptr;
@@ -993,11 +1119,11 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
 
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer);
+    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc);
     Arena ar;
     ar.cap = measure.off;
     CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
-    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer);
+    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc);
     if (ar.overflow) {
         (void)hipFreeAsync(ar.base, st);
         set_error("caps_search: internal workspace layout error");
@@ -1050,8 +1176,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             if (rs != CAPS_OK) return rs;
             prof_end(CAPS_STAGE_ROUTE, st);
             prof_begin(CAPS_STAGE_TOPM, st);
-            hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
-                               m, probes);
+            launch_topm(scores, nb, b, pb, m, probes, st);
             prof_end(CAPS_STAGE_TOPM, st);
             prof_begin(CAPS_STAGE_SELECT, st);
             hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
@@ -1063,8 +1188,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                            q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
         prof_end(CAPS_STAGE_ROUTE, st);
         prof_begin(CAPS_STAGE_TOPM, st);
-        hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb,
-                           m, router ? W.probes_c : probes);
+        launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st);
         prof_end(CAPS_STAGE_TOPM, st);
         if (router) {
             const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
@@ -1099,19 +1223,22 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             const int32_t r1 = round == 0 ? s_seed : m;
             if (r0 >= r1) continue;
             prof_begin(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                               nb, m, r0, r1, b, ngrp, hist);
+            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b * nc, st, probes,
+                               sel, nb, m, r0, r1, b * nc, nc, ngrp, hist);
             {
-                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
+                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * nc * ngrp, htotal, st);
                 if (es != CAPS_OK) return es;
             }
-            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
+            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, nc, ngrp, qb, pstart, pcount,
                                tstart);
-            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                               nb, m, r0, r1, b, ngrp, hscan, entries);
+            const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
+            const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
+            hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
+                               qb, (int32_t)grid, W.tiles);
+            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b * nc, st, probes,
+                               sel, nb, m, r0, r1, b * nc, nc, ngrp, hscan, entries);
             CAPS_HIP(hipGetLastError());
             prof_end(CAPS_STAGE_SELECT, st);
-            const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
             if (mfma) {
                 const bool seed_pass = seeded_exact && round == 0;
                 LowpScan S{};
@@ -1120,10 +1247,9 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.r = r;
                 S.exact = !lowp && !seed_pass;
                 S.first_round = round == 0;
-                S.max_tiles = max_tiles;
-                S.tstart = tstart;
-                S.pstart = pstart;
-                S.pcount = pcount;
+                S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
+                S.max_tiles = grid;
+                S.tiles = W.tiles;
                 S.entries = entries;
                 S.sel = sel;
                 S.qd = qd;
@@ -1143,9 +1269,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 if (ls != CAPS_OK) return ls;
             } else {
                 ScanArgs A;
-                A.tstart = tstart;
-                A.pstart = pstart;
-                A.pcount = pcount;
+                A.tiles = W.tiles;
+                A.ntiles = (int32_t)grid;
                 A.entries = entries;
                 A.sel = sel;
                 A.q = q + (int64_t)q0 * d;
@@ -1165,17 +1290,16 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 A.b = b;
                 A.k = k;
                 prof_begin(CAPS_STAGE_SCAN, st);
-                const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
                 hipLaunchKernelGGL(scan_fn, dim3((unsigned)grid), dim3(scan_waves(k) * 64), lds, st, A);
                 prof_end(CAPS_STAGE_SCAN, st);
                 CAPS_HIP(hipGetLastError());
             }
             if (round == 0 && seeded_exact) {
-                prof_begin(CAPS_STAGE_SELECT, st);
+                prof_begin(CAPS_STAGE_SEED, st);
                 hipLaunchKernelGGL(k_seed_exact, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, W.pcnt, sel, nb,
                                    m, s_seed, r, std::min(2 * k, 64), k, ix->vecs, q + (int64_t)q0 * d, ix->perm, d,
                                    ix->metric, tau);
-                prof_end(CAPS_STAGE_SELECT, st);
+                prof_end(CAPS_STAGE_SEED, st);
                 CAPS_HIP(hipGetLastError());
             } else if (round == 0 && s_seed < m) {
                 prof_begin(CAPS_STAGE_SELECT, st);

@@ -156,3 +156,16 @@ def test_build_errors(caps):
     lo = np.array([0, 2] + [2] * 9, np.int64)
     with pytest.raises(caps.CapsError):
         caps.Index.build(x, None, None, lo, np.array([1, 1], np.uint32), 4, n_partitions=2)
+
+
+@pytest.mark.parametrize("b", [200, 700, 2100])
+def test_many_partitions(caps, orc, b):
+    """Best-m selection over 256 to 4096 sort slots (pb = 256, 1024, 4096):
+    probes in the oracle's order (score, then partition id), masks, ids."""
+    w = synth.make_tiny(300 + b, n=max(6000, 4 * b), d=6, n_q=60, vocabs=(3, 5), label_vocab=0, b=b, h=2,
+                        cmin=0, cmax=2, integer=True)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2)
+    _check_build(oi, ix.export())
+    for m in (1, 37, b):
+        _check_search(orc, oi, ix, w, 10, m)
