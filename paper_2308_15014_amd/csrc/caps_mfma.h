@@ -29,7 +29,7 @@ struct LowpArgs {
     const float *vecs, *q;      // FP32 CSR rows and queries (exact rescoring)
     const int32_t *perm;
     uint64_t *partials;         // per (query, probe): up to r keys
-    int32_t *pcnt;              // approximate: keys written per (query, probe)
+    int32_t *pcnt;              // keys written per (query, probe) (sorted, at most r)
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
     int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count, or null
@@ -628,17 +628,13 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     for (int i = 0; i < kLQPW; i++) {
         const int qi = qbase + i;
         if (qi >= nqt) break;
-        buf_reduce<CB>(buf, bcnt, tau, qi, r);
+        if (bcnt[qi] > 0) buf_reduce<CB>(buf, bcnt, tau, qi, r);
         const int c = bcnt[qi];
         const int32_t slot = qslot[qi];
         uint64_t *out = A.partials + (int64_t)slot * r;
-        if (EXACT) {   // r = k keys per slot, padded (the plain scan's layout)
-            if (lane < r) out[lane] = lane < c ? buf[qi * CB + lane] : ~0ull;
-        } else if (lane < c) {
-            out[lane] = buf[qi * CB + lane];
-        }
+        if (lane < c) out[lane] = buf[qi * CB + lane];   // the keys written are counted in pcnt
         if (lane == 0) {
-            if (!EXACT) A.pcnt[slot] = c;
+            A.pcnt[slot] = c;
             if (c == r) atomicMin((unsigned long long *)(A.tau + slot / A.m), (unsigned long long)buf[qi * CB + r - 1]);
         }
     }

@@ -315,53 +315,74 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
 }
 
 // Bucketing of the chosen (query, probe) pairs by partition without global
-// atomics: block g counts its queries' pairs per bucket (hist, stored
-// bucket-major), an exclusive scan turns the counts into positions, and the
-// fill pass places each pair.  A partition's pairs are further grouped by
-// their level mask (nc classes, nc = 2^(h+1) for h <= 3, else 1): a tile then
-// mostly holds queries that scan the same levels, and the scans skip the
-// levels none of a tile's queries selected.
+// atomics: block g counts its queries' pairs per partition (hist, stored
+// partition-major), an exclusive scan turns the counts into positions, and
+// the fill pass places each pair.  k_class_sort then groups each partition's
+// pairs by their level mask (nc classes, nc = 2^(h+1) for h <= 3, else 1): a
+// tile mostly holds queries that scan the same levels, and the scans skip
+// the levels none of a tile's queries selected.
 constexpr int kBucketQ = 16;   // queries per bucketing block
 
-// (the block histogram of b * nc counters must fit 64 KiB of LDS)
-inline int32_t bucket_classes(int32_t b, int32_t h) {
-    const int32_t nc = h <= 3 ? 1 << (h + 1) : 1;
-    return (int64_t)b * nc <= 16384 ? nc : 1;
-}
+inline int32_t bucket_classes(int32_t h) { return h <= 3 ? 1 << (h + 1) : 1; }
 
 __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t nbk, int32_t nc,
-                                                     int32_t ngrp, int32_t *__restrict__ hist) {
+                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                     int32_t *__restrict__ hist) {
     extern __shared__ int32_t cnt[];
-    for (int i = threadIdx.x; i < nbk; i += 256) cnt[i] = 0;
+    for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
         const int32_t rr = (int32_t)(e % m);
-        const uint32_t sm = sel[e];
-        if (rr >= r0 && rr < r1 && sm) atomicAdd(&cnt[probes[e] * nc + (int32_t)(sm & (uint32_t)(nc - 1))], 1);
+        if (rr >= r0 && rr < r1 && sel[e]) atomicAdd(&cnt[probes[e]], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nbk; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+    for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
 }
 
 __global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t nbk, int32_t nc,
-                                                     int32_t ngrp, const int32_t *__restrict__ hscan,
+                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                     const int32_t *__restrict__ hscan,
                                                      int32_t *__restrict__ entries) {
     extern __shared__ int32_t run[];
-    for (int i = threadIdx.x; i < nbk; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+    for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
     const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
         const int32_t rr = (int32_t)(e % m);
-        const uint32_t sm = sel[e];
-        if (rr >= r0 && rr < r1 && sm)
-            entries[atomicAdd(&run[probes[e] * nc + (int32_t)(sm & (uint32_t)(nc - 1))], 1)] = (int32_t)e;
+        if (rr >= r0 && rr < r1 && sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
+    }
+}
+
+// One workgroup per partition: copies its entries from `in` to `out` grouped
+// by level-mask class (in any order within a class).
+__global__ __launch_bounds__(256) void k_class_sort(const int32_t *__restrict__ in, const uint32_t *__restrict__ sel,
+                                                    const int32_t *__restrict__ pstart,
+                                                    const int32_t *__restrict__ pcount, int32_t nc,
+                                                    int32_t *__restrict__ out) {
+    __shared__ int32_t cnt[16];
+    const int32_t p = blockIdx.x, t = threadIdx.x;
+    const int32_t ps = pstart[p], pn = pcount[p];
+    if (t < 16) cnt[t] = 0;
+    __syncthreads();
+    for (int32_t i = t; i < pn; i += 256) atomicAdd(&cnt[sel[in[ps + i]] & (uint32_t)(nc - 1)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int32_t run = 0;
+        for (int c = 0; c < nc; c++) {
+            const int32_t v = cnt[c];
+            cnt[c] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int32_t i = t; i < pn; i += 256) {
+        const int32_t e = in[ps + i];
+        out[ps + atomicAdd(&cnt[sel[e] & (uint32_t)(nc - 1)], 1)] = e;
     }
 }
 
@@ -420,9 +441,8 @@ __global__ __launch_bounds__(256) void k_seed_exact(const uint64_t *__restrict__
 
 // Bucket starts, sizes and tile starts per partition (single workgroup).
 __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan, const int32_t *__restrict__ total,
-                                               int32_t b, int32_t nc, int32_t ngrp, int32_t qb,
-                                               int32_t *__restrict__ pstart, int32_t *__restrict__ pcount,
-                                               int32_t *__restrict__ tstart) {
+                                               int32_t b, int32_t ngrp, int32_t qb, int32_t *__restrict__ pstart,
+                                               int32_t *__restrict__ pcount, int32_t *__restrict__ tstart) {
     __shared__ int scratch[1024 / kWave + 1];
     __shared__ int carry_t;
     if (threadIdx.x == 0) carry_t = 0;
@@ -431,8 +451,8 @@ __global__ __launch_bounds__(1024) void k_plan(const int32_t *__restrict__ hscan
         const int p = b0 + threadIdx.x;
         int c = 0;
         if (p < b) {
-            const int32_t s0 = hscan[(int64_t)p * nc * ngrp];
-            const int32_t s1 = p + 1 < b ? hscan[(int64_t)(p + 1) * nc * ngrp] : *total;
+            const int32_t s0 = hscan[(int64_t)p * ngrp];
+            const int32_t s1 = p + 1 < b ? hscan[(int64_t)(p + 1) * ngrp] : *total;
             pstart[p] = s0;
             pcount[p] = s1 - s0;
             c = s1 - s0;
@@ -865,6 +885,7 @@ struct Deferred {
 
 template <int KM>
 __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ partials,
+                                               const int32_t *__restrict__ pcnt,
                                                const uint32_t *__restrict__ sel, const int32_t *__restrict__ cand,
                                                int32_t nq, int32_t m, int32_t k, int32_t metric,
                                                int32_t *__restrict__ ids, float *__restrict__ dist,
@@ -898,7 +919,8 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
         if (sel[slot] == 0) continue;
         nc += cand[slot];
         const uint64_t *src = partials + slot * k;
-        for (int i = 0; i < k; i++) {
+        const int c = pcnt ? min(pcnt[slot], k) : k;   // else lists padded with ~0
+        for (int i = 0; i < c; i++) {
             const uint64_t key = src[i];
             if (key >= lst[KM - 1]) break;   // lists are sorted: the rest is worse
             insert(key);
@@ -1005,7 +1027,7 @@ struct SearchWs {
     float *scores;
     int32_t *probes;
     uint32_t *sel;
-    int32_t *cand, *entries;
+    int32_t *cand, *entries, *entries2;   // entries2: class-grouped copy
     uint64_t *partials, *tau;
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
@@ -1044,8 +1066,9 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.tau = ar.take<uint64_t>((size_t)sb);
     w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
-    w.hist = ar.take<int32_t>((size_t)b * nc * ngrp_max + 1);
-    w.hscan = ar.take<int32_t>((size_t)b * nc * ngrp_max + 1);
+    w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
     w.htotal = ar.take<int32_t>(1);
     w.pcount = ar.take<int32_t>(b + 1);
     w.pstart = ar.take<int32_t>(b + 1);
@@ -1081,8 +1104,8 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
     P.qlow_row = P.mfma ? (size_t)ix->dpad * (ix->prec == CAPS_PREC_FP8 ? 1 : 2) : 0;
     const size_t per_q = sizeof(float) * (size_t)b + sizeof(int32_t) * 5 * (size_t)m +
                          sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
-                         2 * sizeof(int32_t) * (size_t)b * bucket_classes(b, ix->h) / kBucketQ + P.qlow_row +
-                         5 * sizeof(float) + 64 +
+                         2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
+                         sizeof(int32_t) * (size_t)m +
                          (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 1) : 0) + sizeof(int4) * (size_t)m / 64 +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
@@ -1097,7 +1120,7 @@ size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int
     SearchWs W;
     Arena measure;
     carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router, P.defer,
-          bucket_classes(ix->b, ix->h));
+          bucket_classes(ix->h));
     return measure.off;
 }
 
@@ -1110,7 +1133,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     const SearchPlan P = plan_search(ix, sp, nq);
     const bool lowp = P.lowp, mfma = P.mfma;
     const int32_t r = P.r, sb = P.sb;
-    const int32_t nc = bucket_classes(b, h);
+    const int32_t nc = bucket_classes(h);
     const size_t qlow_row = P.qlow_row;
     const Router *router = P.router;
     const bool probes_only = out_probes != nullptr;
@@ -1223,20 +1246,26 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             const int32_t r1 = round == 0 ? s_seed : m;
             if (r0 >= r1) continue;
             prof_begin(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b * nc, st, probes,
-                               sel, nb, m, r0, r1, b * nc, nc, ngrp, hist);
+            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                               nb, m, r0, r1, b, ngrp, hist);
             {
-                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * nc * ngrp, htotal, st);
+                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
                 if (es != CAPS_OK) return es;
             }
-            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, nc, ngrp, qb, pstart, pcount,
+            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
                                tstart);
             const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
             const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
             hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
                                qb, (int32_t)grid, W.tiles);
-            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b * nc, st, probes,
-                               sel, nb, m, r0, r1, b * nc, nc, ngrp, hscan, entries);
+            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                               nb, m, r0, r1, b, ngrp, hscan, entries);
+            const int32_t *ent = entries;
+            if (nc > 1) {
+                hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(256), 0, st, entries, sel, pstart, pcount, nc,
+                                   W.entries2);
+                ent = W.entries2;
+            }
             CAPS_HIP(hipGetLastError());
             prof_end(CAPS_STAGE_SELECT, st);
             if (mfma) {
@@ -1250,7 +1279,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
                 S.max_tiles = grid;
                 S.tiles = W.tiles;
-                S.entries = entries;
+                S.entries = ent;
                 S.sel = sel;
                 S.qd = qd;
                 S.q = q + (int64_t)q0 * d;
@@ -1271,7 +1300,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 ScanArgs A;
                 A.tiles = W.tiles;
                 A.ntiles = (int32_t)grid;
-                A.entries = entries;
+                A.entries = ent;
                 A.sel = sel;
                 A.q = q + (int64_t)q0 * d;
                 A.qd = qd;
@@ -1318,6 +1347,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         prof_begin(CAPS_STAGE_MERGE, st);
         int32_t *oi = out_ids + (int64_t)q0 * k;
         float *od = out_dist + (int64_t)q0 * k;
+        const int32_t *mcnt = mfma ? W.pcnt : nullptr;   // matrix-core lists are counted, plain ones padded
         Deferred D{};
         if (P.defer) {
             D.pos = W.dpos;
@@ -1329,14 +1359,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             D.perm = ix->perm;
         }
         if (k <= 16)
-            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0, D);
+            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                               k, ix->metric, oi, od, ncand + q0, D);
         else if (k <= 32)
-            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0, D);
+            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                               k, ix->metric, oi, od, ncand + q0, D);
         else
-            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, sel, cand, nb, m, k,
-                               ix->metric, oi, od, ncand + q0, D);
+            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                               k, ix->metric, oi, od, ncand + q0, D);
         prof_end(CAPS_STAGE_MERGE, st);
         CAPS_HIP(hipGetLastError());
     }
