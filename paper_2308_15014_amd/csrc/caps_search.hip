@@ -1239,7 +1239,9 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         // round is an approximate scan of the seed probes whose best
         // candidates are rescored exactly for the bound (k_seed_exact), and
         // the second scans every probe, deferring its pairs to the merge.
-        const int32_t s_seed = m >= 32 ? std::max(8, m / 16) : m;
+        // (the approximate seed pass is cheap per probe but its bound looser:
+        // half as many seed probes there)
+        const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 32 : 16)) : m;
         const bool seeded_exact = P.defer && s_seed < m;
         for (int round = 0; round < 2; round++) {
             const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
