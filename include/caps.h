@@ -219,6 +219,8 @@ enum {
     CAPS_STAGE_MERGE = 5,   /* per-query top-k merge */
     CAPS_STAGE_SEED = 6,    /* exact search on the matrix cores: approximate scan of the
                                first probes and the exact seed bound */
+    CAPS_STAGE_RESCUE = 7,  /* exact search on the matrix cores: rescan of the queries
+                               whose candidate pairs overflowed */
     CAPS_N_STAGES = 8
 };
 typedef struct {

@@ -78,7 +78,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", c_i64 * 8)]
 
 
-STAGES = ["prep", "route", "topm", "select", "scan", "merge", "seed"]
+STAGES = ["prep", "route", "topm", "select", "scan", "merge", "seed", "rescue"]
 
 # name -> (restype, argtypes); every symbol include/caps.h declares
 SIGNATURES = {

@@ -137,7 +137,7 @@ caps_status build_lowp(Index *ix, hipStream_t st);
 // one launch of the matrix-core scan over a sub-batch of nb queries
 struct LowpScan {
     int32_t nb, m, r;             // r: keys kept per (query, probe)
-    bool exact;                   // exact keys (mode 0) or approximate ones (mode 1)
+    int kind;                     // 0 approximate keys, 1 exact main pass, 2 exact rescue pass
     bool first_round;             // also round the queries (first launch of a sub-batch)
     int stage;                    // profiling stage of the launch (CAPS_STAGE_SCAN or _SEED)
     int64_t max_tiles;
@@ -150,10 +150,11 @@ struct LowpScan {
     float *qscale, *qaux;
     uint64_t *partials, *tau;
     int32_t *pcnt, *nsurv;
-    int32_t *dpos, *dcnt;         // exact keys: deferred pairs per query (null: rescored in the scan)
+    int32_t *dpos, *dcnt;         // exact main pass: deferred pairs per query and their count
     int32_t dcap;                 // capacity of each query's deferred list
+    int32_t *oflow;               // exact: per query, set by the main pass for the rescue pass
 };
-size_t lowp_scan_lds(const Index *ix, int r, bool exact);
+size_t lowp_scan_lds(const Index *ix, int r, int kind);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);
 caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
                        int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,

@@ -32,7 +32,8 @@ struct LowpArgs {
     int32_t *pcnt;              // keys written per (query, probe) (sorted, at most r)
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
-    int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count, or null
+    int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count
+    int32_t *oflow;             // exact: per query flag, set when its pairs did not fit (rescue pass input)
     int32_t m, h, b, r, metric, d, dcap, ntiles;   // ntiles: length of `tiles` (the grid's tile range)
     float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
 };
@@ -47,7 +48,8 @@ constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting resco
 
 struct LowpLds {
     size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, dhist, qnq, scnt, total;
-    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, bool exact, bool labels)
+    // kind: 0 approximate keys, 1 exact main pass (no buffers), 2 exact rescue pass
+    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, int kind, bool labels)
         : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), dhist(0), qnq(0), scnt(0),
           total(0) {
         size_t o = 0;
@@ -64,11 +66,11 @@ struct LowpLds {
         xw = take(sizeof(uint32_t) * kLCH);
         xn = take(sizeof(float) * kLCH);
         xsc = take(sizeof(float) * kLCH);
-        ring = take(exact ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
-        dhist = take(exact ? sizeof(int32_t) * kLNW * kLQPW : 0);
-        qnq = take(exact ? sizeof(float) * kLQB : 0);
+        ring = take(kind != 0 ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
+        dhist = take(kind == 1 ? sizeof(int32_t) * kLNW * kLQPW : 0);
+        qnq = take(kind != 0 ? sizeof(float) * kLQB : 0);
         scnt = take(sizeof(int32_t) * kLQB);
-        buf = take(sizeof(uint64_t) * (size_t)kLQB * cb);
+        buf = take(kind == 1 ? 0 : sizeof(uint64_t) * (size_t)kLQB * cb);
         xl = take((size_t)kLCH * (row_bytes + 16));
         total = take(16);
     }
@@ -215,9 +217,12 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // more of the row reads than one tile can.
 // Three workgroups per compute unit (at most 168 VGPRs) up to 128-element
 // rows without label tests, two otherwise (their state does not fit).
-template <int PREC, bool HAS_LABELS, int CB, int NS, bool EXACT>
+template <int PREC, bool HAS_LABELS, int CB, int NS, int KIND>
 __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS ? 2 : 3))) void k_scan_mfma(
     LowpArgs A) {
+    constexpr bool EXACT = KIND != 0;    // exact keys (bounds + exact rescoring)
+    constexpr bool DEFER = KIND == 1;    // main pass: passing pairs go to the deferred lists
+    constexpr bool RESCUE = KIND == 2;   // rescue pass: flagged queries only, rescored here
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
     constexpr int ES = Op::ES;
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row
     constexpr int PIECES = kLCH * V16;
     constexpr int UPT = (PIECES + kLNT - 1) / kLNT;      // pieces per thread per chunk
-    constexpr LowpLds L(ROWB, CB, EXACT, HAS_LABELS);
+    constexpr LowpLds L(ROWB, CB, KIND, HAS_LABELS);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t spo[kMaxHeight + 2];
     __shared__ uint32_t lvw[kLNW];
@@ -272,12 +277,17 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     if (lane < kLQPW && qbase + lane < nqt) {
         const int qi = qbase + lane;
         const int32_t slot = ent[qi];
-        my_qq = slot / A.m;
-        my_sel = A.sel[slot];
+        const int32_t qq = slot / A.m;
         qslot[qi] = slot;
-        if (HAS_LABELS) qds[qi] = A.qd[my_qq];
-        tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!RESCUE || A.oflow[qq]) {   // the rescue pass takes flagged queries only
+            my_qq = qq;
+            my_sel = A.sel[slot];
+            if (HAS_LABELS) qds[qi] = A.qd[my_qq];
+            tau[qi] = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
+    // rows with a query to scan: bit i for row qbase + i
+    const uint32_t active = (uint32_t)__builtin_amdgcn_ballot_w64(lane < kLQPW && my_qq >= 0);
     if (lane < kLQPW) {   // rows without a query too
         bcnt[qbase + lane] = 0;
         scnt[qbase + lane] = 0;
@@ -308,7 +318,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     for (int rr = 0; rr < 4; rr++) {
         const int qi = qbase + g * 4 + rr;
         rsel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
-        if (qi < nqt) {
+        if ((active >> (g * 4 + rr)) & 1u) {
             const int32_t qq = ent[qi] / A.m;
             const QDesc qd = A.qd[qq];
             rmask[rr] = qd.dmask;
@@ -358,7 +368,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
             const int qi = qbase + g * 4 + rr;
-            rtf[rr] = qi < nqt ? row_bound(tau[qi], EXACT ? qnq[qi] : 0.0f) : qnan;
+            rtf[rr] = ((active >> (qi - qbase)) & 1u) ? row_bound(tau[qi], EXACT ? qnq[qi] : 0.0f) : qnan;
         }
     };
     refresh_bounds();
@@ -366,6 +376,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 #pragma unroll
     for (int i = 0; i < kLNW; i++) lv |= lvw[i];
     lv = __builtin_amdgcn_readfirstlane(lv);
+    if (RESCUE && lv == 0) return;   // no flagged query in this tile (uniform)
     // chunk cursor (wave-uniform, kept in scalar registers): level j, first
     // row c0 of the chunk, end of the level
     auto po = [&](int i) { return __builtin_amdgcn_readfirstlane(spo[i]); };
@@ -440,23 +451,11 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         return pre_ok ? pt : qnan;
     };
 
-    // exact: rescoring of queued pairs, one per lane (lanes with v set)
+    // exact: the queued pairs, one per lane.  Main pass: appended to their
+    // queries' deferred lists (per-row ranks from an LDS histogram, one
+    // returning atomic per row); a query whose list is full is flagged for the
+    // rescue pass instead.  Rescue pass: rescored exactly here.
     int vhead = 0, vtail = 0;   // wave-uniform ring cursors
-    auto rescore = [&](bool v, uint32_t pos, int qi) {
-        if (!__builtin_amdgcn_ballot_w64(v)) return;
-        uint64_t key = ~0ull;
-        if (v) {
-            const int32_t qq = qslot[qi] / A.m;
-            const float sc = exact_score<(HAS_LABELS && NS < 8) ? 2 : 4>(A.vecs + (int64_t)pos * A.d,
-                                                                         A.q + (int64_t)qq * A.d, A.d, l2);
-            key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)A.perm[pos];
-        }
-        const bool qual = v && key < tau[qi];
-        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
-    };
-    // takes the next n queued pairs: with deferred lists, appends them to
-    // their queries' lists (one atomic per query) and rescores here only
-    // what no longer fits; otherwise rescores them all here
     auto drain = [&](int n) {
         wave_sync();   // ring entries written by this wave are visible
         const bool v = lane < n;
@@ -464,10 +463,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         const uint32_t pos = v ? ring_pos[slot] : 0u;
         const int qi = v ? (int)ring_row[slot] : qbase;
         vtail += n;
-        bool here = v;
-        if (A.dpos) {
-            // per-row counts in LDS: each pair's slot among its row's pairs,
-            // then one global atomic per row for the list offset
+        if (DEFER) {
             const int ri = qi - qbase;   // row of the wave, 0..15
             if (lane < kLQPW) dhist[lane] = 0;
             wave_sync();
@@ -477,11 +473,21 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             int base = 0;
             if (cnt > 0) base = atomicAdd(A.dcnt + my_qq, cnt);
             const int at = __shfl(base, ri, 64) + rank;
-            const bool fits = v && at < A.dcap;
-            if (fits) A.dpos[(int64_t)(qslot[qi] / A.m) * A.dcap + at] = (int32_t)pos;
-            here = v && !fits;
+            const int32_t qq = qslot[qi] / A.m;
+            if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = (int32_t)pos;
+            if (v && at >= A.dcap) A.oflow[qq] = 1;
         }
-        rescore(here, pos, qi);
+        if (RESCUE) {
+            uint64_t key = ~0ull;
+            if (v) {
+                const int32_t qq = qslot[qi] / A.m;
+                const float sc = exact_score<(HAS_LABELS && NS < 8) ? 2 : 4>(A.vecs + (int64_t)pos * A.d,
+                                                                             A.q + (int64_t)qq * A.d, A.d, l2);
+                key = ((uint64_t)f2ord(sc) << 32) | (uint32_t)A.perm[pos];
+            }
+            const bool qual = v && key < tau[qi];
+            append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
+        }
     };
 
     int cj = -1;
@@ -578,7 +584,23 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                     if (HAS_LABELS && qual)
                         qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
                                             A.slots + (int64_t)(c0 + pi) * kMaxLabels);
-                    if (EXACT) {
+                    if (DEFER) {
+                        // queue the pair for the deferred lists; when the ring
+                        // is full, its query goes to the rescue pass instead
+                        const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
+                        if (vhead - vtail + __popcll(qm) > kVRing) {
+                            if (qual) A.oflow[qslot[qi] / A.m] = 1;
+                            continue;
+                        }
+                        if (qual) {
+                            const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
+                            ring_pos[sl] = (uint32_t)(c0 + pi);
+                            ring_row[sl] = (uint32_t)qi;
+                        }
+                        vhead += __popcll(qm);
+                        continue;
+                    }
+                    if (RESCUE) {
                         // queue the pair; rescore once 64 are pending
                         const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
                         if (qual) {
@@ -618,16 +640,23 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             }
         }
     }
-    if (EXACT && vhead > vtail) drain(vhead - vtail);
+    if (EXACT)
+        while (vhead > vtail) drain(min(64, vhead - vtail));
     // ---- survivors per query
     if (count) {
         wave_sync();
         if (lane < kLQPW && my_qq >= 0 && scnt[qbase + lane]) atomicAdd(&A.nsurv[my_qq], scnt[qbase + lane]);
     }
     // ---- finalize my queries: best r sorted, partial list, shared bound
+    // (the main pass keeps no keys: its lists are empty)
+    if (DEFER) {
+        if (lane < kLQPW && qbase + lane < nqt) A.pcnt[qslot[qbase + lane]] = 0;
+        return;
+    }
     for (int i = 0; i < kLQPW; i++) {
         const int qi = qbase + i;
         if (qi >= nqt) break;
+        if (!((active >> i) & 1u)) continue;
         if (bcnt[qi] > 0) buf_reduce<CB>(buf, bcnt, tau, qi, r);
         const int c = bcnt[qi];
         const int32_t slot = qslot[qi];
@@ -646,27 +675,31 @@ typedef void (*LowpFn)(LowpArgs);
 // smaller buffers of small r let three workgroups share a compute unit's LDS.
 inline int lowp_cb(int r) { return r <= 16 ? 32 : r <= 48 ? 64 : 128; }
 
-template <int PREC, bool LAB, int NS, bool EX>
+template <int PREC, bool LAB, int NS, int KIND>
 LowpFn pick_cb(int r) {
+    if (KIND == 1) return k_scan_mfma<PREC, LAB, 32, NS, KIND>;   // (keeps no keys)
     const int cb = lowp_cb(r);
-    if (cb == 32) return k_scan_mfma<PREC, LAB, 32, NS, EX>;
-    if (cb == 64) return k_scan_mfma<PREC, LAB, 64, NS, EX>;
-    return k_scan_mfma<PREC, LAB, 128, NS, EX>;
+    if (cb == 32) return k_scan_mfma<PREC, LAB, 32, NS, KIND>;
+    if (cb == 64) return k_scan_mfma<PREC, LAB, 64, NS, KIND>;
+    return k_scan_mfma<PREC, LAB, 128, NS, KIND>;
 }
 
-template <int PREC, int NS, bool EX>
+template <int PREC, int NS, int KIND>
 LowpFn pick_lab(bool lab, int r) {
-    return lab ? pick_cb<PREC, true, NS, EX>(r) : pick_cb<PREC, false, NS, EX>(r);
+    return lab ? pick_cb<PREC, true, NS, KIND>(r) : pick_cb<PREC, false, NS, KIND>(r);
 }
 
-// the kernel for one precision and key kind (defined by caps_scan_inst.hip)
-template <int PREC, bool EX>
+// the kernel for one precision and kind (defined by caps_scan_inst.hip)
+template <int PREC, int KIND>
 LowpFn pick_ns(int ns, bool lab, int r);
-template <> LowpFn pick_ns<CAPS_PREC_BF16, false>(int, bool, int);
-template <> LowpFn pick_ns<CAPS_PREC_BF16, true>(int, bool, int);
-template <> LowpFn pick_ns<CAPS_PREC_FP16, false>(int, bool, int);
-template <> LowpFn pick_ns<CAPS_PREC_FP16, true>(int, bool, int);
-template <> LowpFn pick_ns<CAPS_PREC_FP8, false>(int, bool, int);
-template <> LowpFn pick_ns<CAPS_PREC_FP8, true>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, 0>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, 1>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, 2>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, 0>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, 1>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, 2>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, 0>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, 1>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, 2>(int, bool, int);
 
 }  // namespace caps

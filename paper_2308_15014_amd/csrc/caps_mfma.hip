@@ -228,15 +228,16 @@ __global__ __launch_bounds__(256) void k_merge_rerank(const uint64_t *__restrict
 }
 
 // ------------------------------------------------------------------ host
-template <bool EX>
+template <int EX>
 static LowpFn pick_prec(int prec, int ns, bool lab, int r) {
     if (prec == CAPS_PREC_BF16) return pick_ns<CAPS_PREC_BF16, EX>(ns, lab, r);
     if (prec == CAPS_PREC_FP16) return pick_ns<CAPS_PREC_FP16, EX>(ns, lab, r);
     return pick_ns<CAPS_PREC_FP8, EX>(ns, lab, r);
 }
 
-size_t lowp_scan_lds(const Index *ix, int r, bool exact) {
-    return LowpLds(ix->dpad * esize_of(ix->prec), lowp_cb(r), exact, ix->sch.label_vocab > 0).total + 64;
+size_t lowp_scan_lds(const Index *ix, int r, int kind) {
+    return LowpLds(ix->dpad * esize_of(ix->prec), kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0).total +
+           64;
 }
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
@@ -271,6 +272,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.dpos = S.dpos;
     A.dcnt = S.dcnt;
     A.dcap = S.dcap;
+    A.oflow = S.oflow;
     A.m = S.m;
     A.h = ix->h;
     A.b = ix->b;
@@ -287,9 +289,10 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.eta = (float)(6.0 * ix->dpad + 64.0) * 0x1p-24f;
     A.gam = (float)(8.0 * ix->dpad) * 0x1p-24f;
     const bool lab = ix->sch.label_vocab > 0;
-    const LowpFn fn = S.exact ? pick_prec<true>(ix->prec, ix->dpad / 32, lab, S.r)
-                              : pick_prec<false>(ix->prec, ix->dpad / 32, lab, S.r);
-    const size_t lds = lowp_scan_lds(ix, S.r, S.exact);
+    const LowpFn fn = S.kind == 0   ? pick_prec<0>(ix->prec, ix->dpad / 32, lab, S.r)
+                      : S.kind == 1 ? pick_prec<1>(ix->prec, ix->dpad / 32, lab, S.r)
+                                    : pick_prec<2>(ix->prec, ix->dpad / 32, lab, S.r);
+    const size_t lds = lowp_scan_lds(ix, S.r, S.kind);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(S.stage, st);
     const int64_t grid = (S.max_tiles + kXcds - 1) / kXcds * kXcds;

@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void k_seed_tau(const uint64_t *__restrict__ p
 // Seed bound for exact keys from an approximate scan of a query's first s
 // probes: the keep (<= 64) best approximate candidates are rescored exactly;
 // being valid candidates, their k-th best exact key bounds the final k-th key
-// from above (~0 when fewer than k).  One wave per query.
+// from above, and the bound is one past it (~0 when fewer than k).  One wave
+// per query.
 __global__ __launch_bounds__(256) void k_seed_exact(const uint64_t *__restrict__ partials,
                                                     const int32_t *__restrict__ pcnt,
                                                     const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
@@ -436,7 +437,9 @@ __global__ __launch_bounds__(256) void k_seed_exact(const uint64_t *__restrict__
     int rank = 0;   // among the wave's exact keys (distinct ids)
     for (int i = 0; i < n; i++) rank += readlane_u64(key, i) < key ? 1 : 0;
     const uint64_t at = __ballot(lane < n && rank == k - 1);
-    if (lane == 0) tau[qq] = at ? readlane_u64(key, __builtin_ctzll(at)) : ~0ull;
+    // (the bound admits keys below it; that k-th key is itself a candidate
+    // of the exact pass, which covers the seed probes too: one past it)
+    if (lane == 0) tau[qq] = at ? readlane_u64(key, __builtin_ctzll(at)) + 1 : ~0ull;
 }
 
 // Bucket starts, sizes and tile starts per partition (single workgroup).
@@ -878,6 +881,7 @@ static size_t scan_lds_bytes(int d, int k) {
 // rescored here with the plain scan's arithmetic.
 struct Deferred {
     const int32_t *pos, *cnt;   // null: none
+    const int32_t *oflow;       // queries rescanned by the rescue pass: their lists are ignored
     int32_t cap, d;
     const float *vecs, *q;      // FP32 CSR rows, the sub-batch's queries
     const int32_t *perm;
@@ -904,7 +908,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
         }
         lst[0] = key < lst[0] ? key : lst[0];
     };
-    if (D.pos) {
+    if (D.pos && !D.oflow[q]) {
         const int n = min(D.cnt[q], D.cap);
         const float *qr = D.q + (int64_t)q * D.d;
         for (int i = lane; i < n; i += 64) {
@@ -1030,6 +1034,7 @@ struct SearchWs {
     int32_t *cand, *entries, *entries2;   // entries2: class-grouped copy
     uint64_t *partials, *tau;
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
+    int32_t *oflow;             // exact matrix-core scan: queries for the rescue pass
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
     int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
@@ -1066,6 +1071,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.tau = ar.take<uint64_t>((size_t)sb);
     w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
+    w.oflow = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
@@ -1106,7 +1112,7 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
                          2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
                          sizeof(int32_t) * (size_t)m +
-                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 1) : 0) + sizeof(int4) * (size_t)m / 64 +
+                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 2) : 0) + sizeof(int4) * (size_t)m / 64 +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
@@ -1168,7 +1174,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
 
     const bool has_labels = ix->sch.label_vocab > 0;
-    const size_t lds = mfma ? lowp_scan_lds(ix, r, !lowp) : scan_lds_bytes(d, k);
+    const size_t lds = mfma ? lowp_scan_lds(ix, r, lowp ? 0 : 2) : scan_lds_bytes(d, k);
     const int qb = mfma ? lowp_qb() : scan_waves(k) * kQPW;
     const ScanFn scan_fn = pick_scan(ix->metric, has_labels, d, k);
     if (!probes_only && !mfma) {
@@ -1231,18 +1237,22 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             continue;
         }
         hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
-        if (P.defer) hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
+        if (P.defer) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
+            hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.oflow, (int64_t)nb, 0);
+        }
         prof_end(CAPS_STAGE_SELECT, st);
         // Two rounds: the first probes of every query (best first) give each
         // query a tight seed bound on its final r-th key; the remaining probes
         // are scanned against it.  Exact keys on the matrix cores: the first
-        // round is an approximate scan of the seed probes whose best
-        // candidates are rescored exactly for the bound (k_seed_exact), and
-        // the second scans every probe, deferring its pairs to the merge.
-        // (the approximate seed pass is cheap per probe but its bound looser:
-        // half as many seed probes there)
+        // round is an approximate scan of the seed probes (every probe when
+        // m < 32) whose best candidates are rescored exactly for the bound
+        // (k_seed_exact); the second scans every probe and defers its pairs
+        // to the merge, and a rescue pass rescans the queries whose pairs
+        // did not fit.  (The approximate seed pass is cheap per probe but
+        // its bound looser: half as many seed probes there.)
         const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 32 : 16)) : m;
-        const bool seeded_exact = P.defer && s_seed < m;
+        const bool seeded_exact = P.defer;
         for (int round = 0; round < 2; round++) {
             const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
             const int32_t r1 = round == 0 ? s_seed : m;
@@ -1276,7 +1286,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.nb = nb;
                 S.m = m;
                 S.r = r;
-                S.exact = !lowp && !seed_pass;
+                S.kind = lowp || seed_pass ? 0 : 1;
                 S.first_round = round == 0;
                 S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
                 S.max_tiles = grid;
@@ -1292,12 +1302,19 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.tau = tau;
                 S.pcnt = W.pcnt;
                 S.nsurv = out_nsurv && !seed_pass ? nsurv + q0 : nullptr;   // counted only when asked for
-                const bool defer_now = seeded_exact && round == 1;
-                S.dpos = defer_now ? W.dpos : nullptr;
-                S.dcnt = defer_now ? W.dcnt : nullptr;
+                S.dpos = W.dpos;
+                S.dcnt = W.dcnt;
                 S.dcap = kDeferCap;
+                S.oflow = W.oflow;
                 const caps_status ls = lowp_scan(ix, S, st);
                 if (ls != CAPS_OK) return ls;
+                if (S.kind == 1) {   // rescue pass over the same tiles: flagged queries only
+                    S.kind = 2;
+                    S.nsurv = nullptr;
+                    S.stage = CAPS_STAGE_RESCUE;
+                    const caps_status rs = lowp_scan(ix, S, st);
+                    if (rs != CAPS_OK) return rs;
+                }
             } else {
                 ScanArgs A;
                 A.tiles = W.tiles;
@@ -1354,6 +1371,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         if (P.defer) {
             D.pos = W.dpos;
             D.cnt = W.dcnt;
+            D.oflow = W.oflow;
             D.cap = kDeferCap;
             D.d = d;
             D.vecs = ix->vecs;
