@@ -153,6 +153,7 @@ struct LowpScan {
     int32_t *dpos, *dcnt;         // exact main pass: deferred pairs per query and their count
     int32_t dcap;                 // capacity of each query's deferred list
     int32_t *oflow;               // exact: per query, set by the main pass for the rescue pass
+    const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
 };
 size_t lowp_scan_lds(const Index *ix, int r, int kind);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);

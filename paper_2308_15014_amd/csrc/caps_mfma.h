@@ -34,6 +34,7 @@ struct LowpArgs {
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
     int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count
     int32_t *oflow;             // exact: per query flag, set when its pairs did not fit (rescue pass input)
+    const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
     int32_t m, h, b, r, metric, d, dcap, ntiles;   // ntiles: length of `tiles` (the grid's tile range)
     float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
 };
@@ -239,8 +240,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     __shared__ uint32_t lvw[kLNW];
     __shared__ float qmx[2][kLNW];
 
-    const int tile = xcd_tile(blockIdx.x, A.ntiles);
-    if (tile < 0) return;
+    int tile;
+    if (RESCUE) {   // the tiles holding a flagged query, listed by k_rescue_tiles
+        if ((int)blockIdx.x >= *A.rcount) return;
+        tile = A.rlist[blockIdx.x];
+    } else {
+        tile = xcd_tile(blockIdx.x, A.ntiles);
+        if (tile < 0) return;
+    }
     const int4 dsc = A.tiles[tile];
     if (dsc.z <= 0) return;
     const int p = dsc.x;
@@ -298,6 +305,10 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) wor |= __shfl_xor(wor, o, 64);
         if (lane == 0) lvw[w] = wor;
+    }
+    if (RESCUE) {   // leave early when no query of the tile is flagged (uniform)
+        __syncthreads();
+        if ((lvw[0] | lvw[1] | lvw[2] | lvw[3]) == 0) return;
     }
     // MFMA A operands: query row qbase + lane%16, K slice (lane/16)*8 of each step
     VT a[NS];
@@ -376,7 +387,6 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 #pragma unroll
     for (int i = 0; i < kLNW; i++) lv |= lvw[i];
     lv = __builtin_amdgcn_readfirstlane(lv);
-    if (RESCUE && lv == 0) return;   // no flagged query in this tile (uniform)
     // chunk cursor (wave-uniform, kept in scalar registers): level j, first
     // row c0 of the chunk, end of the level
     auto po = [&](int i) { return __builtin_amdgcn_readfirstlane(spo[i]); };
@@ -528,6 +538,8 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             wave_sync();   // the wave's own bound slots, read below
             refresh_bounds();
         }
+
+        if (active == 0) continue;   // a wave without queries only helps stage the chunks
 
         // ---- MFMA: my 16 queries x the chunk's 64 points
         f32x4 acc[4];

@@ -273,6 +273,8 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.dcnt = S.dcnt;
     A.dcap = S.dcap;
     A.oflow = S.oflow;
+    A.rlist = S.rlist;
+    A.rcount = S.rcount;
     A.m = S.m;
     A.h = ix->h;
     A.b = ix->b;

@@ -494,6 +494,20 @@ __global__ __launch_bounds__(256) void k_tile_desc(const int32_t *__restrict__ t
     tiles[t] = dsc;
 }
 
+// Tiles of the exact main pass that hold a flagged query: listed (in any
+// order) for the rescue pass.  One thread per tile.
+__global__ __launch_bounds__(256) void k_rescue_tiles(const int4 *__restrict__ tiles, int32_t ntiles,
+                                                      const int32_t *__restrict__ entries, int32_t m,
+                                                      const int32_t *__restrict__ oflow, int32_t *__restrict__ rlist,
+                                                      int32_t *__restrict__ rcount) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int4 dsc = tiles[t];
+    bool hit = false;
+    for (int i = 0; i < dsc.z && !hit; i++) hit = oflow[entries[dsc.y + i] / m] != 0;
+    if (hit) rlist[atomicAdd(rcount, 1)] = t;
+}
+
 // ------------------------------------------------------------------ scan
 struct ScanArgs {
     const int4 *tiles;     // per tile: partition, first entry, entries (0: no tile)
@@ -1035,6 +1049,7 @@ struct SearchWs {
     uint64_t *partials, *tau;
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *oflow;             // exact matrix-core scan: queries for the rescue pass
+    int32_t *rlist, *rcount;    // exact matrix-core scan: tiles for the rescue pass
     int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
     int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
@@ -1072,6 +1087,8 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.oflow = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
+    w.rlist = defer ? ar.take<int32_t>(tile_cap(sb, m, b)) : nullptr;
+    w.rcount = defer ? ar.take<int32_t>(1) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
@@ -1112,7 +1129,8 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          sizeof(uint64_t) * (size_t)m * P.r + sizeof(QDesc) + sizeof(uint64_t) +
                          2 * sizeof(int32_t) * (size_t)b / kBucketQ + P.qlow_row + 5 * sizeof(float) + 64 +
                          sizeof(int32_t) * (size_t)m +
-                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 2) : 0) + sizeof(int4) * (size_t)m / 64 +
+                         (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 2 + m / 64) : 0) +
+                         sizeof(int4) * (size_t)m / 64 +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
@@ -1308,8 +1326,13 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 S.oflow = W.oflow;
                 const caps_status ls = lowp_scan(ix, S, st);
                 if (ls != CAPS_OK) return ls;
-                if (S.kind == 1) {   // rescue pass over the same tiles: flagged queries only
+                if (S.kind == 1) {   // rescue pass over the tiles that hold a flagged query
+                    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, W.rcount, (int64_t)1, 0);
+                    hipLaunchKernelGGL(k_rescue_tiles, dim3(nblocks(grid, 256)), dim3(256), 0, st, W.tiles,
+                                       (int32_t)grid, ent, m, W.oflow, W.rlist, W.rcount);
                     S.kind = 2;
+                    S.rlist = W.rlist;
+                    S.rcount = W.rcount;
                     S.nsurv = nullptr;
                     S.stage = CAPS_STAGE_RESCUE;
                     const caps_status rs = lowp_scan(ix, S, st);
