@@ -123,8 +123,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md, 'Sharding').", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
+              "(sharding is described in the design notes).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -304,12 +304,16 @@ def main():
 
     if args.calib_copy:
         # a plain streaming kernel of known traffic (reads 512 MiB, writes
-        # 512 MiB) for scaling the TCC byte counters
+        # 512 MiB) for scaling the TCC byte counters; a 1 GiB fill between
+        # the source's fill and the copy evicts the source from the 256 MB
+        # Infinity Cache, so that the copy's reads reach HBM
         a = torch.ones(128 * 2**20, dtype=torch.float32, device=dev)
+        flush = torch.zeros(256 * 2**20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
-        del a, b
+        del a, b, flush
 
     out = {
         "metric": METRIC,
