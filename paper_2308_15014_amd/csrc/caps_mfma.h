@@ -48,10 +48,12 @@ constexpr int kTauRefresh = 8;   // chunks between reads of the shared per-query
 constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting rescoring
 
 struct LowpLds {
-    size_t xl, xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, dhist, qnq, scnt, total;
-    // kind: 0 approximate keys, 1 exact main pass (no buffers), 2 exact rescue pass
-    __host__ __device__ constexpr LowpLds(int row_bytes, int cb, int kind, bool labels)
-        : xl(0), xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), dhist(0), qnq(0), scnt(0),
+    size_t xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, dhist, qnq, scnt, total;
+    // kind: 0 approximate keys, 1 exact main pass (no buffers), 2 exact rescue pass.
+    // The chunk tiles themselves are static arrays of the kernel (two of
+    // kLCH rows); the per-point arrays here are double buffered alike.
+    __host__ __device__ constexpr LowpLds(int cb, int kind, bool labels)
+        : xw(0), xn(0), xsc(0), buf(0), bcnt(0), tau(0), qslot(0), qd(0), ring(0), dhist(0), qnq(0), scnt(0),
           total(0) {
         size_t o = 0;
         const auto take = [&o](size_t bytes) {
@@ -64,15 +66,14 @@ struct LowpLds {
         tau = take(sizeof(uint64_t) * kLQB);
         qslot = take(sizeof(int32_t) * kLQB);
         qd = take(labels ? sizeof(QDesc) * kLQB : 0);
-        xw = take(sizeof(uint32_t) * kLCH);
-        xn = take(sizeof(float) * kLCH);
-        xsc = take(sizeof(float) * kLCH);
+        xw = take(sizeof(uint32_t) * 2 * kLCH);
+        xn = take(sizeof(float) * 2 * kLCH);
+        xsc = take(sizeof(float) * 2 * kLCH);
         ring = take(kind != 0 ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
         dhist = take(kind == 1 ? sizeof(int32_t) * kLNW * kLQPW : 0);
         qnq = take(kind != 0 ? sizeof(float) * kLQB : 0);
         scnt = take(sizeof(int32_t) * kLQB);
         buf = take(kind == 1 ? 0 : sizeof(uint64_t) * (size_t)kLQB * cb);
-        xl = take((size_t)kLCH * (row_bytes + 16));
         total = take(16);
     }
 };
@@ -230,12 +231,21 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     constexpr int KSTEP_BYTES = 32 * ES;                 // one MFMA K-step of a row
     constexpr int LANE_BYTES = 8 * ES;                   // one lane's slice of a K-step
     constexpr int ROWB = NS * KSTEP_BYTES;               // bytes per CSR row of the copy
-    constexpr int XSTRIDE = ROWB + 16;                   // padded LDS row (bank spread)
-    constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row
-    constexpr int PIECES = kLCH * V16;
-    constexpr int UPT = (PIECES + kLNT - 1) / kLNT;      // pieces per thread per chunk
-    constexpr LowpLds L(ROWB, CB, KIND, HAS_LABELS);
+    constexpr int V16 = ROWB / 16;                       // 16-byte pieces per row (a power of two)
+    constexpr int NDMA = V16;                            // 1 KB direct loads per chunk (64 lanes x 16 B)
+    constexpr int UPW = (NDMA + kLNW - 1) / kLNW;        // of them per wave
+    // Tile rows are unpadded; piece p of row r sits at position p ^ swz(r), so
+    // that the 16 rows one operand read touches (same K slice) fall in
+    // distinct banks: rows of >= 256 bytes XOR their low four row bits,
+    // shorter rows (RPL of them share a 256-byte bank line) the bits above.
+    constexpr int RPL = ROWB >= 256 ? 1 : 256 / ROWB;
+    constexpr int SWZ = ROWB >= 256 ? 15 : V16 - 1;
+    constexpr LowpLds L(CB, KIND, HAS_LABELS);
     extern __shared__ __align__(16) unsigned char smem[];
+    // the two chunk tiles (ping-pong): distinct arrays, so that the compiler
+    // can tell the reads of one from the direct loads into the other
+    __shared__ __align__(16) uint8_t xt0[kLCH * ROWB];
+    __shared__ __align__(16) uint8_t xt1[kLCH * ROWB];
     __shared__ int32_t spo[kMaxHeight + 2];
     __shared__ uint32_t lvw[kLNW];
     __shared__ float qmx[2][kLNW];
@@ -254,7 +264,6 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     const int nqt = dsc.z;
     const int32_t *ent = A.entries + dsc.y;
     const int h = A.h, r = A.r;
-    uint8_t *xl = smem + L.xl;
     uint32_t *xw = reinterpret_cast<uint32_t *>(smem + L.xw);
     float *xn = reinterpret_cast<float *>(smem + L.xn);
     float *xsc = reinterpret_cast<float *>(smem + L.xsc);
@@ -322,6 +331,16 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     }
     // per-lane epilogue rows: (lane/16)*4 + rr of the wave's 16 queries
     const int g = lane >> 4;
+    // MFMA B operands: row lane%16 of each 16-row block, K slice g of each
+    // step; per step the lane's byte offset in a tile (same for every block,
+    // whose 16 rows span whole swizzle periods)
+    uint32_t xoff[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int r16 = lane & 15;
+        const int byte = s * KSTEP_BYTES + g * LANE_BYTES;
+        xoff[s] = (uint32_t)(r16 * ROWB + 16 * ((byte / 16) ^ ((r16 / RPL) & SWZ)) + byte % 16);
+    }
     uint32_t rsel[4], rmask[4], rval[4];
     float rqs[4], rtf[4];
     float qa = 0.0f, qb = 0.0f;   // exact: largest |q| and |q - q~| + gam |q~| of my rows
@@ -403,46 +422,50 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         if (c0 >= end) next_level(j, c0, end);
     };
 
-    // register staging of one chunk: UPT 16-byte pieces per thread, plus the
-    // per-point word / score-term inputs / scale stored by the first 64
-    // threads.  Rows past the level's end load the level's last row (in
-    // bounds); their columns are masked by a NaN score term.  Only loads
-    // happen here: whatever consumes a loaded value runs after the next
-    // barrier (`point_term` and the LDS stores), so the loads stay in flight
-    // while the current chunk is scored.  `wsrc`: the packed words, or any
-    // array of n words when there are none (then unused).
+    // Staging of one chunk: NDMA direct global->LDS loads of 16 bytes per
+    // lane (lane L of load i fills tile bytes 1024 i + 16 L, i.e. row
+    // (64 i + L) / V16, position (64 i + L) % V16), issued one chunk ahead
+    // into the other tile; rows past the level's end load the level's last
+    // row (in bounds) and are masked by a NaN score term.  Wave 0 also loads
+    // the per-point word / score-term inputs / scale into registers; they
+    // are stored after the chunk's barrier wait.  `wsrc`: the packed words,
+    // or any array of n words when there are none (then unused).
+    uint32_t voff[UPW];   // per lane and load: byte offset of its piece in the chunk's rows
+    int vrow[UPW];        // per lane and load: its tile row
+#pragma unroll
+    for (int u = 0; u < UPW; u++) {
+        const int slot = 64 * (w + kLNW * u) + lane;
+        const int row = slot / V16;
+        vrow[u] = row;
+        voff[u] = (uint32_t)(row * ROWB + 16 * ((slot % V16) ^ ((row / RPL) & SWZ)));
+    }
     const uint32_t *wsrc = has_dense ? A.words : reinterpret_cast<const uint32_t *>(A.xnorm);
-    typedef uint32_t PreT __attribute__((ext_vector_type(4 * UPT)));   // stays in VGPRs
-    PreT pre = {};
     uint32_t pre_w = 0;
     float pre_x = 0.0f, pre_e = 0.0f, pre_l = 0.0f, pre_s = 1.0f;
     bool pre_ok = false;
-    auto fetch = [&](int32_t c0, int cn) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.lvecs + (int64_t)c0 * ROWB);
+    auto fetch = [&](int32_t c0, int cn, uint8_t *dst) {
+        const uint8_t *base = A.lvecs + (int64_t)c0 * ROWB;
 #pragma unroll
-        for (int u = 0; u < UPT; u++) {
-            const int e = t + u * kLNT;
-            if (PIECES % kLNT == 0 || e < PIECES) {
-                const int row = min(e / V16, cn - 1);
-                const uint4 v = src[row * V16 + e % V16];
-                pre[4 * u + 0] = v.x;
-                pre[4 * u + 1] = v.y;
-                pre[4 * u + 2] = v.z;
-                pre[4 * u + 3] = v.w;
+        for (int u = 0; u < UPW; u++) {
+            const int i = w + kLNW * u;   // wave-uniform
+            if (NDMA % kLNW == 0 || i < NDMA) {
+                uint32_t off = voff[u];
+                if (cn < kLCH) off -= (uint32_t)(max(vrow[u] - (cn - 1), 0) * ROWB);
+                __builtin_amdgcn_global_load_lds(base + off, (__attribute__((address_space(3))) void *)(dst + 1024 * i),
+                                                 16, 0, 0);
             }
         }
-        // every thread loads (only the first 64 store): no load is skipped on
-        // any path, so the compiler can count the loads in flight exactly
-        const int pt_row = min(t & (kLCH - 1), cn - 1);
-        const int row = c0 + pt_row;
-        pre_x = A.xnorm[row];
-        if (EXACT) {
-            pre_e = A.lerr[row];
-            pre_l = A.lnrm[row];
+        if (w == 0) {
+            const int row = c0 + min(lane, cn - 1);
+            pre_x = A.xnorm[row];
+            if (EXACT) {
+                pre_e = A.lerr[row];
+                pre_l = A.lnrm[row];
+            }
+            pre_w = wsrc[row];
+            if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
+            pre_ok = lane < cn;
         }
-        pre_w = wsrc[row];
-        if (PREC == CAPS_PREC_FP8) pre_s = A.lscale[row];
-        pre_ok = t < cn;
     };
     // per-point term of the staged row (NaN for a padding row)
     auto point_term = [&]() {
@@ -503,155 +526,157 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     int cj = -1;
     int32_t cc0 = 0, cend = 0;
     next_level(cj, cc0, cend);
-    if (cj <= h) fetch(cc0, min(kLCH, cend - cc0));
+    if (cj <= h) fetch(cc0, min(kLCH, cend - cc0), xt0);
     int nchunk = 0;
 
-    while (cj <= h) {
+    // One chunk: tile `cur` (loaded by the previous step), point arrays `pb`;
+    // loads the next chunk into `nxt`.  Returns whether there is one.
+    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb) -> bool {
         const int j = cj;
         const int32_t c0 = cc0;
         const int cn = min(kLCH, cend - c0);
-        __syncthreads();   // previous chunk fully consumed
-#pragma unroll
-        for (int u = 0; u < UPT; u++) {
-            const int e = t + u * kLNT;
-            if (PIECES % kLNT == 0 || e < PIECES)
-                *reinterpret_cast<uint4 *>(xl + (e / V16) * XSTRIDE + (e % V16) * 16) =
-                    make_uint4(pre[4 * u], pre[4 * u + 1], pre[4 * u + 2], pre[4 * u + 3]);
+        const uint32_t *xwp = xw + pb * kLCH;
+        const float *xnp = xn + pb * kLCH;
+        const float *xscp = xsc + pb * kLCH;
+        if (w == 0) {
+            xw[pb * kLCH + lane] = has_dense ? pre_w : 0u;
+            xn[pb * kLCH + lane] = point_term();
+            xsc[pb * kLCH + lane] = pre_s;
         }
-        if (t < kLCH) {
-            xw[t] = has_dense ? pre_w : 0u;
-            xn[t] = point_term();
-            xsc[t] = pre_s;
-        }
+        // this wave's direct loads into `cur` have landed; after the barrier
+        // every wave's have, and every wave is done with `nxt` (read by the
+        // previous step) and with the point arrays `pb` written two steps ago
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __syncthreads();
         // the shared bounds are read before the next chunk's loads are issued
         // and used after them, so that their latency overlaps too
-        // (every lane loads every chunk and the last chunk fetches itself
-        // again, for the same reason as in `fetch`)
         const bool refresh = (++nchunk % kTauRefresh) == 0;
-        const uint64_t gt = __hip_atomic_load(A.tau + max(my_qq, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t gt = ~0ull;
+        if (refresh) gt = __hip_atomic_load(A.tau + max(my_qq, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         advance(cj, cc0, cend);
         const bool more = cj <= h;
-        fetch(more ? cc0 : c0, more ? min(kLCH, cend - cc0) : cn);
-        __syncthreads();
+        if (more) fetch(cc0, min(kLCH, cend - cc0), nxt);
         if (refresh) {
             if (lane < kLQPW && my_qq >= 0 && gt < tau[qbase + lane]) tau[qbase + lane] = gt;
             wave_sync();   // the wave's own bound slots, read below
             refresh_bounds();
         }
+        if (active == 0) return more;   // a wave without queries only helps stage the chunks
 
-        if (active == 0) continue;   // a wave without queries only helps stage the chunks
+            // ---- MFMA: my 16 queries x the chunk's 64 points
+            f32x4 acc[4];
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+#pragma unroll
+                for (int bb = 0; bb < 4; bb++) acc[bb] = Op::mma(a[s], Op::load(cur + bb * 16 * ROWB + xoff[s]), acc[bb]);
 
-        // ---- MFMA: my 16 queries x the chunk's 64 points
-        f32x4 acc[4];
+            // ---- epilogue, one 16-point block at a time
+            float tfj[4];
 #pragma unroll
-        for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        const uint8_t *xb = xl + (lane & 15) * XSTRIDE + (lane >> 4) * LANE_BYTES;
+            for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
 #pragma unroll
-        for (int s = 0; s < NS; s++)
-#pragma unroll
-            for (int bb = 0; bb < 4; bb++)
-                acc[bb] = Op::mma(a[s], Op::load(xb + bb * 16 * XSTRIDE + s * KSTEP_BYTES), acc[bb]);
-
-        // ---- epilogue, one 16-point block at a time
-        float tfj[4];
-#pragma unroll
-        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
-#pragma unroll
-        for (int bb = 0; bb < 4; bb++) {
-            const int pi = bb * 16 + (lane & 15);
-            const uint32_t pw = xw[pi];
-            const float pn = xn[pi];
-            const float ps = xsc[pi];
-            float esc[4];
-            uint64_t hit[4];
-#pragma unroll
-            for (int rr = 0; rr < 4; rr++) {
-                float dd = acc[bb][rr];
-                if (PREC == CAPS_PREC_FP8) dd = dd * ps * rqs[rr];
-                esc[rr] = fmaf(cm, dd, pn);
-                // two single-compare ballots: each is one v_cmp into an SGPR pair
-                hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]) &
-                          __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
-            }
-            if (count) {   // survivors of the exact filter (statistics only)
+            for (int bb = 0; bb < 4; bb++) {
+                const int pi = bb * 16 + (lane & 15);
+                const uint32_t pw = xwp[pi];
+                const float pn = xnp[pi];
+                const float ps = xscp[pi];
+                float esc[4];
+                uint64_t hit[4];
 #pragma unroll
                 for (int rr = 0; rr < 4; rr++) {
-                    bool ok = pi < cn && ((rsel[rr] >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
-                    if (HAS_LABELS && ok) {
-                        const int qi = qbase + g * 4 + rr;
-                        ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
-                                          A.slots + (int64_t)(c0 + pi) * kMaxLabels);
-                    }
-                    if (ok) atomicAdd(scnt + qbase + g * 4 + rr, 1);
+                    float dd = acc[bb][rr];
+                    if (PREC == CAPS_PREC_FP8) dd = dd * ps * rqs[rr];
+                    esc[rr] = fmaf(cm, dd, pn);
+                    // two single-compare ballots: each is one v_cmp into an SGPR pair
+                    hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]) &
+                              __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
                 }
-            }
-            if (hit[0] | hit[1] | hit[2] | hit[3]) {
-                bool moved = false;
+                if (count) {   // survivors of the exact filter (statistics only)
 #pragma unroll
-                for (int rr = 0; rr < 4; rr++) {   // wave-uniform test per row group
-                    if (!hit[rr]) continue;
-                    // lanes 16g..16g+15 hold row 4g+rr: one query per 16-lane group
-                    const int qi = qbase + g * 4 + rr;
-                    bool qual = (hit[rr] >> lane) & 1ull;
-                    if (HAS_LABELS && qual)
-                        qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
-                                            A.slots + (int64_t)(c0 + pi) * kMaxLabels);
-                    if (DEFER) {
-                        // queue the pair for the deferred lists; when the ring
-                        // is full, its query goes to the rescue pass instead
-                        const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
-                        if (vhead - vtail + __popcll(qm) > kVRing) {
-                            if (qual) A.oflow[qslot[qi] / A.m] = 1;
+                    for (int rr = 0; rr < 4; rr++) {
+                        bool ok = pi < cn && ((rsel[rr] >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
+                        if (HAS_LABELS && ok) {
+                            const int qi = qbase + g * 4 + rr;
+                            ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                              A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                        }
+                        if (ok) atomicAdd(scnt + qbase + g * 4 + rr, 1);
+                    }
+                }
+                if (hit[0] | hit[1] | hit[2] | hit[3]) {
+                    bool moved = false;
+#pragma unroll
+                    for (int rr = 0; rr < 4; rr++) {   // wave-uniform test per row group
+                        if (!hit[rr]) continue;
+                        // lanes 16g..16g+15 hold row 4g+rr: one query per 16-lane group
+                        const int qi = qbase + g * 4 + rr;
+                        bool qual = (hit[rr] >> lane) & 1ull;
+                        if (HAS_LABELS && qual)
+                            qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
+                                                A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                        if (DEFER) {
+                            // queue the pair for the deferred lists; when the ring
+                            // is full, its query goes to the rescue pass instead
+                            const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
+                            if (vhead - vtail + __popcll(qm) > kVRing) {
+                                if (qual) A.oflow[qslot[qi] / A.m] = 1;
+                                continue;
+                            }
+                            if (qual) {
+                                const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
+                                ring_pos[sl] = (uint32_t)(c0 + pi);
+                                ring_row[sl] = (uint32_t)qi;
+                            }
+                            vhead += __popcll(qm);
                             continue;
                         }
-                        if (qual) {
-                            const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
-                            ring_pos[sl] = (uint32_t)(c0 + pi);
-                            ring_row[sl] = (uint32_t)qi;
+                        if (RESCUE) {
+                            // queue the pair; rescore once 64 are pending
+                            const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
+                            if (qual) {
+                                const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
+                                ring_pos[sl] = (uint32_t)(c0 + pi);
+                                ring_row[sl] = (uint32_t)qi;
+                            }
+                            vhead += __popcll(qm);
+                            if (vhead - vtail >= 64) {
+                                drain(64);
+                                moved = true;
+                            }
+                            continue;
                         }
-                        vhead += __popcll(qm);
-                        continue;
-                    }
-                    if (RESCUE) {
-                        // queue the pair; rescore once 64 are pending
-                        const uint64_t qm = __builtin_amdgcn_ballot_w64(qual);
-                        if (qual) {
-                            const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
-                            ring_pos[sl] = (uint32_t)(c0 + pi);
-                            ring_row[sl] = (uint32_t)qi;
-                        }
-                        vhead += __popcll(qm);
-                        if (vhead - vtail >= 64) {
-                            drain(64);
+                        // the score bound admits ties with the current bound key;
+                        // such keys are no better than it and never reach the final r
+                        const uint64_t key = ((uint64_t)f2ord(canon0(esc[rr])) << 32) | (uint32_t)(c0 + pi);
+                        const uint64_t gm = __builtin_amdgcn_ballot_w64(qual) & (0xFFFFull << (16 * g));
+                        const int cnt = __popcll(gm);
+                        const int c = bcnt[qi];
+                        if (__builtin_amdgcn_ballot_w64(c + cnt > CB) == 0) {
+                            // every group's keys fit: direct slots, one count update per group
+                            if (qual) buf[qi * CB + c + __popcll(gm & lanemask_lt())] = key;
+                            if ((lane & 15) == 0 && cnt) bcnt[qi] = c + cnt;
+                            wave_sync();
+                        } else {
+                            wave_sync();
+                            append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
                             moved = true;
                         }
-                        continue;
                     }
-                    // the score bound admits ties with the current bound key;
-                    // such keys are no better than it and never reach the final r
-                    const uint64_t key = ((uint64_t)f2ord(canon0(esc[rr])) << 32) | (uint32_t)(c0 + pi);
-                    const uint64_t gm = __builtin_amdgcn_ballot_w64(qual) & (0xFFFFull << (16 * g));
-                    const int cnt = __popcll(gm);
-                    const int c = bcnt[qi];
-                    if (__builtin_amdgcn_ballot_w64(c + cnt > CB) == 0) {
-                        // every group's keys fit: direct slots, one count update per group
-                        if (qual) buf[qi * CB + c + __popcll(gm & lanemask_lt())] = key;
-                        if ((lane & 15) == 0 && cnt) bcnt[qi] = c + cnt;
-                        wave_sync();
-                    } else {
-                        wave_sync();
-                        append_keys<CB>(qual, qi, key, buf, bcnt, tau, r);
-                        moved = true;
-                    }
-                }
-                if (moved) {   // bounds may have tightened
-                    refresh_bounds();
+                    if (moved) {   // bounds may have tightened
+                        refresh_bounds();
 #pragma unroll
-                    for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                    }
                 }
             }
+
+        return more;
+    };
+    if (cj <= h)
+        while (step(xt0, xt1, 0) && step(xt1, xt0, 1)) {
         }
-    }
     if (EXACT)
         while (vhead > vtail) drain(min(64, vhead - vtail));
     // ---- survivors per query

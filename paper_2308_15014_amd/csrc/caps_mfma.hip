@@ -236,8 +236,7 @@ static LowpFn pick_prec(int prec, int ns, bool lab, int r) {
 }
 
 size_t lowp_scan_lds(const Index *ix, int r, int kind) {
-    return LowpLds(ix->dpad * esize_of(ix->prec), kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0).total +
-           64;
+    return LowpLds(kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0).total + 64;
 }
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
