@@ -217,10 +217,12 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // bounds rarely tighten within a tile), they are appended to their queries'
 // lists in global memory and rescored by the merge, which overlaps many
 // more of the row reads than one tile can.
-// Three workgroups per compute unit (at most 168 VGPRs) up to 128-element
-// rows without label tests, two otherwise (their state does not fit).
+// Register budget per SIMD: four waves (at most 128 VGPRs) for the exact
+// main pass up to 128-element rows without label tests (it keeps no key
+// buffers), three for the other kinds, two with label tests or longer rows
+// (their state does not fit).
 template <int PREC, bool HAS_LABELS, int CB, int NS, int KIND>
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS ? 2 : 3))) void k_scan_mfma(
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS ? 2 : KIND == 1 ? 4 : 3))) void k_scan_mfma(
     LowpArgs A) {
     constexpr bool EXACT = KIND != 0;    // exact keys (bounds + exact rescoring)
     constexpr bool DEFER = KIND == 1;    // main pass: passing pairs go to the deferred lists
@@ -567,10 +569,18 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             f32x4 acc[4];
 #pragma unroll
             for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            // the four B operands of a K-step are read before its products,
+            // so that one wait covers them (the order is kept by the
+            // scheduling barrier)
 #pragma unroll
-            for (int s = 0; s < NS; s++)
+            for (int s = 0; s < NS; s++) {
+                VT bfr[4];
 #pragma unroll
-                for (int bb = 0; bb < 4; bb++) acc[bb] = Op::mma(a[s], Op::load(cur + bb * 16 * ROWB + xoff[s]), acc[bb]);
+                for (int bb = 0; bb < 4; bb++) bfr[bb] = Op::load(cur + bb * 16 * ROWB + xoff[s]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int bb = 0; bb < 4; bb++) acc[bb] = Op::mma(a[s], bfr[bb], acc[bb]);
+            }
 
             // ---- epilogue, one 16-point block at a time
             float tfj[4];
