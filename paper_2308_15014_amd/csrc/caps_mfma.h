@@ -219,10 +219,11 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // more of the row reads than one tile can.
 // Register budget per SIMD: four waves (at most 128 VGPRs) for the exact
 // main pass up to 128-element rows without label tests (it keeps no key
-// buffers), three for the other kinds, two with label tests or longer rows
-// (their state does not fit).
+// buffers), three for the approximate kind, two for the rescue pass (few
+// tiles, looped) and with label tests or longer rows (their state does not
+// fit).
 template <int PREC, bool HAS_LABELS, int CB, int NS, int KIND>
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS ? 2 : KIND == 1 ? 4 : 3))) void k_scan_mfma(
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS || KIND == 2 ? 2 : KIND == 1 ? 4 : 3))) void k_scan_mfma(
     LowpArgs A) {
     constexpr bool EXACT = KIND != 0;    // exact keys (bounds + exact rescoring)
     constexpr bool DEFER = KIND == 1;    // main pass: passing pairs go to the deferred lists
@@ -252,14 +253,12 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     __shared__ uint32_t lvw[kLNW];
     __shared__ float qmx[2][kLNW];
 
-    int tile;
-    if (RESCUE) {   // the tiles holding a flagged query, listed by k_rescue_tiles
-        if ((int)blockIdx.x >= *A.rcount) return;
-        tile = A.rlist[blockIdx.x];
-    } else {
-        tile = xcd_tile(blockIdx.x, A.ntiles);
-        if (tile < 0) return;
-    }
+    // one tile per workgroup; the rescue pass (a small grid) walks the list
+    // of tiles that hold a flagged query, written by k_rescue_tiles.  Every
+    // LDS region a tile writes before its first barrier belongs to the
+    // writing wave, so a wave may start the next tile while others finish
+    // the last one.
+    auto run_tile = [&](const int tile) {
     const int4 dsc = A.tiles[tile];
     if (dsc.z <= 0) return;
     const int p = dsc.x;
@@ -713,6 +712,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             A.pcnt[slot] = c;
             if (c == r) atomicMin((unsigned long long *)(A.tau + slot / A.m), (unsigned long long)buf[qi * CB + r - 1]);
         }
+    }
+    };
+    if (RESCUE) {
+        const int nr = *A.rcount;
+        for (int i = blockIdx.x; i < nr; i += gridDim.x) run_tile(A.rlist[i]);
+    } else {
+        const int tile = xcd_tile(blockIdx.x, A.ntiles);
+        if (tile >= 0) run_tile(tile);
     }
 }
 

@@ -235,6 +235,10 @@ static LowpFn pick_prec(int prec, int ns, bool lab, int r) {
     return pick_ns<CAPS_PREC_FP8, EX>(ns, lab, r);
 }
 
+// workgroups of the rescue pass (32 per compute unit): enough to spread a
+// long list, few enough that an empty one costs little
+constexpr int64_t kRescueWgs = 8192;
+
 size_t lowp_scan_lds(const Index *ix, int r, int kind) {
     return LowpLds(kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0).total + 64;
 }
@@ -296,7 +300,9 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     const size_t lds = lowp_scan_lds(ix, S.r, S.kind);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(S.stage, st);
-    const int64_t grid = (S.max_tiles + kXcds - 1) / kXcds * kXcds;
+    // the rescue pass walks its (device-side) tile list with a bounded grid
+    const int64_t full = (S.max_tiles + kXcds - 1) / kXcds * kXcds;
+    const int64_t grid = S.kind == 2 ? std::min<int64_t>(full, kRescueWgs) : full;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kLNT), lds, st, A);
     prof_end(S.stage, st);
     CAPS_HIP(hipGetLastError());
