@@ -232,9 +232,96 @@ __global__ __launch_bounds__(kTopmNT) void k_topm_reg(const float *__restrict__ 
     }
 }
 
+// The search itself needs the best m partitions of a query as a set, with
+// its best s (the seed probes) in the first s slots, in no particular order
+// otherwise.  One wave per query finds the m-th and the s-th smallest key
+// (ordered score, then id) by bisection over the score bits, then over the
+// ids of the tied scores, and writes the ids in two compacted groups.  KPT =
+// pb / 64 scores per lane (position r * 64 + lane).
+template <int KPT>
+__global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scores, int32_t nq, int32_t b, int32_t m,
+                                                  int32_t s, int32_t *__restrict__ probes) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const float *sc = scores + q * b;
+    uint32_t u[KPT];
+#pragma unroll
+    for (int r = 0; r < KPT; r++) {
+        const int i = r * 64 + lane;
+        u[r] = i < b ? f2ord(sc[i]) : ~0u;
+    }
+    auto wsum = [](int v) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    };
+    // the n-th smallest key (n >= 1): score su and id iu; ties of su are taken
+    // by ascending id up to iu
+    auto kth = [&](int n, uint32_t &su, int &iu) {
+        uint32_t ans = 0;
+        for (int bit = 31; bit >= 0; bit--) {
+            const uint32_t t = ans | (1u << bit);
+            int c = 0;
+#pragma unroll
+            for (int r = 0; r < KPT; r++) c += u[r] < t ? 1 : 0;
+            if (wsum(c) < n) ans = t;
+        }
+        su = ans;
+        int lt = 0;
+#pragma unroll
+        for (int r = 0; r < KPT; r++) lt += u[r] < su ? 1 : 0;
+        const int need = n - wsum(lt);   // >= 1 ties of su to take, by id
+        int ia = 0;
+        for (int bit = 31 - __builtin_clz((unsigned)(KPT * 64)); bit >= 0; bit--) {
+            const int t = ia | (1 << bit);
+            int c = 0;
+#pragma unroll
+            for (int r = 0; r < KPT; r++) c += (u[r] == su && r * 64 + lane < t) ? 1 : 0;
+            if (wsum(c) < need) ia = t;
+        }
+        iu = ia;
+    };
+    auto below = [&](uint32_t v, int i, uint32_t su, int iu) { return v < su || (v == su && i <= iu); };
+    uint32_t sm, ss = 0;
+    int im, is = -1;
+    kth(m, sm, im);
+    if (s < m) kth(s, ss, is);
+    int32_t *out = probes + q * m;
+    int n0 = 0, n1 = s < m ? s : 0;
+#pragma unroll
+    for (int r = 0; r < KPT; r++) {
+        const int i = r * 64 + lane;
+        const bool in_m = below(u[r], i, sm, im);
+        const bool in_s = s < m && below(u[r], i, ss, is);
+        const uint64_t b0 = __ballot(in_s), b1 = __ballot(in_m && !in_s);
+        const uint64_t lt = lanemask_lt();
+        // (exactly s and m - s keys qualify; the bounds are a guard)
+        const int p0 = n0 + __popcll(b0 & lt), p1 = n1 + __popcll(b1 & lt);
+        if (in_s && p0 < s) out[p0] = i;
+        else if (!in_s && in_m && p1 < m) out[p1] = i;
+        n0 += __popcll(b0);
+        n1 += __popcll(b1);
+    }
+}
+
 // Launches the register bitonic top-m when pb allows, else the LDS one.
+// With s >= 0 (a search, not the probes query) the selection kernel instead,
+// for B up to 4096: the best m as a set, the best s in the first slots.
 static void launch_topm(const float *scores, int32_t nb, int32_t b, int32_t pb, int32_t m, int32_t *probes,
-                        hipStream_t st) {
+                        hipStream_t st, int32_t s = -1) {
+    if (s >= 0 && pb >= 64 && pb <= 4096) {
+        const dim3 g((nb + 3) / 4);
+        switch (pb) {
+        case 64: hipLaunchKernelGGL(k_topm_sel<1>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 128: hipLaunchKernelGGL(k_topm_sel<2>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 256: hipLaunchKernelGGL(k_topm_sel<4>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 512: hipLaunchKernelGGL(k_topm_sel<8>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 1024: hipLaunchKernelGGL(k_topm_sel<16>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 2048: hipLaunchKernelGGL(k_topm_sel<32>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        default: hipLaunchKernelGGL(k_topm_sel<64>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        }
+    }
     switch (pb) {
     case 256: hipLaunchKernelGGL(k_topm_reg<1>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
     case 512: hipLaunchKernelGGL(k_topm_reg<2>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
@@ -320,11 +407,16 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
 // the fill pass places each pair.  k_class_sort then groups each partition's
 // pairs by their level mask (nc classes, nc = 2^(h+1) for h <= 3, else 1): a
 // tile mostly holds queries that scan the same levels, and the scans skip
-// the levels none of a tile's queries selected.
+// the levels none of a tile's queries selected.  (Folding the classes into
+// the bucketing bins made the histogram eight times larger and its strided
+// stores cost more than the class pass.)
 constexpr int kBucketQ = 16;   // queries per bucketing block
+constexpr int kClassShift = 27;   // packed class of an entry (entries < 2^27)
 
 inline int32_t bucket_classes(int32_t h) { return h <= 3 ? 1 << (h + 1) : 1; }
 
+// Probe slots [r0, r1) of the block's queries: thread t takes slots r0 + t,
+// r0 + t + 256, ... of each query in turn (coalesced, no division).
 __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
                                                      int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
@@ -332,12 +424,13 @@ __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__
     extern __shared__ int32_t cnt[];
     for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
-    const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
-        const int32_t rr = (int32_t)(e % m);
-        if (rr >= r0 && rr < r1 && sel[e]) atomicAdd(&cnt[probes[e]], 1);
-    }
+    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
+    for (int32_t qq = q0; qq < q1; qq++)
+        for (int32_t rr = r0 + (int32_t)threadIdx.x; rr < r1; rr += 256) {
+            const int64_t e = (int64_t)qq * m + rr;
+            const uint32_t sm = sel[e];
+            if (sm) atomicAdd(&cnt[probes[e]], 1);
+        }
     __syncthreads();
     for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
 }
@@ -345,44 +438,69 @@ __global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__
 __global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
                                                      const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
                                                      int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
-                                                     const int32_t *__restrict__ hscan,
+                                                     const int32_t *__restrict__ hscan, int32_t nc_pack,
                                                      int32_t *__restrict__ entries) {
     extern __shared__ int32_t run[];
     for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * kBucketQ * m;
-    const int64_t hi = min((int64_t)nq * m, lo + (int64_t)kBucketQ * m);
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
-        const int32_t rr = (int32_t)(e % m);
-        if (rr >= r0 && rr < r1 && sel[e]) entries[atomicAdd(&run[probes[e]], 1)] = (int32_t)e;
-    }
+    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
+    for (int32_t qq = q0; qq < q1; qq++)
+        for (int32_t rr = r0 + (int32_t)threadIdx.x; rr < r1; rr += 256) {
+            const int64_t e = (int64_t)qq * m + rr;
+            const uint32_t sm = sel[e];
+            // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
+            if (sm)
+                entries[atomicAdd(&run[probes[e]], 1)] =
+                    (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
+        }
 }
 
 // One workgroup per partition: copies its entries from `in` to `out` grouped
-// by level-mask class (in any order within a class).
+// by level-mask class (in any order within a class).  The class is packed
+// above bit kClassShift of each entry (packed != 0) or read from `sel`.
+// Counts and ranks come from one ballot per class and 64 entries.
 __global__ __launch_bounds__(256) void k_class_sort(const int32_t *__restrict__ in, const uint32_t *__restrict__ sel,
                                                     const int32_t *__restrict__ pstart,
-                                                    const int32_t *__restrict__ pcount, int32_t nc,
+                                                    const int32_t *__restrict__ pcount, int32_t nc, int32_t packed,
                                                     int32_t *__restrict__ out) {
-    __shared__ int32_t cnt[16];
-    const int32_t p = blockIdx.x, t = threadIdx.x;
+    __shared__ int32_t wcnt[4][16];
+    const int32_t p = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int32_t ps = pstart[p], pn = pcount[p];
-    if (t < 16) cnt[t] = 0;
-    __syncthreads();
-    for (int32_t i = t; i < pn; i += 256) atomicAdd(&cnt[sel[in[ps + i]] & (uint32_t)(nc - 1)], 1);
-    __syncthreads();
-    if (t == 0) {
-        int32_t run = 0;
-        for (int c = 0; c < nc; c++) {
-            const int32_t v = cnt[c];
-            cnt[c] = run;
-            run += v;
+    const int32_t emask = (1 << kClassShift) - 1;
+    auto cls_of = [&](int32_t v) {
+        return packed ? (v >> kClassShift) & (nc - 1) : (int32_t)(sel[v] & (uint32_t)(nc - 1));
+    };
+    // pass 1: per wave and class, its entries (64-entry blocks w, w + 4, ...)
+    int32_t cnt = 0;   // lane c < nc: this wave's count of class c
+    for (int32_t i0 = w * 64; i0 < pn; i0 += 256) {
+        const int32_t i = i0 + lane;
+        const int32_t c = i < pn ? cls_of(in[ps + i]) : -1;
+        for (int k = 0; k < nc; k++) {
+            const int32_t n = __popcll(__ballot(c == k));
+            if (lane == k) cnt += n;
         }
     }
+    if (lane < 16) wcnt[w][lane] = lane < nc ? cnt : 0;
     __syncthreads();
-    for (int32_t i = t; i < pn; i += 256) {
-        const int32_t e = in[ps + i];
-        out[ps + atomicAdd(&cnt[sel[e] & (uint32_t)(nc - 1)], 1)] = e;
+    // base of (wave w, class c): entries of smaller classes, then of the
+    // same class in waves before w
+    int32_t base = 0;
+    if (lane < nc) {
+        for (int k = 0; k < lane; k++) base += wcnt[0][k] + wcnt[1][k] + wcnt[2][k] + wcnt[3][k];
+        for (int v = 0; v < w; v++) base += wcnt[v][lane];
+    }
+    // pass 2: place
+    const uint64_t lt = lanemask_lt();
+    for (int32_t i0 = w * 64; i0 < pn; i0 += 256) {
+        const int32_t i = i0 + lane;
+        const int32_t v = i < pn ? in[ps + i] : 0;
+        const int32_t c = i < pn ? cls_of(v) : -1;
+        for (int k = 0; k < nc; k++) {
+            const uint64_t bk = __ballot(c == k);
+            const int32_t bk0 = __shfl(base, k, 64);
+            if (c == k) out[ps + bk0 + __popcll(bk & lt)] = packed ? v & emask : v;
+            if (lane == k) base += __popcll(bk);
+        }
     }
 }
 
@@ -1210,6 +1328,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         const int32_t nb = std::min(sb, nq - q0);
         const int64_t pairs = (int64_t)nb * m;
         const int32_t ngrp = (nb + kBucketQ - 1) / kBucketQ;
+        const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 24 : 16)) : m;
+        // the probes query returns them sorted; a search takes the best m as
+        // a set with the s_seed best first
+        const int32_t topm_s = probes_only ? -1 : s_seed;
         prof_begin(CAPS_STAGE_PREP, st);
         hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
                            con_val, n_con, nb, ix->sch, qd);
@@ -1223,7 +1345,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             if (rs != CAPS_OK) return rs;
             prof_end(CAPS_STAGE_ROUTE, st);
             prof_begin(CAPS_STAGE_TOPM, st);
-            launch_topm(scores, nb, b, pb, m, probes, st);
+            launch_topm(scores, nb, b, pb, m, probes, st, topm_s);
             prof_end(CAPS_STAGE_TOPM, st);
             prof_begin(CAPS_STAGE_SELECT, st);
             hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
@@ -1235,7 +1357,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                            q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
         prof_end(CAPS_STAGE_ROUTE, st);
         prof_begin(CAPS_STAGE_TOPM, st);
-        launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st);
+        launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s);
         prof_end(CAPS_STAGE_TOPM, st);
         if (router) {
             const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
@@ -1270,7 +1392,6 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
         // did not fit.  (The approximate seed pass is cheap per probe but
         // its bound looser: m/24 seed probes there, enough that on the
         // 1M-point benchmark no query's pairs overflow.)
-        const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 24 : 16)) : m;
         const bool seeded_exact = P.defer;
         for (int round = 0; round < 2; round++) {
             const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
@@ -1289,12 +1410,14 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
             hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
                                qb, (int32_t)grid, W.tiles);
+            // the fill packs each entry's class when entries stay below 2^27
+            const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
             hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                               nb, m, r0, r1, b, ngrp, hscan, entries);
+                               nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
             const int32_t *ent = entries;
             if (nc > 1) {
                 hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(256), 0, st, entries, sel, pstart, pcount, nc,
-                                   W.entries2);
+                                   (int32_t)(nc_pack > 1), W.entries2);
                 ent = W.entries2;
             }
             CAPS_HIP(hipGetLastError());
