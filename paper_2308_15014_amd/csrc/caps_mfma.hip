@@ -163,22 +163,58 @@ caps_status build_lowp(Index *ix, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ queries
-// One thread per query: rounded copy, FP8 scale and qaux = {|q| (up),
-// |q|^2 (down), |q - q~| (up), |q~| (up)}.
-__global__ void k_qquant(const float *__restrict__ q, int32_t nq, int32_t d, int32_t dpad, int32_t prec,
-                         void *__restrict__ out, float *__restrict__ scale, float *__restrict__ qaux) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per query: rounded copy (the codes of quantize_row, element by
+// element), FP8 scale and qaux = {|q| (up), |q|^2 (down), |q - q~| (up),
+// |q~| (up)}; the FP64 sums are reduced across the wave (their order does
+// not matter: kNormSlack covers any order).
+__global__ __launch_bounds__(256) void k_qquant(const float *__restrict__ q, int32_t nq, int32_t d, int32_t dpad,
+                                                int32_t prec, void *__restrict__ out, float *__restrict__ scale,
+                                                float *__restrict__ qaux) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nq) return;
-    const float *r = q + (int64_t)i * d;
-    const int64_t eb = prec == CAPS_PREC_FP8 ? 1 : 2;
-    double e2, a2;
-    scale[i] = quantize_row(r, d, dpad, prec, reinterpret_cast<uint8_t *>(out) + (int64_t)i * dpad * eb, e2, a2);
-    double n2 = 0.0;
-    for (int j = 0; j < d; j++) n2 += (double)r[j] * (double)r[j];
-    qaux[4 * i + 0] = f32_up(sqrt(n2) * kNormSlack);
-    qaux[4 * i + 1] = f32_down(n2 / kNormSlack);
-    qaux[4 * i + 2] = f32_up(sqrt(e2) * kNormSlack);
-    qaux[4 * i + 3] = f32_up(sqrt(a2) * kNormSlack);
+    const float *r = q + i * d;
+    float s = 1.0f;
+    if (prec == CAPS_PREC_FP8) {
+        float amax = 0.0f;
+        for (int j = lane; j < d; j += 64) amax = fmaxf(amax, fabsf(r[j]));
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        s = amax > 0.0f ? amax / 448.0f : 1.0f;
+    }
+    double e2 = 0.0, a2 = 0.0, n2 = 0.0;
+    for (int j = lane; j < dpad; j += 64) {
+        const float x = j < d ? r[j] : 0.0f;
+        double v;
+        if (prec == CAPS_PREC_FP8) {
+            const uint8_t c = j < d ? e4m3_rne_sat(x / s) : (uint8_t)0;
+            reinterpret_cast<uint8_t *>(out)[i * dpad + j] = c;
+            v = (double)s * e4m3_value(c);
+        } else {
+            const uint16_t c = j < d ? (prec == CAPS_PREC_BF16 ? bf16_rne(x) : f16_rne_sat(x)) : (uint16_t)0;
+            reinterpret_cast<uint16_t *>(out)[i * dpad + j] = c;
+            v = prec == CAPS_PREC_BF16 ? (double)__builtin_bit_cast(float, (uint32_t)c << 16)
+                                       : (double)__builtin_bit_cast(_Float16, c);
+        }
+        if (j < d) {
+            e2 += ((double)x - v) * ((double)x - v);
+            a2 += v * v;
+            n2 += (double)x * (double)x;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        e2 += __shfl_xor(e2, o, 64);
+        a2 += __shfl_xor(a2, o, 64);
+        n2 += __shfl_xor(n2, o, 64);
+    }
+    if (lane == 0) {
+        scale[i] = s;
+        qaux[4 * i + 0] = f32_up(sqrt(n2) * kNormSlack);
+        qaux[4 * i + 1] = f32_down(n2 / kNormSlack);
+        qaux[4 * i + 2] = f32_up(sqrt(e2) * kNormSlack);
+        qaux[4 * i + 3] = f32_up(sqrt(a2) * kNormSlack);
+    }
 }
 
 // ------------------------------------------------------------------ merge + rerank
@@ -245,7 +281,7 @@ size_t lowp_scan_lds(const Index *ix, int r, int kind) {
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     if (S.first_round)
-        hipLaunchKernelGGL(k_qquant, dim3((S.nb + 127) / 128), dim3(128), 0, st, S.q, S.nb, ix->d, ix->dpad, ix->prec,
+        hipLaunchKernelGGL(k_qquant, dim3((S.nb + 3) / 4), dim3(256), 0, st, S.q, S.nb, ix->d, ix->dpad, ix->prec,
                            S.qlow, S.qscale, S.qaux);
     LowpArgs A;
     A.tiles = S.tiles;
