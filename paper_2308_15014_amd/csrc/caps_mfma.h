@@ -310,11 +310,19 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         scnt[qbase + lane] = 0;
         if (EXACT) qnq[qbase + lane] = my_qq >= 0 ? A.qaux[4 * (int64_t)my_qq + 1] : 0.0f;
     }
+    // levels every active row of the wave selects (wave-uniform): a chunk of
+    // such a level keeps the row bounds as they are
+    uint32_t wall;
     {
         uint32_t wor = my_sel;
+        wall = lane < kLQPW && my_qq >= 0 ? my_sel : ~0u;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) wor |= __shfl_xor(wor, o, 64);
+        for (int o = 32; o >= 1; o >>= 1) {
+            wor |= __shfl_xor(wor, o, 64);
+            wall &= __shfl_xor(wall, o, 64);
+        }
         if (lane == 0) lvw[w] = wor;
+        wall = __builtin_amdgcn_readfirstlane(wall);
     }
     if (RESCUE) {   // leave early when no query of the tile is flagged (uniform)
         __syncthreads();
@@ -342,13 +350,15 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         const int byte = s * KSTEP_BYTES + g * LANE_BYTES;
         xoff[s] = (uint32_t)(r16 * ROWB + 16 * ((byte / 16) ^ ((r16 / RPL) & SWZ)) + byte % 16);
     }
-    uint32_t rsel[4], rmask[4], rval[4];
+    uint32_t rmask[4], rval[4];
+    // level mask of epilogue row rr of this lane (read from the row's lane
+    // when needed: rare, so it is not kept in registers)
+    auto rsel = [&](int rr) { return (uint32_t)__builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel); };
     float rqs[4], rtf[4];
     float qa = 0.0f, qb = 0.0f;   // exact: largest |q| and |q - q~| + gam |q~| of my rows
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int qi = qbase + g * 4 + rr;
-        rsel[rr] = __builtin_amdgcn_ds_bpermute((g * 4 + rr) << 2, (int)my_sel);
         if ((active >> (g * 4 + rr)) & 1u) {
             const int32_t qq = ent[qi] / A.m;
             const QDesc qd = A.qd[qq];
@@ -583,8 +593,13 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 
             // ---- epilogue, one 16-point block at a time
             float tfj[4];
+            if ((wall >> j) & 1u) {
 #pragma unroll
-            for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                for (int rr = 0; rr < 4; rr++) tfj[rr] = rtf[rr];
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel(rr) >> j) & 1u) ? rtf[rr] : qnan;
+            }
 #pragma unroll
             for (int bb = 0; bb < 4; bb++) {
                 const int pi = bb * 16 + (lane & 15);
@@ -605,7 +620,8 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                 if (count) {   // survivors of the exact filter (statistics only)
 #pragma unroll
                     for (int rr = 0; rr < 4; rr++) {
-                        bool ok = pi < cn && ((rsel[rr] >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
+                        const uint32_t rs = rsel(rr);   // every lane (a cross-lane read)
+                        bool ok = pi < cn && ((rs >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
                         if (HAS_LABELS && ok) {
                             const int qi = qbase + g * 4 + rr;
                             ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
@@ -676,7 +692,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                     if (moved) {   // bounds may have tightened
                         refresh_bounds();
 #pragma unroll
-                        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel[rr] >> j) & 1u) ? rtf[rr] : qnan;
+                        for (int rr = 0; rr < 4; rr++) tfj[rr] = ((rsel(rr) >> j) & 1u) ? rtf[rr] : qnan;
                     }
                 }
             }
