@@ -326,7 +326,10 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     }
     if (RESCUE) {   // leave early when no query of the tile is flagged (uniform)
         __syncthreads();
-        if ((lvw[0] | lvw[1] | lvw[2] | lvw[3]) == 0) return;
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < kLNW; i++) any |= lvw[i];
+        if (any == 0) return;
     }
     // MFMA A operands: query row qbase + lane%16, K slice (lane/16)*8 of each step
     VT a[NS];
