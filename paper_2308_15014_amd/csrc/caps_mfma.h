@@ -563,8 +563,10 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         // the shared bounds are read before the next chunk's loads are issued
-        // and used after them, so that their latency overlaps too
-        const bool refresh = (++nchunk % kTauRefresh) == 0;
+        // and used after them, so that their latency overlaps too.  (Nothing
+        // lowers them during the main pass, which keeps no keys: it reads
+        // them once per tile.)
+        const bool refresh = !DEFER && (++nchunk % kTauRefresh) == 0;
         uint64_t gt = ~0ull;
         if (refresh) gt = __hip_atomic_load(A.tau + max(my_qq, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         advance(cj, cc0, cend);
