@@ -1222,7 +1222,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
 }
 
 // Shape of one search call: which scan, keys per (query, probe), the
-// sub-batch that keeps the workspace near 1 GiB.
+// sub-batch that keeps the workspace near 4 GiB.
 struct SearchPlan {
     bool lowp, mfma, defer;
     int32_t r, sb;
@@ -1252,7 +1252,7 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
-    const size_t budget = (size_t)1 << 30;
+    const size_t budget = (size_t)4 << 30;   // of 288 GB: a 10k-query batch in one go in every mode
     P.sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nq, 1), budget / per_q));
     return P;
 }
