@@ -142,6 +142,10 @@ typedef struct {
                          router's softmax top-1 probability is below its
                          fallback level or its probes hold fewer than k
                          candidates.  EINVAL without a router. */
+    int64_t workspace_bytes;  /* device budget of one call's workspace; the
+                         queries are searched in sub-batches that fit it
+                         (at least one query each).  0: 4 GiB.  Results do
+                         not depend on it. */
 } caps_search_params;
 
 /*

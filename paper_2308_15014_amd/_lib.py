@@ -34,7 +34,7 @@ class BuildParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("mode", c_i32),
-                ("rerank", c_i32), ("routing", c_i32)]
+                ("rerank", c_i32), ("routing", c_i32), ("workspace_bytes", c_i64)]
 
 
 class RouterParams(ctypes.Structure):

@@ -1252,7 +1252,8 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
-    const size_t budget = (size_t)4 << 30;   // of 288 GB: a 10k-query batch in one go in every mode
+    // default of 4 GiB (of 288 GB): a 10k-query batch in one go in every mode
+    const size_t budget = sp->workspace_bytes > 0 ? (size_t)sp->workspace_bytes : (size_t)4 << 30;
     P.sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nq, 1), budget / per_q));
     return P;
 }

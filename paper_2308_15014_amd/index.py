@@ -115,13 +115,15 @@ class Index:
 
     def search(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
                mode: int = 0, rerank: int = 0, routing: int = 0, stream=None, counters: bool = False,
-               out=None):
+               out=None, workspace_bytes: int = 0):
         """Top-k filtered search for a batch.  Returns device tensors
         (ids int32 [Q,k], dist float32 [Q,k]) and, with counters=True, the
         per-query candidate and survivor counts.  mode 1 scans the
         low-precision copy with matrix cores and rescores `rerank`
         candidates per query exactly; mode 2 forces the plain FP32 scan.
-        routing 1 uses the learned router (with its centroid fallback)."""
+        routing 1 uses the learned router (with its centroid fallback).
+        workspace_bytes caps the device workspace of the call (0: 4 GiB);
+        the batch is searched in sub-batches that fit it."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
@@ -132,7 +134,7 @@ class Index:
             ids, dist = out
         nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
         ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
-        sp = SearchParams(k, nprobe, rule, mode, rerank, routing)
+        sp = SearchParams(k, nprobe, rule, mode, rerank, routing, workspace_bytes)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),

@@ -169,3 +169,34 @@ def test_many_partitions(caps, orc, b):
     _check_build(oi, ix.export())
     for m in (1, 37, b):
         _check_search(orc, oi, ix, w, 10, m)
+
+
+@pytest.mark.parametrize("prec,mode", [("bf16", 0), ("bf16", 1), ("bf16", 2), ("fp8", 0), ("none", 0)])
+def test_sub_batches_equal_one_batch(caps, orc, prec, mode):
+    """A workspace budget that splits the batch into several sub-batches (and
+    several probe rounds each) gives every query the same ids, distances and
+    counters as one batch, and in the exact modes the oracle's results."""
+    w = synth.make_tiny(230, n=2500, d=48, n_q=301, vocabs=(4, 6), label_vocab=30, b=40, h=2,
+                        cmin=0, cmax=3, max_labels=8)
+    ix = caps.Index.from_workload(w, kmeans_iters=3, precision=prec)
+    m, k = 34, 9   # m >= 32: seed round and main round
+
+    def run(budget):
+        ids, dist, nc, ns = ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m, mode=mode, counters=True,
+                                      workspace_bytes=budget)
+        return ids.cpu().numpy(), dist.cpu().numpy(), nc.cpu().numpy(), ns.cpu().numpy()
+
+    one = run(0)
+    for budget in (40_000, 150_000):   # a few queries per sub-batch; tens of them
+        split = run(budget)
+        assert np.array_equal(split[0], one[0]), budget
+        assert np.array_equal(split[1].view(np.uint32), one[1].view(np.uint32)), budget
+        assert np.array_equal(split[2], one[2]), budget
+        assert np.array_equal(split[3], one[3]), budget
+    if mode != 1:
+        oi = orc.build_from_workload(w, iters=3)
+        r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, k, m)
+        assert np.array_equal(one[0], r.ids)
+        assert np.array_equal(one[1].view(np.uint32), r.dist.view(np.uint32))
+        assert np.array_equal(one[2], r.n_cand)
+        assert np.array_equal(one[3], r.n_surv)
