@@ -612,6 +612,20 @@ __global__ __launch_bounds__(256) void k_tile_desc(const int32_t *__restrict__ t
     tiles[t] = dsc;
 }
 
+// Clears the rescue list's length (rcount[0]) and records in rcount[1]
+// whether any query of the sub-batch is flagged, so that the tile listing
+// ends at once when none is.  One workgroup.
+__global__ __launch_bounds__(1024) void k_rescue_init(const int32_t *__restrict__ oflow, int32_t nq,
+                                                      int32_t *__restrict__ rcount) {
+    int any = 0;
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) any |= oflow[i];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) {
+        rcount[0] = 0;
+        rcount[1] = any != 0;
+    }
+}
+
 // Tiles of the exact main pass that hold a flagged query: listed (in any
 // order) for the rescue pass.  One thread per tile.
 __global__ __launch_bounds__(256) void k_rescue_tiles(const int4 *__restrict__ tiles, int32_t ntiles,
@@ -619,7 +633,7 @@ __global__ __launch_bounds__(256) void k_rescue_tiles(const int4 *__restrict__ t
                                                       const int32_t *__restrict__ oflow, int32_t *__restrict__ rlist,
                                                       int32_t *__restrict__ rcount) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+    if (t >= ntiles || rcount[1] == 0) return;
     const int4 dsc = tiles[t];
     bool hit = false;
     for (int i = 0; i < dsc.z && !hit; i++) hit = oflow[entries[dsc.y + i] / m] != 0;
@@ -1206,7 +1220,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.oflow = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.rlist = defer ? ar.take<int32_t>(tile_cap(sb, m, b)) : nullptr;
-    w.rcount = defer ? ar.take<int32_t>(1) : nullptr;
+    w.rcount = defer ? ar.take<int32_t>(2) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
@@ -1452,7 +1466,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 const caps_status ls = lowp_scan(ix, S, st);
                 if (ls != CAPS_OK) return ls;
                 if (S.kind == 1) {   // rescue pass over the tiles that hold a flagged query
-                    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, W.rcount, (int64_t)1, 0);
+                    hipLaunchKernelGGL(k_rescue_init, dim3(1), dim3(1024), 0, st, W.oflow, nb, W.rcount);
                     hipLaunchKernelGGL(k_rescue_tiles, dim3(nblocks(grid, 256)), dim3(256), 0, st, W.tiles,
                                        (int32_t)grid, ent, m, W.oflow, W.rlist, W.rcount);
                     S.kind = 2;
