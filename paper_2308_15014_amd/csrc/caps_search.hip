@@ -415,44 +415,71 @@ constexpr int kClassShift = 27;   // packed class of an entry (entries < 2^27)
 
 inline int32_t bucket_classes(int32_t h) { return h <= 3 ? 1 << (h + 1) : 1; }
 
-// Probe slots [r0, r1) of the block's queries: thread t takes slots r0 + t,
-// r0 + t + 256, ... of each query in turn (coalesced, no division).
-__global__ __launch_bounds__(256) void k_bucket_hist(const int32_t *__restrict__ probes,
-                                                     const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
-                                                     int32_t *__restrict__ hist) {
-    extern __shared__ int32_t cnt[];
-    for (int i = threadIdx.x; i < b; i += 256) cnt[i] = 0;
-    __syncthreads();
-    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
-    for (int32_t qq = q0; qq < q1; qq++)
-        for (int32_t rr = r0 + (int32_t)threadIdx.x; rr < r1; rr += 256) {
-            const int64_t e = (int64_t)qq * m + rr;
-            const uint32_t sm = sel[e];
-            if (sm) atomicAdd(&cnt[probes[e]], 1);
+constexpr int kBucketT = 1024;   // threads per bucketing block
+
+// The block's (query, probe-slot) span [q0, q1) x [r0, r1), flattened: thread
+// t visits flat slots t, t + T, ... (coalesced, one division per thread), four
+// at a time with all their loads issued before any is used.  visit(e, mask,
+// partition) runs for each chosen slot e.
+template <typename F>
+__device__ inline void bucket_slots(const int32_t *__restrict__ probes, const uint32_t *__restrict__ sel,
+                                    int32_t q0, int32_t q1, int32_t m, int32_t r0, int32_t r1, F &&visit) {
+    const int32_t w = r1 - r0;
+    if (w <= 0 || q1 <= q0) return;
+    const int32_t n = (q1 - q0) * w, T = (int32_t)blockDim.x, t = (int32_t)threadIdx.x;
+    const int32_t dq = T / w, dr = T - dq * w;
+    int32_t qq = q0 + t / w, rr = r0 + t % w;
+    for (int32_t f = t; f < n; f += 4 * T) {
+        int64_t e[4];
+        uint32_t sm[4];
+        int32_t pr[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const bool ok = f + u * T < n;
+            e[u] = (int64_t)qq * m + rr;
+            sm[u] = ok ? sel[e[u]] : 0u;
+            pr[u] = ok ? probes[e[u]] : 0;
+            rr += dr;   // advance the flat slot by T
+            qq += dq;
+            if (rr >= r1) {
+                rr -= w;
+                qq++;
+            }
         }
-    __syncthreads();
-    for (int i = threadIdx.x; i < b; i += 256) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (sm[u]) visit(e[u], sm[u], pr[u]);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_bucket_fill(const int32_t *__restrict__ probes,
-                                                     const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
-                                                     int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
-                                                     const int32_t *__restrict__ hscan, int32_t nc_pack,
-                                                     int32_t *__restrict__ entries) {
-    extern __shared__ int32_t run[];
-    for (int i = threadIdx.x; i < b; i += 256) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+__global__ __launch_bounds__(kBucketT) void k_bucket_hist(const int32_t *__restrict__ probes,
+                                                          const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                          int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                          int32_t *__restrict__ hist) {
+    extern __shared__ int32_t cnt[];
+    for (int i = threadIdx.x; i < b; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
-    for (int32_t qq = q0; qq < q1; qq++)
-        for (int32_t rr = r0 + (int32_t)threadIdx.x; rr < r1; rr += 256) {
-            const int64_t e = (int64_t)qq * m + rr;
-            const uint32_t sm = sel[e];
-            // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
-            if (sm)
-                entries[atomicAdd(&run[probes[e]], 1)] =
-                    (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
-        }
+    bucket_slots(probes, sel, q0, q1, m, r0, r1,
+                 [&](int64_t, uint32_t, int32_t p) { atomicAdd(&cnt[p], 1); });
+    __syncthreads();
+    for (int i = threadIdx.x; i < b; i += blockDim.x) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+}
+
+__global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restrict__ probes,
+                                                          const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                          int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
+                                                          const int32_t *__restrict__ hscan, int32_t nc_pack,
+                                                          int32_t *__restrict__ entries) {
+    extern __shared__ int32_t run[];
+    for (int i = threadIdx.x; i < b; i += blockDim.x) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+    __syncthreads();
+    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
+    // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
+    bucket_slots(probes, sel, q0, q1, m, r0, r1, [&](int64_t e, uint32_t sm, int32_t p) {
+        entries[atomicAdd(&run[p], 1)] =
+            (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
+    });
 }
 
 // One workgroup per partition: copies its entries from `in` to `out` grouped
@@ -1413,7 +1440,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             const int32_t r1 = round == 0 ? s_seed : m;
             if (r0 >= r1) continue;
             prof_begin(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                nb, m, r0, r1, b, ngrp, hist);
             {
                 const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
@@ -1427,7 +1454,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                                qb, (int32_t)grid, W.tiles);
             // the fill packs each entry's class when entries stay below 2^27
             const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
-            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(256), sizeof(int32_t) * (size_t)b, st, probes, sel,
+            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
             const int32_t *ent = entries;
             if (nc > 1) {
