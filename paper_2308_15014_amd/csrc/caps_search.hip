@@ -251,11 +251,8 @@ __global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scor
         const int i = r * 64 + lane;
         u[r] = i < b ? f2ord(sc[i]) : ~0u;
     }
-    auto wsum = [](int v) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        return v;
-    };
+    // wave-wide counts come from one ballot per register (scalar popcounts,
+    // no cross-lane data movement)
     // the n-th smallest key (n >= 1): score su and id iu; ties of su are taken
     // by ascending id up to iu
     auto kth = [&](int n, uint32_t &su, int &iu) {
@@ -264,21 +261,21 @@ __global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scor
             const uint32_t t = ans | (1u << bit);
             int c = 0;
 #pragma unroll
-            for (int r = 0; r < KPT; r++) c += u[r] < t ? 1 : 0;
-            if (wsum(c) < n) ans = t;
+            for (int r = 0; r < KPT; r++) c += __popcll(__ballot(u[r] < t));
+            if (c < n) ans = t;
         }
         su = ans;
         int lt = 0;
 #pragma unroll
-        for (int r = 0; r < KPT; r++) lt += u[r] < su ? 1 : 0;
-        const int need = n - wsum(lt);   // >= 1 ties of su to take, by id
+        for (int r = 0; r < KPT; r++) lt += __popcll(__ballot(u[r] < su));
+        const int need = n - lt;   // >= 1 ties of su to take, by id
         int ia = 0;
         for (int bit = 31 - __builtin_clz((unsigned)(KPT * 64)); bit >= 0; bit--) {
             const int t = ia | (1 << bit);
             int c = 0;
 #pragma unroll
-            for (int r = 0; r < KPT; r++) c += (u[r] == su && r * 64 + lane < t) ? 1 : 0;
-            if (wsum(c) < need) ia = t;
+            for (int r = 0; r < KPT; r++) c += __popcll(__ballot(u[r] == su && r * 64 + lane < t));
+            if (c < need) ia = t;
         }
         iu = ia;
     };
@@ -486,20 +483,23 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restr
 // by level-mask class (in any order within a class).  The class is packed
 // above bit kClassShift of each entry (packed != 0) or read from `sel`.
 // Counts and ranks come from one ballot per class and 64 entries.
-__global__ __launch_bounds__(256) void k_class_sort(const int32_t *__restrict__ in, const uint32_t *__restrict__ sel,
-                                                    const int32_t *__restrict__ pstart,
-                                                    const int32_t *__restrict__ pcount, int32_t nc, int32_t packed,
-                                                    int32_t *__restrict__ out) {
-    __shared__ int32_t wcnt[4][16];
+constexpr int kClassW = 8;   // waves per class-sort block
+
+__global__ __launch_bounds__(kClassW * 64) void k_class_sort(const int32_t *__restrict__ in,
+                                                             const uint32_t *__restrict__ sel,
+                                                             const int32_t *__restrict__ pstart,
+                                                             const int32_t *__restrict__ pcount, int32_t nc,
+                                                             int32_t packed, int32_t *__restrict__ out) {
+    __shared__ int32_t wcnt[kClassW][16];
     const int32_t p = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int32_t ps = pstart[p], pn = pcount[p];
     const int32_t emask = (1 << kClassShift) - 1;
     auto cls_of = [&](int32_t v) {
         return packed ? (v >> kClassShift) & (nc - 1) : (int32_t)(sel[v] & (uint32_t)(nc - 1));
     };
-    // pass 1: per wave and class, its entries (64-entry blocks w, w + 4, ...)
+    // pass 1: per wave and class, its entries (64-entry blocks w, w + kClassW, ...)
     int32_t cnt = 0;   // lane c < nc: this wave's count of class c
-    for (int32_t i0 = w * 64; i0 < pn; i0 += 256) {
+    for (int32_t i0 = w * 64; i0 < pn; i0 += kClassW * 64) {
         const int32_t i = i0 + lane;
         const int32_t c = i < pn ? cls_of(in[ps + i]) : -1;
         for (int k = 0; k < nc; k++) {
@@ -513,12 +513,13 @@ __global__ __launch_bounds__(256) void k_class_sort(const int32_t *__restrict__ 
     // same class in waves before w
     int32_t base = 0;
     if (lane < nc) {
-        for (int k = 0; k < lane; k++) base += wcnt[0][k] + wcnt[1][k] + wcnt[2][k] + wcnt[3][k];
+        for (int k = 0; k < lane; k++)
+            for (int v = 0; v < kClassW; v++) base += wcnt[v][k];
         for (int v = 0; v < w; v++) base += wcnt[v][lane];
     }
     // pass 2: place
     const uint64_t lt = lanemask_lt();
-    for (int32_t i0 = w * 64; i0 < pn; i0 += 256) {
+    for (int32_t i0 = w * 64; i0 < pn; i0 += kClassW * 64) {
         const int32_t i = i0 + lane;
         const int32_t v = i < pn ? in[ps + i] : 0;
         const int32_t c = i < pn ? cls_of(v) : -1;
@@ -1458,7 +1459,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                                nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
             const int32_t *ent = entries;
             if (nc > 1) {
-                hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(256), 0, st, entries, sel, pstart, pcount, nc,
+                hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(kClassW * 64), 0, st, entries, sel, pstart, pcount, nc,
                                    (int32_t)(nc_pack > 1), W.entries2);
                 ent = W.entries2;
             }
