@@ -23,7 +23,6 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
-#include <deque>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -35,19 +34,51 @@ namespace caps {
 
 using Clock = std::chrono::steady_clock;
 
-struct SrvReq {
-    uint64_t ticket;
-    Clock::time_point t0;
+// Waiting requests, oldest first from `head`: query rows (d floats each),
+// constraint pairs, and per request its ticket, submit time and number of
+// constraints.  Flat arrays, so that submitting and batching allocate
+// nothing per request; consumed entries are dropped once the head passes
+// half of the arrays.
+struct ReqQueue {
     std::vector<float> q;
     std::vector<int32_t> attr, val;
+    std::vector<uint64_t> ticket;
+    std::vector<Clock::time_point> t0;
+    std::vector<int32_t> ncon;
+    size_t head = 0, chead = 0;   // first waiting request and its first constraint
+    size_t size() const { return ticket.size() - head; }
+    bool empty() const { return size() == 0; }
+    void compact(size_t d) {
+        if (head == 0 || head * 2 < ticket.size()) return;
+        ticket.erase(ticket.begin(), ticket.begin() + (ptrdiff_t)head);
+        t0.erase(t0.begin(), t0.begin() + (ptrdiff_t)head);
+        ncon.erase(ncon.begin(), ncon.begin() + (ptrdiff_t)head);
+        q.erase(q.begin(), q.begin() + (ptrdiff_t)(head * d));
+        attr.erase(attr.begin(), attr.begin() + (ptrdiff_t)chead);
+        val.erase(val.begin(), val.begin() + (ptrdiff_t)chead);
+        head = chead = 0;
+    }
 };
 
-struct SrvDone {
-    uint64_t ticket;
-    double lat_ms;
-    int32_t status;
+// Finished requests, oldest first from `head`: ticket, latency, status and
+// k ids and distances each (flat, like the request queue).
+struct DoneQueue {
+    std::vector<uint64_t> ticket;
+    std::vector<float> lat;
+    std::vector<int32_t> status;
     std::vector<int32_t> ids;
     std::vector<float> dist;
+    size_t head = 0;
+    size_t size() const { return ticket.size() - head; }
+    void compact(size_t k) {
+        if (head == 0 || head * 2 < ticket.size()) return;
+        ticket.erase(ticket.begin(), ticket.begin() + (ptrdiff_t)head);
+        lat.erase(lat.begin(), lat.begin() + (ptrdiff_t)head);
+        status.erase(status.begin(), status.begin() + (ptrdiff_t)head);
+        ids.erase(ids.begin(), ids.begin() + (ptrdiff_t)(head * k));
+        dist.erase(dist.begin(), dist.begin() + (ptrdiff_t)(head * k));
+        head = 0;
+    }
 };
 
 struct SrvSlot {
@@ -55,7 +86,8 @@ struct SrvSlot {
     hipEvent_t ev = nullptr;
     bool busy = false;
     caps_status status = CAPS_OK;
-    std::vector<SrvReq> reqs;
+    std::vector<uint64_t> tickets;         // the batch in flight
+    std::vector<Clock::time_point> t0s;
     float *hq = nullptr, *hdist = nullptr, *dq = nullptr, *ddist = nullptr;
     int32_t *hoff = nullptr, *hattr = nullptr, *hval = nullptr, *hids = nullptr;
     int32_t *doff = nullptr, *dattr = nullptr, *dval = nullptr, *dids = nullptr;
@@ -69,8 +101,8 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv;        // new request / stop (scheduler side)
     std::condition_variable cv_done;   // a batch retired (drain side)
-    std::deque<SrvReq> pending;
-    std::deque<SrvDone> done;
+    ReqQueue pending;
+    DoneQueue done;
     bool stop = false;
     uint64_t next_ticket = 1;
     int64_t submitted = 0, completed = 0, rejected = 0, failed = 0, batches = 0, batched = 0;
@@ -84,50 +116,63 @@ struct Server {
 
 static void retire(Server *S, SrvSlot &sl) {
     const Clock::time_point t = Clock::now();
-    std::vector<SrvDone> out;
-    out.reserve(sl.reqs.size());
-    for (size_t i = 0; i < sl.reqs.size(); i++) {
-        SrvDone r;
-        r.ticket = sl.reqs[i].ticket;
-        r.lat_ms = std::chrono::duration<double, std::milli>(t - sl.reqs[i].t0).count();
-        r.status = sl.status;
-        r.ids.assign((size_t)S->k, -1);
-        r.dist.assign((size_t)S->k, 0.0f);
-        if (sl.status == CAPS_OK) {
-            memcpy(r.ids.data(), sl.hids + i * S->k, sizeof(int32_t) * (size_t)S->k);
-            memcpy(r.dist.data(), sl.hdist + i * S->k, sizeof(float) * (size_t)S->k);
-        }
-        out.push_back(std::move(r));
-    }
+    const size_t nb = sl.tickets.size(), k = (size_t)S->k;
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        for (auto &r : out) {
-            S->lat.push_back(r.lat_ms);
-            if (r.status != CAPS_OK) S->failed++;
-            S->completed++;
-            S->done.push_back(std::move(r));
+        DoneQueue &D = S->done;
+        for (size_t i = 0; i < nb; i++) {
+            const double ms = std::chrono::duration<double, std::milli>(t - sl.t0s[i]).count();
+            S->lat.push_back(ms);
+            D.ticket.push_back(sl.tickets[i]);
+            D.lat.push_back((float)ms);
+            D.status.push_back(sl.status);
         }
+        const size_t o = D.ids.size();
+        if (sl.status == CAPS_OK) {
+            D.ids.insert(D.ids.end(), sl.hids, sl.hids + nb * k);
+            D.dist.insert(D.dist.end(), sl.hdist, sl.hdist + nb * k);
+        } else {
+            D.ids.resize(o + nb * k, -1);
+            D.dist.resize(o + nb * k, 0.0f);
+            S->failed += (int64_t)nb;
+        }
+        S->completed += (int64_t)nb;
         S->t_last = t;
     }
     S->cv_done.notify_all();
     sl.busy = false;
-    sl.reqs.clear();
+    sl.tickets.clear();
+    sl.t0s.clear();
 }
 
-static void launch(Server *S, SrvSlot &sl, std::vector<SrvReq> &&batch) {
-    const int32_t nb = (int32_t)batch.size(), d = S->d, k = S->k;
+// Takes the oldest nb waiting requests into the slot's pinned buffers and
+// ticket list (the caller holds the lock); returns their constraint count.
+static int32_t take_batch(Server *S, SrvSlot &sl, size_t nb) {
+    ReqQueue &P = S->pending;
+    const size_t d = (size_t)S->d;
+    memcpy(sl.hq, P.q.data() + P.head * d, sizeof(float) * nb * d);
     int32_t ncon = 0;
     sl.hoff[0] = 0;
-    for (int32_t i = 0; i < nb; i++) {
-        const SrvReq &r = batch[(size_t)i];
-        memcpy(sl.hq + (size_t)i * d, r.q.data(), sizeof(float) * (size_t)d);
-        for (size_t e = 0; e < r.attr.size(); e++) {
-            sl.hattr[ncon] = r.attr[e];
-            sl.hval[ncon] = r.val[e];
-            ncon++;
-        }
+    for (size_t i = 0; i < nb; i++) {
+        ncon += P.ncon[P.head + i];
         sl.hoff[i + 1] = ncon;
     }
+    if (ncon > 0) {
+        memcpy(sl.hattr, P.attr.data() + P.chead, sizeof(int32_t) * (size_t)ncon);
+        memcpy(sl.hval, P.val.data() + P.chead, sizeof(int32_t) * (size_t)ncon);
+    }
+    sl.tickets.assign(P.ticket.begin() + (ptrdiff_t)P.head, P.ticket.begin() + (ptrdiff_t)(P.head + nb));
+    sl.t0s.assign(P.t0.begin() + (ptrdiff_t)P.head, P.t0.begin() + (ptrdiff_t)(P.head + nb));
+    P.head += nb;
+    P.chead += (size_t)ncon;
+    P.compact(d);
+    return ncon;
+}
+
+// Enqueues the packed batch on the slot's stream: copies in, the search,
+// copies out, the completion event.
+static void launch(Server *S, SrvSlot &sl, int32_t ncon) {
+    const int32_t nb = (int32_t)sl.tickets.size(), d = S->d, k = S->k;
     caps_status s = CAPS_OK;
     hipError_t e = hipMemcpyAsync(sl.dq, sl.hq, sizeof(float) * (size_t)nb * d, hipMemcpyHostToDevice, sl.st);
     if (e == hipSuccess)
@@ -151,7 +196,6 @@ static void launch(Server *S, SrvSlot &sl, std::vector<SrvReq> &&batch) {
         if (S->err.empty()) S->err = caps_last_error();
     }
     sl.status = s;
-    sl.reqs = std::move(batch);
     sl.busy = true;
     if (hipEventRecord(sl.ev, sl.st) != hipSuccess) {
         // no event to wait for: the stream is in error, finish the batch now
@@ -186,24 +230,20 @@ static void run(Server *S) {
                 free_slot = &sl;
                 break;
             }
-        std::vector<SrvReq> batch;
-        bool quit = false;
+        bool taken = false, quit = false;
+        int32_t ncon = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (free_slot && !S->pending.empty()) {
                 const bool fill = S->p.batch_window_us > 0 && !S->stop &&
                                   (int32_t)S->pending.size() < S->cap &&
-                                  Clock::now() - S->pending.front().t0 < window;
+                                  Clock::now() - S->pending.t0[S->pending.head] < window;
                 if (!fill) {
-                    const size_t nb = std::min((size_t)S->cap, S->pending.size());
-                    batch.reserve(nb);
-                    for (size_t i = 0; i < nb; i++) {
-                        batch.push_back(std::move(S->pending.front()));
-                        S->pending.pop_front();
-                    }
+                    ncon = take_batch(S, *free_slot, std::min((size_t)S->cap, S->pending.size()));
+                    taken = true;
                 }
             }
-            if (batch.empty() && !progressed) {
+            if (!taken && !progressed) {
                 bool busy_now = false;
                 for (auto &sl : S->slots) busy_now |= sl.busy;
                 if (S->stop && S->pending.empty() && !busy_now) {
@@ -217,7 +257,7 @@ static void run(Server *S) {
             }
         }
         if (quit) break;
-        if (!batch.empty()) launch(S, *free_slot, std::move(batch));
+        if (taken) launch(S, *free_slot, ncon);
     }
 }
 
@@ -248,34 +288,40 @@ static void destroy(Server *S) {
 
 static caps_status enqueue(Server *S, const float *q, int32_t n_con, const int32_t *attr, const int32_t *val,
                            Clock::time_point t0, uint64_t *ticket) {
-    SrvReq r;
-    r.t0 = t0;
-    r.q.assign(q, q + S->d);
-    if (n_con > 0) {
-        r.attr.assign(attr, attr + n_con);
-        r.val.assign(val, val + n_con);
-    }
+    bool wake = false;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) {
             set_error("caps_server_submit: server is stopping");
             return CAPS_EINVAL;
         }
-        if ((int32_t)S->pending.size() >= S->p.queue_slots) {
+        ReqQueue &P = S->pending;
+        if ((int32_t)P.size() >= S->p.queue_slots) {
             S->rejected++;
             set_error("caps_server_submit: queue full (%d waiting)", S->p.queue_slots);
             return CAPS_EBUSY;
         }
-        r.ticket = S->next_ticket++;
-        if (ticket) *ticket = r.ticket;
+        const uint64_t tk = S->next_ticket++;
+        if (ticket) *ticket = tk;
         if (!S->have_first) {
             S->t_first = t0;
             S->have_first = true;
         }
         S->submitted++;
-        S->pending.push_back(std::move(r));
+        // the scheduler polls at a fine grain while requests wait: it needs a
+        // wake-up only when the queue was empty (it may be in its long sleep)
+        // or a full batch is ready
+        wake = P.empty() || (int32_t)P.size() + 1 >= S->cap;
+        P.q.insert(P.q.end(), q, q + S->d);
+        if (n_con > 0) {
+            P.attr.insert(P.attr.end(), attr, attr + n_con);
+            P.val.insert(P.val.end(), val, val + n_con);
+        }
+        P.ticket.push_back(tk);
+        P.t0.push_back(t0);
+        P.ncon.push_back(n_con);
     }
-    S->cv.notify_one();
+    if (wake) S->cv.notify_one();
     return CAPS_OK;
 }
 
@@ -417,18 +463,18 @@ extern "C" caps_status caps_server_poll(caps_server *srv, int32_t max, uint64_t 
     }
     Server *S = srv->s;
     std::lock_guard<std::mutex> lk(S->mu);
-    int32_t c = 0;
-    while (c < max && !S->done.empty()) {
-        SrvDone &r = S->done.front();
-        tickets[c] = r.ticket;
-        memcpy(ids + (size_t)c * S->k, r.ids.data(), sizeof(int32_t) * (size_t)S->k);
-        memcpy(dist + (size_t)c * S->k, r.dist.data(), sizeof(float) * (size_t)S->k);
-        if (latency_ms) latency_ms[c] = (float)r.lat_ms;
-        if (status) status[c] = r.status;
-        S->done.pop_front();
-        c++;
+    DoneQueue &D = S->done;
+    const size_t c = std::min((size_t)max, D.size()), k = (size_t)S->k, h = D.head;
+    if (c > 0) {
+        memcpy(tickets, D.ticket.data() + h, sizeof(uint64_t) * c);
+        memcpy(ids, D.ids.data() + h * k, sizeof(int32_t) * c * k);
+        memcpy(dist, D.dist.data() + h * k, sizeof(float) * c * k);
+        if (latency_ms) memcpy(latency_ms, D.lat.data() + h, sizeof(float) * c);
+        if (status) memcpy(status, D.status.data() + h, sizeof(int32_t) * c);
+        D.head += c;
+        D.compact(k);
     }
-    *n_done = c;
+    *n_done = (int32_t)c;
     return CAPS_OK;
 }
 
