@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (skip the sweep)")
     ap.add_argument("--target", type=float, default=0.9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-rates", default="100000,250000,500000,750000",
+    ap.add_argument("--serve-rates", default="100000,500000,1000000,2000000",
                     help="Poisson arrival rates (queries/s) for the serving sweep; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=0.4)
     ap.add_argument("--router-train", type=int, default=2_000_000,
