@@ -1,0 +1,73 @@
+"""GPU parity at the benchmark's full size, on sampled queries.
+
+The workload the benchmark times: the SIFT1M-shaped integer corpus (1M x 128,
+three dense attributes, B = 1024 partitions, AFT height 2), 10k filtered
+queries searched as one batch at nprobe 624, k = 10, squared L2, on an index
+that holds the BF16 copy (search mode 0: matrix-core bounds, exact FP32
+rescoring; mode 2: the plain FP32 scan).  The oracle's query path (Alg. 2,
+§5.2) runs over the GPU-built partitions for a sample of the queries; ids,
+distances, candidate and survivor counts must agree bit for bit.  The search
+without counters is the launch configuration the benchmark times; the one
+with counters adds the survivor count.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLE = 384
+NPROBE = 624
+K = 10
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_15014_amd as caps
+    caps.lib()
+    w = synth.make_c2()
+    ix = caps.Index.from_workload(w, precision="bf16")
+    dev = torch.device("cuda", 0)
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    return w, ix, dq
+
+
+@pytest.fixture(scope="module")
+def sampled(full, orc):
+    """Oracle results for a seeded sample of the queries, over the GPU-built index's
+    partitions and CSR layout."""
+    w, ix, _ = full
+    g = ix.export()
+    oi = orc.Index(w.x, orc.workload_tokens(w), w.metric, w.n_partitions, w.aft_height, g["centroids"],
+                   g["assign"], g["tags"], g["level"], g["perm"], g["offs"], np.zeros(0, np.int32))
+    sel = np.sort(np.random.default_rng(2308).choice(w.n_q, N_SAMPLE, replace=False))
+    co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
+    ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    return sel, orc.search(oi, w.q[sel], co, ca, cv, K, NPROBE)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_full_size_sampled_parity(full, sampled, mode):
+    import torch
+    w, ix, (q, co, ca, cv) = full
+    sel, r = sampled
+    dev = q.device
+    ids = torch.empty((w.n_q, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((w.n_q, K), dtype=torch.float32, device=dev)
+    ix.search(q, co, ca, cv, K, NPROBE, mode=mode, out=(ids, dist))
+    ids, dist = ids.cpu().numpy()[sel], dist.cpu().numpy()[sel]
+    assert np.array_equal(ids, r.ids), mode
+    assert np.array_equal(dist.view(np.uint32), r.dist.view(np.uint32)), mode
+    ids2, dist2, nc, ns = ix.search(q, co, ca, cv, K, NPROBE, mode=mode, counters=True)
+    assert np.array_equal(ids2.cpu().numpy()[sel], r.ids), mode
+    assert np.array_equal(dist2.cpu().numpy()[sel].view(np.uint32), r.dist.view(np.uint32)), mode
+    assert np.array_equal(nc.cpu().numpy()[sel], r.n_cand), mode
+    assert np.array_equal(ns.cpu().numpy()[sel], r.n_surv), mode
+    # the sample exercises the filter: candidates pass the sub-partition
+    # lookup and only a fraction of them satisfy the constraints
+    assert (r.n_cand > 0).all() and (r.n_surv < r.n_cand).all()
