@@ -8,12 +8,15 @@ rescoring; mode 2: the plain FP32 scan).  The oracle's query path (Alg. 2,
 §5.2) runs over the GPU-built partitions for a sample of the queries; ids,
 distances, candidate and survivor counts must agree bit for bit.  The search
 without counters is the launch configuration the benchmark times; the one
-with counters adds the survivor count.
+with counters adds the survivor count.  Mode 1 (approximate BF16 keys, FP32
+rerank of the best 4k) is checked by its properties: exact filter counts,
+valid ids, exact distances, recall against the exact result.
 """
 import numpy as np
 import pytest
 
 import synth
+from oracle import ref64
 
 pytestmark = pytest.mark.gpu
 
@@ -48,14 +51,14 @@ def sampled(full, orc):
     co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
     ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
     cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
-    return sel, orc.search(oi, w.q[sel], co, ca, cv, K, NPROBE)
+    return sel, orc.search(oi, w.q[sel], co, ca, cv, K, NPROBE), orc.search(oi, w.q[sel], co, ca, cv, 64, NPROBE)
 
 
 @pytest.mark.parametrize("mode", [0, 2])
 def test_full_size_sampled_parity(full, sampled, mode):
     import torch
     w, ix, (q, co, ca, cv) = full
-    sel, r = sampled
+    sel, r, _ = sampled
     dev = q.device
     ids = torch.empty((w.n_q, K), dtype=torch.int32, device=dev)
     dist = torch.empty((w.n_q, K), dtype=torch.float32, device=dev)
@@ -71,3 +74,28 @@ def test_full_size_sampled_parity(full, sampled, mode):
     # the sample exercises the filter: candidates pass the sub-partition
     # lookup and only a fraction of them satisfy the constraints
     assert (r.n_cand > 0).all() and (r.n_surv < r.n_cand).all()
+
+
+def test_full_size_sampled_mode1(full, sampled):
+    w, ix, (q, co, ca, cv) = full
+    sel, r, wide = sampled
+    ids, dist, nc, ns = ix.search(q, co, ca, cv, K, NPROBE, mode=1, rerank=40, counters=True)
+    ids, dist = ids.cpu().numpy()[sel], dist.cpu().numpy()[sel]
+    nc, ns = nc.cpu().numpy()[sel], ns.cpu().numpy()[sel]
+    assert np.array_equal(nc, r.n_cand) and np.array_equal(ns, r.n_surv)   # the filter is exact
+    hit = tot = 0
+    for j, i in enumerate(sel):
+        valid = ids[j] >= 0
+        assert valid.sum() == min(K, ns[j])
+        mask = ref64.valid_mask(w.dense, w.label_off, w.labels,
+                                ref64.pairs_of(w.con_off, w.con_attr, w.con_val, i), w.n_dense,
+                                w.dense_vocab, w.label_vocab)
+        assert np.all(mask[ids[j][valid]])
+        exact = {int(a): b for a, b in zip(wide.ids[j], wide.dist[j].view(np.uint32)) if a >= 0}
+        for a, b in zip(ids[j][valid], dist[j][valid].view(np.uint32)):
+            if int(a) in exact:
+                assert exact[int(a)] == b
+        t = set(r.ids[j][r.ids[j] >= 0].tolist())
+        hit += len(t & set(ids[j][valid].tolist()))
+        tot += len(t)
+    assert hit / max(tot, 1) >= 0.97, hit / max(tot, 1)
