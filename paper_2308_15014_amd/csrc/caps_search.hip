@@ -407,7 +407,7 @@ __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t
 // the levels none of a tile's queries selected.  (Folding the classes into
 // the bucketing bins made the histogram eight times larger and its strided
 // stores cost more than the class pass.)
-constexpr int kBucketQ = 16;   // queries per bucketing block
+constexpr int kBucketQ = 32;   // queries per bucketing block
 constexpr int kClassShift = 27;   // packed class of an entry (entries < 2^27)
 
 inline int32_t bucket_classes(int32_t h) { return h <= 3 ? 1 << (h + 1) : 1; }
