@@ -377,7 +377,8 @@ caps_status caps_server_submit(caps_server *srv, const float *q, int32_t n_con, 
 /* Submits n requests (q n x d, constraint CSR con_off n+1) at arrival_s[i]
  * seconds after the call (non-decreasing), from the calling thread, and
  * returns after the last one; tickets[i] = 0 marks a request refused with a
- * full queue.  HOST arrays. */
+ * full queue.  HOST arrays; con_attr and con_val may be null only when no
+ * request has constraints (else EINVAL). */
 caps_status caps_server_replay(caps_server *srv, const float *q, const int32_t *con_off, const int32_t *con_attr,
                                const int32_t *con_val, int32_t n, const double *arrival_s, uint64_t *tickets);
 

@@ -429,7 +429,8 @@ extern "C" caps_status caps_server_submit(caps_server *srv, const float *q, int3
 extern "C" caps_status caps_server_replay(caps_server *srv, const float *q, const int32_t *con_off,
                                           const int32_t *con_attr, const int32_t *con_val, int32_t n,
                                           const double *arrival_s, uint64_t *tickets) {
-    if (!srv || n < 0 || (n > 0 && (!q || !con_off || !arrival_s))) {
+    if (!srv || n < 0 || (n > 0 && (!q || !con_off || !arrival_s)) ||
+        (n > 0 && con_off[n] > con_off[0] && (!con_attr || !con_val))) {
         set_error("caps_server_replay: bad arguments");
         return CAPS_EINVAL;
     }
