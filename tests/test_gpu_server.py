@@ -87,6 +87,43 @@ def test_alone_and_mixed_results_are_identical(caps, work, mode):
         srv.close()
 
 
+def test_small_polls_between_submits(caps, work):
+    """Results taken a few at a time while requests keep arriving (the queues
+    are consumed from their heads and compacted as they go): every request
+    comes back exactly once, equal bit for bit to the one-batch search."""
+    w, ix = work
+    k, m = 10, 6
+    batch_ids, batch_dist = (t.cpu().numpy() for t in ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m))
+    srv = caps.Server(ix, k=k, nprobe=m, max_batch=16, streams=2)
+    try:
+        tick, got = {}, {}
+
+        def take(r):
+            for t, a, b, s in zip(r["tickets"], r["ids"], r["dist"], r["status"]):
+                assert s == 0 and int(t) not in got
+                got[int(t)] = (a.copy(), b.copy())
+
+        for rep in range(3):
+            for i in range(w.n_q):
+                tick[srv.submit(w.q[i], *_pairs(w, i))] = i
+                if i % 5 == 4:
+                    take(srv.poll(7))
+        srv.drain(60.0)
+        while True:
+            r = srv.poll(7)
+            if not len(r["tickets"]):
+                break
+            take(r)
+        assert set(got) == set(tick)
+        for t, i in tick.items():
+            assert np.array_equal(got[t][0], batch_ids[i]), i
+            assert np.array_equal(got[t][1].view(np.uint32), batch_dist[i].view(np.uint32)), i
+        st = srv.stats()
+        assert st["completed"] == st["submitted"] == len(tick) and st["failed"] == 0
+    finally:
+        srv.close()
+
+
 def test_queue_full_refuses_and_accepted_requests_finish(caps, work):
     w, ix = work
     srv = caps.Server(ix, k=5, nprobe=24, max_batch=1, streams=1, queue_slots=2)
