@@ -15,9 +15,16 @@ Procedure
   4. W warmup steps, then K timed steps at that nprobe, each step one search
      of the whole 10,000-query batch with inputs resident in HBM;
   5. stage timing with HIP events on the search stream; the dominant kernel
-     (the filtered scan) is reported against the vector-ALU roofline;
-  6. CPU baseline: the oracle's query path on a bounded sample of the same
-     queries at the same nprobe, on the host's cores.
+     (the exact main pass of the filtered scan) is reported against the HBM
+     roofline with the union-bytes rule: every distinct candidate word and
+     survivor row of the batch counted once, plus queries, lookup tables and
+     outputs (the per-query byte sum exceeds the peak through batch reuse);
+  6. cold-cache protocol: 20 more repetitions, each after a 512 MiB scratch
+     write (twice the 256 MB Infinity Cache), timed with HIP events; median;
+  7. CPU baseline: the oracle's query path on a bounded sample of the same
+     queries at the same nprobe, at one thread and at every host core, its
+     results compared with the GPU's, and the recall truth compared with the
+     oracle's filtered brute force on a query sample.
 Modes: `value` is exact search (mode 0: BF16 lower bounds on the matrix
 cores, exact FP32 rescoring); `modes` also holds BF16 + rerank (mode 1),
 the plain FP32 scan (mode 2) and the learned router (a 192-1024-1024 MLP
@@ -42,14 +49,11 @@ if ROOT not in sys.path:
 
 METRIC = "filtered queries/s at recall@10>=0.9 (plain FP32 centroid-routed CAPS)"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 FP32 VALU lane
-# operations per second (non-packed).  One survivor-dimension of the exact
-# squared-L2 scan is a subtract and a fused multiply-add: two VALU
-# operations carrying three floating-point operations.
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-SCAN_PEAK_TFLOPS = VALU_LANE_OPS / 2 * 3 / 1e12
-# published dense BF16 matrix-core peak of MI355X
+# published MI355X peaks: HBM3E bandwidth, FP32 vector and dense BF16 matrix-core rates
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK = 2500.0
+FLUSH_BYTES = 512 << 20
 
 # HBM bytes per launch of the exact main pass (mode 0, BF16 copy, 10k queries, nprobe 624) from
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the timed
@@ -97,32 +101,122 @@ def recall10(found, truth, nvalid):
     return r
 
 
-def cpu_baseline(ix, w, m, budget_s=20.0):
-    """Oracle query path (C, OpenMP over queries) on a bounded query sample,
-    with the GPU-built index's partitions and CSR as its index."""
+def subset(w, sel):
+    """Queries `sel` of a workload with their constraint pairs (CSR rebased)."""
+    co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
+    ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    return w.q[sel], co, ca, cv
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ix, w, m, gpu_ids, gpu_dist, truth, budget_s=12.0):
+    """Oracle query path (C, OpenMP over queries) on bounded query samples at
+    every host core and at one thread, with the GPU-built index's partitions
+    and CSR as its index; its results are compared with the GPU's, and the
+    recall truth (every partition probed on the GPU) with the oracle's
+    filtered brute force on 200 queries."""
     import oracle
     g = ix.export()
-    oi = oracle.Index(w.x, oracle.workload_tokens(w), w.metric, w.n_partitions, w.aft_height,
-                      g["centroids"], g["assign"], g["tags"], g["level"], g["perm"], g["offs"],
-                      np.zeros(0, np.int32))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = 64
-    total_q, total_t = 0, 0.0
-    start = 0
-    while total_t < budget_s and start < w.n_q:
-        sel = np.arange(start, min(w.n_q, start + n))
-        co = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
-        ca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
-        cv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
-        t0 = time.perf_counter()
-        oracle.search(oi, w.q[sel], co, ca, cv, 10, m)
-        total_t += time.perf_counter() - t0
-        total_q += len(sel)
-        start += len(sel)
-        n = min(4 * n, 4096)
-    return {"value": total_q / total_t, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {total_q} of the {w.n_q} queries at nprobe={m} "
-                      f"({total_t:.1f} s of CPU work, OpenMP over queries)"}
+    tk = oracle.workload_tokens(w)
+    oi = oracle.Index(w.x, tk, w.metric, w.n_partitions, w.aft_height, g["centroids"], g["assign"], g["tags"],
+                      g["level"], g["perm"], g["offs"], np.zeros(0, np.int32))
+    nproc = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def timed(threads, budget):
+        used = oracle.set_threads(threads)
+        n, start, total_q, total_t = 32, 0, 0, 0.0
+        same = True
+        while total_t < budget and start < w.n_q:
+            sel = np.arange(start, min(w.n_q, start + n))
+            t0 = time.perf_counter()
+            r = oracle.search(oi, *subset(w, sel), 10, m)
+            total_t += time.perf_counter() - t0
+            same &= bool(np.array_equal(r.ids, gpu_ids[sel]) and
+                         np.array_equal(r.dist.view(np.uint32), gpu_dist[sel].view(np.uint32)))
+            total_q += len(sel)
+            start += len(sel)
+            n = min(4 * n, 4096)
+        return used, total_q, total_t, same
+
+    cores, nq_all, t_all, same_all = timed(nproc, budget_s)
+    one, nq_one, t_one, same_one = timed(1, budget_s / 2)
+    oracle.set_threads(nproc)
+    sel = np.sort(np.random.default_rng(7).choice(w.n_q, 200, replace=False))
+    t0 = time.perf_counter()
+    bf = oracle.bruteforce(w.x, tk, w.metric, *subset(w, sel), 10)
+    bf_s = time.perf_counter() - t0
+    truth_ok = bool(np.array_equal(bf.ids, truth[sel]))
+    return {"value": nq_all / t_all, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {nq_all} of the {w.n_q} queries at nprobe={m} ({t_all:.1f} s of CPU work, "
+                      f"OpenMP over queries on {cores} threads)",
+            "single_thread": {"value": nq_one / t_one, "unit": "queries/s", "cores": one,
+                              "sample": f"first {nq_one} queries ({t_one:.1f} s)"},
+            "host": {"nproc": nproc, "cpu_model": cpu_model()},
+            "parity_check": {"queries": nq_all, "ids_and_distance_bits_equal_gpu": bool(same_all and same_one)},
+            "truth_check": {"queries": len(sel), "gpu_all_partitions_equals_oracle_bruteforce": truth_ok,
+                            "bruteforce_s": round(bf_s, 2)}}
+
+
+def union_bytes(ix, w, q, co, ca, cv, k, m, dev):
+    """Algorithmic bytes of one exact search of the whole batch under the
+    union rule: every distinct candidate word (4 B) and survivor row (FP32
+    row + id, 4d + 4 B) counted once, plus the queries, the tag and offset
+    tables and the outputs.  Candidates come from the probes query's chosen
+    sub-partitions, survivors from the debug search's per-position pass bits
+    (1024 queries at a time, OR-reduced)."""
+    import torch
+    info = ix.info()
+    n, h, b, d = info["n"], info["aft_height"], info["n_partitions"], info["d"]
+    offs = ix.export()["offs"]
+    seglen = np.diff(offs.astype(np.int64))
+    pr, mk = ix.probes(q, co, ca, cv, m)
+    pr, mk = pr.cpu().numpy().astype(np.int64), mk.cpu().numpy().view(np.uint32)
+    seg = np.zeros(b * (h + 1), bool)
+    for j in range(h + 1):
+        on = ((mk >> j) & 1).astype(bool)
+        seg[pr[on] * (h + 1) + j] = True
+    cand = int(seglen[seg].sum())
+    acc = None
+    for s0 in range(0, w.n_q, 1024):
+        sel = np.arange(s0, min(w.n_q, s0 + 1024))
+        mask = ix.search_debug(*subset(w, sel), k, m)[4]
+        while mask.shape[0] > 1:
+            if mask.shape[0] % 2:
+                mask = torch.cat([mask, torch.zeros_like(mask[:1])])
+            mask = mask[0::2] | mask[1::2]
+        acc = mask[0] if acc is None else acc | mask[0]
+    surv = int(np.unpackbits(acc.cpu().numpy().view(np.uint8)).sum())
+    tables = 4 * b * (h + 1) + 4 + 4 * b * h
+    total = 4 * cand + (4 * d + 4) * surv + 4 * d * w.n_q + tables + 8 * k * w.n_q
+    return {"bytes": total, "candidate_rows": cand, "survivor_rows": surv}
+
+
+def event_median(fn, reps, flush=None):
+    """Median milliseconds of `reps` calls timed with HIP events on the
+    current stream; `flush` (a device tensor) is overwritten before each."""
+    import torch
+    out = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1.0)
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        e.record()
+        e.synchronize()
+        out.append(a.elapsed_time(e))
+    return float(np.median(out)), out
 
 
 def main():
@@ -146,6 +240,7 @@ def main():
                          "(approximate + rerank, mode 1), valu (exact, plain FP32 scan only, "
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
+    ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -190,7 +285,7 @@ def main():
     log(f"truth (all {B} partitions probed): {time.perf_counter() - t0:.2f}s, "
         f"mean |D_C| = {nvalid.mean():.0f}")
 
-    def measure(mode, label, routing=0):
+    def measure(mode, label, routing=0, roofline=False, cold=False):
         sweep = []
         # nprobe grid: powers of two, then steps of 16 around where recall@10
         # crosses 0.9 on the 1M-point corpus, then coarser again
@@ -236,38 +331,65 @@ def main():
         caps.profile_enable(False)
         ms_step = el * 1e3 / args.steps
         qps = w.n_q * args.steps / el
+        ub = union_bytes(ix, w, q, co, ca, cv, k, m, dev) if roofline else None
+        coldd = None
+        if cold:
+            # cold-cache protocol: each repetition after a 512 MiB scratch write
+            flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+            run = lambda: ix.search(q, co, ca, cv, k, m, mode=mode, routing=routing, out=(ids, dist))  # noqa: E731
+            med_cold, all_cold = event_median(run, args.reps, flush)
+            med_warm, _ = event_median(run, args.reps)
+            del flush
+            coldd = {"reps": args.reps, "flush_bytes": FLUSH_BYTES, "median_ms": round(med_cold, 4),
+                     "queries_per_s_at_median": round(w.n_q / (med_cold / 1e3), 1),
+                     "min_ms": round(min(all_cold), 4), "max_ms": round(max(all_cold), 4),
+                     "warm_median_ms": round(med_warm, 4)}
+            log(f"[{label}] cold-cache median {med_cold:.3f} ms (warm median {med_warm:.3f} ms) over {args.reps} reps")
         scan_ms, scan_n = prof["scan"]
         scan_avg_s = scan_ms / 1e3 / max(scan_n, 1)
         launches_per_step = max(scan_n, 1) / args.steps
         stage_ms = {s_: round(v[0] / args.steps, 4) for s_, v in prof.items()}
         log(f"[{label}] timed: {args.steps} steps, {ms_step:.3f} ms/step, {qps:,.0f} queries/s at nprobe={m} "
             f"recall@10={rec:.4f}; stages ms/step {stage_ms}")
-        if mode == 2:
-            work = 3.0 * w.d * surv_total / launches_per_step
-            roof = {"kernel": "k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)",
-                    "bound": "alu", "achieved": round(work / scan_avg_s / 1e12, 3),
-                    "peak": round(SCAN_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-                    "frac": round(work / scan_avg_s / 1e12 / SCAN_PEAK_TFLOPS, 4), "traffic": None,
-                    "avg_launch_ms": round(scan_avg_s * 1e3, 4), "algorithmic_flops_per_launch": work}
-        else:
-            # both matrix-core modes bound or score every candidate pair with
-            # one BF16 dot product of length d
-            what = ("exact keys: BF16 lower bounds on MFMA, exact FP32 rescoring of the pairs that "
-                    "can enter the top k" if mode == 0 else "approximate keys, per-query top-4k")
-            work = 2.0 * w.d * cand_total / launches_per_step
-            roof = {"kernel": f"k_scan_mfma<bf16> (query x candidate dot products on MFMA, exact filter "
-                              f"epilogue; {what})",
-                    "bound": "mfma", "achieved": round(work / scan_avg_s / 1e12, 3), "peak": MFMA_BF16_PEAK,
-                    "unit": "TFLOP/s", "frac": round(work / scan_avg_s / 1e12 / MFMA_BF16_PEAK, 4),
-                    "traffic": main_pass_traffic(m, w.n_q) if (mode == 0 and routing == 0) else None,
-                    "traffic_unit": "bytes per launch (HBM, rocprofv3 TCC counters, calibrated)",
-                    "avg_launch_ms": round(scan_avg_s * 1e3, 4),
-                    "algorithmic_flops_per_launch": work}
+        # algorithmic work of one launch of the dominant kernel (the whole
+        # batch is one sub-batch: one launch per step)
+        flops_method = 3.0 * w.d * surv_total / launches_per_step      # exact FP32 scan of the survivors
+        flops_dense = 2.0 * w.d * cand_total / launches_per_step       # one dot product per candidate pair
+        qbytes = (4.0 * cand_total + (4 * w.d + 4) * surv_total +
+                  w.n_q * (4.0 * m * (2 * w.aft_height + 2) + 4 * w.d + 8 * k)) / launches_per_step
+        kern = ("k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)" if mode == 2 else
+                "k_scan_mfma<bf16> " + ("exact main pass (BF16 lower bounds on MFMA, exact filter epilogue, "
+                                        "passing pairs deferred to the FP32 rescoring merge)" if mode == 0 else
+                                        "approximate keys (BF16 scores on MFMA, exact filter, per-query top-4k)"))
+        roof = {"kernel": kern, "avg_launch_ms": round(scan_avg_s * 1e3, 4),
+                "method_flops": {"per_launch": flops_method,
+                                 "tflops": round(flops_method / scan_avg_s / 1e12, 3),
+                                 "frac_fp32_vector_peak": round(flops_method / scan_avg_s / 1e12 / FP32_PEAK_TFLOPS,
+                                                                4)},
+                "dense_equivalent_mfma": {"flops_per_launch": flops_dense,
+                                          "tflops": round(flops_dense / scan_avg_s / 1e12, 3),
+                                          "frac_bf16_peak": round(flops_dense / scan_avg_s / 1e12 / MFMA_BF16_PEAK, 4),
+                                          "note": "2d per candidate pair, filtered or not; not the method's work"},
+                "per_query_bytes": {"sum_per_launch": qbytes, "gbps": round(qbytes / scan_avg_s / 1e9, 1),
+                                    "note": "sum over queries of 4 C_q + (4d+4) S_q + 4m(2h+2) + 4d + 8k; above the "
+                                            "peak through batch reuse, hence the union rule"}}
+        if ub is not None:
+            gbps = ub["bytes"] / scan_avg_s / 1e9
+            roof.update({"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbps / HBM_PEAK_GBS, 4),
+                         "traffic": main_pass_traffic(m, w.n_q) if (mode == 0 and routing == 0) else None,
+                         "traffic_unit": "bytes per launch (HBM, rocprofv3 TCC counters, calibrated)",
+                         "algorithmic_bytes_per_launch": ub["bytes"],
+                         "bytes_rule": "union: each distinct candidate word (4 B) and survivor row (4d+4 B) of "
+                                       "the batch once, plus queries, tag/offset tables and outputs",
+                         "union_candidate_rows": ub["candidate_rows"], "union_survivor_rows": ub["survivor_rows"],
+                         "step_frac": round(ub["bytes"] / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)})
         return dict(nprobe=m, recall=rec, qps=qps, ms_step=ms_step, stage_ms=stage_ms, sweep=sweep,
-                    cand_per_query=cand_total / w.n_q, surv_per_query=surv_total / w.n_q, roofline=roof)
+                    cand_per_query=cand_total / w.n_q, surv_per_query=surv_total / w.n_q, roofline=roof,
+                    cold=coldd, ids=ids.cpu().numpy(), dist=dist.cpu().numpy())
 
     modes = args.modes.split(",")
-    plain = measure(0, "fp32") if "fp32" in modes else None
+    plain = measure(0, "fp32", roofline=True, cold=True) if "fp32" in modes else None
     lowp = measure(1, "bf16") if "bf16" in modes else None
     valu = measure(2, "valu") if "valu" in modes else None
     routed = routed_rr = None
@@ -408,9 +530,11 @@ def main():
             "queries_per_s": round(lowp["qps"], 1), "nprobe": lowp["nprobe"], "recall@10": lowp["recall"],
             "ms_per_step": round(lowp["ms_step"], 4), "rerank": 4 * k, "stage_ms_per_step": lowp["stage_ms"],
             "roofline": lowp["roofline"]}
+    if plain["cold"] is not None:
+        out["cold_cache"] = plain["cold"]
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle query path on a query sample ...")
-        out["cpu_baseline"] = cpu_baseline(ix, w, plain["nprobe"])
+        out["cpu_baseline"] = cpu_baseline(ix, w, plain["nprobe"], plain["ids"], plain["dist"], truth)
         log(f"  {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

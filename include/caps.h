@@ -142,11 +142,35 @@ typedef struct {
                          router's softmax top-1 probability is below its
                          fallback level or its probes hold fewer than k
                          candidates.  EINVAL without a router. */
+    int32_t flags;    /* CAPS_SEARCH_* bits below */
+    int32_t rescue_grid;  /* workgroups of the exact matrix-core search's
+                         rescue pass (the rescan of queries whose candidate
+                         pairs overflowed their lists); 0: 8192.  Results do
+                         not depend on it. */
     int64_t workspace_bytes;  /* device budget of one call's workspace; the
                          queries are searched in sub-batches that fit it
                          (at least one query each).  0: 4 GiB.  Results do
                          not depend on it. */
 } caps_search_params;
+
+/* caps_search_params.flags */
+enum {
+    /* Synchronise the stream after the search and return CAPS_EINVAL when
+     * a query row holds NaN or Inf.  Without it the call stays
+     * asynchronous and such a row is answered as a query with an empty
+     * D_C (ids -1, distances +inf / -inf). */
+    CAPS_SEARCH_VALIDATE = 1,
+    /* The constraint lists may be disjunctions (Section 5.3 "Query
+     * Algorithm": several sub-partitions per partition are joined when
+     * the query constrains attributes with OR): a pair with attr ==
+     * CAPS_OR separates the AND-terms of one query, and a point is valid
+     * when it satisfies every pair of at least one term.  At most
+     * CAPS_MAX_TERMS terms per query.  Without this flag a CAPS_OR pair
+     * makes its query unsatisfiable, as any negative attribute does. */
+    CAPS_SEARCH_DISJUNCTIVE = 2
+};
+#define CAPS_OR (-1)
+#define CAPS_MAX_TERMS 4
 
 /*
  * caps_search -- Algorithm 2 over a batch.  All pointers are DEVICE
@@ -165,14 +189,46 @@ typedef struct {
  * outside its vocabulary, an attribute index outside [0, n_dense], two
  * different values for one dense attribute, more than 8 distinct labels.
  * Duplicate constraints are ignored; zero constraints give plain IVF kNN.
+ * A query row holding NaN or Inf is answered with an empty result; with
+ * CAPS_SEARCH_VALIDATE in sp->flags the call synchronises `stream` and
+ * returns EINVAL instead.
  * Errors: EINVAL (k, nprobe, n_q < 0, NULL pointers, mode 1 on an index
- * without a low-precision copy, rerank outside [k, 64]), ENOMEM, EDEVICE.
+ * without a low-precision copy, rerank outside [k, 64], rescue_grid < 0,
+ * unknown flags, non-finite query rows under CAPS_SEARCH_VALIDATE),
+ * ENOMEM, EDEVICE.  The device workspace is released on every path.
  */
 caps_status caps_search(const caps_index *idx, const caps_search_params *sp,
                         const float *q, int32_t n_q,
                         const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
                         int32_t n_con, int32_t *out_ids, float *out_dist,
                         int32_t *out_ncand, int32_t *out_nsurv, void *stream);
+
+/*
+ * caps_search_debug -- caps_search (same arguments and arithmetic) that also
+ * writes the filter's pass bits and validates the queries: out_surv_mask
+ * (DEVICE, n_q x ceil(n / 64) uint64 words, cleared by the call) gets, for
+ * query i, bit pos % 64 of word i * ceil(n / 64) + pos / 64 set exactly when
+ * CSR position pos (see caps_index_export: perm[pos] is the point id) lies
+ * in a sub-partition the query's search chose (Algorithm 2, sub-partition
+ * lookup) and the point there satisfies the query's constraints
+ * (Definition 1, "Attribute Match").  Always synchronises `stream`; a query
+ * row with NaN or Inf gives EINVAL.  For tests and inspection: the mask is
+ * computed by a separate pass over the chosen sub-partitions.
+ */
+caps_status caps_search_debug(const caps_index *idx, const caps_search_params *sp,
+                              const float *q, int32_t n_q,
+                              const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                              int32_t n_con, int32_t *out_ids, float *out_dist,
+                              int32_t *out_ncand, int32_t *out_nsurv, uint64_t *out_surv_mask, void *stream);
+
+/*
+ * caps_search_workspace -- *out_bytes = the device workspace one
+ * caps_search call of n_q queries with these parameters allocates (its
+ * sub-batch under sp->workspace_bytes included).  Host only; no device work.
+ * Errors: EINVAL as caps_search.
+ */
+caps_status caps_search_workspace(const caps_index *idx, const caps_search_params *sp, int32_t n_q,
+                                  int64_t *out_bytes);
 
 /*
  * caps_search_probes -- the routing and sub-partition choice of
@@ -341,9 +397,12 @@ typedef struct {
     int32_t streams;          /* batches in flight, 1..8 */
     int32_t queue_slots;      /* waiting requests admitted; submit returns EBUSY beyond */
     int32_t max_constraints;  /* constraint pairs per request, 0..64 */
-    int32_t reserved;
-    int64_t workspace_bytes;  /* device budget of one batch's search workspace
-                                 (caps the batch size; 0: no cap) */
+    int32_t flags;            /* 0 or CAPS_SEARCH_DISJUNCTIVE (requests may hold
+                                 CAPS_OR separators) */
+    int64_t workspace_bytes;  /* device memory the search workspaces of all
+                                 batches in flight share: a batch is sized to
+                                 what the others leave free (and waits when
+                                 not one query fits); 0: no budget */
     double batch_window_us;   /* wait up to this long for a batch to fill once a
                                  slot is free (0: launch what is waiting) */
 } caps_server_params;
@@ -369,8 +428,8 @@ typedef struct caps_server caps_server;
 caps_status caps_server_create(const caps_index *idx, const caps_server_params *p, caps_server **out);
 
 /* Queues one request (q: d floats; n_con pairs).  *ticket identifies its
- * result.  EBUSY when queue_slots requests wait; EINVAL for bad arguments or
- * more than max_constraints pairs. */
+ * result.  EBUSY when queue_slots requests wait; EINVAL for bad arguments,
+ * a NaN or Inf coordinate, or more than max_constraints pairs. */
 caps_status caps_server_submit(caps_server *srv, const float *q, int32_t n_con, const int32_t *con_attr,
                                const int32_t *con_val, uint64_t *ticket);
 

@@ -109,9 +109,14 @@ def tokens_of(dense, dense_vocab, label_off, labels, label_vocab) -> Tokens:
                   label_vocab if labels is not None else 0)
 
 
-def query_tokens(tk: Tokens, con_off, con_attr, con_val):
+def query_tokens(tk: Tokens, con_off, con_attr, con_val, disjunctive: bool = False):
     """Constraint pairs -> token CSR plus a per-query flag for pairs whose
-    attribute or value lies outside the index's vocabularies."""
+    attribute or value lies outside the index's vocabularies.
+
+    disjunctive=True (Section 5.3: several attributes joined with OR): a pair
+    with attr == -1 separates AND-terms and becomes token -1; a pair outside
+    the vocabularies makes only its own term unsatisfiable (token -2 in that
+    term), and so does a term asking for more than MAX_LABELS labels."""
     con_off = np.asarray(con_off, dtype=np.int64)
     a = np.asarray(con_attr, dtype=np.int64)
     v = np.asarray(con_val, dtype=np.int64)
@@ -133,8 +138,23 @@ def query_tokens(tk: Tokens, con_off, con_attr, con_val):
     else:
         bad_pair |= is_lab
     bad_pair |= (a < 0) | (a > tk.n_dense)
-    tok = np.where(bad_pair, 0, tok)
     q_bad = np.zeros(nq, dtype=np.uint8)
+    if disjunctive:
+        sep = a == -1
+        tok = np.where(sep, -1, np.where(bad_pair, -2, tok))
+        # a point holds at most MAX_LABELS labels: a term asking for more
+        # distinct labels is unsatisfiable
+        for qi in range(nq):
+            lo, hi = int(con_off[qi]), int(con_off[qi + 1])
+            start = lo
+            for e in range(lo, hi + 1):
+                if e < hi and not sep[e]:
+                    continue
+                if len(set(v[start:e][is_lab[start:e]].tolist())) > MAX_LABELS:
+                    tok[start:e] = -2
+                start = e + 1
+        return con_off.astype(np.int64), tok.astype(np.int32), q_bad
+    tok = np.where(bad_pair, 0, tok)
     owner = np.repeat(np.arange(nq), np.diff(con_off))
     if len(a):
         np.maximum.at(q_bad, owner, bad_pair.astype(np.uint8))
@@ -145,6 +165,15 @@ def query_tokens(tk: Tokens, con_off, con_attr, con_val):
         if len(set(v[lo:hi][is_lab[lo:hi]].tolist())) > MAX_LABELS:
             q_bad[qi] = 1
     return con_off.astype(np.int64), tok.astype(np.int32), q_bad
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel loops (n <= 0: unchanged); returns
+    the count in effect."""
+    L = lib()
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = ctypes.c_int
+    return int(L.orc_set_threads(int(n)))
 
 
 # ---------------------------------------------------------------- sampler
@@ -301,12 +330,14 @@ class Result:
     masks: Optional[np.ndarray] = None
 
 
-def search(idx: Index, q, con_off, con_attr, con_val, k, m, rule=0) -> Result:
+def search(idx: Index, q, con_off, con_attr, con_val, k, m, rule=0, disjunctive=False) -> Result:
     """Algorithm 2 over a query batch (rule 0: exact sub-partition choice;
-    rule 1: the algorithm's one-sub-partition choice read literally)."""
+    rule 1: the algorithm's one-sub-partition choice read literally).
+    disjunctive=True: constraint lists are OR-ed AND-terms separated by
+    attr == -1 (the chosen sub-partitions are the union over the terms)."""
     q = _c(q, np.float32)
     nq, d = q.shape
-    qo, qt, qbad = query_tokens(idx.tk, con_off, con_attr, con_val)
+    qo, qt, qbad = query_tokens(idx.tk, con_off, con_attr, con_val, disjunctive)
     ids = np.zeros((nq, k), dtype=np.int32)
     dist = np.zeros((nq, k), dtype=np.float32)
     nc = np.zeros(nq, dtype=np.int64)
@@ -330,12 +361,12 @@ def search(idx: Index, q, con_off, con_attr, con_val, k, m, rule=0) -> Result:
     return Result(ids, dist, nc, ns, probes, masks)
 
 
-def bruteforce(x, tk: Tokens, metric, q, con_off, con_attr, con_val, k) -> Result:
+def bruteforce(x, tk: Tokens, metric, q, con_off, con_attr, con_val, k, disjunctive=False) -> Result:
     """Exact filtered top-k in FP32 (Appendix "Groundtruth")."""
     x = _c(x, np.float32)
     q = _c(q, np.float32)
     nq, d = q.shape
-    qo, qt, qbad = query_tokens(tk, con_off, con_attr, con_val)
+    qo, qt, qbad = query_tokens(tk, con_off, con_attr, con_val, disjunctive)
     ids = np.zeros((nq, k), dtype=np.int32)
     dist = np.zeros((nq, k), dtype=np.float32)
     nv = np.zeros(nq, dtype=np.int64)

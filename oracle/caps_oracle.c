@@ -27,6 +27,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the parallel loops below (over independent points or
+ * queries); returns the count in effect.  n <= 0 leaves it unchanged. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Init sampler: splitmix64 (Steele, Lea & Flood, OOPSLA 2014, as in    */
@@ -344,6 +360,50 @@ static int64_t orc_qtokens(const int32_t *in, int64_t nin, const int32_t *tok_at
     return m;
 }
 
+/* A query's constraint list is a disjunction of AND-terms (Section 5.3
+ * "Query Algorithm" joins several sub-partitions per partition when the
+ * query constrains attributes with OR): token -1 separates terms and a term
+ * holding token -2 (a pair outside the vocabularies) is unsatisfiable; a
+ * list without separators is one term.  A term's tokens are normalised by
+ * orc_qtokens, which also marks contradictory terms.  More than
+ * ORC_MAX_TERMS terms: the query is unsatisfiable (returns 0 terms). */
+#define ORC_MAX_TERMS 4
+typedef struct {
+    const int32_t *tok;
+    int64_t n;
+    int ok;
+} orc_term;
+
+static int orc_split_terms(const int32_t *in, int64_t nin, const int32_t *tok_attr, int32_t *buf,
+                           orc_term *terms)
+{
+    int nt = 0;
+    int64_t lo = 0, used = 0;
+    for (int64_t e = 0; e <= nin; e++) {
+        if (e < nin && in[e] != -1) continue;
+        if (nt == ORC_MAX_TERMS) return 0;
+        int bad = 0;
+        for (int64_t f = lo; f < e; f++) bad |= in[f] == -2;
+        int ok = 1;
+        int64_t m = bad ? 0 : orc_qtokens(in + lo, e - lo, tok_attr, buf + used, &ok);
+        terms[nt].tok = buf + used;
+        terms[nt].n = m;
+        terms[nt].ok = ok && !bad;
+        nt++;
+        used += m;
+        lo = e + 1;
+    }
+    return nt;
+}
+
+/* Valid for a disjunction: some satisfiable term's tokens are all held. */
+static int orc_valid_any(const orc_term *terms, int nt, const int32_t *pt, int64_t npt)
+{
+    for (int t = 0; t < nt; t++)
+        if (terms[t].ok && orc_valid(terms[t].tok, terms[t].n, pt, npt)) return 1;
+    return 0;
+}
+
 static int orc_conflicts(int32_t tag, const int32_t *qt, int64_t nqt, const int32_t *tok_attr)
 {
     if (tag < 0 || tok_attr[tag] < 0) return 0;
@@ -411,9 +471,9 @@ int orc_search(const float *x, int64_t n, int32_t d,
         const float *qv = q + (size_t)qi * d;
         int64_t nin = qtok_off[qi + 1] - qtok_off[qi];
         int32_t *qt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nin + 1));
-        int ok = 1;
-        int64_t nqt = orc_qtokens(qtoks + qtok_off[qi], nin, tok_attr, qt, &ok);
-        if (q_bad && q_bad[qi]) ok = 0;
+        orc_term terms[ORC_MAX_TERMS];
+        int nt = orc_split_terms(qtoks + qtok_off[qi], nin, tok_attr, qt, terms);
+        if (q_bad && q_bad[qi]) nt = 0;
 
         orc_rank *rk = (orc_rank *)malloc(sizeof(orc_rank) * (size_t)b);
         for (int32_t c = 0; c < b; c++) {
@@ -427,7 +487,9 @@ int orc_search(const float *x, int64_t n, int32_t d,
         for (int32_t r = 0; r < m; r++) {
             int32_t p = rk[r].id;
             if (out_probes) out_probes[(size_t)qi * m + r] = p;
-            uint32_t mask = ok ? orc_select(rule, tags + (size_t)p * h, h, qt, nqt, tok_attr) : 0u;
+            uint32_t mask = 0u;   /* the union over the satisfiable terms */
+            for (int t = 0; t < nt; t++)
+                if (terms[t].ok) mask |= orc_select(rule, tags + (size_t)p * h, h, terms[t].tok, terms[t].n, tok_attr);
             if (out_masks) out_masks[(size_t)qi * m + r] = mask;
             for (int32_t j = 0; j <= h; j++) {
                 if (!(mask & (1u << j))) continue;
@@ -435,7 +497,7 @@ int orc_search(const float *x, int64_t n, int32_t d,
                 for (int32_t pos = lo; pos < hi; pos++) {
                     int32_t id = perm[pos];
                     cand++;
-                    if (!orc_valid(qt, nqt, toks + tok_off[id], tok_off[id + 1] - tok_off[id])) continue;
+                    if (!orc_valid_any(terms, nt, toks + tok_off[id], tok_off[id + 1] - tok_off[id])) continue;
                     if (nh == cap) {
                         cap *= 2;
                         hits = (orc_hit *)realloc(hits, sizeof(orc_hit) * (size_t)cap);
@@ -472,13 +534,13 @@ int orc_bruteforce(const float *x, int64_t n, int32_t d,
         const float *qv = q + (size_t)qi * d;
         int64_t nin = qtok_off[qi + 1] - qtok_off[qi];
         int32_t *qt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nin + 1));
-        int ok = 1;
-        int64_t nqt = orc_qtokens(qtoks + qtok_off[qi], nin, tok_attr, qt, &ok);
-        if (q_bad && q_bad[qi]) ok = 0;
+        orc_term terms[ORC_MAX_TERMS];
+        int nt = orc_split_terms(qtoks + qtok_off[qi], nin, tok_attr, qt, terms);
+        if (q_bad && q_bad[qi]) nt = 0;
         int64_t cap = 64, nh = 0;
         orc_hit *hits = (orc_hit *)malloc(sizeof(orc_hit) * (size_t)cap);
-        for (int64_t i = 0; ok && i < n; i++) {
-            if (!orc_valid(qt, nqt, toks + tok_off[i], tok_off[i + 1] - tok_off[i])) continue;
+        for (int64_t i = 0; nt > 0 && i < n; i++) {
+            if (!orc_valid_any(terms, nt, toks + tok_off[i], tok_off[i + 1] - tok_off[i])) continue;
             if (nh == cap) {
                 cap *= 2;
                 hits = (orc_hit *)realloc(hits, sizeof(orc_hit) * (size_t)cap);

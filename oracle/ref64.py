@@ -33,6 +33,27 @@ def valid_mask(dense, label_off, labels, pairs, n_dense, dense_vocab=None, label
     return m
 
 
+def valid_mask_dnf(dense, label_off, labels, pairs, n_dense, dense_vocab=None, label_vocab=0, max_terms=4):
+    """Points satisfying at least one AND-term of a disjunction whose terms
+    are separated by pairs with attr == -1 (OR); more than max_terms terms
+    make the query unsatisfiable (the build's limit)."""
+    n = dense.shape[0] if dense is not None else len(label_off) - 1
+    terms, cur = [], []
+    for a, v in pairs:
+        if a == -1:
+            terms.append(cur)
+            cur = []
+        else:
+            cur.append((a, v))
+    terms.append(cur)
+    m = np.zeros(n, dtype=bool)
+    if len(terms) > max_terms:
+        return m
+    for t in terms:
+        m |= valid_mask(dense, label_off, labels, t, n_dense, dense_vocab, label_vocab)
+    return m
+
+
 def pairs_of(con_off, con_attr, con_val, qi):
     lo, hi = int(con_off[qi]), int(con_off[qi + 1])
     return [(int(con_attr[e]), int(con_val[e])) for e in range(lo, hi)]
@@ -48,15 +69,16 @@ def dist64(x, q, metric):
 
 
 def topk64(x, dense, label_off, labels, dense_vocab, label_vocab, metric, q, con_off,
-           con_attr, con_val, k, queries=None):
+           con_attr, con_val, k, queries=None, disjunctive=False):
     """Per query: (ids, dists) of the exact filtered top-k in FP64, ties
     broken by the smaller id, padded with -1.  Also returns |D_C|."""
     n_dense = 0 if dense is None else dense.shape[1]
     qs = range(q.shape[0]) if queries is None else queries
+    vm = valid_mask_dnf if disjunctive else valid_mask
     out_ids, out_d, nvalid = [], [], []
     for qi in qs:
-        m = valid_mask(dense, label_off, labels, pairs_of(con_off, con_attr, con_val, qi),
-                       n_dense, dense_vocab, label_vocab)
+        m = vm(dense, label_off, labels, pairs_of(con_off, con_attr, con_val, qi),
+               n_dense, dense_vocab, label_vocab)
         ids = np.nonzero(m)[0]
         dd = dist64(x[ids], q[qi], metric)
         key = dd if metric == 0 else -dd

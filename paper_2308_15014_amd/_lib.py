@@ -34,7 +34,14 @@ class BuildParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", c_i32), ("nprobe", c_i32), ("rule", c_i32), ("mode", c_i32),
-                ("rerank", c_i32), ("routing", c_i32), ("workspace_bytes", c_i64)]
+                ("rerank", c_i32), ("routing", c_i32), ("flags", c_i32), ("rescue_grid", c_i32),
+                ("workspace_bytes", c_i64)]
+
+
+SEARCH_VALIDATE = 1
+SEARCH_DISJUNCTIVE = 2
+OR = -1          # constraint attribute that separates the AND-terms of a disjunctive query
+MAX_TERMS = 4
 
 
 class RouterParams(ctypes.Structure):
@@ -53,7 +60,7 @@ class RouterInfo(ctypes.Structure):
 class ServerParams(ctypes.Structure):
     _fields_ = [("k", c_i32), ("nprobe", c_i32), ("mode", c_i32), ("routing", c_i32), ("rerank", c_i32),
                 ("max_batch", c_i32), ("streams", c_i32), ("queue_slots", c_i32),
-                ("max_constraints", c_i32), ("reserved", c_i32), ("workspace_bytes", c_i64),
+                ("max_constraints", c_i32), ("flags", c_i32), ("workspace_bytes", c_i64),
                 ("batch_window_us", ctypes.c_double)]
 
 
@@ -86,6 +93,9 @@ SIGNATURES = {
                            ctypes.POINTER(BuildParams), c_vp, ctypes.POINTER(c_vp)]),
     "caps_search": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
                             c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_search_debug": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
+                                  c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_search_workspace": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_i32, ctypes.POINTER(c_i64)]),
     "caps_search_probes": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp,
                                    c_vp, c_i32, c_vp, c_vp, c_vp]),
     "caps_index_info": (c_i32, [c_vp, ctypes.POINTER(IndexInfo)]),

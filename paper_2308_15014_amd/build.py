@@ -36,26 +36,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source to an object in parallel, then links."""
+def _stale(obj: str, src: str) -> bool:
+    """An object is stale when it is older than its source or any header
+    of the library (every source includes some of them)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src), os.path.join(HERE, "..", "include", "caps.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return any(os.path.getmtime(f) > t for f in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source to an object in parallel, then links.  With
+    incremental=True, objects newer than their sources and the headers are
+    kept."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
     jobs = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
     jobs += [("caps_scan_inst.hip", name + ".o", defs) for name, defs in INSTANCES]
+    objs_all = []
     for src, oname, defs in jobs:
         obj = os.path.join(objdir, oname)
+        objs_all.append(obj)
+        if incremental and not _stale(obj, src):
+            continue
         cmd = [hipcc()] + [f for f in FLAGS if f != "-shared"] + defs + ["-c", "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
-    objs, failed = [], []
+    failed = []
     for src, obj, pr in procs:
         out, err = pr.communicate()
         if pr.returncode != 0:
             sys.stderr.write(out + err)
             failed.append(src)
-        objs.append(obj)
+    objs = objs_all
     if failed:
         raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp"
@@ -71,4 +88,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -164,6 +164,9 @@ static caps_status check_search(const caps_index *idx, const caps_search_params 
             return fail(CAPS_EINVAL, "caps_search: rerank must be in [k, %d]", kMaxK);
     }
     if (sp->routing != 0 && sp->routing != 1) return fail(CAPS_EINVAL, "caps_search: routing must be 0 or 1");
+    if (sp->flags & ~(int32_t)(CAPS_SEARCH_VALIDATE | CAPS_SEARCH_DISJUNCTIVE))
+        return fail(CAPS_EINVAL, "caps_search: unknown flags 0x%x", (unsigned)sp->flags);
+    if (sp->rescue_grid < 0) return fail(CAPS_EINVAL, "caps_search: rescue_grid < 0");
     if (sp->routing == 1 && !ix.router) return fail(CAPS_EINVAL, "caps_search: routing 1 needs a trained router");
     if (n_con < 0) return fail(CAPS_EINVAL, "caps_search: n_con < 0");
     if (n_q > 0 && (!q || !con_off)) return fail(CAPS_EINVAL, "caps_search: null query arrays");
@@ -180,6 +183,35 @@ extern "C" caps_status caps_search(const caps_index *idx, const caps_search_para
     if (n_q > 0 && (!out_ids || !out_dist)) return fail(CAPS_EINVAL, "caps_search: null outputs");
     return search(&idx->ix, sp, q, n_q, con_off, con_attr, con_val, n_con, out_ids, out_dist, out_ncand,
                   out_nsurv, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" caps_status caps_search_debug(const caps_index *idx, const caps_search_params *sp, const float *q,
+                                         int32_t n_q, const int32_t *con_off, const int32_t *con_attr,
+                                         const int32_t *con_val, int32_t n_con, int32_t *out_ids, float *out_dist,
+                                         int32_t *out_ncand, int32_t *out_nsurv, uint64_t *out_surv_mask,
+                                         void *stream) {
+    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    if (s != CAPS_OK) return s;
+    if (n_q > 0 && (!out_ids || !out_dist || !out_surv_mask))
+        return fail(CAPS_EINVAL, "caps_search_debug: null outputs");
+    caps_search_params p = *sp;
+    p.flags |= CAPS_SEARCH_VALIDATE;
+    SearchExtra ex;
+    ex.surv_mask = out_surv_mask;
+    s = search(&idx->ix, &p, q, n_q, con_off, con_attr, con_val, n_con, out_ids, out_dist, out_ncand, out_nsurv,
+               nullptr, nullptr, (hipStream_t)stream, &ex);
+    if (s == CAPS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(CAPS_EDEVICE, "caps_search_debug: stream synchronisation failed");
+    return s;
+}
+
+extern "C" caps_status caps_search_workspace(const caps_index *idx, const caps_search_params *sp, int32_t n_q,
+                                             int64_t *out_bytes) {
+    caps_status s = check_search(idx, sp, nullptr, 0, nullptr, nullptr, nullptr, 0);
+    if (s != CAPS_OK) return s;
+    if (n_q < 0 || !out_bytes) return fail(CAPS_EINVAL, "caps_search_workspace: bad arguments");
+    *out_bytes = n_q == 0 ? 0 : (int64_t)search_workspace_bytes(&idx->ix, sp, n_q);
+    return CAPS_OK;
 }
 
 extern "C" caps_status caps_search_probes(const caps_index *idx, const caps_search_params *sp, const float *q,

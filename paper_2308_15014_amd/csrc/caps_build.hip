@@ -416,11 +416,11 @@ static int nbits_for(int32_t v) {
 // nblk, key-major) ends up with the exclusive prefix: hscan[k*nblk] is the
 // first sorted position of key k.
 static caps_status stable_sort(const int32_t *keys, int64_t n, int32_t nkeys, int32_t *hist,
-                               int32_t *hscan, int32_t *sorted, hipStream_t st) {
+                               int32_t *hscan, int32_t *sums, int32_t *sorted, hipStream_t st) {
     const int32_t nblk = (int32_t)((n + kSortBlock - 1) / kSortBlock);
     const size_t lds = sizeof(int32_t) * (size_t)nkeys;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(256), lds, st, keys, n, nkeys, nblk, hist);
-    CAPS_TRY(exclusive_scan_i32(hist, hscan, (int64_t)nkeys * nblk, nullptr, st));
+    CAPS_TRY(exclusive_scan_i32(hist, hscan, (int64_t)nkeys * nblk, nullptr, sums, st));
     hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(64), lds, st, keys, n, nkeys, nblk,
                        nbits_for(nkeys), hscan, sorted);
     CAPS_HIP(hipGetLastError());
@@ -436,7 +436,7 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
     const int64_t nnz = has_labels ? label_off[n] : 0;
 
     // inputs on the device (freed at return)
-    DevBuf dx, ddense, dloff, dlab, dinit, dassign, dhist, dhscan, dsorted, dlev;
+    DevBuf dx, ddense, dloff, dlab, dinit, dassign, dhist, dhscan, dsums, dsorted, dlev;
     CAPS_HIP(hipMalloc(&dx.p, sizeof(float) * (size_t)n * d));
     CAPS_HIP(hipMemcpyAsync(dx.p, x, sizeof(float) * (size_t)n * d, hipMemcpyHostToDevice, st));
     if (sch.n_dense) {
@@ -480,6 +480,7 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
     const int32_t nblk = (int32_t)((n + kSortBlock - 1) / kSortBlock);
     CAPS_HIP(hipMalloc(&dhist.p, sizeof(int32_t) * (size_t)b * nblk));
     CAPS_HIP(hipMalloc(&dhscan.p, sizeof(int32_t) * (size_t)b * nblk));
+    CAPS_HIP(hipMalloc(&dsums.p, sizeof(int32_t) * (size_t)exclusive_scan_tiles((int64_t)b * nblk)));
     CAPS_HIP(hipMalloc(&dsorted.p, sizeof(int32_t) * (size_t)n));
     CAPS_HIP(hipMalloc(&dlev.p, sizeof(int32_t) * (size_t)n));
     float *X = (float *)dx.p;
@@ -497,7 +498,7 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
         hipLaunchKernelGGL(k_scores<true>, sgrid, dim3(256), 0, st, X, n, d, ix->cent, ix->cnorm, b,
                            ix->metric, A, nullptr);
         CAPS_HIP(hipGetLastError());
-        CAPS_TRY(stable_sort(A, n, b, hist, hscan, sorted, st));
+        CAPS_TRY(stable_sort(A, n, b, hist, hscan, (int32_t *)dsums.p, sorted, st));
         if (it == p->kmeans_iters) break;
         const int64_t tot = (int64_t)b * d;
         hipLaunchKernelGGL(k_update, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, d, sorted,

@@ -121,6 +121,18 @@ __device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_la
     return true;
 }
 
+// Filter of one point against a query (summary descriptor qd; `terms`: the
+// query's term descriptors, read only for a disjunction): some term passes.
+__device__ inline bool query_passes(const QDesc &qd, const QDesc *terms, bool has_dense, bool has_labels, uint32_t w,
+                                    uint64_t sig, const uint16_t *sl) {
+    if (qd.flags & kQOr) {
+        for (int t = 0; t < qd.nterm; t++)
+            if (point_passes(terms[t], has_dense, has_labels, w, sig, sl)) return true;
+        return false;
+    }
+    return point_passes(qd, has_dense, has_labels, w, sig, sl);
+}
+
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -42,13 +42,23 @@ struct Schema {
 };
 
 // Per-query filter description built on the device from constraint pairs.
+// A disjunctive query (AND-terms joined by OR) has one descriptor per
+// satisfiable term (kMaxTerms per query, in a separate array) and a summary
+// descriptor: flag kQOr, the number of terms, and the dense constraints all
+// its terms share (a necessary condition the scans test first).
+constexpr uint32_t kQUnsat = 1u;     // contradictory / out of range: chooses nothing
+constexpr uint32_t kQNonFinite = 2u; // query row holds NaN or Inf: chooses nothing
+constexpr uint32_t kQOr = 4u;        // disjunction: evaluate the terms
+constexpr int kMaxTerms = CAPS_MAX_TERMS;
 struct alignas(16) QDesc {
     uint32_t dmask;       // packed-field mask of constrained dense attributes
     uint32_t dval;        // required packed values under dmask
-    uint32_t flags;       // bit 0: unsatisfiable (contradiction / out of range)
+    uint32_t flags;       // kQ* bits
     int32_t nlab;         // distinct label constraints (<= kMaxLabels)
     uint64_t lsig;        // OR of signature bits of the label constraints
     uint16_t lab[kMaxLabels];
+    int32_t nterm;        // kQOr: satisfiable terms (2..kMaxTerms)
+    int32_t pad;
 };
 
 struct Index {
@@ -120,10 +130,15 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
                         const caps_build_params *p, hipStream_t st);
 
 // ---- search (caps_search.hip)
+struct SearchExtra {
+    uint64_t *surv_mask = nullptr;   // debug: per query, survivor bits over CSR positions (device)
+    void *ws = nullptr;              // caller workspace: the search allocates nothing
+    size_t ws_bytes = 0;
+};
 caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
                    const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand, int32_t *out_nsurv,
-                   int32_t *out_probes, uint32_t *out_masks, hipStream_t st);
+                   int32_t *out_probes, uint32_t *out_masks, hipStream_t st, const SearchExtra *extra = nullptr);
 
 // device bytes the workspace of one search call of nq queries takes
 size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq);
@@ -145,6 +160,8 @@ struct LowpScan {
     const int32_t *entries;
     const uint32_t *sel;
     const QDesc *qd;
+    const QDesc *qterms;          // disjunctive searches: term descriptors (kMaxTerms per query)
+    bool disj;                    // the batch may hold disjunctions (the filter's slow path is compiled in)
     const float *q;               // nb x d FP32 queries of the sub-batch
     void *qlow;
     float *qscale, *qaux;
@@ -154,15 +171,18 @@ struct LowpScan {
     int32_t dcap;                 // capacity of each query's deferred list
     int32_t *oflow;               // exact: per query, set by the main pass for the rescue pass
     const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
+    int32_t rescue_grid;          // rescue pass: workgroups walking its tile list (0: default)
 };
-size_t lowp_scan_lds(const Index *ix, int r, int kind);
+size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);
 caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
                        int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,
                        int32_t *out_ids, float *out_dist, hipStream_t st);
 
 // ---- shared device utilities (caps_util.hip)
-caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+// `sums` is caller workspace of exclusive_scan_tiles(n) ints
+int64_t exclusive_scan_tiles(int64_t n);
+caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *sums,
                                hipStream_t st);
 
 // ---- learned routing inside a search (caps_router.hip): fills `scores`

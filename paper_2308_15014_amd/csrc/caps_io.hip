@@ -16,6 +16,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "caps_device.h"
@@ -135,6 +136,59 @@ __global__ void k_io_bf16(const float *__restrict__ x, int64_t n, uint16_t *__re
     if (i < n) y[i] = bf16_rne(x[i]);
 }
 
+// Checks the header's attribute schema against what caps_build derives
+// from the vocabularies (the search kernels index with these fields).
+static bool schema_ok(const Schema &s) {
+    if (s.n_dense < 0 || s.n_dense > kMaxDense || s.label_vocab < 0 || s.label_vocab > 65535) return false;
+    int bits = 0, off = 0;
+    for (int a = 0; a < s.n_dense; a++) {
+        const int32_t v = s.dense_vocab[a];
+        if (v < 1) return false;
+        int w = 1;
+        while ((1ll << w) < v) w++;
+        if (s.dense_off[a] != off || s.field_shift[a] != bits || s.field_bits[a] != w) return false;
+        off += v;
+        bits += w;
+    }
+    if (bits > 32 || s.dense_off[s.n_dense] != off) return false;
+    return s.n_tok == off + s.label_vocab && s.n_tok <= kMaxTokensLds;
+}
+
+// Checks the partition arrays that steer the search's memory accesses: offs
+// a monotone cover of [0, n) with one range per (partition, level), perm a
+// permutation, assign and level consistent with the range holding each
+// point, tags tokens of the schema (or -1 for an empty level), max_sub the
+// largest range.  A file failing any of them is refused before any search.
+static bool layout_ok(const Index &ix, const std::vector<int32_t> &tags, const std::vector<int32_t> &offs,
+                      const std::vector<int32_t> &perm, const std::vector<int32_t> &assign,
+                      const std::vector<int8_t> &level) {
+    const int64_t n = ix.n, ns = (int64_t)ix.b * (ix.h + 1);
+    if ((int64_t)offs.size() != ns + 1 || offs[0] != 0 || offs[(size_t)ns] != n) return false;
+    int32_t mx = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        if (offs[(size_t)s + 1] < offs[(size_t)s]) return false;
+        mx = std::max(mx, offs[(size_t)s + 1] - offs[(size_t)s]);
+    }
+    if (mx != ix.max_sub) return false;
+    std::vector<char> seen((size_t)n, 0);
+    for (int64_t s = 0; s < ns; s++) {
+        const int32_t p = (int32_t)(s / (ix.h + 1)), j = (int32_t)(s % (ix.h + 1));
+        for (int32_t pos = offs[(size_t)s]; pos < offs[(size_t)s + 1]; pos++) {
+            const int32_t id = perm[(size_t)pos];
+            if (id < 0 || id >= n || seen[(size_t)id]) return false;
+            seen[(size_t)id] = 1;
+            if (assign[(size_t)id] != p || level[(size_t)id] != j) return false;
+        }
+    }
+    for (int64_t t = 0; t < (int64_t)ix.b * ix.h; t++) {
+        const int32_t tk = tags[(size_t)t];
+        if (tk < -1 || tk >= ix.sch.n_tok) return false;
+        const int64_t s = t / ix.h * (ix.h + 1) + t % ix.h;   // the level this tag names
+        if (tk < 0 && offs[(size_t)s + 1] != offs[(size_t)s]) return false;
+    }
+    return true;
+}
+
 // Reads the file into a fresh index (device arrays allocated here).
 static caps_status load(Index &ix, const char *path) {
     File F;
@@ -147,10 +201,15 @@ static caps_status load(Index &ix, const char *path) {
     if (!get(F.f, &ver, 4) || ver != kVersion) return io_fail("caps_load: unsupported file version", path);
     if (!get(F.f, &hb, 4) || hb != sizeof(Header) || !get(F.f, &hd, sizeof hd))
         return io_fail("caps_load: bad header", path);
-    if (hd.n < 1 || hd.d < 1 || hd.b < 1 || hd.b > kMaxPartitions || hd.h < 0 || hd.h > kMaxHeight ||
-        (hd.metric != 0 && hd.metric != 1) || hd.prec < CAPS_PREC_NONE || hd.prec > CAPS_PREC_FP16 ||
-        hd.sch.n_dense < 0 || hd.sch.n_dense > kMaxDense)
+    if (hd.n < 1 || hd.n > INT32_MAX - 1 || hd.d < 1 || hd.b < 1 || hd.b > kMaxPartitions || hd.b > hd.n ||
+        hd.h < 0 || hd.h > kMaxHeight || (hd.metric != 0 && hd.metric != 1) || hd.prec < CAPS_PREC_NONE ||
+        hd.prec > CAPS_PREC_FP16 || !schema_ok(hd.sch))
         return io_fail("caps_load: header values out of range", path);
+    if (hd.prec != CAPS_PREC_NONE) {   // the copy's row width: the smallest of 32, 64, 128, 256 >= d
+        int ns = 1;
+        while (32 * ns < hd.d) ns <<= 1;
+        if (hd.d > 256 || hd.dpad != 32 * ns) return io_fail("caps_load: low-precision row width does not match d", path);
+    }
     CAPS_HIP(hipGetDevice(&ix.device));
     ix.n = hd.n;
     ix.d = hd.d;
@@ -162,6 +221,12 @@ static caps_status load(Index &ix, const char *path) {
     ix.max_sub = hd.max_sub;
     ix.sch = hd.sch;
     std::vector<uint8_t> host;
+    std::vector<int32_t> tags, offs, perm, assign;
+    std::vector<int8_t> level;
+    auto keep = [&](auto &v) {
+        v.resize(host.size() / sizeof(v[0]));
+        memcpy(v.data(), host.data(), host.size());
+    };
     for (const ArrayRef &a : arrays(ix)) {
         uint32_t tag = 0;
         uint64_t bytes = 0;
@@ -170,6 +235,17 @@ static caps_status load(Index &ix, const char *path) {
         if (!bytes) continue;
         host.resize(bytes);
         if (!get(F.f, host.data(), bytes)) return io_fail("caps_load: truncated file", path);
+        if (a.tag == 3) keep(tags);
+        if (a.tag == 4) keep(offs);
+        if (a.tag == 5) keep(perm);
+        if (a.tag == 6) keep(assign);
+        if (a.tag == 7) {   // the last of the layout arrays: check them before any vector is read
+            keep(level);
+            if (ix.h == 0) tags.clear();
+            if (!layout_ok(ix, tags, offs, perm, assign, level))
+                return io_fail("caps_load: inconsistent partition layout (offsets, permutation, levels or tags)",
+                               path);
+        }
         CAPS_HIP(hipMalloc(a.ptr, bytes));
         ix.bytes += (int64_t)bytes;
         CAPS_HIP(hipMemcpy(*a.ptr, host.data(), bytes, hipMemcpyHostToDevice));
@@ -182,7 +258,9 @@ static caps_status load(Index &ix, const char *path) {
         bool ok = get(F.f, &R->din, 4) && get(F.f, &R->dpad, 4) && get(F.f, &R->hid, 4) && get(F.f, &R->nout, 4) &&
                   get(F.f, &R->in_scale, 4) && get(F.f, &R->in_shift, 4) && get(F.f, &R->fb_prob, 4) &&
                   get(F.f, &R->step, 8) && get(F.f, &R->nparam, 8);
-        if (!ok || R->din != ix.d + 64 || R->dpad != (R->din + 31) / 32 * 32 || R->hid < 16 || R->nout != ix.b ||
+        if (!ok || R->din != ix.d + 64 || R->dpad != (R->din + 31) / 32 * 32 || R->hid < 16 || R->hid > 8192 ||
+            R->hid % 16 != 0 || R->nout != ix.b || R->step < 0 || !(R->in_scale == R->in_scale) ||
+            !(R->in_shift == R->in_shift) || !(R->fb_prob == R->fb_prob) ||
             R->nparam != (int64_t)R->hid * R->dpad + R->hid + (int64_t)R->nout * R->hid + R->nout)
             return io_fail("caps_load: bad router section", path);
         R->o_b1 = (int64_t)R->hid * R->dpad;

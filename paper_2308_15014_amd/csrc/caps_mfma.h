@@ -18,6 +18,7 @@ struct LowpArgs {
     const int32_t *entries;
     const uint32_t *sel;
     const QDesc *qd;
+    const QDesc *qterms;        // disjunctive searches: kMaxTerms term descriptors per query
     const int32_t *offs;
     const uint8_t *lvecs;       // CSR rows of dpad elements
     const float *lscale, *xnorm, *lerr, *lnrm;
@@ -217,6 +218,8 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // bounds rarely tighten within a tile), they are appended to their queries'
 // lists in global memory and rescored by the merge, which overlaps many
 // more of the row reads than one tile can.
+// HAS_LABELS selects the variant with the filter's slow path (label tests on
+// indexes with labels, the terms of disjunctive searches on any index).
 // Register budget per SIMD: four waves (at most 128 VGPRs) for the exact
 // main pass up to 128-element rows without label tests (it keeps no key
 // buffers), three for the approximate kind, two for the rescue pass (few
@@ -254,10 +257,8 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     __shared__ float qmx[2][kLNW];
 
     // one tile per workgroup; the rescue pass (a small grid) walks the list
-    // of tiles that hold a flagged query, written by k_rescue_tiles.  Every
-    // LDS region a tile writes before its first barrier belongs to the
-    // writing wave, so a wave may start the next tile while others finish
-    // the last one.
+    // of tiles that hold a flagged query, written by k_rescue_tiles, with a
+    // workgroup barrier between consecutive tiles.
     auto run_tile = [&](const int tile) {
     const int4 dsc = A.tiles[tile];
     if (dsc.z <= 0) return;
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     float *qnq = reinterpret_cast<float *>(smem + L.qnq);          // exact: |q|^2 per query
     int32_t *scnt = reinterpret_cast<int32_t *>(smem + L.scnt);    // survivors per query (counted runs)
     const bool has_dense = A.words != nullptr;
+    const bool has_lab = A.sigs != nullptr;
     const bool l2 = A.metric == 0;
     const bool count = A.nsurv != nullptr;
     const float qnan = __builtin_nanf("");
@@ -537,6 +539,20 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         }
     };
 
+    // The filter's slow path (the kernel variant with label tests, also used
+    // for disjunctive searches): a pair that passed the packed dense test
+    // (the exact test of a conjunction's dense constraints; for a disjunction
+    // the fields all its terms share) is checked against the query's labels,
+    // or against each term of a disjunction in full.
+    auto slow_pass = [&](int qi, uint32_t pw, int64_t pos) -> bool {
+        const QDesc &qd = qds[qi];
+        if (qd.flags & kQOr)
+            return query_passes(qd, A.qterms + (int64_t)(qslot[qi] / A.m) * kMaxTerms, has_dense, has_lab, pw,
+                                has_lab ? A.sigs[pos] : 0ull, has_lab ? A.slots + pos * kMaxLabels : nullptr);
+        if (!has_lab) return true;
+        return point_passes(qd, false, true, 0u, A.sigs[pos], A.slots + pos * kMaxLabels);
+    };
+
     int cj = -1;
     int32_t cc0 = 0, cend = 0;
     next_level(cj, cc0, cend);
@@ -627,11 +643,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                     for (int rr = 0; rr < 4; rr++) {
                         const uint32_t rs = rsel(rr);   // every lane (a cross-lane read)
                         bool ok = pi < cn && ((rs >> j) & 1u) && (pw & rmask[rr]) == rval[rr];
-                        if (HAS_LABELS && ok) {
-                            const int qi = qbase + g * 4 + rr;
-                            ok = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
-                                              A.slots + (int64_t)(c0 + pi) * kMaxLabels);
-                        }
+                        if (HAS_LABELS && ok) ok = slow_pass(qbase + g * 4 + rr, pw, c0 + pi);
                         if (ok) atomicAdd(scnt + qbase + g * 4 + rr, 1);
                     }
                 }
@@ -643,9 +655,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                         // lanes 16g..16g+15 hold row 4g+rr: one query per 16-lane group
                         const int qi = qbase + g * 4 + rr;
                         bool qual = (hit[rr] >> lane) & 1ull;
-                        if (HAS_LABELS && qual)
-                            qual = point_passes(qds[qi], false, true, 0u, A.sigs[c0 + pi],
-                                                A.slots + (int64_t)(c0 + pi) * kMaxLabels);
+                        if (HAS_LABELS && qual) qual = slow_pass(qi, pw, c0 + pi);
                         if (DEFER) {
                             // queue the pair for the deferred lists; when the ring
                             // is full, its query goes to the rescue pass instead
@@ -736,8 +746,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     }
     };
     if (RESCUE) {
+        // a workgroup walking several tiles waits for all its waves between
+        // them: the cursor and bound arrays (spo, lvw, qmx) are rewritten at
+        // the start of a tile and read until its end
         const int nr = *A.rcount;
-        for (int i = blockIdx.x; i < nr; i += gridDim.x) run_tile(A.rlist[i]);
+        for (int i = blockIdx.x; i < nr; i += gridDim.x) {
+            run_tile(A.rlist[i]);
+            __syncthreads();
+        }
     } else {
         const int tile = xcd_tile(blockIdx.x, A.ntiles);
         if (tile >= 0) run_tile(tile);

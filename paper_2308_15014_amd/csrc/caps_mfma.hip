@@ -275,8 +275,8 @@ static LowpFn pick_prec(int prec, int ns, bool lab, int r) {
 // long list, few enough that an empty one costs little
 constexpr int64_t kRescueWgs = 8192;
 
-size_t lowp_scan_lds(const Index *ix, int r, int kind) {
-    return LowpLds(kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0).total + 64;
+size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj) {
+    return LowpLds(kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0 || disj).total + 64;
 }
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
@@ -289,6 +289,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.entries = S.entries;
     A.sel = S.sel;
     A.qd = S.qd;
+    A.qterms = S.qterms;
     A.offs = ix->offs;
     A.lvecs = reinterpret_cast<const uint8_t *>(ix->lvecs);
     A.lscale = ix->lscale;
@@ -329,16 +330,18 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     // (four times that).
     A.eta = (float)(6.0 * ix->dpad + 64.0) * 0x1p-24f;
     A.gam = (float)(8.0 * ix->dpad) * 0x1p-24f;
-    const bool lab = ix->sch.label_vocab > 0;
+    // the variant with the filter's slow path: label tests, disjunctions
+    const bool lab = ix->sch.label_vocab > 0 || S.disj;
     const LowpFn fn = S.kind == 0   ? pick_prec<0>(ix->prec, ix->dpad / 32, lab, S.r)
                       : S.kind == 1 ? pick_prec<1>(ix->prec, ix->dpad / 32, lab, S.r)
                                     : pick_prec<2>(ix->prec, ix->dpad / 32, lab, S.r);
-    const size_t lds = lowp_scan_lds(ix, S.r, S.kind);
+    const size_t lds = lowp_scan_lds(ix, S.r, S.kind, S.disj);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(S.stage, st);
     // the rescue pass walks its (device-side) tile list with a bounded grid
     const int64_t full = (S.max_tiles + kXcds - 1) / kXcds * kXcds;
-    const int64_t grid = S.kind == 2 ? std::min<int64_t>(full, kRescueWgs) : full;
+    const int64_t rcap = S.rescue_grid > 0 ? S.rescue_grid : kRescueWgs;
+    const int64_t grid = S.kind == 2 ? std::min<int64_t>(full, rcap) : full;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kLNT), lds, st, A);
     prof_end(S.stage, st);
     CAPS_HIP(hipGetLastError());

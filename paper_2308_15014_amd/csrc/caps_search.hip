@@ -27,54 +27,109 @@ namespace caps {
 
 
 // ------------------------------------------------------------------ prep
-__global__ __launch_bounds__(128) void k_qprep(const int32_t *__restrict__ con_off, const int32_t *__restrict__ con_attr,
-                        const int32_t *__restrict__ con_val, int32_t n_con, int32_t nq, Schema sch,
-                        QDesc *__restrict__ out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    QDesc r;
+__device__ inline void qd_clear(QDesc &r) {
     r.dmask = 0;
     r.dval = 0;
     r.flags = 0;
     r.nlab = 0;
     r.lsig = 0;
     for (int i = 0; i < kMaxLabels; i++) r.lab[i] = 0xFFFF;
+    r.nterm = 1;
+    r.pad = 0;
+}
+
+// Adds constraint pair (a, v) to the AND-term r: a dense value becomes a
+// packed field under dmask, a label joins the label list and signature; a
+// pair outside the vocabularies, a second value of one dense attribute or a
+// ninth label makes the term unsatisfiable.
+__device__ inline void qd_add(QDesc &r, const Schema &sch, int32_t a, int32_t v) {
+    if (a < 0 || a > sch.n_dense) {
+        r.flags |= kQUnsat;
+        return;
+    }
+    if (a < sch.n_dense) {
+        if (v < 0 || v >= sch.dense_vocab[a]) {
+            r.flags |= kQUnsat;
+            return;
+        }
+        const uint32_t fm = (uint32_t)(((1ull << sch.field_bits[a]) - 1ull) << sch.field_shift[a]);
+        const uint32_t fv = (uint32_t)v << sch.field_shift[a];
+        if ((r.dmask & fm) && ((r.dval & fm) != fv)) r.flags |= kQUnsat;
+        r.dmask |= fm;
+        r.dval = (r.dval & ~fm) | fv;
+        return;
+    }
+    if (sch.label_vocab == 0 || v < 0 || v >= sch.label_vocab) {
+        r.flags |= kQUnsat;
+        return;
+    }
+    for (int i = 0; i < r.nlab; i++)
+        if (r.lab[i] == (uint16_t)v) return;   // duplicate: AND is idempotent
+    if (r.nlab == kMaxLabels) {
+        r.flags |= kQUnsat;
+        return;
+    }
+    r.lab[r.nlab++] = (uint16_t)v;
+    r.lsig |= 1ull << label_sig_bit((uint32_t)v);
+}
+
+// One thread per query.  Without `disj` every pair is ANDed (a pair with a
+// negative attribute, CAPS_OR included, makes the query unsatisfiable).
+// With `disj` the pairs with attr == CAPS_OR separate AND-terms: the
+// satisfiable terms go to terms[q * kMaxTerms ..] and the summary holds
+// kQOr, their number and the dense fields every term fixes to the same value
+// (a query with one satisfiable term is that term; none, or more than
+// kMaxTerms terms: unsatisfiable).
+__global__ __launch_bounds__(128) void k_qprep(const int32_t *__restrict__ con_off, const int32_t *__restrict__ con_attr,
+                        const int32_t *__restrict__ con_val, int32_t n_con, int32_t nq, Schema sch, int32_t disj,
+                        QDesc *__restrict__ out, QDesc *__restrict__ terms) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    QDesc r;
+    qd_clear(r);
     int32_t lo = con_off[q], hi = con_off[q + 1];
     if (lo < 0 || hi < lo || hi > n_con) {
-        r.flags |= 1u;
-        lo = hi = 0;
+        r.flags |= kQUnsat;
+        out[q] = r;
+        return;
     }
-    for (int32_t e = lo; e < hi; e++) {
-        const int32_t a = con_attr[e], v = con_val[e];
-        if (a < 0 || a > sch.n_dense) {
-            r.flags |= 1u;
+    if (!disj) {
+        for (int32_t e = lo; e < hi; e++) qd_add(r, sch, con_attr[e], con_val[e]);
+        out[q] = r;
+        return;
+    }
+    QDesc *tq = terms + (int64_t)q * kMaxTerms;
+    QDesc cur;
+    qd_clear(cur);
+    int nt = 0, nsat = 0;
+    for (int32_t e = lo; e <= hi; e++) {
+        if (e < hi && con_attr[e] != CAPS_OR) {
+            qd_add(cur, sch, con_attr[e], con_val[e]);
             continue;
         }
-        if (a < sch.n_dense) {
-            if (v < 0 || v >= sch.dense_vocab[a]) {
-                r.flags |= 1u;
-                continue;
-            }
-            const uint32_t fm = (uint32_t)(((1ull << sch.field_bits[a]) - 1ull) << sch.field_shift[a]);
-            const uint32_t fv = (uint32_t)v << sch.field_shift[a];
-            if ((r.dmask & fm) && ((r.dval & fm) != fv)) r.flags |= 1u;
-            r.dmask |= fm;
-            r.dval = (r.dval & ~fm) | fv;
-        } else {
-            if (sch.label_vocab == 0 || v < 0 || v >= sch.label_vocab) {
-                r.flags |= 1u;
-                continue;
-            }
-            bool dup = false;
-            for (int i = 0; i < r.nlab; i++) dup |= r.lab[i] == (uint16_t)v;
-            if (dup) continue;
-            if (r.nlab == kMaxLabels) {
-                r.flags |= 1u;
-                continue;
-            }
-            r.lab[r.nlab++] = (uint16_t)v;
-            r.lsig |= 1ull << label_sig_bit((uint32_t)v);
+        if (++nt > kMaxTerms) break;
+        if (!(cur.flags & kQUnsat)) tq[nsat++] = cur;
+        qd_clear(cur);
+    }
+    if (nt > kMaxTerms || nsat == 0) {
+        r.flags |= kQUnsat;
+    } else if (nsat == 1) {
+        r = tq[0];
+    } else {
+        uint32_t all = ~0u, diff = 0;
+        for (int t = 0; t < nsat; t++) {
+            all &= tq[t].dmask;
+            diff |= tq[t].dval ^ tq[0].dval;
         }
+        uint32_t keep = 0;
+        for (int a = 0; a < sch.n_dense; a++) {
+            const uint32_t fm = (uint32_t)(((1ull << sch.field_bits[a]) - 1ull) << sch.field_shift[a]);
+            if ((all & fm) == fm && !(diff & fm)) keep |= fm;
+        }
+        r.dmask = keep;
+        r.dval = tq[0].dval & keep;
+        r.flags = kQOr;
+        r.nterm = nsat;
     }
     out[q] = r;
 }
@@ -350,7 +405,7 @@ __device__ inline void tag_decode(const Schema &s, int32_t tok, int &attr, int32
 // dense constraint; scan the remainder iff J* = h.  rule 1: only level J*.
 __device__ inline uint32_t choose_levels(const Schema &s, const QDesc &qd, const int32_t *tags, int h,
                                          int rule) {
-    if (qd.flags & 1u) return 0u;
+    if (qd.flags & (kQUnsat | kQNonFinite)) return 0u;
     int js = h;
     uint32_t ok = 0;
     for (int j = 0; j < h; j++) {
@@ -382,15 +437,27 @@ __device__ inline uint32_t choose_levels(const Schema &s, const QDesc &qd, const
     return mask;
 }
 
+// A query's levels: the union over its terms for a disjunction (Section 5.3:
+// several sub-partitions per partition join the candidate set).
+__device__ inline uint32_t choose_query_levels(const Schema &s, const QDesc &qd, const QDesc *terms,
+                                               const int32_t *tags, int h, int rule) {
+    if (qd.flags & (kQUnsat | kQNonFinite)) return 0u;
+    if (!(qd.flags & kQOr)) return choose_levels(s, qd, tags, h, rule);
+    uint32_t mask = 0;
+    for (int t = 0; t < qd.nterm; t++) mask |= choose_levels(s, terms[t], tags, h, rule);
+    return mask;
+}
+
 __global__ void k_select(const int32_t *__restrict__ probes, int32_t nq, int32_t m,
-                         const QDesc *__restrict__ qd, Schema sch, const int32_t *__restrict__ tags,
-                         int32_t h, const int32_t *__restrict__ offs, int32_t rule,
+                         const QDesc *__restrict__ qd, const QDesc *__restrict__ qterms, Schema sch,
+                         const int32_t *__restrict__ tags, int32_t h, const int32_t *__restrict__ offs, int32_t rule,
                          uint32_t *__restrict__ sel, int32_t *__restrict__ cand_out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)nq * m) return;
     const int32_t q = (int32_t)(e / m);
     const int32_t p = probes[e];
-    const uint32_t mask = choose_levels(sch, qd[q], tags + (int64_t)p * h, h, rule);
+    const uint32_t mask = choose_query_levels(sch, qd[q], qterms + (int64_t)q * kMaxTerms, tags + (int64_t)p * h, h,
+                                              rule);
     int32_t cand = 0;
     for (int j = 0; j <= h; j++)
         if (mask & (1u << j)) cand += offs[(int64_t)p * (h + 1) + j + 1] - offs[(int64_t)p * (h + 1) + j];
@@ -676,6 +743,7 @@ struct ScanArgs {
     const uint32_t *sel;
     const float *q;
     const QDesc *qd;
+    const QDesc *qterms;   // disjunctive searches: kMaxTerms term descriptors per query
     const int32_t *offs, *perm;
     const float *vecs;
     const uint32_t *words;
@@ -1006,8 +1074,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
             const uint32_t sl = __builtin_amdgcn_readlane(my_sel, i);
             if (!(sl & (1u << j))) continue;
             bool pass;
-            if (HAS_LABELS) {
-                pass = lane_ok && point_passes(qds[qbase + i], has_dense, true, myw, mysig,
+            if (HAS_LABELS || (qds[qbase + i].flags & kQOr)) {
+                const QDesc *terms = A.qterms + (int64_t)(qslot[qbase + i] / A.m) * kMaxTerms;
+                pass = lane_ok && query_passes(qds[qbase + i], terms, has_dense, HAS_LABELS, myw, mysig,
                                                xslot + lane * kMaxLabels);
             } else {
                 const uint32_t dm = __builtin_amdgcn_readlane(my_dmask, i);
@@ -1210,11 +1279,13 @@ struct SearchWs {
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *oflow;             // exact matrix-core scan: queries for the rescue pass
     int32_t *rlist, *rcount;    // exact matrix-core scan: tiles for the rescue pass
-    int32_t *hist, *hscan, *htotal, *pcount, *pstart, *tstart;
+    int32_t *hist, *hscan, *scan_sums, *htotal, *pcount, *pstart, *tstart;
     int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
     float *conf;                // learned routing: softmax top-1 probability
     int32_t *probes_c;          // learned routing: centroid probes for the fallback
+    int32_t *bad;               // query rows holding NaN or Inf (one counter per call)
+    QDesc *qterms;              // disjunctive searches: term descriptors (kMaxTerms per query)
 };
 
 // Tiles of one round at most: every (query, probe) entry in tiles of at
@@ -1228,8 +1299,10 @@ constexpr int32_t kDeferCap = 512;
 
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
                   bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router, bool defer,
-                  int32_t nc) {
+                  int32_t nc, bool disj) {
     const int32_t ngrp_max = (sb + kBucketQ - 1) / kBucketQ;
+    w.bad = ar.take<int32_t>(1);
+    w.qterms = disj ? ar.take<QDesc>((size_t)sb * kMaxTerms) : nullptr;
     w.qlow = qlow_row_bytes ? ar.take<uint8_t>((size_t)sb * qlow_row_bytes) : nullptr;
     w.qscale = qlow_row_bytes ? ar.take<float>((size_t)sb) : nullptr;
     w.qaux = qlow_row_bytes ? ar.take<float>((size_t)sb * 4) : nullptr;
@@ -1251,6 +1324,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.rcount = defer ? ar.take<int32_t>(2) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
+    w.scan_sums = ar.take<int32_t>((size_t)exclusive_scan_tiles((int64_t)b * ngrp_max) + 1);
     w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
     w.htotal = ar.take<int32_t>(1);
     w.pcount = ar.take<int32_t>(b + 1);
@@ -1264,7 +1338,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
 }
 
 // Shape of one search call: which scan, keys per (query, probe), the
-// sub-batch that keeps the workspace near 4 GiB.
+// sub-batch that keeps the workspace within the budget.
 struct SearchPlan {
     bool lowp, mfma, defer;
     int32_t r, sb;
@@ -1272,7 +1346,7 @@ struct SearchPlan {
     const Router *router;
 };
 
-static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int32_t nq) {
+static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int32_t nq, size_t budget) {
     const int32_t b = ix->b, m = sp->nprobe, k = sp->k;
     SearchPlan P;
     // mode 1: approximate keys on the matrix cores, rescored at the merge;
@@ -1291,49 +1365,127 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          sizeof(int32_t) * (size_t)m +
                          (P.defer ? sizeof(int32_t) * (size_t)(kDeferCap + 2 + m / 64) : 0) +
                          sizeof(int4) * (size_t)m / 64 +
+                         ((sp->flags & CAPS_SEARCH_DISJUNCTIVE) ? sizeof(QDesc) * kMaxTerms : 0) +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
                                          sizeof(int32_t) * (size_t)m
                                    : 0);
-    // default of 4 GiB (of 288 GB): a 10k-query batch in one go in every mode
-    const size_t budget = sp->workspace_bytes > 0 ? (size_t)sp->workspace_bytes : (size_t)4 << 30;
     P.sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nq, 1), budget / per_q));
     return P;
 }
 
-size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq) {
-    const SearchPlan P = plan_search(ix, sp, nq);
+// default workspace budget of one call (of 288 GB): a 10k-query batch in
+// one go in every mode
+static size_t default_budget(const caps_search_params *sp) {
+    return sp->workspace_bytes > 0 ? (size_t)sp->workspace_bytes : (size_t)4 << 30;
+}
+
+static size_t measure_ws(const Index *ix, const caps_search_params *sp, const SearchPlan &P, int32_t nq,
+                         int32_t sb, bool own_ncand, bool own_nsurv) {
     SearchWs W;
     Arena measure;
-    carve(measure, W, nq, P.sb, ix->b, sp->nprobe, P.r, true, true, P.qlow_row, P.router, P.defer,
-          bucket_classes(ix->h));
+    carve(measure, W, nq, sb, ix->b, sp->nprobe, P.r, own_ncand, own_nsurv, P.qlow_row, P.router, P.defer,
+          bucket_classes(ix->h), (sp->flags & CAPS_SEARCH_DISJUNCTIVE) != 0);
     return measure.off;
+}
+
+size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq) {
+    const SearchPlan P = plan_search(ix, sp, nq, default_budget(sp));
+    return measure_ws(ix, sp, P, nq, P.sb, true, true);
+}
+
+// Non-finite query rows: flagged unsatisfiable (they choose no sub-partition,
+// so their results are all padding) and counted.  One wave per query.
+__global__ __launch_bounds__(256) void k_qcheck(const float *__restrict__ q, int32_t nq, int32_t d,
+                                                QDesc *__restrict__ qd, int32_t *__restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nq) return;
+    bool ok = true;
+    for (int j = lane; j < d; j += 64) ok &= __builtin_isfinite(q[i * d + j]);
+    if (__ballot(!ok) != 0 && lane == 0) {
+        qd[i].flags |= 2u;
+        atomicAdd(bad, 1);
+    }
+}
+
+// Survivor bits for the debug entry point: bit pos % 64 of word pos / 64 of
+// a query's row is set when CSR position pos lies in a sub-partition its
+// search chose and passes its filter.  One wave per (query, probe) slot.
+__global__ __launch_bounds__(256) void k_surv_mask(const int32_t *__restrict__ probes, const uint32_t *__restrict__ sel,
+                                                   int32_t nq, int32_t m, const QDesc *__restrict__ qd,
+                                                   const QDesc *__restrict__ qterms,
+                                                   const int32_t *__restrict__ offs, int32_t h,
+                                                   const uint32_t *__restrict__ words, const uint64_t *__restrict__ sigs,
+                                                   const uint16_t *__restrict__ slots, uint64_t *__restrict__ mask,
+                                                   int64_t mask_words) {
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= (int64_t)nq * m) return;
+    const uint32_t sm = sel[e];
+    if (!sm) return;
+    const int64_t qi = e / m;
+    const int32_t p = probes[e];
+    const QDesc Q = qd[qi];
+    for (int j = 0; j <= h; j++) {
+        if (!((sm >> j) & 1u)) continue;
+        const int32_t lo = offs[(int64_t)p * (h + 1) + j], hi = offs[(int64_t)p * (h + 1) + j + 1];
+        for (int32_t pos = lo + lane; pos < hi; pos += 64) {
+            const bool pass = query_passes(Q, qterms + qi * kMaxTerms, words != nullptr, sigs != nullptr,
+                                           words ? words[pos] : 0u, sigs ? sigs[pos] : 0ull,
+                                           slots ? slots + (int64_t)pos * kMaxLabels : nullptr);
+            if (pass) atomicOr((unsigned long long *)(mask + qi * mask_words + pos / 64), 1ull << (pos % 64));
+        }
+    }
 }
 
 caps_status search(const Index *ix, const caps_search_params *sp, const float *q, int32_t nq,
                    const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand,
-                   int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st) {
+                   int32_t *out_nsurv, int32_t *out_probes, uint32_t *out_masks, hipStream_t st,
+                   const SearchExtra *extra) {
+    const SearchExtra ex = extra ? *extra : SearchExtra{};
     const int32_t b = ix->b, d = ix->d, h = ix->h, m = sp->nprobe, k = sp->k;
     if (nq == 0) return CAPS_OK;
-    const SearchPlan P = plan_search(ix, sp, nq);
+    // a caller workspace (no allocation) bounds the sub-batch: shrink it
+    // until its layout fits
+    const size_t budget = ex.ws ? ex.ws_bytes : default_budget(sp);
+    SearchPlan P = plan_search(ix, sp, nq, budget);
+    size_t need = measure_ws(ix, sp, P, nq, P.sb, !out_ncand, !out_nsurv);
+    if (ex.ws) {
+        while (need > ex.ws_bytes && P.sb > 1) {
+            P.sb = std::max<int32_t>(1, (int32_t)((double)P.sb * (double)ex.ws_bytes / (double)need * 0.95));
+            need = measure_ws(ix, sp, P, nq, P.sb, !out_ncand, !out_nsurv);
+        }
+        if (need > ex.ws_bytes) {
+            set_error("caps_search: one query needs %zu bytes of workspace, more than the %zu available", need,
+                      ex.ws_bytes);
+            return CAPS_EUNSUPPORTED;
+        }
+    }
     const bool lowp = P.lowp, mfma = P.mfma;
     const int32_t r = P.r, sb = P.sb;
     const int32_t nc = bucket_classes(h);
     const size_t qlow_row = P.qlow_row;
     const Router *router = P.router;
     const bool probes_only = out_probes != nullptr;
+    const bool disj = (sp->flags & CAPS_SEARCH_DISJUNCTIVE) != 0;
+    const int64_t mask_words = (ix->n + 63) / 64;
     int pb = 1;
     while (pb < b) pb <<= 1;
 
     SearchWs W;
-    Arena measure;
-    carve(measure, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc);
     Arena ar;
-    ar.cap = measure.off;
-    CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
-    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc);
+    ar.cap = need;
+    if (ex.ws) {
+        ar.base = reinterpret_cast<char *>(ex.ws);
+    } else {
+        CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
+    }
+    carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc, disj);
+
+    // the search proper; every exit below goes through the release at the end
+    auto run = [&]() -> caps_status {
     if (ar.overflow) {
-        (void)hipFreeAsync(ar.base, st);
         set_error("caps_search: internal workspace layout error");
         return CAPS_EDEVICE;
     }
@@ -1350,238 +1502,270 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     int32_t *hist = W.hist, *hscan = W.hscan, *htotal = W.htotal;
     int32_t *pcount = W.pcount, *pstart = W.pstart, *tstart = W.tstart;
 
-    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, W.bad, (int64_t)1, 0);
+    if (!probes_only) hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nq, 256)), dim3(256), 0, st, nsurv, (int64_t)nq, 0);
+    if (ex.surv_mask)
+        hipLaunchKernelGGL(k_fill_u64, dim3(nblocks((int64_t)nq * mask_words, 256)), dim3(256), 0, st, ex.surv_mask,
+                           (int64_t)nq * mask_words, 0ull);
 
     const bool has_labels = ix->sch.label_vocab > 0;
-    const size_t lds = mfma ? lowp_scan_lds(ix, r, lowp ? 0 : 2) : scan_lds_bytes(d, k);
+    const size_t lds = mfma ? lowp_scan_lds(ix, r, lowp ? 0 : 2, disj) : scan_lds_bytes(d, k);
     const int qb = mfma ? lowp_qb() : scan_waves(k) * kQPW;
     const ScanFn scan_fn = pick_scan(ix->metric, has_labels, d, k);
     if (!probes_only && !mfma) {
         int lds_max = 0;
         CAPS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
         if (lds > (size_t)lds_max) {
-            (void)hipFreeAsync(ar.base, st);
             set_error("caps_search: d=%d, k=%d need %zu bytes of LDS per workgroup (limit %d)", d, k, lds,
                       lds_max);
             return CAPS_EUNSUPPORTED;
         }
         CAPS_HIP(hipFuncSetAttribute((const void *)scan_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
-    for (int32_t q0 = 0; q0 < nq; q0 += sb) {
-        const int32_t nb = std::min(sb, nq - q0);
-        const int64_t pairs = (int64_t)nb * m;
-        const int32_t ngrp = (nb + kBucketQ - 1) / kBucketQ;
-        const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 24 : 16)) : m;
-        // the probes query returns them sorted; a search takes the best m as
-        // a set with the s_seed best first
-        const int32_t topm_s = probes_only ? -1 : s_seed;
-        prof_begin(CAPS_STAGE_PREP, st);
-        hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
-                           con_val, n_con, nb, ix->sch, qd);
-        prof_end(CAPS_STAGE_PREP, st);
-        if (router) {
-            // learned routing: router probes, their candidate counts, then a
-            // per-query fallback to the centroid probes
+        for (int32_t q0 = 0; q0 < nq; q0 += sb) {
+            const int32_t nb = std::min(sb, nq - q0);
+            const int64_t pairs = (int64_t)nb * m;
+            const int32_t ngrp = (nb + kBucketQ - 1) / kBucketQ;
+            const int32_t s_seed = m >= 32 ? std::max(8, m / (P.defer ? 24 : 16)) : m;
+            // the probes query returns them sorted; a search takes the best m as
+            // a set with the s_seed best first
+            const int32_t topm_s = probes_only ? -1 : s_seed;
+            prof_begin(CAPS_STAGE_PREP, st);
+            hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
+                               con_val, n_con, nb, ix->sch, (int32_t)disj, qd, W.qterms);
+            hipLaunchKernelGGL(k_qcheck, dim3(nblocks(nb, 4)), dim3(256), 0, st, q + (int64_t)q0 * d, nb, d, qd, W.bad);
+            prof_end(CAPS_STAGE_PREP, st);
+            if (router) {
+                // learned routing: router probes, their candidate counts, then a
+                // per-query fallback to the centroid probes
+                prof_begin(CAPS_STAGE_ROUTE, st);
+                const caps_status rs = router_scores(ix, q + (int64_t)q0 * d, nb, con_off + q0, con_attr, con_val, n_con,
+                                                     W.rx, W.rh, scores, W.conf, st);
+                if (rs != CAPS_OK) return rs;
+                prof_end(CAPS_STAGE_ROUTE, st);
+                prof_begin(CAPS_STAGE_TOPM, st);
+                launch_topm(scores, nb, b, pb, m, probes, st, topm_s);
+                prof_end(CAPS_STAGE_TOPM, st);
+                prof_begin(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, W.qterms, ix->sch,
+                                   ix->tags, h, ix->offs, sp->rule, sel, cand);
+                prof_end(CAPS_STAGE_SELECT, st);
+            }
             prof_begin(CAPS_STAGE_ROUTE, st);
-            const caps_status rs = router_scores(ix, q + (int64_t)q0 * d, nb, con_off + q0, con_attr, con_val, n_con,
-                                                 W.rx, W.rh, scores, W.conf, st);
-            if (rs != CAPS_OK) return rs;
+            hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
+                               q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
             prof_end(CAPS_STAGE_ROUTE, st);
             prof_begin(CAPS_STAGE_TOPM, st);
-            launch_topm(scores, nb, b, pb, m, probes, st, topm_s);
+            launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s);
             prof_end(CAPS_STAGE_TOPM, st);
+            if (router) {
+                const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
+                if (fs != CAPS_OK) return fs;
+            }
             prof_begin(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
+            hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, W.qterms, ix->sch,
                                ix->tags, h, ix->offs, sp->rule, sel, cand);
-            prof_end(CAPS_STAGE_SELECT, st);
-        }
-        prof_begin(CAPS_STAGE_ROUTE, st);
-        hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
-                           q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
-        prof_end(CAPS_STAGE_ROUTE, st);
-        prof_begin(CAPS_STAGE_TOPM, st);
-        launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s);
-        prof_end(CAPS_STAGE_TOPM, st);
-        if (router) {
-            const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
-            if (fs != CAPS_OK) return fs;
-        }
-        prof_begin(CAPS_STAGE_SELECT, st);
-        hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, ix->sch,
-                           ix->tags, h, ix->offs, sp->rule, sel, cand);
-        CAPS_HIP(hipGetLastError());
-        if (probes_only) {
-            prof_end(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes,
-                               out_probes + (int64_t)q0 * m, pairs);
-            hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, (const int32_t *)sel,
-                               (int32_t *)(out_masks + (int64_t)q0 * m), pairs);
             CAPS_HIP(hipGetLastError());
-            continue;
-        }
-        hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
-        if (P.defer) {
-            hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
-            hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.oflow, (int64_t)nb, 0);
-        }
-        prof_end(CAPS_STAGE_SELECT, st);
-        // Two rounds: the first probes of every query (best first) give each
-        // query a tight seed bound on its final r-th key; the remaining probes
-        // are scanned against it.  Exact keys on the matrix cores: the first
-        // round is an approximate scan of the seed probes (every probe when
-        // m < 32) whose best candidates are rescored exactly for the bound
-        // (k_seed_exact); the second scans every probe and defers its pairs
-        // to the merge, and a rescue pass rescans the queries whose pairs
-        // did not fit.  (The approximate seed pass is cheap per probe but
-        // its bound looser: m/24 seed probes there, enough that on the
-        // 1M-point benchmark no query's pairs overflow.)
-        const bool seeded_exact = P.defer;
-        for (int round = 0; round < 2; round++) {
-            const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
-            const int32_t r1 = round == 0 ? s_seed : m;
-            if (r0 >= r1) continue;
-            prof_begin(CAPS_STAGE_SELECT, st);
-            hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                               nb, m, r0, r1, b, ngrp, hist);
-            {
-                const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, st);
-                if (es != CAPS_OK) return es;
-            }
-            hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
-                               tstart);
-            const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
-            const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
-            hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
-                               qb, (int32_t)grid, W.tiles);
-            // the fill packs each entry's class when entries stay below 2^27
-            const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
-            hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                               nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
-            const int32_t *ent = entries;
-            if (nc > 1) {
-                hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(kClassW * 64), 0, st, entries, sel, pstart, pcount, nc,
-                                   (int32_t)(nc_pack > 1), W.entries2);
-                ent = W.entries2;
-            }
-            CAPS_HIP(hipGetLastError());
-            prof_end(CAPS_STAGE_SELECT, st);
-            if (mfma) {
-                const bool seed_pass = seeded_exact && round == 0;
-                LowpScan S{};
-                S.nb = nb;
-                S.m = m;
-                S.r = r;
-                S.kind = lowp || seed_pass ? 0 : 1;
-                S.first_round = round == 0;
-                S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
-                S.max_tiles = grid;
-                S.tiles = W.tiles;
-                S.entries = ent;
-                S.sel = sel;
-                S.qd = qd;
-                S.q = q + (int64_t)q0 * d;
-                S.qlow = W.qlow;
-                S.qscale = W.qscale;
-                S.qaux = W.qaux;
-                S.partials = partials;
-                S.tau = tau;
-                S.pcnt = W.pcnt;
-                S.nsurv = out_nsurv && !seed_pass ? nsurv + q0 : nullptr;   // counted only when asked for
-                S.dpos = W.dpos;
-                S.dcnt = W.dcnt;
-                S.dcap = kDeferCap;
-                S.oflow = W.oflow;
-                const caps_status ls = lowp_scan(ix, S, st);
-                if (ls != CAPS_OK) return ls;
-                if (S.kind == 1) {   // rescue pass over the tiles that hold a flagged query
-                    hipLaunchKernelGGL(k_rescue_init, dim3(1), dim3(1024), 0, st, W.oflow, nb, W.rcount);
-                    hipLaunchKernelGGL(k_rescue_tiles, dim3(nblocks(grid, 256)), dim3(256), 0, st, W.tiles,
-                                       (int32_t)grid, ent, m, W.oflow, W.rlist, W.rcount);
-                    S.kind = 2;
-                    S.rlist = W.rlist;
-                    S.rcount = W.rcount;
-                    S.nsurv = nullptr;
-                    S.stage = CAPS_STAGE_RESCUE;
-                    const caps_status rs = lowp_scan(ix, S, st);
-                    if (rs != CAPS_OK) return rs;
-                }
-            } else {
-                ScanArgs A;
-                A.tiles = W.tiles;
-                A.ntiles = (int32_t)grid;
-                A.entries = ent;
-                A.sel = sel;
-                A.q = q + (int64_t)q0 * d;
-                A.qd = qd;
-                A.offs = ix->offs;
-                A.perm = ix->perm;
-                A.vecs = ix->vecs;
-                A.words = ix->words;
-                A.sigs = ix->sigs;
-                A.slots = ix->slots;
-                A.partials = partials;
-                A.tau = tau;
-                A.nsurv = nsurv + q0;
-                A.d = d;
-                A.m = m;
-                A.h = h;
-                A.b = b;
-                A.k = k;
-                prof_begin(CAPS_STAGE_SCAN, st);
-                hipLaunchKernelGGL(scan_fn, dim3((unsigned)grid), dim3(scan_waves(k) * 64), lds, st, A);
-                prof_end(CAPS_STAGE_SCAN, st);
-                CAPS_HIP(hipGetLastError());
-            }
-            if (round == 0 && seeded_exact) {
-                prof_begin(CAPS_STAGE_SEED, st);
-                hipLaunchKernelGGL(k_seed_exact, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, W.pcnt, sel, nb,
-                                   m, s_seed, r, std::min(2 * k, 64), k, ix->vecs, q + (int64_t)q0 * d, ix->perm, d,
-                                   ix->metric, tau);
-                prof_end(CAPS_STAGE_SEED, st);
-                CAPS_HIP(hipGetLastError());
-            } else if (round == 0 && s_seed < m) {
-                prof_begin(CAPS_STAGE_SELECT, st);
-                hipLaunchKernelGGL(k_seed_tau, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials,
-                                   lowp ? W.pcnt : nullptr, sel, nb, m, s_seed, r, r, tau);
+            if (probes_only) {
                 prof_end(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes,
+                                   out_probes + (int64_t)q0 * m, pairs);
+                hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(pairs, 256)), dim3(256), 0, st, (const int32_t *)sel,
+                                   (int32_t *)(out_masks + (int64_t)q0 * m), pairs);
                 CAPS_HIP(hipGetLastError());
+                continue;
             }
+            if (ex.surv_mask)
+                hipLaunchKernelGGL(k_surv_mask, dim3(nblocks(pairs, 4)), dim3(256), 0, st, probes, sel, nb, m, qd, W.qterms, ix->offs,
+                                   h, ix->words, ix->sigs, ix->slots, ex.surv_mask + (int64_t)q0 * mask_words, mask_words);
+            hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
+            if (P.defer) {
+                hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
+                hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.oflow, (int64_t)nb, 0);
+            }
+            prof_end(CAPS_STAGE_SELECT, st);
+            // Two rounds: the first probes of every query (best first) give each
+            // query a tight seed bound on its final r-th key; the remaining probes
+            // are scanned against it.  Exact keys on the matrix cores: the first
+            // round is an approximate scan of the seed probes (every probe when
+            // m < 32) whose best candidates are rescored exactly for the bound
+            // (k_seed_exact); the second scans every probe and defers its pairs
+            // to the merge, and a rescue pass rescans the queries whose pairs
+            // did not fit.  (The approximate seed pass is cheap per probe but
+            // its bound looser: m/24 seed probes there, enough that on the
+            // 1M-point benchmark no query's pairs overflow.)
+            const bool seeded_exact = P.defer;
+            for (int round = 0; round < 2; round++) {
+                const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
+                const int32_t r1 = round == 0 ? s_seed : m;
+                if (r0 >= r1) continue;
+                prof_begin(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                                   nb, m, r0, r1, b, ngrp, hist);
+                {
+                    const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, W.scan_sums, st);
+                    if (es != CAPS_OK) return es;
+                }
+                hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
+                                   tstart);
+                const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
+                const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
+                hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
+                                   qb, (int32_t)grid, W.tiles);
+                // the fill packs each entry's class when entries stay below 2^27
+                const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
+                hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                                   nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
+                const int32_t *ent = entries;
+                if (nc > 1) {
+                    hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(kClassW * 64), 0, st, entries, sel, pstart, pcount, nc,
+                                       (int32_t)(nc_pack > 1), W.entries2);
+                    ent = W.entries2;
+                }
+                CAPS_HIP(hipGetLastError());
+                prof_end(CAPS_STAGE_SELECT, st);
+                if (mfma) {
+                    const bool seed_pass = seeded_exact && round == 0;
+                    LowpScan S{};
+                    S.nb = nb;
+                    S.m = m;
+                    S.r = r;
+                    S.kind = lowp || seed_pass ? 0 : 1;
+                    S.first_round = round == 0;
+                    S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
+                    S.max_tiles = grid;
+                    S.tiles = W.tiles;
+                    S.entries = ent;
+                    S.sel = sel;
+                    S.qd = qd;
+                    S.qterms = W.qterms;
+                    S.disj = disj;
+                    S.q = q + (int64_t)q0 * d;
+                    S.qlow = W.qlow;
+                    S.qscale = W.qscale;
+                    S.qaux = W.qaux;
+                    S.partials = partials;
+                    S.tau = tau;
+                    S.pcnt = W.pcnt;
+                    S.nsurv = out_nsurv && !seed_pass ? nsurv + q0 : nullptr;   // counted only when asked for
+                    S.dpos = W.dpos;
+                    S.dcnt = W.dcnt;
+                    S.dcap = kDeferCap;
+                    S.oflow = W.oflow;
+                    S.rescue_grid = sp->rescue_grid;
+                    const caps_status ls = lowp_scan(ix, S, st);
+                    if (ls != CAPS_OK) return ls;
+                    if (S.kind == 1) {   // rescue pass over the tiles that hold a flagged query
+                        hipLaunchKernelGGL(k_rescue_init, dim3(1), dim3(1024), 0, st, W.oflow, nb, W.rcount);
+                        hipLaunchKernelGGL(k_rescue_tiles, dim3(nblocks(grid, 256)), dim3(256), 0, st, W.tiles,
+                                           (int32_t)grid, ent, m, W.oflow, W.rlist, W.rcount);
+                        S.kind = 2;
+                        S.rlist = W.rlist;
+                        S.rcount = W.rcount;
+                        S.nsurv = nullptr;
+                        S.stage = CAPS_STAGE_RESCUE;
+                        const caps_status rs = lowp_scan(ix, S, st);
+                        if (rs != CAPS_OK) return rs;
+                    }
+                } else {
+                    ScanArgs A;
+                    A.tiles = W.tiles;
+                    A.ntiles = (int32_t)grid;
+                    A.entries = ent;
+                    A.sel = sel;
+                    A.q = q + (int64_t)q0 * d;
+                    A.qd = qd;
+                    A.qterms = W.qterms;
+                    A.offs = ix->offs;
+                    A.perm = ix->perm;
+                    A.vecs = ix->vecs;
+                    A.words = ix->words;
+                    A.sigs = ix->sigs;
+                    A.slots = ix->slots;
+                    A.partials = partials;
+                    A.tau = tau;
+                    A.nsurv = nsurv + q0;
+                    A.d = d;
+                    A.m = m;
+                    A.h = h;
+                    A.b = b;
+                    A.k = k;
+                    prof_begin(CAPS_STAGE_SCAN, st);
+                    hipLaunchKernelGGL(scan_fn, dim3((unsigned)grid), dim3(scan_waves(k) * 64), lds, st, A);
+                    prof_end(CAPS_STAGE_SCAN, st);
+                    CAPS_HIP(hipGetLastError());
+                }
+                if (round == 0 && seeded_exact) {
+                    prof_begin(CAPS_STAGE_SEED, st);
+                    hipLaunchKernelGGL(k_seed_exact, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, W.pcnt, sel, nb,
+                                       m, s_seed, r, std::min(2 * k, 64), k, ix->vecs, q + (int64_t)q0 * d, ix->perm, d,
+                                       ix->metric, tau);
+                    prof_end(CAPS_STAGE_SEED, st);
+                    CAPS_HIP(hipGetLastError());
+                } else if (round == 0 && s_seed < m) {
+                    prof_begin(CAPS_STAGE_SELECT, st);
+                    hipLaunchKernelGGL(k_seed_tau, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials,
+                                       lowp ? W.pcnt : nullptr, sel, nb, m, s_seed, r, r, tau);
+                    prof_end(CAPS_STAGE_SELECT, st);
+                    CAPS_HIP(hipGetLastError());
+                }
+            }
+            if (lowp) {
+                const caps_status ls = lowp_merge(ix, q + (int64_t)q0 * d, nb, sel, m, k, r, partials, W.pcnt, cand,
+                                                  ncand + q0, out_ids + (int64_t)q0 * k, out_dist + (int64_t)q0 * k, st);
+                if (ls != CAPS_OK) return ls;
+                continue;
+            }
+            prof_begin(CAPS_STAGE_MERGE, st);
+            int32_t *oi = out_ids + (int64_t)q0 * k;
+            float *od = out_dist + (int64_t)q0 * k;
+            const int32_t *mcnt = mfma ? W.pcnt : nullptr;   // matrix-core lists are counted, plain ones padded
+            Deferred D{};
+            if (P.defer) {
+                D.pos = W.dpos;
+                D.cnt = W.dcnt;
+                D.oflow = W.oflow;
+                D.cap = kDeferCap;
+                D.d = d;
+                D.vecs = ix->vecs;
+                D.q = q + (int64_t)q0 * d;
+                D.perm = ix->perm;
+            }
+            if (k <= 16)
+                hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                                   k, ix->metric, oi, od, ncand + q0, D);
+            else if (k <= 32)
+                hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                                   k, ix->metric, oi, od, ncand + q0, D);
+            else
+                hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
+                                   k, ix->metric, oi, od, ncand + q0, D);
+            prof_end(CAPS_STAGE_MERGE, st);
+            CAPS_HIP(hipGetLastError());
         }
-        if (lowp) {
-            const caps_status ls = lowp_merge(ix, q + (int64_t)q0 * d, nb, sel, m, k, r, partials, W.pcnt, cand,
-                                              ncand + q0, out_ids + (int64_t)q0 * k, out_dist + (int64_t)q0 * k, st);
-            if (ls != CAPS_OK) return ls;
-            continue;
-        }
-        prof_begin(CAPS_STAGE_MERGE, st);
-        int32_t *oi = out_ids + (int64_t)q0 * k;
-        float *od = out_dist + (int64_t)q0 * k;
-        const int32_t *mcnt = mfma ? W.pcnt : nullptr;   // matrix-core lists are counted, plain ones padded
-        Deferred D{};
-        if (P.defer) {
-            D.pos = W.dpos;
-            D.cnt = W.dcnt;
-            D.oflow = W.oflow;
-            D.cap = kDeferCap;
-            D.d = d;
-            D.vecs = ix->vecs;
-            D.q = q + (int64_t)q0 * d;
-            D.perm = ix->perm;
-        }
-        if (k <= 16)
-            hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
-                               k, ix->metric, oi, od, ncand + q0, D);
-        else if (k <= 32)
-            hipLaunchKernelGGL(k_merge<32>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
-                               k, ix->metric, oi, od, ncand + q0, D);
-        else
-            hipLaunchKernelGGL(k_merge<64>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
-                               k, ix->metric, oi, od, ncand + q0, D);
-        prof_end(CAPS_STAGE_MERGE, st);
-        CAPS_HIP(hipGetLastError());
-    }
-    CAPS_HIP(hipFreeAsync(ar.base, st));
     return CAPS_OK;
+    };
+    caps_status s = run();
+    if (s == CAPS_OK && (sp->flags & CAPS_SEARCH_VALIDATE)) {
+        int32_t nbad = 0;
+        hipError_t e = hipMemcpyAsync(&nbad, W.bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            set_error("caps_search: %s", hipGetErrorString(e));
+            s = CAPS_EDEVICE;
+        } else if (nbad > 0) {
+            set_error("caps_search: %d query rows hold NaN or Inf", nbad);
+            s = CAPS_EINVAL;
+        }
+    }
+    if (!ex.ws) {
+        const hipError_t e = hipFreeAsync(ar.base, st);
+        if (s == CAPS_OK && e != hipSuccess) {
+            set_error("caps_search: hipFreeAsync failed: %s", hipGetErrorString(e));
+            s = CAPS_EDEVICE;
+        }
+    }
+    return s;
 }
 
 }  // namespace caps

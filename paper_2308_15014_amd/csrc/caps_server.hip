@@ -12,11 +12,13 @@
 // request's ids and distances go to a result queue with its latency (submit
 // to the moment the scheduler sees the event complete).
 //
-// Admission: submit refuses (EBUSY) beyond `queue_slots` waiting requests;
-// the batch cap is the largest size whose search workspace (exact bytes of
-// the search's own layout) fits `workspace_bytes`.  A query's result does
-// not depend on the batch it lands in: every search kernel is batch
-// invariant.
+// Admission: submit refuses (EBUSY) beyond `queue_slots` waiting requests
+// and rejects non-finite query rows (EINVAL).  Device memory: the search
+// workspaces of all batches in flight share `workspace_bytes`; a batch is
+// sized to the largest count whose workspace (exact bytes of the search's
+// own layout) fits what the batches in flight leave free, and waits for a
+// retirement when not even one query fits.  A query's result does not
+// depend on the batch it lands in: every search kernel is batch invariant.
 #include <math.h>
 #include <string.h>
 
@@ -86,6 +88,7 @@ struct SrvSlot {
     hipEvent_t ev = nullptr;
     bool busy = false;
     caps_status status = CAPS_OK;
+    size_t ws_bytes = 0;                   // workspace reserved by the batch in flight
     std::vector<uint64_t> tickets;         // the batch in flight
     std::vector<Clock::time_point> t0s;
     float *hq = nullptr, *hdist = nullptr, *dq = nullptr, *ddist = nullptr;
@@ -98,6 +101,7 @@ struct Server {
     caps_server_params p{};
     caps_search_params sp{};
     int32_t d = 0, k = 0, cap = 0;
+    size_t inflight = 0;               // workspace bytes reserved by batches in flight (scheduler thread)
     std::mutex mu;
     std::condition_variable cv;        // new request / stop (scheduler side)
     std::condition_variable cv_done;   // a batch retired (drain side)
@@ -140,6 +144,8 @@ static void retire(Server *S, SrvSlot &sl) {
         S->t_last = t;
     }
     S->cv_done.notify_all();
+    S->inflight -= sl.ws_bytes;
+    sl.ws_bytes = 0;
     sl.busy = false;
     sl.tickets.clear();
     sl.t0s.clear();
@@ -210,6 +216,27 @@ static void launch(Server *S, SrvSlot &sl, int32_t ncon) {
     }
 }
 
+// Largest batch of at most `want` queries whose search workspace fits the
+// budget the batches in flight leave free (0: none fits); *ws receives its
+// bytes.  Without a budget every batch fits.
+static int32_t admit(Server *S, int32_t want, size_t *ws) {
+    if (S->p.workspace_bytes <= 0) {
+        *ws = 0;
+        return want;
+    }
+    const size_t budget = (size_t)S->p.workspace_bytes;
+    const size_t avail = budget > S->inflight ? budget - S->inflight : 0;
+    if (search_workspace_bytes(S->ix, &S->sp, 1) > avail) return 0;
+    int32_t lo = 1, hi = want;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (search_workspace_bytes(S->ix, &S->sp, mid) <= avail) lo = mid;
+        else hi = mid - 1;
+    }
+    *ws = search_workspace_bytes(S->ix, &S->sp, lo);
+    return lo;
+}
+
 static void run(Server *S) {
     (void)hipSetDevice(S->ix->device);
     const auto window = std::chrono::duration<double, std::micro>(S->p.batch_window_us);
@@ -217,9 +244,15 @@ static void run(Server *S) {
         bool progressed = false, any_busy = false;
         for (auto &sl : S->slots) {
             if (!sl.busy) continue;
-            if (hipEventQuery(sl.ev) == hipErrorNotReady) {
+            const hipError_t q = hipEventQuery(sl.ev);
+            if (q == hipErrorNotReady) {
                 any_busy = true;
                 continue;
+            }
+            if (q != hipSuccess) {   // the batch's copies or kernels failed: its buffers are not results
+                sl.status = CAPS_EDEVICE;
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->err.empty()) S->err = std::string("caps_server: ") + hipGetErrorString(q);
             }
             retire(S, sl);
             progressed = true;
@@ -239,8 +272,14 @@ static void run(Server *S) {
                                   (int32_t)S->pending.size() < S->cap &&
                                   Clock::now() - S->pending.t0[S->pending.head] < window;
                 if (!fill) {
-                    ncon = take_batch(S, *free_slot, std::min((size_t)S->cap, S->pending.size()));
-                    taken = true;
+                    size_t ws = 0;
+                    const int32_t nb = admit(S, (int32_t)std::min((size_t)S->cap, S->pending.size()), &ws);
+                    if (nb > 0) {   // else wait for a batch in flight to free its workspace
+                        ncon = take_batch(S, *free_slot, (size_t)nb);
+                        free_slot->ws_bytes = ws;
+                        S->inflight += ws;
+                        taken = true;
+                    }
                 }
             }
             if (!taken && !progressed) {
@@ -343,7 +382,7 @@ extern "C" caps_status caps_server_create(const caps_index *idx, const caps_serv
     if (p->k < 1 || p->k > kMaxK || p->nprobe < 1 || p->nprobe > ix.b || p->mode < 0 || p->mode > 2 ||
         p->routing < 0 || p->routing > 1 || p->max_batch < 1 || p->max_batch > 65536 || p->streams < 1 ||
         p->streams > 8 || p->queue_slots < 1 || p->max_constraints < 0 || p->max_constraints > 64 ||
-        !(p->batch_window_us >= 0.0) || p->workspace_bytes < 0) {
+        !(p->batch_window_us >= 0.0) || p->workspace_bytes < 0 || (p->flags & ~(int32_t)CAPS_SEARCH_DISJUNCTIVE)) {
         set_error("caps_server_create: parameter out of range");
         return CAPS_EINVAL;
     }
@@ -364,6 +403,7 @@ extern "C" caps_status caps_server_create(const caps_index *idx, const caps_serv
     S->sp.mode = p->mode;
     S->sp.rerank = p->rerank;
     S->sp.routing = p->routing;
+    S->sp.flags = p->flags & CAPS_SEARCH_DISJUNCTIVE;   // (the budget is the server's own: not a sub-batch cap)
     S->d = ix.d;
     S->k = p->k;
     // batch cap: largest size whose search workspace fits the budget
@@ -423,6 +463,11 @@ extern "C" caps_status caps_server_submit(caps_server *srv, const float *q, int3
                   srv->s->p.max_constraints);
         return CAPS_EINVAL;
     }
+    for (int32_t j = 0; j < srv->s->d; j++)
+        if (!isfinite(q[j])) {
+            set_error("caps_server_submit: query coordinate %d is not finite", j);
+            return CAPS_EINVAL;
+        }
     return enqueue(srv->s, q, n_con, con_attr, con_val, Clock::now(), ticket);
 }
 
@@ -442,6 +487,11 @@ extern "C" caps_status caps_server_replay(caps_server *srv, const float *q, cons
             set_error("caps_server_replay: request %d has bad constraint offsets or too many constraints", i);
             return CAPS_EINVAL;
         }
+        for (int32_t j = 0; j < S->d; j++)
+            if (!isfinite(q[(size_t)i * S->d + j])) {
+                set_error("caps_server_replay: request %d has a non-finite coordinate", i);
+                return CAPS_EINVAL;
+            }
         const Clock::time_point at =
             start + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
         Clock::time_point now = Clock::now();

@@ -61,17 +61,16 @@ __global__ __launch_bounds__(kScanNT) void k_scan_add(int32_t *out, int64_t n, c
     }
 }
 
-caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+int64_t exclusive_scan_tiles(int64_t n) { return n <= 0 ? 0 : (n + kScanTile - 1) / kScanTile; }
+
+caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *sums,
                                hipStream_t st) {
     if (n <= 0) return CAPS_OK;
-    int64_t nt = (n + kScanTile - 1) / kScanTile;
-    int32_t *sums = nullptr;
-    CAPS_HIP(hipMallocAsync((void **)&sums, sizeof(int32_t) * (size_t)nt, st));
+    const int64_t nt = exclusive_scan_tiles(n);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanNT), 0, st, in, out, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nt, total);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(kScanNT), 0, st, out, n, sums);
     CAPS_HIP(hipGetLastError());
-    CAPS_HIP(hipFreeAsync(sums, st));
     return CAPS_OK;
 }
 

@@ -10,7 +10,8 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import PREC, BuildParams, IndexInfo, RouterInfo, RouterParams, SearchParams, check, lib
+from ._lib import (PREC, SEARCH_DISJUNCTIVE, SEARCH_VALIDATE, BuildParams, IndexInfo, RouterInfo, RouterParams,
+                   SearchParams, check, lib)
 
 
 def _torch():
@@ -115,7 +116,8 @@ class Index:
 
     def search(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
                mode: int = 0, rerank: int = 0, routing: int = 0, stream=None, counters: bool = False,
-               out=None, workspace_bytes: int = 0):
+               out=None, workspace_bytes: int = 0, validate: bool = False, disjunctive: bool = False,
+               rescue_grid: int = 0):
         """Top-k filtered search for a batch.  Returns device tensors
         (ids int32 [Q,k], dist float32 [Q,k]) and, with counters=True, the
         per-query candidate and survivor counts.  mode 1 scans the
@@ -123,7 +125,9 @@ class Index:
         candidates per query exactly; mode 2 forces the plain FP32 scan.
         routing 1 uses the learned router (with its centroid fallback).
         workspace_bytes caps the device workspace of the call (0: 4 GiB);
-        the batch is searched in sub-batches that fit it."""
+        the batch is searched in sub-batches that fit it.  validate=True
+        synchronises and raises on NaN/Inf query rows; disjunctive=True lets
+        a constraint pair with attr == OR (-1) separate AND-terms."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
@@ -134,7 +138,8 @@ class Index:
             ids, dist = out
         nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
         ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
-        sp = SearchParams(k, nprobe, rule, mode, rerank, routing, workspace_bytes)
+        sp = self._sparams(k, nprobe, rule, mode, rerank, routing, workspace_bytes, validate, disjunctive,
+                           rescue_grid)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
@@ -145,15 +150,50 @@ class Index:
             return ids, dist, nc, ns
         return ids, dist
 
+    @staticmethod
+    def _sparams(k, nprobe, rule=0, mode=0, rerank=0, routing=0, workspace_bytes=0, validate=False,
+                 disjunctive=False, rescue_grid=0):
+        flags = (SEARCH_VALIDATE if validate else 0) | (SEARCH_DISJUNCTIVE if disjunctive else 0)
+        return SearchParams(k, nprobe, rule, mode, rerank, routing, flags, rescue_grid, workspace_bytes)
+
+    def workspace_bytes(self, n_q: int, k: int, nprobe: int, *, mode: int = 0, rerank: int = 0,
+                        routing: int = 0, workspace_bytes: int = 0) -> int:
+        """Device bytes one search call of n_q queries allocates."""
+        sp = self._sparams(k, nprobe, 0, mode, rerank, routing, workspace_bytes)
+        out = ctypes.c_int64()
+        check(lib().caps_search_workspace(self._h, ctypes.byref(sp), n_q, ctypes.byref(out)))
+        return int(out.value)
+
+    def search_debug(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0,
+                     mode: int = 0, rerank: int = 0, routing: int = 0, disjunctive: bool = False,
+                     rescue_grid: int = 0, workspace_bytes: int = 0):
+        """caps_search_debug: (ids, dist, ncand, nsurv, surv_mask) with surv_mask
+        [Q, ceil(n/64)] int64 words of filter pass bits over CSR positions."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        nq = int(qd.shape[0])
+        words = (self.info()["n"] + 63) // 64
+        ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        nc = torch.empty(nq, dtype=torch.int32, device=self.device)
+        ns = torch.empty(nq, dtype=torch.int32, device=self.device)
+        mask = torch.empty((nq, words), dtype=torch.int64, device=self.device)
+        sp = self._sparams(k, nprobe, rule, mode, rerank, routing, workspace_bytes, False, disjunctive, rescue_grid)
+        with torch.cuda.device(self.device):
+            check(lib().caps_search_debug(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
+                                          ca.data_ptr(), cv.data_ptr(), n_con, ids.data_ptr(), dist.data_ptr(),
+                                          nc.data_ptr(), ns.data_ptr(), mask.data_ptr(), _stream(None)))
+        return ids, dist, nc, ns, mask
+
     def probes(self, q, con_off, con_attr, con_val, nprobe: int, *, rule: int = 0, routing: int = 0,
-               k: int = 1, stream=None):
+               k: int = 1, stream=None, disjunctive: bool = False):
         """Routing and sub-partition choice only: (probes [Q,m], masks [Q,m])."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
         pr = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
         mk = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
-        sp = SearchParams(k, nprobe, rule, 0, 0, routing)
+        sp = self._sparams(k, nprobe, rule, 0, 0, routing, disjunctive=disjunctive)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search_probes(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),

@@ -6,7 +6,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import ServerParams, ServerStats, check, lib
+from ._lib import SEARCH_DISJUNCTIVE, ServerParams, ServerStats, check, lib
 
 
 def _p(a):
@@ -17,12 +17,13 @@ class Server:
     """Continuous-batching server over one index (host-side requests)."""
 
     def __init__(self, index, *, k=10, nprobe=32, mode=0, routing=0, rerank=0, max_batch=4096, streams=2,
-                 queue_slots=1 << 20, max_constraints=16, workspace_bytes=0, batch_window_us=0.0):
+                 queue_slots=1 << 20, max_constraints=16, workspace_bytes=0, batch_window_us=0.0,
+                 disjunctive=False):
         self.index = index          # keeps the index alive as long as the server
         self.k = k
         self.d = index.info()["d"]
-        p = ServerParams(k, nprobe, mode, routing, rerank, max_batch, streams, queue_slots, max_constraints, 0,
-                         workspace_bytes, batch_window_us)
+        p = ServerParams(k, nprobe, mode, routing, rerank, max_batch, streams, queue_slots, max_constraints,
+                         SEARCH_DISJUNCTIVE if disjunctive else 0, workspace_bytes, batch_window_us)
         h = ctypes.c_void_p()
         check(lib().caps_server_create(index._h, ctypes.byref(p), ctypes.byref(h)))
         self._h = h

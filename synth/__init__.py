@@ -193,6 +193,30 @@ def draw_constraints(rng, n_q, n, dense, label_off, labels, cmin, cmax,
             np.asarray(vals, dtype=np.int32), sel)
 
 
+OR_ATTR = -1   # constraint attribute that separates the AND-terms of a disjunctive query
+
+
+def draw_disjunctions(rng, n_q, n, dense, label_off, labels, tmin, tmax, cmin, cmax):
+    """Disjunctive queries: t ~ U{tmin..tmax} AND-terms, each drawn as by
+    draw_constraints (pairs copied from its own random database point), joined
+    by (OR_ATTR, 0) separators."""
+    off = [0]
+    attrs: List[int] = []
+    vals: List[int] = []
+    for _ in range(n_q):
+        t = int(rng.integers(tmin, tmax + 1))
+        co, ca, cv, _sel = draw_constraints(rng, t, n, dense, label_off, labels, cmin, cmax)
+        for j in range(t):
+            if j:
+                attrs.append(OR_ATTR)
+                vals.append(0)
+            attrs.extend(ca[co[j]:co[j + 1]].tolist())
+            vals.extend(cv[co[j]:co[j + 1]].tolist())
+        off.append(len(attrs))
+    return (np.asarray(off, dtype=np.int32), np.asarray(attrs, dtype=np.int32),
+            np.asarray(vals, dtype=np.int32))
+
+
 def _streams(seed):
     ss = np.random.SeedSequence(seed)
     return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(4)]

@@ -26,15 +26,15 @@ def caps():
     return caps
 
 
-def _search(ix, q, co, ca, cv, k, m, mode, rule=0):
-    ids, dist, nc, ns = ix.search(q, co, ca, cv, k, m, rule=rule, mode=mode, counters=True)
+def _search(ix, q, co, ca, cv, k, m, mode, rule=0, rescue_grid=0):
+    ids, dist, nc, ns = ix.search(q, co, ca, cv, k, m, rule=rule, mode=mode, counters=True, rescue_grid=rescue_grid)
     return ids.cpu().numpy(), dist.cpu().numpy(), nc.cpu().numpy(), ns.cpu().numpy()
 
 
-def _check(orc, oi, ix, q, co, ca, cv, k, m, rule=0):
+def _check(orc, oi, ix, q, co, ca, cv, k, m, rule=0, rescue_grid=0):
     r = orc.search(oi, q, co, ca, cv, k, m, rule=rule)
     for mode in (0, 2):
-        ids, dist, nc, ns = _search(ix, q, co, ca, cv, k, m, mode, rule)
+        ids, dist, nc, ns = _search(ix, q, co, ca, cv, k, m, mode, rule, rescue_grid)
         assert np.array_equal(ids, r.ids), (mode, k, m)
         assert np.array_equal(dist.view(np.uint32), r.dist.view(np.uint32)), (mode, k, m)
         assert np.array_equal(nc, r.n_cand), (mode, k, m)
@@ -151,6 +151,10 @@ def test_exact_prune_equidistant_shell(caps, orc, prec):
     for m in (48, 64):
         for k in (10, 64):
             _check(orc, oi, ix, w.q, w.con_off, w.con_attr, w.con_val, k, m)
+    # the rescue pass with a grid of one and of three workgroups: each walks
+    # several of the flagged queries' tiles in turn
+    for rg in (1, 3):
+        _check(orc, oi, ix, w.q, w.con_off, w.con_attr, w.con_val, 64, 64, rescue_grid=rg)
 
 
 def test_exact_prune_edge_cases(caps, orc):

@@ -99,3 +99,21 @@ def test_full_size_sampled_mode1(full, sampled):
         hit += len(t & set(ids[j][valid].tolist()))
         tot += len(t)
     assert hit / max(tot, 1) >= 0.97, hit / max(tot, 1)
+
+
+def test_full_size_truth_is_bruteforce(full, orc):
+    """The recall truth the benchmark uses (every partition probed) is the
+    oracle's filtered brute force (Appendix "Groundtruth") on 256 sampled
+    queries: ids, distance bits and |D_C|, in both exact modes."""
+    w, ix, (q, co, ca, cv) = full
+    sel = np.sort(np.random.default_rng(4).choice(w.n_q, 256, replace=False))
+    sco = np.concatenate([[0], np.cumsum(np.diff(w.con_off)[sel])]).astype(np.int32)
+    sca = np.concatenate([w.con_attr[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    scv = np.concatenate([w.con_val[w.con_off[i]:w.con_off[i + 1]] for i in sel]).astype(np.int32)
+    bf = orc.bruteforce(w.x, orc.workload_tokens(w), w.metric, w.q[sel], sco, sca, scv, K)
+    for mode in (0, 2):
+        ids, dist, nc, ns = ix.search(q, co, ca, cv, K, w.n_partitions, mode=mode, counters=True)
+        assert np.array_equal(ids.cpu().numpy()[sel], bf.ids), mode
+        assert np.array_equal(dist.cpu().numpy()[sel].view(np.uint32), bf.dist.view(np.uint32)), mode
+        assert np.array_equal(ns.cpu().numpy()[sel], bf.n_surv), mode
+        assert (nc.cpu().numpy()[sel] <= w.n).all() and (nc.cpu().numpy()[sel] >= bf.n_surv).all(), mode

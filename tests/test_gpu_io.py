@@ -74,3 +74,68 @@ def test_damaged_files_are_refused(caps, tmp_path):
     with pytest.raises(caps.CapsError) as e:
         caps.Index.load(str(bad))
     assert e.value.status == -6
+
+
+def _array_offsets(raw):
+    """Byte offset of each array payload of an index file: the header length
+    is stored after the magic and version; then (u32 tag, u64 bytes,
+    payload) records follow in tag order."""
+    hb = int(np.frombuffer(raw[12:16], np.uint32)[0])
+    o = 16 + hb
+    out = {}
+    while o + 12 <= len(raw):
+        tag = int(np.frombuffer(raw[o:o + 4], np.uint32)[0])
+        nb = int(np.frombuffer(raw[o + 4:o + 12], np.uint64)[0])
+        out[tag] = (o + 12, nb)
+        o += 12 + nb
+        if tag == 16:
+            break
+    return out
+
+
+def _refused(caps, path):
+    with pytest.raises(caps.CapsError) as e:
+        caps.Index.load(str(path))
+    assert e.value.status == -6
+
+
+def test_inconsistent_contents_are_refused(caps, tmp_path):
+    """A file whose frame is intact but whose partition layout is damaged
+    (an offset, a permutation entry, a tag, the low-precision row width) is
+    refused before any search can read through it."""
+    w = synth.make_tiny(502, n=900, d=20, n_q=4, vocabs=(3, 4), label_vocab=6, b=5, h=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2, precision="bf16")
+    path = tmp_path / "ok.caps"
+    ix.save(str(path))
+    raw = path.read_bytes()
+    caps.Index.load(str(path)).close()
+    offs = _array_offsets(raw)
+    bad = tmp_path / "bad.caps"
+
+    def patch(tag, index, value, dtype=np.int32):
+        b = bytearray(raw)
+        at, nb = offs[tag]
+        arr = np.frombuffer(bytes(b[at:at + nb]), dtype).copy()
+        arr[index] = value
+        b[at:at + nb] = arr.tobytes()
+        bad.write_bytes(bytes(b))
+
+    patch(4, 3, 10**6)             # offs: a range past the end
+    _refused(caps, bad)
+    patch(4, 2, -1)                # offs: decreasing
+    _refused(caps, bad)
+    p0 = np.frombuffer(raw[offs[5][0]:offs[5][0] + 4], np.int32)[0]
+    patch(5, 1, p0)                # perm: a repeated id
+    _refused(caps, bad)
+    patch(5, 0, 900)               # perm: an id out of range
+    _refused(caps, bad)
+    patch(3, 0, 10**5)             # tags: a token outside the vocabulary
+    _refused(caps, bad)
+    patch(7, 0, 9, np.int8)        # level: disagrees with the range holding the point
+    _refused(caps, bad)
+    b = bytearray(raw)             # header: dpad of the BF16 copy doubled
+    dp = np.frombuffer(raw[44:48], np.int32)[0]
+    assert dp == 32
+    b[44:48] = np.int32(64).tobytes()
+    bad.write_bytes(bytes(b))
+    _refused(caps, bad)

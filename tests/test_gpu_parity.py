@@ -200,3 +200,83 @@ def test_sub_batches_equal_one_batch(caps, orc, prec, mode):
         assert np.array_equal(one[1].view(np.uint32), r.dist.view(np.uint32))
         assert np.array_equal(one[2], r.n_cand)
         assert np.array_equal(one[3], r.n_surv)
+
+
+def test_8192_partitions(caps, orc):
+    """The largest supported B: the register top-m network of 32 keys per
+    thread (probes query, sorted) and the search's selection at B = 8192."""
+    w = synth.make_tiny(8192, n=20_000, d=8, n_q=48, vocabs=(4, 3), label_vocab=0, b=8192, h=1, cmin=0, cmax=2)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2)
+    _check_build(oi, ix.export())
+    for m in (1, 37, 4097, 8192):
+        _check_search(orc, oi, ix, w, 10, m)
+
+
+def test_nonfinite_queries(caps, orc):
+    """A query row holding NaN or Inf has an empty answer on the asynchronous
+    path and makes the validating call fail with EINVAL; the other rows are
+    unaffected."""
+    w = synth.make_tiny(31, n=3000, d=12, n_q=40, vocabs=(3, 5), label_vocab=0, b=8, h=2, cmin=0, cmax=2)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2, precision="bf16")
+    r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 5, 4)
+    q = w.q.copy()
+    q[3, 1] = np.nan
+    q[7, 0] = np.inf
+    q[8, 11] = -np.inf
+    bad = np.zeros(w.n_q, bool)
+    bad[[3, 7, 8]] = True
+    for mode in (0, 1, 2):
+        ids, dist = ix.search(q, w.con_off, w.con_attr, w.con_val, 5, 4, mode=mode)
+        ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+        assert (ids[bad] == -1).all() and np.isposinf(dist[bad]).all()
+        if mode != 1:
+            assert np.array_equal(ids[~bad], r.ids[~bad])
+            assert np.array_equal(dist[~bad].view(np.uint32), r.dist[~bad].view(np.uint32))
+        with pytest.raises(caps.CapsError) as e:
+            ix.search(q, w.con_off, w.con_attr, w.con_val, 5, 4, mode=mode, validate=True)
+        assert e.value.status == -1
+    ids, dist = ix.search(w.q, w.con_off, w.con_attr, w.con_val, 5, 4, validate=True)
+    assert np.array_equal(ids.cpu().numpy(), r.ids)
+    with pytest.raises(caps.CapsError) as e:
+        ix.search_debug(q, w.con_off, w.con_attr, w.con_val, 5, 4)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("case", [
+    # seed, n, d, vocabs, label_vocab, b, h, cmin, cmax, mode
+    (40, 2500, 16, (3, 5), 0, 9, 2, 0, 3, 0),
+    (41, 2500, 16, (3, 5), 30, 9, 3, 0, 4, 2),
+    (42, 1800, 40, (), 25, 6, 4, 1, 4, 0),
+])
+def test_survivor_mask_matches_definition(caps, orc, case):
+    """Per CSR position, the filter's pass bit for every (query, chosen
+    sub-partition): equal to Definition 1 evaluated on the raw attributes
+    over the sub-partitions the oracle chose, and summing to the survivor
+    count."""
+    from oracle import ref64
+    seed, n, d, voc, lv, b, h, cmin, cmax, mode = case
+    w = synth.make_tiny(seed, n=n, d=d, n_q=60, vocabs=voc, label_vocab=lv, b=b, h=h, cmin=cmin, cmax=cmax,
+                        max_labels=8)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2, precision="bf16")
+    assert np.array_equal(ix.export()["perm"], oi.perm)   # the same CSR positions on both sides
+    m = max(1, b // 2)
+    r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 10, m)
+    ids, dist, nc, ns, mask = ix.search_debug(w.q, w.con_off, w.con_attr, w.con_val, 10, m, mode=mode)
+    assert np.array_equal(ids.cpu().numpy(), r.ids)
+    assert np.array_equal(ns.cpu().numpy(), r.n_surv)
+    bits = np.unpackbits(mask.cpu().numpy().view(np.uint8), axis=1, bitorder="little")[:, :n].astype(bool)
+    for i in range(w.n_q):
+        valid = ref64.valid_mask(w.dense, w.label_off, w.labels,
+                                 ref64.pairs_of(w.con_off, w.con_attr, w.con_val, i), w.n_dense,
+                                 w.dense_vocab, w.label_vocab)
+        want = np.zeros(n, bool)
+        for p, mk in zip(r.probes[i], r.masks[i]):
+            for j in range(h + 1):
+                if (int(mk) >> j) & 1:
+                    lo, hi = oi.offs[p * (h + 1) + j], oi.offs[p * (h + 1) + j + 1]
+                    want[lo:hi] = valid[oi.perm[lo:hi]]
+        assert np.array_equal(bits[i], want), i
+        assert bits[i].sum() == r.n_surv[i]

@@ -134,3 +134,66 @@ def test_learned_routing_gain(caps):
     r0 = recall(ix.search(qt, cot, cat, cvt, 10, m, routing=0)[0])
     r1 = recall(ix.search(qt, cot, cat, cvt, 10, m, routing=1)[0])
     assert r1 > r0 + 0.15, (r0, r1)
+
+
+def test_adam_steps_match_oracle(caps, tiny):
+    """k_adam against the Adam step of the oracle (bias-corrected, FP64)
+    applied to the GPU's own batch gradient: three steps on one row each,
+    the moments carried from step to step."""
+    w, ix = tiny
+    rng = np.random.default_rng(4)
+    dp = R.pad_width(w.d)
+    wt = _weights(rng, 32, dp, 16)
+    lr, b1, b2, eps = 3e-3, 0.9, 0.999, 1e-8
+    ix.router_set(**wt, hidden=32, in_scale=0.5, in_shift=0.0)
+    labels = rng.integers(0, 16, size=(w.n_q, 2)).astype(np.int32)
+    params = {k: v.astype(np.float64) for k, v in wt.items()}
+    mom = {k: np.zeros_like(v) for k, v in params.items()}
+    vel = {k: np.zeros_like(v) for k, v in params.items()}
+    for step in (1, 2, 3):
+        q, co, ca, cv = _subset(w, [step])
+        lab = labels[step:step + 1]
+        _, g = ix.router_grads(q, co, ca, cv, lab)
+        ix.router_train(q, co, ca, cv, lab, hidden=32, epochs=1, batch=1, reset=0, lr=lr, beta1=b1, beta2=b2,
+                        eps=eps, in_scale=0.5, in_shift=0.0)
+        assert ix.router_info()["steps"] == step
+        params = R.adam(params, g, mom, vel, step, lr, b1, b2, eps)
+        got = ix.router_get()
+        for k in params:
+            want = params[k]
+            # the GPU rounds each parameter to FP32 once per step and evaluates
+            # the update (about lr in size) in FP32 from FP32 moments
+            tol = 4 * step * np.spacing(np.abs(want).astype(np.float32)).astype(np.float64) + step * lr * 1e-6
+            assert np.all(np.abs(got[k] - want) <= tol), (k, step, np.max(np.abs(got[k] - want) - tol))
+        assert np.any(got["w1"] != wt["w1"])
+
+
+def test_short_training_run_tracks_oracle(caps, tiny):
+    """Five full-batch Adam steps on the GPU against the same five steps of
+    the oracle (FP64 gradients with the GPU's BF16 operand roundings): the
+    per-step losses agree within 1e-3 and the weight changes within 2% of
+    their norm (a gradient entry near zero may differ in sign between FP32
+    and FP64 accumulation, which moves that entry by up to 2 lr)."""
+    w, ix = tiny
+    rng = np.random.default_rng(5)
+    dp = R.pad_width(w.d)
+    wt = _weights(rng, 32, dp, 16)
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    labels = rng.integers(-1, 16, size=(w.n_q, 3)).astype(np.int32)
+    ix.router_set(**wt, hidden=32, in_scale=0.5, in_shift=0.0)
+    gpu_loss = ix.router_train(w.q, w.con_off, w.con_attr, w.con_val, labels, hidden=32, epochs=5, batch=w.n_q,
+                               reset=0, lr=lr, beta1=b1, beta2=b2, eps=eps, in_scale=0.5, in_shift=0.0)
+    x = R.input_rows(w.q, w.con_off, w.con_attr, w.con_val, w.dense_vocab, w.label_vocab, 0.5, 0.0)
+    params = {k: v.astype(np.float64) for k, v in wt.items()}
+    mom = {k: np.zeros_like(v) for k, v in params.items()}
+    vel = {k: np.zeros_like(v) for k, v in params.items()}
+    orc_loss = []
+    for step in range(1, 6):
+        f32 = {k: v.astype(np.float32) for k, v in params.items()}   # the GPU's masters are FP32
+        loss, g = R.loss_and_grads(x, labels, **f32)
+        orc_loss.append(loss)
+        params = R.adam(params, g, mom, vel, step, lr, b1, b2, eps)
+    assert np.allclose(gpu_loss, orc_loss, rtol=1e-3), (gpu_loss, orc_loss)
+    got = ix.router_get()
+    for k in params:
+        assert _rel(got[k] - wt[k], params[k] - wt[k]) < 0.02, k

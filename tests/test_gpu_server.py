@@ -160,3 +160,75 @@ def test_workspace_budget_caps_the_batch(caps, work):
         caps.Server(ix, k=0, nprobe=8)
     with pytest.raises(caps.CapsError):
         caps.Server(ix, k=10, nprobe=8, routing=1)   # no router on this index
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_server_results_match_oracle(caps, work, orc, mode):
+    """Every request served in a mix (random order, three streams, uneven
+    batches) against the oracle's Algorithm 2 on its own index: modes 0 and 2
+    bit-exact; mode 1 (BF16 scores, FP32 rerank) by its properties: only
+    valid ids, as many as the survivors allow, exact FP32 distances, and
+    recall against the exact answer."""
+    from oracle import ref64
+    w, ix = work
+    oi = orc.build_from_workload(w, iters=4)
+    assert np.array_equal(ix.export()["perm"], oi.perm)
+    k, m = 10, 6
+    r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, k, m)
+    wide = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 64, m)
+    rng = np.random.default_rng(100 + mode)
+    srv = caps.Server(ix, k=k, nprobe=m, mode=mode, max_batch=48, streams=3)
+    try:
+        tick = {}
+        for i in rng.permutation(w.n_q):
+            tick[srv.submit(w.q[i], *_pairs(w, i))] = int(i)
+        got = _collect(srv, len(tick))
+    finally:
+        srv.close()
+    hit = tot = 0
+    for t, i in tick.items():
+        ids, dist = got[t]
+        if mode != 1:
+            assert np.array_equal(ids, r.ids[i]), (mode, i)
+            assert np.array_equal(dist.view(np.uint32), r.dist[i].view(np.uint32)), (mode, i)
+            continue
+        valid = ids >= 0
+        assert valid.sum() == min(k, r.n_surv[i])
+        mask = ref64.valid_mask(w.dense, w.label_off, w.labels, ref64.pairs_of(w.con_off, w.con_attr, w.con_val, i),
+                                w.n_dense, w.dense_vocab, w.label_vocab)
+        assert mask[ids[valid]].all()
+        exact = {int(a): b for a, b in zip(wide.ids[i], wide.dist[i].view(np.uint32)) if a >= 0}
+        for a, b in zip(ids[valid], dist[valid].view(np.uint32)):
+            if int(a) in exact:
+                assert exact[int(a)] == b
+        truth = set(r.ids[i][r.ids[i] >= 0].tolist())
+        hit += len(truth & set(ids[valid].tolist()))
+        tot += len(truth)
+    if mode == 1:
+        assert hit / max(tot, 1) >= 0.95, hit / max(tot, 1)
+
+
+def test_server_shares_workspace_budget(caps, work):
+    """The workspace budget is shared by the batches in flight: with room for
+    about two batches of 32, three streams still serve everything, batches
+    stay within the cap and results equal the one-batch search."""
+    w, ix = work
+    k, m = 10, 6
+    ws32 = ix.workspace_bytes(32, k, m)
+    assert ix.workspace_bytes(1, k, m) < ws32 < ix.workspace_bytes(64, k, m)
+    budget = ws32 * 5 // 2
+    batch_ids, batch_dist = (t.cpu().numpy() for t in ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m))
+    srv = caps.Server(ix, k=k, nprobe=m, mode=0, max_batch=32, streams=3, workspace_bytes=budget)
+    try:
+        tick = {}
+        for i in range(w.n_q):
+            tick[srv.submit(w.q[i], *_pairs(w, i))] = i
+        got = _collect(srv, len(tick))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == w.n_q and st["failed"] == 0
+    assert st["mean_batch"] <= 32
+    for t, i in tick.items():
+        assert np.array_equal(got[t][0], batch_ids[i])
+        assert np.array_equal(got[t][1].view(np.uint32), batch_dist[i].view(np.uint32))

@@ -35,6 +35,17 @@ def test_splitmix64_published_vectors(orc):
         assert got == want
 
 
+def test_init_ids_hand_worked(orc):
+    # partial Fisher-Yates on the published generator outputs, worked by hand
+    for line in open(os.path.join(GOLD, "init_ids_worked.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        head, vals = line.split(":")
+        seed, n, b = (int(v) for v in head.split())
+        assert orc.init_ids(seed, n, b).tolist() == [int(v) for v in vals.split()], head
+
+
 def test_init_ids_distinct_in_range(orc):
     for seed in range(20):
         ids = orc.init_ids(seed, 1000, 64)
@@ -61,6 +72,33 @@ def test_kmeans_b1_is_fp64_mean_rounded(orc):
     want = (x.astype(np.float64).sum(0) / x.shape[0]).astype(np.float32)
     assert np.array_equal(cent[0], want)
     assert np.all(a == 0)
+
+
+def test_objective_hand_value(orc):
+    # three points, one centroid at the origin: 0 + 2^2 + 4^2
+    x = np.array([[0, 0], [2, 0], [0, 4]], np.float32)
+    assert orc.objective(x, np.zeros((1, 2), np.float32), np.zeros(3, np.int32)) == 20.0
+    # two clusters: distances 1 and 1 to c0, 9 to c1
+    x = np.array([[1, 0], [-1, 0], [5, 3]], np.float32)
+    c = np.array([[0, 0], [5, 0]], np.float32)
+    assert orc.objective(x, c, np.array([0, 0, 1], np.int32)) == 11.0
+
+
+def test_objective_koenig_huygens(orc):
+    # for one cluster, sum |x - c|^2 = sum |x - mean|^2 + n |c - mean|^2 and
+    # sum |x - mean|^2 = sum |x|^2 - n |mean|^2 (integer data with an
+    # integer mean: every quantity is exact in FP64)
+    rng = np.random.default_rng(11)
+    x = rng.integers(-30, 30, size=(40, 5)).astype(np.int64)
+    x[-1] -= x.sum(0) - 40 * rng.integers(-3, 3, size=5)   # force an integer mean
+    mean = x.sum(0) // 40
+    assert np.array_equal(mean * 40, x.sum(0))
+    a = np.zeros(40, np.int32)
+    within = orc.objective(x.astype(np.float32), mean[None].astype(np.float32), a)
+    assert within == float((x * x).sum() - 40 * (mean * mean).sum())
+    for c in (mean + np.array([1, 0, -2, 3, 0]), mean - 7):
+        got = orc.objective(x.astype(np.float32), c[None].astype(np.float32), a)
+        assert got == within + 40 * float(((c - mean) ** 2).sum())
 
 
 def test_kmeans_objective_nonincreasing(orc):
@@ -172,6 +210,108 @@ def test_subpartition_choice_hand_worked(orc, rule):
         # the literal rule misses point 3 for {A0=c}: it is the reason for
         # the exact rule
         assert 3 not in r.ids[1].tolist()
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_disjunctive_choice_hand_worked(orc, rule):
+    g, dense = _worked()
+    n = len(dense)
+    x = np.arange(n * 2, dtype=np.float32).reshape(n, 2)
+    idx = orc.build_index(x, dense, g["dense_vocab"], None, None, 0, metric=0, b=1,
+                          h=g["h"], iters=0, seed=0, init=np.array([0], dtype=np.int32))
+    qs = g["or_queries"]
+    con_off = np.cumsum([0] + [len(qq["pairs"]) for qq in qs]).astype(np.int32)
+    ca = np.array([p[0] for qq in qs for p in qq["pairs"]], dtype=np.int32)
+    cv = np.array([p[1] for qq in qs for p in qq["pairs"]], dtype=np.int32)
+    q = np.zeros((len(qs), 2), dtype=np.float32)
+    r = orc.search(idx, q, con_off, ca, cv, k=8, m=1, rule=rule, disjunctive=True)
+    for i, qq in enumerate(qs):
+        if rule == 0:
+            assert int(r.masks[i, 0]) == qq["mask"], i
+            assert int(r.n_cand[i]) == qq["n_cand"], i
+            assert sorted(v for v in r.ids[i].tolist() if v >= 0) == qq["valid"], i
+        else:
+            assert int(r.masks[i, 0]) == qq["literal_mask"], i
+    # without the disjunctive reading the separator is an invalid pair
+    r = orc.search(idx, q, con_off, ca, cv, k=8, m=1)
+    assert (r.ids == -1).all() and (r.masks == 0).all()
+
+
+def _or_workload(seed, **kw):
+    w = _tiny(seed, **kw)
+    rng = np.random.default_rng(seed + 1)
+    co, ca, cv = synth.draw_disjunctions(rng, w.n_q, w.n, w.dense, w.label_off, w.labels, 1, 3, 0, 2)
+    w.con_off, w.con_attr, w.con_val = co, ca, cv
+    return w
+
+
+OR_CASES = [
+    dict(n=700, d=6, n_q=60, vocabs=(3, 5), label_vocab=0, b=6, h=2),
+    dict(n=900, d=9, n_q=60, vocabs=(4,), label_vocab=12, b=5, h=3, integer=True),
+    dict(n=800, d=5, n_q=60, vocabs=(), label_vocab=9, b=4, h=1, metric=1),
+]
+
+
+@pytest.mark.parametrize("case", OR_CASES)
+def test_disjunctive_all_partitions_equals_bruteforce(orc, case):
+    w = _or_workload(61, **case)
+    idx = orc.build_from_workload(w, iters=2)
+    r = orc.search(idx, w.q, w.con_off, w.con_attr, w.con_val, 7, w.n_partitions, disjunctive=True)
+    bf = orc.bruteforce(w.x, idx.tk, w.metric, w.q, w.con_off, w.con_attr, w.con_val, 7, disjunctive=True)
+    assert np.array_equal(r.ids, bf.ids)
+    assert np.array_equal(r.dist.view(np.uint32), bf.dist.view(np.uint32))
+    assert np.array_equal(r.n_surv, bf.n_surv)
+
+
+@pytest.mark.parametrize("case", OR_CASES)
+def test_disjunction_is_union_of_its_terms(orc, case):
+    """The top k of T1 or T2 is the top k of the two terms' own top-k lists
+    merged: checked against AND-only searches of each term."""
+    w = _or_workload(62, **case)
+    tk = orc.tokens_of(w.dense, w.dense_vocab, w.label_off, w.labels, w.label_vocab)
+    k = 6
+    bf = orc.bruteforce(w.x, tk, w.metric, w.q, w.con_off, w.con_attr, w.con_val, k, disjunctive=True)
+    for i in range(w.n_q):
+        pairs = ref64.pairs_of(w.con_off, w.con_attr, w.con_val, i)
+        terms, cur = [], []
+        for a, v in pairs:
+            if a == -1:
+                terms.append(cur)
+                cur = []
+            else:
+                cur.append((a, v))
+        terms.append(cur)
+        hits = {}
+        for t in terms:
+            co = np.array([0, len(t)], np.int32)
+            ca = np.array([a for a, _ in t], np.int32)
+            cv = np.array([v for _, v in t], np.int32)
+            r = orc.bruteforce(w.x, tk, w.metric, w.q[i:i + 1], co, ca, cv, k)
+            for a, dd in zip(r.ids[0], r.dist[0]):
+                if a >= 0:
+                    hits[int(a)] = float(dd)
+        key = (lambda kv: (kv[1], kv[0])) if w.metric == 0 else (lambda kv: (-kv[1], kv[0]))
+        want = [a for a, _ in sorted(hits.items(), key=key)][:k]
+        assert [int(a) for a in bf.ids[i] if a >= 0] == want, i
+
+
+def test_disjunctive_bruteforce_matches_fp64(orc):
+    w = _or_workload(63, n=1500, d=12, n_q=50, vocabs=(3, 4), label_vocab=10, b=4, h=2, integer=True)
+    tk = orc.tokens_of(w.dense, w.dense_vocab, w.label_off, w.labels, w.label_vocab)
+    bf = orc.bruteforce(w.x, tk, 0, w.q, w.con_off, w.con_attr, w.con_val, 10, disjunctive=True)
+    ids64, _, nv = ref64.topk64(w.x, w.dense, w.label_off, w.labels, w.dense_vocab, w.label_vocab, 0, w.q,
+                                w.con_off, w.con_attr, w.con_val, 10, disjunctive=True)
+    assert np.array_equal(bf.ids, ids64)        # integer data: FP32 distances are exact
+    assert np.array_equal(bf.n_surv, nv)
+
+
+def test_single_term_disjunction_is_the_conjunction(orc):
+    w = _tiny(64, n=800, d=7, n_q=40, vocabs=(3, 4), label_vocab=8, b=5, h=2, cmin=0, cmax=3)
+    idx = orc.build_from_workload(w, iters=2)
+    a = orc.search(idx, w.q, w.con_off, w.con_attr, w.con_val, 5, 3)
+    b = orc.search(idx, w.q, w.con_off, w.con_attr, w.con_val, 5, 3, disjunctive=True)
+    for u, v in ((a.ids, b.ids), (a.masks, b.masks), (a.n_cand, b.n_cand), (a.n_surv, b.n_surv)):
+        assert np.array_equal(u, v)
 
 
 def _aft_properties(idx):
