@@ -219,6 +219,313 @@ def event_median(fn, reps, flush=None):
     return float(np.median(out)), out
 
 
+def timed_search(ix, args_q, k, m, steps, warmup, **kw):
+    """Seconds per search of the batch, averaged over `steps` back-to-back
+    calls after `warmup` (synchronised on both sides)."""
+    import torch
+    for _ in range(warmup):
+        ix.search(*args_q, k, m, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ix.search(*args_q, k, m, **kw)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def sweep_to_target(ix, args_q, k, truth, nvalid, target, grid, **kw):
+    """(nprobe, recall, candidates/query, survivors/query) along the grid up to
+    the first point with mean recall@10 >= target."""
+    rows = []
+    for m in grid:
+        ids, _, nc, ns = ix.search(*args_q, k, m, counters=True, **kw)
+        rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
+        rows.append({"nprobe": m, "recall@10": round(rec, 4), "cand_per_q": round(float(nc.float().mean()), 1),
+                     "surv_per_q": round(float(ns.float().mean()), 1)})
+        if rec >= target:
+            break
+    return rows
+
+
+def run_ablation(args, dev):
+    """Section 6 "Ablation Study" on the 1M-point corpus: (1) the AFT height
+    h in {0, 1, 2, 4, 8} -- with the exact sub-partition rule the results at a
+    given nprobe are the same for every h, only the candidates scanned
+    shrink; (2) the absence fraction (each attribute dropped from a query with
+    that probability): recall and throughput along an nprobe grid."""
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k = 10
+    w = synth.make_c2(n=args.n, n_q=args.nq)
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    B = w.n_partitions
+    grid = [16, 64, 128, 256, 384, 512] + list(range(576, 704, 16)) + [768, 896, 1024]
+    out = {"metric": "ablation: queries/s and candidates per query vs AFT height h; recall and queries/s vs "
+                     "absence fraction", "config": {"workload": "c2 1M x 128, B=1024, 10k queries, k=10, exact "
+                                                                "search (mode 0, BF16 bounds + FP32 rescoring)"},
+           "h_sweep": [], "absence_sweep": []}
+    truth = nvalid = None
+    ref_ids = None
+    for h in (0, 1, 2, 4, 8):
+        ix = caps.Index.from_workload(w, aft_height=h, precision="bf16")
+        if truth is None:
+            tid, _, _, tsurv = ix.search(*dq, k, B, counters=True)
+            truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+        rows = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid)
+        m = rows[-1]["nprobe"]
+        if ref_ids is None:
+            ref_ids = (m, ix.search(*dq, k, m)[0].cpu().numpy())
+        # the exact rule prunes only sub-partitions without valid points:
+        # the same answers at the same nprobe for every h
+        same = bool(np.array_equal(ix.search(*dq, k, ref_ids[0])[0].cpu().numpy(), ref_ids[1]))
+        sec = timed_search(ix, dq, k, m, args.steps, args.warmup)
+        row = {"h": h, "nprobe": m, "recall@10": rows[-1]["recall@10"], "queries_per_s": round(w.n_q / sec, 1),
+               "ms_per_batch": round(sec * 1e3, 4), "cand_per_q": rows[-1]["cand_per_q"],
+               "surv_per_q": rows[-1]["surv_per_q"], "ids_equal_h0": same}
+        out["h_sweep"].append(row)
+        log(f"[ablation h={h}] {row}")
+        if h != 2:
+            ix.close()
+        else:
+            ix2 = ix
+    for absence in (0.0, 0.25, 0.5, 0.75, 1.0):
+        q, co, ca, cv = synth.make_absence_queries(args.nq, 2308_15014 + 60, w, absence)
+        aq = tuple(torch.from_numpy(a).to(dev) for a in (q, co, ca, cv))
+        tid, _, _, tsurv = ix2.search(*aq, k, B, counters=True)
+        at, anv = tid.cpu().numpy(), tsurv.cpu().numpy()
+        curve = []
+        for m in (16, 64, 256, 512, 768, 1024):
+            ids, _, nc, ns = ix2.search(*aq, k, m, counters=True)
+            rec = float(recall10(ids.cpu().numpy(), at, anv).mean())
+            sec = timed_search(ix2, aq, k, m, max(2, args.steps // 2), 1)
+            curve.append({"nprobe": m, "recall@10": round(rec, 4), "queries_per_s": round(args.nq / sec, 1),
+                          "cand_per_q": round(float(nc.float().mean()), 1)})
+        row = {"absence": absence, "constraints_per_q": round(float(np.diff(co).mean()), 3),
+               "mean_selectivity": round(float(anv.mean()) / w.n, 5), "curve": curve}
+        out["absence_sweep"].append(row)
+        log(f"[ablation absence={absence}] {row}")
+    print(json.dumps(out), flush=True)
+
+
+def c3_baseline(w, sample, results):
+    """CPU leg of the precision experiment: the FP64 filtered brute force
+    (Appendix "Groundtruth", FP64 distances, label intersection through an
+    inverted index) on a query sample and the recall@10 of every measured
+    configuration against it."""
+    from oracle import ref64
+    t0 = time.perf_counter()
+    inv = ref64.label_index(w.label_off, w.labels, w.n)
+    ids64, _, nv64 = ref64.topk64_labels(w.x, inv, w.metric, w.q, w.con_off, w.con_attr, w.con_val, 10, 0, sample)
+    t64 = time.perf_counter() - t0
+    rec64 = {}
+    for key, ids in results.items():
+        rec64[key] = round(float(recall10(ids[sample], ids64, nv64).mean()), 4)
+    return {"kind": "oracle", "fp64_truth_queries": len(sample), "fp64_truth_s": round(t64, 1),
+            "recall@10_vs_fp64": rec64, "host": {"nproc": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                                                "cpu_model": cpu_model()}}
+
+
+def run_c3(args, dev):
+    """Precision mode (E1) on the angular corpus: 5M x 96 unit vectors, inner
+    product, label sets of 1-8 labels of 1000 (Zipf 1.1), B = 4096, h = 4,
+    10k queries with 1-4 label constraints.  Indexes with no copy (FP32),
+    a BF16 copy and an FP8-E4M3 copy with per-vector scales; per index the
+    exact search (mode 0: the copy bounds, FP32 rescoring) and the
+    precision mode (mode 1: routing and scan on the copies with FP32
+    accumulation, top 4k reranked in FP32).  For each: the smallest nprobe
+    of the grid with recall@10 >= 0.9 against the exact FP32 result, its
+    queries/s; recall@10 against the FP64 brute force on a query sample."""
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k = 10
+    t0 = time.perf_counter()
+    w = synth.make_c3(n=args.c3_n, n_q=args.nq)
+    log(f"c3: N={w.n} d={w.d} Q={w.n_q} labels={len(w.labels)} generated in {time.perf_counter() - t0:.1f}s")
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    B = w.n_partitions
+    grid = [64, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096]
+    rows, results = [], {}
+    truth = nvalid = None
+    for prec in ("none", "bf16", "fp8"):
+        t0 = time.perf_counter()
+        ix = caps.Index.from_workload(w, precision=prec)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        if truth is None:
+            tid, _, _, tsurv = ix.search(*dq, k, B, counters=True)
+            truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+            log(f"c3 truth: mean |D_C| {nvalid.mean():.0f}")
+        for mode in ((0,) if prec == "none" else (0, 1)):
+            kw = dict(mode=mode, rerank=4 * k if mode == 1 else 0)
+            sweep = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid, **kw)
+            m = sweep[-1]["nprobe"]
+            ids = ix.search(*dq, k, m, **kw)[0].cpu().numpy()
+            sec = timed_search(ix, dq, k, m, args.steps, args.warmup, **kw)
+            label = {"none": "fp32", "bf16": "bf16", "fp8": "fp8_e4m3"}[prec] + ("_exact" if mode == 0 else "_rerank40")
+            results[label] = ids
+            row = {"config": label, "precision": prec, "mode": mode, "nprobe": m,
+                   "recall@10_vs_fp32_exact": sweep[-1]["recall@10"], "queries_per_s": round(w.n_q / sec, 1),
+                   "ms_per_batch": round(sec * 1e3, 3), "cand_per_q": sweep[-1]["cand_per_q"],
+                   "surv_per_q": sweep[-1]["surv_per_q"], "build_s": round(build_s, 2), "sweep": sweep,
+                   "index_device_mib": round(ix.info()["device_bytes"] / 2**20, 1)}
+            rows.append(row)
+            log(f"[c3 {label}] nprobe={m} recall={row['recall@10_vs_fp32_exact']} {row['queries_per_s']:,.0f} q/s")
+        ix.close()
+    out = {"metric": "c3 precision mode: queries/s at recall@10>=0.9 per storage precision; recall@10 vs FP64",
+           "unit": "queries/s", "config": {"workload": "c3: N=5M d=96 unit Gaussian, inner product, 1-8 labels of "
+                                                       "1000 (Zipf 1.1), B=4096 h=4, 10k queries, 1-4 label ANDs, "
+                                                       "k=10, rerank 4k=40", "n": w.n, "n_queries": w.n_q},
+           "rows": rows}
+    if not args.no_cpu_baseline:
+        sample = np.sort(np.random.default_rng(9).choice(w.n_q, args.c3_sample, replace=False))
+        out["cpu_baseline"] = c3_baseline(w, sample, results)
+        log(f"[c3 cpu] {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+def serve_sweep(caps, ix, w, truth, nvalid, rates, seconds, **srv_kw):
+    """Poisson arrivals at each rate through the serving loop; per rate the
+    achieved queries/s, p50/p99 latency (submit to completion), mean batch
+    and recall@10 of the served results."""
+    rows = []
+    srv = caps.Server(ix, **srv_kw)
+    rng = np.random.default_rng(5)
+    try:
+        for rate in rates:
+            n = max(200, int(rate * seconds))
+            sel = np.arange(n) % w.n_q
+            q, co, ca, cv = subset(w, sel)
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+            srv.stats(reset=True)
+            tks = srv.replay(q, co, ca, cv, arrivals)
+            srv.drain(300.0)
+            st = srv.stats(reset=True)
+            found = {}
+            while True:
+                r = srv.poll()
+                if not len(r["tickets"]):
+                    break
+                for t, ids_ in zip(r["tickets"], r["ids"]):
+                    found[int(t)] = ids_
+            pos = {int(t): i for i, t in enumerate(tks) if t != 0}
+            got = np.stack([found[t] for t in pos])
+            qi = sel[np.array(list(pos.values()))]
+            rec = float(recall10(got, truth[qi], nvalid[qi]).mean())
+            row = {"offered_qps": rate, "achieved_qps": round(st["qps"], 1), "p50_ms": round(st["p50_ms"], 3),
+                   "p99_ms": round(st["p99_ms"], 3), "mean_batch": round(st["mean_batch"], 1), "requests": n,
+                   "rejected": st["rejected"], "failed": st["failed"], "recall@10": round(rec, 4)}
+            rows.append(row)
+            log(f"[serve] {row}")
+    finally:
+        srv.close()
+    return rows
+
+
+def run_c5(args, dev):
+    """Serving (E5) at the serving configuration: 10M x 128 integer vectors
+    stored with an FP16 copy, three dense attributes (10/50/200, Zipf 1.0)
+    plus label sets (1-8 of 5000, Zipf 1.1), B = 8192, h = 4; 10k queries
+    with 1-4 constraints of selectivity 0.01%-50%.  Centroid routing and a
+    learned router (192 -> 1024 -> 8192, trained on the GPU on queries
+    labelled by exact search) in front of the FP16 matrix-core scan; the
+    smallest nprobe with recall@10 >= 0.9 for each; then Poisson arrivals at
+    5k-100k queries/s through the serving loop (learned router, FP16 scan
+    with FP32 rerank of the top 4k), memory-based admission."""
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k = 10
+    t0 = time.perf_counter()
+    w = synth.make_c5(n=args.c5_n, n_q=args.nq)
+    log(f"c5: N={w.n} d={w.d} Q={w.n_q} labels={len(w.labels)} generated in {time.perf_counter() - t0:.1f}s")
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    B = w.n_partitions
+    t0 = time.perf_counter()
+    ix = caps.Index.from_workload(w, precision="fp16")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"c5 build {build_s:.1f}s, {ix.info()['device_bytes'] / 2**30:.2f} GiB on device")
+    t0 = time.perf_counter()
+    tid, _, _, tsurv = ix.search(*dq, k, B, counters=True)
+    truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+    log(f"c5 truth {time.perf_counter() - t0:.2f}s, mean |D_C| {nvalid.mean():.0f}")
+    grid = [64, 256, 512, 1024, 2048, 3072, 4096, 4608, 5120, 5632, 6144, 7168, 8192]
+    rows = []
+
+    def measure(label, **kw):
+        sweep = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid, **kw)
+        m = sweep[-1]["nprobe"]
+        sec = timed_search(ix, dq, k, m, args.steps, args.warmup, **kw)
+        row = {"config": label, "nprobe": m, "recall@10": sweep[-1]["recall@10"],
+               "queries_per_s": round(w.n_q / sec, 1), "ms_per_batch": round(sec * 1e3, 3),
+               "cand_per_q": sweep[-1]["cand_per_q"], "surv_per_q": sweep[-1]["surv_per_q"], "sweep": sweep}
+        rows.append(row)
+        log(f"[c5 {label}] nprobe={m} recall={row['recall@10']} {row['queries_per_s']:,.0f} q/s")
+        return row
+
+    measure("fp16_exact_centroid", mode=0)
+    measure("fp16_rerank40_centroid", mode=1, rerank=4 * k)
+    # learned router on C5-shaped training queries labelled by exact search
+    t0 = time.perf_counter()
+    rq, rco, rca, rcv = synth.make_c5_queries(args.c5_train, 2308_15014 + 50, w)
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    labels = []
+    for s0 in range(0, args.c5_train, 10_000):
+        sel = np.arange(s0, min(args.c5_train, s0 + 10_000))
+        co = np.concatenate([[0], np.cumsum(np.diff(rco)[sel])]).astype(np.int32)
+        ca, cv = rca[rco[sel[0]]:rco[sel[-1] + 1]], rcv[rco[sel[0]]:rco[sel[-1] + 1]]
+        ids, _ = ix.search(rq[sel], co, ca, cv, k, B)
+        labels.append(ix.router_labels(ids))
+    labels = torch.cat(labels)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = ix.router_train(rq, rco, rca, rcv, labels, hidden=1024, epochs=args.c5_epochs, batch=4096, lr=1e-3,
+                             in_scale=1.0 / 255.0, in_shift=-0.5, seed=13)
+    train_s = time.perf_counter() - t0
+    log(f"c5 router: {args.c5_train} queries (gen {gen_s:.1f}s, labels {label_s:.1f}s), {args.c5_epochs} epochs "
+        f"{train_s:.1f}s, loss {[round(float(x), 4) for x in losses]}")
+    r_exact = measure("fp16_exact_router", mode=0, routing=1)
+    r_rr = measure("fp16_rerank40_router", mode=1, rerank=4 * k, routing=1)
+    router = {"layers": "192-1024-8192", "train_queries": args.c5_train, "epochs": args.c5_epochs,
+              "label_s": round(label_s, 2), "train_s": round(train_s, 2),
+              "loss_per_epoch": [round(float(x), 4) for x in losses], "ln_B": round(float(np.log(B)), 4)}
+    rates = [float(x) for x in args.c5_rates.split(",") if x]
+    serving = serve_sweep(caps, ix, w, truth, nvalid, rates, args.serve_seconds, k=k, nprobe=r_rr["nprobe"], mode=1,
+                          rerank=4 * k, routing=1, max_batch=2048, streams=3, max_constraints=8,
+                          workspace_bytes=4 << 30)
+    out = {"metric": "c5 serving: p50/p99 latency and achieved queries/s under Poisson arrivals at recall@10>=0.9 "
+                     "(learned router + FP16 matrix-core scan)",
+           "config": {"workload": "c5: N=10M d=128 integer vectors, FP16 copy, 3 dense attrs (10/50/200 Zipf 1.0) + "
+                                  "1-8 labels of 5000 (Zipf 1.1), B=8192 h=4, 10k queries with 1-4 constraints of "
+                                  "selectivity 0.01-50%, k=10", "n": w.n, "n_queries": w.n_q,
+                      "build_s": round(build_s, 2), "mean_valid_per_q": float(nvalid.mean())},
+           "rows": rows, "router": router,
+           "serving": {"routing": "learned (centroid fallback)", "scan": "FP16 MFMA, FP32 rerank of the top 40",
+                       "nprobe": r_rr["nprobe"], "max_batch": 2048, "streams": 3,
+                       "workspace_budget_bytes": 4 << 30, "arrivals": "Poisson", "rates": serving}}
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = np.sort(np.random.default_rng(3).choice(w.n_q, args.c5_sample, replace=False))
+        tk = oracle.workload_tokens(w)
+        t0 = time.perf_counter()
+        bf = oracle.bruteforce(w.x, tk, w.metric, *subset(w, sample), k)
+        bf_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "kind": "oracle", "value": round(len(sample) / bf_s, 2), "unit": "queries/s",
+            "cores": oracle.set_threads(0), "sample": f"{len(sample)} queries, filtered brute force over all "
+                                                      f"{w.n} points ({bf_s:.1f} s)",
+            "truth_check": {"queries": len(sample),
+                            "gpu_all_partitions_equals_oracle_bruteforce": bool(np.array_equal(bf.ids, truth[sample])),
+                            "dist_valid_counts_equal": bool(np.array_equal(bf.n_surv, nvalid[sample]))},
+            "host": {"cpu_model": cpu_model()}}
+        log(f"[c5 cpu] {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +548,16 @@ def main():
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
+    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5"],
+                    help="headline: the benchmark line; ablation: AFT height and absence-fraction sweeps; "
+                         "c3: precision mode on the 5M-point angular corpus")
+    ap.add_argument("--c3-n", type=int, default=5_000_000)
+    ap.add_argument("--c3-sample", type=int, default=300, help="queries of the FP64 truth sample (c3)")
+    ap.add_argument("--c5-n", type=int, default=10_000_000)
+    ap.add_argument("--c5-train", type=int, default=200_000, help="router training queries (c5)")
+    ap.add_argument("--c5-epochs", type=int, default=4)
+    ap.add_argument("--c5-sample", type=int, default=100, help="queries of the oracle truth check (c5)")
+    ap.add_argument("--c5-rates", default="5000,10000,20000,50000,100000")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -257,6 +574,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.experiment == "ablation":
+        run_ablation(args, dev)
+        return
+    if args.experiment == "c3":
+        run_c3(args, dev)
+        return
+    if args.experiment == "c5":
+        run_c5(args, dev)
+        return
 
     t0 = time.perf_counter()
     w = synth.make_c2(n=args.n, n_q=args.nq)

@@ -109,6 +109,27 @@ caps_status caps_build(const float *x, int64_t n, int32_t d,
                        const int64_t *label_off, const uint32_t *labels, int32_t label_vocab,
                        const caps_build_params *params, void *stream, caps_index **out);
 
+/*
+ * caps_insert -- dynamic insertions (Table 1 "Dynamic Insertions"; Section 1
+ * "Practical Utility"): adds n_new points to a built index without
+ * rebuilding it.  HOST arrays laid out as for caps_build (x n_new x d;
+ * dense_vals n_new x n_dense, NULL without dense attributes; label_off
+ * n_new+1 offsets into labels, given exactly when the index has labels).
+ * The partition model stays frozen: new point i gets id n + i (n = the
+ * index's point count before the call), joins the partition the k-means
+ * assignment picks against the final centroids (argmin of |c|^2 - 2 x.c,
+ * IP -x.c, ties to the smaller partition) and, inside it, the first tagged
+ * level whose tag it holds (the order Algorithm 1 split the partition in),
+ * else the remainder.  Centroids, tags and the router do not change; the CSR
+ * stays in (partition, level, id) order and every per-point array, the
+ * low-precision copy included, grows.  Synchronises `stream`.  Errors:
+ * EINVAL (arguments, vocabularies, non-finite x, label sets given to an
+ * index without labels or missing), EUNSUPPORTED (limits of caps_build),
+ * ENOMEM, EDEVICE; on error the index is unchanged.
+ */
+caps_status caps_insert(caps_index *idx, const float *x, int64_t n_new, const uint32_t *dense_vals,
+                        const int64_t *label_off, const uint32_t *labels, void *stream);
+
 typedef struct {
     int32_t k;        /* 1 <= k <= 64 */
     int32_t nprobe;   /* m, 1 <= m <= B */

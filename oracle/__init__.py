@@ -312,6 +312,36 @@ def build_index(x, dense, dense_vocab, label_off, labels, label_vocab, *, metric
     return Index(x, tk, metric, b, h, cent, a, tags, level, perm, offs, np.asarray(init))
 
 
+def insert(idx: Index, x_new, dense_new, label_off_new, labels_new) -> Index:
+    """Dynamic insertion (Table 1; Section 1 "Practical Utility"): the new
+    points get ids n, n+1, ... and join the frozen partition model -- the
+    centroid the k-means assignment picks, then the first tagged level whose
+    tag they hold, else the remainder; centroids and tags are unchanged and
+    the CSR is laid out again in (partition, level, id) order."""
+    x_new = _c(x_new, np.float32)
+    n_new = x_new.shape[0]
+    tk = idx.tk
+    dense_vocab = np.diff(tk.dense_off).astype(np.int64)
+    tkn = tokens_of(dense_new, dense_vocab, label_off_new, labels_new, tk.label_vocab)
+    if tkn.n_tok != tk.n_tok:
+        raise ValueError("new points must carry the index's attribute kinds")
+    a_new = assign(x_new, idx.centroids, idx.metric)
+    lev_new = np.zeros(n_new, dtype=np.int8)
+    L = lib()
+    L.orc_insert_levels.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    tags = _c(idx.tags.reshape(-1), np.int32) if idx.h > 0 else np.zeros(1, np.int32)
+    L.orc_insert_levels(n_new, _p(a_new), _p(tags), idx.h, _p(tkn.tok_off), _p(tkn.toks), _p(lev_new))
+    tok_off = np.concatenate([tk.tok_off, tk.tok_off[-1] + tkn.tok_off[1:]])
+    allt = Tokens(tok_off, np.concatenate([tk.toks, tkn.toks]), tk.tok_attr, tk.n_tok, tk.dense_off, tk.n_dense,
+                  tk.label_vocab)
+    a_all = np.concatenate([idx.assign, a_new]).astype(np.int32)
+    l_all = np.concatenate([idx.level, lev_new]).astype(np.int8)
+    perm, offs = csr(a_all, l_all, idx.b, idx.h)
+    return Index(np.concatenate([idx.x, x_new]), allt, idx.metric, idx.b, idx.h, idx.centroids, a_all,
+                 idx.tags, l_all, perm, offs, idx.init)
+
+
 def build_from_workload(w, **over) -> Index:
     kw = dict(metric=w.metric, b=w.n_partitions, h=w.aft_height, iters=w.kmeans_iters,
               seed=w.seed)

@@ -250,6 +250,28 @@ int orc_aft(int64_t n, const int32_t *assign, int32_t b, int32_t h,
     return 0;
 }
 
+/* Dynamic insertion (Table 1 "Dynamic Insertions"; Section 1 and
+ * Section 7): the partition model and the tree's tags stay frozen.  A new
+ * point joins the partition the k-means assignment picks (orc_assign
+ * against the final centroids) and, inside it, the first tagged level whose
+ * tag it holds -- the order in which Algorithm 1 split the partition -- or
+ * the remainder (level h) when it holds none.  tok(i) as in orc_aft, for the
+ * new points only. */
+void orc_insert_levels(int64_t n_new, const int32_t *assign, const int32_t *tags, int32_t h,
+                       const int64_t *tok_off, const int32_t *toks, int8_t *level)
+{
+    for (int64_t i = 0; i < n_new; i++) {
+        const int32_t *t = tags + (size_t)assign[i] * h;
+        int32_t l = h;
+        for (int32_t j = 0; j < h && l == h; j++) {
+            if (t[j] < 0) continue;
+            for (int64_t e = tok_off[i]; e < tok_off[i + 1]; e++)
+                if (toks[e] == t[j]) { l = j; break; }
+        }
+        level[i] = (int8_t)l;
+    }
+}
+
 /* CSR over sub-partitions (Appendix "Index size"): order points by
  * (partition, level, id); offs[p*(h+1)+j] is the first CSR position of
  * sub-partition j of partition p, offs[B*(h+1)] = n; perm[pos] = point id. */

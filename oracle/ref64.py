@@ -105,3 +105,45 @@ def recall_at_k(found, truth, nvalid, k):
         f = set(int(v) for v in found[i, :k] if v >= 0)
         r[i] = 1.0 if denom == 0 else len(t & f) / denom
     return r
+
+
+def label_index(label_off, labels, n):
+    """Inverted index of label sets: (starts, ids), the ids holding label l
+    being ids[starts[l]:starts[l + 1]] in ascending order."""
+    label_off = np.asarray(label_off, dtype=np.int64)
+    labels = np.asarray(labels, dtype=np.int64)
+    owner = np.repeat(np.arange(n, dtype=np.int64), np.diff(label_off))
+    order = np.lexsort((owner, labels))
+    vocab = int(labels.max()) + 1 if len(labels) else 0
+    starts = np.zeros(vocab + 1, dtype=np.int64)
+    np.add.at(starts, labels + 1, 1)
+    return np.cumsum(starts), owner[order]
+
+
+def topk64_labels(x, inv, metric, q, con_off, con_attr, con_val, k, label_attr, queries):
+    """topk64 for label-only constraints through an inverted index: the valid
+    set is the intersection of the constrained labels' id lists (Definition
+    1); distances in FP64, ties to the smaller id.  Returns (ids, dists,
+    |D_C|) for the given queries."""
+    starts, ids_all = inv
+    out_ids, out_d, nvalid = [], [], []
+    n = x.shape[0]
+    for qi in queries:
+        pairs = pairs_of(con_off, con_attr, con_val, qi)
+        valid = np.arange(n)
+        for a, v in pairs:
+            if a != label_attr or v < 0 or v + 1 >= len(starts):
+                valid = np.zeros(0, dtype=np.int64)
+                break
+            valid = np.intersect1d(valid, ids_all[starts[v]:starts[v + 1]], assume_unique=True)
+        dd = dist64(x[valid], q[qi], metric)
+        key = dd if metric == 0 else -dd
+        order = np.lexsort((valid, key))[:k]
+        r_ids = np.full(k, -1, dtype=np.int64)
+        r_d = np.full(k, np.inf if metric == 0 else -np.inf)
+        r_ids[:len(order)] = valid[order]
+        r_d[:len(order)] = dd[order]
+        out_ids.append(r_ids)
+        out_d.append(r_d)
+        nvalid.append(len(valid))
+    return np.array(out_ids), np.array(out_d), np.array(nvalid)

@@ -91,6 +91,7 @@ STAGES = ["prep", "route", "topm", "select", "scan", "merge", "seed", "rescue"]
 SIGNATURES = {
     "caps_build": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32,
                            ctypes.POINTER(BuildParams), c_vp, ctypes.POINTER(c_vp)]),
+    "caps_insert": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "caps_search": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
                             c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_search_debug": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,

@@ -31,11 +31,42 @@ static caps_status fail(caps_status s, const char *fmt, ...) {
 
 void release_index(Index &ix) {
     void *ptrs[] = {ix.cent, ix.cnorm, ix.tags, ix.offs, ix.perm, ix.assign, ix.level,
-                    ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm, ix.lerr, ix.lnrm};
+                    ix.words, ix.sigs, ix.slots, ix.vecs, ix.lvecs, ix.lscale, ix.xnorm, ix.lerr, ix.lnrm,
+                    ix.clow, ix.cscale};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     router_free(ix.router);
     ix = Index{};
+}
+
+// Points to add to an index with schema `sch`: finite vectors, dense
+// values inside their vocabularies, label sets of at most kMaxLabels
+// distinct labels inside the label vocabulary (HOST arrays).
+static caps_status check_points(const char *who, const Schema &sch, const float *x, int64_t n, int32_t d,
+                                const uint32_t *dense_vals, const int64_t *label_off, const uint32_t *labels) {
+    const int32_t n_dense = sch.n_dense;
+    if (label_off) {
+        if (label_off[0] != 0) return fail(CAPS_EINVAL, "%s: label_off[0] != 0", who);
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t lo = label_off[i], hi = label_off[i + 1];
+            if (hi < lo) return fail(CAPS_EINVAL, "%s: label_off decreases at %lld", who, (long long)i);
+            if (hi - lo > kMaxLabels)
+                return fail(CAPS_EUNSUPPORTED, "%s: point %lld has more than %d labels", who, (long long)i, kMaxLabels);
+            for (int64_t e = lo; e < hi; e++) {
+                if (labels[e] >= (uint32_t)sch.label_vocab)
+                    return fail(CAPS_EINVAL, "%s: label %u outside vocabulary", who, labels[e]);
+                for (int64_t f = lo; f < e; f++)
+                    if (labels[f] == labels[e])
+                        return fail(CAPS_EINVAL, "%s: point %lld repeats label %u", who, (long long)i, labels[e]);
+            }
+        }
+    }
+    for (int64_t i = 0; i < n * n_dense; i++)
+        if (dense_vals[i] >= (uint32_t)sch.dense_vocab[i % n_dense])
+            return fail(CAPS_EINVAL, "%s: dense value outside vocabulary at %lld", who, (long long)i);
+    for (int64_t i = 0; i < n * (int64_t)d; i++)
+        if (!isfinite(x[i])) return fail(CAPS_EINVAL, "%s: non-finite x at %lld", who, (long long)i);
+    return CAPS_OK;
 }
 
 }  // namespace caps
@@ -90,30 +121,15 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
     if (has_labels) {
         if (label_vocab < 1 || label_vocab > 65535)
             return fail(label_vocab < 1 ? CAPS_EINVAL : CAPS_EUNSUPPORTED, "caps_build: label_vocab %d", label_vocab);
-        if (label_off[0] != 0) return fail(CAPS_EINVAL, "caps_build: label_off[0] != 0");
-        for (int64_t i = 0; i < n; i++) {
-            const int64_t lo = label_off[i], hi = label_off[i + 1];
-            if (hi < lo) return fail(CAPS_EINVAL, "caps_build: label_off decreases at %lld", (long long)i);
-            if (hi - lo > kMaxLabels)
-                return fail(CAPS_EUNSUPPORTED, "caps_build: point %lld has more than %d labels", (long long)i, kMaxLabels);
-            for (int64_t e = lo; e < hi; e++) {
-                if (labels[e] >= (uint32_t)label_vocab)
-                    return fail(CAPS_EINVAL, "caps_build: label %u outside vocabulary", labels[e]);
-                for (int64_t f = lo; f < e; f++)
-                    if (labels[f] == labels[e])
-                        return fail(CAPS_EINVAL, "caps_build: point %lld repeats label %u", (long long)i, labels[e]);
-            }
-        }
         sch.label_vocab = label_vocab;
     }
     sch.n_tok = sch.dense_off[n_dense] + (has_labels ? label_vocab : 0);
     if (sch.n_tok > kMaxTokensLds)
         return fail(CAPS_EUNSUPPORTED, "caps_build: %d attribute values exceed %d", sch.n_tok, kMaxTokensLds);
-    for (int64_t i = 0; i < n * n_dense; i++)
-        if (dense_vals[i] >= (uint32_t)sch.dense_vocab[i % n_dense])
-            return fail(CAPS_EINVAL, "caps_build: dense value outside vocabulary at %lld", (long long)i);
-    for (int64_t i = 0; i < n * (int64_t)d; i++)
-        if (!isfinite(x[i])) return fail(CAPS_EINVAL, "caps_build: non-finite x at %lld", (long long)i);
+    {
+        const caps_status cs = check_points("caps_build", sch, x, n, d, dense_vals, label_off, labels);
+        if (cs != CAPS_OK) return cs;
+    }
     if (p->init_ids) {
         std::vector<char> seen((size_t)n, 0);
         for (int32_t c = 0; c < b; c++) {
@@ -146,7 +162,7 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
     return CAPS_OK;
 }
 
-static caps_status check_search(const caps_index *idx, const caps_search_params *sp, const float *q, int32_t n_q,
+caps_status caps::caps_search_check(const caps_index *idx, const caps_search_params *sp, const float *q, int32_t n_q,
                                 const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
                                 int32_t n_con) {
     if (!idx || !sp) return fail(CAPS_EINVAL, "caps_search: null index or params");
@@ -178,7 +194,7 @@ extern "C" caps_status caps_search(const caps_index *idx, const caps_search_para
                                    int32_t n_q, const int32_t *con_off, const int32_t *con_attr,
                                    const int32_t *con_val, int32_t n_con, int32_t *out_ids, float *out_dist,
                                    int32_t *out_ncand, int32_t *out_nsurv, void *stream) {
-    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    caps_status s = caps_search_check(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
     if (s != CAPS_OK) return s;
     if (n_q > 0 && (!out_ids || !out_dist)) return fail(CAPS_EINVAL, "caps_search: null outputs");
     return search(&idx->ix, sp, q, n_q, con_off, con_attr, con_val, n_con, out_ids, out_dist, out_ncand,
@@ -190,7 +206,7 @@ extern "C" caps_status caps_search_debug(const caps_index *idx, const caps_searc
                                          const int32_t *con_val, int32_t n_con, int32_t *out_ids, float *out_dist,
                                          int32_t *out_ncand, int32_t *out_nsurv, uint64_t *out_surv_mask,
                                          void *stream) {
-    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    caps_status s = caps_search_check(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
     if (s != CAPS_OK) return s;
     if (n_q > 0 && (!out_ids || !out_dist || !out_surv_mask))
         return fail(CAPS_EINVAL, "caps_search_debug: null outputs");
@@ -207,7 +223,7 @@ extern "C" caps_status caps_search_debug(const caps_index *idx, const caps_searc
 
 extern "C" caps_status caps_search_workspace(const caps_index *idx, const caps_search_params *sp, int32_t n_q,
                                              int64_t *out_bytes) {
-    caps_status s = check_search(idx, sp, nullptr, 0, nullptr, nullptr, nullptr, 0);
+    caps_status s = caps_search_check(idx, sp, nullptr, 0, nullptr, nullptr, nullptr, 0);
     if (s != CAPS_OK) return s;
     if (n_q < 0 || !out_bytes) return fail(CAPS_EINVAL, "caps_search_workspace: bad arguments");
     *out_bytes = n_q == 0 ? 0 : (int64_t)search_workspace_bytes(&idx->ix, sp, n_q);
@@ -218,7 +234,7 @@ extern "C" caps_status caps_search_probes(const caps_index *idx, const caps_sear
                                           int32_t n_q, const int32_t *con_off, const int32_t *con_attr,
                                           const int32_t *con_val, int32_t n_con, int32_t *out_probes,
                                           uint32_t *out_masks, void *stream) {
-    caps_status s = check_search(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
+    caps_status s = caps_search_check(idx, sp, q, n_q, con_off, con_attr, con_val, n_con);
     if (s != CAPS_OK) return s;
     if (n_q > 0 && (!out_probes || !out_masks)) return fail(CAPS_EINVAL, "caps_search_probes: null outputs");
     return search(&idx->ix, sp, q, n_q, con_off, con_attr, con_val, n_con, nullptr, nullptr, nullptr, nullptr,
@@ -273,4 +289,23 @@ extern "C" void caps_free(caps_index *idx) {
     if (!idx) return;
     release_index(idx->ix);
     delete idx;
+}
+
+extern "C" caps_status caps_insert(caps_index *idx, const float *x, int64_t n_new, const uint32_t *dense_vals,
+                                   const int64_t *label_off, const uint32_t *labels, void *stream) {
+    if (!idx || n_new < 0) return fail(CAPS_EINVAL, "caps_insert: null index or n_new < 0");
+    if (n_new == 0) return CAPS_OK;
+    Index &ix = idx->ix;
+    if (!x) return fail(CAPS_EINVAL, "caps_insert: null x");
+    if (ix.n + n_new > INT32_MAX - 1) return fail(CAPS_EUNSUPPORTED, "caps_insert: more than 2^31-2 points");
+    if (ix.sch.n_dense > 0 && !dense_vals) return fail(CAPS_EINVAL, "caps_insert: dense values missing");
+    if ((ix.sch.label_vocab > 0) != (label_off != nullptr))
+        return fail(CAPS_EINVAL, "caps_insert: label sets must be given exactly when the index has labels");
+    if (label_off && !labels && label_off[n_new] != 0) return fail(CAPS_EINVAL, "caps_insert: labels missing");
+    caps_status s = check_points("caps_insert", ix.sch, x, n_new, ix.d, dense_vals, label_off, labels);
+    if (s != CAPS_OK) return s;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ix.device)
+        return fail(CAPS_EINVAL, "caps_insert: the index's device must be current");
+    return insert_points(&ix, x, n_new, dense_vals, label_off, labels, (hipStream_t)stream);
 }

@@ -427,6 +427,53 @@ static caps_status stable_sort(const int32_t *keys, int64_t n, int32_t nkeys, in
     return CAPS_OK;
 }
 
+// ------------------------------------------------------------------ insertion
+// Level of each new point in its (frozen) partition: the first tagged level
+// whose tag the point holds, else the remainder h.
+__global__ void k_insert_level(const int32_t *__restrict__ assign, int64_t n_new, int32_t h,
+                               const int32_t *__restrict__ tags, Schema sch, AttrSrc src,
+                               int8_t *__restrict__ level) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_new) return;
+    const int32_t *t = tags + (int64_t)assign[i] * h;
+    int8_t l = (int8_t)h;
+    for (int j = 0; j < h; j++)
+        if (t[j] >= 0 && holds_token(src, sch, (int32_t)i, t[j])) {
+            l = (int8_t)j;
+            break;
+        }
+    level[i] = l;
+}
+
+// New CSR position of every old one: shifted by the new points that land in
+// earlier segments (add[s] = their count before segment s).
+__global__ void k_insert_oldpos(const int32_t *__restrict__ offs, int32_t nseg, const int32_t *__restrict__ add,
+                                int64_t n_old, int32_t *__restrict__ newpos) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n_old) return;
+    int lo = 0, hi = nseg;   // the segment s with offs[s] <= pos < offs[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= pos) lo = mid;
+        else hi = mid;
+    }
+    newpos[pos] = (int32_t)pos + add[lo];
+}
+
+// dst row newpos[r] = src row r, rows of `w` 32-bit words.
+__global__ void k_scatter_rows(const uint32_t *__restrict__ src, int64_t nrows, int32_t w,
+                               const int32_t *__restrict__ newpos, uint32_t *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrows * w) return;
+    const int64_t r = e / w;
+    dst[(int64_t)newpos[r] * w + (e - r * w)] = src[e];
+}
+
+__global__ void k_iota(int32_t *__restrict__ p, int64_t n, int32_t base) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = base + (int32_t)i;
+}
+
 caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const uint32_t *dense,
                         const int64_t *label_off, const uint32_t *labels,
                         const caps_build_params *p, hipStream_t st) {
@@ -530,6 +577,173 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
     int32_t mx = 0;
     for (size_t s = 0; s + 1 < ix->h_offs.size(); s++) mx = std::max(mx, ix->h_offs[s + 1] - ix->h_offs[s]);
     ix->max_sub = mx;
+    return CAPS_OK;
+}
+
+}  // namespace caps
+
+namespace caps {
+
+// Dynamic insertion (Table 1 "Dynamic Insertions"): the partition model
+// stays frozen.  New point i gets id n + i, the partition the k-means
+// assignment picks and the first tagged level whose tag it holds; the CSR
+// keeps its (partition, level, id) order, so every old row moves by the
+// number of new rows in earlier segments and the new rows go to the end of
+// their segments in id order.  Every per-row array (vectors, packed
+// attributes, low-precision copy and its norms, permutation) is laid out
+// again in one pass; centroids, tags and the router are unchanged.
+caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32_t *dense, const int64_t *label_off,
+                          const uint32_t *labels, hipStream_t st) {
+    const Schema &sch = ix->sch;
+    const int64_t n_old = ix->n, n_tot = n_old + n_new;
+    const int32_t d = ix->d, b = ix->b, h = ix->h, nseg = b * (h + 1);
+    const int64_t nnz = label_off ? label_off[n_new] : 0;
+    DevBuf dx, ddense, dloff, dlab, dassign, dlevel, dnewpos_new, dnewpos_old, dadd, diota;
+    CAPS_HIP(hipMalloc(&dx.p, sizeof(float) * (size_t)n_new * d));
+    CAPS_HIP(hipMemcpyAsync(dx.p, x, sizeof(float) * (size_t)n_new * d, hipMemcpyHostToDevice, st));
+    if (sch.n_dense) {
+        CAPS_HIP(hipMalloc(&ddense.p, sizeof(uint32_t) * (size_t)n_new * sch.n_dense));
+        CAPS_HIP(hipMemcpyAsync(ddense.p, dense, sizeof(uint32_t) * (size_t)n_new * sch.n_dense,
+                                hipMemcpyHostToDevice, st));
+    }
+    if (label_off) {
+        CAPS_HIP(hipMalloc(&dloff.p, sizeof(int64_t) * (size_t)(n_new + 1)));
+        CAPS_HIP(hipMemcpyAsync(dloff.p, label_off, sizeof(int64_t) * (size_t)(n_new + 1), hipMemcpyHostToDevice, st));
+        CAPS_HIP(hipMalloc(&dlab.p, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+        if (nnz) CAPS_HIP(hipMemcpyAsync(dlab.p, labels, sizeof(uint32_t) * (size_t)nnz, hipMemcpyHostToDevice, st));
+    }
+    AttrSrc src{(const uint32_t *)ddense.p, (const int64_t *)dloff.p, (const uint32_t *)dlab.p};
+    // partition and level of the new points
+    CAPS_HIP(hipMalloc(&dassign.p, sizeof(int32_t) * (size_t)n_new));
+    CAPS_HIP(hipMalloc(&dlevel.p, sizeof(int8_t) * (size_t)n_new));
+    hipLaunchKernelGGL(k_scores<true>, dim3((unsigned)((n_new + kTile - 1) / kTile)), dim3(256), 0, st,
+                       (const float *)dx.p, n_new, d, ix->cent, ix->cnorm, b, ix->metric, (int32_t *)dassign.p,
+                       nullptr);
+    hipLaunchKernelGGL(k_insert_level, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, st,
+                       (const int32_t *)dassign.p, n_new, h, ix->tags, sch, src, (int8_t *)dlevel.p);
+    CAPS_HIP(hipGetLastError());
+    std::vector<int32_t> a_new((size_t)n_new);
+    std::vector<int8_t> l_new((size_t)n_new);
+    CAPS_HIP(hipMemcpyAsync(a_new.data(), dassign.p, sizeof(int32_t) * (size_t)n_new, hipMemcpyDeviceToHost, st));
+    CAPS_HIP(hipMemcpyAsync(l_new.data(), dlevel.p, sizeof(int8_t) * (size_t)n_new, hipMemcpyDeviceToHost, st));
+    CAPS_HIP(hipStreamSynchronize(st));
+    // new layout on the host: counts per segment, offsets, positions
+    std::vector<int32_t> cnt((size_t)nseg, 0), add((size_t)nseg + 1, 0), run((size_t)nseg, 0);
+    for (int64_t i = 0; i < n_new; i++) cnt[(size_t)a_new[(size_t)i] * (h + 1) + l_new[(size_t)i]]++;
+    for (int32_t sgi = 0; sgi < nseg; sgi++) add[(size_t)sgi + 1] = add[(size_t)sgi] + cnt[(size_t)sgi];
+    std::vector<int32_t> offs_new((size_t)nseg + 1), pos_new((size_t)n_new);
+    for (int32_t sgi = 0; sgi <= nseg; sgi++) offs_new[(size_t)sgi] = ix->h_offs[(size_t)sgi] + add[(size_t)sgi];
+    for (int64_t i = 0; i < n_new; i++) {
+        const int32_t sg = a_new[(size_t)i] * (h + 1) + l_new[(size_t)i];
+        pos_new[(size_t)i] = ix->h_offs[(size_t)sg + 1] + add[(size_t)sg] + run[(size_t)sg]++;
+    }
+    CAPS_HIP(hipMalloc(&dnewpos_new.p, sizeof(int32_t) * (size_t)n_new));
+    CAPS_HIP(hipMemcpyAsync(dnewpos_new.p, pos_new.data(), sizeof(int32_t) * (size_t)n_new, hipMemcpyHostToDevice, st));
+    CAPS_HIP(hipMalloc(&dadd.p, sizeof(int32_t) * (size_t)(nseg + 1)));
+    CAPS_HIP(hipMemcpyAsync(dadd.p, add.data(), sizeof(int32_t) * (size_t)(nseg + 1), hipMemcpyHostToDevice, st));
+    CAPS_HIP(hipMalloc(&dnewpos_old.p, sizeof(int32_t) * (size_t)(n_old > 0 ? n_old : 1)));
+    hipLaunchKernelGGL(k_insert_oldpos, dim3((unsigned)((n_old + 255) / 256)), dim3(256), 0, st, ix->offs, nseg,
+                       (const int32_t *)dadd.p, n_old, (int32_t *)dnewpos_old.p);
+    CAPS_HIP(hipGetLastError());
+    const int32_t *np_old = (const int32_t *)dnewpos_old.p, *np_new = (const int32_t *)dnewpos_new.p;
+
+    // every array is first built anew beside the old one; only when all of
+    // them are ready are they swapped in (an error leaves the index as it was)
+    struct Swap {
+        void **slot;
+        void *fresh;
+        size_t grow;
+    };
+    std::vector<Swap> swaps;
+    struct Pending {
+        std::vector<Swap> *v;
+        ~Pending() {
+            for (auto &sw : *v)
+                if (sw.fresh) (void)hipFree(sw.fresh);
+        }
+    } pending{&swaps};
+    // a per-row array in CSR order: old rows moved, new rows (`fresh`, input
+    // order) placed
+    auto relayout = [&](void **arr, size_t row_bytes, const void *fresh) -> caps_status {
+        if (!*arr) return CAPS_OK;
+        void *out = nullptr;
+        CAPS_TRY(dalloc(&out, row_bytes * (size_t)n_tot, nullptr));
+        swaps.push_back({arr, out, row_bytes * (size_t)n_new});
+        const int32_t w = (int32_t)(row_bytes / 4);
+        hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n_old * w + 255) / 256)), dim3(256), 0, st,
+                           (const uint32_t *)*arr, n_old, w, np_old, (uint32_t *)out);
+        hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n_new * w + 255) / 256)), dim3(256), 0, st,
+                           (const uint32_t *)fresh, n_new, w, np_new, (uint32_t *)out);
+        CAPS_HIP(hipGetLastError());
+        return CAPS_OK;
+    };
+    // a per-point array in id order: the new points appended
+    auto append = [&](void **arr, size_t elem, const void *fresh) -> caps_status {
+        void *out = nullptr;
+        CAPS_TRY(dalloc(&out, elem * (size_t)n_tot, nullptr));
+        swaps.push_back({arr, out, elem * (size_t)n_new});
+        CAPS_HIP(hipMemcpyAsync(out, *arr, elem * (size_t)n_old, hipMemcpyDeviceToDevice, st));
+        CAPS_HIP(hipMemcpyAsync((char *)out + elem * (size_t)n_old, fresh, elem * (size_t)n_new,
+                                hipMemcpyDeviceToDevice, st));
+        return CAPS_OK;
+    };
+    // the new rows of every array, in input order
+    DevBuf fperm, fwords, fsigs, fslots, flvec, fscale, fxn, ferr, fnrm;
+    CAPS_HIP(hipMalloc(&fperm.p, sizeof(int32_t) * (size_t)n_new));
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, st, (int32_t *)fperm.p, n_new,
+                       (int32_t)n_old);
+    CAPS_HIP(hipMalloc(&diota.p, sizeof(int32_t) * (size_t)n_new));
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, st, (int32_t *)diota.p, n_new, 0);
+    if (ix->words) CAPS_HIP(hipMalloc(&fwords.p, sizeof(uint32_t) * (size_t)n_new));
+    if (ix->sigs) {
+        CAPS_HIP(hipMalloc(&fsigs.p, sizeof(uint64_t) * (size_t)n_new));
+        CAPS_HIP(hipMalloc(&fslots.p, sizeof(uint16_t) * (size_t)n_new * kMaxLabels));
+    }
+    hipLaunchKernelGGL(k_permute_attrs, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, st,
+                       (const int32_t *)diota.p, n_new, sch, src, (uint32_t *)fwords.p, (uint64_t *)fsigs.p,
+                       (uint16_t *)fslots.p);
+    CAPS_HIP(hipGetLastError());
+    const size_t eb = ix->prec == CAPS_PREC_FP8 ? 1 : 2;
+    if (ix->prec != CAPS_PREC_NONE) {
+        CAPS_HIP(hipMalloc(&flvec.p, (size_t)n_new * ix->dpad * eb));
+        CAPS_HIP(hipMalloc(&fxn.p, sizeof(float) * (size_t)n_new));
+        CAPS_HIP(hipMalloc(&ferr.p, sizeof(float) * (size_t)n_new));
+        CAPS_HIP(hipMalloc(&fnrm.p, sizeof(float) * (size_t)n_new));
+        if (ix->prec == CAPS_PREC_FP8) CAPS_HIP(hipMalloc(&fscale.p, sizeof(float) * (size_t)n_new));
+        CAPS_TRY(quantize_rows(ix, (const float *)dx.p, n_new, flvec.p, (float *)fscale.p, (float *)fxn.p,
+                               (float *)ferr.p, (float *)fnrm.p, st));
+    }
+    CAPS_TRY(relayout((void **)&ix->perm, sizeof(int32_t), fperm.p));
+    CAPS_TRY(relayout((void **)&ix->vecs, sizeof(float) * (size_t)d, dx.p));
+    CAPS_TRY(relayout((void **)&ix->words, sizeof(uint32_t), fwords.p));
+    CAPS_TRY(relayout((void **)&ix->sigs, sizeof(uint64_t), fsigs.p));
+    CAPS_TRY(relayout((void **)&ix->slots, sizeof(uint16_t) * kMaxLabels, fslots.p));
+    CAPS_TRY(relayout(&ix->lvecs, (size_t)ix->dpad * eb, flvec.p));
+    CAPS_TRY(relayout((void **)&ix->lscale, sizeof(float), fscale.p));
+    CAPS_TRY(relayout((void **)&ix->xnorm, sizeof(float), fxn.p));
+    CAPS_TRY(relayout((void **)&ix->lerr, sizeof(float), ferr.p));
+    CAPS_TRY(relayout((void **)&ix->lnrm, sizeof(float), fnrm.p));
+    CAPS_TRY(append((void **)&ix->assign, sizeof(int32_t), dassign.p));
+    CAPS_TRY(append((void **)&ix->level, sizeof(int8_t), dlevel.p));
+    {
+        void *o = nullptr;
+        CAPS_TRY(dalloc(&o, sizeof(int32_t) * (size_t)(nseg + 1), nullptr));
+        swaps.push_back({(void **)&ix->offs, o, 0});
+        CAPS_HIP(hipMemcpyAsync(o, offs_new.data(), sizeof(int32_t) * (size_t)(nseg + 1), hipMemcpyHostToDevice, st));
+    }
+    CAPS_HIP(hipStreamSynchronize(st));
+    // commit: swap the new arrays in, release the old ones
+    for (auto &sw : swaps) {
+        (void)hipFree(*sw.slot);
+        *sw.slot = sw.fresh;
+        sw.fresh = nullptr;
+        ix->bytes += (int64_t)sw.grow;
+    }
+    ix->h_offs = offs_new;
+    int32_t mx = 0;
+    for (int32_t sgi = 0; sgi < nseg; sgi++) mx = std::max(mx, offs_new[(size_t)sgi + 1] - offs_new[(size_t)sgi]);
+    ix->max_sub = mx;
+    ix->n = n_tot;
     return CAPS_OK;
 }
 

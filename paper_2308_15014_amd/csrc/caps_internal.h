@@ -88,6 +88,8 @@ struct Index {
     float *xnorm = nullptr;     // n exact FP32 |x|^2 (sequential fma), CSR order
     float *lerr = nullptr;      // n upper bounds on |x - x~| (x~: the copy's value), CSR order
     float *lnrm = nullptr;      // n upper bounds on |x~|, CSR order
+    void *clow = nullptr;       // b x dpad centroid copy in the same format (precision-mode routing)
+    float *cscale = nullptr;    // b per-centroid FP8 scales
     std::vector<int32_t> h_offs;
     struct Router *router = nullptr;   // learned router (owned), if trained or set
 };
@@ -140,6 +142,11 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                    int32_t n_con, int32_t *out_ids, float *out_dist, int32_t *out_ncand, int32_t *out_nsurv,
                    int32_t *out_probes, uint32_t *out_masks, hipStream_t st, const SearchExtra *extra = nullptr);
 
+// argument checks shared by the search entry points (caps_api.hip)
+caps_status caps_search_check(const caps_index *idx, const caps_search_params *sp, const float *q, int32_t n_q,
+                              const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                              int32_t n_con);
+
 // device bytes the workspace of one search call of nq queries takes
 size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq);
 
@@ -149,11 +156,22 @@ void prof_end(int stage, hipStream_t st);
 
 // ---- low-precision path (caps_mfma.hip)
 caps_status build_lowp(Index *ix, hipStream_t st);
+caps_status build_lowp_centroids(Index *ix, hipStream_t st);
+// precision-mode routing: scores of nb rounded queries against the centroid copy
+caps_status lowp_route(const Index *ix, const void *qlow, const float *qscale, int32_t nb, float *scores,
+                       hipStream_t st);
+caps_status lowp_qquant(const Index *ix, const float *q, int32_t nb, void *qlow, float *qscale, float *qaux,
+                        hipStream_t st);
+// low-precision rows (and their FP32 norms and error norms) of n FP32 rows
+caps_status quantize_rows(const Index *ix, const float *x, int64_t n, void *lvec, float *scale, float *xnorm,
+                          float *lerr, float *lnrm, hipStream_t st);
+// dynamic insertion of n_new points (HOST arrays, validated by the caller)
+caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32_t *dense, const int64_t *label_off,
+                          const uint32_t *labels, hipStream_t st);
 // one launch of the matrix-core scan over a sub-batch of nb queries
 struct LowpScan {
     int32_t nb, m, r;             // r: keys kept per (query, probe)
     int kind;                     // 0 approximate keys, 1 exact main pass, 2 exact rescue pass
-    bool first_round;             // also round the queries (first launch of a sub-batch)
     int stage;                    // profiling stage of the launch (CAPS_STAGE_SCAN or _SEED)
     int64_t max_tiles;
     const int4 *tiles;            // per tile: partition, first entry, entries (0: none)

@@ -252,6 +252,11 @@ static caps_status load(Index &ix, const char *path) {
     }
     ix.h_offs.resize((size_t)ix.b * (ix.h + 1) + 1);
     CAPS_HIP(hipMemcpy(ix.h_offs.data(), ix.offs, sizeof(int32_t) * ix.h_offs.size(), hipMemcpyDeviceToHost));
+    {   // the centroid copy of precision-mode routing is derived, not stored
+        const caps_status cs = build_lowp_centroids(&ix, nullptr);
+        if (cs != CAPS_OK) return cs;
+        CAPS_HIP(hipDeviceSynchronize());
+    }
     if (hd.has_router) {
         Router *R = new Router;
         ix.router = R;

@@ -136,6 +136,15 @@ __global__ void k_quantize(const float *__restrict__ x, int64_t n, int32_t d, in
 
 static int esize_of(int prec) { return prec == CAPS_PREC_FP8 ? 1 : 2; }
 
+caps_status quantize_rows(const Index *ix, const float *x, int64_t n, void *lvec, float *scale, float *xnorm,
+                          float *lerr, float *lnrm, hipStream_t st) {
+    if (n <= 0) return CAPS_OK;
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, ix->d, ix->dpad,
+                       ix->prec, lvec, scale, xnorm, lerr, lnrm);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
 caps_status build_lowp(Index *ix, hipStream_t st) {
     if (ix->prec == CAPS_PREC_NONE) return CAPS_OK;
     // rows padded to 32 x {1, 2, 4, 8} coordinates: the scan kernels are
@@ -159,7 +168,7 @@ caps_status build_lowp(Index *ix, hipStream_t st) {
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)((ix->n + 255) / 256)), dim3(256), 0, st, ix->vecs, ix->n, ix->d,
                        ix->dpad, ix->prec, ix->lvecs, ix->lscale, ix->xnorm, ix->lerr, ix->lnrm);
     CAPS_HIP(hipGetLastError());
-    return CAPS_OK;
+    return build_lowp_centroids(ix, st);
 }
 
 // ------------------------------------------------------------------ queries
@@ -215,6 +224,121 @@ __global__ __launch_bounds__(256) void k_qquant(const float *__restrict__ q, int
         qaux[4 * i + 2] = f32_up(sqrt(e2) * kNormSlack);
         qaux[4 * i + 3] = f32_up(sqrt(a2) * kNormSlack);
     }
+}
+
+// ------------------------------------------------------------------ routing
+// Precision-mode routing: query x centroid scores from the low-precision
+// copies on the matrix cores (FP32 accumulation).  64 queries x 64
+// centroids per workgroup, wave w owning queries 16w..16w+15: per K-step
+// one A operand (its query rows) and four B operands (four 16-centroid
+// blocks), read straight from global memory (the centroid copy is small and
+// stays in cache).  Score: L2 |c|^2 - 2 q~.c~ (|c|^2 of the FP32 centroid,
+// sequential fma), IP -q~.c~; FP8 products are scaled by both scales.
+template <int PREC, int NS>
+__global__ __launch_bounds__(256) void k_route_mfma(const uint8_t *__restrict__ qlow, const float *__restrict__ qscale,
+                                                    int32_t nq, const uint8_t *__restrict__ clow,
+                                                    const float *__restrict__ cscale, const float *__restrict__ cn,
+                                                    int32_t b, int32_t metric, float *__restrict__ scores) {
+    typedef MfmaOp<PREC> Op;
+    typedef typename Op::T VT;
+    constexpr int ES = Op::ES;
+    constexpr int KSTEP_BYTES = 32 * ES, LANE_BYTES = 8 * ES, ROWB = NS * KSTEP_BYTES;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * 64 + 16 * w;
+    const int c0 = blockIdx.y * 64;
+    const int64_t arow = q0 + (lane & 15);
+    const bool aok = arow < nq;
+    const uint8_t *asrc = qlow + (aok ? arow : 0) * ROWB + (lane >> 4) * LANE_BYTES;
+    f32x4 acc[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const VT a = aok ? Op::load(asrc + s * KSTEP_BYTES) : VT{};
+        VT bf[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) {
+            const int c = c0 + bb * 16 + (lane & 15);
+            bf[bb] = c < b ? Op::load(clow + (int64_t)c * ROWB + s * KSTEP_BYTES + (lane >> 4) * LANE_BYTES) : VT{};
+        }
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) acc[bb] = Op::mma(a, bf[bb], acc[bb]);
+    }
+#pragma unroll
+    for (int bb = 0; bb < 4; bb++) {
+        const int c = c0 + bb * 16 + (lane & 15);
+        if (c >= b) continue;
+        const float cs = PREC == CAPS_PREC_FP8 ? cscale[c] : 1.0f;
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const int64_t q = q0 + (lane >> 4) * 4 + rr;
+            if (q >= nq) continue;
+            float dd = acc[bb][rr];
+            if (PREC == CAPS_PREC_FP8) dd = dd * qscale[q] * cs;
+            scores[q * b + c] = canon0(metric == 0 ? fmaf(-2.0f, dd, cn[c]) : -dd);
+        }
+    }
+}
+
+template <int PREC>
+static void launch_route(int ns, dim3 g, hipStream_t st, const uint8_t *qlow, const float *qscale, int32_t nq,
+                         const uint8_t *clow, const float *cscale, const float *cn, int32_t b, int32_t metric,
+                         float *scores) {
+    switch (ns) {
+    case 1: hipLaunchKernelGGL((k_route_mfma<PREC, 1>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
+    case 2: hipLaunchKernelGGL((k_route_mfma<PREC, 2>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
+    case 4: hipLaunchKernelGGL((k_route_mfma<PREC, 4>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
+    default: hipLaunchKernelGGL((k_route_mfma<PREC, 8>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
+    }
+}
+
+// Scores of nb rounded queries (k_qquant output) against the centroid copy.
+caps_status lowp_route(const Index *ix, const void *qlow, const float *qscale, int32_t nb, float *scores,
+                       hipStream_t st) {
+    const dim3 g((unsigned)((nb + 63) / 64), (unsigned)((ix->b + 63) / 64));
+    const uint8_t *q = reinterpret_cast<const uint8_t *>(qlow), *c = reinterpret_cast<const uint8_t *>(ix->clow);
+    const int ns = ix->dpad / 32;
+    if (ix->prec == CAPS_PREC_BF16)
+        launch_route<CAPS_PREC_BF16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+    else if (ix->prec == CAPS_PREC_FP16)
+        launch_route<CAPS_PREC_FP16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+    else
+        launch_route<CAPS_PREC_FP8>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+// Rounds the queries of a sub-batch into the index's copy format (codes,
+// FP8 scale, error norms) for the matrix-core kernels.
+caps_status lowp_qquant(const Index *ix, const float *q, int32_t nb, void *qlow, float *qscale, float *qaux,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_qquant, dim3((nb + 3) / 4), dim3(256), 0, st, q, nb, ix->d, ix->dpad, ix->prec, qlow, qscale,
+                       qaux);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+// Low-precision copy of the centroids (the same format as the vectors', FP8
+// with one scale per centroid) for precision-mode routing.
+caps_status build_lowp_centroids(Index *ix, hipStream_t st) {
+    if (ix->prec == CAPS_PREC_NONE) return CAPS_OK;
+    const size_t eb = (size_t)esize_of(ix->prec), b = (size_t)ix->b;
+    if (!ix->clow) {
+        CAPS_HIP(hipMalloc(&ix->clow, b * ix->dpad * eb));
+        CAPS_HIP(hipMalloc((void **)&ix->cscale, sizeof(float) * b));
+        ix->bytes += (int64_t)(b * ix->dpad * eb + sizeof(float) * b);
+    }
+    float *tmp = nullptr;   // the norms k_quantize also writes (unused here)
+    CAPS_HIP(hipMallocAsync((void **)&tmp, sizeof(float) * 3 * b, st));
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((b + 255) / 256)), dim3(256), 0, st, ix->cent, (int64_t)b, ix->d,
+                       ix->dpad, ix->prec, ix->clow, ix->cscale, tmp, tmp + b, tmp + 2 * b);
+    const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(tmp, st);
+    if (e != hipSuccess) {
+        set_error("build_lowp_centroids: %s", hipGetErrorString(e));
+        return CAPS_EDEVICE;
+    }
+    return CAPS_OK;
 }
 
 // ------------------------------------------------------------------ merge + rerank
@@ -280,9 +404,6 @@ size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj) {
 }
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
-    if (S.first_round)
-        hipLaunchKernelGGL(k_qquant, dim3((S.nb + 3) / 4), dim3(256), 0, st, S.q, S.nb, ix->d, ix->dpad, ix->prec,
-                           S.qlow, S.qscale, S.qaux);
     LowpArgs A;
     A.tiles = S.tiles;
     A.ntiles = (int32_t)S.max_tiles;

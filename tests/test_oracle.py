@@ -314,6 +314,53 @@ def test_single_term_disjunction_is_the_conjunction(orc):
         assert np.array_equal(u, v)
 
 
+def test_insert_hand_worked(orc):
+    g, dense = _worked()
+    n = len(dense)
+    x = np.arange(n * 2, dtype=np.float32).reshape(n, 2)
+    idx = orc.build_index(x, dense, g["dense_vocab"], None, None, 0, metric=0, b=1,
+                          h=g["h"], iters=0, seed=0, init=np.array([0], dtype=np.int32))
+    new = np.array(g["inserts"], dtype=np.uint32)
+    iy = orc.insert(idx, np.zeros((len(new), 2), np.float32), new, None, None)
+    assert iy.level[n:].tolist() == g["insert_level"]
+    assert iy.perm.tolist() == g["insert_perm"]
+    assert iy.offs.tolist() == g["insert_offs"]
+    assert np.array_equal(iy.tags, idx.tags) and np.array_equal(iy.centroids, idx.centroids)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=1200, d=8, n_q=40, vocabs=(3, 5), label_vocab=0, b=7, h=2),
+    dict(n=1500, d=6, n_q=40, vocabs=(4,), label_vocab=12, b=6, h=3, integer=True),
+    dict(n=1000, d=5, n_q=40, vocabs=(), label_vocab=9, b=5, h=4, metric=1),
+])
+def test_reinserted_points_land_with_their_twins(orc, case):
+    """A copy of a build point (same vector and attributes) joins the twin's
+    partition and sub-partition: the final assignment is the argmin against
+    the final centroids, and Algorithm 1 placed every point in the first
+    level whose tag it holds."""
+    w = _tiny(80, **case)
+    idx = orc.build_from_workload(w, iters=3)
+    sel = np.arange(0, w.n, 3)
+    lo = w.label_off
+    if w.labels is not None:
+        lab = [w.labels[lo[i]:lo[i + 1]] for i in sel]
+        loff = np.concatenate([[0], np.cumsum([len(v) for v in lab])]).astype(np.int64)
+        labs = np.concatenate(lab).astype(np.uint32) if len(lab) else np.zeros(0, np.uint32)
+    else:
+        loff, labs = None, None
+    iy = orc.insert(idx, w.x[sel], None if w.dense is None else w.dense[sel], loff, labs)
+    assert np.array_equal(iy.assign[w.n:], idx.assign[sel])
+    assert np.array_equal(iy.level[w.n:], idx.level[sel])
+    # the layout stays a disjoint cover in (partition, level, id) order
+    assert sorted(iy.perm.tolist()) == list(range(w.n + len(sel)))
+    assert iy.offs[0] == 0 and iy.offs[-1] == w.n + len(sel) and np.all(np.diff(iy.offs) >= 0)
+    # every partition probed: still the filtered brute force over all points
+    r = orc.search(iy, w.q, w.con_off, w.con_attr, w.con_val, 9, w.n_partitions)
+    bf = orc.bruteforce(iy.x, iy.tk, w.metric, w.q, w.con_off, w.con_attr, w.con_val, 9)
+    assert np.array_equal(r.ids, bf.ids)
+    assert np.array_equal(r.dist.view(np.uint32), bf.dist.view(np.uint32))
+
+
 def _aft_properties(idx):
     tk = idx.tk
     n = idx.x.shape[0]
@@ -535,3 +582,13 @@ def test_c1_recall_against_fp64(orc):
     full = orc.search(idx, w.q, w.con_off, w.con_attr, w.con_val, k=10, m=32)
     assert ref64.recall_at_k(full.ids, ids64, nv, 10).mean() == 1.0
     assert 0.3 < rec <= 1.0
+
+
+def test_label_index_bruteforce_equals_mask_bruteforce():
+    w = _tiny(91, n=3000, d=7, n_q=40, vocabs=(), label_vocab=30, metric=1, cmin=0, cmax=4, max_labels=8)
+    inv = ref64.label_index(w.label_off, w.labels, w.n)
+    a = ref64.topk64_labels(w.x, inv, 1, w.q, w.con_off, w.con_attr, w.con_val, 10, 0, range(w.n_q))
+    b = ref64.topk64(w.x, None, w.label_off, w.labels, [], w.label_vocab, 1, w.q, w.con_off, w.con_attr,
+                     w.con_val, 10)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
