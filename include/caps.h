@@ -225,6 +225,29 @@ caps_status caps_search(const caps_index *idx, const caps_search_params *sp,
                         int32_t *out_ncand, int32_t *out_nsurv, void *stream);
 
 /*
+ * caps_search_static -- caps_search (same arguments, results and errors)
+ * that allocates nothing, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Its workspace is the library's own static device array of
+ * CAPS_STATIC_WORKSPACE_BYTES (64 MiB), held by every GPU the library runs
+ * on until the process ends; the batch is searched in sub-batches that fit
+ * it (sp->workspace_bytes, if set, must not exceed it: EINVAL).  A single
+ * query needing more than the array (very large B x nprobe) gives
+ * EUNSUPPORTED.  The index's device must be the current device (else
+ * EINVAL).  Every call on one GPU shares that GPU's array and overwrites
+ * it: calls that overlap on one GPU (two host threads, or two streams
+ * without an ordering between them) race and must not be issued; calls in
+ * order on one stream are safe.  Every kernel initialises the workspace
+ * memory it reads, so no state carries over from the previous call.
+ */
+#define CAPS_STATIC_WORKSPACE_BYTES (64ll << 20)
+caps_status caps_search_static(const caps_index *idx, const caps_search_params *sp,
+                               const float *q, int32_t n_q,
+                               const int32_t *con_off, const int32_t *con_attr, const int32_t *con_val,
+                               int32_t n_con, int32_t *out_ids, float *out_dist,
+                               int32_t *out_ncand, int32_t *out_nsurv, void *stream);
+
+/*
  * caps_search_debug -- caps_search (same arguments and arithmetic) that also
  * writes the filter's pass bits and validates the queries: out_surv_mask
  * (DEVICE, n_q x ceil(n / 64) uint64 words, cleared by the call) gets, for

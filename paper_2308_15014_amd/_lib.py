@@ -94,6 +94,8 @@ SIGNATURES = {
     "caps_insert": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "caps_search": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
                             c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "caps_search_static": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
+                                   c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_search_debug": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
                                   c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_search_workspace": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_i32, ctypes.POINTER(c_i64)]),

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcaps.so")
 
-SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_mfma.hip", "caps_router.hip", "caps_server.hip", "caps_io.hip", "caps_util.hip"]
+SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_mfma.hip", "caps_router.hip", "caps_server.hip", "caps_io.hip", "caps_util.hip", "caps_static.hip"]
 # caps_scan_inst.hip once per (precision, kind): the matrix-core scan
 # instantiations, compiled in parallel (CAPS_PREC_BF16 = 1, FP8 = 2, FP16 = 3;
 # kinds: approximate keys, exact main pass, exact rescue pass)

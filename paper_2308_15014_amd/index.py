@@ -165,6 +165,32 @@ class Index:
             return ids, dist, nc, ns
         return ids, dist
 
+    def search_static(self, q, con_off, con_attr, con_val, k: int, nprobe: int, *, rule: int = 0, mode: int = 0,
+                      rerank: int = 0, routing: int = 0, stream=None, counters: bool = False, out=None,
+                      workspace_bytes: int = 0, disjunctive: bool = False):
+        """caps_search_static: the same search in the library's static device
+        workspace (no allocation by the library; outputs allocated here unless
+        `out` = (ids, dist) is given)."""
+        torch = _torch()
+        qd, co, ca, cv, n_con = self._qargs(q, con_off, con_attr, con_val)
+        nq = int(qd.shape[0])
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        else:
+            ids, dist = out
+        nc = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
+        ns = torch.empty(nq, dtype=torch.int32, device=self.device) if counters else None
+        sp = self._sparams(k, nprobe, rule, mode, rerank, routing, workspace_bytes, False, disjunctive)
+        with torch.cuda.device(self.device):
+            check(lib().caps_search_static(self._h, ctypes.byref(sp), qd.data_ptr(), nq, co.data_ptr(),
+                                           ca.data_ptr(), cv.data_ptr(), n_con, ids.data_ptr(), dist.data_ptr(),
+                                           nc.data_ptr() if counters else None, ns.data_ptr() if counters else None,
+                                           _stream(stream)))
+        if counters:
+            return ids, dist, nc, ns
+        return ids, dist
+
     @staticmethod
     def _sparams(k, nprobe, rule=0, mode=0, rerank=0, routing=0, workspace_bytes=0, validate=False,
                  disjunctive=False, rescue_grid=0):
