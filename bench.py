@@ -423,6 +423,54 @@ def serve_sweep(caps, ix, w, truth, nvalid, rates, seconds, **srv_kw):
     return rows
 
 
+def run_wide(args, dev):
+    """Larger attribute lengths (the paper's appendix): every item holds L
+    attributes (L = 3, 10, 100; values Zipf(1.0) over 10 each, stored as
+    labels), a query keeps each attribute of a random item with probability
+    1, 0.3, 0.03; the 1M-point integer corpus, B = 1024, h = 2, exact search
+    on the BF16 bounds.  Per L: recall@10 and queries/s along an nprobe grid
+    and the smallest grid nprobe with recall@10 >= 0.9."""
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k = 10
+    out = {"metric": "larger attribute lengths: queries/s vs recall@10 for L = 3, 10, 100",
+           "config": {"workload": "1M x 128 integer vectors, L attributes per item as labels (10 values each, "
+                                  "Zipf 1.0), query keeps each with probability 1/0.3/0.03, B=1024 h=2, 10k queries, "
+                                  "k=10, exact search (mode 0)"}, "rows": []}
+    for n_attrs, p in ((3, 1.0), (10, 0.3), (100, 0.03)):
+        t0 = time.perf_counter()
+        w = synth.make_wide(n_attrs, p, n=args.n, n_q=args.nq)
+        gen_s = time.perf_counter() - t0
+        dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+        t0 = time.perf_counter()
+        ix = caps.Index.from_workload(w, precision="bf16")
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        tid, _, _, tsurv = ix.search(*dq, k, w.n_partitions, counters=True)
+        truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+        curve = []
+        for m in (64, 256, 512, 768, 1024):
+            ids, _, nc, ns = ix.search(*dq, k, m, counters=True)
+            rec = float(recall10(ids.cpu().numpy(), truth, nvalid).mean())
+            sec = timed_search(ix, dq, k, m, args.steps, args.warmup)
+            curve.append({"nprobe": m, "recall@10": round(rec, 4), "queries_per_s": round(w.n_q / sec, 1),
+                          "cand_per_q": round(float(nc.float().mean()), 1),
+                          "surv_per_q": round(float(ns.float().mean()), 1)})
+        grid = [16, 32, 64, 128, 256, 384, 512, 640, 768, 896, 1024]
+        sweep = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid)
+        m = sweep[-1]["nprobe"]
+        sec = timed_search(ix, dq, k, m, args.steps, args.warmup)
+        row = {"L": n_attrs, "p_select": p, "constraints_per_q": round(float(np.diff(w.con_off).mean()), 3),
+               "mean_selectivity": round(float(nvalid.mean()) / w.n, 5), "label_slots": ix.info()["label_slots"],
+               "nprobe_at_0.9": m, "recall@10": sweep[-1]["recall@10"], "queries_per_s": round(w.n_q / sec, 1),
+               "build_s": round(build_s, 2), "gen_s": round(gen_s, 1), "curve": curve}
+        out["rows"].append(row)
+        log(f"[wide L={n_attrs}] {row}")
+        ix.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_c5(args, dev):
     """Serving (E5) at the serving configuration: 10M x 128 integer vectors
     stored with an FP16 copy, three dense attributes (10/50/200, Zipf 1.0)
@@ -548,7 +596,7 @@ def main():
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
-    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5"],
+    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide"],
                     help="headline: the benchmark line; ablation: AFT height and absence-fraction sweeps; "
                          "c3: precision mode on the 5M-point angular corpus")
     ap.add_argument("--c3-n", type=int, default=5_000_000)
@@ -583,6 +631,9 @@ def main():
         return
     if args.experiment == "c5":
         run_c5(args, dev)
+        return
+    if args.experiment == "wide":
+        run_wide(args, dev)
         return
 
     t0 = time.perf_counter()

@@ -8,7 +8,8 @@
  * points among D_C = { i : a_i satisfies every constraint of b }.
  * Attributes come in two kinds (Section 2 "Attribute Model", Table 1):
  *   dense:  L_dense attributes with one value each, value < vocab[attr];
- *   labels: a set of up to 8 distinct labels per point, label < label_vocab.
+ *   labels: a set of up to 128 distinct labels per point, label < label_vocab
+ *           (a query constrains at most 8 distinct labels).
  * A query constraint is a pair (attr, val): attr in [0, L_dense) names a
  * dense attribute, attr == L_dense names a label.  Constraints are ANDed;
  * unconstrained attributes match anything.
@@ -88,8 +89,9 @@ typedef struct {
  *   dense_vocab n_dense vocabulary sizes (>= 1); packed widths must total
  *              <= 32 bits (ceil(log2(vocab)) bits per attribute)
  *   label_off  n+1 int64 CSR offsets into labels, or NULL (no labels)
- *   labels     label ids < label_vocab <= 65535, at most 8 distinct per
- *              point (a repeated label is an error)
+ *   labels     label ids < label_vocab <= 65535, at most 128 distinct per
+ *              point (a repeated label is an error); sets of more than 8
+ *              labels widen every point's slot row to the next power of two
  *   stream     hipStream_t to run on (NULL = default stream); the call
  *              synchronises it before returning
  * k-means: init centroids at the sampled points; each iteration assigns
@@ -292,6 +294,9 @@ typedef struct {
     int32_t max_subpartition;   /* largest sub-partition size */
     int32_t precision;          /* CAPS_PREC_* of the low-precision copy */
     int32_t lowp_dpad;          /* row width of that copy (0 without one) */
+    int32_t label_slots;        /* label slots per point (8, or a power of two up to
+                                   128 when a point holds more labels; 0 without labels) */
+    int32_t reserved;
     int64_t device_bytes;       /* bytes the index holds on the device */
 } caps_index_info_t;
 

@@ -30,7 +30,7 @@ _SRC = os.path.join(_HERE, "caps_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-MAX_LABELS = 8   # labels a point may hold (larger sets are rejected at build)
+MAX_LABELS = 8   # distinct label constraints a query may hold (more: answered as empty)
 
 
 def build(force: bool = True) -> str:
@@ -142,8 +142,8 @@ def query_tokens(tk: Tokens, con_off, con_attr, con_val, disjunctive: bool = Fal
     if disjunctive:
         sep = a == -1
         tok = np.where(sep, -1, np.where(bad_pair, -2, tok))
-        # a point holds at most MAX_LABELS labels: a term asking for more
-        # distinct labels is unsatisfiable
+        # a term asking for more than MAX_LABELS distinct labels is outside
+        # the build's limits: unsatisfiable
         for qi in range(nq):
             lo, hi = int(con_off[qi]), int(con_off[qi + 1])
             start = lo
@@ -158,8 +158,8 @@ def query_tokens(tk: Tokens, con_off, con_attr, con_val, disjunctive: bool = Fal
     owner = np.repeat(np.arange(nq), np.diff(con_off))
     if len(a):
         np.maximum.at(q_bad, owner, bad_pair.astype(np.uint8))
-    # a point holds at most MAX_LABELS labels, so a query asking for more
-    # distinct labels has an empty D_C and chooses no sub-partition
+    # a query asking for more than MAX_LABELS distinct labels is outside the
+    # build's limits and answered as empty (it chooses no sub-partition)
     for qi in range(nq):
         lo, hi = con_off[qi], con_off[qi + 1]
         if len(set(v[lo:hi][is_lab[lo:hi]].tolist())) > MAX_LABELS:

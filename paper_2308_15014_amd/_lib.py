@@ -78,7 +78,7 @@ class IndexInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("d", c_i32), ("n_partitions", c_i32), ("aft_height", c_i32),
                 ("metric", c_i32), ("n_dense", c_i32), ("label_vocab", c_i32),
                 ("n_tokens", c_i32), ("max_subpartition", c_i32), ("precision", c_i32),
-                ("lowp_dpad", c_i32), ("device_bytes", c_i64)]
+                ("lowp_dpad", c_i32), ("label_slots", c_i32), ("reserved", c_i32), ("device_bytes", c_i64)]
 
 
 class Profile(ctypes.Structure):

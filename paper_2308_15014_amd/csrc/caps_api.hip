@@ -40,18 +40,19 @@ void release_index(Index &ix) {
 }
 
 // Points to add to an index with schema `sch`: finite vectors, dense
-// values inside their vocabularies, label sets of at most kMaxLabels
+// values inside their vocabularies, label sets of at most max_labels
 // distinct labels inside the label vocabulary (HOST arrays).
 static caps_status check_points(const char *who, const Schema &sch, const float *x, int64_t n, int32_t d,
-                                const uint32_t *dense_vals, const int64_t *label_off, const uint32_t *labels) {
+                                const uint32_t *dense_vals, const int64_t *label_off, const uint32_t *labels,
+                                int32_t max_labels = kMaxPointLabels) {
     const int32_t n_dense = sch.n_dense;
     if (label_off) {
         if (label_off[0] != 0) return fail(CAPS_EINVAL, "%s: label_off[0] != 0", who);
         for (int64_t i = 0; i < n; i++) {
             const int64_t lo = label_off[i], hi = label_off[i + 1];
             if (hi < lo) return fail(CAPS_EINVAL, "%s: label_off decreases at %lld", who, (long long)i);
-            if (hi - lo > kMaxLabels)
-                return fail(CAPS_EUNSUPPORTED, "%s: point %lld has more than %d labels", who, (long long)i, kMaxLabels);
+            if (hi - lo > max_labels)
+                return fail(CAPS_EUNSUPPORTED, "%s: point %lld has more than %d labels", who, (long long)i, max_labels);
             for (int64_t e = lo; e < hi; e++) {
                 if (labels[e] >= (uint32_t)sch.label_vocab)
                     return fail(CAPS_EINVAL, "%s: label %u outside vocabulary", who, labels[e]);
@@ -138,9 +139,17 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
         }
     }
 
+    // label slots per point: 8, or the next power of two above the largest set
+    int32_t lslots = kMaxLabels;
+    if (has_labels) {
+        int64_t mx = 0;
+        for (int64_t i = 0; i < n; i++) mx = std::max(mx, label_off[i + 1] - label_off[i]);
+        while (lslots < mx) lslots <<= 1;
+    }
     caps_index *h_idx = new (std::nothrow) caps_index;
     if (!h_idx) return fail(CAPS_ENOMEM, "caps_build: host allocation");
     Index &ix = h_idx->ix;
+    ix.lslots = lslots;
     CAPS_HIP(hipGetDevice(&ix.device));
     ix.n = n;
     ix.d = d;
@@ -255,6 +264,8 @@ extern "C" caps_status caps_index_info(const caps_index *idx, caps_index_info_t 
     out->max_subpartition = ix.max_sub;
     out->precision = ix.prec;
     out->lowp_dpad = ix.prec == CAPS_PREC_NONE ? 0 : ix.dpad;
+    out->label_slots = ix.sch.label_vocab > 0 ? ix.lslots : 0;
+    out->reserved = 0;
     out->device_bytes = ix.bytes;
     return CAPS_OK;
 }
@@ -302,7 +313,7 @@ extern "C" caps_status caps_insert(caps_index *idx, const float *x, int64_t n_ne
     if ((ix.sch.label_vocab > 0) != (label_off != nullptr))
         return fail(CAPS_EINVAL, "caps_insert: label sets must be given exactly when the index has labels");
     if (label_off && !labels && label_off[n_new] != 0) return fail(CAPS_EINVAL, "caps_insert: labels missing");
-    caps_status s = check_points("caps_insert", ix.sch, x, n_new, ix.d, dense_vals, label_off, labels);
+    caps_status s = check_points("caps_insert", ix.sch, x, n_new, ix.d, dense_vals, label_off, labels, ix.lslots);
     if (s != CAPS_OK) return s;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != ix.device)

@@ -352,7 +352,7 @@ __global__ void k_permute_vecs(const float *__restrict__ x, const int32_t *__res
 
 __global__ void k_permute_attrs(const int32_t *__restrict__ perm, int64_t n, Schema sch, AttrSrc src,
                                 uint32_t *__restrict__ words, uint64_t *__restrict__ sigs,
-                                uint16_t *__restrict__ slots) {
+                                uint16_t *__restrict__ slots, int32_t lslots) {
     int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= n) return;
     const int32_t id = perm[pos];
@@ -363,10 +363,12 @@ __global__ void k_permute_attrs(const int32_t *__restrict__ perm, int64_t n, Sch
         words[pos] = w;
     }
     if (sigs) {
-        uint16_t s[kMaxLabels];
+        // the point's labels sorted ascending (insertion into its own slot
+        // row), 0xFFFF padding after them
+        uint16_t *s = slots + pos * lslots;
         int c = 0;
         uint64_t sig = 0;
-        for (int64_t e = src.label_off[id]; e < src.label_off[id + 1] && c < kMaxLabels; e++) {
+        for (int64_t e = src.label_off[id]; e < src.label_off[id + 1] && c < lslots; e++) {
             const uint16_t l = (uint16_t)src.labels[e];
             sig |= 1ull << label_sig_bit(l);
             int i = c++;
@@ -376,9 +378,8 @@ __global__ void k_permute_attrs(const int32_t *__restrict__ perm, int64_t n, Sch
             }
             s[i] = l;
         }
-        for (int i = c; i < kMaxLabels; i++) s[i] = 0xFFFF;
+        for (int i = c; i < lslots; i++) s[i] = 0xFFFF;
         sigs[pos] = sig;
-        for (int i = 0; i < kMaxLabels; i++) slots[pos * kMaxLabels + i] = s[i];
     }
 }
 
@@ -521,7 +522,7 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
     if (sch.n_dense) CAPS_TRY(dalloc((void **)&ix->words, sizeof(uint32_t) * (size_t)n, &ix->bytes));
     if (has_labels) {
         CAPS_TRY(dalloc((void **)&ix->sigs, sizeof(uint64_t) * (size_t)n, &ix->bytes));
-        CAPS_TRY(dalloc((void **)&ix->slots, sizeof(uint16_t) * (size_t)n * kMaxLabels, &ix->bytes));
+        CAPS_TRY(dalloc((void **)&ix->slots, sizeof(uint16_t) * (size_t)n * ix->lslots, &ix->bytes));
     }
 
     const int32_t nblk = (int32_t)((n + kSortBlock - 1) / kSortBlock);
@@ -567,7 +568,7 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
         hipLaunchKernelGGL(k_permute_vecs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X,
                            ix->perm, n, d, ix->vecs);
         hipLaunchKernelGGL(k_permute_attrs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ix->perm,
-                           n, sch, src, ix->words, ix->sigs, ix->slots);
+                           n, sch, src, ix->words, ix->sigs, ix->slots, ix->lslots);
         CAPS_HIP(hipGetLastError());
     }
     ix->h_offs.resize((size_t)b * (h + 1) + 1);
@@ -697,11 +698,11 @@ caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32
     if (ix->words) CAPS_HIP(hipMalloc(&fwords.p, sizeof(uint32_t) * (size_t)n_new));
     if (ix->sigs) {
         CAPS_HIP(hipMalloc(&fsigs.p, sizeof(uint64_t) * (size_t)n_new));
-        CAPS_HIP(hipMalloc(&fslots.p, sizeof(uint16_t) * (size_t)n_new * kMaxLabels));
+        CAPS_HIP(hipMalloc(&fslots.p, sizeof(uint16_t) * (size_t)n_new * ix->lslots));
     }
     hipLaunchKernelGGL(k_permute_attrs, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, st,
                        (const int32_t *)diota.p, n_new, sch, src, (uint32_t *)fwords.p, (uint64_t *)fsigs.p,
-                       (uint16_t *)fslots.p);
+                       (uint16_t *)fslots.p, ix->lslots);
     CAPS_HIP(hipGetLastError());
     const size_t eb = ix->prec == CAPS_PREC_FP8 ? 1 : 2;
     if (ix->prec != CAPS_PREC_NONE) {
@@ -717,7 +718,7 @@ caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32
     CAPS_TRY(relayout((void **)&ix->vecs, sizeof(float) * (size_t)d, dx.p));
     CAPS_TRY(relayout((void **)&ix->words, sizeof(uint32_t), fwords.p));
     CAPS_TRY(relayout((void **)&ix->sigs, sizeof(uint64_t), fsigs.p));
-    CAPS_TRY(relayout((void **)&ix->slots, sizeof(uint16_t) * kMaxLabels, fslots.p));
+    CAPS_TRY(relayout((void **)&ix->slots, sizeof(uint16_t) * ix->lslots, fslots.p));
     CAPS_TRY(relayout(&ix->lvecs, (size_t)ix->dpad * eb, flvec.p));
     CAPS_TRY(relayout((void **)&ix->lscale, sizeof(float), fscale.p));
     CAPS_TRY(relayout((void **)&ix->xnorm, sizeof(float), fxn.p));

@@ -105,18 +105,32 @@ __device__ inline uint64_t wave_match(uint32_t key, int nbits) {
     return peers;
 }
 
+// Whether a point's sorted label slots (ns of them, 0xFFFF padded) hold v:
+// a comparison with each of 8 slots, a binary search over wider rows.
+__device__ inline bool slots_hold(const uint16_t *sl, int ns, uint16_t v) {
+    if (ns <= kMaxLabels) {
+        bool f = false;
+#pragma unroll
+        for (int s = 0; s < kMaxLabels; s++) f |= sl[s] == v;
+        return f;
+    }
+    int lo = 0, hi = ns;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sl[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < ns && sl[lo] == v;
+}
+
 // Exact filter of one point against one query (Definition 1 with wildcards).
 __device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_labels, uint32_t w,
-                                    uint64_t sig, const uint16_t *sl) {
+                                    uint64_t sig, const uint16_t *sl, int ns = kMaxLabels) {
     if (has_dense && ((w & qd.dmask) != qd.dval)) return false;
     if (has_labels && qd.nlab > 0) {
         if (qd.lsig & ~sig) return false;
-        for (int i = 0; i < qd.nlab; i++) {
-            bool f = false;
-#pragma unroll
-            for (int s = 0; s < kMaxLabels; s++) f |= sl[s] == qd.lab[i];
-            if (!f) return false;
-        }
+        for (int i = 0; i < qd.nlab; i++)
+            if (!slots_hold(sl, ns, qd.lab[i])) return false;
     }
     return true;
 }
@@ -124,13 +138,13 @@ __device__ inline bool point_passes(const QDesc &qd, bool has_dense, bool has_la
 // Filter of one point against a query (summary descriptor qd; `terms`: the
 // query's term descriptors, read only for a disjunction): some term passes.
 __device__ inline bool query_passes(const QDesc &qd, const QDesc *terms, bool has_dense, bool has_labels, uint32_t w,
-                                    uint64_t sig, const uint16_t *sl) {
+                                    uint64_t sig, const uint16_t *sl, int ns = kMaxLabels) {
     if (qd.flags & kQOr) {
         for (int t = 0; t < qd.nterm; t++)
-            if (point_passes(terms[t], has_dense, has_labels, w, sig, sl)) return true;
+            if (point_passes(terms[t], has_dense, has_labels, w, sig, sl, ns)) return true;
         return false;
     }
-    return point_passes(qd, has_dense, has_labels, w, sig, sl);
+    return point_passes(qd, has_dense, has_labels, w, sig, sl, ns);
 }
 
 __device__ inline void wave_sync() {

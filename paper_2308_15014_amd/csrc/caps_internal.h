@@ -12,7 +12,8 @@
 namespace caps {
 
 constexpr int kMaxDense = 8;        // dense attributes per point
-constexpr int kMaxLabels = 8;       // labels per point / distinct labels per query
+constexpr int kMaxLabels = 8;       // distinct labels per query; label slots of a narrow point
+constexpr int kMaxPointLabels = 128; // labels per point (wide slot rows above kMaxLabels)
 constexpr int kMaxHeight = 15;      // AFT height
 constexpr int kMaxPartitions = 8192;
 constexpr int kMaxTokensLds = 16384;  // token vocabulary the AFT histogram holds in LDS
@@ -78,7 +79,8 @@ struct Index {
     int8_t *level = nullptr;    // n (original order)
     uint32_t *words = nullptr;  // n packed dense words, CSR order (n_dense > 0)
     uint64_t *sigs = nullptr;   // n label signatures, CSR order (labels)
-    uint16_t *slots = nullptr;  // n x kMaxLabels sorted labels, 0xFFFF padded
+    uint16_t *slots = nullptr;  // n x lslots sorted labels, 0xFFFF padded
+    int32_t lslots = kMaxLabels; // label slots per point: 8, or a power of two up to 128 for wider sets
     float *vecs = nullptr;      // n x d, CSR order
     // low-precision copy for the matrix-core scan (search mode 1)
     int32_t prec = 0;           // CAPS_PREC_*

@@ -2,9 +2,9 @@
 // little-endian blob.
 //
 //   "CAPSIDX1"  magic (8 bytes)
-//   u32 version (1), u32 header bytes, then the header: n (i64), d, b, h,
+//   u32 version (2), u32 header bytes, then the header: n (i64), d, b, h,
 //   metric, precision, dpad, max_sub (i32), the attribute schema (i32
-//   fields in declaration order), has_router (i32)
+//   fields in declaration order), has_router, label slots per point (i32)
 //   arrays: u32 tag, u64 bytes, payload -- in the fixed order of `arrays()`,
 //   absent ones with 0 bytes
 //   router (if present): din, dpad, hid, nout (i32), in_scale, in_shift,
@@ -25,7 +25,7 @@
 namespace caps {
 
 static const char kMagic[8] = {'C', 'A', 'P', 'S', 'I', 'D', 'X', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct ArrayRef {
     uint32_t tag;
@@ -48,7 +48,7 @@ static std::vector<ArrayRef> arrays(Index &ix) {
         {8, (void **)&ix.vecs, 4 * n * d},
         {9, (void **)&ix.words, dense ? 4 * n : 0},
         {10, (void **)&ix.sigs, lab ? 8 * n : 0},
-        {11, (void **)&ix.slots, lab ? 2 * n * kMaxLabels : 0},
+        {11, (void **)&ix.slots, lab ? 2 * n * (size_t)ix.lslots : 0},
         {12, (void **)&ix.lvecs, lowp ? n * (size_t)ix.dpad * es : 0},
         {13, (void **)&ix.lscale, ix.prec == CAPS_PREC_FP8 ? 4 * n : 0},
         {14, (void **)&ix.xnorm, lowp ? 4 * n : 0},
@@ -72,6 +72,7 @@ struct Header {
     int32_t d, b, h, metric, prec, dpad, max_sub;
     Schema sch;
     int32_t has_router;
+    int32_t lslots;
 };
 
 static caps_status io_fail(const char *what, const char *path) {
@@ -96,6 +97,7 @@ static caps_status save(const Index &cix, const char *path) {
     hd.max_sub = ix.max_sub;
     hd.sch = ix.sch;
     hd.has_router = ix.router ? 1 : 0;
+    hd.lslots = ix.lslots;
     const uint32_t hb = sizeof(Header);
     bool ok = put(F.f, kMagic, 8) && put(F.f, &kVersion, 4) && put(F.f, &hb, 4) && put(F.f, &hd, sizeof hd);
     std::vector<uint8_t> host;
@@ -220,6 +222,9 @@ static caps_status load(Index &ix, const char *path) {
     ix.dpad = hd.dpad;
     ix.max_sub = hd.max_sub;
     ix.sch = hd.sch;
+    if (hd.lslots < kMaxLabels || hd.lslots > kMaxPointLabels || (hd.lslots & (hd.lslots - 1)))
+        return io_fail("caps_load: label slot width out of range", path);
+    ix.lslots = hd.lslots;
     std::vector<uint8_t> host;
     std::vector<int32_t> tags, offs, perm, assign;
     std::vector<int8_t> level;

@@ -25,6 +25,7 @@ struct LowpArgs {
     const uint32_t *words;
     const uint64_t *sigs;
     const uint16_t *slots;
+    int32_t lslots;             // label slots per point
     const uint8_t *qlow;        // query rows of dpad elements
     const float *qscale, *qaux;
     const float *vecs, *q;      // FP32 CSR rows and queries (exact rescoring)
@@ -548,9 +549,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         const QDesc &qd = qds[qi];
         if (qd.flags & kQOr)
             return query_passes(qd, A.qterms + (int64_t)(qslot[qi] / A.m) * kMaxTerms, has_dense, has_lab, pw,
-                                has_lab ? A.sigs[pos] : 0ull, has_lab ? A.slots + pos * kMaxLabels : nullptr);
+                                has_lab ? A.sigs[pos] : 0ull, has_lab ? A.slots + pos * A.lslots : nullptr, A.lslots);
         if (!has_lab) return true;
-        return point_passes(qd, false, true, 0u, A.sigs[pos], A.slots + pos * kMaxLabels);
+        return point_passes(qd, false, true, 0u, A.sigs[pos], A.slots + pos * A.lslots, A.lslots);
     };
 
     int cj = -1;

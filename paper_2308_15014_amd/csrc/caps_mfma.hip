@@ -420,6 +420,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.words = ix->words;
     A.sigs = ix->sigs;
     A.slots = ix->slots;
+    A.lslots = ix->lslots;
     A.qlow = reinterpret_cast<const uint8_t *>(S.qlow);
     A.qscale = S.qscale;
     A.qaux = S.qaux;

@@ -749,6 +749,7 @@ struct ScanArgs {
     const uint32_t *words;
     const uint64_t *sigs;
     const uint16_t *slots;
+    int32_t lslots;       // label slots per point (rows wider than kMaxLabels are read from global memory)
     uint64_t *partials;
     uint64_t *tau;        // per query: shared upper bound on its final k-th key
     int32_t *nsurv;
@@ -820,7 +821,7 @@ __device__ __attribute__((always_inline)) inline void fetch_chunk(
     pw = wsrc[r];
     if (HAS_LABELS) {
         psig = A.sigs[r];
-        pslot = *reinterpret_cast<const uint4 *>(A.slots + (int64_t)r * kMaxLabels);
+        pslot = *reinterpret_cast<const uint4 *>(A.slots + (int64_t)r * A.lslots);   // (narrow rows only used)
     }
 }
 
@@ -1076,8 +1077,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, 2)))
             bool pass;
             if (HAS_LABELS || (qds[qbase + i].flags & kQOr)) {
                 const QDesc *terms = A.qterms + (int64_t)(qslot[qbase + i] / A.m) * kMaxTerms;
-                pass = lane_ok && query_passes(qds[qbase + i], terms, has_dense, HAS_LABELS, myw, mysig,
-                                               xslot + lane * kMaxLabels);
+                const bool wide = A.lslots > kMaxLabels;
+                const uint16_t *sl = wide ? A.slots + (int64_t)(c0 + min(lane, cn - 1)) * A.lslots
+                                          : xslot + lane * kMaxLabels;
+                pass = lane_ok && query_passes(qds[qbase + i], terms, has_dense, HAS_LABELS, myw, mysig, sl,
+                                               A.lslots);
             } else {
                 const uint32_t dm = __builtin_amdgcn_readlane(my_dmask, i);
                 const uint32_t dv = __builtin_amdgcn_readlane(my_dval, i);
@@ -1416,8 +1420,8 @@ __global__ __launch_bounds__(256) void k_surv_mask(const int32_t *__restrict__ p
                                                    const QDesc *__restrict__ qterms,
                                                    const int32_t *__restrict__ offs, int32_t h,
                                                    const uint32_t *__restrict__ words, const uint64_t *__restrict__ sigs,
-                                                   const uint16_t *__restrict__ slots, uint64_t *__restrict__ mask,
-                                                   int64_t mask_words) {
+                                                   const uint16_t *__restrict__ slots, int32_t lslots,
+                                                   uint64_t *__restrict__ mask, int64_t mask_words) {
     const int lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= (int64_t)nq * m) return;
@@ -1432,7 +1436,7 @@ __global__ __launch_bounds__(256) void k_surv_mask(const int32_t *__restrict__ p
         for (int32_t pos = lo + lane; pos < hi; pos += 64) {
             const bool pass = query_passes(Q, qterms + qi * kMaxTerms, words != nullptr, sigs != nullptr,
                                            words ? words[pos] : 0u, sigs ? sigs[pos] : 0ull,
-                                           slots ? slots + (int64_t)pos * kMaxLabels : nullptr);
+                                           slots ? slots + (int64_t)pos * lslots : nullptr, lslots);
             if (pass) atomicOr((unsigned long long *)(mask + qi * mask_words + pos / 64), 1ull << (pos % 64));
         }
     }
@@ -1588,7 +1592,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             }
             if (ex.surv_mask)
                 hipLaunchKernelGGL(k_surv_mask, dim3(nblocks(pairs, 4)), dim3(256), 0, st, probes, sel, nb, m, qd, W.qterms, ix->offs,
-                                   h, ix->words, ix->sigs, ix->slots, ex.surv_mask + (int64_t)q0 * mask_words, mask_words);
+                                   h, ix->words, ix->sigs, ix->slots, ix->lslots, ex.surv_mask + (int64_t)q0 * mask_words,
+                               mask_words);
             hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nb, 256)), dim3(256), 0, st, tau, (int64_t)nb, ~0ull);
             if (P.defer) {
                 hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb, 256)), dim3(256), 0, st, W.dcnt, (int64_t)nb, 0);
@@ -1692,6 +1697,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     A.words = ix->words;
                     A.sigs = ix->sigs;
                     A.slots = ix->slots;
+                    A.lslots = ix->lslots;
                     A.partials = partials;
                     A.tau = tau;
                     A.nsurv = nsurv + q0;

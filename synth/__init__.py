@@ -155,6 +155,59 @@ class _LabelCounter:
         return cur
 
 
+class _BitCounter:
+    """|{i : every pair (attr, val) holds}| for dense values and labels from
+    packed bitsets: one per dense value and per label with a long posting
+    list; a pair set with a short posting list is counted by testing those
+    ids against the other pairs' bitsets.  (Used only to keep queries inside
+    a selectivity band; the counts equal a direct evaluation.)"""
+
+    def __init__(self, dense, vocabs, off, labels, n, long_posting=20_000):
+        self.n, self.nd = n, len(vocabs)
+        self.words = (n + 63) // 64
+        self.dense_bits = {}
+        for a, v in enumerate(vocabs):
+            col = dense[:, a]
+            for val in range(v):
+                self.dense_bits[(a, val)] = self._pack(np.flatnonzero(col == val))
+        self.lab = _LabelCounter(off, labels, n)
+        counts = np.bincount(labels, minlength=int(labels.max()) + 1 if len(labels) else 1)
+        self.label_bits = {int(l): self._pack(self.lab.posting(l)) for l in np.flatnonzero(counts >= long_posting)}
+
+    def _pack(self, ids):
+        bits = np.zeros(self.words * 64, dtype=bool)
+        bits[ids] = True
+        return np.packbits(bits, bitorder="little").view(np.uint64)
+
+    def _bits(self, a, v):
+        return self.dense_bits[(a, v)] if a < self.nd else self.label_bits.get(v)
+
+    def count(self, pairs):
+        pairs = list(dict.fromkeys(pairs))
+        dense_vals = {}
+        for a, v in pairs:
+            if a < self.nd:
+                if dense_vals.setdefault(a, v) != v:
+                    return 0
+        short = [v for a, v in pairs if a >= self.nd and v not in self.label_bits]
+        if short:
+            ids = self.lab.ids(short)
+            if ids.size == 0:
+                return 0
+            keep = np.ones(ids.size, dtype=bool)
+            for a, v in pairs:
+                if a >= self.nd and v in short:
+                    continue
+                b = self._bits(a, v)
+                keep &= ((b[ids >> 6] >> (ids & 63).astype(np.uint64)) & np.uint64(1)).astype(bool)
+            return int(keep.sum())
+        acc = None
+        for a, v in pairs:
+            b = self._bits(a, v)
+            acc = b.copy() if acc is None else acc & b
+        return self.n if acc is None else int(np.bitwise_count(acc).sum())
+
+
 def draw_constraints(rng, n_q, n, dense, label_off, labels, cmin, cmax,
                      band=None, counter=None):
     """Each query copies c ~ U{cmin..cmax} attributes (dense values and/or
@@ -368,25 +421,42 @@ def make_c5(n=10_000_000, n_q=10_000, seed=None, n_partitions=8192,
     dense = draw_dense(ra, n, vocab, 1.0)
     off, labels = draw_label_sets(ra, n, 5000, 1.1)
     q = rq.integers(0, 256, size=(n_q, d), dtype=np.int32).astype(np.float32)
-    dc = _DenseCounter(dense, vocab)
-    lc = _LabelCounter(off, labels, n)
-
-    def count(pairs):
-        dp = [(a, v) for a, v in pairs if a < 3]
-        lp = [v for a, v in pairs if a == 3]
-        if not lp:
-            return dc.count(dp)
-        ids = lc.ids(lp)
-        if ids.size == 0:
-            return 0
-        m = np.ones(ids.size, dtype=bool)
-        for a, v in dp:
-            m &= dense[ids, a] == v
-        return int(m.sum())
-
-    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, off, labels, 1, 4, band, count)
+    cnt = _BitCounter(dense, vocab, off, labels, n)
+    co, ca, cv, sel = draw_constraints(rc, n_q, n, dense, off, labels, 1, 4, band, cnt.count)
     return Workload("c5", x, dense, vocab, off, labels, 5000, q, co, ca, cv, 0,
                     n_partitions, 4, 10, 10, 64, seed, sel)
+
+
+def make_wide(n_attrs, p_select, n=1_000_000, n_q=10_000, seed=None, vocab=10, n_partitions=1024,
+              max_constraints=8) -> Workload:
+    """Larger attribute lengths (the paper's appendix, L = 3 / 10 / 100 with
+    per-query selection probability 1 / 0.3 / 0.03) as a label-style
+    workload at the 1M-point scale: c2's integer vectors; every point holds
+    L attributes, attribute a with a value v ~ Zipf(1.0) over `vocab`,
+    stored as label a * vocab + v (so each point has exactly L labels).  A
+    query copies the attributes of a random database point and keeps each
+    with probability `p_select` (drawn again when more than
+    `max_constraints` are kept).  B=1024, h=2."""
+    seed = BASE_SEED + 7 + n_attrs if seed is None else seed
+    base = make_c2(n=n, n_q=1)
+    _rv, ra, rq, rc = _streams(seed)
+    vals = draw_dense(ra, n, [vocab] * n_attrs, 1.0).astype(np.int64)
+    labels = (vals + vocab * np.arange(n_attrs)[None, :]).astype(np.uint32).reshape(-1)
+    off = (np.arange(n + 1, dtype=np.int64) * n_attrs)
+    q = rq.integers(0, 256, size=(n_q, base.d), dtype=np.int32).astype(np.float32)
+    co, ca, cv = [0], [], []
+    for _ in range(n_q):
+        pt = int(rc.integers(n))
+        while True:
+            keep = np.flatnonzero(rc.random(n_attrs) < p_select)
+            if len(keep) <= max_constraints:
+                break
+        ca.extend([0] * len(keep))
+        cv.extend(labels[pt * n_attrs + keep].tolist())
+        co.append(len(ca))
+    return Workload(f"wide{n_attrs}", base.x, None, [], off, labels, vocab * n_attrs, q,
+                    np.asarray(co, np.int32), np.asarray(ca, np.int32), np.asarray(cv, np.int32), 0,
+                    n_partitions, 2, 10, 10, 32, seed, None)
 
 
 def make_c5_queries(n_q, seed, base: Workload):
