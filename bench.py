@@ -574,6 +574,105 @@ def run_c5(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_router(args, dev):
+    """Learned routing (BLISS-style filtered labels, Section 5.2) on the
+    1M-point corpus, B = 1024: a 192-1024-1024 router trained on the GPU on
+    queries labelled with the partitions of their exact filtered top-10, with
+    a cosine-decayed learning rate (one call per epoch, moments kept).  Two
+    peak rates are trained and the one with the lower held-out loss is kept.
+    Reports the loss per epoch against ln B, recall@10 at fixed nprobe for the
+    router and for centroid routing, nprobe and queries/s at recall 0.9 for
+    both, and the router's inference time on the 10k-query batch."""
+    import math
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k = 10
+    w = synth.make_c2(n=args.n, n_q=args.nq)
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    ix = caps.Index.from_workload(w, precision="bf16")
+    B = w.n_partitions
+    tid, _, _, tsurv = ix.search(*dq, k, B, counters=True)
+    truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+    n_tr, n_ho = args.router_train, 20_000
+    t0 = time.perf_counter()
+    rq, rco, rca, rcv = synth.make_c2_train_queries(n_tr + n_ho, 2308_15014 + 40, w)
+    gen_s = time.perf_counter() - t0
+    tq = torch.from_numpy(rq).to(dev)
+    tco, tca, tcv = (torch.from_numpy(a).to(dev) for a in (rco, rca, rcv))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rids, _ = ix.search(tq, tco, tca, tcv, k, B)
+    labels = ix.router_labels(rids)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    del rids
+    lsz = (labels >= 0).sum(dim=1).float()
+    label_floor = float(torch.log(lsz.clamp(min=1)).mean())
+    # training rows: the first n_tr; held out: the last n_ho (rows and constraints)
+    e_tr = int(rco[n_tr])
+    tr = (tq[:n_tr], tco[:n_tr + 1], tca[:e_tr], tcv[:e_tr])
+    ho = (tq[n_tr:], tco[n_tr:] - e_tr, tca[e_tr:], tcv[e_tr:])
+    lab_tr, lab_ho = labels[:n_tr].contiguous(), labels[n_tr:].contiguous()
+    epochs = args.router_epochs
+    runs = []
+    best = None
+    for lr0 in (1e-3, 3e-3):
+        losses, held = [], []
+        t0 = time.perf_counter()
+        for e in range(epochs):
+            lr = lr0 * 0.5 * (1.0 + math.cos(math.pi * e / epochs))
+            losses.append(float(ix.router_train(*tr, lab_tr, hidden=1024, epochs=1, batch=4096, lr=lr,
+                                                reset=1 if e == 0 else 0, in_scale=1.0 / 255.0,
+                                                in_shift=-0.5, seed=11)[0]))
+            held.append(ix.router_grads(*ho, lab_ho)[0])
+        torch.cuda.synchronize()
+        run = {"lr_peak": lr0, "schedule": "cosine over epochs", "train_s": round(time.perf_counter() - t0, 2),
+               "loss_per_epoch": [round(x, 4) for x in losses], "held_out_loss": [round(x, 4) for x in held]}
+        log(f"[router lr={lr0}] {run}")
+        runs.append(run)
+        if best is None or held[-1] < best[0]:
+            best = (held[-1], lr0, ix.router_get())
+    wts = best[2]
+    ix.router_set(wts["w1"], wts["b1"], wts["w2"], wts["b2"], hidden=1024, in_scale=1.0 / 255.0, in_shift=-0.5)
+    grid = [16, 32, 64, 128, 256, 384, 512] + list(range(576, 704, 16)) + [768, 896, 1024]
+    fixed = []
+    for m in (16, 32, 64, 128, 256, 512):
+        row = {"nprobe": m}
+        for name, routing in (("centroid", 0), ("router", 1)):
+            ids, _, nc, _ = ix.search(*dq, k, m, routing=routing, counters=True)
+            row[f"recall@10_{name}"] = round(float(recall10(ids.cpu().numpy(), truth, nvalid).mean()), 4)
+            row[f"cand_per_q_{name}"] = round(float(nc.float().mean()), 1)
+        fixed.append(row)
+        log(f"[router fixed] {row}")
+    at_target = {}
+    for name, routing in (("centroid", 0), ("router", 1)):
+        rows = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid, routing=routing)
+        m = rows[-1]["nprobe"]
+        sec = timed_search(ix, dq, k, m, args.steps, args.warmup, routing=routing)
+        at_target[name] = {"nprobe": m, "recall@10": rows[-1]["recall@10"], "queries_per_s": round(w.n_q / sec, 1),
+                           "ms_per_batch": round(sec * 1e3, 4)}
+        log(f"[router at 0.9] {name} {at_target[name]}")
+    # inference: logits of the 10k-query batch (input rows + two GEMMs)
+    ix.router_logits(*dq)
+    med, _ = event_median(lambda: ix.router_logits(*dq), 20)
+    flops = 2.0 * w.n_q * (ix.router_info()["dpad"] * 1024 + 1024 * B)
+    infer = {"queries": w.n_q, "ms_median": round(med, 4), "tflop_per_s": round(flops / med / 1e9, 1),
+             "bf16_peak_frac": round(flops / med / 1e9 / MFMA_BF16_PEAK, 4)}
+    log(f"[router inference] {infer}")
+    out = {"metric": "learned router vs centroid routing: recall@10 at fixed nprobe, queries/s at recall 0.9",
+           "config": {"workload": "c2 1M x 128 uniform integer vectors, 3 dense attributes, B=1024 h=2, "
+                                  "10k queries, k=10, exact search (mode 0)",
+                      "router": "192-1024-1024 (BF16 products, FP32 masters, Adam)",
+                      "train_queries": n_tr, "held_out_queries": n_ho, "epochs": epochs,
+                      "gen_s": round(gen_s, 1), "label_s": round(label_s, 2)},
+           "ln_B": round(math.log(B), 4), "label_entropy_floor": round(label_floor, 4),
+           "mean_labels_per_query": round(float(lsz.mean()), 3),
+           "runs": runs, "kept_lr_peak": best[1], "fixed_nprobe": fixed, "at_recall_0.9": at_target,
+           "inference": infer}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -596,7 +695,7 @@ def main():
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
-    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide"],
+    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide", "router"],
                     help="headline: the benchmark line; ablation: AFT height and absence-fraction sweeps; "
                          "c3: precision mode on the 5M-point angular corpus")
     ap.add_argument("--c3-n", type=int, default=5_000_000)
@@ -634,6 +733,9 @@ def main():
         return
     if args.experiment == "wide":
         run_wide(args, dev)
+        return
+    if args.experiment == "router":
+        run_router(args, dev)
         return
 
     t0 = time.perf_counter()

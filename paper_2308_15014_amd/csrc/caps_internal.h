@@ -159,9 +159,10 @@ void prof_end(int stage, hipStream_t st);
 // ---- low-precision path (caps_mfma.hip)
 caps_status build_lowp(Index *ix, hipStream_t st);
 caps_status build_lowp_centroids(Index *ix, hipStream_t st);
-// precision-mode routing: scores of nb rounded queries against the centroid copy
+// precision-mode routing: scores of nb rounded queries against the centroid
+// copy; with a row list, score row r belongs to query rows[r], r < *nrows
 caps_status lowp_route(const Index *ix, const void *qlow, const float *qscale, int32_t nb, float *scores,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t *rows = nullptr, const int32_t *nrows = nullptr);
 caps_status lowp_qquant(const Index *ix, const float *q, int32_t nb, void *qlow, float *qscale, float *qaux,
                         hipStream_t st);
 // low-precision rows (and their FP32 norms and error norms) of n FP32 rows
@@ -212,11 +213,15 @@ caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32
 caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int32_t *con_off,
                           const int32_t *con_attr, const int32_t *con_val, int32_t n_con, uint16_t *X,
                           uint16_t *H, float *scores, float *conf, hipStream_t st);
-// per query: keep the router's probes unless its top-1 probability is below
-// the fallback level or its probes hold fewer than k candidates, else copy
-// the centroid probes
-caps_status router_fallback(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
-                            const int32_t *cand, const int32_t *probes_c, int32_t *probes, hipStream_t st);
+// Lists the queries whose router probes fall back to centroid routing (top-1
+// probability below the fallback level, or fewer than k candidates in the
+// router's probes): fbq[0 .. *nfb), in no particular order.
+caps_status router_fallback_list(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
+                                 const int32_t *cand, int32_t *fbq, int32_t *nfb, hipStream_t st);
+// Copies row r of probes_c (the centroid probes of query fbq[r]) over that
+// query's probes, for r < *nfb.
+caps_status router_fallback_apply(int32_t nb, int32_t m, const int32_t *fbq, const int32_t *nfb,
+                                  const int32_t *probes_c, int32_t *probes, hipStream_t st);
 
 }  // namespace caps
 

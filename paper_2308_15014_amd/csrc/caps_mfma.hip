@@ -238,17 +238,22 @@ template <int PREC, int NS>
 __global__ __launch_bounds__(256) void k_route_mfma(const uint8_t *__restrict__ qlow, const float *__restrict__ qscale,
                                                     int32_t nq, const uint8_t *__restrict__ clow,
                                                     const float *__restrict__ cscale, const float *__restrict__ cn,
-                                                    int32_t b, int32_t metric, float *__restrict__ scores) {
+                                                    int32_t b, int32_t metric, float *__restrict__ scores,
+                                                    const int32_t *__restrict__ rows,
+                                                    const int32_t *__restrict__ nrows) {
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
     constexpr int ES = Op::ES;
     constexpr int KSTEP_BYTES = 32 * ES, LANE_BYTES = 8 * ES, ROWB = NS * KSTEP_BYTES;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (nrows) nq = min(nq, *nrows);
+    if ((int64_t)blockIdx.x * 64 >= nq) return;
     const int64_t q0 = (int64_t)blockIdx.x * 64 + 16 * w;
     const int c0 = blockIdx.y * 64;
     const int64_t arow = q0 + (lane & 15);
     const bool aok = arow < nq;
-    const uint8_t *asrc = qlow + (aok ? arow : 0) * ROWB + (lane >> 4) * LANE_BYTES;
+    const int64_t asrc_row = aok ? (rows ? (int64_t)rows[arow] : arow) : 0;
+    const uint8_t *asrc = qlow + asrc_row * ROWB + (lane >> 4) * LANE_BYTES;
     f32x4 acc[4];
 #pragma unroll
     for (int bb = 0; bb < 4; bb++) acc[bb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(256) void k_route_mfma(const uint8_t *__restrict__ 
             const int64_t q = q0 + (lane >> 4) * 4 + rr;
             if (q >= nq) continue;
             float dd = acc[bb][rr];
-            if (PREC == CAPS_PREC_FP8) dd = dd * qscale[q] * cs;
+            if (PREC == CAPS_PREC_FP8) dd = dd * qscale[rows ? (int64_t)rows[q] : q] * cs;
             scores[q * b + c] = canon0(metric == 0 ? fmaf(-2.0f, dd, cn[c]) : -dd);
         }
     }
@@ -283,27 +288,31 @@ __global__ __launch_bounds__(256) void k_route_mfma(const uint8_t *__restrict__ 
 template <int PREC>
 static void launch_route(int ns, dim3 g, hipStream_t st, const uint8_t *qlow, const float *qscale, int32_t nq,
                          const uint8_t *clow, const float *cscale, const float *cn, int32_t b, int32_t metric,
-                         float *scores) {
+                         float *scores, const int32_t *rows, const int32_t *nrows) {
     switch (ns) {
-    case 1: hipLaunchKernelGGL((k_route_mfma<PREC, 1>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
-    case 2: hipLaunchKernelGGL((k_route_mfma<PREC, 2>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
-    case 4: hipLaunchKernelGGL((k_route_mfma<PREC, 4>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
-    default: hipLaunchKernelGGL((k_route_mfma<PREC, 8>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores); return;
+    case 1: hipLaunchKernelGGL((k_route_mfma<PREC, 1>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores, rows, nrows); return;
+    case 2: hipLaunchKernelGGL((k_route_mfma<PREC, 2>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores, rows, nrows); return;
+    case 4: hipLaunchKernelGGL((k_route_mfma<PREC, 4>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores, rows, nrows); return;
+    default: hipLaunchKernelGGL((k_route_mfma<PREC, 8>), g, dim3(256), 0, st, qlow, qscale, nq, clow, cscale, cn, b, metric, scores, rows, nrows); return;
     }
 }
 
 // Scores of nb rounded queries (k_qquant output) against the centroid copy.
+// With a row list, score row r belongs to query rows[r], for r < *nrows.
 caps_status lowp_route(const Index *ix, const void *qlow, const float *qscale, int32_t nb, float *scores,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t *rows, const int32_t *nrows) {
     const dim3 g((unsigned)((nb + 63) / 64), (unsigned)((ix->b + 63) / 64));
     const uint8_t *q = reinterpret_cast<const uint8_t *>(qlow), *c = reinterpret_cast<const uint8_t *>(ix->clow);
     const int ns = ix->dpad / 32;
     if (ix->prec == CAPS_PREC_BF16)
-        launch_route<CAPS_PREC_BF16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+        launch_route<CAPS_PREC_BF16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores,
+                                     rows, nrows);
     else if (ix->prec == CAPS_PREC_FP16)
-        launch_route<CAPS_PREC_FP16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+        launch_route<CAPS_PREC_FP16>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores,
+                                     rows, nrows);
     else
-        launch_route<CAPS_PREC_FP8>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores);
+        launch_route<CAPS_PREC_FP8>(ns, g, st, q, qscale, nb, c, ix->cscale, ix->cnorm, ix->b, ix->metric, scores,
+                                    rows, nrows);
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;
 }

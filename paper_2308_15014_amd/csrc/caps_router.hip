@@ -73,90 +73,54 @@ __global__ __launch_bounds__(64) void k_router_input(const float *__restrict__ q
 
 // ------------------------------------------------------------------ GEMM (K11, K12)
 // C[m][n] = sum_k A(m, k) B(n, k), A(m, k) = A[m*sam + k*sak], B(n, k) =
-// B[n*sbn + k*sbk] (BF16), FP32 accumulation.  64 x 64 tile per workgroup,
-// four waves of 32 x 32 (2 x 2 MFMA blocks), K in steps of 32 through LDS.
+// B[n*sbn + k*sbk] (BF16), FP32 accumulation.  128 x 128 tile per
+// workgroup, four waves of 64 x 64 (4 x 4 blocks of
+// v_mfma_f32_16x16x32_bf16), K in steps of 64 through LDS.
+// Tiles are numbered in groups of kGroupM row tiles (every column tile of a
+// group before the next group), and when the tile count divides evenly each
+// XCD (workgroups are dealt to the 8 dies in turn) takes one contiguous range
+// of that order, so a die's working set of rows and columns stays in its L2.
 // Epilogue: + bias[n], ReLU, zero where mask(m, n) <= 0 (a BF16 array with
 // leading dimension ldm), negation (scores, smaller is better); written as
 // FP32 and/or BF16 with leading dimension ldc.
+//
+// Two kernels: k_gemm_nt for operands whose rows are K-contiguous (every
+// forward product and inference), with branch-free loads issued two K steps
+// ahead into registers and two LDS buffers (one barrier per step); and
+// k_gemm_bf16 for any strides (the transposed operands of the weight
+// gradients), which can also split K over blockIdx.y into FP32 partial
+// products summed afterwards in a fixed order.
 enum { kGemmRelu = 1, kGemmMask = 2, kGemmNeg = 4 };
-constexpr int kGT = 64, kGK = 64, kGKP = kGK + 8;
-enum { kGemmVecA = 8, kGemmVecB = 16 };   // operand rows are 16-byte aligned runs of K (vector loads)
+// operand layouts of the strided kernel: K-contiguous 16-byte runs,
+// row-contiguous 16-byte runs, else element gathers
+enum { kGemmVecA = 8, kGemmVecB = 16, kGemmRowA = 32, kGemmRowB = 64 };
+constexpr int kGT = 128, kGK = 64, kGKP = kGK + 8, kGroupM = 8;
+constexpr int kGLoads = kGT * kGK / (8 * 256);   // 16-byte groups per thread per operand and step
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t sam, int64_t sak,
-                                                   const uint16_t *__restrict__ B, int64_t sbn, int64_t sbk,
-                                                   int32_t M, int32_t N, int32_t K, const float *__restrict__ bias,
-                                                   int32_t flags, const uint16_t *__restrict__ mask, int64_t ldm,
-                                                   float *__restrict__ C32, uint16_t *__restrict__ C16,
-                                                   int64_t ldc) {
-    __shared__ __align__(16) uint16_t As[kGT][kGKP];
-    __shared__ __align__(16) uint16_t Bs[kGT][kGKP];
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
-    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-    f32x4 acc[2][2];
+__device__ inline void gemm_tile_origin(int32_t M, int32_t N, int64_t &m0, int64_t &n0) {
+    const int64_t gm = (M + kGT - 1) / kGT, gn = (N + kGT - 1) / kGT, T = gm * gn;
+    int64_t L = blockIdx.x;
+    if (T % kXcds == 0) L = (L % kXcds) * (T / kXcds) + L / kXcds;
+    const int64_t gsz = (int64_t)kGroupM * gn, g0 = (L / gsz) * kGroupM, rr = L % gsz;
+    const int64_t gh = gm - g0 < kGroupM ? gm - g0 : kGroupM;
+    m0 = (g0 + rr % gh) * kGT;
+    n0 = (rr / gh) * kGT;
+}
+
+// The products of one wave's 64 x 64 block: 4 x 4 16 x 16 blocks; D row
+// (lane/16)*4 + r, column lane%16 of each.
+__device__ inline void gemm_epilogue(const f32x4 (&acc)[4][4], int64_t m0, int64_t n0, int32_t M, int32_t N,
+                                     const float *__restrict__ bias, int32_t flags, const uint16_t *__restrict__ mask,
+                                     int64_t ldm, float *__restrict__ C32, uint16_t *__restrict__ C16, int64_t ldc) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // one operand tile: rows r0.., k0..; the fast thread index walks the
-    // unit-stride dimension so that the loads coalesce
-    auto load_tile = [&](uint16_t (*S)[kGKP], const uint16_t *P, int64_t srow, int64_t sk, int64_t r0, int32_t R,
-                         int64_t k0, bool vec) {
-        if (vec) {   // 8 consecutive k per thread (K is a multiple of 8)
-#pragma unroll
-            for (int u = 0; u < kGT * kGK / (8 * 256); u++) {
-                const int e = t + u * 256;
-                const int r = e / (kGK / 8), kk = (e % (kGK / 8)) * 8;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (r0 + r < R && k0 + kk < K) v = *reinterpret_cast<const uint4 *>(P + (r0 + r) * srow + k0 + kk);
-                *reinterpret_cast<uint4 *>(&S[r][kk]) = v;
-            }
-            return;
-        }
-#pragma unroll
-        for (int u = 0; u < kGT * kGK / 256; u++) {
-            const int e = t + u * 256;
-            int r, kk;
-            if (sk == 1) {
-                r = e / kGK;
-                kk = e % kGK;
-            } else {
-                r = e % kGT;
-                kk = e / kGT;
-            }
-            uint16_t v = 0;
-            if (r0 + r < R && k0 + kk < K) v = P[(r0 + r) * srow + (k0 + kk) * sk];
-            S[r][kk] = v;
-        }
-    };
-    for (int64_t k0 = 0; k0 < K; k0 += kGK) {
-        load_tile(As, A, sam, sak, m0, M, k0, (flags & kGemmVecA) != 0);
-        load_tile(Bs, B, sbn, sbk, n0, N, k0, (flags & kGemmVecB) != 0);
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < kGK; ks += 32)
-#pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const bf16x8 a = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const uint4 *>(&As[wm + i * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const bf16x8 b = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const uint4 *>(&Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-                }
-            }
-        __syncthreads();
-    }
-    // D row (lane/16)*4 + r, column lane%16 of each 16 x 16 block
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < 4; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int64_t mm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-                const int64_t nn = n0 + wn + j * 16 + (lane & 15);
+                const int64_t mm = m0 + i * 16 + (lane >> 4) * 4 + r;
+                const int64_t nn = n0 + j * 16 + (lane & 15);
                 if (mm >= M || nn >= N) continue;
                 float v = acc[i][j][r];
                 if (bias) v = v + bias[nn];
@@ -169,17 +133,274 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
             }
 }
 
+__device__ inline void gemm_mfma_step(const uint16_t (*As)[kGKP], const uint16_t (*Bs)[kGKP], int wm, int wn,
+                                      f32x4 (&acc)[4][4]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int ks = 0; ks < kGK; ks += 32) {
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            a[i] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&As[wm + i * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
+            b[i] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&Bs[wn + i * 16 + (lane & 15)][ks + (lane >> 4) * 8]));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// K-contiguous operands: A row m at A + m*lda, B row n at B + n*ldb, K a
+// multiple of 8, rows 16-byte aligned, every element offset below 2^31.
+// Thread t loads rows t/8 + 32u (u < 4) of each operand, columns
+// (t%8)*8 .. +7 of the step; rows past M or N and the K tail are loaded
+// clamped to an element in range and zeroed by a select.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nt(
+    const uint16_t *__restrict__ A, int32_t lda, const uint16_t *__restrict__ B, int32_t ldb, int32_t M, int32_t N,
+    int32_t K, const float *__restrict__ bias, int32_t flags, const uint16_t *__restrict__ mask, int64_t ldm,
+    float *__restrict__ C32, uint16_t *__restrict__ C16, int64_t ldc) {
+    __shared__ __align__(16) uint16_t As[2][kGT][kGKP];
+    __shared__ __align__(16) uint16_t Bs[2][kGT][kGKP];
+    const int t = threadIdx.x, w = t >> 6;
+    int64_t m0, n0;
+    gemm_tile_origin(M, N, m0, n0);
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    const int kk0 = (t & 7) * 8;
+    int32_t oa[4], ob[4];
+    uint32_t ok = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int r = (t >> 3) + 32 * u;
+        const int64_t ra = m0 + r, rb = n0 + r;
+        ok |= (ra < M ? 1u : 0u) << u;
+        ok |= (rb < N ? 1u : 0u) << (4 + u);
+        oa[u] = (int32_t)((ra < M ? ra : M - 1) * (int64_t)lda) + kk0;
+        ob[u] = (int32_t)((rb < N ? rb : N - 1) * (int64_t)ldb) + kk0;
+    }
+    auto fetch = [&](uint4 (&ga)[4], uint4 (&gb)[4], int32_t k0) {
+        const bool okk = k0 + kk0 < K;
+        const int32_t kc = okk ? k0 : K - 8 - kk0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint4 va = *reinterpret_cast<const uint4 *>(A + oa[u] + kc);
+            const uint4 vb = *reinterpret_cast<const uint4 *>(B + ob[u] + kc);
+            const bool ka = okk && ((ok >> u) & 1u), kb = okk && ((ok >> (4 + u)) & 1u);
+            ga[u] = make_uint4(ka ? va.x : 0u, ka ? va.y : 0u, ka ? va.z : 0u, ka ? va.w : 0u);
+            gb[u] = make_uint4(kb ? vb.x : 0u, kb ? vb.y : 0u, kb ? vb.z : 0u, kb ? vb.w : 0u);
+        }
+    };
+    auto stage = [&](int buf, const uint4 (&ga)[4], const uint4 (&gb)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r = (t >> 3) + 32 * u;
+            *reinterpret_cast<uint4 *>(&As[buf][r][kk0]) = ga[u];
+            *reinterpret_cast<uint4 *>(&Bs[buf][r][kk0]) = gb[u];
+        }
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // a0/b0 and a1/b1 alternate: while step s is multiplied from LDS buffer
+    // s%2, step s+1 is staged into the other buffer and step s+2 (or s+3)
+    // is in flight into the registers just staged
+    const int32_t ns = (K + kGK - 1) / kGK;
+    uint4 a0[4], b0[4], a1[4], b1[4];
+    fetch(a0, b0, 0);
+    if (ns > 1) fetch(a1, b1, kGK);
+    stage(0, a0, b0);
+    if (ns > 2) fetch(a0, b0, 2 * kGK);
+    __syncthreads();
+    for (int32_t s = 0; s < ns; s += 2) {
+        gemm_mfma_step(As[0], Bs[0], wm, wn, acc);
+        if (s + 1 < ns) {
+            stage(1, a1, b1);
+            if (s + 3 < ns) fetch(a1, b1, (s + 3) * kGK);
+        }
+        __syncthreads();
+        if (s + 1 < ns) {
+            gemm_mfma_step(As[1], Bs[1], wm, wn, acc);
+            if (s + 2 < ns) {
+                stage(0, a0, b0);
+                if (s + 4 < ns) fetch(a0, b0, (s + 4) * kGK);
+            }
+            __syncthreads();
+        }
+    }
+    gemm_epilogue(acc, m0 + wm, n0 + wn, M, N, bias, flags, mask, ldm, C32, C16, ldc);
+}
+
+// Loads one operand tile (rows r0.., k0..) into registers as 16-byte groups
+// of 8 elements: 8 consecutive k of one row, or (row-contiguous) 8
+// consecutive rows of one k.  Out-of-range elements read as zero.
+__device__ inline void gemm_fetch(uint4 (&g)[kGLoads], const uint16_t *__restrict__ P, int64_t srow, int64_t sk,
+                                  int64_t r0, int32_t R, int64_t k0, int64_t K, int vec, int rowv) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kGLoads; u++) {
+        const int e = t + u * 256;
+        if (rowv) {
+            const int kk = e / (kGT / 8), rg = (e % (kGT / 8)) * 8;
+            const int64_t k = k0 + kk, r = r0 + rg;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (k < K) {
+                if (r + 8 <= R) {
+                    v = *reinterpret_cast<const uint4 *>(P + k * sk + r);
+                } else {
+                    uint16_t h[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) h[i] = r + i < R ? P[k * sk + r + i] : (uint16_t)0;
+                    v = __builtin_bit_cast(uint4, h);
+                }
+            }
+            g[u] = v;
+        } else {
+            const int r = e / (kGK / 8), kk = (e % (kGK / 8)) * 8;
+            const int64_t row = r0 + r, k = k0 + kk;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (row < R) {
+                if (vec) {   // K-range ends are multiples of 8: the group is all in or all out
+                    if (k < K) v = *reinterpret_cast<const uint4 *>(P + row * srow + k);
+                } else {
+                    uint16_t h[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) h[i] = k + i < K ? P[row * srow + (k + i) * sk] : (uint16_t)0;
+                    v = __builtin_bit_cast(uint4, h);
+                }
+            }
+            g[u] = v;
+        }
+    }
+}
+
+__device__ inline void gemm_stage(uint16_t (*S)[kGKP], const uint4 (&g)[kGLoads], int rowv) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kGLoads; u++) {
+        const int e = t + u * 256;
+        if (rowv) {
+            const int kk = e / (kGT / 8), rg = (e % (kGT / 8)) * 8;
+            uint16_t h[8];
+            *reinterpret_cast<uint4 *>(h) = g[u];
+#pragma unroll
+            for (int i = 0; i < 8; i++) S[rg + i][kk] = h[i];
+        } else {
+            const int r = e / (kGK / 8), kk = (e % (kGK / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&S[r][kk]) = g[u];
+        }
+    }
+}
+
+// Any strides.  With gridDim.y = S > 1, workgroup (x, y) multiplies K range
+// [y*kchunk, min(K, (y+1)*kchunk)) and writes its plain FP32 partial product
+// to C32 + y*M*ldc (no epilogue).
+__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t sam, int64_t sak,
+                                                   const uint16_t *__restrict__ B, int64_t sbn, int64_t sbk,
+                                                   int32_t M, int32_t N, int32_t K, int32_t kchunk,
+                                                   const float *__restrict__ bias, int32_t flags,
+                                                   const uint16_t *__restrict__ mask, int64_t ldm,
+                                                   float *__restrict__ C32, uint16_t *__restrict__ C16,
+                                                   int64_t ldc) {
+    __shared__ __align__(16) uint16_t As[kGT][kGKP];
+    __shared__ __align__(16) uint16_t Bs[kGT][kGKP];
+    const int t = threadIdx.x, w = t >> 6;
+    int64_t m0, n0;
+    gemm_tile_origin(M, N, m0, n0);
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    const int va = (flags & kGemmVecA) != 0, vb = (flags & kGemmVecB) != 0;
+    const int ra = (flags & kGemmRowA) != 0, rb = (flags & kGemmRowB) != 0;
+    const int64_t klo = (int64_t)blockIdx.y * kchunk, khi = klo + kchunk < K ? klo + kchunk : K;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    uint4 pa[kGLoads], pb[kGLoads];
+    gemm_fetch(pa, A, sam, sak, m0, M, klo, khi, va, ra);
+    gemm_fetch(pb, B, sbn, sbk, n0, N, klo, khi, vb, rb);
+    for (int64_t k0 = klo; k0 < khi; k0 += kGK) {
+        gemm_stage(As, pa, ra);
+        gemm_stage(Bs, pb, rb);
+        __syncthreads();
+        if (k0 + kGK < khi) {
+            gemm_fetch(pa, A, sam, sak, m0, M, k0 + kGK, khi, va, ra);
+            gemm_fetch(pb, B, sbn, sbk, n0, N, k0 + kGK, khi, vb, rb);
+        }
+        gemm_mfma_step(As, Bs, wm, wn, acc);
+        __syncthreads();
+    }
+    if (gridDim.y > 1)
+        gemm_epilogue(acc, m0 + wm, n0 + wn, M, N, nullptr, 0, nullptr, 0, C32 + (int64_t)blockIdx.y * M * ldc,
+                      nullptr, ldc);
+    else
+        gemm_epilogue(acc, m0 + wm, n0 + wn, M, N, bias, flags, mask, ldm, C32, C16, ldc);
+}
+
+// out[i] = sum over s = 0..S-1 (in order) of P[s*n + i]
+__global__ void k_sum_parts(const float *__restrict__ P, int32_t S, int64_t n, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.0f;
+    for (int32_t s = 0; s < S; s++) v += P[s * n + i];
+    out[i] = v;
+}
+
+// Size in floats of the training scratch that holds split-K partial
+// products and column-sum parts (32 MiB).
+constexpr int64_t kGemmParts = 8ll << 20;
+
+// parts: kGemmParts floats of scratch for split-K (null: no split)
 static caps_status gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbn, int64_t sbk,
                         int32_t M, int32_t N, int32_t K, const float *bias, int32_t flags, const uint16_t *mask,
-                        int64_t ldm, float *C32, uint16_t *C16, int64_t ldc, hipStream_t st) {
+                        int64_t ldm, float *C32, uint16_t *C16, int64_t ldc, hipStream_t st,
+                        float *parts = nullptr) {
     if (M <= 0 || N <= 0) return CAPS_OK;
-    const auto vec_ok = [K](const uint16_t *P, int64_t srow, int64_t sk) {
-        return sk == 1 && K % 8 == 0 && srow % 8 == 0 && ((uintptr_t)P & 15) == 0;
+    const auto aligned = [](const uint16_t *P) { return ((uintptr_t)P & 15) == 0; };
+    // K-contiguous rows whose 8-element groups are 16-byte aligned
+    const auto vec_ok = [&](const uint16_t *P, int64_t srow, int64_t sk) {
+        return sk == 1 && K % 8 == 0 && srow % 8 == 0 && aligned(P);
     };
+    // row-contiguous columns (unit row stride) with aligned 8-row groups
+    const auto row_ok = [&](const uint16_t *P, int64_t srow, int64_t sk) {
+        return srow == 1 && sk != 1 && sk % 8 == 0 && aligned(P);
+    };
+    const int64_t tiles = (int64_t)((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
+    if (tiles > INT32_MAX) {
+        set_error("router GEMM: too many tiles");
+        return CAPS_EINVAL;
+    }
+    if (vec_ok(A, sam, sak) && vec_ok(B, sbn, sbk) && (int64_t)M * sam < INT32_MAX && (int64_t)N * sbn < INT32_MAX) {
+        hipLaunchKernelGGL(k_gemm_nt, dim3((unsigned)tiles), dim3(256), 0, st, A, (int32_t)sam, B, (int32_t)sbn, M,
+                           N, K, bias, flags, mask, ldm, C32, C16, ldc);
+        CAPS_HIP(hipGetLastError());
+        return CAPS_OK;
+    }
     if (vec_ok(A, sam, sak)) flags |= kGemmVecA;
+    else if (row_ok(A, sam, sak)) flags |= kGemmRowA;
     if (vec_ok(B, sbn, sbk)) flags |= kGemmVecB;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT)),
-                       dim3(256), 0, st, A, sam, sak, B, sbn, sbk, M, N, K, bias, flags, mask, ldm, C32, C16, ldc);
+    else if (row_ok(B, sbn, sbk)) flags |= kGemmRowB;
+    // split K when the tiles alone cannot fill the chip (plain FP32 output only)
+    int32_t splits = 1, kchunk = K;
+    if (parts && C32 && !C16 && !bias && flags == (flags & ~(kGemmRelu | kGemmMask | kGemmNeg)) && ldc == N) {
+        const int64_t want = (512 + tiles - 1) / tiles;
+        const int64_t most = std::max<int64_t>(1, std::min<int64_t>(K / (4 * kGK), kGemmParts / ((int64_t)M * N)));
+        splits = (int32_t)std::min<int64_t>(want, most);
+        kchunk = (int32_t)(((K + splits - 1) / splits + kGK - 1) / kGK * kGK);
+        splits = (K + kchunk - 1) / kchunk;
+    }
+    if (splits > 1) {
+        hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, st, A, sam, sak, B,
+                           sbn, sbk, M, N, K, kchunk, nullptr, flags, nullptr, 0, parts, nullptr, ldc);
+        const int64_t n = (int64_t)M * N;
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, parts, splits, n, C32);
+    } else {
+        hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)tiles), dim3(256), 0, st, A, sam, sak, B, sbn, sbk, M, N, K,
+                           K, bias, flags, mask, ldm, C32, C16, ldc);
+    }
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;
 }
@@ -250,12 +471,31 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z,
 }
 
 // Column sums of an M x N FP32 matrix, rows in ascending order.
-__global__ void k_colsum(const float *__restrict__ X, int32_t M, int32_t N, float *__restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// Column sums of an M x N FP32 matrix in two deterministic stages: workgroup
+// (x, y) sums rows [rp*y, rp*y + rp) of columns [64x, 64x + 64) (four row
+// lanes, each over every fourth row, then the lanes in order) into
+// part[y*N + j]; then k_sum_parts adds the parts in order.  rp is 64, or
+// more when the parts would not fit kGemmParts floats.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ X, int32_t M, int32_t N, int32_t rp,
+                                                     float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, l = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + c, r0 = (int64_t)blockIdx.y * rp;
     float s = 0.0f;
-    for (int64_t i = 0; i < M; i++) s += X[i * N + j];
-    out[j] = s;
+    if (j < N)
+        for (int64_t i = r0 + l; i < r0 + rp && i < M; i += 4) s += X[i * N + j];
+    red[l][c] = s;
+    __syncthreads();
+    if (l == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+static void colsum(const float *X, int32_t M, int32_t N, float *part, float *out, hipStream_t st) {
+    int64_t rp = 64;
+    while ((M + rp - 1) / rp * (int64_t)N > kGemmParts) rp *= 2;
+    const int32_t ry = (int32_t)((M + rp - 1) / rp);
+    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((N + 63) / 64), (unsigned)ry), dim3(256), 0, st, X, M, N,
+                       (int32_t)rp, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, ry, (int64_t)N, out);
 }
 
 // Adds the mean of M values to *acc (single workgroup).
@@ -339,15 +579,25 @@ __global__ __launch_bounds__(64) void k_router_conf(const float *__restrict__ S,
     if (threadIdx.x == 0) conf[i] = 1.0f / sum;
 }
 
-__global__ void k_router_fallback(int32_t nb, int32_t m, int32_t k, float fb_prob, const float *__restrict__ conf,
-                                  const int32_t *__restrict__ cand, const int32_t *__restrict__ probes_c,
-                                  int32_t *__restrict__ probes) {
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
+__global__ void k_router_fb_list(int32_t nb, int32_t m, int32_t k, float fb_prob, const float *__restrict__ conf,
+                                 const int32_t *__restrict__ cand, int32_t *__restrict__ fbq,
+                                 int32_t *__restrict__ nfb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     int64_t c = 0;
     for (int j = 0; j < m; j++) c += cand[i * m + j];
-    if (conf[i] < fb_prob || c < k)
-        for (int j = 0; j < m; j++) probes[i * m + j] = probes_c[i * m + j];
+    if (conf[i] < fb_prob || c < k) fbq[atomicAdd(nfb, 1)] = (int32_t)i;
+}
+
+__global__ void k_router_fb_apply(int32_t nb, int32_t m, const int32_t *__restrict__ fbq,
+                                  const int32_t *__restrict__ nfb, const int32_t *__restrict__ probes_c,
+                                  int32_t *__restrict__ probes) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = e / m;
+    if (r >= nb || r >= *nfb) return;
+    probes[(int64_t)fbq[r] * m + e % m] = probes_c[e];
 }
 
 static int64_t nblk(int64_t n, int t) { return (n + t - 1) / t; }
@@ -370,10 +620,19 @@ caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int
     return CAPS_OK;
 }
 
-caps_status router_fallback(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
-                            const int32_t *cand, const int32_t *probes_c, int32_t *probes, hipStream_t st) {
-    hipLaunchKernelGGL(k_router_fallback, dim3((unsigned)nblk(nb, 256)), dim3(256), 0, st, nb, m, k,
-                       ix->router->fb_prob, conf, cand, probes_c, probes);
+caps_status router_fallback_list(const Index *ix, int32_t nb, int32_t m, int32_t k, const float *conf,
+                                 const int32_t *cand, int32_t *fbq, int32_t *nfb, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, nfb);
+    hipLaunchKernelGGL(k_router_fb_list, dim3((unsigned)nblk(nb, 256)), dim3(256), 0, st, nb, m, k,
+                       ix->router->fb_prob, conf, cand, fbq, nfb);
+    CAPS_HIP(hipGetLastError());
+    return CAPS_OK;
+}
+
+caps_status router_fallback_apply(int32_t nb, int32_t m, const int32_t *fbq, const int32_t *nfb,
+                                  const int32_t *probes_c, int32_t *probes, hipStream_t st) {
+    hipLaunchKernelGGL(k_router_fb_apply, dim3((unsigned)nblk((int64_t)nb * m, 256)), dim3(256), 0, st, nb, m, fbq,
+                       nfb, probes_c, probes);
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;
 }
@@ -457,7 +716,7 @@ static caps_status router_alloc(Index *ix, int32_t hid, float in_scale, float in
 struct BatchWs {
     uint16_t *Xb, *Hb, *dZ16, *dH16;
     int32_t *Lb;
-    float *Z, *dZ32, *dH32, *grad, *loss_rows;
+    float *Z, *dZ32, *dH32, *grad, *loss_rows, *parts;
 };
 
 static size_t batch_ws(const Router &R, int32_t bs, int32_t L, uint8_t *base, BatchWs *w) {
@@ -479,6 +738,7 @@ static size_t batch_ws(const Router &R, int32_t bs, int32_t L, uint8_t *base, Ba
     t.dH32 = (float *)take(sizeof(float) * (size_t)bs * R.hid);
     t.grad = (float *)take(sizeof(float) * (size_t)R.nparam);
     t.loss_rows = (float *)take(sizeof(float) * (size_t)bs);
+    t.parts = (float *)take(sizeof(float) * (size_t)kGemmParts);
     if (w) *w = t;
     return o + 256;
 }
@@ -498,16 +758,18 @@ static caps_status batch_grads(const Router &R, const BatchWs &w, int32_t nb, in
     CAPS_HIP(hipGetLastError());
     float *gw1 = w.grad, *gb1 = w.grad + R.o_b1, *gw2 = w.grad + R.o_w2, *gb2 = w.grad + R.o_b2;
     // dW2 = dZ^T h;  db2 = column sums of dZ
-    s = gemm(w.dZ16, 1, R.nout, w.Hb, 1, R.hid, R.nout, R.hid, nb, nullptr, 0, nullptr, 0, gw2, nullptr, R.hid, st);
+    s = gemm(w.dZ16, 1, R.nout, w.Hb, 1, R.hid, R.nout, R.hid, nb, nullptr, 0, nullptr, 0, gw2, nullptr, R.hid, st,
+             w.parts);
     if (s != CAPS_OK) return s;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(R.nout, 256)), dim3(256), 0, st, w.dZ32, nb, R.nout, gb2);
+    colsum(w.dZ32, nb, R.nout, w.parts, gb2, st);
     // dH = (dZ W2) masked by h > 0;  db1 = column sums of dH
     s = gemm(w.dZ16, R.nout, 1, R.w2h, 1, R.hid, nb, R.hid, R.nout, nullptr, kGemmMask, w.Hb, R.hid, w.dH32, w.dH16,
              R.hid, st);
     if (s != CAPS_OK) return s;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(R.hid, 256)), dim3(256), 0, st, w.dH32, nb, R.hid, gb1);
+    colsum(w.dH32, nb, R.hid, w.parts, gb1, st);
     // dW1 = dH^T x
-    s = gemm(w.dH16, 1, R.hid, w.Xb, 1, R.dpad, R.hid, R.dpad, nb, nullptr, 0, nullptr, 0, gw1, nullptr, R.dpad, st);
+    s = gemm(w.dH16, 1, R.hid, w.Xb, 1, R.dpad, R.hid, R.dpad, nb, nullptr, 0, nullptr, 0, gw1, nullptr, R.dpad, st,
+             w.parts);
     if (s != CAPS_OK) return s;
     CAPS_HIP(hipGetLastError());
     return CAPS_OK;

@@ -139,16 +139,22 @@ constexpr int kDC = 32;
 constexpr int kTile = 64;
 
 // Q x B scores, 64 x 64 tile per workgroup, sequential fma over dims.
+// With a row list, score row r belongs to query rows[r] and only the first
+// *nrows rows (a count on the device, at most nq) are computed.
 __global__ __launch_bounds__(256) void k_route_scores(const float *__restrict__ q, int32_t nq, int32_t d,
                                                       const float *__restrict__ cent,
                                                       const float *__restrict__ cn, int32_t b,
-                                                      int32_t metric, float *__restrict__ scores) {
+                                                      int32_t metric, float *__restrict__ scores,
+                                                      const int32_t *__restrict__ rows = nullptr,
+                                                      const int32_t *__restrict__ nrows = nullptr) {
     __shared__ float xs[kDC][kTile + 4];
     __shared__ float cs[kDC][kTile + 4];
     const int t = threadIdx.x;
     const int ty = t >> 4, tx = t & 15;
     const int64_t r0 = (int64_t)blockIdx.x * kTile;
     const int c0 = blockIdx.y * kTile;
+    if (nrows) nq = min(nq, *nrows);
+    if (r0 >= nq) return;
     float acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(256) void k_route_scores(const float *__restrict__ 
             const int ri = e / kDC, jj = e % kDC;
             float v = 0.0f, w = 0.0f;
             if (jj < dc) {
-                if (r0 + ri < nq) v = q[(r0 + ri) * d + j0 + jj];
+                if (r0 + ri < nq) v = q[(rows ? (int64_t)rows[r0 + ri] : r0 + ri) * d + j0 + jj];
                 if (c0 + ri < b) w = cent[(int64_t)(c0 + ri) * d + j0 + jj];
             }
             xs[jj][ri] = v;
@@ -196,9 +202,11 @@ __global__ __launch_bounds__(256) void k_route_scores(const float *__restrict__ 
 constexpr int kTopmNT = 256;
 
 __global__ __launch_bounds__(kTopmNT) void k_topm(const float *__restrict__ scores, int32_t b, int32_t pb,
-                                                  int32_t m, int32_t *__restrict__ probes) {
+                                                  int32_t m, int32_t *__restrict__ probes,
+                                                  const int32_t *__restrict__ nrows) {
     extern __shared__ uint64_t keys[];   // pb (power of two >= b)
     const int64_t q = blockIdx.x;
+    if (nrows && q >= *nrows) return;
     const float *s = scores + q * b;
     for (int i = threadIdx.x; i < pb; i += kTopmNT)
         keys[i] = i < b ? (((uint64_t)f2ord(s[i]) << 32) | (uint32_t)i) : ~0ull;
@@ -229,10 +237,12 @@ __global__ __launch_bounds__(kTopmNT) void k_topm(const float *__restrict__ scor
 // pb = 1024 instead of 55 barrier stages).
 template <int KPT>
 __global__ __launch_bounds__(kTopmNT) void k_topm_reg(const float *__restrict__ scores, int32_t b, int32_t m,
-                                                      int32_t *__restrict__ probes) {
+                                                      int32_t *__restrict__ probes,
+                                                      const int32_t *__restrict__ nrows) {
     constexpr int PB = KPT * kTopmNT;
     __shared__ uint64_t ex[PB];
     const int64_t q = blockIdx.x;
+    if (nrows && q >= *nrows) return;
     const float *s = scores + q * b;
     const int t = threadIdx.x;
     uint64_t v[KPT];
@@ -295,10 +305,11 @@ __global__ __launch_bounds__(kTopmNT) void k_topm_reg(const float *__restrict__ 
 // pb / 64 scores per lane (position r * 64 + lane).
 template <int KPT>
 __global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scores, int32_t nq, int32_t b, int32_t m,
-                                                  int32_t s, int32_t *__restrict__ probes) {
+                                                  int32_t s, int32_t *__restrict__ probes,
+                                                  const int32_t *__restrict__ nrows) {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nq) return;
+    if (q >= nq || (nrows && q >= *nrows)) return;
     const float *sc = scores + q * b;
     uint32_t u[KPT];
 #pragma unroll
@@ -360,30 +371,31 @@ __global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scor
 // Launches the register bitonic top-m when pb allows, else the LDS one.
 // With s >= 0 (a search, not the probes query) the selection kernel instead,
 // for B up to 4096: the best m as a set, the best s in the first slots.
+// nrows (a device count, or null): only the first *nrows of the nb rows.
 static void launch_topm(const float *scores, int32_t nb, int32_t b, int32_t pb, int32_t m, int32_t *probes,
-                        hipStream_t st, int32_t s = -1) {
+                        hipStream_t st, int32_t s = -1, const int32_t *nrows = nullptr) {
     if (s >= 0 && pb >= 64 && pb <= 4096) {
         const dim3 g((nb + 3) / 4);
         switch (pb) {
-        case 64: hipLaunchKernelGGL(k_topm_sel<1>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        case 128: hipLaunchKernelGGL(k_topm_sel<2>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        case 256: hipLaunchKernelGGL(k_topm_sel<4>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        case 512: hipLaunchKernelGGL(k_topm_sel<8>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        case 1024: hipLaunchKernelGGL(k_topm_sel<16>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        case 2048: hipLaunchKernelGGL(k_topm_sel<32>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
-        default: hipLaunchKernelGGL(k_topm_sel<64>, g, dim3(256), 0, st, scores, nb, b, m, s, probes); return;
+        case 64: hipLaunchKernelGGL(k_topm_sel<1>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        case 128: hipLaunchKernelGGL(k_topm_sel<2>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        case 256: hipLaunchKernelGGL(k_topm_sel<4>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        case 512: hipLaunchKernelGGL(k_topm_sel<8>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        case 1024: hipLaunchKernelGGL(k_topm_sel<16>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        case 2048: hipLaunchKernelGGL(k_topm_sel<32>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
+        default: hipLaunchKernelGGL(k_topm_sel<64>, g, dim3(256), 0, st, scores, nb, b, m, s, probes, nrows); return;
         }
     }
     switch (pb) {
-    case 256: hipLaunchKernelGGL(k_topm_reg<1>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
-    case 512: hipLaunchKernelGGL(k_topm_reg<2>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
-    case 1024: hipLaunchKernelGGL(k_topm_reg<4>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
-    case 2048: hipLaunchKernelGGL(k_topm_reg<8>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
-    case 4096: hipLaunchKernelGGL(k_topm_reg<16>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
-    case 8192: hipLaunchKernelGGL(k_topm_reg<32>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes); return;
+    case 256: hipLaunchKernelGGL(k_topm_reg<1>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
+    case 512: hipLaunchKernelGGL(k_topm_reg<2>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
+    case 1024: hipLaunchKernelGGL(k_topm_reg<4>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
+    case 2048: hipLaunchKernelGGL(k_topm_reg<8>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
+    case 4096: hipLaunchKernelGGL(k_topm_reg<16>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
+    case 8192: hipLaunchKernelGGL(k_topm_reg<32>, dim3(nb), dim3(kTopmNT), 0, st, scores, b, m, probes, nrows); return;
     default:
         hipLaunchKernelGGL(k_topm, dim3(nb), dim3(kTopmNT), sizeof(uint64_t) * (size_t)pb, st, scores, b, pb, m,
-                           probes);
+                           probes, nrows);
     }
 }
 
@@ -1287,7 +1299,8 @@ struct SearchWs {
     int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
     float *conf;                // learned routing: softmax top-1 probability
-    int32_t *probes_c;          // learned routing: centroid probes for the fallback
+    int32_t *probes_c;          // learned routing: centroid probes of the falling-back queries
+    int32_t *fbq, *nfb;         // learned routing: the queries that fall back, their count
     int32_t *bad;               // query rows holding NaN or Inf (one counter per call)
     QDesc *qterms;              // disjunctive searches: term descriptors (kMaxTerms per query)
 };
@@ -1339,6 +1352,8 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.rh = router ? ar.take<uint16_t>((size_t)sb * router->hid) : nullptr;
     w.conf = router ? ar.take<float>((size_t)sb) : nullptr;
     w.probes_c = router ? ar.take<int32_t>((size_t)sb * m) : nullptr;
+    w.fbq = router ? ar.take<int32_t>((size_t)sb) : nullptr;
+    w.nfb = router ? ar.take<int32_t>(1) : nullptr;
 }
 
 // Shape of one search call: which scan, keys per (query, probe), the
@@ -1371,7 +1386,7 @@ static SearchPlan plan_search(const Index *ix, const caps_search_params *sp, int
                          sizeof(int4) * (size_t)m / 64 +
                          ((sp->flags & CAPS_SEARCH_DISJUNCTIVE) ? sizeof(QDesc) * kMaxTerms : 0) +
                          (P.router ? sizeof(uint16_t) * (size_t)(P.router->dpad + P.router->hid) + sizeof(float) +
-                                         sizeof(int32_t) * (size_t)m
+                                         sizeof(int32_t) * (size_t)(m + 1)
                                    : 0);
     P.sb = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nq, 1), budget / per_q));
     return P;
@@ -1544,8 +1559,9 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             }
             prof_end(CAPS_STAGE_PREP, st);
             if (router) {
-                // learned routing: router probes, their candidate counts, then a
-                // per-query fallback to the centroid probes
+                // learned routing: router probes and their candidate counts,
+                // then centroid routing for only the queries that fall back
+                // (low confidence, or fewer than k candidates)
                 prof_begin(CAPS_STAGE_ROUTE, st);
                 const caps_status rs = router_scores(ix, q + (int64_t)q0 * d, nb, con_off + q0, con_attr, con_val, n_con,
                                                      W.rx, W.rh, scores, W.conf, st);
@@ -1557,24 +1573,29 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 prof_begin(CAPS_STAGE_SELECT, st);
                 hipLaunchKernelGGL(k_select, dim3(nblocks(pairs, 256)), dim3(256), 0, st, probes, nb, m, qd, W.qterms, ix->sch,
                                    ix->tags, h, ix->offs, sp->rule, sel, cand);
+                const caps_status fl = router_fallback_list(ix, nb, m, k, W.conf, cand, W.fbq, W.nfb, st);
+                if (fl != CAPS_OK) return fl;
                 prof_end(CAPS_STAGE_SELECT, st);
             }
+            // centroid scores: every query, or (learned routing) score row r
+            // for falling-back query fbq[r], r < nfb
+            const int32_t *rows = router ? W.fbq : nullptr, *nrows = router ? W.nfb : nullptr;
             prof_begin(CAPS_STAGE_ROUTE, st);
             if (lowp) {
                 // precision mode: centroid scores on the matrix cores from the
                 // rounded queries and the centroid copy
-                const caps_status rs = lowp_route(ix, W.qlow, W.qscale, nb, scores, st);
+                const caps_status rs = lowp_route(ix, W.qlow, W.qscale, nb, scores, st, rows, nrows);
                 if (rs != CAPS_OK) return rs;
             } else {
                 hipLaunchKernelGGL(k_route_scores, dim3(nblocks(nb, kTile), nblocks(b, kTile)), dim3(256), 0, st,
-                                   q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores);
+                                   q + (int64_t)q0 * d, nb, d, ix->cent, ix->cnorm, b, ix->metric, scores, rows, nrows);
             }
             prof_end(CAPS_STAGE_ROUTE, st);
             prof_begin(CAPS_STAGE_TOPM, st);
-            launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s);
+            launch_topm(scores, nb, b, pb, m, router ? W.probes_c : probes, st, topm_s, nrows);
             prof_end(CAPS_STAGE_TOPM, st);
             if (router) {
-                const caps_status fs = router_fallback(ix, nb, m, k, W.conf, cand, W.probes_c, probes, st);
+                const caps_status fs = router_fallback_apply(nb, m, W.fbq, W.nfb, W.probes_c, probes, st);
                 if (fs != CAPS_OK) return fs;
             }
             prof_begin(CAPS_STAGE_SELECT, st);

@@ -135,13 +135,15 @@ class _LabelCounter:
         self.n = n
         owner = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
         order = np.argsort(labels, kind="stable")
-        self.lab_sorted = labels[order]
         self.own_sorted = owner[order]
+        # label l's owners are own_sorted[start[l]:start[l + 1]]
+        counts = np.bincount(labels, minlength=int(labels.max()) + 1 if len(labels) else 1)
+        self.start = np.concatenate([[0], np.cumsum(counts)])
 
     def posting(self, lab):
-        lo = np.searchsorted(self.lab_sorted, lab, side="left")
-        hi = np.searchsorted(self.lab_sorted, lab, side="right")
-        return self.own_sorted[lo:hi]
+        if lab < 0 or lab + 1 >= len(self.start):
+            return self.own_sorted[:0]
+        return self.own_sorted[self.start[lab]:self.start[lab + 1]]
 
     def ids(self, labs):
         if not labs:

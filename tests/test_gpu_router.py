@@ -98,6 +98,38 @@ def test_always_fallback_is_centroid_routing(caps, tiny):
         assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())
 
 
+def test_partial_fallback_mixes_router_and_centroid_probes(caps, tiny):
+    """Queries below the fallback level take the centroid probes, the others
+    the router's top-m (unless their router probes hold fewer than k
+    candidates): the centroid scores are computed for the falling-back
+    queries only, on a compacted list."""
+    w, ix = tiny
+    rng = np.random.default_rng(4)
+    ix.router_set(**_weights(rng, 32, R.pad_width(w.d), 16), hidden=32)
+    z = ix.router_logits(w.q, w.con_off, w.con_attr, w.con_val).cpu().numpy().astype(np.float64)
+    conf = 1.0 / np.exp(z - z.max(axis=1, keepdims=True)).sum(axis=1)
+    cs = np.sort(conf)
+    gaps = np.diff(cs)
+    mid = len(cs) // 2
+    j = mid - 5 + int(np.argmax(gaps[mid - 5:mid + 5]))   # the widest gap near the median
+    assert gaps[j] > 1e-4 * cs[j]
+    fb = 0.5 * (cs[j] + cs[j + 1])
+    ix.router_set(**ix.router_get(), hidden=32, fallback_prob=float(fb))
+    m = 5
+    pc, _ = ix.probes(w.q, w.con_off, w.con_attr, w.con_val, m, routing=0)
+    pr, _ = ix.probes(w.q, w.con_off, w.con_attr, w.con_val, m, routing=1, k=1)
+    pc, pr = pc.cpu().numpy(), pr.cpu().numpy()
+    n_router = 0
+    for i in range(w.n_q):
+        if conf[i] < fb:
+            assert np.array_equal(pr[i], pc[i]), i
+        else:
+            key = sorted(range(z.shape[1]), key=lambda c: (-np.float32(z[i, c]), c))[:m]
+            assert np.array_equal(pr[i], key) or np.array_equal(pr[i], pc[i]), i
+            n_router += int(np.array_equal(pr[i], key))
+    assert (conf < fb).sum() > 10 and n_router > 10
+
+
 def test_labels_are_partitions_of_the_ids(caps, tiny):
     w, ix = tiny
     ids, _ = ix.search(w.q, w.con_off, w.con_attr, w.con_val, 10, 16)
