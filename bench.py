@@ -56,14 +56,14 @@ MFMA_BF16_PEAK = 2500.0
 FLUSH_BYTES = 512 << 20
 
 # HBM bytes per launch of the exact main pass (mode 0, BF16 copy, 10k queries, nprobe 624) from
-# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the timed
-# launches) scaled by what the same counters read for a 512 MiB copy (read factor 2.00, write
+# two rocprofv3 --pmc runs (FETCH_SIZE: mean of the steady launches; WRITE_SIZE: their median,
+# KiB per dispatch) scaled by what the same counters read for a 512 MiB copy (read factor 2.00, write
 # factor 1.00).  Valid only for the kernel sources they were taken on (SHA-256 of the two
 # files below) and that workload; otherwise the line reports null.
 MAIN_PASS_TRAFFIC = {
-    "sources_sha256": "e6cdaf4485823d7220d6b4e06d651aa9f272f9af493cfaa65a8795df92e81fee",
+    "sources_sha256": "a86611273e3239998321634f840af7fba81b96ccc07f432409ab66f9b106162a",
     "nprobe": 624, "n_queries": 10_000,
-    "fetch_kib": 1_125_076, "write_kib": 301_685, "read_factor": 2.00, "write_factor": 1.00,
+    "fetch_kib": 1_133_089, "write_kib": 245_929, "read_factor": 2.00, "write_factor": 1.00,
 }
 SCAN_SOURCES = ("paper_2308_15014_amd/csrc/caps_mfma.h", "paper_2308_15014_amd/csrc/caps_scan_inst.hip")
 
