@@ -531,8 +531,12 @@ def run_c5(args, dev):
     torch.cuda.synchronize()
     label_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    losses = ix.router_train(rq, rco, rca, rcv, labels, hidden=1024, epochs=args.c5_epochs, batch=4096, lr=1e-3,
-                             in_scale=1.0 / 255.0, in_shift=-0.5, seed=13)
+    # one call per epoch, cosine-decayed rate (Adam moments kept across calls)
+    losses = []
+    for e in range(args.c5_epochs):
+        lr = 3e-3 * 0.5 * (1.0 + np.cos(np.pi * e / args.c5_epochs))
+        losses += list(ix.router_train(rq, rco, rca, rcv, labels, hidden=1024, epochs=1, batch=4096, lr=float(lr),
+                                       reset=1 if e == 0 else 0, in_scale=1.0 / 255.0, in_shift=-0.5, seed=13))
     train_s = time.perf_counter() - t0
     log(f"c5 router: {args.c5_train} queries (gen {gen_s:.1f}s, labels {label_s:.1f}s), {args.c5_epochs} epochs "
         f"{train_s:.1f}s, loss {[round(float(x), 4) for x in losses]}")
@@ -542,9 +546,15 @@ def run_c5(args, dev):
               "label_s": round(label_s, 2), "train_s": round(train_s, 2),
               "loss_per_epoch": [round(float(x), 4) for x in losses], "ln_B": round(float(np.log(B)), 4)}
     rates = [float(x) for x in args.c5_rates.split(",") if x]
-    serving = serve_sweep(caps, ix, w, truth, nvalid, rates, args.serve_seconds, k=k, nprobe=r_rr["nprobe"], mode=1,
-                          rerank=4 * k, routing=1, max_batch=2048, streams=3, max_constraints=8,
+    # the serving loop over the exact FP16 scan (the faster kind here), with
+    # the learned router and, for comparison, with centroid routing
+    serving = serve_sweep(caps, ix, w, truth, nvalid, rates, args.serve_seconds, k=k, nprobe=r_exact["nprobe"],
+                          mode=0, routing=1, max_batch=2048, streams=3, max_constraints=8,
                           workspace_bytes=4 << 30)
+    c_exact = rows[0]
+    serving_c = serve_sweep(caps, ix, w, truth, nvalid, rates, args.serve_seconds, k=k, nprobe=c_exact["nprobe"],
+                            mode=0, routing=0, max_batch=2048, streams=3, max_constraints=8,
+                            workspace_bytes=4 << 30)
     out = {"metric": "c5 serving: p50/p99 latency and achieved queries/s under Poisson arrivals at recall@10>=0.9 "
                      "(learned router + FP16 matrix-core scan)",
            "config": {"workload": "c5: N=10M d=128 integer vectors, FP16 copy, 3 dense attrs (10/50/200 Zipf 1.0) + "
@@ -552,9 +562,12 @@ def run_c5(args, dev):
                                   "selectivity 0.01-50%, k=10", "n": w.n, "n_queries": w.n_q,
                       "build_s": round(build_s, 2), "mean_valid_per_q": float(nvalid.mean())},
            "rows": rows, "router": router,
-           "serving": {"routing": "learned (centroid fallback)", "scan": "FP16 MFMA, FP32 rerank of the top 40",
-                       "nprobe": r_rr["nprobe"], "max_batch": 2048, "streams": 3,
-                       "workspace_budget_bytes": 4 << 30, "arrivals": "Poisson", "rates": serving}}
+           "serving": {"routing": "learned (centroid fallback)", "scan": "FP16 MFMA bounds, exact FP32 rescoring",
+                       "nprobe": r_exact["nprobe"], "max_batch": 2048, "streams": 3,
+                       "workspace_budget_bytes": 4 << 30, "arrivals": "Poisson", "rates": serving},
+           "serving_centroid": {"routing": "centroid", "scan": "FP16 MFMA bounds, exact FP32 rescoring",
+                                "nprobe": c_exact["nprobe"], "max_batch": 2048, "streams": 3,
+                                "workspace_budget_bytes": 4 << 30, "arrivals": "Poisson", "rates": serving_c}}
     if not args.no_cpu_baseline:
         import oracle
         sample = np.sort(np.random.default_rng(3).choice(w.n_q, args.c5_sample, replace=False))
@@ -673,6 +686,87 @@ def run_router(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_bliss(args, dev):
+    """Learned partitions (Section 5.2, CAPS-BLISS2) on the 1M-point corpus,
+    B = 1024: starting from the k-means partitions, each round trains the
+    192-1024-1024 router on queries labelled with the partitions of their
+    exact filtered top-10 (cosine-decayed rate, as the router experiment),
+    then re-partitions: every point's top-K partitions by the router (its own
+    vector, no constraints), the least-loaded rule, a rebuild.  Round 0 is
+    the k-means index with its router (the learned-routing configuration at
+    equal index bytes); recall@10 at fixed nprobe with router and centroid
+    routing, and queries/s at recall 0.9, per round."""
+    import math
+    import torch
+    import synth
+    import paper_2308_15014_amd as caps
+    k, K = 10, args.bliss_k
+    w = synth.make_c2(n=args.n, n_q=args.nq)
+    dq = tuple(torch.from_numpy(a).to(dev) for a in (w.q, w.con_off, w.con_attr, w.con_val))
+    B = w.n_partitions
+    rq, rco, rca, rcv = synth.make_c2_train_queries(args.router_train, 2308_15014 + 40, w)
+    tr = tuple(torch.from_numpy(a).to(dev) for a in (rq, rco, rca, rcv))
+    xd = torch.from_numpy(w.x).to(dev)
+    none_off = torch.zeros(w.n + 1, dtype=torch.int32, device=dev)
+    none = torch.zeros(1, dtype=torch.int32, device=dev)
+    grid = [16, 32, 64, 128, 256, 384, 512] + list(range(576, 704, 16)) + [768, 896, 1024]
+    rounds = []
+    assign = None
+    truth = nvalid = None
+    for rnd in range(args.bliss_rounds + 1):
+        t0 = time.perf_counter()
+        ix = caps.Index.from_workload(w, precision="bf16", assign=assign)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        if truth is None:   # the exact filtered top-10 does not depend on the partitions
+            tid, _, _, tsurv = ix.search(*dq, k, B, counters=True)
+            truth, nvalid = tid.cpu().numpy(), tsurv.cpu().numpy()
+        t0 = time.perf_counter()
+        rids, _ = ix.search(*tr, k, B)
+        labels = ix.router_labels(rids)
+        del rids
+        losses = []
+        for e in range(args.router_epochs):
+            lr = 3e-3 * 0.5 * (1.0 + math.cos(math.pi * e / args.router_epochs))
+            losses.append(float(ix.router_train(*tr, labels, hidden=1024, epochs=1, batch=4096, lr=lr,
+                                                reset=1 if e == 0 else 0, in_scale=1.0 / 255.0, in_shift=-0.5,
+                                                seed=11)[0]))
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        sizes = np.bincount(ix.export()["assign"], minlength=B)
+        row = {"round": rnd, "partitions": "k-means" if rnd == 0 else "learned (BLISS2)", "build_s": round(build_s, 2),
+               "train_s": round(train_s, 2), "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)],
+               "partition_size_min_max": [int(sizes.min()), int(sizes.max())],
+               "index_device_mib": round(ix.info()["device_bytes"] / 2**20, 1), "fixed_nprobe": []}
+        for m in (16, 64, 128, 256, 512):
+            ent = {"nprobe": m}
+            for name, routing in (("router", 1), ("centroid", 0)):
+                ids, _, nc, _ = ix.search(*dq, k, m, routing=routing, counters=True)
+                ent[f"recall@10_{name}"] = round(float(recall10(ids.cpu().numpy(), truth, nvalid).mean()), 4)
+                ent[f"cand_per_q_{name}"] = round(float(nc.float().mean()), 1)
+            row["fixed_nprobe"].append(ent)
+        sw = sweep_to_target(ix, dq, k, truth, nvalid, 0.9, grid, routing=1)
+        m = sw[-1]["nprobe"]
+        sec = timed_search(ix, dq, k, m, args.steps, args.warmup, routing=1)
+        row["router_at_0.9"] = {"nprobe": m, "recall@10": sw[-1]["recall@10"], "queries_per_s": round(w.n_q / sec, 1)}
+        log(f"[bliss round {rnd}] {row}")
+        rounds.append(row)
+        if rnd == args.bliss_rounds:
+            break
+        # re-partition: the router's top-K partitions of every point, least-loaded rule
+        cand, _ = ix.probes(xd, none_off, none, none, K, routing=1)
+        assign = caps.bliss_assign(cand.cpu().numpy(), B)
+        ix.close()
+    out = {"metric": "learned partitions (CAPS-BLISS2) vs k-means partitions with the learned router: recall@10 "
+                     "at fixed nprobe and queries/s at recall 0.9, at equal index bytes",
+           "config": {"workload": "c2 1M x 128 uniform integer vectors, 3 dense attributes, B=1024 h=2, 10k "
+                                  "queries, k=10, exact search (mode 0)",
+                      "router": "192-1024-1024, retrained each round", "train_queries": args.router_train,
+                      "epochs": args.router_epochs, "top_k_candidates": K, "rounds": args.bliss_rounds},
+           "rounds": rounds}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -695,14 +789,16 @@ def main():
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
-    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide", "router"],
+    ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide", "router", "bliss"],
                     help="headline: the benchmark line; ablation: AFT height and absence-fraction sweeps; "
                          "c3: precision mode on the 5M-point angular corpus")
+    ap.add_argument("--bliss-rounds", type=int, default=3, help="re-partitioning rounds (bliss)")
+    ap.add_argument("--bliss-k", type=int, default=4, help="candidate partitions per point (bliss)")
     ap.add_argument("--c3-n", type=int, default=5_000_000)
     ap.add_argument("--c3-sample", type=int, default=300, help="queries of the FP64 truth sample (c3)")
     ap.add_argument("--c5-n", type=int, default=10_000_000)
-    ap.add_argument("--c5-train", type=int, default=200_000, help="router training queries (c5)")
-    ap.add_argument("--c5-epochs", type=int, default=4)
+    ap.add_argument("--c5-train", type=int, default=1_000_000, help="router training queries (c5)")
+    ap.add_argument("--c5-epochs", type=int, default=8)
     ap.add_argument("--c5-sample", type=int, default=100, help="queries of the oracle truth check (c5)")
     ap.add_argument("--c5-rates", default="5000,10000,20000,50000,100000")
     ap.add_argument("--calib-copy", action="store_true",
@@ -736,6 +832,9 @@ def main():
         return
     if args.experiment == "router":
         run_router(args, dev)
+        return
+    if args.experiment == "bliss":
+        run_bliss(args, dev)
         return
 
     t0 = time.perf_counter()

@@ -78,6 +78,14 @@ typedef struct {
     int32_t precision;       /* CAPS_PREC_*: also store a low-precision copy
                                 (needed by search mode 1) */
     int32_t reserved;
+    const int32_t *assign;   /* optional host array of n first-level partition
+                                ids in [0, B) (learned partitions, Section 5.2
+                                CAPS-BLISS): used instead of the Lloyd
+                                iterations (kmeans_iters ignored); each
+                                non-empty partition's centroid is the FP64 mean
+                                of its points in ascending id, rounded to FP32
+                                (IP: then normalised), an empty one keeps its
+                                initial point; NULL: k-means */
 } caps_build_params;
 
 /*
@@ -110,6 +118,21 @@ caps_status caps_build(const float *x, int64_t n, int32_t d,
                        const uint32_t *dense_vals, int32_t n_dense, const int32_t *dense_vocab,
                        const int64_t *label_off, const uint32_t *labels, int32_t label_vocab,
                        const caps_build_params *params, void *stream, caps_index **out);
+
+/*
+ * caps_bliss_assign -- the re-partitioning step of learned partitions
+ * (Section 5.2 "Index creation", CAPS-BLISS: partitions learned from
+ * filtered near-neighbour labels).  HOST arrays.  cand: n x K candidate
+ * partitions per point, best first (the learned router's top-K for the
+ * point's own vector, e.g. from caps_search_probes with routing 1); every
+ * entry in [0, b).  Points are taken in ascending id; each goes to the
+ * least loaded of its K candidates (load = points assigned so far), ties to
+ * the earlier candidate; out_assign (n) receives the partitions, ready for
+ * caps_build_params.assign.  A host computation (the rule is sequential).
+ * Errors: EINVAL (null arrays, n < 0, K < 1, b < 1, a candidate outside
+ * [0, b)).
+ */
+caps_status caps_bliss_assign(const int32_t *cand, int64_t n, int32_t k_cand, int32_t b, int32_t *out_assign);
 
 /*
  * caps_insert -- dynamic insertions (Table 1 "Dynamic Insertions"; Section 1

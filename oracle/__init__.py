@@ -312,6 +312,38 @@ def build_index(x, dense, dense_vocab, label_off, labels, label_vocab, *, metric
     return Index(x, tk, metric, b, h, cent, a, tags, level, perm, offs, np.asarray(init))
 
 
+def bliss_assign(cand, b) -> np.ndarray:
+    """Section 5.2 (CAPS-BLISS) re-partitioning: every item in ascending id to
+    the least loaded of its K candidate buckets (best first), ties to the
+    better-ranked one."""
+    cand = _c(cand, np.int32)
+    n, k = cand.shape
+    out = np.zeros(n, dtype=np.int32)
+    L = lib()
+    L.orc_bliss_assign.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p]
+    if L.orc_bliss_assign(_p(cand), n, k, int(b), _p(out)) != 0:
+        raise ValueError("candidate outside [0, b)")
+    return out
+
+
+def build_assigned(x, dense, dense_vocab, label_off, labels, label_vocab, assign, *, metric, b, h,
+                   seed, init=None) -> Index:
+    """Algorithm 1 with given first-level partitions (learned partitions,
+    Section 5.2): each centroid is one Lloyd update of the sampled initial
+    centroids with the given assignment (the mean of its points; an empty
+    partition keeps its initial point), then the truncated AFT and the CSR."""
+    x = _c(x, np.float32)
+    tk = tokens_of(dense, dense_vocab, label_off, labels, label_vocab)
+    if init is None:
+        init = init_ids(seed, x.shape[0], b)
+    a = _c(assign, np.int32)
+    cent = update(x, a, x[np.asarray(init)], metric)
+    tags, level = aft(a, b, h, tk)
+    perm, offs = csr(a, level, b, h)
+    return Index(x, tk, metric, b, h, cent, a, tags, level, perm, offs, np.asarray(init))
+
+
 def insert(idx: Index, x_new, dense_new, label_off_new, labels_new) -> Index:
     """Dynamic insertion (Table 1; Section 1 "Practical Utility"): the new
     points get ids n, n+1, ... and join the frozen partition model -- the

@@ -250,6 +250,31 @@ int orc_aft(int64_t n, const int32_t *assign, int32_t b, int32_t h,
     return 0;
 }
 
+/* Learned partitions (Section 5.2, CAPS-BLISS): the re-partitioning step of
+ * BLISS as published -- every item, in turn (here ascending id), goes to the
+ * least loaded of its model's top-K buckets, loads counting the items placed
+ * so far; ties go to the better-ranked bucket.  cand: n x k_cand, best
+ * first, entries in [0, b).  Returns -1 on a candidate out of range. */
+int orc_bliss_assign(const int32_t *cand, int64_t n, int32_t k_cand, int32_t b, int32_t *out)
+{
+    int64_t *load = (int64_t *)calloc((size_t)b, sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) {
+        int32_t pick = -1;
+        for (int32_t r = 0; r < k_cand; r++) {
+            int32_t c = cand[i * k_cand + r];
+            if (c < 0 || c >= b) {
+                free(load);
+                return -1;
+            }
+            if (pick < 0 || load[c] < load[pick]) pick = c;
+        }
+        out[i] = pick;
+        load[pick]++;
+    }
+    free(load);
+    return 0;
+}
+
 /* Dynamic insertion (Table 1 "Dynamic Insertions"; Section 1 and
  * Section 7): the partition model and the tree's tags stay frozen.  A new
  * point joins the partition the k-means assignment picks (orc_assign

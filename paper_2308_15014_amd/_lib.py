@@ -29,7 +29,7 @@ class CapsError(RuntimeError):
 class BuildParams(ctypes.Structure):
     _fields_ = [("metric", c_i32), ("n_partitions", c_i32), ("kmeans_iters", c_i32),
                 ("aft_height", c_i32), ("seed", c_u64), ("init_ids", c_vp),
-                ("precision", c_i32), ("reserved", c_i32)]
+                ("precision", c_i32), ("reserved", c_i32), ("assign", c_vp)]
 
 
 class SearchParams(ctypes.Structure):
@@ -92,6 +92,7 @@ SIGNATURES = {
     "caps_build": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32,
                            ctypes.POINTER(BuildParams), c_vp, ctypes.POINTER(c_vp)]),
     "caps_insert": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "caps_bliss_assign": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp]),
     "caps_search": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,
                             c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "caps_search_static": (c_i32, [c_vp, ctypes.POINTER(SearchParams), c_vp, c_i32, c_vp, c_vp, c_vp,

@@ -132,11 +132,15 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
         if (cs != CAPS_OK) return cs;
     }
     if (p->init_ids) {
-        std::vector<char> seen((size_t)n, 0);
         for (int32_t c = 0; c < b; c++) {
             const int32_t id = p->init_ids[c];
             if (id < 0 || id >= n) return fail(CAPS_EINVAL, "caps_build: init id %d out of range", id);
         }
+    }
+    if (p->assign) {
+        for (int64_t i = 0; i < n; i++)
+            if (p->assign[i] < 0 || p->assign[i] >= b)
+                return fail(CAPS_EINVAL, "caps_build: assign[%lld] = %d outside [0, B)", (long long)i, p->assign[i]);
     }
 
     // label slots per point: 8, or the next power of two above the largest set
@@ -168,6 +172,25 @@ extern "C" caps_status caps_build(const float *x, int64_t n, int32_t d, const ui
         return s;
     }
     *out = h_idx;
+    return CAPS_OK;
+}
+
+extern "C" caps_status caps_bliss_assign(const int32_t *cand, int64_t n, int32_t k_cand, int32_t b,
+                                         int32_t *out_assign) {
+    if (n < 0 || k_cand < 1 || b < 1) return fail(CAPS_EINVAL, "caps_bliss_assign: need n >= 0, K >= 1, b >= 1");
+    if (n > 0 && (!cand || !out_assign)) return fail(CAPS_EINVAL, "caps_bliss_assign: null array");
+    for (int64_t e = 0; e < n * (int64_t)k_cand; e++)
+        if (cand[e] < 0 || cand[e] >= b)
+            return fail(CAPS_EINVAL, "caps_bliss_assign: candidate %d outside [0, %d)", cand[e], b);
+    std::vector<int64_t> load((size_t)b, 0);
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t *c = cand + i * k_cand;
+        int32_t best = c[0];
+        for (int32_t r = 1; r < k_cand; r++)
+            if (load[(size_t)c[r]] < load[(size_t)best]) best = c[r];
+        out_assign[i] = best;
+        load[(size_t)best]++;
+    }
     return CAPS_OK;
 }
 

@@ -541,7 +541,20 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
                            (const int32_t *)dinit.p, b, d, ix->cent);
     }
     const dim3 sgrid((unsigned)((n + kTile - 1) / kTile));
-    for (int it = 0; it <= p->kmeans_iters; it++) {
+    if (p->assign) {
+        // given partitions (learned, validated by the caller): one update of
+        // the initial centroids gives each non-empty partition its mean
+        CAPS_HIP(hipMemcpyAsync(A, p->assign, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+        CAPS_TRY(stable_sort(A, n, b, hist, hscan, (int32_t *)dsums.p, sorted, st));
+        const int64_t tot = (int64_t)b * d;
+        hipLaunchKernelGGL(k_update, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, d, sorted, hscan,
+                           nblk, b, n, ix->cent);
+        if (ix->metric == CAPS_METRIC_IP)
+            hipLaunchKernelGGL(k_normalize, dim3((b + 255) / 256), dim3(256), 0, st, ix->cent, b, d, hscan, nblk,
+                               n);
+        CAPS_HIP(hipGetLastError());
+    }
+    for (int it = 0; !p->assign && it <= p->kmeans_iters; it++) {
         hipLaunchKernelGGL(k_cnorm, dim3((b + 255) / 256), dim3(256), 0, st, ix->cent, b, d, ix->cnorm);
         hipLaunchKernelGGL(k_scores<true>, sgrid, dim3(256), 0, st, X, n, d, ix->cent, ix->cnorm, b,
                            ix->metric, A, nullptr);

@@ -56,7 +56,11 @@ class Index:
     @classmethod
     def build(cls, x, dense=None, dense_vocab=None, label_off=None, labels=None, label_vocab=0, *,
               metric: int = 0, n_partitions: int, kmeans_iters: int = 10, aft_height: int = 2,
-              seed: int = 0, init_ids=None, precision="none", device=None, stream=None) -> "Index":
+              seed: int = 0, init_ids=None, precision="none", assign=None, device=None,
+              stream=None) -> "Index":
+        """Algorithm 1 on the current (or given) device.  `assign` (n
+        partition ids, e.g. from bliss_assign) replaces the k-means
+        partitions with given ones."""
         torch = _torch()
         device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         x = _host(x, np.float32)
@@ -69,9 +73,12 @@ class Index:
         if lb is not None and lb.size == 0:
             lb = np.zeros(1, dtype=np.uint32)
         init = _host(init_ids, np.int32)
+        asg = _host(assign, np.int32)
+        if asg is not None and asg.shape != (n,):
+            raise ValueError("assign must hold one partition per point")
         prec = PREC[precision] if isinstance(precision, str) else int(precision)
         p = BuildParams(metric, n_partitions, kmeans_iters, aft_height,
-                        ctypes.c_uint64(seed & (2**64 - 1)).value, _ptr(init), prec, 0)
+                        ctypes.c_uint64(seed & (2**64 - 1)).value, _ptr(init), prec, 0, _ptr(asg))
         out = ctypes.c_void_p()
         with torch.cuda.device(device):
             st = _stream(stream)
@@ -353,3 +360,17 @@ class Index:
             self.close()
         except Exception:
             pass
+
+
+def bliss_assign(cand, n_partitions: int) -> np.ndarray:
+    """Re-partitioning of learned partitions (caps_bliss_assign): each point,
+    in ascending id, to the least loaded of its candidate partitions (n x K,
+    best first), ties to the earlier one.  Host arrays in and out."""
+    cand = np.ascontiguousarray(np.asarray(cand), dtype=np.int32)
+    if cand.ndim != 2:
+        raise ValueError("cand must be n x K")
+    n, k = cand.shape
+    out = np.zeros(n, dtype=np.int32)
+    check(lib().caps_bliss_assign(_ptr(cand), n, k, int(n_partitions), _ptr(out)))
+    return out
+

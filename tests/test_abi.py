@@ -52,3 +52,20 @@ def test_load_refuses_missing_and_foreign_files(tmp_path):
     p.write_bytes(b"NOTCAPS!" + bytes(64))
     assert L.caps_load(str(p).encode(), None, ctypes.byref(out)) == -6
     assert not out.value
+
+
+def test_bliss_assign_host_call_matches_oracle(orc):
+    """caps_bliss_assign is a host computation: callable without a GPU, and
+    equal to the oracle's re-partitioning rule item for item."""
+    from paper_2308_15014_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libcaps.so not built")
+    import numpy as np
+    import paper_2308_15014_amd as caps
+    rng = np.random.default_rng(11)
+    for n, k, b in ((1, 1, 1), (1000, 4, 37), (20000, 8, 1024), (5000, 3, 2)):
+        cand = rng.integers(0, b, size=(n, k)).astype(np.int32)
+        assert np.array_equal(caps.bliss_assign(cand, b), orc.bliss_assign(cand, b))
+    with pytest.raises(caps.CapsError):
+        caps.bliss_assign(np.array([[0, 3]], np.int32), 3)
+    assert caps.bliss_assign(np.zeros((0, 2), np.int32), 3).shape == (0,)

@@ -592,3 +592,54 @@ def test_label_index_bruteforce_equals_mask_bruteforce():
                      w.con_val, 10)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+# ---------------------------------------------------------------- learned partitions (Section 5.2)
+def test_bliss_assign_hand_worked(orc):
+    g = json.load(open(os.path.join(GOLD, "bliss_assign_worked.json")))
+    got = orc.bliss_assign(np.array(g["cand"], np.int32), g["b"])
+    assert got.tolist() == g["assign"]
+
+
+def test_bliss_assign_single_candidate_is_identity(orc):
+    rng = np.random.default_rng(7)
+    cand = rng.integers(0, 9, size=(500, 1)).astype(np.int32)
+    assert np.array_equal(orc.bliss_assign(cand, 9), cand[:, 0])
+
+
+def test_bliss_assign_balances_when_every_bucket_is_a_candidate(orc):
+    # every item may go anywhere: least-loaded placement keeps the loads
+    # within one of each other after every item (a most-loaded rule, or a
+    # dropped load update, would not)
+    rng = np.random.default_rng(8)
+    b = 7
+    cand = np.stack([rng.permutation(b) for _ in range(300)]).astype(np.int32)
+    a = orc.bliss_assign(cand, b)
+    for n in (1, 10, 57, 300):
+        cnt = np.bincount(a[:n], minlength=b)
+        assert cnt.max() - cnt.min() <= 1
+    assert all(a[i] in cand[i] for i in range(len(a)))
+
+
+def test_bliss_assign_prefers_the_better_rank_on_ties(orc):
+    # two buckets, equal loads before every even item: the even items take
+    # their first choice
+    cand = np.array([[1, 0], [1, 0], [0, 1], [0, 1]], np.int32)
+    assert orc.bliss_assign(cand, 2).tolist() == [1, 0, 0, 1]
+
+
+def test_build_assigned_pins(orc):
+    # a given assignment: centroids are the FP64 means of their points (an
+    # empty partition keeps its initial point); the layout is the AFT/CSR of
+    # that assignment
+    w = synth.make_tiny(31, n=200, d=6, n_q=1, vocabs=(3, 4), b=5, h=2)
+    a = (np.arange(w.n) % 4).astype(np.int32)          # partition 4 stays empty
+    init = np.array([3, 17, 40, 99, 150], np.int32)
+    ix = orc.build_assigned(w.x, w.dense, w.dense_vocab, None, None, 0, a, metric=0, b=5, h=2, seed=0,
+                            init=init)
+    for c in range(4):
+        mean = w.x[a == c].astype(np.float64).mean(axis=0).astype(np.float32)
+        assert np.allclose(ix.centroids[c], mean, rtol=0, atol=2e-6 * max(1.0, float(np.abs(mean).max())))
+    assert np.array_equal(ix.centroids[4], w.x[150])
+    tags, level = orc.aft(a, 5, 2, orc.tokens_of(w.dense, w.dense_vocab, None, None, 0))
+    assert np.array_equal(ix.tags, tags) and np.array_equal(ix.level, level)
