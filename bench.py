@@ -789,6 +789,8 @@ def main():
                          "mode 2), router (learned router, routing 1, with modes 0 and 1); the JSON line "
                          "needs fp32")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the cold-cache protocol")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp8"],
+                    help="low-precision copy of the headline index (the matrix-core bounds of mode 0)")
     ap.add_argument("--experiment", default="headline", choices=["headline", "ablation", "c3", "c5", "wide", "router", "bliss"],
                     help="headline: the benchmark line; ablation: AFT height and absence-fraction sweeps; "
                          "c3: precision mode on the 5M-point angular corpus")
@@ -843,7 +845,7 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ix = caps.Index.from_workload(w, precision="bf16")
+    ix = caps.Index.from_workload(w, precision=args.precision)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = ix.info()
@@ -936,10 +938,12 @@ def main():
         flops_dense = 2.0 * w.d * cand_total / launches_per_step       # one dot product per candidate pair
         qbytes = (4.0 * cand_total + (4 * w.d + 4) * surv_total +
                   w.n_q * (4.0 * m * (2 * w.aft_height + 2) + 4 * w.d + 8 * k)) / launches_per_step
+        pn = {"bf16": "BF16", "fp16": "FP16", "fp8": "FP8"}[args.precision]
         kern = ("k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)" if mode == 2 else
-                "k_scan_mfma<bf16> " + ("exact main pass (BF16 lower bounds on MFMA, exact filter epilogue, "
-                                        "passing pairs deferred to the FP32 rescoring merge)" if mode == 0 else
-                                        "approximate keys (BF16 scores on MFMA, exact filter, per-query top-4k)"))
+                f"k_scan_mfma<{args.precision}> " +
+                (f"exact main pass ({pn} lower bounds on MFMA, exact filter epilogue, passing pairs deferred to "
+                 "the FP32 rescoring merge)" if mode == 0 else
+                 f"approximate keys ({pn} scores on MFMA, exact filter, per-query top-4k)"))
         roof = {"kernel": kern, "avg_launch_ms": round(scan_avg_s * 1e3, 4),
                 "method_flops": {"per_launch": flops_method,
                                  "tflops": round(flops_method / scan_avg_s / 1e12, 3),
@@ -956,7 +960,8 @@ def main():
             gbps = ub["bytes"] / scan_avg_s / 1e9
             roof.update({"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbps / HBM_PEAK_GBS, 4),
-                         "traffic": main_pass_traffic(m, w.n_q) if (mode == 0 and routing == 0) else None,
+                         "traffic": (main_pass_traffic(m, w.n_q)
+                                     if (mode == 0 and routing == 0 and args.precision == "bf16") else None),
                          "traffic_unit": "bytes per launch (HBM, rocprofv3 TCC counters, calibrated)",
                          "algorithmic_bytes_per_launch": ub["bytes"],
                          "bytes_rule": "union: each distinct candidate word (4 B) and survivor row (4d+4 B) of "

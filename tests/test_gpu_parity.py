@@ -313,3 +313,27 @@ def test_height_sweep(caps, orc):
                     assert (nc <= prev_nc).all()
                 prev_nc = nc
         ix.close()
+
+
+@pytest.mark.parametrize("mode,prec", [(0, "bf16"), (1, "bf16"), (2, "none"), (0, "none")])
+def test_workspace_exact_fit(caps, orc, mode, prec):
+    """A search given exactly the workspace the library reports for the
+    batch, or one byte less (then cut into sub-batches), equals the search
+    with the default budget.  Each sub-batch's allocation is the size of a
+    dry run of its own carve, and the carve's arena refuses any byte past the
+    allocation, so a size formula that missed an array fails here as an
+    error instead of overrunning.  (An earlier size formula missed one
+    bucketing array and the kernels wrote past the allocation.)"""
+    w = synth.make_tiny(61, n=5000, d=40, n_q=300, vocabs=(3, 7), label_vocab=10, b=48, h=3, cmin=0, cmax=3)
+    ix = caps.Index.from_workload(w, precision=prec)
+    for k, m in ((1, 1), (10, 12), (64, 48)):
+        need = ix.workspace_bytes(w.n_q, k, m, mode=mode)
+        a = ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m, mode=mode, counters=True)
+        b = ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m, mode=mode, counters=True, workspace_bytes=need)
+        for x, y in zip(a, b):
+            assert np.array_equal(x.cpu().numpy().view(np.uint32), y.cpu().numpy().view(np.uint32))
+        # one byte less: the batch is cut into sub-batches, same results
+        c = ix.search(w.q, w.con_off, w.con_attr, w.con_val, k, m, mode=mode, counters=True,
+                      workspace_bytes=need - 1)
+        for x, y in zip(a, c):
+            assert np.array_equal(x.cpu().numpy().view(np.uint32), y.cpu().numpy().view(np.uint32))
