@@ -193,6 +193,7 @@ struct LowpScan {
     int32_t *oflow;               // exact: per query, set by the main pass for the rescue pass
     const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
     int32_t rescue_grid;          // rescue pass: workgroups walking its tile list (0: default)
+    bool rhalves;                 // rescue pass after a main pass of 128-entry tiles: entries 2 tile + half
 };
 size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);

@@ -38,6 +38,7 @@ struct LowpArgs {
     int32_t *oflow;             // exact: per query flag, set when its pairs did not fit (rescue pass input)
     const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
     int32_t m, h, b, r, metric, d, dcap, ntiles;   // ntiles: length of `tiles` (the grid's tile range)
+    int32_t rhalves;            // rescue pass over 128-entry tiles: list entries are 2 tile + half
     float eta, gam;             // exact: relative rounding margin, MFMA accumulation bound
 };
 
@@ -51,7 +52,8 @@ constexpr int kVRing = 128;      // exact: per-wave ring of pairs awaiting resco
 
 struct LowpLds {
     size_t xw, xn, xsc, buf, bcnt, tau, qslot, qd, ring, dhist, qnq, scnt, total;
-    // kind: 0 approximate keys, 1 exact main pass (no buffers), 2 exact rescue pass.
+    // kind: 0 approximate keys, 1 exact main pass (no buffers), 2 exact rescue
+    // pass, 3 exact main pass counting the survivors of the filter.
     // The chunk tiles themselves are static arrays of the kernel (two of
     // kLCH rows); the per-point arrays here are double buffered alike.
     __host__ __device__ constexpr LowpLds(int cb, int kind, bool labels)
@@ -72,10 +74,10 @@ struct LowpLds {
         xn = take(sizeof(float) * 2 * kLCH);
         xsc = take(sizeof(float) * 2 * kLCH);
         ring = take(kind != 0 ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
-        dhist = take(kind == 1 ? sizeof(int32_t) * kLNW * kLQPW : 0);
+        dhist = take(kind == 1 || kind == 3 ? sizeof(int32_t) * kLNW * kLQPW : 0);
         qnq = take(kind != 0 ? sizeof(float) * kLQB : 0);
         scnt = take(sizeof(int32_t) * kLQB);
-        buf = take(kind == 1 ? 0 : sizeof(uint64_t) * (size_t)kLQB * cb);
+        buf = take(kind == 1 || kind == 3 ? 0 : sizeof(uint64_t) * (size_t)kLQB * cb);
         total = take(16);
     }
 };
@@ -227,10 +229,10 @@ __device__ inline float exact_score(const float *__restrict__ xr, const float *_
 // tiles, looped) and with label tests or longer rows (their state does not
 // fit).
 template <int PREC, bool HAS_LABELS, int CB, int NS, int KIND>
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS || KIND == 2 ? 2 : KIND == 1 ? 4 : 3))) void k_scan_mfma(
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 || HAS_LABELS || KIND == 2 ? 2 : KIND == 1 || KIND == 3 ? 4 : 3))) void k_scan_mfma(
     LowpArgs A) {
     constexpr bool EXACT = KIND != 0;    // exact keys (bounds + exact rescoring)
-    constexpr bool DEFER = KIND == 1;    // main pass: passing pairs go to the deferred lists
+    constexpr bool DEFER = KIND == 1 || KIND == 3;   // main pass: passing pairs go to the deferred lists
     constexpr bool RESCUE = KIND == 2;   // rescue pass: flagged queries only, rescored here
     typedef MfmaOp<PREC> Op;
     typedef typename Op::T VT;
@@ -260,8 +262,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     // one tile per workgroup; the rescue pass (a small grid) walks the list
     // of tiles that hold a flagged query, written by k_rescue_tiles, with a
     // workgroup barrier between consecutive tiles.
-    auto run_tile = [&](const int tile) {
-    const int4 dsc = A.tiles[tile];
+    auto run_tile = [&](int4 dsc) {
     if (dsc.z <= 0) return;
     const int p = dsc.x;
     const int nqt = dsc.z;
@@ -286,7 +287,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
     const bool has_dense = A.words != nullptr;
     const bool has_lab = A.sigs != nullptr;
     const bool l2 = A.metric == 0;
-    const bool count = A.nsurv != nullptr;
+    // survivor counts: the main pass has a counting kind of its own, so that
+    // the uncounted one tests the packed dense fields only where a score passed
+    const bool count = KIND == 3 ? true : KIND == 1 ? false : A.nsurv != nullptr;
     const float qnan = __builtin_nanf("");
     const float inf = __builtin_huge_valf();
     const float cm = l2 ? -2.0f : -1.0f;   // score = cm * dot + per-point term
@@ -635,9 +638,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                     float dd = acc[bb][rr];
                     if (PREC == CAPS_PREC_FP8) dd = dd * ps * rqs[rr];
                     esc[rr] = fmaf(cm, dd, pn);
-                    // two single-compare ballots: each is one v_cmp into an SGPR pair
-                    hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]) &
-                              __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
+                    // a single-compare ballot: one v_cmp into an SGPR pair
+                    hit[rr] = __builtin_amdgcn_ballot_w64(esc[rr] <= tfj[rr]);
+                }
+                // the packed dense test, only for blocks where a score passed
+                // (rare once the bounds are set: most blocks skip it)
+                if (hit[0] | hit[1] | hit[2] | hit[3]) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; rr++) hit[rr] &= __builtin_amdgcn_ballot_w64((pw & rmask[rr]) == rval[rr]);
                 }
                 if (count) {   // survivors of the exact filter (statistics only)
 #pragma unroll
@@ -752,13 +760,379 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         // the start of a tile and read until its end
         const int nr = *A.rcount;
         for (int i = blockIdx.x; i < nr; i += gridDim.x) {
-            run_tile(A.rlist[i]);
+            const int e = A.rlist[i];
+            int4 dsc = A.tiles[A.rhalves ? e >> 1 : e];
+            if (A.rhalves) {   // the 64 entries of one half of a 128-entry tile
+                dsc.y += kLQB * (e & 1);
+                dsc.z = min(kLQB, dsc.z - kLQB * (e & 1));
+            }
+            run_tile(dsc);
             __syncthreads();
         }
     } else {
         const int tile = xcd_tile(blockIdx.x, A.ntiles);
-        if (tile >= 0) run_tile(tile);
+        if (tile >= 0) run_tile(A.tiles[tile]);
     }
+}
+
+// ------------------------------------------------ exact main pass, 32 x 32
+// The exact main pass of two-byte copies with rows of at most four 32-element
+// steps, without label tests or disjunctions (the other cases run
+// k_scan_mfma).  Same bound, point term and element test as k_scan_mfma's
+// exact main pass; what differs is the blocking:
+//  * a tile holds up to 128 (query, probe) entries of one partition, wave w
+//    the 32 queries 32w..32w+31, whose operands stay in registers;
+//  * each product is a 32 x 32 block (points x queries, K = 16 per step), so
+//    a staged row read from LDS serves 32 queries instead of 16;
+//  * chunks are 32 rows, staged by direct loads three chunks ahead into four
+//    buffers, with explicit per-wave wait counts and plain barriers;
+//  * the packed dense test runs only for the products where a score passed.
+// Element r of lane l is point 8(r/4) + 4(l/32) + r%4 of the chunk and query
+// l%32 of the wave.
+constexpr int kXW = 4;                 // waves per tile
+constexpr int kXQ = 32;                // queries per wave
+constexpr int kXQB = kXW * kXQ;        // entries per tile
+constexpr int kXCH = 32;               // rows per chunk
+constexpr int kXRing = 64;             // per-wave ring of deferred pairs
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int PREC>
+struct Mfma32;
+template <>
+struct Mfma32<CAPS_PREC_BF16> {
+    typedef bf16x8 T;
+    __device__ static f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mfma32<CAPS_PREC_FP16> {
+    typedef f16x8 T;
+    __device__ static f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+
+__host__ __device__ constexpr bool lowp_x32_kernel(int prec, int ns, bool lab) {
+    return (prec == CAPS_PREC_BF16 || prec == CAPS_PREC_FP16) && (ns == 1 || ns == 2 || ns == 4) && !lab;
+}
+
+template <int PREC, int NS, bool COUNT>
+__global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_x32(LowpArgs A) {
+    typedef typename Mfma32<PREC>::T VT;
+    constexpr int ROWB = NS * 64;                  // bytes per row of the copy
+    constexpr int KS = ROWB / 32;                  // 16-element steps per row
+    constexpr int V16 = ROWB / 16;                 // 16-byte pieces per row
+    constexpr int NDMA = kXCH * ROWB / 1024;       // 1 KB direct loads per chunk
+    constexpr int UPW = (NDMA + kXW - 1) / kXW;
+    constexpr int RPL = ROWB >= 256 ? 1 : 256 / ROWB;
+    constexpr int SWZ = ROWB >= 256 ? 15 : V16 - 1;
+    constexpr int PRE = 4;                         // wave 0's per-point direct loads per chunk
+    // the four chunk buffers: distinct arrays, so that the compiler can tell
+    // the reads of one from the direct loads into the others
+    __shared__ __align__(16) uint8_t xb0[kXCH * ROWB];
+    __shared__ __align__(16) uint8_t xb1[kXCH * ROWB];
+    __shared__ __align__(16) uint8_t xb2[kXCH * ROWB];
+    __shared__ __align__(16) uint8_t xb3[kXCH * ROWB];
+    __shared__ __align__(16) float rw0[PRE][64];   // the per-point inputs of each buffer's chunk
+    __shared__ __align__(16) float rw1[PRE][64];
+    __shared__ __align__(16) float rw2[PRE][64];
+    __shared__ __align__(16) float rw3[PRE][64];
+    __shared__ __align__(16) uint32_t xw[2][kXCH];
+    __shared__ __align__(16) float xn[2][kXCH];
+    __shared__ uint32_t ring[kXW][2][kXRing];
+    __shared__ int32_t dhist[kXW][kXQ];
+    __shared__ int32_t scnt[kXQB];
+    __shared__ float qmx[2][kXW];
+    __shared__ uint32_t lvw[kXW];
+    __shared__ int32_t spo[kMaxHeight + 2];
+
+    const int tile = xcd_tile(blockIdx.x, A.ntiles);
+    if (tile < 0) return;
+    const int4 dsc = A.tiles[tile];
+    if (dsc.z <= 0) return;
+    const int p = dsc.x;
+    const int nqt = dsc.z;
+    const int32_t *ent = A.entries + dsc.y;
+    const int h = A.h;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int g = lane >> 5, c32 = lane & 31;
+    const bool has_dense = A.words != nullptr;
+    const bool l2 = A.metric == 0;
+    const float qnan = __builtin_nanf("");
+    const float inf = __builtin_huge_valf();
+    const float cm = l2 ? -2.0f : -1.0f;   // score = cm * dot + per-point term
+
+    // ---- the lane's query: tile entry 32w + c32 (lanes l and l + 32 share it)
+    const int qi = kXQ * w + c32;
+    const bool own = qi < nqt;
+    int32_t my_slot = 0, my_qq = 0;
+    uint32_t my_sel = 0, my_mask = 0, my_val = 1;   // a lane without a query never matches
+    float my_tf = qnan, qa = 0.0f, qb = 0.0f;
+    if (own) {
+        my_slot = ent[qi];
+        my_qq = my_slot / A.m;
+        my_sel = A.sel[my_slot];
+        my_mask = A.qd[my_qq].dmask;
+        my_val = A.qd[my_qq].dval;
+        const float4 ax = *reinterpret_cast<const float4 *>(A.qaux + 4 * (int64_t)my_qq);
+        qa = ax.x;
+        qb = fmaf(A.gam, ax.w, ax.z);
+        // the bound, read once per tile (the main pass keeps no keys)
+        const float td = bound_score(__hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const float nq = ax.y;
+        my_tf = !(td < inf) ? inf
+                : l2        ? fmaf(A.eta, nq + td, td - nq) + 1e-37f
+                            : fmaf(A.eta, nq + fabsf(td), td) + 1e-37f;
+    }
+    // tile maxima of |q| and |q - q~| + gam |q~| (the point term's error
+    // products) and the levels any query of the tile selects
+    uint32_t lv = my_sel;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        qa = fmaxf(qa, __shfl_xor(qa, o, 64));
+        qb = fmaxf(qb, __shfl_xor(qb, o, 64));
+        lv |= __shfl_xor(lv, o, 64);
+    }
+    if (lane == 0) {
+        qmx[0][w] = qa;
+        qmx[1][w] = qb;
+        lvw[w] = lv;
+    }
+    if (COUNT && w == 0) {
+        scnt[lane] = 0;
+        scnt[lane + 64] = 0;
+    }
+    if (t <= h + 1) spo[t] = A.offs[(int64_t)p * (h + 1) + t];   // level starts (and the end)
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kXW; i++) {
+        qa = fmaxf(qa, qmx[0][i]);
+        qb = fmaxf(qb, qmx[1][i]);
+        lv |= lvw[i];
+    }
+    lv = __builtin_amdgcn_readfirstlane(lv);
+    // MFMA B operands: the lane's query, K slice 8g of each step
+    VT bq[KS];
+    {
+        const uint8_t *src = A.qlow + (int64_t)my_qq * ROWB + 16 * g;
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+            bq[s] = own ? __builtin_bit_cast(VT, *reinterpret_cast<const uint4 *>(src + 32 * s)) : VT{};
+    }
+    // MFMA A operands: row c32 of a staged chunk, K slice 8g of step s at
+    // c32 ROWB + 16 ((2s + g) ^ swizzle) = xo ^ 32s (the row's bytes are a
+    // power of two and 2s + g = 2s | g)
+    const uint32_t xo = (uint32_t)(c32 * ROWB + 16 * (g ^ ((c32 / RPL) & SWZ)));
+
+    // chunk cursors (wave-uniform): level j, first row c0, end of the level
+    // (level bounds from LDS: a global load here would wait for every
+    // direct load in flight)
+    auto next_level = [&](int &j, int32_t &c0, int32_t &end) {
+        for (j++; j <= h; j++) {
+            if (!((lv >> j) & 1u)) continue;
+            c0 = __builtin_amdgcn_readfirstlane(spo[j]);
+            end = __builtin_amdgcn_readfirstlane(spo[j + 1]);
+            if (c0 < end) return;
+        }
+    };
+    auto advance = [&](int &j, int32_t &c0, int32_t &end) {
+        c0 += kXCH;
+        if (c0 >= end) next_level(j, c0, end);
+    };
+
+    // Staging.  Every wave issues the same loads per chunk (UPW row loads
+    // and one per-point load), always, so that one wait count holds for all
+    // waves and every path (a missing chunk loads row 0 into the unused
+    // buffer instead).  Row load i, lane L fills tile bytes 1024 i + 16 L:
+    // row (64 i + L) / V16, piece (64 i + L) % V16, which holds global piece
+    // piece ^ swizzle of the row; rows past the level's end load its last row
+    // and are masked by a NaN point term; loads past NDMA (short rows) repeat
+    // load i - NDMA.  Per-point load of wave w, lane L: input w (squared
+    // norm, error norms, packed dense word) of row c0 + min(L, cn - 1).
+    uint32_t voff[UPW];
+    int vrow[UPW];
+#pragma unroll
+    for (int u = 0; u < UPW; u++) {
+        const int i = (w + kXW * u) % NDMA;
+        const int slot = 64 * i + lane;
+        const int row = slot / V16;
+        vrow[u] = row;
+        voff[u] = (uint32_t)(row * ROWB + 16 * ((slot % V16) ^ ((row / RPL) & SWZ)));
+    }
+    constexpr int OPC = UPW + 1;   // loads per wave per chunk
+    const uint32_t *wsrc = has_dense ? A.words : reinterpret_cast<const uint32_t *>(A.xnorm);
+    const float *psrc = w == 0   ? A.xnorm
+                        : w == 1 ? A.lerr
+                        : w == 2 ? A.lnrm
+                                 : reinterpret_cast<const float *>(wsrc);
+    auto fetch_rows = [&](bool real, int32_t c0, int cn, uint8_t *dst) {
+        const uint8_t *base = real ? A.lvecs + (int64_t)c0 * ROWB : A.lvecs;
+#pragma unroll
+        for (int u = 0; u < UPW; u++) {
+            const int i = (w + kXW * u) % NDMA;
+            uint32_t off = real ? voff[u] : 0u;
+            if (real && cn < kXCH) off -= (uint32_t)(max(vrow[u] - (cn - 1), 0) * ROWB);
+            __builtin_amdgcn_global_load_lds(base + off, (__attribute__((address_space(3))) void *)(dst + 1024 * i), 16,
+                                             0, 0);
+        }
+    };
+    auto fetch_points = [&](bool real, int32_t c0, int cn, float (*raw)[64]) {
+        const int64_t row = real ? c0 + min(lane, cn - 1) : 0;
+        __builtin_amdgcn_global_load_lds(psrc + row, (__attribute__((address_space(3))) void *)raw[w], 4, 0, 0);
+    };
+    // wave 0: the point terms of a chunk whose per-point inputs have landed
+    auto point_terms = [&](float (*raw)[64], int cn, int pb) {
+        const float nx = raw[0][c32];
+        const float slack = fmaf(raw[1][c32], qa, raw[2][c32] * qb) * (1.0f + 0x1p-20f);
+        float pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
+        if (!(fabsf(pt) < inf)) pt = -inf;
+        xn[pb][c32] = c32 < cn ? pt : qnan;   // (lanes l and l + 32 write alike)
+        xw[pb][c32] = has_dense ? __float_as_uint(raw[3][c32]) : 0u;
+    };
+
+    // deferred pairs of this wave: (CSR position, wave query) in a ring of
+    // 64, appended to their queries' lists when a ballot's pairs would not
+    // fit (per-query ranks from an LDS histogram, one returning atomic per
+    // query); a query whose list is full is flagged for the rescue pass
+    uint32_t *ring_pos = ring[w][0];
+    uint32_t *ring_row = ring[w][1];
+    int32_t *hist = dhist[w];
+    int vhead = 0, vtail = 0;
+    auto drain = [&](int n) {
+        wave_sync();
+        const bool v = lane < n;
+        const int slot = (vtail + lane) & (kXRing - 1);
+        const uint32_t pos = v ? ring_pos[slot] : 0u;
+        const int qj = v ? (int)ring_row[slot] : 0;
+        vtail += n;
+        if (lane < kXQ) hist[lane] = 0;
+        wave_sync();
+        const int rank = v ? atomicAdd(hist + qj, 1) : 0;
+        wave_sync();
+        const int cnt = lane < kXQ ? hist[lane] : 0;
+        int base = 0;
+        if (cnt > 0) base = atomicAdd(A.dcnt + my_qq, cnt);
+        const int at = __shfl(base, qj, 64) + rank;
+        const int32_t qq = __shfl(my_qq, qj, 64);
+        if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = (int32_t)pos;
+        if (v && at >= A.dcap) A.oflow[qq] = 1;
+    };
+
+    // ---- pipeline.  Fetch F_c = rows of chunk c into buffer c % 4 and the
+    // per-point inputs of chunk c + 1 into slot (c + 1) % 4.  Step k waits
+    // for F_k (two later fetches may stay in flight), passes the barrier,
+    // issues F_{k+3}, lets wave 0 turn the inputs of chunk k + 1 into its
+    // point terms, and scores chunk k.
+    int cj = -1;
+    int32_t cc0 = 0, cend = 0;
+    next_level(cj, cc0, cend);
+    if (cj > h) {   // nothing to scan
+        if (g == 0 && own) A.pcnt[my_slot] = 0;
+        return;
+    }
+    // fetch cursor (chunk of the rows of the next fetch) and the chunk after it
+    int fj = cj, rj = cj;
+    int32_t fc0 = cc0, fend = cend, rc0 = cc0, rend = cend;
+    advance(rj, rc0, rend);
+    auto fetch_next = [&](uint8_t *dst, float (*raw)[64]) {
+        const bool fr = fj <= h, rr = rj <= h;
+        fetch_rows(fr, fc0, fr ? min(kXCH, fend - fc0) : 1, dst);
+        fetch_points(rr, rc0, rr ? min(kXCH, rend - rc0) : 1, raw);
+        if (fr) advance(fj, fc0, fend);
+        if (rr) advance(rj, rc0, rend);
+    };
+    fetch_points(true, cc0, min(kXCH, cend - cc0), rw0);   // the inputs of chunk 0
+    fetch_next(xb0, rw1);
+    fetch_next(xb1, rw2);
+    fetch_next(xb2, rw3);
+    // the first three chunks have landed on every wave (waiting for all of
+    // them lets the compiler's own wait tracking enter the loop with nothing
+    // in flight)
+    __builtin_amdgcn_s_waitcnt(0xC07F & 0x0F70);   // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    if (w == 0) point_terms(rw0, min(kXCH, cend - cc0), 0);
+    int lj = -1;
+    float tfj = qnan;
+
+    // Chunk k from buffer `cur` (point arrays `pb`); `nraw` holds the inputs
+    // of chunk k + 1; F_{k+3} goes to `nxt` and `fraw`.  Returns whether
+    // another chunk follows.
+    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb, float (*nraw)[64], float (*fraw)[64]) -> bool {
+        const int j = cj;
+        const int32_t c0 = cc0;
+        const int cn = min(kXCH, cend - c0);
+        // F_k has landed once at most the two later fetches are outstanding
+        // (stores and atomics issued since only make the wait stricter); the
+        // point terms wave 0 wrote are complete
+        __builtin_amdgcn_s_waitcnt(0xC07F & (0x0F70 | ((2 * OPC) & 15) | (((2 * OPC) >> 4) << 14)));
+        __builtin_amdgcn_s_barrier();
+        advance(cj, cc0, cend);
+        const bool more = cj <= h;
+        fetch_next(nxt, fraw);
+        if (w == 0 && more) point_terms(nraw, min(kXCH, cend - cc0), pb ^ 1);
+
+        f32x16 acc = {};
+#pragma unroll
+        for (int s0 = 0; s0 < KS; s0 += 2) {   // operands of two steps, then their products
+            VT a[2];
+#pragma unroll
+            for (int s = s0; s < s0 + 2; s++)
+                a[s - s0] = __builtin_bit_cast(VT, *reinterpret_cast<const uint4 *>(cur + (xo ^ (32u * s))));
+#pragma unroll
+            for (int s = s0; s < s0 + 2; s++) acc = Mfma32<PREC>::mma(a[s - s0], bq[s], acc);
+        }
+
+        if (j != lj) {   // level changed: the query's bound if it selects the level, NaN if not
+            lj = j;
+            tfj = ((my_sel >> j) & 1u) ? my_tf : qnan;
+        }
+        const bool sj = (my_sel >> j) & 1u;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; q4++) {   // points 8 q4 + 4 g + e of the chunk, e < 4
+            const int rb = 8 * q4 + 4 * g;
+            const float4 pn = *reinterpret_cast<const float4 *>(&xn[pb][rb]);
+            const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
+            uint64_t hit[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) hit[e] = __builtin_amdgcn_ballot_w64(fmaf(cm, acc[4 * q4 + e], pv[e]) <= tfj);
+            if (COUNT) {   // survivors of the exact filter (statistics only)
+                const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
+                const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
+                int c = 0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) c += (sj && rb + e < cn && (wv[e] & my_mask) == my_val) ? 1 : 0;
+                if (c) atomicAdd(&scnt[qi], c);
+            }
+            if (!(hit[0] | hit[1] | hit[2] | hit[3])) continue;
+            {   // the packed dense test where a score passed
+                const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
+                const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) hit[e] &= __builtin_amdgcn_ballot_w64((wv[e] & my_mask) == my_val);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint64_t hm = hit[e];
+                if (!hm) continue;
+                const int n = __popcll(hm);   // at most 64
+                if (vhead - vtail + n > kXRing) drain(vhead - vtail);
+                if ((hm >> lane) & 1ull) {
+                    const int sl = (vhead + __popcll(hm & lanemask_lt())) & (kXRing - 1);
+                    ring_pos[sl] = (uint32_t)(c0 + rb + e);
+                    ring_row[sl] = (uint32_t)c32;
+                }
+                vhead += n;
+            }
+        }
+        return more;
+    };
+    while (step(xb0, xb3, 0, rw1, rw0) && step(xb1, xb0, 1, rw2, rw1) && step(xb2, xb1, 0, rw3, rw2) &&
+           step(xb3, xb2, 1, rw0, rw3)) {
+    }
+    if (vhead > vtail) drain(vhead - vtail);
+    if (COUNT) {
+        __syncthreads();
+        if (g == 0 && own && scnt[qi]) atomicAdd(&A.nsurv[my_qq], scnt[qi]);
+    }
+    // the main pass keeps no keys: its partial lists are empty
+    if (g == 0 && own) A.pcnt[my_slot] = 0;
 }
 
 typedef void (*LowpFn)(LowpArgs);
@@ -769,11 +1143,16 @@ inline int lowp_cb(int r) { return r <= 16 ? 32 : r <= 48 ? 64 : 128; }
 
 template <int PREC, bool LAB, int NS, int KIND>
 LowpFn pick_cb(int r) {
-    if (KIND == 1) return k_scan_mfma<PREC, LAB, 32, NS, KIND>;   // (keeps no keys)
-    const int cb = lowp_cb(r);
-    if (cb == 32) return k_scan_mfma<PREC, LAB, 32, NS, KIND>;
-    if (cb == 64) return k_scan_mfma<PREC, LAB, 64, NS, KIND>;
-    return k_scan_mfma<PREC, LAB, 128, NS, KIND>;
+    if constexpr ((KIND == 1 || KIND == 3) && lowp_x32_kernel(PREC, NS, LAB)) {
+        return k_scan_x32<PREC, NS, KIND == 3>;
+    } else if constexpr (KIND == 1 || KIND == 3) {
+        return k_scan_mfma<PREC, LAB, 32, NS, KIND>;   // (keeps no keys)
+    } else {
+        const int cb = lowp_cb(r);
+        if (cb == 32) return k_scan_mfma<PREC, LAB, 32, NS, KIND>;
+        if (cb == 64) return k_scan_mfma<PREC, LAB, 64, NS, KIND>;
+        return k_scan_mfma<PREC, LAB, 128, NS, KIND>;
+    }
 }
 
 template <int PREC, int NS, int KIND>
@@ -787,11 +1166,14 @@ LowpFn pick_ns(int ns, bool lab, int r);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 2>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, 3>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 2>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, 3>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 2>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, 3>(int, bool, int);
 
 }  // namespace caps

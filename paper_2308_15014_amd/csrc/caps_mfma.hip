@@ -409,7 +409,7 @@ static LowpFn pick_prec(int prec, int ns, bool lab, int r) {
 constexpr int64_t kRescueWgs = 8192;
 
 size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj) {
-    return LowpLds(kind == 1 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0 || disj).total + 64;
+    return LowpLds(kind == 1 || kind == 3 ? 32 : lowp_cb(r), kind, ix->sch.label_vocab > 0 || disj).total + 64;
 }
 
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
@@ -446,6 +446,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.oflow = S.oflow;
     A.rlist = S.rlist;
     A.rcount = S.rcount;
+    A.rhalves = S.rhalves ? 1 : 0;
     A.m = S.m;
     A.h = ix->h;
     A.b = ix->b;
@@ -464,9 +465,12 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     // the variant with the filter's slow path: label tests, disjunctions
     const bool lab = ix->sch.label_vocab > 0 || S.disj;
     const LowpFn fn = S.kind == 0   ? pick_prec<0>(ix->prec, ix->dpad / 32, lab, S.r)
-                      : S.kind == 1 ? pick_prec<1>(ix->prec, ix->dpad / 32, lab, S.r)
+                      : S.kind == 1 ? (S.nsurv ? pick_prec<3>(ix->prec, ix->dpad / 32, lab, S.r)
+                                               : pick_prec<1>(ix->prec, ix->dpad / 32, lab, S.r))
                                     : pick_prec<2>(ix->prec, ix->dpad / 32, lab, S.r);
-    const size_t lds = lowp_scan_lds(ix, S.r, S.kind, S.disj);
+    // (the 32 x 32 main pass holds its arrays in static LDS)
+    const bool x32 = S.kind == 1 && lowp_x32_kernel(ix->prec, ix->dpad / 32, lab);
+    const size_t lds = x32 ? 0 : lowp_scan_lds(ix, S.r, S.kind, S.disj);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(S.stage, st);
     // the rescue pass walks its (device-side) tile list with a bounded grid
@@ -495,5 +499,9 @@ caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32
 }
 
 int lowp_qb() { return kLQB; }
+
+int lowp_qb_main(const Index *ix, bool disj) {
+    return lowp_x32_kernel(ix->prec, ix->dpad / 32, ix->sch.label_vocab > 0 || disj) ? kXQB : kLQB;
+}
 
 }  // namespace caps

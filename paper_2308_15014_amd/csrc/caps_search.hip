@@ -734,17 +734,22 @@ __global__ __launch_bounds__(1024) void k_rescue_init(const int32_t *__restrict_
 }
 
 // Tiles of the exact main pass that hold a flagged query: listed (in any
-// order) for the rescue pass.  One thread per tile.
+// order) for the rescue pass, whose tiles hold up to `qr` entries.  Main-pass
+// tiles of 2 qr entries are listed by half (entry 2 t + half).  One thread
+// per tile.
 __global__ __launch_bounds__(256) void k_rescue_tiles(const int4 *__restrict__ tiles, int32_t ntiles,
                                                       const int32_t *__restrict__ entries, int32_t m,
-                                                      const int32_t *__restrict__ oflow, int32_t *__restrict__ rlist,
-                                                      int32_t *__restrict__ rcount) {
+                                                      const int32_t *__restrict__ oflow, int32_t qr, int32_t halves,
+                                                      int32_t *__restrict__ rlist, int32_t *__restrict__ rcount) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles || rcount[1] == 0) return;
     const int4 dsc = tiles[t];
-    bool hit = false;
-    for (int i = 0; i < dsc.z && !hit; i++) hit = oflow[entries[dsc.y + i] / m] != 0;
-    if (hit) rlist[atomicAdd(rcount, 1)] = t;
+    for (int hf = 0; hf <= halves; hf++) {
+        const int i0 = hf * qr, i1 = halves ? min(dsc.z, i0 + qr) : dsc.z;
+        bool hit = false;
+        for (int i = i0; i < i1 && !hit; i++) hit = oflow[entries[dsc.y + i] / m] != 0;
+        if (hit) rlist[atomicAdd(rcount, 1)] = halves ? 2 * t + hf : t;
+    }
 }
 
 // ------------------------------------------------------------------ scan
@@ -1280,6 +1285,7 @@ struct Arena {
 };
 
 int lowp_qb();
+int lowp_qb_main(const Index *ix, bool disj);
 
 struct SearchWs {
     uint8_t *qlow;
@@ -1337,7 +1343,8 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.oflow = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
-    w.rlist = defer ? ar.take<int32_t>(tile_cap(sb, m, b)) : nullptr;
+    // (main-pass tiles of 128 entries are listed by half: one more per partition)
+    w.rlist = defer ? ar.take<int32_t>(tile_cap(sb, m, b) + b) : nullptr;
     w.rcount = defer ? ar.take<int32_t>(2) : nullptr;
     w.hist = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
@@ -1636,6 +1643,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
                 const int32_t r1 = round == 0 ? s_seed : m;
                 if (r0 >= r1) continue;
+                // tile width of this round: the exact main pass may run 128-entry tiles
+                const int qbr = mfma && !lowp && !(seeded_exact && round == 0) ? lowp_qb_main(ix, disj) : qb;
                 prof_begin(CAPS_STAGE_SELECT, st);
                 hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                    nb, m, r0, r1, b, ngrp, hist);
@@ -1643,12 +1652,12 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, W.scan_sums, st);
                     if (es != CAPS_OK) return es;
                 }
-                hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qb, pstart, pcount,
+                hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, hscan, htotal, b, ngrp, qbr, pstart, pcount,
                                    tstart);
-                const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qb - 1) / qb + b;
+                const int64_t max_tiles = ((int64_t)nb * (r1 - r0) + qbr - 1) / qbr + b;
                 const int64_t grid = (max_tiles + kXcds - 1) / kXcds * kXcds;
                 hipLaunchKernelGGL(k_tile_desc, dim3(nblocks(grid, 256)), dim3(256), 0, st, tstart, pstart, pcount, b,
-                                   qb, (int32_t)grid, W.tiles);
+                                   qbr, (int32_t)grid, W.tiles);
                 // the fill packs each entry's class when entries stay below 2^27
                 const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
                 hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
@@ -1694,8 +1703,10 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     if (S.kind == 1) {   // rescue pass over the tiles that hold a flagged query
                         hipLaunchKernelGGL(k_rescue_init, dim3(1), dim3(1024), 0, st, W.oflow, nb, W.rcount);
                         hipLaunchKernelGGL(k_rescue_tiles, dim3(nblocks(grid, 256)), dim3(256), 0, st, W.tiles,
-                                           (int32_t)grid, ent, m, W.oflow, W.rlist, W.rcount);
+                                           (int32_t)grid, ent, m, W.oflow, qb, (int32_t)(qbr != qb), W.rlist,
+                                           W.rcount);
                         S.kind = 2;
+                        S.rhalves = qbr != qb;
                         S.rlist = W.rlist;
                         S.rcount = W.rcount;
                         S.nsurv = nullptr;
