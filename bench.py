@@ -61,9 +61,9 @@ FLUSH_BYTES = 512 << 20
 # factor 1.00).  Valid only for the kernel sources they were taken on (SHA-256 of the two
 # files below) and that workload; otherwise the line reports null.
 MAIN_PASS_TRAFFIC = {
-    "sources_sha256": "a86611273e3239998321634f840af7fba81b96ccc07f432409ab66f9b106162a",
+    "sources_sha256": "818bc34c2c1802d8a05c17cf3cfd7abf87f02c7676c0567f14853990169de0cf",
     "nprobe": 624, "n_queries": 10_000,
-    "fetch_kib": 1_133_089, "write_kib": 245_929, "read_factor": 2.00, "write_factor": 1.00,
+    "fetch_kib": 1_207_490, "write_kib": 240_971, "read_factor": 2.00, "write_factor": 1.00,
 }
 SCAN_SOURCES = ("paper_2308_15014_amd/csrc/caps_mfma.h", "paper_2308_15014_amd/csrc/caps_scan_inst.hip")
 
@@ -940,10 +940,13 @@ def main():
                   w.n_q * (4.0 * m * (2 * w.aft_height + 2) + 4 * w.d + 8 * k)) / launches_per_step
         pn = {"bf16": "BF16", "fp16": "FP16", "fp8": "FP8"}[args.precision]
         kern = ("k_scan_fp32 (filter + exact FP32 squared-L2 scan + per-partition top-k)" if mode == 2 else
-                f"k_scan_mfma<{args.precision}> " +
-                (f"exact main pass ({pn} lower bounds on MFMA, exact filter epilogue, passing pairs deferred to "
-                 "the FP32 rescoring merge)" if mode == 0 else
-                 f"approximate keys ({pn} scores on MFMA, exact filter, per-query top-4k)"))
+                (f"k_scan_x32<{args.precision}> exact main pass ({pn} lower bounds on 32x32 MFMA blocks, exact "
+                 "filter where a score passes, passing pairs deferred to the FP32 rescoring merge)"
+                 if args.precision != "fp8" else
+                 f"k_scan_mfma<{args.precision}> exact main pass ({pn} lower bounds on MFMA, exact filter "
+                 "epilogue, passing pairs deferred to the FP32 rescoring merge)") if mode == 0 else
+                f"k_scan_mfma<{args.precision}> approximate keys ({pn} scores on MFMA, exact filter, "
+                "per-query top-4k)")
         roof = {"kernel": kern, "avg_launch_ms": round(scan_avg_s * 1e3, 4),
                 "method_flops": {"per_launch": flops_method,
                                  "tflops": round(flops_method / scan_avg_s / 1e12, 3),

@@ -823,7 +823,8 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     constexpr int UPW = (NDMA + kXW - 1) / kXW;
     constexpr int RPL = ROWB >= 256 ? 1 : 256 / ROWB;
     constexpr int SWZ = ROWB >= 256 ? 15 : V16 - 1;
-    constexpr int PRE = 4;                         // wave 0's per-point direct loads per chunk
+    constexpr int PRE = 4;                         // per-point inputs per chunk (one direct load per wave)
+    static_assert(PRE == kXW, "each wave stages one per-point input");
     // the four chunk buffers: distinct arrays, so that the compiler can tell
     // the reads of one from the direct loads into the others
     __shared__ __align__(16) uint8_t xb0[kXCH * ROWB];
@@ -977,7 +978,8 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         const int64_t row = real ? c0 + min(lane, cn - 1) : 0;
         __builtin_amdgcn_global_load_lds(psrc + row, (__attribute__((address_space(3))) void *)raw[w], 4, 0, 0);
     };
-    // wave 0: the point terms of a chunk whose per-point inputs have landed
+    // the point terms of a chunk whose per-point inputs have landed (one
+    // wave per chunk, in turn)
     auto point_terms = [&](float (*raw)[64], int cn, int pb) {
         const float nx = raw[0][c32];
         const float slack = fmaf(raw[1][c32], qa, raw[2][c32] * qb) * (1.0f + 0x1p-20f);
@@ -1018,7 +1020,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     // ---- pipeline.  Fetch F_c = rows of chunk c into buffer c % 4 and the
     // per-point inputs of chunk c + 1 into slot (c + 1) % 4.  Step k waits
     // for F_k (two later fetches may stay in flight), passes the barrier,
-    // issues F_{k+3}, lets wave 0 turn the inputs of chunk k + 1 into its
+    // issues F_{k+3}, lets wave k % 4 turn the inputs of chunk k + 1 into its
     // point terms, and scores chunk k.
     int cj = -1;
     int32_t cc0 = 0, cend = 0;
@@ -1052,9 +1054,10 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     float tfj = qnan;
 
     // Chunk k from buffer `cur` (point arrays `pb`); `nraw` holds the inputs
-    // of chunk k + 1; F_{k+3} goes to `nxt` and `fraw`.  Returns whether
-    // another chunk follows.
-    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb, float (*nraw)[64], float (*fraw)[64]) -> bool {
+    // of chunk k + 1, whose point terms wave `ptw` (k % 4) computes; F_{k+3}
+    // goes to `nxt` and `fraw`.  Returns whether another chunk follows.
+    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb, float (*nraw)[64], float (*fraw)[64],
+                    const int ptw) -> bool {
         const int j = cj;
         const int32_t c0 = cc0;
         const int cn = min(kXCH, cend - c0);
@@ -1066,7 +1069,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         advance(cj, cc0, cend);
         const bool more = cj <= h;
         fetch_next(nxt, fraw);
-        if (w == 0 && more) point_terms(nraw, min(kXCH, cend - cc0), pb ^ 1);
+        if (w == ptw && more) point_terms(nraw, min(kXCH, cend - cc0), pb ^ 1);
 
         f32x16 acc = {};
 #pragma unroll
@@ -1123,8 +1126,8 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         return more;
     };
-    while (step(xb0, xb3, 0, rw1, rw0) && step(xb1, xb0, 1, rw2, rw1) && step(xb2, xb1, 0, rw3, rw2) &&
-           step(xb3, xb2, 1, rw0, rw3)) {
+    while (step(xb0, xb3, 0, rw1, rw0, 0) && step(xb1, xb0, 1, rw2, rw1, 1) && step(xb2, xb1, 0, rw3, rw2, 2) &&
+           step(xb3, xb2, 1, rw0, rw3, 3)) {
     }
     if (vhead > vtail) drain(vhead - vtail);
     if (COUNT) {
