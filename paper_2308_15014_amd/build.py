@@ -13,10 +13,10 @@ SOURCES = ["caps_api.hip", "caps_build.hip", "caps_search.hip", "caps_mfma.hip",
 # caps_scan_inst.hip once per (precision, kind): the matrix-core scan
 # instantiations, compiled in parallel (CAPS_PREC_BF16 = 1, FP8 = 2, FP16 = 3;
 # kinds: approximate keys, exact main pass, exact rescue pass, exact main pass
-# with survivor counts)
+# with survivor counts, seed lists)
 INSTANCES = [(f"caps_scan_{name}_{kind}", ["-DCAPS_INST_PREC=%d" % prec, "-DCAPS_INST_KIND=%d" % kd])
              for name, prec in (("bf16", 1), ("fp8", 2), ("fp16", 3))
-             for kind, kd in (("approx", 0), ("exact", 1), ("rescue", 2), ("exactcnt", 3))]
+             for kind, kd in (("approx", 0), ("exact", 1), ("rescue", 2), ("exactcnt", 3), ("seed", 4))]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written out
 # explicitly (fmaf); the compiler must not fuse anything else, so that the

@@ -174,7 +174,8 @@ caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32
 // one launch of the matrix-core scan over a sub-batch of nb queries
 struct LowpScan {
     int32_t nb, m, r;             // r: keys kept per (query, probe)
-    int kind;                     // 0 approximate keys, 1 exact main pass, 2 exact rescue pass
+    int kind;                     // 0 approximate keys, 1 exact main pass, 2 exact rescue pass, 4 seed lists
+                                  // (approximate keys of the seed probes on 32 x 32 blocks)
     int stage;                    // profiling stage of the launch (CAPS_STAGE_SCAN or _SEED)
     int64_t max_tiles;
     const int4 *tiles;            // per tile: partition, first entry, entries (0: none)

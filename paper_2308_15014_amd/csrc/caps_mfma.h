@@ -788,7 +788,11 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 //    buffers, with explicit per-wave wait counts and plain barriers;
 //  * the packed dense test runs only for the products where a score passed.
 // Element r of lane l is point 8(r/4) + 4(l/32) + r%4 of the chunk and query
-// l%32 of the wave.
+// l%32 of the wave.  MODE 0 is the exact main pass, MODE 1 the same counting
+// the survivors of the filter, MODE 2 the seed pass of the exact search:
+// approximate keys (plain point term) of the first probes, of which each
+// lane keeps its MH best that pass the filter in registers, written as the
+// (query, probe)'s partial list for the exact seed bound.
 constexpr int kXW = 4;                 // waves per tile
 constexpr int kXQ = 32;                // queries per wave
 constexpr int kXQB = kXW * kXQ;        // entries per tile
@@ -813,8 +817,10 @@ __host__ __device__ constexpr bool lowp_x32_kernel(int prec, int ns, bool lab) {
     return (prec == CAPS_PREC_BF16 || prec == CAPS_PREC_FP16) && (ns == 1 || ns == 2 || ns == 4) && !lab;
 }
 
-template <int PREC, int NS, bool COUNT>
+template <int PREC, int NS, int MODE, int MH>
 __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_x32(LowpArgs A) {
+    constexpr bool COUNT = MODE == 1;   // survivor counts of the exact filter
+    constexpr bool SEED = MODE == 2;    // approximate keys: per query and probe the best 2 MH
     typedef typename Mfma32<PREC>::T VT;
     constexpr int ROWB = NS * 64;                  // bytes per row of the copy
     constexpr int KS = ROWB / 32;                  // 16-element steps per row
@@ -866,6 +872,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     int32_t my_slot = 0, my_qq = 0;
     uint32_t my_sel = 0, my_mask = 0, my_val = 1;   // a lane without a query never matches
     float my_tf = qnan, qa = 0.0f, qb = 0.0f;
+    uint64_t my_tk = ~0ull;   // seed: the shared bound key at the tile's start
     if (own) {
         my_slot = ent[qi];
         my_qq = my_slot / A.m;
@@ -875,12 +882,16 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         const float4 ax = *reinterpret_cast<const float4 *>(A.qaux + 4 * (int64_t)my_qq);
         qa = ax.x;
         qb = fmaf(A.gam, ax.w, ax.z);
-        // the bound, read once per tile (the main pass keeps no keys)
-        const float td = bound_score(__hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        // the bound, read once per tile (the main pass keeps no keys; the
+        // seed pass shares it between the tiles of a query by atomic min)
+        const uint64_t tk = __hip_atomic_load(A.tau + my_qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float td = bound_score(tk);
         const float nq = ax.y;
-        my_tf = !(td < inf) ? inf
-                : l2        ? fmaf(A.eta, nq + td, td - nq) + 1e-37f
-                            : fmaf(A.eta, nq + fabsf(td), td) + 1e-37f;
+        my_tf = SEED          ? td
+                : !(td < inf) ? inf
+                : l2          ? fmaf(A.eta, nq + td, td - nq) + 1e-37f
+                              : fmaf(A.eta, nq + fabsf(td), td) + 1e-37f;
+        if (SEED) my_tk = tk;
     }
     // tile maxima of |q| and |q - q~| + gam |q~| (the point term's error
     // products) and the levels any query of the tile selects
@@ -985,6 +996,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         const float slack = fmaf(raw[1][c32], qa, raw[2][c32] * qb) * (1.0f + 0x1p-20f);
         float pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
         if (!(fabsf(pt) < inf)) pt = -inf;
+        if (SEED) pt = l2 ? nx : 0.0f;   // approximate keys: the plain point term
         xn[pb][c32] = c32 < cn ? pt : qnan;   // (lanes l and l + 32 write alike)
         xw[pb][c32] = has_dense ? __float_as_uint(raw[3][c32]) : 0u;
     };
@@ -1052,6 +1064,9 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     if (w == 0) point_terms(rw0, min(kXCH, cend - cc0), 0);
     int lj = -1;
     float tfj = qnan;
+    uint64_t lst[SEED ? MH : 1];   // seed: the lane's best keys, ascending (~0: empty)
+#pragma unroll
+    for (int i = 0; i < (SEED ? MH : 1); i++) lst[i] = ~0ull;
 
     // Chunk k from buffer `cur` (point arrays `pb`); `nraw` holds the inputs
     // of chunk k + 1, whose point terms wave `ptw` (k % 4) computes; F_{k+3}
@@ -1082,46 +1097,88 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             for (int s = s0; s < s0 + 2; s++) acc = Mfma32<PREC>::mma(a[s - s0], bq[s], acc);
         }
 
-        if (j != lj) {   // level changed: the query's bound if it selects the level, NaN if not
-            lj = j;
-            tfj = ((my_sel >> j) & 1u) ? my_tf : qnan;
-        }
-        const bool sj = (my_sel >> j) & 1u;
-#pragma unroll
-        for (int q4 = 0; q4 < 4; q4++) {   // points 8 q4 + 4 g + e of the chunk, e < 4
-            const int rb = 8 * q4 + 4 * g;
-            const float4 pn = *reinterpret_cast<const float4 *>(&xn[pb][rb]);
-            const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
-            uint64_t hit[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) hit[e] = __builtin_amdgcn_ballot_w64(fmaf(cm, acc[4 * q4 + e], pv[e]) <= tfj);
-            if (COUNT) {   // survivors of the exact filter (statistics only)
-                const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
-                const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
-                int c = 0;
-#pragma unroll
-                for (int e = 0; e < 4; e++) c += (sj && rb + e < cn && (wv[e] & my_mask) == my_val) ? 1 : 0;
-                if (c) atomicAdd(&scnt[qi], c);
-            }
-            if (!(hit[0] | hit[1] | hit[2] | hit[3])) continue;
-            {   // the packed dense test where a score passed
-                const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
-                const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
-#pragma unroll
-                for (int e = 0; e < 4; e++) hit[e] &= __builtin_amdgcn_ballot_w64((wv[e] & my_mask) == my_val);
+        if constexpr (SEED) {
+            // approximate keys below the lane's bound (the shared bound at the
+            // tile's start, then the worst of its MH best) that pass the
+            // packed dense test enter its sorted list; lanes l and l + 32 keep
+            // one list each for query l % 32 (its half of the chunk's points)
+            if (j != lj) {
+                lj = j;
+                tfj = ((my_sel >> j) & 1u) ? bound_score(lst[MH - 1] < my_tk ? lst[MH - 1] : my_tk) : qnan;
             }
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const uint64_t hm = hit[e];
-                if (!hm) continue;
-                const int n = __popcll(hm);   // at most 64
-                if (vhead - vtail + n > kXRing) drain(vhead - vtail);
-                if ((hm >> lane) & 1ull) {
-                    const int sl = (vhead + __popcll(hm & lanemask_lt())) & (kXRing - 1);
-                    ring_pos[sl] = (uint32_t)(c0 + rb + e);
-                    ring_row[sl] = (uint32_t)c32;
+            for (int q4 = 0; q4 < 4; q4++) {
+                const int rb = 8 * q4 + 4 * g;
+                const float4 pn = *reinterpret_cast<const float4 *>(&xn[pb][rb]);
+                const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
+                float esc[4];
+                uint64_t hit[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    esc[e] = fmaf(cm, acc[4 * q4 + e], pv[e]);
+                    hit[e] = __builtin_amdgcn_ballot_w64(esc[e] <= tfj);
                 }
-                vhead += n;
+                if (!(hit[0] | hit[1] | hit[2] | hit[3])) continue;
+                const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
+                const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (!((hit[e] >> lane) & 1ull) || (wv[e] & my_mask) != my_val) continue;
+                    const uint64_t key = ((uint64_t)f2ord(canon0(esc[e])) << 32) | (uint32_t)(c0 + rb + e);
+                    if (!(key < lst[MH - 1])) continue;
+                    uint64_t kk = key;   // one compare-exchange pass keeps the list sorted
+#pragma unroll
+                    for (int i = 0; i < MH; i++) {
+                        const bool lt = kk < lst[i];
+                        const uint64_t lo = lt ? kk : lst[i];
+                        kk = lt ? lst[i] : kk;
+                        lst[i] = lo;
+                    }
+                    tfj = bound_score(lst[MH - 1] < my_tk ? lst[MH - 1] : my_tk);
+                }
+            }
+        } else {
+            if (j != lj) {   // level changed: the query's bound if it selects the level, NaN if not
+                lj = j;
+                tfj = ((my_sel >> j) & 1u) ? my_tf : qnan;
+            }
+            const bool sj = (my_sel >> j) & 1u;
+#pragma unroll
+            for (int q4 = 0; q4 < 4; q4++) {   // points 8 q4 + 4 g + e of the chunk, e < 4
+                const int rb = 8 * q4 + 4 * g;
+                const float4 pn = *reinterpret_cast<const float4 *>(&xn[pb][rb]);
+                const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
+                uint64_t hit[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) hit[e] = __builtin_amdgcn_ballot_w64(fmaf(cm, acc[4 * q4 + e], pv[e]) <= tfj);
+                if (COUNT) {   // survivors of the exact filter (statistics only)
+                    const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
+                    const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
+                    int c = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) c += (sj && rb + e < cn && (wv[e] & my_mask) == my_val) ? 1 : 0;
+                    if (c) atomicAdd(&scnt[qi], c);
+                }
+                if (!(hit[0] | hit[1] | hit[2] | hit[3])) continue;
+                {   // the packed dense test where a score passed
+                    const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
+                    const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++) hit[e] &= __builtin_amdgcn_ballot_w64((wv[e] & my_mask) == my_val);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint64_t hm = hit[e];
+                    if (!hm) continue;
+                    const int n = __popcll(hm);   // at most 64
+                    if (vhead - vtail + n > kXRing) drain(vhead - vtail);
+                    if ((hm >> lane) & 1ull) {
+                        const int sl = (vhead + __popcll(hm & lanemask_lt())) & (kXRing - 1);
+                        ring_pos[sl] = (uint32_t)(c0 + rb + e);
+                        ring_row[sl] = (uint32_t)c32;
+                    }
+                    vhead += n;
+                }
             }
         }
         return more;
@@ -1129,13 +1186,39 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     while (step(xb0, xb3, 0, rw1, rw0, 0) && step(xb1, xb0, 1, rw2, rw1, 1) && step(xb2, xb1, 0, rw3, rw2, 2) &&
            step(xb3, xb2, 1, rw0, rw3, 3)) {
     }
-    if (vhead > vtail) drain(vhead - vtail);
-    if (COUNT) {
-        __syncthreads();
-        if (g == 0 && own && scnt[qi]) atomicAdd(&A.nsurv[my_qq], scnt[qi]);
+    if constexpr (SEED) {
+        // the slot's list: the keys of half 0, then those of half 1 (2 MH <= r
+        // entries); a full list of r keys bounds the query's r-th key
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < MH; i++) cnt += lst[i] != ~0ull ? 1 : 0;
+        const int c_lo = __shfl(cnt, c32, 64);
+        const int c_hi = __shfl(cnt, c32 + 32, 64);
+        const uint64_t w_hi = ((uint64_t)(uint32_t)__shfl((int)(lst[MH - 1] >> 32), c32 + 32, 64) << 32) |
+                              (uint32_t)__shfl((int)(uint32_t)lst[MH - 1], c32 + 32, 64);
+        if (own) {
+            uint64_t *out = A.partials + (int64_t)my_slot * A.r + (g ? c_lo : 0);
+#pragma unroll
+            for (int i = 0; i < MH; i++)
+                if (i < cnt) out[i] = lst[i];
+            if (g == 0) {
+                A.pcnt[my_slot] = c_lo + c_hi;
+                if (c_lo + c_hi == A.r) {
+                    const uint64_t worst = lst[MH - 1] > w_hi ? lst[MH - 1] : w_hi;
+                    atomicMin((unsigned long long *)(A.tau + my_qq), (unsigned long long)worst);
+                }
+            }
+        }
+        return;
+    } else {
+        if (vhead > vtail) drain(vhead - vtail);
+        if (COUNT) {
+            __syncthreads();
+            if (g == 0 && own && scnt[qi]) atomicAdd(&A.nsurv[my_qq], scnt[qi]);
+        }
+        // the main pass keeps no keys: its partial lists are empty
+        if (g == 0 && own) A.pcnt[my_slot] = 0;
     }
-    // the main pass keeps no keys: its partial lists are empty
-    if (g == 0 && own) A.pcnt[my_slot] = 0;
 }
 
 typedef void (*LowpFn)(LowpArgs);
@@ -1147,7 +1230,16 @@ inline int lowp_cb(int r) { return r <= 16 ? 32 : r <= 48 ? 64 : 128; }
 template <int PREC, bool LAB, int NS, int KIND>
 LowpFn pick_cb(int r) {
     if constexpr ((KIND == 1 || KIND == 3) && lowp_x32_kernel(PREC, NS, LAB)) {
-        return k_scan_x32<PREC, NS, KIND == 3>;
+        return k_scan_x32<PREC, NS, KIND == 3 ? 1 : 0, 1>;
+    } else if constexpr (KIND == 4 && lowp_x32_kernel(PREC, NS, LAB)) {
+        // seed lists: per (query, probe) the best key of each half of the
+        // partition's rows (longer lists cost more insertions than their
+        // tighter bound saved: MH = 2 and 5 ran 0.34 and 0.44 ms per c2 step
+        // against 0.28 ms, with the same main pass)
+        (void)r;
+        return k_scan_x32<PREC, NS, 2, 1>;
+    } else if constexpr (KIND == 4) {
+        return k_scan_mfma<PREC, LAB, 32, NS, 0>;   // (not used: the seed kind needs the 32 x 32 pass)
     } else if constexpr (KIND == 1 || KIND == 3) {
         return k_scan_mfma<PREC, LAB, 32, NS, KIND>;   // (keeps no keys)
     } else {
@@ -1170,13 +1262,16 @@ template <> LowpFn pick_ns<CAPS_PREC_BF16, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 2>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_BF16, 3>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_BF16, 4>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 2>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP16, 3>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP16, 4>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 0>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 1>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 2>(int, bool, int);
 template <> LowpFn pick_ns<CAPS_PREC_FP8, 3>(int, bool, int);
+template <> LowpFn pick_ns<CAPS_PREC_FP8, 4>(int, bool, int);
 
 }  // namespace caps

@@ -465,11 +465,12 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     // the variant with the filter's slow path: label tests, disjunctions
     const bool lab = ix->sch.label_vocab > 0 || S.disj;
     const LowpFn fn = S.kind == 0   ? pick_prec<0>(ix->prec, ix->dpad / 32, lab, S.r)
+                      : S.kind == 4 ? pick_prec<4>(ix->prec, ix->dpad / 32, lab, S.r)
                       : S.kind == 1 ? (S.nsurv ? pick_prec<3>(ix->prec, ix->dpad / 32, lab, S.r)
                                                : pick_prec<1>(ix->prec, ix->dpad / 32, lab, S.r))
                                     : pick_prec<2>(ix->prec, ix->dpad / 32, lab, S.r);
     // (the 32 x 32 main pass holds its arrays in static LDS)
-    const bool x32 = S.kind == 1 && lowp_x32_kernel(ix->prec, ix->dpad / 32, lab);
+    const bool x32 = (S.kind == 1 || S.kind == 4) && lowp_x32_kernel(ix->prec, ix->dpad / 32, lab);
     const size_t lds = x32 ? 0 : lowp_scan_lds(ix, S.r, S.kind, S.disj);
     CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     prof_begin(S.stage, st);
@@ -502,6 +503,10 @@ int lowp_qb() { return kLQB; }
 
 int lowp_qb_main(const Index *ix, bool disj) {
     return lowp_x32_kernel(ix->prec, ix->dpad / 32, ix->sch.label_vocab > 0 || disj) ? kXQB : kLQB;
+}
+
+bool lowp_seed_x32(const Index *ix, bool disj, int r) {
+    return r >= 2 && lowp_x32_kernel(ix->prec, ix->dpad / 32, ix->sch.label_vocab > 0 || disj);
 }
 
 }  // namespace caps

@@ -1,11 +1,11 @@
 // Instantiates the matrix-core scan kernels of one precision and kind
 // (0 approximate keys, 1 exact main pass, 2 exact rescue pass, 3 exact main
-// pass with survivor counts): compiled once
+// pass with survivor counts, 4 seed lists): compiled once
 // per (CAPS_INST_PREC, CAPS_INST_KIND) pair so that they build in parallel.
 #include "caps_mfma.h"
 
 #if !defined(CAPS_INST_PREC) || !defined(CAPS_INST_KIND)
-#error "compile with -DCAPS_INST_PREC=<CAPS_PREC_*> -DCAPS_INST_KIND=<0|1|2|3>"
+#error "compile with -DCAPS_INST_PREC=<CAPS_PREC_*> -DCAPS_INST_KIND=<0|1|2|3|4>"
 #endif
 
 namespace caps {

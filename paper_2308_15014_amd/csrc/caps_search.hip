@@ -1286,6 +1286,7 @@ struct Arena {
 
 int lowp_qb();
 int lowp_qb_main(const Index *ix, bool disj);
+bool lowp_seed_x32(const Index *ix, bool disj, int r);
 
 struct SearchWs {
     uint8_t *qlow;
@@ -1643,8 +1644,11 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
                 const int32_t r1 = round == 0 ? s_seed : m;
                 if (r0 >= r1) continue;
-                // tile width of this round: the exact main pass may run 128-entry tiles
-                const int qbr = mfma && !lowp && !(seeded_exact && round == 0) ? lowp_qb_main(ix, disj) : qb;
+                // tile width of this round: the exact main pass and the seed lists may
+                // run 128-entry tiles
+                const bool seed_x32 = mfma && !lowp && seeded_exact && round == 0 && lowp_seed_x32(ix, disj, r);
+                const int qbr = mfma && !lowp && (!(seeded_exact && round == 0) || seed_x32) ? lowp_qb_main(ix, disj)
+                                                                                            : qb;
                 prof_begin(CAPS_STAGE_SELECT, st);
                 hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                    nb, m, r0, r1, b, ngrp, hist);
@@ -1676,7 +1680,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     S.nb = nb;
                     S.m = m;
                     S.r = r;
-                    S.kind = lowp || seed_pass ? 0 : 1;
+                    S.kind = seed_x32 ? 4 : lowp || seed_pass ? 0 : 1;
                     S.stage = seed_pass ? CAPS_STAGE_SEED : CAPS_STAGE_SCAN;
                     S.max_tiles = grid;
                     S.tiles = W.tiles;
