@@ -152,6 +152,14 @@ caps_status caps_search_check(const caps_index *idx, const caps_search_params *s
 // device bytes the workspace of one search call of nq queries takes
 size_t search_workspace_bytes(const Index *ix, const caps_search_params *sp, int32_t nq);
 
+// ---- per-call runtime settings (caps_util.hip)
+// stream-ordered device memory from the library's pool on `device` (freed
+// with hipFreeAsync; the pool keeps it for the next call)
+caps_status ws_alloc(void **p, size_t bytes, int device, hipStream_t st);
+// hipFuncAttributeMaxDynamicSharedMemorySize of `fn`, set only when `bytes`
+// exceeds what was set before on `device`
+caps_status set_kernel_lds(const void *fn, size_t bytes, int device);
+
 // ---- stage timer (caps_util.hip): no-ops unless enabled
 void prof_begin(int stage, hipStream_t st);
 void prof_end(int stage, hipStream_t st);

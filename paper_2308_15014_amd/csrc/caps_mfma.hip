@@ -472,7 +472,10 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     // (the 32 x 32 main pass holds its arrays in static LDS)
     const bool x32 = (S.kind == 1 || S.kind == 4) && lowp_x32_kernel(ix->prec, ix->dpad / 32, lab);
     const size_t lds = x32 ? 0 : lowp_scan_lds(ix, S.r, S.kind, S.disj);
-    CAPS_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    {
+        const caps_status ls = set_kernel_lds((const void *)fn, lds, ix->device);
+        if (ls != CAPS_OK) return ls;
+    }
     prof_begin(S.stage, st);
     // the rescue pass walks its (device-side) tile list with a bounded grid
     const int64_t full = (S.max_tiles + kXcds - 1) / kXcds * kXcds;

@@ -1506,7 +1506,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
     if (ex.ws) {
         ar.base = reinterpret_cast<char *>(ex.ws);
     } else {
-        CAPS_HIP(hipMallocAsync((void **)&ar.base, ar.cap, st));
+        const caps_status as = ws_alloc((void **)&ar.base, ar.cap, ix->device, st);
+        if (as != CAPS_OK) return as;
     }
     carve(ar, W, nq, sb, b, m, r, !out_ncand, !out_nsurv, qlow_row, router, P.defer, nc, disj);
 
@@ -1547,7 +1548,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                       lds_max);
             return CAPS_EUNSUPPORTED;
         }
-        CAPS_HIP(hipFuncSetAttribute((const void *)scan_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const caps_status ls = set_kernel_lds((const void *)scan_fn, lds, ix->device);
+        if (ls != CAPS_OK) return ls;
     }
         for (int32_t q0 = 0; q0 < nq; q0 += sb) {
             const int32_t nb = std::min(sb, nq - q0);

@@ -74,6 +74,64 @@ caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32
     return CAPS_OK;
 }
 
+// ---- host-side caches of the per-call runtime settings
+// A library memory pool per device that keeps what is freed into it
+// (release threshold: never), so that a search's stream-ordered free does not
+// hand its workspace back to the system: with the default pool that free cost
+// about 1.7 ms of host time per call, as long as the kernels of a call.
+constexpr int kMaxDevices = 64;
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pool[kMaxDevices];
+
+caps_status ws_alloc(void **p, size_t bytes, int device, hipStream_t st) {
+    if (device < 0 || device >= kMaxDevices) {
+        CAPS_HIP(hipMallocAsync(p, bytes, st));
+        return CAPS_OK;
+    }
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        if (!g_pool[device]) {
+            hipMemPoolProps props{};
+            props.allocType = hipMemAllocationTypePinned;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = device;
+            hipMemPool_t np = nullptr;
+            CAPS_HIP(hipMemPoolCreate(&np, &props));
+            uint64_t keep = ~0ull;
+            const hipError_t e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
+            if (e != hipSuccess) {
+                (void)hipMemPoolDestroy(np);
+                set_error("hipMemPoolSetAttribute failed: %s", hipGetErrorString(e));
+                return CAPS_EDEVICE;
+            }
+            g_pool[device] = np;
+        }
+        pool = g_pool[device];
+    }
+    CAPS_HIP(hipMallocFromPoolAsync(p, bytes, pool, st));
+    return CAPS_OK;
+}
+
+// The maximum dynamic LDS of a kernel, set once per (kernel, device) to the
+// largest size asked for (each setting cost about 0.2 ms of host time).
+static std::mutex g_lds_mu;
+static std::vector<std::pair<std::pair<const void *, int>, int>> g_lds;
+
+caps_status set_kernel_lds(const void *fn, size_t bytes, int device) {
+    std::lock_guard<std::mutex> g(g_lds_mu);
+    for (auto &e : g_lds)
+        if (e.first.first == fn && e.first.second == device) {
+            if ((int)bytes <= e.second) return CAPS_OK;
+            CAPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+            e.second = (int)bytes;
+            return CAPS_OK;
+        }
+    CAPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    g_lds.push_back({{fn, device}, (int)bytes});
+    return CAPS_OK;
+}
+
 // ------------------------------------------------------------------ stage timer
 namespace {
 struct Rec {
