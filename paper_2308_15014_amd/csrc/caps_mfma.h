@@ -1085,6 +1085,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         const bool more = cj <= h;
         fetch_next(nxt, fraw);
         if (w == ptw && more) point_terms(nraw, min(kXCH, cend - cc0), pb ^ 1);
+        if (kXQ * w >= nqt) return more;   // a wave without queries (small batches) only stages
 
         f32x16 acc = {};
 #pragma unroll
