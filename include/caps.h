@@ -241,7 +241,10 @@ enum {
  * Errors: EINVAL (k, nprobe, n_q < 0, NULL pointers, mode 1 on an index
  * without a low-precision copy, rerank outside [k, 64], rescue_grid < 0,
  * unknown flags, non-finite query rows under CAPS_SEARCH_VALIDATE),
- * ENOMEM, EDEVICE.  The device workspace is released on every path.
+ * ENOMEM, EDEVICE.  The device workspace is released on every path: it is
+ * taken stream-ordered from a memory pool the library keeps per device, which
+ * holds freed memory for later calls (up to the largest workspace in use at
+ * once) until the process ends.
  */
 caps_status caps_search(const caps_index *idx, const caps_search_params *sp,
                         const float *q, int32_t n_q,
