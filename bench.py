@@ -58,14 +58,15 @@ FLUSH_BYTES = 512 << 20
 # HBM bytes per launch of the exact main pass (mode 0, BF16 copy, 10k queries, nprobe 624) from
 # two rocprofv3 --pmc runs (FETCH_SIZE: mean of the steady launches; WRITE_SIZE: their median,
 # KiB per dispatch) scaled by what the same counters read for a 512 MiB copy (read factor 2.00, write
-# factor 1.00).  Valid only for the kernel sources they were taken on (SHA-256 of the two
+# factor 1.00).  Valid only for the kernel sources they were taken on (SHA-256 of the three
 # files below) and that workload; otherwise the line reports null.
 MAIN_PASS_TRAFFIC = {
-    "sources_sha256": "b0d884a1aa2fe020b6f50dcc0618e78ad86049d713e48909b94cd81cdc0971ae",
+    "sources_sha256": "e4335f1fb39a4f7617abc1b1a4336bffb1d4c6a1ed52ec80e786850adfeb4082",
     "nprobe": 624, "n_queries": 10_000,
-    "fetch_kib": 1_211_707, "write_kib": 246_222, "read_factor": 2.00, "write_factor": 1.00,
+    "fetch_kib": 383_552, "write_kib": 54_556, "read_factor": 2.00, "write_factor": 1.00,
 }
-SCAN_SOURCES = ("paper_2308_15014_amd/csrc/caps_mfma.h", "paper_2308_15014_amd/csrc/caps_scan_inst.hip")
+SCAN_SOURCES = ("paper_2308_15014_amd/csrc/caps_mfma.h", "paper_2308_15014_amd/csrc/caps_scan_inst.hip",
+                "paper_2308_15014_amd/csrc/caps_search.hip")   # the kernel and the entry lists it reads
 
 
 def main_pass_traffic(nprobe: int, n_queries: int):

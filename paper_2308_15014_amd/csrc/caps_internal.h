@@ -188,6 +188,7 @@ struct LowpScan {
     int64_t max_tiles;
     const int4 *tiles;            // per tile: partition, first entry, entries (0: none)
     const int32_t *entries;
+    const uint32_t *esel;         // level mask per entry, in entry order (or null)
     const uint32_t *sel;
     const QDesc *qd;
     const QDesc *qterms;          // disjunctive searches: term descriptors (kMaxTerms per query)

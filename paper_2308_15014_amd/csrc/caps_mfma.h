@@ -16,6 +16,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 struct LowpArgs {
     const int4 *tiles;          // per tile: partition, first entry, entries (0: no tile)
     const int32_t *entries;
+    const uint32_t *esel;       // level mask per entry, in entry order (null: read sel by slot)
     const uint32_t *sel;
     const QDesc *qd;
     const QDesc *qterms;        // disjunctive searches: kMaxTerms term descriptors per query
@@ -31,7 +32,7 @@ struct LowpArgs {
     const float *vecs, *q;      // FP32 CSR rows and queries (exact rescoring)
     const int32_t *perm;
     uint64_t *partials;         // per (query, probe): up to r keys
-    int32_t *pcnt;              // keys written per (query, probe) (sorted, at most r)
+    int32_t *pcnt;              // keys written per (query, probe) (sorted, at most r; the exact main pass writes none)
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
     int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count
@@ -734,11 +735,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         if (lane < kLQPW && my_qq >= 0 && scnt[qbase + lane]) atomicAdd(&A.nsurv[my_qq], scnt[qbase + lane]);
     }
     // ---- finalize my queries: best r sorted, partial list, shared bound
-    // (the main pass keeps no keys: its lists are empty)
-    if (DEFER) {
-        if (lane < kLQPW && qbase + lane < nqt) A.pcnt[qslot[qbase + lane]] = 0;
-        return;
-    }
+    // (the main pass keeps no keys and writes no counts: the merge reads the
+    // lists of the queries the rescue pass rescanned only)
+    if (DEFER) return;
     for (int i = 0; i < kLQPW; i++) {
         const int qi = qbase + i;
         if (qi >= nqt) break;
@@ -848,7 +847,6 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ int32_t scnt[kXQB];
     __shared__ float qmx[2][kXW];
     __shared__ uint32_t lvw[kXW];
-    __shared__ int32_t spo[kMaxHeight + 2];
 
     const int tile = xcd_tile(blockIdx.x, A.ntiles);
     if (tile < 0) return;
@@ -876,7 +874,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     if (own) {
         my_slot = ent[qi];
         my_qq = my_slot / A.m;
-        my_sel = A.sel[my_slot];
+        my_sel = A.esel ? A.esel[dsc.y + qi] : A.sel[my_slot];   // (in entry order: one coalesced read)
         my_mask = A.qd[my_qq].dmask;
         my_val = A.qd[my_qq].dval;
         const float4 ax = *reinterpret_cast<const float4 *>(A.qaux + 4 * (int64_t)my_qq);
@@ -911,7 +909,11 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         scnt[lane] = 0;
         scnt[lane + 64] = 0;
     }
-    if (t <= h + 1) spo[t] = A.offs[(int64_t)p * (h + 1) + t];   // level starts (and the end)
+    // level bounds, one per lane: lane j holds the start of level j, lane
+    // h + 1 the end of the partition (read out by lane index, no memory wait)
+    const int32_t spv = A.offs[(int64_t)p * (h + 1) + min(lane, h + 1)];
+    const int32_t spn = __shfl_down(spv, 1, 64);   // every lane takes part
+    const uint32_t lne = (uint32_t)__builtin_amdgcn_ballot_w64(lane <= h && spv < spn);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kXW; i++) {
@@ -919,7 +921,8 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         qb = fmaxf(qb, qmx[1][i]);
         lv |= lvw[i];
     }
-    lv = __builtin_amdgcn_readfirstlane(lv);
+    // the levels to scan: selected by a query of the tile and not empty
+    lv = __builtin_amdgcn_readfirstlane(lv & lne);
     // MFMA B operands: the lane's query, K slice 8g of each step
     VT bq[KS];
     {
@@ -933,16 +936,17 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     // power of two and 2s + g = 2s | g)
     const uint32_t xo = (uint32_t)(c32 * ROWB + 16 * (g ^ ((c32 / RPL) & SWZ)));
 
-    // chunk cursors (wave-uniform): level j, first row c0, end of the level
-    // (level bounds from LDS: a global load here would wait for every
-    // direct load in flight)
+    // chunk cursors (wave-uniform): level j, first row c0, end of the level;
+    // past the last level j = h + 1
     auto next_level = [&](int &j, int32_t &c0, int32_t &end) {
-        for (j++; j <= h; j++) {
-            if (!((lv >> j) & 1u)) continue;
-            c0 = __builtin_amdgcn_readfirstlane(spo[j]);
-            end = __builtin_amdgcn_readfirstlane(spo[j + 1]);
-            if (c0 < end) return;
+        const uint32_t rest = lv >> (j + 1);   // j + 1 <= h + 1 <= 16
+        if (!rest) {
+            j = h + 1;
+            return;
         }
+        j += 1 + __builtin_ctz(rest);
+        c0 = __builtin_amdgcn_readlane(spv, j);
+        end = __builtin_amdgcn_readlane(spv, j + 1);
     };
     auto advance = [&](int &j, int32_t &c0, int32_t &end) {
         c0 += kXCH;
@@ -1038,7 +1042,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     int32_t cc0 = 0, cend = 0;
     next_level(cj, cc0, cend);
     if (cj > h) {   // nothing to scan
-        if (g == 0 && own) A.pcnt[my_slot] = 0;
+        if (SEED && g == 0 && own) A.pcnt[my_slot] = 0;
         return;
     }
     // fetch cursor (chunk of the rows of the next fetch) and the chunk after it
@@ -1144,10 +1148,13 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
                 tfj = ((my_sel >> j) & 1u) ? my_tf : qnan;
             }
             const bool sj = (my_sel >> j) & 1u;
+            // point terms of the next group read while this one is scored
+            float4 pnx = *reinterpret_cast<const float4 *>(&xn[pb][4 * g]);
 #pragma unroll
             for (int q4 = 0; q4 < 4; q4++) {   // points 8 q4 + 4 g + e of the chunk, e < 4
                 const int rb = 8 * q4 + 4 * g;
-                const float4 pn = *reinterpret_cast<const float4 *>(&xn[pb][rb]);
+                const float4 pn = pnx;
+                if (q4 < 3) pnx = *reinterpret_cast<const float4 *>(&xn[pb][rb + 8]);
                 const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
                 uint64_t hit[4];
 #pragma unroll
@@ -1217,8 +1224,6 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             __syncthreads();
             if (g == 0 && own && scnt[qi]) atomicAdd(&A.nsurv[my_qq], scnt[qi]);
         }
-        // the main pass keeps no keys: its partial lists are empty
-        if (g == 0 && own) A.pcnt[my_slot] = 0;
     }
 }
 

@@ -417,6 +417,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     A.tiles = S.tiles;
     A.ntiles = (int32_t)S.max_tiles;
     A.entries = S.entries;
+    A.esel = S.esel;
     A.sel = S.sel;
     A.qd = S.qd;
     A.qterms = S.qterms;

@@ -546,21 +546,25 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restr
                                                           const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
                                                           int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
                                                           const int32_t *__restrict__ hscan, int32_t nc_pack,
-                                                          int32_t *__restrict__ entries) {
+                                                          int32_t *__restrict__ entries, uint32_t *__restrict__ esel) {
     extern __shared__ int32_t run[];
     for (int i = threadIdx.x; i < b; i += blockDim.x) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
     __syncthreads();
     const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
     // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
+    // esel (if given): the entry's level mask at the same position
     bucket_slots(probes, sel, q0, q1, m, r0, r1, [&](int64_t e, uint32_t sm, int32_t p) {
-        entries[atomicAdd(&run[p], 1)] =
-            (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
+        const int32_t at = atomicAdd(&run[p], 1);
+        entries[at] = (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
+        if (esel) esel[at] = sm;
     });
 }
 
 // One workgroup per partition: copies its entries from `in` to `out` grouped
 // by level-mask class (in any order within a class).  The class is packed
 // above bit kClassShift of each entry (packed != 0) or read from `sel`.
+// With esel_out, each entry's class (its whole level mask: nc = 2^(h+1)) is
+// written beside it.
 // Counts and ranks come from one ballot per class and 64 entries.
 constexpr int kClassW = 8;   // waves per class-sort block
 
@@ -568,7 +572,8 @@ __global__ __launch_bounds__(kClassW * 64) void k_class_sort(const int32_t *__re
                                                              const uint32_t *__restrict__ sel,
                                                              const int32_t *__restrict__ pstart,
                                                              const int32_t *__restrict__ pcount, int32_t nc,
-                                                             int32_t packed, int32_t *__restrict__ out) {
+                                                             int32_t packed, int32_t *__restrict__ out,
+                                                             uint32_t *__restrict__ esel_out) {
     __shared__ int32_t wcnt[kClassW][16];
     const int32_t p = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int32_t ps = pstart[p], pn = pcount[p];
@@ -605,7 +610,11 @@ __global__ __launch_bounds__(kClassW * 64) void k_class_sort(const int32_t *__re
         for (int k = 0; k < nc; k++) {
             const uint64_t bk = __ballot(c == k);
             const int32_t bk0 = __shfl(base, k, 64);
-            if (c == k) out[ps + bk0 + __popcll(bk & lt)] = packed ? v & emask : v;
+            if (c == k) {
+                const int32_t at = ps + bk0 + __popcll(bk & lt);
+                out[at] = packed ? v & emask : v;
+                if (esel_out) esel_out[at] = (uint32_t)k;
+            }
             if (lane == k) base += __popcll(bk);
         }
     }
@@ -1145,7 +1154,7 @@ static size_t scan_lds_bytes(int d, int k) {
 // rescored here with the plain scan's arithmetic.
 struct Deferred {
     const int32_t *pos, *cnt;   // null: none
-    const int32_t *oflow;       // queries rescanned by the rescue pass: their lists are ignored
+    const int32_t *oflow;       // queries rescanned by the rescue pass: deferred pairs ignored, partial lists read
     int32_t cap, d;
     const float *vecs, *q;      // FP32 CSR rows, the sub-batch's queries
     const int32_t *perm;
@@ -1181,13 +1190,16 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
             insert(((uint64_t)f2ord(sc) << 32) | (uint32_t)D.perm[pos]);
         }
     }
+    // with deferred pairs the partial lists hold keys only for the queries the
+    // rescue pass rescanned (the main pass writes none)
+    const bool lists = !D.pos || D.oflow[q];
     int nc = 0;
     for (int r = lane; r < m; r += 64) {
         const int64_t slot = (int64_t)q * m + r;
         if (sel[slot] == 0) continue;
         nc += cand[slot];
         const uint64_t *src = partials + slot * k;
-        const int c = pcnt ? min(pcnt[slot], k) : k;   // else lists padded with ~0
+        const int c = !lists ? 0 : pcnt ? min(pcnt[slot], k) : k;   // else lists padded with ~0
         for (int i = 0; i < c; i++) {
             const uint64_t key = src[i];
             if (key >= lst[KM - 1]) break;   // lists are sorted: the rest is worse
@@ -1298,6 +1310,7 @@ struct SearchWs {
     int32_t *probes;
     uint32_t *sel;
     int32_t *cand, *entries, *entries2;   // entries2: class-grouped copy
+    uint32_t *esel;             // exact matrix-core scan: level mask per entry of the scanned entry list
     uint64_t *partials, *tau;
     int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
     int32_t *oflow;             // exact matrix-core scan: queries for the rescue pass
@@ -1351,6 +1364,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.hscan = ar.take<int32_t>((size_t)b * ngrp_max + 1);
     w.scan_sums = ar.take<int32_t>((size_t)exclusive_scan_tiles((int64_t)b * ngrp_max) + 1);
     w.entries2 = nc > 1 ? ar.take<int32_t>((size_t)sb * m) : nullptr;
+    w.esel = defer ? ar.take<uint32_t>((size_t)sb * m) : nullptr;
     w.htotal = ar.take<int32_t>(1);
     w.pcount = ar.take<int32_t>(b + 1);
     w.pstart = ar.take<int32_t>(b + 1);
@@ -1667,11 +1681,12 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 // the fill packs each entry's class when entries stay below 2^27
                 const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
                 hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                                   nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries);
+                                   nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries, nc > 1 ? nullptr : W.esel);
                 const int32_t *ent = entries;
+                const uint32_t *esel = W.esel;   // (the class sort writes the level masks itself)
                 if (nc > 1) {
                     hipLaunchKernelGGL(k_class_sort, dim3(b), dim3(kClassW * 64), 0, st, entries, sel, pstart, pcount, nc,
-                                       (int32_t)(nc_pack > 1), W.entries2);
+                                       (int32_t)(nc_pack > 1), W.entries2, W.esel);
                     ent = W.entries2;
                 }
                 CAPS_HIP(hipGetLastError());
@@ -1687,6 +1702,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                     S.max_tiles = grid;
                     S.tiles = W.tiles;
                     S.entries = ent;
+                    S.esel = esel;
                     S.sel = sel;
                     S.qd = qd;
                     S.qterms = W.qterms;
