@@ -443,7 +443,8 @@ caps_status caps_router_get(const caps_index *idx, float *w1, float *b1, float *
 caps_status caps_router_info(const caps_index *idx, caps_router_info_t *out);
 
 /* Router logits (DEVICE n x B float32) of n DEVICE query rows, enqueued on
- * `stream`.  EINVAL without a router. */
+ * `stream` (the two products on hipBLASLt, FP32 accumulation; scratch for the
+ * input and hidden rows from the library's pool).  EINVAL without a router. */
 caps_status caps_router_logits(const caps_index *idx, const float *q, int32_t n, const int32_t *con_off,
                                const int32_t *con_attr, const int32_t *con_val, int32_t n_con,
                                float *out_logits, void *stream);

@@ -220,10 +220,10 @@ caps_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32
 // ---- learned routing inside a search (caps_router.hip): fills `scores`
 // (nb x B, smaller is better) from the router's logits and `conf` with the
 // softmax top-1 probability of each query; X and H are workspace of
-// nb x dpad and nb x hid BF16 elements.
+// nb x dpad and nb x hid BF16 elements, bneg of B floats (the negated bias).
 caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int32_t *con_off,
                           const int32_t *con_attr, const int32_t *con_val, int32_t n_con, uint16_t *X,
-                          uint16_t *H, float *scores, float *conf, hipStream_t st);
+                          uint16_t *H, float *bneg, float *scores, float *conf, hipStream_t st);
 // Lists the queries whose router probes fall back to centroid routing (top-1
 // probability below the fallback level, or fewer than k candidates in the
 // router's probes): fbq[0 .. *nfb), in no particular order.

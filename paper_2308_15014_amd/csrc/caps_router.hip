@@ -12,13 +12,17 @@
 // attribute i, value v: off_i + v; label l: off_L + l) sets position
 // mix64(token) mod 64, mix64 being splitmix64's output function.
 //
-// Products run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
-// accumulation) in one strided GEMM kernel; the softmax cross-entropy, bias
-// gradients and Adam (FP32 masters, BF16 copies) are plain kernels.
+// Training products run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) in this file's GEMM kernels; the two inference products (a
+// plain GEMM with a bias or bias + ReLU epilogue) go to hipBLASLt, with these
+// kernels for any shape it has no algorithm for.  The softmax cross-entropy,
+// bias gradients and Adam (FP32 masters, BF16 copies) are plain kernels.
+#include <hipblaslt/hipblaslt.h>
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "caps_device.h"
@@ -405,6 +409,103 @@ static caps_status gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint1
     return CAPS_OK;
 }
 
+// ------------------------------------------------------------------ library GEMM (inference)
+// D (M x N, row-major, leading dimension ldc) = epi(alpha * A B^T + bias) with
+// A (M x K) and B (N x K) row-major BF16 (K-contiguous), FP32 accumulation,
+// bias FP32 per column n of D, epi = ReLU or identity, D FP32 or BF16.  In
+// hipBLASLt's column-major terms: D^T (N x M) = op_T(B) op_N(A), the bias per
+// row of D^T.  One plan (descriptors and the heuristic's first algorithm, no
+// workspace) per device and shape, kept for the process; the descriptor's bias
+// pointer is set under the lock just before the (asynchronous) enqueue.
+namespace {
+constexpr int kLtDevices = 64;
+struct LtPlan {
+    int dev;
+    int32_t M, N, K, lda, ldb;
+    int64_t ldc;
+    bool relu, out16;
+    hipblasLtMatmulDesc_t desc = nullptr;
+    hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, ld = nullptr;
+    hipblasLtMatmulAlgo_t algo;
+    bool ok = false;
+};
+std::mutex g_lt_mu;
+hipblasLtHandle_t g_lt[kLtDevices] = {};
+bool g_lt_failed[kLtDevices] = {};
+std::vector<LtPlan *> g_lt_plans;
+
+LtPlan *lt_plan(int dev, int32_t M, int32_t N, int32_t K, int32_t lda, int32_t ldb, int64_t ldc, bool relu,
+                bool out16) {
+    for (LtPlan *p : g_lt_plans)
+        if (p->dev == dev && p->M == M && p->N == N && p->K == K && p->lda == lda && p->ldb == ldb &&
+            p->ldc == ldc && p->relu == relu && p->out16 == out16)
+            return p;
+    LtPlan *p = new LtPlan{dev, M, N, K, lda, ldb, ldc, relu, out16};
+    g_lt_plans.push_back(p);
+    if (!g_lt[dev] && !g_lt_failed[dev] && hipblasLtCreate(&g_lt[dev]) != HIPBLAS_STATUS_SUCCESS) {
+        g_lt[dev] = nullptr;
+        g_lt_failed[dev] = true;
+    }
+    if (!g_lt[dev]) return p;
+    const hipblasOperation_t opT = HIPBLAS_OP_T, opN = HIPBLAS_OP_N;
+    const hipblasLtEpilogue_t epi = relu ? HIPBLASLT_EPILOGUE_RELU_BIAS : HIPBLASLT_EPILOGUE_BIAS;
+    const int32_t bias_type = HIP_R_32F;
+    const uint64_t no_ws = 0;
+    hipblasLtMatmulPreference_t pref = nullptr;
+    hipblasLtMatmulHeuristicResult_t res[1];
+    int nres = 0;
+    bool ok = hipblasLtMatmulDescCreate(&p->desc, HIPBLAS_COMPUTE_32F, HIP_R_32F) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opT, sizeof(opT)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opN, sizeof(opN)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_EPILOGUE, &epi, sizeof(epi)) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_BIAS_DATA_TYPE, &bias_type,
+                                              sizeof(bias_type)) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&p->la, HIP_R_16BF, (uint64_t)K, (uint64_t)N, ldb) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&p->lb, HIP_R_16BF, (uint64_t)K, (uint64_t)M, lda) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&p->ld, out16 ? HIP_R_16BF : HIP_R_32F, (uint64_t)N, (uint64_t)M, ldc) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulPreferenceCreate(&pref) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &no_ws,
+                                                    sizeof(no_ws)) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulAlgoGetHeuristic(g_lt[dev], p->desc, p->la, p->lb, p->ld, p->ld, pref, 1, res, &nres) ==
+                  HIPBLAS_STATUS_SUCCESS &&
+              nres > 0 && res[0].state == HIPBLAS_STATUS_SUCCESS && res[0].workspaceSize == 0;
+    if (pref) (void)hipblasLtMatmulPreferenceDestroy(pref);
+    if (ok) p->algo = res[0].algo;
+    p->ok = ok;
+    return p;
+}
+}   // namespace
+
+// Enqueues the product on `st` and returns true, or returns false (nothing
+// enqueued) when the library has no algorithm for the shape.
+static bool lt_gemm(const uint16_t *A, int32_t lda, const uint16_t *B, int32_t ldb, int32_t M, int32_t N, int32_t K,
+                    const float *bias, bool relu, float alpha, float *C32, uint16_t *C16, int64_t ldc,
+                    hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kLtDevices || !bias || (C32 == nullptr) == (C16 == nullptr))
+        return false;
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    LtPlan *p = lt_plan(dev, M, N, K, lda, ldb, ldc, relu, C16 != nullptr);
+    if (!p->ok) return false;
+    if (hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_BIAS_POINTER, &bias, sizeof(bias)) !=
+        HIPBLAS_STATUS_SUCCESS)
+        return false;
+    const float beta = 0.0f;
+    void *D = C16 ? (void *)C16 : (void *)C32;
+    return hipblasLtMatmul(g_lt[dev], p->desc, &alpha, B, p->la, A, p->lb, &beta, D, p->ld, D, p->ld, &p->algo,
+                           nullptr, 0, st) == HIPBLAS_STATUS_SUCCESS;
+}
+
+// y = -x with -0 written as +0 (so that -(acc) + y never yields -0)
+__global__ void k_negate(const float *__restrict__ x, int32_t n, float *__restrict__ y) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = canon0(-x[i]);
+}
+
 // ------------------------------------------------------------------ loss (K12)
 // One workgroup per row: softmax of the logits, loss -(1/|S|) sum_{s in S}
 // log p_s over the row's distinct labels S (entries < 0 are padding), and
@@ -604,16 +705,22 @@ static int64_t nblk(int64_t n, int t) { return (n + t - 1) / t; }
 
 caps_status router_scores(const Index *ix, const float *q, int32_t nb, const int32_t *con_off,
                           const int32_t *con_attr, const int32_t *con_val, int32_t n_con, uint16_t *X,
-                          uint16_t *H, float *scores, float *conf, hipStream_t st) {
+                          uint16_t *H, float *bneg, float *scores, float *conf, hipStream_t st) {
     const Router &R = *ix->router;
     hipLaunchKernelGGL(k_router_input, dim3((unsigned)nb), dim3(64), 0, st, q, nb, ix->d, con_off, con_attr,
                        con_val, n_con, ix->sch, R.in_scale, R.in_shift, R.dpad, X);
+    hipLaunchKernelGGL(k_negate, dim3((unsigned)nblk(R.nout, 256)), dim3(256), 0, st, R.param + R.o_b2, R.nout,
+                       bneg);
     CAPS_HIP(hipGetLastError());
-    caps_status s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, nb, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr,
-                         0, nullptr, H, R.hid, st);
+    caps_status s = CAPS_OK;
+    if (!lt_gemm(X, R.dpad, R.w1h, R.dpad, nb, R.hid, R.dpad, R.param + R.o_b1, true, 1.0f, nullptr, H, R.hid, st))
+        s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, nb, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr, 0, nullptr,
+                 H, R.hid, st);
     if (s != CAPS_OK) return s;
-    s = gemm(H, R.hid, 1, R.w2h, R.hid, 1, nb, R.nout, R.hid, R.param + R.o_b2, kGemmNeg, nullptr, 0, scores,
-             nullptr, R.nout, st);
+    // scores = -(H W2^T + b2) = (-1) H W2^T + (-b2): negation is exact
+    if (!lt_gemm(H, R.hid, R.w2h, R.hid, nb, R.nout, R.hid, bneg, false, -1.0f, scores, nullptr, R.nout, st))
+        s = gemm(H, R.hid, 1, R.w2h, R.hid, 1, nb, R.nout, R.hid, R.param + R.o_b2, kGemmNeg, nullptr, 0, scores,
+                 nullptr, R.nout, st);
     if (s != CAPS_OK) return s;
     hipLaunchKernelGGL(k_router_conf, dim3((unsigned)nb), dim3(64), 0, st, scores, nb, R.nout, conf);
     CAPS_HIP(hipGetLastError());
@@ -894,13 +1001,17 @@ extern "C" caps_status caps_router_logits(const caps_index *idx, const float *q,
     hipStream_t st = (hipStream_t)stream;
     uint16_t *ws = nullptr;
     const size_t xb = sizeof(uint16_t) * (size_t)n * R.dpad, hb = sizeof(uint16_t) * (size_t)n * R.hid;
-    CAPS_HIP(hipMallocAsync((void **)&ws, xb + hb + 256, st));
+    s = ws_alloc((void **)&ws, xb + hb + 256, ix.device, st);   // (the library's pool: the free keeps it)
+    if (s != CAPS_OK) return s;
     uint16_t *X = ws, *H = reinterpret_cast<uint16_t *>(reinterpret_cast<uint8_t *>(ws) + ((xb + 255) & ~(size_t)255));
     hipLaunchKernelGGL(k_router_input, dim3((unsigned)n), dim3(64), 0, st, q, n, ix.d, con_off, con_attr, con_val,
                        n_con, ix.sch, R.in_scale, R.in_shift, R.dpad, X);
-    s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, n, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr, 0, nullptr, H,
-             R.hid, st);
-    if (s == CAPS_OK)
+    if (!lt_gemm(X, R.dpad, R.w1h, R.dpad, n, R.hid, R.dpad, R.param + R.o_b1, true, 1.0f, nullptr, H, R.hid, st))
+        s = gemm(X, R.dpad, 1, R.w1h, R.dpad, 1, n, R.hid, R.dpad, R.param + R.o_b1, kGemmRelu, nullptr, 0, nullptr,
+                 H, R.hid, st);
+    if (s == CAPS_OK &&
+        !lt_gemm(H, R.hid, R.w2h, R.hid, n, R.nout, R.hid, R.param + R.o_b2, false, 1.0f, out_logits, nullptr, R.nout,
+                 st))
         s = gemm(H, R.hid, 1, R.w2h, R.hid, 1, n, R.nout, R.hid, R.param + R.o_b2, 0, nullptr, 0, out_logits,
                  nullptr, R.nout, st);
     (void)hipFreeAsync(ws, st);

@@ -1318,6 +1318,7 @@ struct SearchWs {
     int32_t *hist, *hscan, *scan_sums, *htotal, *pcount, *pstart, *tstart;
     int4 *tiles;
     uint16_t *rx, *rh;          // learned routing: input rows, hidden activations
+    float *rbn;                 // learned routing: the output bias, negated
     float *conf;                // learned routing: softmax top-1 probability
     int32_t *probes_c;          // learned routing: centroid probes of the falling-back queries
     int32_t *fbq, *nfb;         // learned routing: the queries that fall back, their count
@@ -1372,6 +1373,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.tiles = ar.take<int4>(tile_cap(sb, m, b));
     w.rx = router ? ar.take<uint16_t>((size_t)sb * router->dpad) : nullptr;
     w.rh = router ? ar.take<uint16_t>((size_t)sb * router->hid) : nullptr;
+    w.rbn = router ? ar.take<float>((size_t)router->nout) : nullptr;
     w.conf = router ? ar.take<float>((size_t)sb) : nullptr;
     w.probes_c = router ? ar.take<int32_t>((size_t)sb * m) : nullptr;
     w.fbq = router ? ar.take<int32_t>((size_t)sb) : nullptr;
@@ -1588,7 +1590,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 // (low confidence, or fewer than k candidates)
                 prof_begin(CAPS_STAGE_ROUTE, st);
                 const caps_status rs = router_scores(ix, q + (int64_t)q0 * d, nb, con_off + q0, con_attr, con_val, n_con,
-                                                     W.rx, W.rh, scores, W.conf, st);
+                                                     W.rx, W.rh, W.rbn, scores, W.conf, st);
                 if (rs != CAPS_OK) return rs;
                 prof_end(CAPS_STAGE_ROUTE, st);
                 prof_begin(CAPS_STAGE_TOPM, st);
