@@ -320,21 +320,51 @@ __global__ __launch_bounds__(256) void k_topm_sel(const float *__restrict__ scor
     // wave-wide counts come from one ballot per register (scalar popcounts,
     // no cross-lane data movement)
     // the n-th smallest key (n >= 1): score su and id iu; ties of su are taken
-    // by ascending id up to iu
+    // by ascending id up to iu.  The bisection keeps the n-th key inside
+    // [ans, ans + 2^(bit+1)) with c_lo keys below the range and c_hi below its
+    // end; once the range holds a single key, that key (the smallest at or
+    // above ans) is the answer.  When every tie of su is needed the ids are
+    // not bisected.
     auto kth = [&](int n, uint32_t &su, int &iu) {
         uint32_t ans = 0;
+        int c_lo = 0, c_hi = KPT * 64;
+        bool one = false;
         for (int bit = 31; bit >= 0; bit--) {
             const uint32_t t = ans | (1u << bit);
             int c = 0;
 #pragma unroll
             for (int r = 0; r < KPT; r++) c += __popcll(__ballot(u[r] < t));
-            if (c < n) ans = t;
+            if (c < n) {
+                ans = t;
+                c_lo = c;
+            } else {
+                c_hi = c;
+            }
+            if (c_hi - c_lo == 1) {
+                one = true;
+                break;
+            }
         }
-        su = ans;
-        int lt = 0;
+        if (one) {
+            uint64_t mn = ~0ull;
 #pragma unroll
-        for (int r = 0; r < KPT; r++) lt += __popcll(__ballot(u[r] < su));
+            for (int r = 0; r < KPT; r++)
+                if (u[r] >= ans && u[r] < mn) mn = u[r];
+            su = (uint32_t)wave_min_u64(mn);
+        } else {
+            su = ans;
+        }
+        int lt = 0, eq = 0;
+#pragma unroll
+        for (int r = 0; r < KPT; r++) {
+            lt += __popcll(__ballot(u[r] < su));
+            eq += __popcll(__ballot(u[r] == su));
+        }
         const int need = n - lt;   // >= 1 ties of su to take, by id
+        if (need >= eq) {          // all of them
+            iu = INT32_MAX;
+            return;
+        }
         int ia = 0;
         for (int bit = 31 - __builtin_clz((unsigned)(KPT * 64)); bit >= 0; bit--) {
             const int t = ia | (1 << bit);
