@@ -562,14 +562,16 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_hist(const int32_t *__restr
                                                           const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
                                                           int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
                                                           int32_t *__restrict__ hist) {
+    const int g = xcd_tile(blockIdx.x, ngrp);   // query group (consecutive groups on one XCD)
+    if (g < 0) return;
     extern __shared__ int32_t cnt[];
     for (int i = threadIdx.x; i < b; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
-    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
+    const int32_t q0 = g * kBucketQ, q1 = min(nq, q0 + kBucketQ);
     bucket_slots(probes, sel, q0, q1, m, r0, r1,
                  [&](int64_t, uint32_t, int32_t p) { atomicAdd(&cnt[p], 1); });
     __syncthreads();
-    for (int i = threadIdx.x; i < b; i += blockDim.x) hist[(int64_t)i * ngrp + blockIdx.x] = cnt[i];
+    for (int i = threadIdx.x; i < b; i += blockDim.x) hist[(int64_t)i * ngrp + g] = cnt[i];
 }
 
 __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restrict__ probes,
@@ -577,10 +579,16 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restr
                                                           int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
                                                           const int32_t *__restrict__ hscan, int32_t nc_pack,
                                                           int32_t *__restrict__ entries, uint32_t *__restrict__ esel) {
+    // query group g: consecutive groups run on one XCD, so that the adjacent
+    // runs they write into each partition's range share that XCD's L2 (runs
+    // of neighbouring groups written from different L2s left every output
+    // line partly written in several of them)
+    const int g = xcd_tile(blockIdx.x, ngrp);
+    if (g < 0) return;
     extern __shared__ int32_t run[];
-    for (int i = threadIdx.x; i < b; i += blockDim.x) run[i] = hscan[(int64_t)i * ngrp + blockIdx.x];
+    for (int i = threadIdx.x; i < b; i += blockDim.x) run[i] = hscan[(int64_t)i * ngrp + g];
     __syncthreads();
-    const int32_t q0 = blockIdx.x * kBucketQ, q1 = min(nq, q0 + kBucketQ);
+    const int32_t q0 = g * kBucketQ, q1 = min(nq, q0 + kBucketQ);
     // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
     // esel (if given): the entry's level mask at the same position
     bucket_slots(probes, sel, q0, q1, m, r0, r1, [&](int64_t e, uint32_t sm, int32_t p) {
@@ -1698,7 +1706,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 const int qbr = mfma && !lowp && (!(seeded_exact && round == 0) || seed_x32) ? lowp_qb_main(ix, disj)
                                                                                             : qb;
                 prof_begin(CAPS_STAGE_SELECT, st);
-                hipLaunchKernelGGL(k_bucket_hist, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                const unsigned ggrid = (unsigned)((ngrp + kXcds - 1) / kXcds * kXcds);   // XCD-mapped groups
+                hipLaunchKernelGGL(k_bucket_hist, dim3(ggrid), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                    nb, m, r0, r1, b, ngrp, hist);
                 {
                     const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, W.scan_sums, st);
@@ -1712,7 +1721,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                                    qbr, (int32_t)grid, W.tiles);
                 // the fill packs each entry's class when entries stay below 2^27
                 const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
-                hipLaunchKernelGGL(k_bucket_fill, dim3(ngrp), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
+                hipLaunchKernelGGL(k_bucket_fill, dim3(ggrid), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
                                    nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries, nc > 1 ? nullptr : W.esel);
                 const int32_t *ent = entries;
                 const uint32_t *esel = W.esel;   // (the class sort writes the level masks itself)
