@@ -198,7 +198,8 @@ struct LowpScan {
     float *qscale, *qaux;
     uint64_t *partials, *tau;
     int32_t *pcnt, *nsurv;
-    int32_t *dpos, *dcnt;         // exact main pass: deferred pairs per query and their count
+    uint64_t *dpos;               // exact main pass: deferred pairs per query, (score key << 32) | position
+    int32_t *dcnt;                // and their count
     int32_t dcap;                 // capacity of each query's deferred list
     int32_t *oflow;               // exact: per query, set by the main pass for the rescue pass
     const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
@@ -207,6 +208,9 @@ struct LowpScan {
 };
 size_t lowp_scan_lds(const Index *ix, int r, int kind, bool disj);
 caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st);
+// The relative rounding margin eta of the exact matrix-core scan's element
+// test (its row bound; the merge applies the same test at a second bound).
+inline float exact_eta(const Index *ix) { return (float)(6.0 * ix->dpad + 64.0) * 0x1p-24f; }
 caps_status lowp_merge(const Index *ix, const float *q, int32_t nb, const uint32_t *sel, int32_t m, int32_t k,
                        int32_t r, const uint64_t *partials, const int32_t *pcnt, const int32_t *cand, int32_t *ncand,
                        int32_t *out_ids, float *out_dist, hipStream_t st);

@@ -35,7 +35,8 @@ struct LowpArgs {
     int32_t *pcnt;              // keys written per (query, probe) (sorted, at most r; the exact main pass writes none)
     uint64_t *tau;              // per query: shared bound on its r-th key
     int32_t *nsurv;             // per query survivor counts, or null (not counted)
-    int32_t *dpos, *dcnt;       // exact: per query deferred pairs (CSR positions) and their count
+    uint64_t *dpos;             // exact: per query deferred pairs, (ordered score of the element test << 32) | CSR position
+    int32_t *dcnt;              // exact: their count per query
     int32_t *oflow;             // exact: per query flag, set when its pairs did not fit (rescue pass input)
     const int32_t *rlist, *rcount;   // rescue pass: tiles with a flagged query and their number
     int32_t m, h, b, r, metric, d, dcap, ntiles;   // ntiles: length of `tiles` (the grid's tile range)
@@ -74,7 +75,7 @@ struct LowpLds {
         xw = take(sizeof(uint32_t) * 2 * kLCH);
         xn = take(sizeof(float) * 2 * kLCH);
         xsc = take(sizeof(float) * 2 * kLCH);
-        ring = take(kind != 0 ? sizeof(uint32_t) * 2 * kLNW * kVRing : 0);
+        ring = take(kind != 0 ? sizeof(uint32_t) * (kind == 1 || kind == 3 ? 3 : 2) * kLNW * kVRing : 0);
         dhist = take(kind == 1 || kind == 3 ? sizeof(int32_t) * kLNW * kLQPW : 0);
         qnq = take(kind != 0 ? sizeof(float) * kLQB : 0);
         scnt = take(sizeof(int32_t) * kLQB);
@@ -280,8 +281,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
 
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int qbase = w * kLQPW;
-    uint32_t *ring_pos = reinterpret_cast<uint32_t *>(smem + L.ring) + w * 2 * kVRing;
+    uint32_t *ring_pos = reinterpret_cast<uint32_t *>(smem + L.ring) + w * (DEFER ? 3 : 2) * kVRing;
     uint32_t *ring_row = ring_pos + kVRing;
+    uint32_t *ring_key = ring_row + kVRing;   // deferring kinds: the pair's ordered score
     int32_t *dhist = reinterpret_cast<int32_t *>(smem + L.dhist) + w * kLQPW;
     float *qnq = reinterpret_cast<float *>(smem + L.qnq);          // exact: |q|^2 per query
     int32_t *scnt = reinterpret_cast<int32_t *>(smem + L.scnt);    // survivors per query (counted runs)
@@ -516,6 +518,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
         const int slot = (vtail + lane) & (kVRing - 1);
         const uint32_t pos = v ? ring_pos[slot] : 0u;
         const int qi = v ? (int)ring_row[slot] : qbase;
+        const uint32_t pkey = DEFER && v ? ring_key[slot] : 0u;
         vtail += n;
         if (DEFER) {
             const int ri = qi - qbase;   // row of the wave, 0..15
@@ -528,7 +531,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
             if (cnt > 0) base = atomicAdd(A.dcnt + my_qq, cnt);
             const int at = __shfl(base, ri, 64) + rank;
             const int32_t qq = qslot[qi] / A.m;
-            if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = (int32_t)pos;
+            if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = ((uint64_t)pkey << 32) | pos;
             if (v && at >= A.dcap) A.oflow[qq] = 1;
         }
         if (RESCUE) {
@@ -678,6 +681,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(NS >= 8 ||
                                 const int sl = (vhead + __popcll(qm & lanemask_lt())) & (kVRing - 1);
                                 ring_pos[sl] = (uint32_t)(c0 + pi);
                                 ring_row[sl] = (uint32_t)qi;
+                                ring_key[sl] = f2ord(canon0(esc[rr]));
                             }
                             vhead += __popcll(qm);
                             continue;
@@ -842,11 +846,15 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ __align__(16) float rw3[PRE][64];
     __shared__ __align__(16) uint32_t xw[2][kXCH];
     __shared__ __align__(16) float xn[2][kXCH];
-    __shared__ uint32_t ring[kXW][2][kXRing];
-    __shared__ int32_t dhist[kXW][kXQ];
-    __shared__ int32_t scnt[kXQB];
-    __shared__ float qmx[2][kXW];
-    __shared__ uint32_t lvw[kXW];
+    __shared__ uint32_t ring[kXW][SEED ? 2 : 3][kXRing];
+    __shared__ int32_t dhist[kXW][kXQ];   // (before the pipeline starts: also the tile's maxima, below)
+    __shared__ int32_t scnt[COUNT ? kXQB : 1];   // (only the counting mode: the modes used per search keep 4 workgroups per CU)
+    // the tile prologue's per-wave maxima share the drain histograms' storage:
+    // every read of them completes before the pipeline's first barrier, and
+    // no drain runs before it
+    static_assert(3 * kXW <= kXQ, "the maxima fit in one wave's histogram");
+    float(*qmx)[kXW] = reinterpret_cast<float(*)[kXW]>(&dhist[0][0]);
+    uint32_t *lvw = reinterpret_cast<uint32_t *>(&dhist[0][2 * kXW]);
 
     const int tile = xcd_tile(blockIdx.x, A.ntiles);
     if (tile < 0) return;
@@ -905,9 +913,11 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         qmx[1][w] = qb;
         lvw[w] = lv;
     }
-    if (COUNT && w == 0) {
-        scnt[lane] = 0;
-        scnt[lane + 64] = 0;
+    if constexpr (COUNT) {
+        if (w == 0) {
+            scnt[lane] = 0;
+            scnt[lane + 64] = 0;
+        }
     }
     // level bounds, one per lane: lane j holds the start of level j, lane
     // h + 1 the end of the partition (read out by lane index, no memory wait)
@@ -1011,6 +1021,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     // query); a query whose list is full is flagged for the rescue pass
     uint32_t *ring_pos = ring[w][0];
     uint32_t *ring_row = ring[w][1];
+    uint32_t *ring_key = ring[w][SEED ? 1 : 2];   // the pair's ordered score (not in the seed mode)
     int32_t *hist = dhist[w];
     int vhead = 0, vtail = 0;
     auto drain = [&](int n) {
@@ -1019,6 +1030,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         const int slot = (vtail + lane) & (kXRing - 1);
         const uint32_t pos = v ? ring_pos[slot] : 0u;
         const int qj = v ? (int)ring_row[slot] : 0;
+        const uint32_t pkey = v ? ring_key[slot] : 0u;
         vtail += n;
         if (lane < kXQ) hist[lane] = 0;
         wave_sync();
@@ -1029,7 +1041,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         if (cnt > 0) base = atomicAdd(A.dcnt + my_qq, cnt);
         const int at = __shfl(base, qj, 64) + rank;
         const int32_t qq = __shfl(my_qq, qj, 64);
-        if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = (int32_t)pos;
+        if (v && at < A.dcap) A.dpos[(int64_t)qq * A.dcap + at] = ((uint64_t)pkey << 32) | pos;
         if (v && at >= A.dcap) A.oflow[qq] = 1;
     };
 
@@ -1157,9 +1169,13 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
                 if (q4 < 3) pnx = *reinterpret_cast<const float4 *>(&xn[pb][rb + 8]);
                 const float pv[4] = {pn.x, pn.y, pn.z, pn.w};
                 uint64_t hit[4];
+                float sc[4];   // the element test's scores (deferred with their pairs)
 #pragma unroll
-                for (int e = 0; e < 4; e++) hit[e] = __builtin_amdgcn_ballot_w64(fmaf(cm, acc[4 * q4 + e], pv[e]) <= tfj);
-                if (COUNT) {   // survivors of the exact filter (statistics only)
+                for (int e = 0; e < 4; e++) {
+                    sc[e] = fmaf(cm, acc[4 * q4 + e], pv[e]);
+                    hit[e] = __builtin_amdgcn_ballot_w64(sc[e] <= tfj);
+                }
+                if constexpr (COUNT) {   // survivors of the exact filter (statistics only)
                     const uint4 pw = *reinterpret_cast<const uint4 *>(&xw[pb][rb]);
                     const uint32_t wv[4] = {pw.x, pw.y, pw.z, pw.w};
                     int c = 0;
@@ -1184,6 +1200,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
                         const int sl = (vhead + __popcll(hm & lanemask_lt())) & (kXRing - 1);
                         ring_pos[sl] = (uint32_t)(c0 + rb + e);
                         ring_row[sl] = (uint32_t)c32;
+                        ring_key[sl] = f2ord(canon0(sc[e]));
                     }
                     vhead += n;
                 }
@@ -1220,7 +1237,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         return;
     } else {
         if (vhead > vtail) drain(vhead - vtail);
-        if (COUNT) {
+        if constexpr (COUNT) {
             __syncthreads();
             if (g == 0 && own && scnt[qi]) atomicAdd(&A.nsurv[my_qq], scnt[qi]);
         }

@@ -461,7 +461,7 @@ caps_status lowp_scan(const Index *ix, const LowpScan &S, hipStream_t st) {
     // MFMA accumulation (at most dpad additions, each within 2^-23 of the
     // sum of magnitudes) is bounded by gam |x~| |q~|, gam = 8 dpad 2^-24
     // (four times that).
-    A.eta = (float)(6.0 * ix->dpad + 64.0) * 0x1p-24f;
+    A.eta = exact_eta(ix);
     A.gam = (float)(8.0 * ix->dpad) * 0x1p-24f;
     // the variant with the filter's slow path: label tests, disjunctions
     const bool lab = ix->sch.label_vocab > 0 || S.disj;

@@ -1188,15 +1188,26 @@ static size_t scan_lds_bytes(int d, int k) {
 }
 
 // ------------------------------------------------------------------ merge
-// Deferred pairs of the exact matrix-core scan: CSR positions per query,
-// rescored here with the plain scan's arithmetic.
+// Deferred pairs of the exact matrix-core scan per query: (ordered score of
+// the scan's element test << 32) | CSR position, rescored here with the plain
+// scan's arithmetic.
 struct Deferred {
-    const int32_t *pos, *cnt;   // null: none
+    const uint64_t *pos;        // null: none
+    const int32_t *cnt;
     const int32_t *oflow;       // queries rescanned by the rescue pass: deferred pairs ignored, partial lists read
     int32_t cap, d;
     const float *vecs, *q;      // FP32 CSR rows, the sub-batch's queries
     const int32_t *perm;
+    const float *qaux;          // the scan's per-query terms (|q|^2 lower bound at 4 q + 1)
+    float eta;                  // the scan's rounding margin
 };
+
+// Deferred pairs kept per query by the exact matrix-core scan (a query with
+// more goes to the rescue pass).
+constexpr int32_t kDeferCap = 512;
+// Pairs rescored first (those with the smallest test scores): k and half
+// again, at least 16, at most 64 (one per lane).
+__device__ inline int merge_first(int k) { return min(64, max(16, k + (k >> 1))); }
 
 template <int KM>
 __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ partials,
@@ -1205,6 +1216,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
                                                int32_t nq, int32_t m, int32_t k, int32_t metric,
                                                int32_t *__restrict__ ids, float *__restrict__ dist,
                                                int32_t *__restrict__ ncand, Deferred D) {
+    __shared__ uint64_t mbuf[4][64], mkb[4][64];   // per wave: round 1's pairs and keys
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= nq) return;
@@ -1222,10 +1234,109 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t *__restrict__ part
     if (D.pos && !D.oflow[q]) {
         const int n = min(D.cnt[q], D.cap);
         const float *qr = D.q + (int64_t)q * D.d;
-        for (int i = lane; i < n; i += 64) {
-            const int32_t pos = D.pos[(int64_t)q * D.cap + i];
+        const uint64_t *src = D.pos + (int64_t)q * D.cap;
+        auto score = [&](uint64_t ent) {   // the pair's exact key
+            const int32_t pos = (int32_t)(uint32_t)ent;
             const float sc = exact_score<8>(D.vecs + (int64_t)pos * D.d, qr, D.d, metric == 0);
-            insert(((uint64_t)f2ord(sc) << 32) | (uint32_t)D.perm[pos]);
+            return ((uint64_t)f2ord(sc) << 32) | (uint32_t)D.perm[pos];
+        };
+        const int first = merge_first(k);
+        if (n <= first) {
+            for (int i = lane; i < n; i += 64) insert(score(src[i]));
+        } else {
+            // Two rounds.  The scan deferred a pair when its test score passed the
+            // row bound of the query's seed key; the same test at any bound tau
+            // fails only for pairs whose exact key is above tau.  Round 1
+            // rescores the `first` pairs with the smallest test scores (more
+            // where scores tie, at most 64); the k-th of their exact keys, K, is
+            // at or above the final k-th key, so round 2 needs only the pairs
+            // that pass the test at bound K.  (first >= k: K is finite.)
+            constexpr int EP = kDeferCap / 64;
+            uint64_t e[EP];   // pair lane + 64 j (~0: none)
+#pragma unroll
+            for (int j = 0; j < EP; j++) {
+                const int i = j * 64 + lane;
+                e[j] = i < n ? src[i] : ~0ull;
+            }
+            auto skey = [](uint64_t v) { return (uint32_t)(v >> 32); };   // (~0 never a valid score key)
+            // T: the first-th smallest test score key (bisection over its
+            // bits, stopped once the range holds a single key)
+            uint32_t ans = 0;
+            int c_lo = 0, c_hi = EP * 64;
+            bool one = false;
+            for (int bit = 31; bit >= 0; bit--) {
+                const uint32_t t = ans | (1u << bit);
+                int c = 0;
+#pragma unroll
+                for (int j = 0; j < EP; j++) c += __popcll(__ballot(skey(e[j]) < t));
+                if (c < first) {
+                    ans = t;
+                    c_lo = c;
+                } else {
+                    c_hi = c;
+                }
+                if (c_hi - c_lo == 1) {
+                    one = true;
+                    break;
+                }
+            }
+            uint32_t T = ans;
+            if (one) {
+                uint64_t mn = ~0ull;
+#pragma unroll
+                for (int j = 0; j < EP; j++)
+                    if (skey(e[j]) >= ans && skey(e[j]) < mn) mn = skey(e[j]);
+                T = (uint32_t)wave_min_u64(mn);
+            }
+            // round 1: the pairs below T, then those at T, up to 64, compacted
+            uint64_t *buf = mbuf[threadIdx.x >> 6];
+            const uint64_t lt = lanemask_lt();
+            int n1 = 0;
+#pragma unroll
+            for (int j = 0; j < EP; j++) {
+                const bool s = e[j] != ~0ull && skey(e[j]) < T;
+                const uint64_t b = __ballot(s);
+                if (s) {
+                    buf[n1 + __popcll(b & lt)] = e[j];
+                    e[j] = ~0ull;
+                }
+                n1 += __popcll(b);
+            }
+#pragma unroll
+            for (int j = 0; j < EP; j++) {
+                const bool s = e[j] != ~0ull && skey(e[j]) == T;
+                const uint64_t b = __ballot(s);
+                const int at = n1 + __popcll(b & lt);
+                if (s && at < 64) {
+                    buf[at] = e[j];
+                    e[j] = ~0ull;
+                }
+                n1 = min(64, n1 + __popcll(b));
+            }
+            wave_sync();
+            uint64_t k1 = ~0ull;
+            if (lane < n1) {
+                k1 = score(buf[lane]);
+                insert(k1);
+            }
+            // K: the k-th smallest of round 1's keys (distinct: the ids differ)
+            uint64_t *kb = mkb[threadIdx.x >> 6];
+            kb[lane] = k1;
+            wave_sync();
+            int rank = 0;
+            if (lane < n1)
+                for (int i = 0; i < n1; i++) rank += kb[i] < k1 ? 1 : 0;
+            const uint64_t kl = __ballot(lane < n1 && rank == k - 1);
+            const uint64_t K = kl ? readlane_u64(k1, __builtin_ctzll(kl)) : ~0ull;
+            // round 2: the row bound at K's score, as the scan computes it
+            const float td = bound_score(K);
+            const float nq = D.qaux[4 * (int64_t)q + 1];
+            const float tf = !(td < __builtin_huge_valf()) ? __builtin_huge_valf()
+                             : metric == 0                 ? fmaf(D.eta, nq + td, td - nq) + 1e-37f
+                                                           : fmaf(D.eta, nq + fabsf(td), td) + 1e-37f;
+#pragma unroll
+            for (int j = 0; j < EP; j++)
+                if (e[j] != ~0ull && ord2f(skey(e[j])) <= tf) insert(score(e[j]));
         }
     }
     // with deferred pairs the partial lists hold keys only for the queries the
@@ -1350,7 +1461,8 @@ struct SearchWs {
     int32_t *cand, *entries, *entries2;   // entries2: class-grouped copy
     uint32_t *esel;             // exact matrix-core scan: level mask per entry of the scanned entry list
     uint64_t *partials, *tau;
-    int32_t *dpos, *dcnt;       // exact matrix-core scan: deferred pairs per query
+    uint64_t *dpos;             // exact matrix-core scan: deferred pairs per query (score key, position)
+    int32_t *dcnt;
     int32_t *oflow;             // exact matrix-core scan: queries for the rescue pass
     int32_t *rlist, *rcount;    // exact matrix-core scan: tiles for the rescue pass
     int32_t *hist, *hscan, *scan_sums, *htotal, *pcount, *pstart, *tstart;
@@ -1369,9 +1481,6 @@ struct SearchWs {
 // XCD multiple of the grid.
 static int64_t tile_cap(int64_t sb, int64_t m, int64_t b) { return (sb * m + 63) / 64 + b + kXcds; }
 
-// Deferred pairs kept per query by the exact matrix-core scan (more are
-// rescored inside the scan).
-constexpr int32_t kDeferCap = 512;
 
 static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int32_t m, int32_t k,
                   bool own_ncand, bool own_nsurv, size_t qlow_row_bytes, const Router *router, bool defer,
@@ -1393,7 +1502,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.entries = ar.take<int32_t>((size_t)sb * m);
     w.partials = ar.take<uint64_t>((size_t)sb * m * k);
     w.tau = ar.take<uint64_t>((size_t)sb);
-    w.dpos = defer ? ar.take<int32_t>((size_t)sb * kDeferCap) : nullptr;
+    w.dpos = defer ? ar.take<uint64_t>((size_t)sb * kDeferCap) : nullptr;
     w.dcnt = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     w.oflow = defer ? ar.take<int32_t>((size_t)sb) : nullptr;
     // (main-pass tiles of 128 entries are listed by half: one more per partition)
@@ -1841,6 +1950,8 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 D.vecs = ix->vecs;
                 D.q = q + (int64_t)q0 * d;
                 D.perm = ix->perm;
+                D.qaux = W.qaux;
+                D.eta = exact_eta(ix);
             }
             if (k <= 16)
                 hipLaunchKernelGGL(k_merge<16>, dim3(nblocks(nb, 4)), dim3(256), 0, st, partials, mcnt, sel, cand, nb, m,
