@@ -269,16 +269,33 @@ def aft(a, b, h, tk: Tokens):
     return tags.reshape(b, h), level
 
 
-def csr(a, level, b, h):
+def attribute_order(dense, n):
+    """The ids sorted by their dense attribute values, attribute 0 first,
+    ties by ascending id (a stable lexicographic sort); ascending ids when
+    there are no dense attributes."""
+    if dense is None or np.asarray(dense).size == 0:
+        return np.arange(n, dtype=np.int32)
+    dense = np.asarray(dense)
+    return np.lexsort(tuple(dense[:, j] for j in range(dense.shape[1] - 1, -1, -1))).astype(np.int32)
+
+
+def csr(a, level, b, h, dense=None, order=None):
+    """CSR layout (Appendix "Index size"): points grouped by (partition,
+    level); inside a sub-partition in `order` (default: attribute_order of
+    `dense`, i.e. by dense attribute values, then id)."""
     a = _c(a, np.int32)
     level = _c(level, np.int8)
     n = a.shape[0]
+    if order is None:
+        order = attribute_order(dense, n)
+    order = _c(order, np.int32)
+    assert order.shape == (n,)
     perm = np.zeros(n, dtype=np.int32)
     offs = np.zeros(b * (h + 1) + 1, dtype=np.int32)
     L = lib()
     L.orc_csr.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
-                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    L.orc_csr(n, _p(a), _p(level), b, h, _p(perm), _p(offs))
+                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_csr(n, _p(a), _p(level), b, h, _p(order), _p(perm), _p(offs))
     return perm, offs
 
 
@@ -308,7 +325,7 @@ def build_index(x, dense, dense_vocab, label_off, labels, label_vocab, *, metric
         init = init_ids(seed, x.shape[0], b)
     cent, a = kmeans(x, b, iters, metric, init=init)
     tags, level = aft(a, b, h, tk)
-    perm, offs = csr(a, level, b, h)
+    perm, offs = csr(a, level, b, h, dense)
     return Index(x, tk, metric, b, h, cent, a, tags, level, perm, offs, np.asarray(init))
 
 
@@ -340,7 +357,7 @@ def build_assigned(x, dense, dense_vocab, label_off, labels, label_vocab, assign
     a = _c(assign, np.int32)
     cent = update(x, a, x[np.asarray(init)], metric)
     tags, level = aft(a, b, h, tk)
-    perm, offs = csr(a, level, b, h)
+    perm, offs = csr(a, level, b, h, dense)
     return Index(x, tk, metric, b, h, cent, a, tags, level, perm, offs, np.asarray(init))
 
 
@@ -349,7 +366,8 @@ def insert(idx: Index, x_new, dense_new, label_off_new, labels_new) -> Index:
     points get ids n, n+1, ... and join the frozen partition model -- the
     centroid the k-means assignment picks, then the first tagged level whose
     tag they hold, else the remainder; centroids and tags are unchanged and
-    the CSR is laid out again in (partition, level, id) order."""
+    the CSR is laid out again: the points already present in their order,
+    each new point at the end of its sub-partition, in ascending id."""
     x_new = _c(x_new, np.float32)
     n_new = x_new.shape[0]
     tk = idx.tk
@@ -369,7 +387,10 @@ def insert(idx: Index, x_new, dense_new, label_off_new, labels_new) -> Index:
                   tk.label_vocab)
     a_all = np.concatenate([idx.assign, a_new]).astype(np.int32)
     l_all = np.concatenate([idx.level, lev_new]).astype(np.int8)
-    perm, offs = csr(a_all, l_all, idx.b, idx.h)
+    # the points already present keep their CSR order; the new ones follow
+    # at the end of their sub-partition in ascending id
+    perm, offs = csr(a_all, l_all, idx.b, idx.h,
+                     order=np.concatenate([idx.perm, np.arange(idx.x.shape[0], idx.x.shape[0] + n_new)]))
     return Index(np.concatenate([idx.x, x_new]), allt, idx.metric, idx.b, idx.h, idx.centroids, a_all,
                  idx.tags, l_all, perm, offs, idx.init)
 

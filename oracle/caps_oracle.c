@@ -297,18 +297,24 @@ void orc_insert_levels(int64_t n_new, const int32_t *assign, const int32_t *tags
     }
 }
 
-/* CSR over sub-partitions (Appendix "Index size"): order points by
- * (partition, level, id); offs[p*(h+1)+j] is the first CSR position of
- * sub-partition j of partition p, offs[B*(h+1)] = n; perm[pos] = point id. */
+/* CSR over sub-partitions (Appendix "Index size"): points grouped by
+ * (partition, level); offs[p*(h+1)+j] is the first CSR position of
+ * sub-partition j of partition p, offs[B*(h+1)] = n; perm[pos] = point id.
+ * The paper leaves the order inside a sub-partition open.  Here it is the
+ * order in which `order` lists the points (a permutation of the ids; NULL:
+ * ascending id): the caller passes the points sorted by their dense
+ * attribute values (attribute 0 first), ties by id, so that points with equal
+ * values sit next to each other. */
 void orc_csr(int64_t n, const int32_t *assign, const int8_t *level, int32_t b, int32_t h,
-             int32_t *perm, int32_t *offs)
+             const int32_t *order, int32_t *perm, int32_t *offs)
 {
     int64_t nk = (int64_t)b * (h + 1);
     int64_t *pos = (int64_t *)calloc((size_t)nk + 1, sizeof(int64_t));
     for (int64_t i = 0; i < n; i++) pos[(int64_t)assign[i] * (h + 1) + level[i] + 1]++;
     for (int64_t s = 0; s < nk; s++) pos[s + 1] += pos[s];
     for (int64_t s = 0; s <= nk; s++) offs[s] = (int32_t)pos[s];
-    for (int64_t i = 0; i < n; i++) {
+    for (int64_t u = 0; u < n; u++) {
+        int64_t i = order ? order[u] : u;
         int64_t key = (int64_t)assign[i] * (h + 1) + level[i];
         perm[pos[key]++] = (int32_t)i;
     }

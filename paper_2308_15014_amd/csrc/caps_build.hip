@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kAftNT) void k_aft(const int32_t *__restrict__ sort
         if (p == b - 1) offs[(int64_t)b * (h + 1)] = (int32_t)n;
     }
     __syncthreads();
-    // stable placement: level-major, ascending id inside a level
+    // stable placement: level-major, in the order of `sorted` inside a level
     for (int32_t g = lo; g < hi; g += kAftNT) {
         const int32_t u = g + t;
         const int32_t l = u < hi ? lev_tmp[u] : -1;
@@ -475,6 +475,79 @@ __global__ void k_iota(int32_t *__restrict__ p, int64_t n, int32_t base) {
     if (i < n) p[i] = base + (int32_t)i;
 }
 
+// ---- order inside a partition: by dense attribute values, then id
+// Each point's dense values as one key, attribute 0 in the most significant
+// field (the packed word holds attribute 0 in its least significant field).
+__global__ void k_attr_key(const uint32_t *__restrict__ dense, int64_t n, Schema sch, int32_t tot_bits,
+                           uint32_t *__restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t k = 0;
+    for (int a = 0; a < sch.n_dense; a++)
+        k |= dense[i * sch.n_dense + a] << (tot_bits - sch.field_shift[a] - sch.field_bits[a]);
+    key[i] = k;
+}
+
+// out[i] = (key[seq[i]] >> shift) & mask
+__global__ void k_seq_digit(const uint32_t *__restrict__ key, const int32_t *__restrict__ seq, int64_t n,
+                            int32_t shift, uint32_t mask, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)((key[seq[i]] >> shift) & mask);
+}
+
+// out[i] = a[idx[i]]
+__global__ void k_gather_i32(const int32_t *__restrict__ a, const int32_t *__restrict__ idx, int64_t n,
+                             int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[idx[i]];
+}
+
+// The ids grouped by partition (hscan as stable_sort leaves it), inside a
+// partition sorted by their dense attribute values (attribute 0 first), ties
+// by ascending id: LSD passes of the stable counting sort over the key's
+// digits, then the stable partition pass.  Points with equal values end up
+// next to each other in every sub-partition, so a run of rows shares its
+// values (the scans skip runs no query of a group can match).
+static caps_status attribute_grouped(const uint32_t *ddense, const int32_t *assign, int64_t n, int32_t b,
+                                     const Schema &sch, int32_t *hist, int32_t *hscan, int32_t *sums,
+                                     int32_t *sorted, hipStream_t st) {
+    constexpr int kDigit = 8;
+    int32_t tot_bits = 0;
+    for (int a = 0; a < sch.n_dense; a++) tot_bits += sch.field_bits[a];
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    const int32_t nblk = (int32_t)((n + kSortBlock - 1) / kSortBlock);
+    DevBuf dkey, dseq, dseq2, ddig, dord, dh, dhs, dsm;
+    CAPS_HIP(hipMalloc(&dkey.p, sizeof(uint32_t) * (size_t)n));
+    CAPS_HIP(hipMalloc(&dseq.p, sizeof(int32_t) * (size_t)n));
+    CAPS_HIP(hipMalloc(&dseq2.p, sizeof(int32_t) * (size_t)n));
+    CAPS_HIP(hipMalloc(&ddig.p, sizeof(int32_t) * (size_t)n));
+    CAPS_HIP(hipMalloc(&dord.p, sizeof(int32_t) * (size_t)n));
+    CAPS_HIP(hipMalloc(&dh.p, sizeof(int32_t) * ((size_t)1 << kDigit) * nblk));
+    CAPS_HIP(hipMalloc(&dhs.p, sizeof(int32_t) * ((size_t)1 << kDigit) * nblk));
+    CAPS_HIP(hipMalloc(&dsm.p, sizeof(int32_t) * (size_t)exclusive_scan_tiles(((int64_t)1 << kDigit) * nblk)));
+    uint32_t *key = (uint32_t *)dkey.p;
+    int32_t *seq = (int32_t *)dseq.p, *seq2 = (int32_t *)dseq2.p, *dig = (int32_t *)ddig.p, *ord = (int32_t *)dord.p;
+    hipLaunchKernelGGL(k_attr_key, dim3(grid), dim3(256), 0, st, ddense, n, sch, tot_bits, key);
+    hipLaunchKernelGGL(k_iota, dim3(grid), dim3(256), 0, st, seq, n, 0);
+    for (int sh = 0; sh < tot_bits; sh += kDigit) {
+        const int bits = std::min(kDigit, tot_bits - sh);
+        hipLaunchKernelGGL(k_seq_digit, dim3(grid), dim3(256), 0, st, (const uint32_t *)key, (const int32_t *)seq,
+                           n, sh, (uint32_t)((1u << bits) - 1u), dig);
+        CAPS_TRY(stable_sort(dig, n, 1 << bits, (int32_t *)dh.p, (int32_t *)dhs.p, (int32_t *)dsm.p, ord, st));
+        hipLaunchKernelGGL(k_gather_i32, dim3(grid), dim3(256), 0, st, (const int32_t *)seq, (const int32_t *)ord,
+                           n, seq2);
+        std::swap(seq, seq2);
+    }
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid), dim3(256), 0, st, assign, (const int32_t *)seq, n, dig);
+    CAPS_TRY(stable_sort(dig, n, b, hist, hscan, sums, ord, st));
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid), dim3(256), 0, st, (const int32_t *)seq, (const int32_t *)ord, n,
+                       sorted);
+    CAPS_HIP(hipGetLastError());
+    // the buffers are freed at return: the stream must be done with them
+    CAPS_HIP(hipStreamSynchronize(st));
+    return CAPS_OK;
+}
+
 caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const uint32_t *dense,
                         const int64_t *label_off, const uint32_t *labels,
                         const caps_build_params *p, hipStream_t st) {
@@ -572,6 +645,9 @@ caps_status build_index(Index *ix, const float *x, int64_t n, int32_t d, const u
     hipLaunchKernelGGL(k_cnorm, dim3((b + 255) / 256), dim3(256), 0, st, ix->cent, b, d, ix->cnorm);
 
     AttrSrc src{(const uint32_t *)ddense.p, (const int64_t *)dloff.p, (const uint32_t *)dlab.p};
+    if (sch.n_dense)
+        CAPS_TRY(attribute_grouped((const uint32_t *)ddense.p, A, n, b, sch, hist, hscan, (int32_t *)dsums.p,
+                                   sorted, st));
     hipLaunchKernelGGL(k_aft, dim3(b), dim3(kAftNT), sizeof(int32_t) * (size_t)sch.n_tok, st, sorted,
                        hscan, nblk, n, b, h, sch, src, (int32_t *)dlev.p, ix->level, ix->tags, ix->perm,
                        ix->offs);
@@ -600,10 +676,9 @@ namespace caps {
 
 // Dynamic insertion (Table 1 "Dynamic Insertions"): the partition model
 // stays frozen.  New point i gets id n + i, the partition the k-means
-// assignment picks and the first tagged level whose tag it holds; the CSR
-// keeps its (partition, level, id) order, so every old row moves by the
-// number of new rows in earlier segments and the new rows go to the end of
-// their segments in id order.  Every per-row array (vectors, packed
+// assignment picks and the first tagged level whose tag it holds; the old
+// rows keep their CSR order, each moved by the number of new rows in earlier
+// segments, and the new rows go to the end of their segments in id order.  Every per-row array (vectors, packed
 // attributes, low-precision copy and its norms, permutation) is laid out
 // again in one pass; centroids, tags and the router are unchanged.
 caps_status insert_points(Index *ix, const float *x, int64_t n_new, const uint32_t *dense, const int64_t *label_off,

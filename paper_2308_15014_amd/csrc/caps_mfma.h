@@ -840,12 +840,13 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ __align__(16) uint8_t xb1[kXCH * ROWB];
     __shared__ __align__(16) uint8_t xb2[kXCH * ROWB];
     __shared__ __align__(16) uint8_t xb3[kXCH * ROWB];
-    __shared__ __align__(16) float rw0[PRE][64];   // the per-point inputs of each buffer's chunk
-    __shared__ __align__(16) float rw1[PRE][64];
-    __shared__ __align__(16) float rw2[PRE][64];
-    __shared__ __align__(16) float rw3[PRE][64];
+    __shared__ __align__(16) float rw0[PRE][kXCH];   // the per-point inputs of each buffer's chunk
+    __shared__ __align__(16) float rw1[PRE][kXCH];
+    __shared__ __align__(16) float rw2[PRE][kXCH];
+    __shared__ __align__(16) float rw3[PRE][kXCH];
     __shared__ __align__(16) uint32_t xw[2][kXCH];
     __shared__ __align__(16) float xn[2][kXCH];
+    __shared__ uint32_t xsum[2][2];   // AND and OR of each point slot's packed words (the chunk's rows)
     __shared__ uint32_t ring[kXW][SEED ? 2 : 3][kXRing];
     __shared__ int32_t dhist[kXW][kXQ];   // (before the pipeline starts: also the tile's maxima, below)
     __shared__ int32_t scnt[COUNT ? kXQB : 1];   // (only the counting mode: the modes used per search keep 4 workgroups per CU)
@@ -864,7 +865,8 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     const int nqt = dsc.z;
     const int32_t *ent = A.entries + dsc.y;
     const int h = A.h;
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);   // (wave-uniform: kept in a scalar register)
     const int g = lane >> 5, c32 = lane & 31;
     const bool has_dense = A.words != nullptr;
     const bool l2 = A.metric == 0;
@@ -971,7 +973,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     // piece ^ swizzle of the row; rows past the level's end load its last row
     // and are masked by a NaN point term; loads past NDMA (short rows) repeat
     // load i - NDMA.  Per-point load of wave w, lane L: input w (squared
-    // norm, error norms, packed dense word) of row c0 + min(L, cn - 1).
+    // norm, error norms, packed dense word) of row c0 + min(L, cn - 1), L < 32.
     uint32_t voff[UPW];
     int vrow[UPW];
 #pragma unroll
@@ -999,20 +1001,45 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
                                              0, 0);
         }
     };
-    auto fetch_points = [&](bool real, int32_t c0, int cn, float (*raw)[64]) {
-        const int64_t row = real ? c0 + min(lane, cn - 1) : 0;
-        __builtin_amdgcn_global_load_lds(psrc + row, (__attribute__((address_space(3))) void *)raw[w], 4, 0, 0);
+    auto fetch_points = [&](bool real, int32_t c0, int cn, float (*raw)[kXCH]) {
+        // lanes 0..31 (lane L fills raw[w][L]; every wave has them active, so
+        // the load is issued on every path)
+        if (lane < kXCH) {
+            const int64_t row = real ? c0 + min(lane, cn - 1) : 0;
+            __builtin_amdgcn_global_load_lds(psrc + row, (__attribute__((address_space(3))) void *)raw[w], 4, 0, 0);
+        }
     };
     // the point terms of a chunk whose per-point inputs have landed (one
     // wave per chunk, in turn)
-    auto point_terms = [&](float (*raw)[64], int cn, int pb) {
+    auto point_terms = [&](float (*raw)[kXCH], int cn, int pb) {
         const float nx = raw[0][c32];
         const float slack = fmaf(raw[1][c32], qa, raw[2][c32] * qb) * (1.0f + 0x1p-20f);
         float pt = l2 ? fmaf(-A.eta, nx, fmaf(-2.0f, slack, nx)) : fmaf(-A.eta, nx, -slack);
         if (!(fabsf(pt) < inf)) pt = -inf;
         if (SEED) pt = l2 ? nx : 0.0f;   // approximate keys: the plain point term
         xn[pb][c32] = c32 < cn ? pt : qnan;   // (lanes l and l + 32 write alike)
-        xw[pb][c32] = has_dense ? __float_as_uint(raw[3][c32]) : 0u;
+        const uint32_t wd = has_dense ? __float_as_uint(raw[3][c32]) : 0u;
+        xw[pb][c32] = wd;
+        // the chunk's summary for the skip test: AND and OR of its rows'
+        // words, reduced inside each 16-lane row by rotations (DPP row_ror
+        // 1, 2, 4, 8), then rows 0 and 1 (lanes 0..31 hold the chunk's rows)
+        int wa = c32 < cn ? (int)wd : -1, wo = c32 < cn ? (int)wd : 0;
+        wa &= __builtin_amdgcn_mov_dpp(wa, 0x121, 0xF, 0xF, false);
+        wo |= __builtin_amdgcn_mov_dpp(wo, 0x121, 0xF, 0xF, false);
+        wa &= __builtin_amdgcn_mov_dpp(wa, 0x122, 0xF, 0xF, false);
+        wo |= __builtin_amdgcn_mov_dpp(wo, 0x122, 0xF, 0xF, false);
+        wa &= __builtin_amdgcn_mov_dpp(wa, 0x124, 0xF, 0xF, false);
+        wo |= __builtin_amdgcn_mov_dpp(wo, 0x124, 0xF, 0xF, false);
+        wa &= __builtin_amdgcn_mov_dpp(wa, 0x128, 0xF, 0xF, false);
+        wo |= __builtin_amdgcn_mov_dpp(wo, 0x128, 0xF, 0xF, false);
+        // (the lane reads stay outside the single-lane branch below: they
+        // read lanes that branch leaves inactive)
+        const uint32_t sa = (uint32_t)(__builtin_amdgcn_readlane(wa, 0) & __builtin_amdgcn_readlane(wa, 16));
+        const uint32_t so = (uint32_t)(__builtin_amdgcn_readlane(wo, 0) | __builtin_amdgcn_readlane(wo, 16));
+        if (lane == 0) {
+            xsum[pb][0] = sa;
+            xsum[pb][1] = so;
+        }
     };
 
     // deferred pairs of this wave: (CSR position, wave query) in a ring of
@@ -1061,7 +1088,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     int fj = cj, rj = cj;
     int32_t fc0 = cc0, fend = cend, rc0 = cc0, rend = cend;
     advance(rj, rc0, rend);
-    auto fetch_next = [&](uint8_t *dst, float (*raw)[64]) {
+    auto fetch_next = [&](uint8_t *dst, float (*raw)[kXCH]) {
         const bool fr = fj <= h, rr = rj <= h;
         fetch_rows(fr, fc0, fr ? min(kXCH, fend - fc0) : 1, dst);
         fetch_points(rr, rc0, rr ? min(kXCH, rend - rc0) : 1, raw);
@@ -1087,7 +1114,7 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     // Chunk k from buffer `cur` (point arrays `pb`); `nraw` holds the inputs
     // of chunk k + 1, whose point terms wave `ptw` (k % 4) computes; F_{k+3}
     // goes to `nxt` and `fraw`.  Returns whether another chunk follows.
-    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb, float (*nraw)[64], float (*fraw)[64],
+    auto step = [&](const uint8_t *cur, uint8_t *nxt, const int pb, float (*nraw)[kXCH], float (*fraw)[kXCH],
                     const int ptw) -> bool {
         const int j = cj;
         const int32_t c0 = cc0;
@@ -1102,6 +1129,17 @@ __global__ __launch_bounds__(kXW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         fetch_next(nxt, fraw);
         if (w == ptw && more) point_terms(nraw, min(kXCH, cend - cc0), pb ^ 1);
         if (kXQ * w >= nqt) return more;   // a wave without queries (small batches) only stages
+        {
+            // A row passes (w & M) == V only if every bit of V is set in the
+            // OR of the chunk's words and every other bit of M is clear in
+            // their AND: where no query of the wave can pass a row of the
+            // chunk, its products and tests are skipped (the queries of a
+            // wave share constraints and a sub-partition's rows are grouped
+            // by their values, so this is common)
+            const uint32_t wa = xsum[pb][0], wo = xsum[pb][1];
+            const uint32_t miss = (my_val & ~wo) | (~my_val & my_mask & wa) | (((my_sel >> j) & 1u) ^ 1u);
+            if (!__builtin_amdgcn_ballot_w64(miss == 0u)) return more;
+        }
 
         f32x16 acc = {};
 #pragma unroll

@@ -523,13 +523,15 @@ inline int32_t bucket_classes(int32_t h) { return h <= 3 ? 1 << (h + 1) : 1; }
 
 constexpr int kBucketT = 1024;   // threads per bucketing block
 
-// The block's (query, probe-slot) span [q0, q1) x [r0, r1), flattened: thread
+// The block's (query, probe-slot) span [q0, q1) x [r0, r1), flattened (with
+// qord: positions q0..q1 of that query order): thread
 // t visits flat slots t, t + T, ... (coalesced, one division per thread), four
 // at a time with all their loads issued before any is used.  visit(e, mask,
 // partition) runs for each chosen slot e.
 template <typename F>
 __device__ inline void bucket_slots(const int32_t *__restrict__ probes, const uint32_t *__restrict__ sel,
-                                    int32_t q0, int32_t q1, int32_t m, int32_t r0, int32_t r1, F &&visit) {
+                                    const int32_t *__restrict__ qord, int32_t q0, int32_t q1, int32_t m, int32_t r0,
+                                    int32_t r1, F &&visit) {
     const int32_t w = r1 - r0;
     if (w <= 0 || q1 <= q0) return;
     const int32_t n = (q1 - q0) * w, T = (int32_t)blockDim.x, t = (int32_t)threadIdx.x;
@@ -542,7 +544,7 @@ __device__ inline void bucket_slots(const int32_t *__restrict__ probes, const ui
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const bool ok = f + u * T < n;
-            e[u] = (int64_t)qq * m + rr;
+            e[u] = (int64_t)(ok && qord ? qord[qq] : qq) * m + rr;
             sm[u] = ok ? sel[e[u]] : 0u;
             pr[u] = ok ? probes[e[u]] : 0;
             rr += dr;   // advance the flat slot by T
@@ -558,8 +560,64 @@ __device__ inline void bucket_slots(const int32_t *__restrict__ probes, const ui
     }
 }
 
+// Query order for the bucketing: the queries sorted by their dense
+// constraint in the order in which the CSR lays out the rows of a
+// sub-partition (dense values, attribute 0 first), so that the queries
+// sharing a tile's wave tend to match the same runs of rows and the exact
+// main pass skips the row chunks none of them can match.  Any order gives
+// the same results.  The key holds one field per dense attribute, attribute 0
+// most significant: the value where the query constrains the attribute, else
+// one past every value; a counting sort over its top kQordBits bits (one
+// workgroup, LDS histogram; the order inside a bucket is arbitrary).
+constexpr int kQordT = 1024;
+constexpr int kQordBits = 13;
+
+__device__ inline uint32_t qorder_key(const QDesc &d, const Schema &sch, int32_t shift) {
+    uint64_t k = 0;
+    for (int a = 0; a < sch.n_dense; a++) {
+        const uint32_t fb = (uint32_t)sch.field_bits[a];
+        const uint32_t fm = (uint32_t)((1ull << fb) - 1ull);
+        const uint32_t f = (d.dmask >> sch.field_shift[a]) & fm ? (d.dval >> sch.field_shift[a]) & fm : fm + 1u;
+        k = (k << (fb + 1)) | f;   // (at most 40 bits: fields of at most 32 bits, 8 attributes)
+    }
+    return (uint32_t)(k >> shift);
+}
+
+__global__ __launch_bounds__(kQordT) void k_qorder(const QDesc *__restrict__ qd, int32_t nq, Schema sch,
+                                                   int32_t shift, int32_t nk, int32_t *__restrict__ qord) {
+    extern __shared__ int32_t cnt[];   // nk buckets
+    __shared__ int32_t part[kQordT];
+    const int t = threadIdx.x;
+    for (int32_t i = t; i < nk; i += kQordT) cnt[i] = 0;
+    __syncthreads();
+    for (int32_t q = t; q < nq; q += kQordT) atomicAdd(&cnt[qorder_key(qd[q], sch, shift)], 1);
+    __syncthreads();
+    // exclusive prefix over the buckets: thread t sums its run of buckets,
+    // a scan over the threads, then each run is written out
+    const int32_t per = (nk + kQordT - 1) / kQordT, b0 = t * per, b1 = min(nk, b0 + per);
+    int32_t sum = 0;
+    for (int32_t i = b0; i < b1; i++) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < kQordT; o <<= 1) {
+        const int32_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int32_t i = b0; i < b1; i++) {
+        const int32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int32_t q = t; q < nq; q += kQordT) qord[atomicAdd(&cnt[qorder_key(qd[q], sch, shift)], 1)] = q;
+}
+
 __global__ __launch_bounds__(kBucketT) void k_bucket_hist(const int32_t *__restrict__ probes,
-                                                          const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                          const uint32_t *__restrict__ sel,
+                                                          const int32_t *__restrict__ qord, int32_t nq, int32_t m,
                                                           int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
                                                           int32_t *__restrict__ hist) {
     const int g = xcd_tile(blockIdx.x, ngrp);   // query group (consecutive groups on one XCD)
@@ -568,14 +626,15 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_hist(const int32_t *__restr
     for (int i = threadIdx.x; i < b; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     const int32_t q0 = g * kBucketQ, q1 = min(nq, q0 + kBucketQ);
-    bucket_slots(probes, sel, q0, q1, m, r0, r1,
+    bucket_slots(probes, sel, qord, q0, q1, m, r0, r1,
                  [&](int64_t, uint32_t, int32_t p) { atomicAdd(&cnt[p], 1); });
     __syncthreads();
     for (int i = threadIdx.x; i < b; i += blockDim.x) hist[(int64_t)i * ngrp + g] = cnt[i];
 }
 
 __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restrict__ probes,
-                                                          const uint32_t *__restrict__ sel, int32_t nq, int32_t m,
+                                                          const uint32_t *__restrict__ sel,
+                                                          const int32_t *__restrict__ qord, int32_t nq, int32_t m,
                                                           int32_t r0, int32_t r1, int32_t b, int32_t ngrp,
                                                           const int32_t *__restrict__ hscan, int32_t nc_pack,
                                                           int32_t *__restrict__ entries, uint32_t *__restrict__ esel) {
@@ -591,7 +650,7 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restr
     const int32_t q0 = g * kBucketQ, q1 = min(nq, q0 + kBucketQ);
     // nc_pack > 1: the level-mask class rides in bits 27.. for k_class_sort
     // esel (if given): the entry's level mask at the same position
-    bucket_slots(probes, sel, q0, q1, m, r0, r1, [&](int64_t e, uint32_t sm, int32_t p) {
+    bucket_slots(probes, sel, qord, q0, q1, m, r0, r1, [&](int64_t e, uint32_t sm, int32_t p) {
         const int32_t at = atomicAdd(&run[p], 1);
         entries[at] = (int32_t)e | (nc_pack > 1 ? (int32_t)(sm & (uint32_t)(nc_pack - 1)) << kClassShift : 0);
         if (esel) esel[at] = sm;
@@ -599,7 +658,7 @@ __global__ __launch_bounds__(kBucketT) void k_bucket_fill(const int32_t *__restr
 }
 
 // One workgroup per partition: copies its entries from `in` to `out` grouped
-// by level-mask class (in any order within a class).  The class is packed
+// by level-mask class (in their order within a class).  The class is packed
 // above bit kClassShift of each entry (packed != 0) or read from `sel`.
 // With esel_out, each entry's class (its whole level mask: nc = 2^(h+1)) is
 // written beside it.
@@ -619,11 +678,14 @@ __global__ __launch_bounds__(kClassW * 64) void k_class_sort(const int32_t *__re
     auto cls_of = [&](int32_t v) {
         return packed ? (v >> kClassShift) & (nc - 1) : (int32_t)(sel[v] & (uint32_t)(nc - 1));
     };
-    // pass 1: per wave and class, its entries (64-entry blocks w, w + kClassW, ...)
+    // pass 1: per wave and class, its entries (wave w takes a contiguous run
+    // of 64-entry blocks, so that a class keeps the order of the fill)
+    const int32_t nblk = (pn + 63) / 64, bpw = (nblk + kClassW - 1) / kClassW;
+    const int32_t e0 = min(pn, w * bpw * 64), e1 = min(pn, (w + 1) * bpw * 64);
     int32_t cnt = 0;   // lane c < nc: this wave's count of class c
-    for (int32_t i0 = w * 64; i0 < pn; i0 += kClassW * 64) {
+    for (int32_t i0 = e0; i0 < e1; i0 += 64) {
         const int32_t i = i0 + lane;
-        const int32_t c = i < pn ? cls_of(in[ps + i]) : -1;
+        const int32_t c = i < e1 ? cls_of(in[ps + i]) : -1;
         for (int k = 0; k < nc; k++) {
             const int32_t n = __popcll(__ballot(c == k));
             if (lane == k) cnt += n;
@@ -641,10 +703,10 @@ __global__ __launch_bounds__(kClassW * 64) void k_class_sort(const int32_t *__re
     }
     // pass 2: place
     const uint64_t lt = lanemask_lt();
-    for (int32_t i0 = w * 64; i0 < pn; i0 += kClassW * 64) {
+    for (int32_t i0 = e0; i0 < e1; i0 += 64) {
         const int32_t i = i0 + lane;
-        const int32_t v = i < pn ? in[ps + i] : 0;
-        const int32_t c = i < pn ? cls_of(v) : -1;
+        const int32_t v = i < e1 ? in[ps + i] : 0;
+        const int32_t c = i < e1 ? cls_of(v) : -1;
         for (int k = 0; k < nc; k++) {
             const uint64_t bk = __ballot(c == k);
             const int32_t bk0 = __shfl(base, k, 64);
@@ -1473,6 +1535,7 @@ struct SearchWs {
     int32_t *probes_c;          // learned routing: centroid probes of the falling-back queries
     int32_t *fbq, *nfb;         // learned routing: the queries that fall back, their count
     int32_t *bad;               // query rows holding NaN or Inf (one counter per call)
+    int32_t *qord;              // bucketing order of the queries (grouped by constraint)
     QDesc *qterms;              // disjunctive searches: term descriptors (kMaxTerms per query)
 };
 
@@ -1495,6 +1558,7 @@ static void carve(Arena &ar, SearchWs &w, int32_t nq, int32_t sb, int32_t b, int
     w.ncand = own_ncand ? ar.take<int32_t>(nq) : nullptr;
     w.nsurv = own_nsurv ? ar.take<int32_t>(nq) : nullptr;
     w.qd = ar.take<QDesc>(sb);
+    w.qord = ar.take<int32_t>(sb);
     w.scores = ar.take<float>((size_t)sb * b);
     w.probes = ar.take<int32_t>((size_t)sb * m);
     w.sel = ar.take<uint32_t>((size_t)sb * m);
@@ -1805,6 +1869,17 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
             // its bound looser: m/24 seed probes there, enough that on the
             // 1M-point benchmark no query's pairs overflow.)
             const bool seeded_exact = P.defer;
+            const int32_t *qord = nullptr;   // bucketing order of the queries (null: as given)
+            if (ix->sch.n_dense > 0) {
+                int32_t kbits = 0;
+                for (int a = 0; a < ix->sch.n_dense; a++) kbits += ix->sch.field_bits[a] + 1;
+                const int32_t shift = std::max(0, kbits - kQordBits), nk = 1 << (kbits - shift);
+                prof_begin(CAPS_STAGE_SELECT, st);
+                hipLaunchKernelGGL(k_qorder, dim3(1), dim3(kQordT), sizeof(int32_t) * (size_t)nk, st, qd, nb,
+                                   ix->sch, shift, nk, W.qord);
+                prof_end(CAPS_STAGE_SELECT, st);
+                qord = W.qord;
+            }
             for (int round = 0; round < 2; round++) {
                 const int32_t r0 = round == 0 || seeded_exact ? 0 : s_seed;
                 const int32_t r1 = round == 0 ? s_seed : m;
@@ -1817,7 +1892,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 prof_begin(CAPS_STAGE_SELECT, st);
                 const unsigned ggrid = (unsigned)((ngrp + kXcds - 1) / kXcds * kXcds);   // XCD-mapped groups
                 hipLaunchKernelGGL(k_bucket_hist, dim3(ggrid), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                                   nb, m, r0, r1, b, ngrp, hist);
+                                   qord, nb, m, r0, r1, b, ngrp, hist);
                 {
                     const caps_status es = exclusive_scan_i32(hist, hscan, (int64_t)b * ngrp, htotal, W.scan_sums, st);
                     if (es != CAPS_OK) return es;
@@ -1831,7 +1906,7 @@ caps_status search(const Index *ix, const caps_search_params *sp, const float *q
                 // the fill packs each entry's class when entries stay below 2^27
                 const int32_t nc_pack = nc > 1 && (int64_t)nb * m < ((int64_t)1 << kClassShift) ? nc : 1;
                 hipLaunchKernelGGL(k_bucket_fill, dim3(ggrid), dim3(kBucketT), sizeof(int32_t) * (size_t)b, st, probes, sel,
-                                   nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries, nc > 1 ? nullptr : W.esel);
+                                   qord, nb, m, r0, r1, b, ngrp, hscan, nc_pack, entries, nc > 1 ? nullptr : W.esel);
                 const int32_t *ent = entries;
                 const uint32_t *esel = W.esel;   // (the class sort writes the level masks itself)
                 if (nc > 1) {

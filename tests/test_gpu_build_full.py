@@ -53,7 +53,7 @@ def test_c2_layout_matches_oracle(caps, orc, c2):
     g = ix.export()
     ix.close()
     tags, level = orc.aft(g["assign"], w.n_partitions, w.aft_height, orc.workload_tokens(w))
-    perm, offs = orc.csr(g["assign"], level, w.n_partitions, w.aft_height)
+    perm, offs = orc.csr(g["assign"], level, w.n_partitions, w.aft_height, w.dense)
     assert np.array_equal(g["tags"], tags)
     assert np.array_equal(g["level"], level)
     assert np.array_equal(g["perm"], perm)

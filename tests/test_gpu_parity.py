@@ -294,7 +294,7 @@ def test_height_sweep(caps, orc):
     prev_nc, ref = None, {}
     for h in (0, 1, 2, 4, 8):
         tags, level = orc.aft(base.assign, w.n_partitions, h, tk)
-        perm, offs = orc.csr(base.assign, level, w.n_partitions, h)
+        perm, offs = orc.csr(base.assign, level, w.n_partitions, h, w.dense)
         oi = orc.Index(base.x, tk, 0, w.n_partitions, h, base.centroids, base.assign, tags, level, perm, offs,
                        base.init)
         ix = caps.Index.from_workload(w, kmeans_iters=3, aft_height=h, precision="bf16")

@@ -181,7 +181,7 @@ def test_aft_hand_worked_example(orc):
     tags, level = orc.aft(a, 1, g["h"], tk)
     assert tags.ravel().tolist() == g["tags"]
     assert level.tolist() == g["level"]
-    perm, offs = orc.csr(a, level, 1, g["h"])
+    perm, offs = orc.csr(a, level, 1, g["h"], np.asarray(dense))
     assert perm.tolist() == g["perm"]
     assert offs.tolist() == g["offs"]
 
@@ -390,7 +390,7 @@ def _aft_properties(idx):
             assert not any(t in toks[i] for t in tags if t >= 0)
 
 
-def _csr_properties(idx):
+def _csr_properties(idx, dense=None):
     n = idx.x.shape[0]
     perm, offs = idx.perm, idx.offs
     assert sorted(perm.tolist()) == list(range(n))
@@ -400,7 +400,9 @@ def _csr_properties(idx):
         seg = perm[offs[s]:offs[s + 1]]
         assert np.all(idx.assign[seg] == s // hp)
         assert np.all(idx.level[seg] == s % hp)
-        assert np.all(np.diff(seg) > 0)
+        # inside a sub-partition: by dense values (attribute 0 first), then id
+        keys = [tuple(dense[i]) + (i,) for i in seg] if dense is not None else [(i,) for i in seg]
+        assert all(keys[j] < keys[j + 1] for j in range(len(keys) - 1))
 
 
 @pytest.mark.parametrize("seed,h,lv", [(0, 0, 0), (1, 1, 0), (2, 2, 0), (3, 4, 0), (4, 2, 12),
@@ -409,7 +411,7 @@ def test_aft_and_csr_properties(orc, seed, h, lv):
     w = _tiny(seed, n=300, d=4, n_q=1, vocabs=(3, 5, 4), label_vocab=lv, b=6, h=h)
     idx = orc.build_from_workload(w, iters=2)
     _aft_properties(idx)
-    _csr_properties(idx)
+    _csr_properties(idx, w.dense)
 
 
 # ------------------------------------------------------------- search
