@@ -145,8 +145,9 @@ caps_status caps_bliss_assign(const int32_t *cand, int64_t n, int32_t k_cand, in
  * assignment picks against the final centroids (argmin of |c|^2 - 2 x.c,
  * IP -x.c, ties to the smaller partition) and, inside it, the first tagged
  * level whose tag it holds (the order Algorithm 1 split the partition in),
- * else the remainder.  Centroids, tags and the router do not change; the CSR
- * stays in (partition, level, id) order and every per-point array, the
+ * else the remainder.  Centroids, tags and the router do not change; the
+ * points already present keep their CSR order, each new point goes to the
+ * end of its sub-partition in id order, and every per-point array, the
  * low-precision copy included, grows.  Synchronises `stream`.  Errors:
  * EINVAL (arguments, vocabularies, non-finite x, label sets given to an
  * index without labels or missing), EUNSUPPORTED (limits of caps_build),
@@ -331,7 +332,9 @@ caps_status caps_index_info(const caps_index *idx, caps_index_info_t *out);
 /*
  * caps_index_export -- copy index arrays to HOST buffers (any may be NULL):
  * centroids B x d, assign n (partition of point i), level n (sub-partition
- * of point i, h = remainder), perm n (CSR position -> point id),
+ * of point i, h = remainder), perm n (CSR position -> point id; inside a
+ * sub-partition the points follow their dense attribute values, attribute 0
+ * first, then id),
  * offs B*(h+1)+1 (first CSR position of sub-partition j of partition p at
  * offs[p*(h+1)+j]), tags B x h (token of each tagged level, -1 unused).
  */

@@ -8,8 +8,9 @@
 //                divided by the count, rounded to FP32; empty clusters keep
 //                their centroid; IP divides by the FP64 norm (spherical).
 //   2. Attribute Frequency Tree per partition, truncated at height h.
-//   3. CSR in (partition, level, id) order, with vectors and packed
-//      attributes permuted alongside (Appendix "Index size").
+//   3. CSR grouped by (partition, level), inside a sub-partition by dense
+//      attribute values (attribute 0 first), then id, with vectors and
+//      packed attributes permuted alongside (Appendix "Index size").
 #include <stdarg.h>
 #include <string.h>
 
