@@ -192,3 +192,27 @@ def test_exact_prune_batch_invariance(caps):
         ids, dist = ix.search(w.q[sub], co, ca, cv, 10, 6)
         assert np.array_equal(ids.cpu().numpy(), a[0][sub])
         assert np.array_equal(dist.cpu().numpy().view(np.uint32), a[1][sub].view(np.uint32))
+
+
+@pytest.mark.parametrize("prec,d", [("bf16", 128), ("fp16", 64), ("bf16", 32)])
+def test_chunk_skip_selective_queries_match_oracle(caps, orc, prec, d):
+    """Large sub-partitions laid out by attribute values and selective queries
+    (2-3 of 3 dense attributes constrained) in batches of several tiles, so
+    that the 32 x 32 main pass often skips a row chunk for a wave (no query
+    of the wave can pass a row there by the chunk's AND/OR word summary).  Results
+    and counters must equal the oracle's bit for bit; the oracle's layout
+    has every sub-partition ordered by dense values, then id."""
+    w = synth.make_tiny(220 + d, n=24000, d=d, n_q=700, vocabs=(4, 8, 16), label_vocab=0, b=4, h=1,
+                        cmin=2, cmax=3, integer=True)
+    oi = orc.build_from_workload(w, iters=2)
+    ix = caps.Index.from_workload(w, kmeans_iters=2, precision=prec)
+    g = ix.export()
+    assert np.array_equal(g["perm"], oi.perm) and np.array_equal(g["offs"], oi.offs)
+    for s in range(len(oi.offs) - 1):
+        seg = oi.perm[oi.offs[s]:oi.offs[s + 1]]
+        keys = [tuple(w.dense[i]) + (i,) for i in seg]
+        assert all(keys[j] < keys[j + 1] for j in range(len(keys) - 1))
+    for m in (1, 2, 4):
+        for k in (1, 10):
+            _check(orc, oi, ix, w.q, w.con_off, w.con_attr, w.con_val, k, m)
+    ix.close()
